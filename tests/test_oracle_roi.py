@@ -1,0 +1,150 @@
+"""Pins of the oracle's ROI map, propagation, budget and quantizer.
+
+* Eq. 2 and Fig. 6 (Sec. IV-C): the coarse block fed by blocks of tolerance
+  tau0, tau1, tau2 gets tau2; blocks away from the ROI keep the background.
+* Sec. IV-C: a partly covered block takes the stricter tolerance.
+* Sec. IV-C: tau_global is the minimum over the last local level.
+* Sec. II-B / V-A: the reconstruction error stays within the bound everywhere,
+  checked by brute force, including adversarial worst-case errors built
+  from the rows of the recomposition matrix (obtained from its transpose).
+* The gain A computed from 1D row sums equals the dense brute force.
+"""
+import numpy as np
+import pytest
+
+from oracle import mgard, roi
+
+
+def test_fig6_propagation():
+    t0, t1, t2 = 1e-2, 1e-3, 1e-4
+    tol = np.full((1, 1, 8), t0)
+    tol[0, 0, 3:5] = [t1, t2]          # adjacent blocks tau0 | tau1 | tau2 | tau0
+    nxt = roi.propagate(tol)
+    assert nxt.shape == (1, 1, 4)
+    # blocks 1 and 2 of the next level receive the tau1/tau2 blocks -> strictest
+    assert nxt[0, 0, 1] == t2 and nxt[0, 0, 2] == t2
+    # block 0 spans fine blocks 0..2 (+ none before), untouched
+    assert nxt[0, 0, 0] == t0
+    # block 3 touches fine block 5 (tau0), 6, 7 only
+    assert nxt[0, 0, 3] == t0
+
+
+def test_influence_region_grows_with_levels():
+    tol = np.full((16, 16, 16), 1.0)
+    tol[7, 7, 7] = 0.1
+    tols = roi.level_block_tolerances(tol, 3)
+    counts = [int((t < 1).sum()) for t in tols]
+    fracs = [c / t.size for c, t in zip(counts, tols)]
+    assert counts[0] == 1
+    assert fracs[1] > fracs[0] and fracs[2] > fracs[1]
+
+
+def test_partial_overlap_is_strict():
+    shape = (17, 17, 17)
+    vt = roi.voxel_tolerance_from_boxes(shape, [(8, 8, 8, 9, 9, 9, 1e-5)], 1e-2)
+    bt = roi.block_tolerance(vt, shape, 9)
+    # node (8,8,8) is a shared corner of all 8 blocks -> all strict
+    assert np.all(bt == 1e-5)
+    vt = roi.voxel_tolerance_from_boxes(shape, [(0, 0, 0, 2, 2, 2, 1e-5)], 1e-2)
+    bt = roi.block_tolerance(vt, shape, 9)
+    assert bt[0, 0, 0] == 1e-5 and (bt == 1e-5).sum() == 1
+
+
+def test_padded_nodes_copy_source_tolerance():
+    shape = (10, 10, 10)             # pads to 17 with b = 9; nodes 10..16 copy node 9
+    vt = np.full(shape, 1e-2)
+    vt[9, 9, 9] = 1e-6
+    bt = roi.block_tolerance(vt, (17, 17, 17), 9)
+    # block 1 spans nodes 8..16 (node 9 and its copies); block 0 spans 0..8
+    assert bt[1, 1, 1] == 1e-6 and bt[0, 0, 0] == 1e-2 and (bt == 1e-6).sum() == 1
+    vt[9, 9, 9] = 1e-2
+    vt[8, 8, 8] = 1e-6                # the corner shared by all 8 blocks
+    bt = roi.block_tolerance(vt, (17, 17, 17), 9)
+    assert np.all(bt == 1e-6)
+
+
+@pytest.mark.parametrize("coords,ff", [([np.arange(9.0)] * 3, False), ([np.arange(9.0)] * 3, True),
+                                        ([np.arange(5.0), np.arange(9.0), np.arange(17.0)], False),
+                                        ([np.arange(2.0), np.arange(9.0), np.arange(5.0)], False)])
+def test_gain_separable_equals_dense(coords, ff):
+    assert roi.amplification(coords, ff) == pytest.approx(roi.amplification_dense(coords, ff), abs=1e-12)
+
+
+def test_gain_is_the_true_worst_case():
+    # the dense gain is attained by the sign pattern of the worst row
+    coords = [np.arange(9.0)] * 3
+    ops = [mgard.axis_ops(c, True) for c in coords]
+    a = [o.P @ o.K for o in ops]
+    E = np.eye(729) - np.kron(np.kron(a[0], a[1]), a[2])
+    coarse = np.zeros((9, 9, 9), bool)
+    coarse[np.ix_(*(o.cidx for o in ops))] = True
+    det = ~coarse.ravel()
+    row = np.abs(E[:, det]).sum(axis=1).argmax()
+    err = np.zeros(729)
+    err[det] = np.sign(E[row, det])
+    assert (E @ err)[row] == pytest.approx(roi.amplification(coords, True), abs=1e-12)
+
+
+def _setup(shape, b, L, M, seed, boxes, bg):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(shape)
+    h = mgard.hierarchy(shape, b, L, M)
+    vt = roi.voxel_tolerance_from_boxes(shape, boxes, bg)
+    tol1 = roi.block_tolerance(vt, h.shape_p, b) if L > 0 else vt.min()
+    return x, h, vt, tol1
+
+
+CASES = [((33, 33, 33), 9, 1, 1, [(2, 3, 4, 10, 12, 9, 1e-4)], 1e-2),
+         ((33, 33, 33), 9, 2, 1, [(20, 20, 20, 26, 30, 25, 1e-5)], 1e-2),
+         ((33, 17, 33), 9, 2, 0, [(0, 0, 0, 5, 5, 5, 1e-4)], 1e-1),
+         ((17, 17, 17), 17, 1, 2, [(9, 9, 9, 12, 12, 12, 1e-5)], 1e-3),
+         ((20, 30, 12), 9, 1, 1, [(15, 25, 6, 20, 30, 12, 1e-5)], 1e-3),
+         ((17, 9, 33), 9, 0, 3, [], 1e-3)]
+
+
+@pytest.mark.parametrize("shape,b,L,M,boxes,bg", CASES)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bound_holds_random(shape, b, L, M, boxes, bg, seed):
+    x, h, vt, tol1 = _setup(shape, b, L, M, seed, boxes, bg)
+    c = mgard.decompose(x, b, L, M)
+    delta = roi.node_delta(h, tol1, 0.0)
+    q = roi.quantize(c, delta)
+    assert np.all(np.abs(c - roi.dequantize(q, delta)) <= delta / 2 * (1 + 1e-12))
+    xr = mgard.recompose(roi.dequantize(q, delta), shape, b, L, M)
+    assert np.all(np.abs(xr - x) <= vt)
+
+
+@pytest.mark.parametrize("shape,b,L,M,boxes,bg", CASES)
+def test_bound_holds_adversarial(shape, b, L, M, boxes, bg):
+    # Worst case: every coefficient off by exactly Delta/2 with the sign of
+    # the recomposition row of a target node.  Rows come from R^T e_target.
+    x, h, vt, tol1 = _setup(shape, b, L, M, 0, boxes, bg)
+    delta = roi.node_delta(h, tol1, 0.0)
+    rng = np.random.default_rng(7)
+    strict = np.argwhere(vt == vt.min())
+    targets = [tuple(strict[0]), tuple(strict[-1])] + [tuple(rng.integers(0, s) for s in shape) for _ in range(4)]
+    for t in targets:
+        e = np.zeros(shape)
+        e[t] = 1.0
+        row = mgard.recompose_adjoint(e, shape, b, L, M)
+        worst = float(np.sum(np.abs(row) * delta / 2))
+        assert worst <= vt[t] * (1 + 1e-12), (t, worst, vt[t])
+
+
+def test_tau_global_is_min_of_last_local_level():
+    tol = np.full((4, 4, 4), 1e-2)
+    tol[1, 2, 3] = 1e-6
+    tols = roi.level_block_tolerances(tol, 2)
+    assert tols[-1].min() == 1e-6
+    h = mgard.hierarchy((33, 33, 33), 9, 2, 1)
+    d = roi.node_delta(h, tol, 0.0)
+    lev = mgard.node_level(h.shape_p, 2, 1)
+    T = 4
+    A3 = roi.level_gains(h)[2]
+    assert np.allclose(d[lev == 3], 1e-6 * 2 / (T * A3))
+
+
+def test_quantizer_round_half_even_and_reciprocal():
+    delta = np.full(6, 0.5)
+    c = np.array([0.25, 0.75, -0.25, 1.0, 0.1, -1.3])
+    assert list(roi.quantize(c, delta)) == [0, 2, 0, 2, 0, -3]
