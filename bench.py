@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the BlockMGARD hot path on one MI355X; prints one JSON line.
+
+Workload: one 512^3 FP32 Gaussian random field with power spectrum k^-3
+(seeded), two disjoint 64^3 ROI boxes at REL 1e-5, background REL 1e-2,
+17^3 shared-face blocks, L = 1 In-cache Block level then M = 2 global levels.
+
+One step = decompose -> ROI quantize -> dequantize -> recompose, all on the
+device with the field already resident in HBM.  `value` is
+2 * (512^3 * 4 bytes) / step time: the decompose and the recompose of the
+field, quantization included.  Per-level kernel times come from HIP events
+the library records on the same stream.  The compression ratio at the ROI
+bounds is measured once outside the timed region (full compress with the
+Huffman stage), and every reconstructed value is checked against its bound.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_local_decompose_512cubed_f32.json")
+
+
+def _src_hash() -> str:
+    p = os.path.join(ROOT, "paper_2609_00205_amd", "csrc", "local_level.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(nbytes_alg: float):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != _src_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(x_np, b, L, M, edge):
+    """The FP64 oracle, as it stands, on a bounded sub-volume of the same field."""
+    from threadpoolctl import threadpool_limits
+    from oracle import mgard
+    sub = x_np[:edge, :edge, :edge].astype("float64")
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        c = mgard.decompose(sub, b, L, M)
+        t1 = time.perf_counter()
+        mgard.recompose(c, sub.shape, b, L, M)
+        t2 = time.perf_counter()
+    gbs = 2 * sub.size * 4 / (t2 - t0) / 1e9
+    return {"value": round(gbs, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"decompose+recompose of the {edge}^3 corner sub-volume (b={b}, L={L}, M={M}) "
+                      f"in {t2 - t0:.1f} s on one host thread; GB/s counts 4-byte input values as on the GPU",
+            "decompose_s": round(t1 - t0, 3), "recompose_s": round(t2 - t1, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-edge", type=int, default=385)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; the method shards fields across GPUs "
+                                   "without communication, see the design notes", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2609_00205_amd import Plan, synth, api
+
+    torch.cuda.set_device(0)
+    n, b, L, M = args.n, 17, 1, 2
+    print(f"[bench] generating {n}^3 field", file=sys.stderr, flush=True)
+    x_np, boxes = synth.workload_roi(n, seed=2)
+    xd = torch.from_numpy(x_np).cuda()
+    scale = float(xd.abs().max())
+    abs_boxes = [bx + (1e-5 * scale,) for bx in boxes]
+    bg = 1e-2 * scale
+    plan = Plan((n, n, n), dtype=torch.float32, block=b, L=L, M=M)
+    bt = plan.tolmap_from_boxes(abs_boxes, bg)
+    coeff = torch.empty(plan.coeff_shape, dtype=torch.float32, device="cuda")
+    coeff2 = torch.empty_like(coeff)
+    codes = torch.empty(plan.coeff_shape, dtype=torch.int32, device="cuda")
+    xr = torch.empty_like(xd)
+
+    def step():
+        plan.decompose(xd, out=coeff)
+        plan.quantize(coeff, bt, codes=codes, stats=False)
+        plan.dequantize(codes, bt, out=coeff2)
+        plan.recompose(coeff2, out=xr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    plan.timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    t = plan.timing_get()
+    plan.timing(False)
+    K = args.steps
+    dec_ms = sum(t["decompose"]) / K
+    rec_ms = sum(t["recompose"]) / K
+    q_ms, dq_ms = t["quantize"] / K, t["dequantize"] / K
+    local_ms = t["decompose"][0] / max(1, t["calls"]["decompose"][0])
+
+    in_bytes = n ** 3 * 4
+    value = 2 * in_bytes / (ms_step * 1e-3) / 1e9
+    npad = 1
+    for d in plan.coeff_shape:
+        npad *= d
+    alg_bytes = 8.0 * npad                      # local level: 4 B read + 4 B write per padded node
+    achieved = alg_bytes / (local_ms * 1e-3) / 1e9
+
+    # bound check of the last step's reconstruction (per voxel, per region)
+    err = (xr.double() - xd.double()).abs()
+    inside = torch.zeros_like(err, dtype=torch.bool)
+    regions = []
+    for (z0, y0, x0, z1, y1, x1, tol) in abs_boxes:
+        e = float(err[z0:z1, y0:y1, x0:x1].max())
+        inside[z0:z1, y0:y1, x0:x1] = True
+        regions.append({"box": [z0, y0, x0, z1, y1, x1], "max_err_over_bound": e / tol})
+    e_bg = float(err[~inside].max())
+    regions.append({"box": "background", "max_err_over_bound": e_bg / bg})
+    bounds_ok = all(r["max_err_over_bound"] <= 1.0 for r in regions)
+    del err, inside
+
+    print("[bench] compress / decompress", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    buf = plan.compress(xd, bt)
+    t1 = time.perf_counter()
+    xr2 = api.decompress(buf)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ratio = in_bytes / len(buf)
+    e2 = (xr2.double() - xd.double()).abs()
+    ok2 = True
+    inside = torch.zeros_like(e2, dtype=torch.bool)
+    for (z0, y0, x0, z1, y1, x1, tol) in abs_boxes:
+        ok2 &= float(e2[z0:z1, y0:y1, x0:x1].max()) <= tol
+        inside[z0:z1, y0:y1, x0:x1] = True
+    ok2 &= float(e2[~inside].max()) <= bg
+    del e2, inside, xr2
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    traffic = _traffic(alg_bytes)
+    out = {
+        "metric": "decompose/recompose GB/s at 512^3 FP32 (ROI quantization in the loop)",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 FP32 k^-3 Gaussian random field, two 64^3 ROI boxes at REL 1e-5, "
+                               f"background REL 1e-2; b=17 shared-face blocks, L=1 local + M=2 global levels",
+                   "block": b, "L": L, "M": M, "padded": list(plan.coeff_shape)},
+        "roofline": {"bound": "hbm", "kernel": "k_local_decompose<float,17> (level 1)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(local_ms, 5)},
+        "phases_ms": {"decompose": round(dec_ms, 4), "quantize": round(q_ms, 4), "dequantize": round(dq_ms, 4),
+                      "recompose": round(rec_ms, 4),
+                      "decompose_levels": [round(v / K, 4) for v in t["decompose"]],
+                      "recompose_levels": [round(v / K, 4) for v in t["recompose"]]},
+        "decompose_GBps": round(in_bytes / (dec_ms * 1e-3) / 1e9, 2),
+        "recompose_GBps": round(in_bytes / (rec_ms * 1e-3) / 1e9, 2),
+        "compression_ratio": round(ratio, 3),
+        "compress_s": round(t1 - t0, 3),
+        "decompress_s": round(t2 - t1, 3),
+        "roi_bounds_held": bool(bounds_ok and ok2),
+        "regions": regions,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(x_np, b, L, M, min(args.cpu_edge, n))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * blockmgard.h -- C ABI of the BlockMGARD hot path for AMD MI355X (gfx950).
+ *
+ * The library decomposes a 3D field with a hybrid hierarchy of In-cache
+ * Block levels followed by global MGARD levels, quantizes the coefficients
+ * under a per-region L-infinity bound, and entropy-codes the result.
+ *
+ * Paper passages each call implements (BlockMGARD, SC'26):
+ *   decompose / recompose ........ Sec. II-B (multilevel decomposition, its
+ *                                  exact inverse), Sec. IV-A (In-cache
+ *                                  Block levels), Sec. IV-B (hybrid
+ *                                  hierarchy of L local + M global levels)
+ *   tolerance maps, quantize ..... Sec. IV-C (block-wise tolerance map,
+ *                                  conservative propagation, Eq. 2, global
+ *                                  budget), Sec. IV-D (per-block
+ *                                  reciprocal quantizer), Sec. V-A (REL
+ *                                  L-infinity bound)
+ *   compress / decompress ........ Sec. IV (transform -> quantize -> lossless
+ *                                  pipeline), Sec. IV-B (Huffman stages),
+ *                                  Sec. V-F (raw copy of incompressible data)
+ *
+ * Conventions (apply to every call):
+ *   - Arrays are dense, C order [z][y][x], x fastest.  "dims" are {nz,ny,nx}.
+ *   - Device pointers are HIP device memory owned by the caller; host
+ *     pointers are ordinary host memory owned by the caller.  The library
+ *     never frees caller memory.
+ *   - A plan owns its constant tables and device workspace.  It is
+ *     immutable after creation; calls on one plan must not overlap in time
+ *     on different streams (they share the workspace).
+ *   - Calls are stream-ordered and asynchronous unless documented as
+ *     synchronous.  Passing stream 0 uses the null stream.
+ *   - Every call returns a bm_status.  No C++ exception crosses the ABI.
+ *     On error, bm_last_error() returns a thread-local message, and no
+ *     caller-visible output except an out_bytes size has been written.
+ *   - The plan's device is the device current at bm_plan_create; calls
+ *     must be made with that device current.
+ */
+#ifndef BLOCKMGARD_H
+#define BLOCKMGARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int bm_status;
+enum {
+  BM_OK = 0,
+  BM_EINVAL = -1,        /* bad argument: shape, block size, levels, null pointer */
+  BM_ENOMEM = -2,        /* device or host allocation failed */
+  BM_EHIP = -3,          /* a HIP runtime call failed (message names it) */
+  BM_ENONFINITE = -4,    /* NaN or Inf in the data or in a tolerance */
+  BM_ECAPACITY = -5,     /* output buffer too small; *out_bytes holds the size needed */
+  BM_ECORRUPT = -6,      /* compressed stream fails its magic, version, size or CRC check */
+  BM_ERANGE = -7,        /* a quantization code does not fit in 32 bits */
+  BM_EUNSUPPORTED = -8   /* valid request outside what this build implements */
+};
+
+typedef enum { BM_F32 = 0, BM_F64 = 1 } bm_dtype;
+
+/* Plan configuration, filled by the caller and copied by bm_plan_create.
+ *   ndim     3 (1 and 2 are accepted as 3D with leading unit dims)
+ *   dims     logical dims {nz, ny, nx}
+ *   dtype    BM_F32 or BM_F64: the type of data and coefficients
+ *   block    b in {9, 17}: nodes per block side of the local levels
+ *            (blocks of 2^k+1 nodes share one face with each neighbour);
+ *            ignored when L == 0
+ *   L, M     number of local (In-cache Block) and global levels (Sec. IV-B)
+ *   pad_mode 0 = clamp (padded nodes copy the nearest node), 1 = zero fill
+ *   eta      safety share of every tolerance kept back for working-precision
+ *            rounding, in [0, 0.5); the quantizer uses tau * (1 - eta). */
+typedef struct {
+  int ndim;
+  int64_t dims[3];
+  int dtype;
+  int block;
+  int L;
+  int M;
+  int pad_mode;
+  double eta;
+} bm_config;
+
+typedef struct bm_plan_s* bm_plan;
+
+/* Per-call quantization statistics (filled synchronously when non-NULL). */
+typedef struct {
+  int64_t n_codes;       /* number of coefficients quantized (= padded node count) */
+  int64_t n_outliers;    /* codes with |q| >= 2^15 (escaped in the Huffman stage) */
+  int64_t max_abs_code;  /* max |q| */
+} bm_qstats;
+
+/* ---- plans ------------------------------------------------------------ */
+
+/* Validate cfg and build a plan: padded dims, level schedule, per-level
+ * gains and device workspace.  The padded length of every axis is the
+ * smallest n' >= n on which the L block levels tile exactly and each of the
+ * M global levels halves an odd length (lengths <= 2 are left alone).
+ * Errors: BM_EINVAL (bad shape/b/L/M/eta, null), BM_ENOMEM, BM_EHIP. */
+bm_status bm_plan_create(const bm_config* cfg, bm_plan* out);
+
+/* Free a plan and its workspace.  NULL is accepted. */
+bm_status bm_plan_destroy(bm_plan plan);
+
+/* Padded dims n' (the coefficient array's dims). */
+bm_status bm_coeff_shape(bm_plan plan, int64_t padded_dims[3]);
+
+/* Number of level-1 blocks per axis ({1,1,1} when L == 0): the shape of the
+ * block tolerance map taken by the quantizer. */
+bm_status bm_block_grid(bm_plan plan, int64_t nblocks[3]);
+
+/* Rounded-up L-infinity gain A_s of the detail coefficients of level s
+ * (s = 1..L+M), written to gains[0..L+M-1] (host).  Sec. II-B budget. */
+bm_status bm_level_gains(bm_plan plan, double* gains);
+
+/* ---- transform (Sec. II-B, IV-A, IV-B) ---------------------------------- */
+
+/* coeff = D(x).  x: device, logical dims, dtype of the plan.  coeff: device,
+ * padded dims, same dtype; every node holds its own coefficient ("in
+ * place"): the detail of the level at which the node leaves the grid, or
+ * the coarsest value.  Asynchronous on stream. */
+bm_status bm_decompose(bm_plan plan, const void* x, void* coeff, hipStream_t stream);
+
+/* x = R(coeff) = D^{-1}(coeff), cropped to the logical dims.  Asynchronous. */
+bm_status bm_recompose(bm_plan plan, const void* coeff, void* x, hipStream_t stream);
+
+/* gx = D^T(gcoeff): gradient of <D(x), gcoeff> with respect to x.  gcoeff has
+ * padded dims, gx logical dims.  Asynchronous. */
+bm_status bm_decompose_adjoint(bm_plan plan, const void* gcoeff, void* gx, hipStream_t stream);
+
+/* gcoeff = R^T(gx).  gx logical dims, gcoeff padded dims.  Asynchronous. */
+bm_status bm_recompose_adjoint(bm_plan plan, const void* gx, void* gcoeff, hipStream_t stream);
+
+/* ---- ROI tolerance maps (Sec. IV-C) ------------------------------------- */
+
+/* Level-1 block tolerance map from half-open boxes.  boxes (host): nbox
+ * records {z0,y0,x0,z1,y1,x1,abs_tol} in logical node coordinates;
+ * background: absolute tolerance elsewhere.  A block takes the minimum over
+ * the nodes of its closed range (a partly covered block is strict); padded
+ * nodes count as the node they copy.  block_tol (device, double,
+ * bm_block_grid entries; 1 entry when L == 0).  Asynchronous.
+ * Errors: BM_EINVAL, BM_ENONFINITE (tolerance <= 0 or not finite). */
+bm_status bm_tolmap_from_boxes(bm_plan plan, const double* boxes, int nbox, double background,
+                               double* block_tol, hipStream_t stream);
+
+/* Level-1 block tolerance map from a per-voxel absolute tolerance (device,
+ * double, logical dims): min over each block's closed node range.
+ * Asynchronous. */
+bm_status bm_tolmap_from_voxels(bm_plan plan, const double* voxel_tol, double* block_tol,
+                                hipStream_t stream);
+
+/* ---- quantization (Sec. IV-C, IV-D) ------------------------------------- */
+
+/* codes = rint(c * (1/Delta)) per node, Delta = tau * 2 (1 - eta) / (T A_s)
+ * for a detail of level s and tau * 2 (1 - eta) / T for a coarsest value,
+ * T = L + M + 1.  tau is the node's propagated block tolerance at local
+ * levels (min over the level's blocks that contain it, with block maps
+ * propagated by Eq. 2) and tau_global = min over the last local level at
+ * global levels.  coeff: device, padded dims; block_tol: device double map
+ * from the calls above; codes: device int32, padded dims.  If stats is
+ * non-NULL the call synchronizes the stream and fills it; a code beyond
+ * int32 range then returns BM_ERANGE. */
+bm_status bm_quantize_roi(bm_plan plan, const void* coeff, const double* block_tol, int32_t* codes,
+                          bm_qstats* stats, hipStream_t stream);
+
+/* coeff = (dtype)(codes * Delta) with the same Delta.  Asynchronous. */
+bm_status bm_dequantize(bm_plan plan, const int32_t* codes, const double* block_tol, void* coeff,
+                        hipStream_t stream);
+
+/* ---- lossless stage (Sec. IV-B lossless stages) ----------------------- */
+
+/* Canonical Huffman coding of n int32 codes (device) in raster order.
+ * Symbols are q + 2^15 for |q| < 2^15, else the escape symbol 0 with the
+ * (index, q) pair kept as an outlier.  Output (host) layout, little endian:
+ *   uint32 magic 0x46484D42 ("BMHF"), uint32 version 2,
+ *   int64 n, int64 nchunks, int64 nwords, int64 noutliers, int64 npresent,
+ *   uint16 symbol[npresent] (ascending), uint8 length[npresent] (code
+ *   lengths of the symbols that occur; absent symbols have no code),
+ *   uint64 chunk_offsets[nchunks+1] (in words),
+ *   uint32 words[nwords] (each chunk of 4096 symbols packed MSB-first,
+ *   starting on a word), uint64 outlier_index[noutliers],
+ *   int32 outlier_value[noutliers].
+ * Synchronous.  BM_ECAPACITY sets *out_bytes to the size needed. */
+bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity,
+                            size_t* out_bytes, hipStream_t stream);
+
+/* Inverse of bm_huffman_encode into codes (device, n entries).  Synchronous.
+ * Errors: BM_ECORRUPT for a malformed stream, BM_EINVAL if n mismatches. */
+bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int64_t n,
+                            hipStream_t stream);
+
+/* ---- end to end (Sec. IV, V-F) -------------------------------------------- */
+
+/* Decompose, quantize with block_tol (device map as above) and Huffman-code x
+ * (device) into a self-describing host buffer: header (config, gains),
+ * block tolerance map, Huffman stream, CRC32.  If the coded form is not
+ * smaller than the raw data the raw bytes are stored instead (Sec. V-F).
+ * Synchronous.  BM_ECAPACITY sets *out_bytes to the size needed. */
+bm_status bm_compress(bm_plan plan, const void* x, const double* block_tol, void* out,
+                      size_t capacity, size_t* out_bytes, hipStream_t stream);
+
+/* Read the configuration stored in a compressed buffer (host, synchronous). */
+bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg);
+
+/* Rebuild x (device, logical dims and dtype of the stored config) from a
+ * buffer written by bm_compress.  Synchronous.  Errors: BM_ECORRUPT. */
+bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t stream);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+
+/* Per-level timing.  bm_timing(plan, 1) resets the counters and makes every
+ * later call on the plan record HIP events on its stream around each level
+ * (and around quantize / dequantize); bm_timing(plan, 0) stops recording.
+ * bm_timing_get waits for the recorded events and returns, for slot k,
+ * total milliseconds ms[k] and number of timed calls calls[k], k < cap:
+ *   slot 2(s-1)   decomposition level s (s = 1..L+M; one kernel for a block level)
+ *   slot 2(s-1)+1 recomposition level s
+ *   slot 2(L+M)   quantize, slot 2(L+M)+1 dequantize.
+ * *n receives the number of slots, 2(L+M)+2.  Synchronous. */
+bm_status bm_timing(bm_plan plan, int enable);
+bm_status bm_timing_get(bm_plan plan, double* ms, int64_t* calls, int cap, int* n);
+
+const char* bm_status_string(bm_status s);
+const char* bm_last_error(void);     /* thread-local; "" when no error */
+const char* bm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLOCKMGARD_H */

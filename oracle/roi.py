@@ -164,8 +164,13 @@ def amplification(coords3, face_fixed: bool) -> float:
 
 
 def round_up4(a: float) -> float:
-    """Round a gain up to 4 decimals (both sides of the parity test use this value)."""
-    return math.ceil(a * 10000.0) / 10000.0
+    """Round a gain up to 4 decimals (both sides of the parity test use this value).
+
+    A slack of 1e-6 in units of the last decimal keeps a gain that is an exact
+    4-decimal number (2.375 for a 3-node level) from being pushed up by
+    rounding noise in how it was summed.
+    """
+    return math.ceil(a * 10000.0 - 1e-6) / 10000.0
 
 
 def level_gains(h: mgard.Hierarchy) -> List[float]:

@@ -1,0 +1,15 @@
+"""BlockMGARD hot path for AMD MI355X (gfx950).
+
+The computation lives in ``libblockmgard.so`` (hand-written HIP kernels
+behind the C ABI in ``include/blockmgard.h``); this package only marshals
+arguments.  Importing it does not load the library; the first call does,
+and raises if the library has not been built.
+"""
+__all__ = ["Plan", "decompress", "compressed_config", "huffman_encode", "huffman_decode"]
+
+
+def __getattr__(name):
+    if name in __all__:
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

@@ -1,0 +1,88 @@
+"""ctypes view of libblockmgard.so (the C ABI declared in include/blockmgard.h).
+
+Argument marshalling only.  If the library has not been built this module
+raises on first use: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libblockmgard.so")
+
+BM_F32, BM_F64 = 0, 1
+STATUS = {0: "BM_OK", -1: "BM_EINVAL", -2: "BM_ENOMEM", -3: "BM_EHIP", -4: "BM_ENONFINITE",
+          -5: "BM_ECAPACITY", -6: "BM_ECORRUPT", -7: "BM_ERANGE", -8: "BM_EUNSUPPORTED"}
+
+
+class BMConfig(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("dims", C.c_int64 * 3), ("dtype", C.c_int), ("block", C.c_int),
+                ("L", C.c_int), ("M", C.c_int), ("pad_mode", C.c_int), ("eta", C.c_double)]
+
+
+class BMQStats(C.Structure):
+    _fields_ = [("n_codes", C.c_int64), ("n_outliers", C.c_int64), ("max_abs_code", C.c_int64)]
+
+
+class BMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+_lib = None
+
+P = C.c_void_p
+_SIGS = {
+    "bm_plan_create": [C.POINTER(BMConfig), C.POINTER(P)],
+    "bm_plan_destroy": [P],
+    "bm_coeff_shape": [P, C.POINTER(C.c_int64)],
+    "bm_block_grid": [P, C.POINTER(C.c_int64)],
+    "bm_level_gains": [P, C.POINTER(C.c_double)],
+    "bm_decompose": [P, P, P, P],
+    "bm_recompose": [P, P, P, P],
+    "bm_decompose_adjoint": [P, P, P, P],
+    "bm_recompose_adjoint": [P, P, P, P],
+    "bm_tolmap_from_boxes": [P, C.POINTER(C.c_double), C.c_int, C.c_double, P, P],
+    "bm_tolmap_from_voxels": [P, P, P, P],
+    "bm_quantize_roi": [P, P, P, P, C.POINTER(BMQStats), P],
+    "bm_dequantize": [P, P, P, P, P],
+    "bm_huffman_encode": [P, C.c_int64, P, C.c_size_t, C.POINTER(C.c_size_t), P],
+    "bm_huffman_decode": [P, C.c_size_t, P, C.c_int64, P],
+    "bm_compress": [P, P, P, P, C.c_size_t, C.POINTER(C.c_size_t), P],
+    "bm_compressed_config": [P, C.c_size_t, C.POINTER(BMConfig)],
+    "bm_decompress": [P, C.c_size_t, P, P],
+    "bm_timing": [P, C.c_int],
+    "bm_timing_get": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)],
+}
+
+
+def lib():
+    """Load the library (once)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_00205_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        h.bm_status_string.argtypes = [C.c_int]
+        h.bm_status_string.restype = C.c_char_p
+        h.bm_last_error.argtypes = []
+        h.bm_last_error.restype = C.c_char_p
+        h.bm_version.argtypes = []
+        h.bm_version.restype = C.c_char_p
+        _lib = h
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != 0:
+        raise BMError(status, lib().bm_last_error().decode())
+
+
+def call(name: str, *args) -> None:
+    check(getattr(lib(), name)(*args))

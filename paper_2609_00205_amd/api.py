@@ -1,0 +1,239 @@
+"""Torch-facing wrappers over the C ABI: device memory and streams come from
+PyTorch; every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import BMConfig, BMQStats, call
+
+_DT = {torch.float32: _lib.BM_F32, torch.float64: _lib.BM_F64}
+_TD = {_lib.BM_F32: torch.float32, _lib.BM_F64: torch.float64}
+
+# Share of each tolerance kept back for working-precision rounding.
+DEFAULT_ETA = {torch.float32: 0.1, torch.float64: 1e-6}
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, shape, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Plan:
+    """A decomposition plan: dims, dtype, block size b, L local + M global levels."""
+
+    def __init__(self, shape: Sequence[int], dtype=torch.float32, block: int = 17, L: int = 1, M: int = 2,
+                 pad_mode: str = "clamp", eta: Optional[float] = None, device=None):
+        shape = tuple(int(s) for s in shape)
+        if len(shape) != 3:
+            raise ValueError("3D shapes only")
+        self.shape = shape
+        self.dtype = dtype
+        self.block, self.L, self.M = block, L, M
+        self.eta = DEFAULT_ETA[dtype] if eta is None else float(eta)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        cfg = BMConfig(3, (C.c_int64 * 3)(*shape), _DT[dtype], block, L, M, 1 if pad_mode == "zero" else 0, self.eta)
+        self._cfg = cfg
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            call("bm_plan_create", C.byref(cfg), C.byref(h))
+        self._h = h
+        pd = (C.c_int64 * 3)()
+        call("bm_coeff_shape", h, pd)
+        self.coeff_shape = tuple(pd)
+        nb = (C.c_int64 * 3)()
+        call("bm_block_grid", h, nb)
+        self.block_grid = tuple(nb)
+        g = (C.c_double * (L + M))()
+        call("bm_level_gains", h, g)
+        self.gains = list(g)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.lib().bm_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # -- transform -----------------------------------------------------------
+    def decompose(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _need(x, self.dtype, self.shape, "x")
+        if out is None:
+            out = torch.empty(self.coeff_shape, dtype=self.dtype, device=x.device)
+        _need(out, self.dtype, self.coeff_shape, "out")
+        call("bm_decompose", self._h, _ptr(x), _ptr(out), _stream(stream))
+        return out
+
+    def recompose(self, coeff: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _need(coeff, self.dtype, self.coeff_shape, "coeff")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=coeff.device)
+        _need(out, self.dtype, self.shape, "out")
+        call("bm_recompose", self._h, _ptr(coeff), _ptr(out), _stream(stream))
+        return out
+
+    def decompose_adjoint(self, gcoeff: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        _need(gcoeff, self.dtype, self.coeff_shape, "gcoeff")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=gcoeff.device)
+        _need(out, self.dtype, self.shape, "out")
+        call("bm_decompose_adjoint", self._h, _ptr(gcoeff), _ptr(out), _stream(stream))
+        return out
+
+    def recompose_adjoint(self, gx: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        _need(gx, self.dtype, self.shape, "gx")
+        if out is None:
+            out = torch.empty(self.coeff_shape, dtype=self.dtype, device=gx.device)
+        _need(out, self.dtype, self.coeff_shape, "out")
+        call("bm_recompose_adjoint", self._h, _ptr(gx), _ptr(out), _stream(stream))
+        return out
+
+    # -- ROI and quantization -----------------------------------------------
+    def tolmap_from_boxes(self, boxes: Sequence[Sequence[float]], background: float, stream=None) -> torch.Tensor:
+        flat = [float(v) for b in boxes for v in b]
+        arr = (C.c_double * max(1, len(flat)))(*flat)
+        out = torch.empty(self.block_grid, dtype=torch.float64, device=self.device)
+        call("bm_tolmap_from_boxes", self._h, arr, len(boxes), float(background), _ptr(out), _stream(stream))
+        return out
+
+    def tolmap_from_voxels(self, voxel_tol: torch.Tensor, stream=None) -> torch.Tensor:
+        _need(voxel_tol, torch.float64, self.shape, "voxel_tol")
+        out = torch.empty(self.block_grid, dtype=torch.float64, device=self.device)
+        call("bm_tolmap_from_voxels", self._h, _ptr(voxel_tol), _ptr(out), _stream(stream))
+        return out
+
+    def quantize(self, coeff: torch.Tensor, block_tol: torch.Tensor, codes: Optional[torch.Tensor] = None,
+                 stats: bool = True, stream=None):
+        _need(coeff, self.dtype, self.coeff_shape, "coeff")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        if codes is None:
+            codes = torch.empty(self.coeff_shape, dtype=torch.int32, device=coeff.device)
+        _need(codes, torch.int32, self.coeff_shape, "codes")
+        st = BMQStats()
+        call("bm_quantize_roi", self._h, _ptr(coeff), _ptr(block_tol), _ptr(codes),
+             C.byref(st) if stats else None, _stream(stream))
+        return codes, ({"n_codes": st.n_codes, "n_outliers": st.n_outliers, "max_abs_code": st.max_abs_code}
+                       if stats else None)
+
+    def dequantize(self, codes: torch.Tensor, block_tol: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+        _need(codes, torch.int32, self.coeff_shape, "codes")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        if out is None:
+            out = torch.empty(self.coeff_shape, dtype=self.dtype, device=codes.device)
+        _need(out, self.dtype, self.coeff_shape, "out")
+        call("bm_dequantize", self._h, _ptr(codes), _ptr(block_tol), _ptr(out), _stream(stream))
+        return out
+
+    # -- per-level timing ------------------------------------------------------
+    def timing(self, enable: bool) -> None:
+        """Start (reset) or stop recording HIP events around each level."""
+        call("bm_timing", self._h, 1 if enable else 0)
+
+    def timing_get(self) -> dict:
+        """{"decompose": [ms per level s=1..], "recompose": [...], "quantize": ms, "dequantize": ms,
+        "calls": {...}}: totals since timing(True)."""
+        k = 2 * (self.L + self.M) + 2
+        ms = (C.c_double * k)()
+        calls = (C.c_int64 * k)()
+        n = C.c_int(0)
+        call("bm_timing_get", self._h, ms, calls, k, C.byref(n))
+        nl = self.L + self.M
+        return {"decompose": [ms[2 * s] for s in range(nl)], "recompose": [ms[2 * s + 1] for s in range(nl)],
+                "quantize": ms[2 * nl], "dequantize": ms[2 * nl + 1],
+                "calls": {"decompose": [calls[2 * s] for s in range(nl)],
+                          "recompose": [calls[2 * s + 1] for s in range(nl)],
+                          "quantize": calls[2 * nl], "dequantize": calls[2 * nl + 1]}}
+
+    # -- end to end ----------------------------------------------------------
+    def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None) -> bytes:
+        _need(x, self.dtype, self.shape, "x")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        need = C.c_size_t(0)
+        st = _stream(stream)
+        try:
+            call("bm_compress", self._h, _ptr(x), _ptr(block_tol), None, 0, C.byref(need), st)
+        except _lib.BMError as e:
+            if e.code != -5:
+                raise
+        buf = C.create_string_buffer(need.value)
+        got = C.c_size_t(0)
+        call("bm_compress", self._h, _ptr(x), _ptr(block_tol), buf, need.value, C.byref(got), st)
+        return buf.raw[: got.value]
+
+
+def compressed_config(buf: bytes) -> dict:
+    cfg = BMConfig()
+    call("bm_compressed_config", buf, len(buf), C.byref(cfg))
+    return {"shape": tuple(cfg.dims), "dtype": _TD[cfg.dtype], "block": cfg.block, "L": cfg.L, "M": cfg.M,
+            "pad_mode": cfg.pad_mode, "eta": cfg.eta}
+
+
+def decompress(buf: bytes, device=None, stream=None) -> torch.Tensor:
+    info = compressed_config(buf)
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(info["shape"], dtype=info["dtype"], device=dev)
+    call("bm_decompress", buf, len(buf), _ptr(out), _stream(stream))
+    return out
+
+
+def huffman_encode(codes: torch.Tensor, stream=None) -> bytes:
+    _need(codes, torch.int32, None, "codes")
+    need = C.c_size_t(0)
+    st = _stream(stream)
+    try:
+        call("bm_huffman_encode", _ptr(codes), codes.numel(), None, 0, C.byref(need), st)
+    except _lib.BMError as e:
+        if e.code != -5:
+            raise
+    buf = C.create_string_buffer(need.value)
+    got = C.c_size_t(0)
+    call("bm_huffman_encode", _ptr(codes), codes.numel(), buf, need.value, C.byref(got), st)
+    return buf.raw[: got.value]
+
+
+def huffman_decode(buf: bytes, n: int, device=None, stream=None) -> torch.Tensor:
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    call("bm_huffman_decode", buf, len(buf), _ptr(out), n, _stream(stream))
+    return out
+
+
+def parse_huffman(buf: bytes) -> dict:
+    """Split a bm_huffman_encode stream into its arrays (layout in blockmgard.h)."""
+    import numpy as np
+    hdr = np.frombuffer(buf, dtype=np.int64, count=6, offset=0)
+    magic = int(np.frombuffer(buf, dtype=np.uint32, count=1)[0])
+    n, nch, nw, nout, npres = (int(v) for v in hdr[1:6])
+    o = 48
+    psym = np.frombuffer(buf, np.uint16, npres, o); o += 2 * npres
+    plen = np.frombuffer(buf, np.uint8, npres, o); o += npres
+    lengths = np.zeros(65536, np.uint8)
+    lengths[psym.astype(np.int64)] = plen
+    offsets = np.frombuffer(buf, np.uint64, nch + 1, o); o += 8 * (nch + 1)
+    words = np.frombuffer(buf, np.uint32, nw, o); o += 4 * nw
+    oidx = np.frombuffer(buf, np.uint64, nout, o); o += 8 * nout
+    oval = np.frombuffer(buf, np.int32, nout, o)
+    return {"magic": magic, "n": n, "nchunks": nch, "lengths": lengths, "offsets": offsets, "words": words,
+            "outlier_index": oidx, "outlier_value": oval}

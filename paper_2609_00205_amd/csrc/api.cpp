@@ -1,0 +1,396 @@
+// extern "C" entry points of libblockmgard: argument checks, error mapping,
+// and the self-describing compressed container (Sec. IV pipeline:
+// transform -> quantize -> lossless; raw copy of incompressible data,
+// Sec. V-F).
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+bm_plan_s* bm_plan_build(const bm_config* c);
+void bm_plan_free(bm_plan_s* p);
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F>
+bm_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    f();
+    return BM_OK;
+  } catch (const bm::Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return BM_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return BM_EINVAL;
+  } catch (...) {
+    g_err = "unknown failure";
+    return BM_EINVAL;
+  }
+}
+
+void need(bool ok, const char* what) {
+  if (!ok) bm::fail(BM_EINVAL, what);
+}
+
+void check_device(const bm_plan_s* p) {
+  int d = -1;
+  BM_HIP(hipGetDevice(&d));
+  if (d != p->device) bm::fail(BM_EINVAL, "the current device is not the plan's device");
+}
+
+uint32_t crc32(const uint8_t* p, size_t n, uint32_t crc = 0) {
+  static uint32_t table[256];
+  static bool init = false;
+  if (!init) {
+    for (uint32_t i = 0; i < 256; ++i) {
+      uint32_t c = i;
+      for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+      table[i] = c;
+    }
+    init = true;
+  }
+  crc = ~crc;
+  for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xFF] ^ (crc >> 8);
+  return ~crc;
+}
+
+// container header; payload follows (block tolerances + Huffman stream, or raw data)
+struct CHeader {
+  uint32_t magic;       // "BMGD"
+  uint32_t version;
+  uint32_t flags;       // bit 0: raw copy
+  int32_t dtype, block, L, M, pad_mode, ndim, pad0;
+  int64_t dims[3];
+  double eta;
+  int64_t ntol;         // block tolerance entries
+  uint64_t payload;     // bytes after the header
+  uint32_t crc;         // CRC32 of header (crc = 0) + payload
+  uint32_t pad1;
+};
+constexpr uint32_t kMagic = 0x44474D42u;   // "BMGD"
+
+void ensure_pipeline_buffers(bm_plan_s& p) {
+  const size_t n = size_t(p.pdims[0]) * p.pdims[1] * p.pdims[2];
+  if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, n * p.esize));
+  if (!p.ws.codes) BM_HIP(hipMalloc(&p.ws.codes, n * sizeof(int32_t)));
+}
+
+bm_config header_config(const CHeader& h) {
+  bm_config c{};
+  c.ndim = 3;
+  c.dims[0] = h.dims[0];
+  c.dims[1] = h.dims[1];
+  c.dims[2] = h.dims[2];
+  c.dtype = h.dtype;
+  c.block = h.block;
+  c.L = h.L;
+  c.M = h.M;
+  c.pad_mode = h.pad_mode;
+  c.eta = h.eta;
+  return c;
+}
+
+CHeader parse(const void* in, size_t in_bytes) {
+  if (!in || in_bytes < sizeof(CHeader)) bm::fail(BM_ECORRUPT, "buffer shorter than the container header");
+  CHeader h;
+  std::memcpy(&h, in, sizeof(h));
+  if (h.magic != kMagic) bm::fail(BM_ECORRUPT, "bad magic");
+  if (h.version != 1) bm::fail(BM_ECORRUPT, "unsupported container version");
+  if (h.payload != in_bytes - sizeof(CHeader)) bm::fail(BM_ECORRUPT, "payload size mismatch");
+  CHeader z = h;
+  z.crc = 0;
+  uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&z), sizeof(z));
+  c = crc32(static_cast<const uint8_t*>(in) + sizeof(CHeader), size_t(h.payload), c);
+  if (c != h.crc) bm::fail(BM_ECORRUPT, "CRC mismatch");
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+bm_status bm_plan_create(const bm_config* cfg, bm_plan* out) {
+  return guarded([&] {
+    need(cfg && out, "null argument");
+    *out = bm_plan_build(cfg);
+  });
+}
+
+bm_status bm_plan_destroy(bm_plan plan) {
+  return guarded([&] { bm_plan_free(plan); });
+}
+
+bm_status bm_coeff_shape(bm_plan p, int64_t padded_dims[3]) {
+  return guarded([&] {
+    need(p && padded_dims, "null argument");
+    for (int a = 0; a < 3; ++a) padded_dims[a] = p->pdims[a];
+  });
+}
+
+bm_status bm_block_grid(bm_plan p, int64_t nb[3]) {
+  return guarded([&] {
+    need(p && nb, "null argument");
+    for (int a = 0; a < 3; ++a) nb[a] = p->nb1[a];
+  });
+}
+
+bm_status bm_level_gains(bm_plan p, double* gains) {
+  return guarded([&] {
+    need(p && gains, "null argument");
+    for (int s = 0; s < p->nlev; ++s) gains[s] = p->lv[s].gain;
+  });
+}
+
+bm_status bm_decompose(bm_plan p, const void* x, void* coeff, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && coeff, "null argument");
+    check_device(p);
+    bm::decompose(*p, x, coeff, st);
+  });
+}
+
+bm_status bm_recompose(bm_plan p, const void* coeff, void* x, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && coeff, "null argument");
+    check_device(p);
+    bm::recompose(*p, coeff, x, st);
+  });
+}
+
+bm_status bm_decompose_adjoint(bm_plan p, const void* gcoeff, void* gx, hipStream_t st) {
+  return guarded([&] {
+    need(p && gcoeff && gx, "null argument");
+    bm::fail(BM_EUNSUPPORTED, "adjoint not built yet");
+  });
+}
+
+bm_status bm_recompose_adjoint(bm_plan p, const void* gx, void* gcoeff, hipStream_t st) {
+  return guarded([&] {
+    need(p && gcoeff && gx, "null argument");
+    bm::fail(BM_EUNSUPPORTED, "adjoint not built yet");
+  });
+}
+
+bm_status bm_tolmap_from_boxes(bm_plan p, const double* boxes, int nbox, double background, double* block_tol,
+                               hipStream_t st) {
+  return guarded([&] {
+    need(p && block_tol, "null argument");
+    check_device(p);
+    bm::tolmap_from_boxes(*p, boxes, nbox, background, block_tol, st);
+  });
+}
+
+bm_status bm_tolmap_from_voxels(bm_plan p, const double* voxel_tol, double* block_tol, hipStream_t st) {
+  return guarded([&] {
+    need(p && voxel_tol && block_tol, "null argument");
+    check_device(p);
+    bm::tolmap_from_voxels(*p, voxel_tol, block_tol, st);
+  });
+}
+
+bm_status bm_quantize_roi(bm_plan p, const void* coeff, const double* block_tol, int32_t* codes, bm_qstats* stats,
+                          hipStream_t st) {
+  return guarded([&] {
+    need(p && coeff && block_tol && codes, "null argument");
+    check_device(p);
+    bm::quantize(*p, coeff, block_tol, codes, stats, st);
+  });
+}
+
+bm_status bm_dequantize(bm_plan p, const int32_t* codes, const double* block_tol, void* coeff, hipStream_t st) {
+  return guarded([&] {
+    need(p && coeff && block_tol && codes, "null argument");
+    check_device(p);
+    bm::dequantize(*p, codes, block_tol, coeff, st);
+  });
+}
+
+bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
+                            hipStream_t st) {
+  return guarded([&] {
+    need(out_bytes != nullptr, "null out_bytes");
+    std::vector<uint8_t> buf;
+    const size_t bytes = bm::huffman_encode(codes, n, buf, st);
+    *out_bytes = bytes;
+    if (!out || capacity < bytes) bm::fail(BM_ECAPACITY, "output buffer too small");
+    std::memcpy(out, buf.data(), bytes);
+  });
+}
+
+bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st) {
+  return guarded([&] {
+    need(codes || n == 0, "null codes");
+    bm::huffman_decode(static_cast<const uint8_t*>(in), in_bytes, codes, n, st);
+  });
+}
+
+bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* out, size_t capacity,
+                      size_t* out_bytes, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && out_bytes, "null argument");
+    check_device(p);
+    ensure_pipeline_buffers(*p);
+    const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];
+    const int64_t nlog = p->dims[0] * p->dims[1] * p->dims[2];
+    const int64_t ntol = p->nb1[0] * p->nb1[1] * p->nb1[2];
+    std::vector<double> tol(ntol);
+    BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
+    BM_HIP(hipStreamSynchronize(st));
+    for (double t : tol)
+      if (!(t > 0) || !std::isfinite(t)) bm::fail(BM_ENONFINITE, "block tolerances must be positive and finite");
+    bm::decompose(*p, x, p->ws.coeff, st);
+    bm_qstats qs;
+    bool too_fine = false;   // codes beyond 32 bits: store the raw data
+    try {
+      bm::quantize(*p, p->ws.coeff, block_tol, static_cast<int32_t*>(p->ws.codes), &qs, st);
+    } catch (const bm::Error& e) {
+      if (e.code != BM_ERANGE) throw;
+      too_fine = true;
+    }
+    std::vector<uint8_t> huff;
+    if (!too_fine) bm::huffman_encode(static_cast<const int32_t*>(p->ws.codes), npad, huff, st);
+    CHeader h{};
+    h.magic = kMagic;
+    h.version = 1;
+    h.dtype = p->cfg.dtype;
+    h.block = p->cfg.block;
+    h.L = p->L;
+    h.M = p->M;
+    h.pad_mode = p->cfg.pad_mode;
+    h.ndim = 3;
+    for (int a = 0; a < 3; ++a) h.dims[a] = p->dims[a];
+    h.eta = p->cfg.eta;
+    h.ntol = ntol;
+    const size_t coded = size_t(ntol) * 8 + huff.size();
+    const size_t raw = size_t(nlog) * p->esize;
+    h.flags = (too_fine || coded >= raw) ? 1u : 0u;
+    h.payload = h.flags ? raw : coded;
+    const size_t total = sizeof(CHeader) + size_t(h.payload);
+    *out_bytes = total;
+    if (!out || capacity < total) bm::fail(BM_ECAPACITY, "output buffer too small");
+    uint8_t* o = static_cast<uint8_t*>(out) + sizeof(CHeader);
+    if (h.flags) {
+      BM_HIP(hipMemcpyAsync(o, x, raw, hipMemcpyDeviceToHost, st));
+      BM_HIP(hipStreamSynchronize(st));
+    } else {
+      std::memcpy(o, tol.data(), size_t(ntol) * 8);
+      std::memcpy(o + size_t(ntol) * 8, huff.data(), huff.size());
+    }
+    h.crc = 0;
+    uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
+    c = crc32(o, size_t(h.payload), c);
+    h.crc = c;
+    std::memcpy(out, &h, sizeof(h));
+  });
+}
+
+bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg) {
+  return guarded([&] {
+    need(cfg != nullptr, "null cfg");
+    *cfg = header_config(parse(in, in_bytes));
+  });
+}
+
+bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st) {
+  return guarded([&] {
+    need(x != nullptr, "null output");
+    const CHeader h = parse(in, in_bytes);
+    const bm_config c = header_config(h);
+    bm_plan_s* p = bm_plan_build(&c);
+    struct Guard {
+      bm_plan_s* p;
+      double* d = nullptr;
+      ~Guard() {
+        if (d) (void)hipFree(d);
+        bm_plan_free(p);
+      }
+    } g{p};
+    const uint8_t* pl = static_cast<const uint8_t*>(in) + sizeof(CHeader);
+    const int64_t nlog = p->dims[0] * p->dims[1] * p->dims[2];
+    if (h.flags & 1u) {
+      if (h.payload != uint64_t(nlog) * p->esize) bm::fail(BM_ECORRUPT, "raw payload size mismatch");
+      BM_HIP(hipMemcpyAsync(x, pl, size_t(h.payload), hipMemcpyHostToDevice, st));
+      BM_HIP(hipStreamSynchronize(st));
+      return;
+    }
+    const int64_t ntol = p->nb1[0] * p->nb1[1] * p->nb1[2];
+    if (h.ntol != ntol || h.payload < uint64_t(ntol) * 8) bm::fail(BM_ECORRUPT, "tolerance map size mismatch");
+    ensure_pipeline_buffers(*p);
+    BM_HIP(hipMalloc(&g.d, size_t(ntol) * sizeof(double)));
+    BM_HIP(hipMemcpyAsync(g.d, pl, size_t(ntol) * 8, hipMemcpyHostToDevice, st));
+    const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];
+    bm::huffman_decode(pl + ntol * 8, size_t(h.payload) - size_t(ntol) * 8, static_cast<int32_t*>(p->ws.codes),
+                       npad, st);
+    bm::dequantize(*p, static_cast<const int32_t*>(p->ws.codes), g.d, p->ws.coeff, st);
+    bm::recompose(*p, p->ws.coeff, x, st);
+    BM_HIP(hipStreamSynchronize(st));
+  });
+}
+
+static void drain_timing(bm_plan_s& p) {
+  for (auto& e : p.timing.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess &&
+        e.slot < int(p.timing.ms.size())) {
+      p.timing.ms[e.slot] += ms;
+      p.timing.calls[e.slot] += 1;
+    }
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  p.timing.pending.clear();
+}
+
+bm_status bm_timing(bm_plan p, int enable) {
+  return guarded([&] {
+    need(p != nullptr, "null plan");
+    drain_timing(*p);
+    p->timing.ms.assign(2 * p->nlev + 2, 0.0);
+    p->timing.calls.assign(2 * p->nlev + 2, 0);
+    p->timing.on = enable != 0;
+  });
+}
+
+bm_status bm_timing_get(bm_plan p, double* ms, int64_t* calls, int cap, int* n) {
+  return guarded([&] {
+    need(p && n, "null argument");
+    drain_timing(*p);
+    const int k = int(p->timing.ms.size());
+    *n = k;
+    for (int i = 0; i < k && i < cap; ++i) {
+      if (ms) ms[i] = p->timing.ms[i];
+      if (calls) calls[i] = p->timing.calls[i];
+    }
+  });
+}
+
+const char* bm_status_string(bm_status s) {
+  switch (s) {
+    case BM_OK: return "ok";
+    case BM_EINVAL: return "invalid argument";
+    case BM_ENOMEM: return "out of memory";
+    case BM_EHIP: return "HIP runtime error";
+    case BM_ENONFINITE: return "non-finite value";
+    case BM_ECAPACITY: return "output buffer too small";
+    case BM_ECORRUPT: return "corrupt stream";
+    case BM_ERANGE: return "code out of range";
+    case BM_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* bm_last_error(void) { return g_err.c_str(); }
+
+const char* bm_version(void) { return "blockmgard-mi355x 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,512 @@
+// Global MGARD levels (Sec. II-B; run on the block-coarse grid in the hybrid
+// hierarchy of Sec. IV-B) and the decompose / recompose drivers.
+//
+// A global level on grid G (dims n) with coarse grid C (dims m):
+//   details  d = u - multilinear interpolant of u_C, on the fine-only nodes;
+//   coarse   c = K_z K_y K_x u with K = Mc^{-1} P^T M per axis (natural
+//            ends).  Because K P = I this equals u_C + K w of the
+//            step-by-step definition (w = u - P u_C), i.e. the L2 projection.
+// Recomposition: z = K_z K_y K_x w (w = details, zero on coarse nodes),
+// u_C = c - z, u = interpolant(u_C) + w.
+//
+// Each K along one axis is a "line pass": restriction by P^T M (5-point
+// rows {1/12, 1/2, 5/6, 1/2, 1/12}; end rows {5/12, 1/2, 1/12}) and a solve
+// with 3 Mc = tridiag(1, 4, 1) (end diagonals 2).  A workgroup stages a tile
+// of lines in LDS (coalesced loads); one wavefront solves a line with its
+// lanes: both Thomas sweeps are first-order affine recurrences, evaluated
+// by a lane-local pass and a 64-lane scan of affine maps with wave shuffles.
+
+#include "internal.h"
+
+namespace bm {
+namespace {
+
+constexpr int NT = 256;
+constexpr int QMAX = 9;     // coarse values per lane: lines up to 64 * 9 coarse nodes
+
+// ------------------------------------------------------------- elementwise
+
+struct Idx3 {
+  int64_t n0, n1, n2;
+};
+
+__device__ inline void unflat(int64_t i, const Idx3& d, int64_t& z, int64_t& y, int64_t& x) {
+  x = i % d.n2;
+  const int64_t t = i / d.n2;
+  y = t % d.n1;
+  z = t / d.n1;
+}
+
+template <typename T>
+struct DetArgs {
+  const T* u;            // compact G^{s-1}
+  Idx3 n;
+  int cm0, cm1, cm2;     // 1 if the axis coarsens at this level
+  T* coeff;
+  int64_t cs[3];
+};
+
+// Interpolant at (z,y,x) from a grid holding the coarse values: mean of the
+// 8 corners of the coarse cell (an axis that does not coarsen, or an even
+// coordinate, uses the node itself twice).  read(zz, yy, xx) fetches a
+// coarse node in full-grid coordinates.
+template <typename T, typename F>
+__device__ inline T interp8(int64_t z, int64_t y, int64_t x, int cm0, int cm1, int cm2, F read) {
+  const int64_t z0 = (cm0 && (z & 1)) ? z - 1 : z, z1 = (cm0 && (z & 1)) ? z + 1 : z;
+  const int64_t y0 = (cm1 && (y & 1)) ? y - 1 : y, y1 = (cm1 && (y & 1)) ? y + 1 : y;
+  const int64_t x0 = (cm2 && (x & 1)) ? x - 1 : x, x1 = (cm2 && (x & 1)) ? x + 1 : x;
+  const T s = ((read(z0, y0, x0) + read(z0, y0, x1)) + (read(z0, y1, x0) + read(z0, y1, x1))) +
+              ((read(z1, y0, x0) + read(z1, y0, x1)) + (read(z1, y1, x0) + read(z1, y1, x1)));
+  return s * T(0.125);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_details(DetArgs<T> a) {
+  const int64_t tot = a.n.n0 * a.n.n1 * a.n.n2;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t z, y, x;
+    unflat(i, a.n, z, y, x);
+    const bool coarse = !((a.cm0 && (z & 1)) || (a.cm1 && (y & 1)) || (a.cm2 && (x & 1)));
+    if (coarse) continue;
+    auto rd = [&](int64_t zz, int64_t yy, int64_t xx) { return a.u[(zz * a.n.n1 + yy) * a.n.n2 + xx]; };
+    const T d = a.u[i] - interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
+    a.coeff[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]] = d;
+  }
+}
+
+template <typename T>
+struct IntArgs {
+  const T* coeff;
+  int64_t cs[3];
+  const T* uc;           // compact G^s (coarse values u_C)
+  Idx3 m;
+  Idx3 n;                // dims of G^{s-1}
+  int cm0, cm1, cm2;
+  T* out;                // dense G^{s-1}
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_interp_add(IntArgs<T> a) {
+  const int64_t tot = a.n.n0 * a.n.n1 * a.n.n2;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t z, y, x;
+    unflat(i, a.n, z, y, x);
+    auto rd = [&](int64_t zz, int64_t yy, int64_t xx) {
+      const int64_t cz = a.cm0 ? zz >> 1 : zz, cy = a.cm1 ? yy >> 1 : yy, cx = a.cm2 ? xx >> 1 : xx;
+      return a.uc[(cz * a.m.n1 + cy) * a.m.n2 + cx];
+    };
+    const bool coarse = !((a.cm0 && (z & 1)) || (a.cm1 && (y & 1)) || (a.cm2 && (x & 1)));
+    T v;
+    if (coarse)
+      v = rd(z, y, x);
+    else
+      v = a.coeff[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]] + interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
+    a.out[i] = v;
+  }
+}
+
+template <typename T>
+struct CopyArgs {
+  const T* src;
+  int64_t ss[3];
+  T* dst;
+  int64_t ds[3];
+  Idx3 n;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_copy(CopyArgs<T> a) {
+  const int64_t tot = a.n.n0 * a.n.n1 * a.n.n2;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t z, y, x;
+    unflat(i, a.n, z, y, x);
+    a.dst[z * a.ds[0] + y * a.ds[1] + x * a.ds[2]] = a.src[z * a.ss[0] + y * a.ss[1] + x * a.ss[2]];
+  }
+}
+
+// Pad the logical input to the padded grid (clamp or zero fill).
+template <typename T>
+struct PadArgs {
+  const T* src;
+  Idx3 sn;
+  T* dst;
+  Idx3 dn;
+  int zero;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pad(PadArgs<T> a) {
+  const int64_t tot = a.dn.n0 * a.dn.n1 * a.dn.n2;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t z, y, x;
+    unflat(i, a.dn, z, y, x);
+    const bool in = z < a.sn.n0 && y < a.sn.n1 && x < a.sn.n2;
+    T v;
+    if (!in && a.zero) {
+      v = T(0);
+    } else {
+      z = z < a.sn.n0 ? z : a.sn.n0 - 1;
+      y = y < a.sn.n1 ? y : a.sn.n1 - 1;
+      x = x < a.sn.n2 ? x : a.sn.n2 - 1;
+      v = a.src[(z * a.sn.n1 + y) * a.sn.n2 + x];
+    }
+    a.dst[i] = v;
+  }
+}
+
+inline unsigned grid_for(int64_t tot) {
+  int64_t g = (tot + NT - 1) / NT;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+// ------------------------------------------------------------- line pass
+
+template <typename T>
+struct PassArgs {
+  const T* in;
+  int64_t is[3];         // input strides
+  int64_t n[3];          // input dims
+  int axis;              // axis of the lines
+  int mask;              // zero the level's coarse nodes on load
+  int cm[3];             // coarsening flags (coarse node: every coarsening coordinate even)
+  T* out;                // dense, dims on
+  int64_t on[3];
+  const T* base;         // optional: out = base - result (dense, dims on)
+  const double* inv;     // Thomas reciprocal pivots, length m
+  int64_t nl, m;         // line length, coarse length
+  int W;                 // lines per tile
+  int64_t nq, ntq;       // extent of the fastest other axis, tiles per row along it
+  int pa, qa;            // the two other axes (q fastest)
+};
+
+// Affine map x -> A x + B; compose(prev then cur).
+template <typename T>
+__device__ inline void scan_up(T& A, T& B, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T Ap = __shfl_up(A, off, 64);
+    const T Bp = __shfl_up(B, off, 64);
+    if (lane >= off) {
+      B = A * Bp + B;
+      A = A * Ap;
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void scan_down(T& A, T& B, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T An = __shfl_down(A, off, 64);
+    const T Bn = __shfl_down(B, off, 64);
+    if (lane + off < 64) {
+      B = A * Bn + B;
+      A = A * An;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
+  extern __shared__ unsigned char smem[];
+  T* tin = reinterpret_cast<T*>(smem);                 // [nl][W+1]
+  const int WP = a.W + 1;
+  T* tout = tin + a.nl * WP;                           // [m][W+1]
+  const int64_t tile = blockIdx.x;
+  const int64_t p = tile / a.ntq;
+  const int64_t q0 = (tile - p * a.ntq) * a.W;
+  const int wv = int(i64min(a.W, a.nq - q0));   // valid lines in this tile
+  const int tid = threadIdx.x;
+  const int64_t sA = a.is[a.axis], sP = a.is[a.pa], sQ = a.is[a.qa];
+  const int64_t total = a.nl * wv;
+  // load: along the line fastest when lines are rows (x), across lines otherwise
+  for (int64_t k = tid; k < total; k += NT) {
+    int64_t i, w;
+    if (a.axis == 2) {
+      w = k / a.nl;
+      i = k - w * a.nl;
+    } else {
+      i = k / wv;
+      w = k - i * wv;
+    }
+    T v = a.in[p * sP + (q0 + w) * sQ + i * sA];
+    if (a.mask) {
+      int64_t c[3];
+      c[a.axis] = i;
+      c[a.pa] = p;
+      c[a.qa] = q0 + w;
+      const bool coarse = !((a.cm[0] && (c[0] & 1)) || (a.cm[1] && (c[1] & 1)) || (a.cm[2] && (c[2] & 1)));
+      if (coarse) v = T(0);
+    }
+    tin[i * WP + w] = v;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t m = a.m, nl = a.nl;
+  const int q = int((m + 63) / 64);
+  const int64_t J0 = int64_t(lane) * q;
+  for (int w = wave; w < wv; w += NT / 64) {
+    const T* col = tin + w;
+    T f[QMAX], al[QMAX];
+    T A = T(1), B = T(0);
+#pragma unroll
+    for (int j = 0; j < QMAX; ++j) {
+      const int64_t J = J0 + j;
+      if (j < q && J < m) {
+        const int64_t c = 2 * J;
+        T r;
+        if (J == 0) {
+          r = T(5.0 / 12.0) * col[0] + T(0.5) * col[WP] + T(1.0 / 12.0) * col[2 * WP];
+        } else if (J == m - 1) {
+          r = T(1.0 / 12.0) * col[(nl - 3) * WP] + T(0.5) * col[(nl - 2) * WP] + T(5.0 / 12.0) * col[(nl - 1) * WP];
+        } else {
+          r = T(1.0 / 12.0) * (col[(c - 2) * WP] + col[(c + 2) * WP]) + T(0.5) * (col[(c - 1) * WP] + col[(c + 1) * WP]) +
+              T(5.0 / 6.0) * col[c * WP];
+        }
+        const T iv = T(a.inv[J]);
+        al[j] = J == 0 ? T(0) : -iv;
+        f[j] = T(3) * r * iv;
+        A = al[j] * A;
+        B = al[j] * B + f[j];
+      }
+    }
+    // forward sweep: d_J = al_J d_{J-1} + f_J
+    scan_up(A, B, lane);
+    T din = __shfl_up(B, 1, 64);
+    if (lane == 0) din = T(0);
+#pragma unroll
+    for (int j = 0; j < QMAX; ++j) {
+      if (j < q && J0 + j < m) {
+        din = al[j] * din + f[j];
+        f[j] = din;                 // f now holds d_J
+      }
+    }
+    // backward sweep: x_J = g_J x_{J+1} + d_J, g_J = -inv_J (J < m-1), g_{m-1} = 0
+    A = T(1);
+    B = T(0);
+#pragma unroll
+    for (int j = QMAX - 1; j >= 0; --j) {
+      const int64_t J = J0 + j;
+      if (j < q && J < m) {
+        al[j] = J == m - 1 ? T(0) : -T(a.inv[J]);
+        A = al[j] * A;
+        B = al[j] * B + f[j];
+      }
+    }
+    scan_down(A, B, lane);
+    T xin = __shfl_down(B, 1, 64);
+    if (lane == 63) xin = T(0);
+#pragma unroll
+    for (int j = QMAX - 1; j >= 0; --j) {
+      const int64_t J = J0 + j;
+      if (j < q && J < m) {
+        xin = al[j] * xin + f[j];
+        tout[J * WP + w] = xin;
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t totm = m * wv;
+  const int64_t oA = a.axis == 0 ? a.on[1] * a.on[2] : (a.axis == 1 ? a.on[2] : 1);
+  const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
+  const int64_t oP = os[a.pa], oQ = os[a.qa];
+  for (int64_t k = tid; k < totm; k += NT) {
+    int64_t J, w;
+    if (a.axis == 2) {
+      w = k / m;
+      J = k - w * m;
+    } else {
+      J = k / wv;
+      w = k - J * wv;
+    }
+    const int64_t o = p * oP + (q0 + w) * oQ + J * oA;
+    const T v = tout[J * WP + w];
+    a.out[o] = a.base ? a.base[o] - v : v;
+  }
+}
+
+template <typename T>
+void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
+                 const void* base, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  PassArgs<T> a{};
+  a.in = static_cast<const T*>(in.ptr);
+  for (int k = 0; k < 3; ++k) {
+    a.is[k] = in.s[k];
+    a.n[k] = in.n[k];
+    a.on[k] = in.n[k];
+    a.cm[k] = L.coarsen[k] ? 1 : 0;
+  }
+  a.axis = axis;
+  a.mask = cmask != nullptr;
+  a.nl = in.n[axis];
+  a.m = L.m[axis];
+  a.on[axis] = a.m;
+  if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * QMAX) fail(BM_EUNSUPPORTED, "line length not supported");
+  a.out = static_cast<T*>(out);
+  a.base = static_cast<const T*>(base);
+  a.inv = L.d_inv[axis];
+  a.pa = axis == 0 ? 1 : 0;
+  a.qa = axis == 2 ? 1 : 2;
+  a.nq = in.n[a.qa];
+  // tile width: keep the LDS tile near 40 KiB
+  const int64_t per_line = (a.nl + a.m) * int64_t(sizeof(T));
+  int W = int(std::min<int64_t>(64, std::max<int64_t>(1, 40960 / per_line - 1)));
+  W = int(std::min<int64_t>(W, a.nq));
+  a.W = W;
+  a.ntq = (a.nq + W - 1) / W;
+  const int64_t tiles = in.n[a.pa] * a.ntq;
+  const size_t shm = size_t(a.nl + a.m) * (W + 1) * sizeof(T);
+  hipLaunchKernelGGL(k_line_pass<T>, dim3(unsigned(tiles)), dim3(NT), shm, st, a);
+  BM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+void global_details(const bm_plan_s& p, int s, const void* u, void* coeff, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  const View3 cv = level_view(p, s, coeff);
+  const int64_t tot = L.n[0] * L.n[1] * L.n[2];
+  if (p.cfg.dtype == BM_F32) {
+    DetArgs<float> a{static_cast<const float*>(u), {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1],
+                     L.coarsen[2], static_cast<float*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}};
+    hipLaunchKernelGGL(k_details<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  } else {
+    DetArgs<double> a{static_cast<const double*>(u), {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1],
+                      L.coarsen[2], static_cast<double*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}};
+    hipLaunchKernelGGL(k_details<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  }
+  BM_HIP(hipGetLastError());
+}
+
+void global_interp_add(const bm_plan_s& p, int s, const void* coeff, const void* uc, void* out, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  const View3 cv = level_view(p, s, const_cast<void*>(coeff));
+  const int64_t tot = L.n[0] * L.n[1] * L.n[2];
+  if (p.cfg.dtype == BM_F32) {
+    IntArgs<float> a{static_cast<const float*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, static_cast<const float*>(uc),
+                     {L.m[0], L.m[1], L.m[2]}, {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
+                     static_cast<float*>(out)};
+    hipLaunchKernelGGL(k_interp_add<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  } else {
+    IntArgs<double> a{static_cast<const double*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, static_cast<const double*>(uc),
+                      {L.m[0], L.m[1], L.m[2]}, {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
+                      static_cast<double*>(out)};
+    hipLaunchKernelGGL(k_interp_add<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  }
+  BM_HIP(hipGetLastError());
+}
+
+void line_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
+               const void* base, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32)
+    launch_pass<float>(p, s, axis, in, cmask, out, base, st);
+  else
+    launch_pass<double>(p, s, axis, in, cmask, out, base, st);
+}
+
+void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t st) {
+  const int64_t tot = src.n[0] * src.n[1] * src.n[2];
+  if (esize == 4) {
+    CopyArgs<float> a{static_cast<const float*>(src.ptr), {src.s[0], src.s[1], src.s[2]},
+                      static_cast<float*>(dst.ptr), {dst.s[0], dst.s[1], dst.s[2]}, {src.n[0], src.n[1], src.n[2]}};
+    hipLaunchKernelGGL(k_copy<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  } else {
+    CopyArgs<double> a{static_cast<const double*>(src.ptr), {src.s[0], src.s[1], src.s[2]},
+                       static_cast<double*>(dst.ptr), {dst.s[0], dst.s[1], dst.s[2]}, {src.n[0], src.n[1], src.n[2]}};
+    hipLaunchKernelGGL(k_copy<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  }
+  BM_HIP(hipGetLastError());
+}
+
+static void pad_input(const bm_plan_s& p, const void* x, void* dst, hipStream_t st) {
+  const int64_t tot = p.pdims[0] * p.pdims[1] * p.pdims[2];
+  if (p.cfg.dtype == BM_F32) {
+    PadArgs<float> a{static_cast<const float*>(x), {p.dims[0], p.dims[1], p.dims[2]}, static_cast<float*>(dst),
+                     {p.pdims[0], p.pdims[1], p.pdims[2]}, p.cfg.pad_mode == 1};
+    hipLaunchKernelGGL(k_pad<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  } else {
+    PadArgs<double> a{static_cast<const double*>(x), {p.dims[0], p.dims[1], p.dims[2]}, static_cast<double*>(dst),
+                      {p.pdims[0], p.pdims[1], p.pdims[2]}, p.cfg.pad_mode == 1};
+    hipLaunchKernelGGL(k_pad<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  }
+  BM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- drivers
+
+// coarse = K_z K_y K_x (in), applied as line passes over the axes that
+// coarsen; intermediate results go through the plan's temporaries.
+static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const void* base, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  int axes[3], na = 0;
+  for (int a : {2, 1, 0})
+    if (L.coarsen[a]) axes[na++] = a;
+  const int64_t cm[3] = {1, 1, 1};
+  void* tmp[2] = {p.ws.t1, p.ws.t2};
+  View3 cur = in;
+  for (int k = 0; k < na; ++k) {
+    const int ax = axes[k];
+    const bool last = k == na - 1;
+    void* dst = last ? out : tmp[k & 1];
+    line_pass(p, s, ax, cur, (k == 0 && mask) ? cm : nullptr, dst, last ? base : nullptr, st);
+    int64_t on[3] = {cur.n[0], cur.n[1], cur.n[2]};
+    on[ax] = L.m[ax];
+    cur = dense_view(dst, on);
+  }
+}
+
+void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
+  const View3 xv = dense_view(const_cast<void*>(x), p.dims);
+  for (int s = 1; s <= p.nlev; ++s) {
+    const Level& L = p.lv[s - 1];
+    TimedScope ts(p, 2 * (s - 1), st);
+    if (L.local) {
+      const View3 src = s == 1 ? xv : dense_view(p.ws.grid[s - 1], L.n);
+      local_decompose(p, s, src, s == 1, coeff, p.ws.grid[s], st);
+    } else {
+      const void* u;
+      if (s == 1) {
+        pad_input(p, x, p.ws.grid[0], st);
+        u = p.ws.grid[0];
+      } else {
+        u = p.ws.grid[s - 1];
+      }
+      global_details(p, s, u, coeff, st);
+      apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
+    }
+  }
+  const Level& last = p.lv[p.nlev - 1];
+  strided_copy(p.esize, dense_view(p.ws.grid[p.nlev], last.m), coarsest_view(p, coeff), st);
+}
+
+void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
+  const Level& last = p.lv[p.nlev - 1];
+  strided_copy(p.esize, coarsest_view(p, const_cast<void*>(coeff)), dense_view(p.ws.grid[p.nlev], last.m), st);
+  for (int s = p.nlev; s >= 1; --s) {
+    const Level& L = p.lv[s - 1];
+    TimedScope ts(p, 2 * (s - 1) + 1, st);
+    if (L.local) {
+      void* out = s == 1 ? x : p.ws.grid[s - 1];
+      local_recompose(p, s, coeff, p.ws.grid[s], out, s == 1, st);
+    } else {
+      // u_C = c - K3 w in place in grid[s], then u = interpolant + w
+      apply_K3(p, s, level_view(p, s, const_cast<void*>(coeff)), true, p.ws.grid[s], p.ws.grid[s], st);
+      void* out = p.ws.grid[s - 1];
+      global_interp_add(p, s, coeff, p.ws.grid[s], out, st);
+      if (s == 1) {
+        View3 src = dense_view(out, p.pdims);
+        src.n[0] = p.dims[0];
+        src.n[1] = p.dims[1];
+        src.n[2] = p.dims[2];
+        strided_copy(p.esize, src, dense_view(x, p.dims), st);
+      }
+    }
+  }
+}
+
+}  // namespace bm

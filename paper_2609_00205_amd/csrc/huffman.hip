@@ -1,0 +1,460 @@
+// Lossless stage: canonical Huffman coding of the quantization codes
+// (the paper's pipeline ends with Huffman stages for outliers, histogram,
+// codebook, encoding; Sec. IV-B).
+//
+// Symbols: q + 2^15 for |q| < 2^15, else the escape symbol 0 with the
+// (raster index, q) pair kept as an outlier.  Code lengths come from
+// Huffman's algorithm merging the two smallest (weight, smallest symbol in
+// the subtree) keys, so the tree is unique; lengths above 32 are cut to 32
+// and the longest codes below 32 are lengthened (largest symbol first) until
+// Kraft's sum is <= 1.  Codes are canonical in (length, symbol) order.
+// The stream is cut into chunks of 4096 symbols, each packed MSB-first into
+// 32-bit words and starting on a word boundary.
+//
+// GPU work: an LDS-privatised histogram, one wavefront per chunk for the
+// bit counts and for the encode (LDS atomic ORs into the chunk's words),
+// one thread per chunk for decoding.  The codebook is built on the host.
+
+#include <algorithm>
+#include <cstring>
+#include <queue>
+
+#include "internal.h"
+
+namespace bm {
+namespace {
+
+constexpr int R = 1 << 15;
+constexpr int NSYM = 2 * R;
+constexpr int CHUNK = 4096;
+constexpr int LMAX = 32;
+constexpr int HW = 4096;           // LDS histogram window: symbols [R - HW, R + HW)
+constexpr int LUTB = 10;           // decode lookup bits
+
+__device__ inline uint32_t sym_of(int32_t q) { return (q > -R && q < R) ? uint32_t(q + R) : 0u; }
+
+__global__ __launch_bounds__(256) void k_hist(const int32_t* codes, int64_t n, unsigned long long* hist) {
+  __shared__ uint32_t h[2 * HW];
+  for (int i = threadIdx.x; i < 2 * HW; i += 256) h[i] = 0;
+  __syncthreads();
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const uint32_t s = sym_of(codes[i]);
+    const int64_t k = int64_t(s) - (R - HW);
+    if (k >= 0 && k < 2 * HW)
+      atomicAdd(&h[k], 1u);
+    else
+      atomicAdd(&hist[s], 1ull);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * HW; i += 256)
+    if (h[i]) atomicAdd(&hist[R - HW + i], (unsigned long long)h[i]);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) p[i] = 0;
+}
+
+// one wavefront per chunk: bit count and escape count
+__global__ __launch_bounds__(64) void k_chunk_bits(const int32_t* codes, int64_t n, const uint8_t* len,
+                                                   uint32_t* bits, uint32_t* esc) {
+  const int64_t c = blockIdx.x;
+  const int64_t b0 = c * CHUNK;
+  const int64_t b1 = b0 + CHUNK < n ? b0 + CHUNK : n;
+  uint32_t nb = 0, ne = 0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 64) {
+    const uint32_t s = sym_of(codes[i]);
+    nb += len[s];
+    ne += s == 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nb += __shfl_down(nb, off, 64);
+    ne += __shfl_down(ne, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    bits[c] = nb;
+    esc[c] = ne;
+  }
+}
+
+__device__ inline uint32_t wave_excl_scan(uint32_t v, int lane) {
+  uint32_t s = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(s, off, 64);
+    if (lane >= off) s += t;
+  }
+  return s - v;
+}
+
+// one wavefront per chunk; lane l codes symbols [64 l, 64 l + 64) of the chunk
+__global__ __launch_bounds__(64) void k_encode(const int32_t* codes, int64_t n, const uint8_t* len,
+                                               const uint32_t* cw, const uint64_t* woff, const uint64_t* ooff,
+                                               uint32_t* words, uint64_t* oidx, int32_t* oval) {
+  __shared__ uint32_t sym[64 * 65];
+  __shared__ uint32_t out[CHUNK];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int64_t b0 = c * CHUNK;
+  const int cnt = int(b0 + CHUNK < n ? CHUNK : n - b0);
+  const uint64_t w0 = woff[c], nw = woff[c + 1] - w0;
+  for (int i = lane; i < CHUNK; i += 64) sym[(i >> 6) * 65 + (i & 63)] = i < cnt ? sym_of(codes[b0 + i]) : 0xFFFFFFFFu;
+  for (uint64_t i = lane; i < nw; i += 64) out[i] = 0;
+  __syncthreads();
+  uint32_t nb = 0, ne = 0;
+  for (int k = 0; k < 64; ++k) {
+    const uint32_t s = sym[lane * 65 + k];
+    if (s != 0xFFFFFFFFu) {
+      nb += len[s];
+      ne += s == 0;
+    }
+  }
+  uint32_t p = wave_excl_scan(nb, lane);
+  uint64_t e = ooff[c] + wave_excl_scan(ne, lane);
+  for (int k = 0; k < 64; ++k) {
+    const uint32_t s = sym[lane * 65 + k];
+    if (s == 0xFFFFFFFFu) break;
+    const uint32_t l = len[s], v = cw[s];
+    const uint32_t w = p >> 5, o = p & 31;
+    if (o + l <= 32) {
+      atomicOr(&out[w], v << (32 - o - l));
+    } else {
+      atomicOr(&out[w], v >> (o + l - 32));
+      atomicOr(&out[w + 1], v << (64 - o - l));
+    }
+    p += l;
+    if (s == 0) {
+      const int64_t idx = b0 + lane * 64 + k;
+      oidx[e] = uint64_t(idx);
+      oval[e] = codes[idx];
+      ++e;
+    }
+  }
+  __syncthreads();
+  for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = out[i];
+}
+
+struct DecTables {
+  const uint32_t* lut;        // [1 << LUTB]: symbol | length << 16 (length 0: longer code)
+  const uint32_t* first;      // [LMAX + 1] first canonical code of each length
+  const uint32_t* count;      // [LMAX + 1]
+  const uint32_t* base;       // [LMAX + 1] index of the first symbol of each length in `sorted`
+  const uint32_t* sorted;     // symbols in (length, symbol) order
+};
+
+// one thread per chunk
+__global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint64_t* woff, int64_t nch, int64_t n,
+                                               DecTables t, const uint64_t* oidx, const int32_t* oval, int64_t nout,
+                                               int32_t* codes, int* err) {
+  const int64_t c = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  if (c >= nch) return;
+  const int64_t b0 = c * CHUNK;
+  const int cnt = int(b0 + CHUNK < n ? CHUNK : n - b0);
+  const uint64_t w0 = woff[c], w1 = woff[c + 1];
+  // first outlier at or after this chunk
+  int64_t lo = 0, hi = nout;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (int64_t(oidx[mid]) < b0) lo = mid + 1; else hi = mid;
+  }
+  int64_t e = lo;
+  uint64_t buf = 0;
+  int avail = 0;
+  uint64_t wp = w0;
+  for (int k = 0; k < cnt; ++k) {
+    while (avail <= 32) {
+      const uint64_t wv = wp < w1 ? words[wp] : 0u;
+      ++wp;
+      buf |= wv << (32 - avail);
+      avail += 32;
+    }
+    uint32_t s, l;
+    const uint32_t lu = t.lut[buf >> (64 - LUTB)];
+    if ((lu >> 16) != 0) {
+      s = lu & 0xFFFFu;
+      l = lu >> 16;
+    } else {
+      l = 0;
+      s = 0;
+      for (uint32_t L = LUTB + 1; L <= LMAX; ++L) {
+        const uint32_t code = uint32_t(buf >> (64 - L));
+        if (t.count[L] && code - t.first[L] < t.count[L]) {
+          s = t.sorted[t.base[L] + code - t.first[L]];
+          l = L;
+          break;
+        }
+      }
+      if (l == 0) {
+        atomicOr(err, 1);
+        return;
+      }
+    }
+    buf <<= l;
+    avail -= int(l);
+    int32_t q;
+    if (s == 0) {
+      if (e >= nout) {
+        atomicOr(err, 1);
+        return;
+      }
+      q = oval[e++];
+    } else {
+      q = int32_t(s) - R;
+    }
+    codes[b0 + k] = q;
+  }
+}
+
+// ------------------------------------------------------------------ host codebook
+
+void code_lengths(const std::vector<uint64_t>& hist, std::vector<uint8_t>& len) {
+  len.assign(NSYM, 0);
+  std::vector<int> present;
+  for (int s = 0; s < NSYM; ++s)
+    if (hist[s]) present.push_back(s);
+  if (present.empty()) return;
+  if (present.size() == 1) {
+    len[present[0]] = 1;
+    return;
+  }
+  struct Node {
+    uint64_t w;
+    int minsym;
+    int id;
+  };
+  auto gt = [](const Node& a, const Node& b) { return a.w != b.w ? a.w > b.w : a.minsym > b.minsym; };
+  std::priority_queue<Node, std::vector<Node>, decltype(gt)> heap(gt);
+  std::vector<int> parent(2 * NSYM, -1);
+  for (int s : present) heap.push({hist[s], s, s});
+  int next = NSYM;
+  while (heap.size() > 1) {
+    const Node a = heap.top();
+    heap.pop();
+    const Node b = heap.top();
+    heap.pop();
+    parent[a.id] = next;
+    parent[b.id] = next;
+    heap.push({a.w + b.w, std::min(a.minsym, b.minsym), next});
+    ++next;
+  }
+  std::vector<int> depth(next, -1);
+  depth[next - 1] = 0;
+  for (int v = next - 2; v >= NSYM; --v) depth[v] = depth[parent[v]] + 1;  // parents are created after children
+  std::vector<int> L(NSYM, 0);
+  int maxl = 0;
+  for (int s : present) {
+    L[s] = depth[parent[s]] + 1;
+    maxl = std::max(maxl, L[s]);
+  }
+  if (maxl > LMAX) {
+    // cap, then lengthen the longest codes below the cap until Kraft holds
+    uint64_t kraft = 0;
+    for (int s : present) {
+      if (L[s] > LMAX) L[s] = LMAX;
+      kraft += uint64_t(1) << (LMAX - L[s]);
+    }
+    while (kraft > (uint64_t(1) << LMAX)) {
+      int best = -1;
+      for (int s : present)
+        if (L[s] < LMAX && (best < 0 || L[s] > L[best] || (L[s] == L[best] && s > best))) best = s;
+      kraft -= uint64_t(1) << (LMAX - L[best] - 1);
+      L[best] += 1;
+    }
+  }
+  for (int s : present) len[s] = uint8_t(L[s]);
+}
+
+void canonical(const std::vector<uint8_t>& len, std::vector<uint32_t>& code, std::vector<uint32_t>& sorted) {
+  code.assign(NSYM, 0);
+  sorted.clear();
+  for (int l = 1; l <= LMAX; ++l)
+    for (int s = 0; s < NSYM; ++s)
+      if (len[s] == l) sorted.push_back(uint32_t(s));
+  uint64_t c = 0;
+  int prev = 0;
+  for (size_t i = 0; i < sorted.size(); ++i) {
+    const int l = len[sorted[i]];
+    if (i) c = (c + 1) << (l - prev);
+    code[sorted[i]] = uint32_t(c);
+    prev = l;
+  }
+}
+
+// stream header; the code-length table lists present symbols only:
+// uint16 symbol[npresent] (ascending), then uint8 length[npresent]
+struct HuffHeader {
+  uint32_t magic, version;
+  int64_t n, nchunks, nwords, noutliers, npresent;
+};
+constexpr uint32_t kHuffMagic = 0x46484D42u;   // "BMHF"
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(size_t n) {
+    if (n) BM_HIP(hipMalloc(&p, n * sizeof(T)));
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+}  // namespace
+
+size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st) {
+  if (n < 0 || (n > 0 && !codes)) fail(BM_EINVAL, "bad code array");
+  const int64_t nch = (n + CHUNK - 1) / CHUNK;
+  DevBuf<unsigned long long> hist(NSYM);
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, hist.p, int64_t(NSYM));
+  if (n) {
+    const int64_t g = std::min<int64_t>(2048, (n + 255) / 256);
+    hipLaunchKernelGGL(k_hist, dim3(unsigned(g)), dim3(256), 0, st, codes, n, hist.p);
+  }
+  BM_HIP(hipGetLastError());
+  std::vector<uint64_t> h(NSYM);
+  BM_HIP(hipMemcpyAsync(h.data(), hist.p, NSYM * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  std::vector<uint8_t> len;
+  std::vector<uint32_t> cw, sorted;
+  code_lengths(h, len);
+  canonical(len, cw, sorted);
+  DevBuf<uint8_t> dlen(NSYM);
+  DevBuf<uint32_t> dcw(NSYM);
+  BM_HIP(hipMemcpyAsync(dlen.p, len.data(), NSYM, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dcw.p, cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  DevBuf<uint32_t> bits(size_t(std::max<int64_t>(nch, 1))), esc(size_t(std::max<int64_t>(nch, 1)));
+  if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, bits.p, esc.p);
+  BM_HIP(hipGetLastError());
+  std::vector<uint32_t> hb(nch), he(nch);
+  if (nch) {
+    BM_HIP(hipMemcpyAsync(hb.data(), bits.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    BM_HIP(hipMemcpyAsync(he.data(), esc.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  }
+  BM_HIP(hipStreamSynchronize(st));
+  std::vector<uint64_t> woff(nch + 1, 0), ooff(nch + 1, 0);
+  for (int64_t c = 0; c < nch; ++c) {
+    woff[c + 1] = woff[c] + (uint64_t(hb[c]) + 31) / 32;
+    ooff[c + 1] = ooff[c] + he[c];
+  }
+  const int64_t nw = int64_t(woff[nch]), nout = int64_t(ooff[nch]);
+  DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
+  DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
+  DevBuf<uint64_t> doidx(size_t(std::max<int64_t>(nout, 1)));
+  DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
+  BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  if (nch)
+    hipLaunchKernelGGL(k_encode, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p, dooff.p,
+                       dwords.p, doidx.p, doval.p);
+  BM_HIP(hipGetLastError());
+  std::vector<uint16_t> psym;
+  std::vector<uint8_t> plen;
+  for (int s = 0; s < NSYM; ++s)
+    if (len[s]) {
+      psym.push_back(uint16_t(s));
+      plen.push_back(len[s]);
+    }
+  const int64_t np = int64_t(psym.size());
+  HuffHeader hh{kHuffMagic, 2, n, nch, nw, nout, np};
+  const size_t bytes = sizeof(hh) + size_t(np) * 3 + (nch + 1) * 8 + size_t(nw) * 4 + size_t(nout) * 12;
+  out.resize(bytes);
+  uint8_t* o = out.data();
+  std::memcpy(o, &hh, sizeof(hh));
+  o += sizeof(hh);
+  if (np) std::memcpy(o, psym.data(), size_t(np) * 2);
+  o += size_t(np) * 2;
+  if (np) std::memcpy(o, plen.data(), size_t(np));
+  o += size_t(np);
+  std::memcpy(o, woff.data(), (nch + 1) * 8);
+  o += (nch + 1) * 8;
+  if (nw) BM_HIP(hipMemcpyAsync(o, dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, st));
+  o += size_t(nw) * 4;
+  if (nout) BM_HIP(hipMemcpyAsync(o, doidx.p, size_t(nout) * 8, hipMemcpyDeviceToHost, st));
+  o += size_t(nout) * 8;
+  if (nout) BM_HIP(hipMemcpyAsync(o, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  return bytes;
+}
+
+void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st) {
+  if (!in || in_bytes < sizeof(HuffHeader)) fail(BM_ECORRUPT, "Huffman stream too short");
+  HuffHeader hh;
+  std::memcpy(&hh, in, sizeof(hh));
+  if (hh.magic != kHuffMagic || hh.version != 2) fail(BM_ECORRUPT, "bad Huffman stream header");
+  if (hh.n != n) fail(BM_EINVAL, "symbol count does not match the destination");
+  if (hh.nchunks != (n + CHUNK - 1) / CHUNK || hh.nwords < 0 || hh.noutliers < 0 || hh.noutliers > n ||
+      hh.npresent < 0 || hh.npresent > NSYM || hh.nwords > (int64_t(1) << 40))
+    fail(BM_ECORRUPT, "inconsistent Huffman stream header");
+  const int64_t nch = hh.nchunks, nw = hh.nwords, nout = hh.noutliers, np = hh.npresent;
+  const size_t need = sizeof(hh) + size_t(np) * 3 + size_t(nch + 1) * 8 + size_t(nw) * 4 + size_t(nout) * 12;
+  if (in_bytes < need) fail(BM_ECORRUPT, "Huffman stream truncated");
+  const uint8_t* p = in + sizeof(hh);
+  std::vector<uint8_t> len(NSYM, 0);
+  {
+    std::vector<uint16_t> psym(np);
+    if (np) std::memcpy(psym.data(), p, size_t(np) * 2);
+    for (int64_t k = 0; k < np; ++k) {
+      if (k && psym[k] <= psym[k - 1]) fail(BM_ECORRUPT, "code table symbols out of order");
+      len[psym[k]] = p[size_t(np) * 2 + k];
+      if (len[psym[k]] == 0) fail(BM_ECORRUPT, "zero code length in the table");
+    }
+  }
+  p += size_t(np) * 3;
+  std::vector<uint64_t> woff(nch + 1);
+  std::memcpy(woff.data(), p, (nch + 1) * 8);
+  p += (nch + 1) * 8;
+  for (int64_t c = 0; c < nch; ++c)
+    if (woff[c + 1] < woff[c] || woff[c + 1] > uint64_t(nw)) fail(BM_ECORRUPT, "bad chunk offsets");
+  uint64_t kraft = 0;
+  for (int s = 0; s < NSYM; ++s) {
+    if (len[s] > LMAX) fail(BM_ECORRUPT, "code length above 32");
+    if (len[s]) kraft += uint64_t(1) << (LMAX - len[s]);
+  }
+  if (kraft > (uint64_t(1) << LMAX)) fail(BM_ECORRUPT, "code lengths violate Kraft's inequality");
+  std::vector<uint32_t> cw, sorted;
+  canonical(len, cw, sorted);
+  std::vector<uint32_t> first(LMAX + 1, 0), count(LMAX + 1, 0), base(LMAX + 1, 0), lut(1u << LUTB, 0);
+  for (size_t i = 0; i < sorted.size(); ++i) {
+    const int l = len[sorted[i]];
+    if (count[l] == 0) {
+      first[l] = cw[sorted[i]];
+      base[l] = uint32_t(i);
+    }
+    ++count[l];
+    if (l <= LUTB) {
+      const uint32_t lo = cw[sorted[i]] << (LUTB - l), span = 1u << (LUTB - l);
+      for (uint32_t k = 0; k < span; ++k) lut[lo + k] = sorted[i] | (uint32_t(l) << 16);
+    }
+  }
+  DevBuf<uint32_t> dlut(lut.size()), dfirst(LMAX + 1), dcount(LMAX + 1), dbase(LMAX + 1),
+      dsorted(std::max<size_t>(sorted.size(), 1));
+  DevBuf<uint64_t> dwoff(nch + 1);
+  DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
+  DevBuf<uint64_t> doidx(size_t(std::max<int64_t>(nout, 1)));
+  DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
+  DevBuf<int> derr(1);
+  BM_HIP(hipMemcpyAsync(dlut.p, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dfirst.p, first.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dcount.p, count.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dbase.p, base.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
+  if (!sorted.empty()) BM_HIP(hipMemcpyAsync(dsorted.p, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
+  if (nw) BM_HIP(hipMemcpyAsync(dwords.p, p, size_t(nw) * 4, hipMemcpyHostToDevice, st));
+  p += size_t(nw) * 4;
+  if (nout) BM_HIP(hipMemcpyAsync(doidx.p, p, size_t(nout) * 8, hipMemcpyHostToDevice, st));
+  p += size_t(nout) * 8;
+  if (nout) BM_HIP(hipMemcpyAsync(doval.p, p, size_t(nout) * 4, hipMemcpyHostToDevice, st));
+  const int zero = 0;
+  BM_HIP(hipMemcpyAsync(derr.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  DecTables t{dlut.p, dfirst.p, dcount.p, dbase.p, dsorted.p};
+  if (nch)
+    hipLaunchKernelGGL(k_decode, dim3(unsigned((nch + 63) / 64)), dim3(64), 0, st, dwords.p, dwoff.p, nch, n, t,
+                       doidx.p, doval.p, nout, codes, derr.p);
+  BM_HIP(hipGetLastError());
+  int herr = 0;
+  BM_HIP(hipMemcpyAsync(&herr, derr.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  if (herr) fail(BM_ECORRUPT, "Huffman stream does not decode");
+}
+
+}  // namespace bm

@@ -1,0 +1,155 @@
+// Internal declarations of the BlockMGARD library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "blockmgard.h"
+
+namespace bm {
+
+constexpr int kMaxBoxes = 4096;
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  bm_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(bm_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+#define BM_HIP(call) ::bm::check_hip((call), #call)
+
+__host__ __device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
+__host__ __device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------- views
+// A 3D strided view of device memory: element (z, y, x) lives at
+// ptr + z*s[0] + y*s[1] + x*s[2] (strides in elements).
+struct View3 {
+  void* ptr;
+  int64_t n[3];
+  int64_t s[3];
+};
+
+inline View3 dense_view(void* p, const int64_t n[3]) {
+  return View3{p, {n[0], n[1], n[2]}, {n[1] * n[2], n[2], 1}};
+}
+
+// ---------------------------------------------------------------- levels
+// Level s (1-based) maps the grid G^{s-1} (dims n) to details on its
+// fine-only nodes plus the coarse grid G^s (dims m).
+struct Level {
+  bool local;          // In-cache Block level (face-fixed blocks) or global
+  int64_t n[3];        // dims of G^{s-1}
+  int64_t m[3];        // dims of G^s
+  int64_t nb[3];       // blocks per axis (local levels)
+  int64_t ps[3];       // spacing of G^{s-1} nodes in the padded grid, per axis
+  bool coarsen[3];     // axis is halved at this level (false: length <= 2 stays)
+  double gain;         // rounded-up L-inf gain of this level's details
+  double* d_inv[3];    // device: Thomas reciprocal pivots of the coarse mass matrix (global levels)
+};
+
+// Device workspace sizes and buffers owned by a plan.
+struct Workspace {
+  std::vector<void*> grid;       // grid[s] = compact G^s, s = 1..L+M (grid[0] unused)
+  void* t1 = nullptr;            // global-level pass temporaries
+  void* t2 = nullptr;
+  size_t t_elems = 0;
+  void* codes = nullptr;         // int32, padded grid (compress path)
+  void* coeff = nullptr;         // dtype, padded grid (compress path)
+  double* tolbuf = nullptr;      // propagated block tolerances, all local levels
+  double* qparam = nullptr;      // per-level quantizer parameters (device)
+  std::vector<int64_t> tol_off;  // offset of level-s block map in tolbuf
+  int64_t* counters = nullptr;   // device scratch counters (stats)
+  double* boxbuf = nullptr;      // device copy of an ROI box list (kMaxBoxes x 7)
+  double* boxhost = nullptr;     // pinned staging for the box list
+};
+
+}  // namespace bm
+
+namespace bm {
+// Optional per-level event timing (bm_timing): pending event pairs per slot.
+struct Timing {
+  bool on = false;
+  struct Pending {
+    int slot;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<double> ms;
+  std::vector<int64_t> calls;
+};
+}  // namespace bm
+
+struct bm_plan_s {
+  bm::Timing timing;
+  bm_config cfg;
+  int device;
+  size_t esize;                  // bytes per element of dtype
+  int64_t dims[3];               // logical
+  int64_t pdims[3];              // padded
+  int L, M, nlev;
+  std::vector<bm::Level> lv;     // lv[0] is level 1
+  bm::Workspace ws;
+  int64_t nb1[3];                // level-1 block grid (1,1,1 when L == 0)
+};
+
+namespace bm {
+
+int64_t padded_length(int64_t n, int b, int L, int M);
+double level_gain_local(int b);
+double level_gain_global(const int64_t n[3]);
+void thomas_pivots_natural(int64_t m, std::vector<double>& inv);
+
+// ---- kernels (launchers, stream-ordered) ----
+void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff,
+                     void* coarse_out, hipStream_t st);
+void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* coarse_in, void* out,
+                     bool last, hipStream_t st);
+
+// global level pieces
+void global_details(const bm_plan_s& p, int s, const void* u, void* coeff, hipStream_t st);
+void global_interp_add(const bm_plan_s& p, int s, const void* coeff, const void* uc, void* out,
+                       hipStream_t st);
+// restriction + tridiagonal solve along one axis (0=z,1=y,2=x) of a view;
+// mask: zero the coarse nodes of the level on load; base != null: out = base - result
+void line_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
+               const void* base, hipStream_t st);
+void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t st);
+
+// decompose / recompose drivers
+void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st);
+void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st);
+
+// quantization
+void tolmap_from_boxes(bm_plan_s& p, const double* boxes, int nbox, double background, double* block_tol,
+                       hipStream_t st);
+void tolmap_from_voxels(bm_plan_s& p, const double* voxel_tol, double* block_tol, hipStream_t st);
+void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t* codes, bm_qstats* stats,
+              hipStream_t st);
+void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* coeff, hipStream_t st);
+
+// huffman (host buffers)
+size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);
+void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);
+
+// RAII event pair around the work of one timing slot (no-op unless timing is on)
+struct TimedScope {
+  bm_plan_s& p;
+  int slot;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedScope(bm_plan_s& p_, int slot_, hipStream_t st_);
+  ~TimedScope();
+};
+
+// plan view of a coefficient array for level s (nodes of G^{s-1} inside the padded grid)
+View3 level_view(const bm_plan_s& p, int s, void* coeff);
+View3 coarsest_view(const bm_plan_s& p, void* coeff);
+
+}  // namespace bm

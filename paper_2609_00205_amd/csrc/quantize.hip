@@ -1,0 +1,442 @@
+// ROI tolerance maps and the reciprocal quantizer (Sec. IV-C, IV-D).
+//
+// Block-wise tolerance assignment: a level-1 block takes the minimum voxel
+// tolerance over its closed node range (a partly covered block is strict;
+// padded nodes count as the node they copy).  Conservative propagation
+// (Eq. 2): a block of local level s+1 takes the minimum over the level-s
+// blocks that share a node with it.  Global levels use tau_global, the
+// minimum over the last local level.
+//
+// Budget (the L-infinity bound of Sec. II-B, with T = L + M + 1 shares):
+// a detail of level s on a node with tolerance tau gets bin width
+// Delta = tau * kappa_s, kappa_s = 2 (1 - eta) / (T A_s), where A_s is the
+// level's L-infinity gain; the coarsest values get kappa = 2 (1 - eta) / T.
+// q = rint(c * (1/Delta)) in FP64 (the per-block reciprocal quantizer of
+// Sec. IV-D), c_hat = q * Delta.  A node inside several blocks of its level
+// uses the smallest Delta (largest reciprocal) of those blocks; because
+// rounding is monotone this equals computing Delta from the smallest tau.
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace bm {
+namespace {
+
+constexpr int NT = 256;
+
+inline unsigned grid_for(int64_t tot) {
+  int64_t g = (tot + NT - 1) / NT;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+// tolerances are positive doubles: their bit patterns order like the values
+__device__ inline void atomic_min_pos(double* p, double v) {
+  atomicMin(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) p[i] = v;
+}
+
+struct BoxArgs {
+  const double* boxes;   // nbox x 7
+  int nbox;
+  double background;
+  int64_t n[3];          // logical dims
+  int64_t nb[3];
+  int64_t w;             // block width in nodes (b-1); 0 when L == 0 (one block)
+  double* out;
+};
+
+__global__ void k_tol_boxes(BoxArgs a) {
+  const int64_t nbt = a.nb[0] * a.nb[1] * a.nb[2];
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < nbt; k += int64_t(gridDim.x) * NT) {
+    const int64_t bx = k % a.nb[2], t = k / a.nb[2], by = t % a.nb[1], bz = t / a.nb[1];
+    const int64_t bi[3] = {bz, by, bx};
+    int64_t lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      if (a.w == 0) {
+        lo[d] = 0;
+        hi[d] = a.n[d] - 1;
+      } else {
+        lo[d] = i64min(bi[d] * a.w, a.n[d] - 1);
+        hi[d] = i64min((bi[d] + 1) * a.w, a.n[d] - 1);
+      }
+    }
+    double v = a.background;
+    for (int j = 0; j < a.nbox; ++j) {
+      const double* r = a.boxes + 7 * j;
+      bool hit = true;
+      for (int d = 0; d < 3; ++d) {
+        const int64_t b0 = int64_t(r[d]), b1 = int64_t(r[d + 3]);
+        hit = hit && b0 < b1 && b0 <= hi[d] && b1 > lo[d];
+      }
+      if (hit && r[6] < v) v = r[6];
+    }
+    a.out[k] = v;
+  }
+}
+
+struct VoxArgs {
+  const double* vt;
+  int64_t n[3];
+  int64_t nb[3];
+  int64_t w;
+  double* out;
+};
+
+// one workgroup per block: min over the block's closed node range
+__global__ __launch_bounds__(NT) void k_tol_voxels(VoxArgs a) {
+  __shared__ double red[NT];
+  const int64_t k = blockIdx.x;
+  const int64_t bx = k % a.nb[2], t = k / a.nb[2], by = t % a.nb[1], bz = t / a.nb[1];
+  const int64_t bi[3] = {bz, by, bx};
+  int64_t lo[3], ext[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = i64min(bi[d] * a.w, a.n[d] - 1);
+    ext[d] = i64min((bi[d] + 1) * a.w, a.n[d] - 1) - lo[d] + 1;
+  }
+  double v = INFINITY;
+  const int64_t cnt = ext[0] * ext[1] * ext[2];
+  for (int64_t i = threadIdx.x; i < cnt; i += NT) {
+    const int64_t x = i % ext[2], r = i / ext[2], y = r % ext[1], z = r / ext[1];
+    const double tv = a.vt[((lo[0] + z) * a.n[1] + lo[1] + y) * a.n[2] + lo[2] + x];
+    v = tv < v ? tv : v;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.out[k] = red[0];
+}
+
+// min over everything (L == 0): grid-stride + atomic min into out[0] (pre-filled with +inf)
+__global__ __launch_bounds__(NT) void k_min_all(const double* v, int64_t n, double* out) {
+  __shared__ double red[NT];
+  double m = INFINITY;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) m = fmin(m, v[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomic_min_pos(out, red[0]);
+}
+
+struct PropArgs {
+  const double* in;
+  int64_t nb[3];        // level s blocks
+  double* out;
+  int64_t nn[3];        // level s+1 blocks
+};
+
+// Eq. 2: next-level block I spans blocks 2I, 2I+1 and touches 2I-1, 2I+2 in a face.
+__global__ void k_propagate(PropArgs a) {
+  const int64_t tot = a.nn[0] * a.nn[1] * a.nn[2];
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < tot; k += int64_t(gridDim.x) * NT) {
+    const int64_t X = k % a.nn[2], t = k / a.nn[2], Y = t % a.nn[1], Z = t / a.nn[1];
+    double v = INFINITY;
+    for (int64_t z = i64max(0, 2 * Z - 1); z <= i64min(a.nb[0] - 1, 2 * Z + 2); ++z)
+      for (int64_t y = i64max(0, 2 * Y - 1); y <= i64min(a.nb[1] - 1, 2 * Y + 2); ++y)
+        for (int64_t x = i64max(0, 2 * X - 1); x <= i64min(a.nb[2] - 1, 2 * X + 2); ++x)
+          v = fmin(v, a.in[(z * a.nb[1] + y) * a.nb[2] + x]);
+    a.out[k] = v;
+  }
+}
+
+// per-block Delta and 1/Delta of one local level
+__global__ void k_block_delta(const double* tau, int64_t n, double kappa, double* delta, double* inv) {
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT) {
+    const double d = tau[k] * kappa;
+    delta[k] = d;
+    inv[k] = 1.0 / d;
+  }
+}
+
+// scalar Delta for the global levels and the coarsest values from tau_global
+struct ScalarArgs {
+  const double* tau_global;
+  int n;
+  double kappa[26];
+  double* q;            // q[2 i] = Delta, q[2 i + 1] = 1 / Delta
+};
+
+__global__ void k_scalar_delta(ScalarArgs a) {
+  const int i = threadIdx.x;
+  if (i < a.n) {
+    const double d = a.tau_global[0] * a.kappa[i];
+    a.q[2 * i] = d;
+    a.q[2 * i + 1] = 1.0 / d;
+  }
+}
+
+__global__ void k_zero_counters(int64_t* c) {
+  if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+struct QArgs {
+  int64_t P[3];               // padded dims
+  int L, M;
+  int D[3];                   // levels each axis coarsens
+  int64_t w;                  // b - 1
+  // per-block Delta and 1/Delta: slot s-1 for the details of local level s;
+  // slot kCoarseSlot for the coarsest values when M == 0 (level-L blocks)
+  const double* bdelta[9];
+  const double* binv[9];
+  int64_t nb[9][3];
+  const double* q;            // scalar Delta / inverse per level (index s-1), coarsest at L+M
+  int64_t* counters;          // [0] outliers, [1] max |q|, [2] out of range
+};
+
+__device__ inline int ctz64(int64_t v) { return v == 0 ? 64 : __builtin_ctzll(static_cast<unsigned long long>(v)); }
+
+// level of a node: 1..L+M for a detail of that level, L+M+1 for a coarsest value
+__device__ inline int node_level(const QArgs& a, int64_t g0, int64_t g1, int64_t g2) {
+  int lev = a.L + a.M + 1;
+  const int64_t g[3] = {g0, g1, g2};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t = ctz64(g[d]);
+    if (t < a.D[d] && t + 1 < lev) lev = t + 1;
+  }
+  return lev;
+}
+
+constexpr int kCoarseSlot = 8;
+
+// Delta and 1/Delta of a node whose tolerance comes from the blocks of local
+// level s (grid coordinates q = g >> (s-1)), from table slot `slot`.
+__device__ inline void block_delta(const QArgs& a, int s, int slot, int64_t g0, int64_t g1, int64_t g2,
+                                   double& del, double& inv) {
+  const int64_t q[3] = {g0 >> (s - 1), g1 >> (s - 1), g2 >> (s - 1)};
+  int64_t lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t nb = a.nb[slot][d];
+    const int64_t f = q[d] / a.w;
+    lo[d] = (q[d] % a.w == 0 && q[d] > 0) ? f - 1 : f;
+    hi[d] = f < nb - 1 ? f : nb - 1;
+    if (lo[d] > hi[d]) lo[d] = hi[d];
+  }
+  del = INFINITY;
+  inv = 0.0;
+  const double* bd = a.bdelta[slot];
+  const double* bi = a.binv[slot];
+  for (int64_t z = lo[0]; z <= hi[0]; ++z)
+    for (int64_t y = lo[1]; y <= hi[1]; ++y)
+      for (int64_t x = lo[2]; x <= hi[2]; ++x) {
+        const int64_t k = (z * a.nb[slot][1] + y) * a.nb[slot][2] + x;
+        del = fmin(del, bd[k]);
+        inv = fmax(inv, bi[k]);
+      }
+}
+
+__device__ inline void node_delta(const QArgs& a, int64_t z, int64_t y, int64_t x, double& del, double& inv) {
+  const int lev = node_level(a, z, y, x);
+  if (lev <= a.L) {
+    block_delta(a, lev, lev - 1, z, y, x, del, inv);
+  } else if (lev == a.L + a.M + 1 && a.M == 0) {
+    block_delta(a, a.L, kCoarseSlot, z, y, x, del, inv);
+  } else {
+    del = a.q[2 * (lev - 1)];
+    inv = a.q[2 * (lev - 1) + 1];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* codes) {
+  const int64_t tot = a.P[0] * a.P[1] * a.P[2];
+  int64_t nout = 0, mx = 0, bad = 0;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    const int64_t x = i % a.P[2], t = i / a.P[2], y = t % a.P[1], z = t / a.P[1];
+    double del, inv;
+    node_delta(a, z, y, x, del, inv);
+    const double v = rint(double(c[i]) * inv);
+    int32_t qv;
+    if (!(fabs(v) <= 2147483647.0)) {
+      bad = 1;
+      qv = 0;
+    } else {
+      qv = int32_t(v);
+    }
+    codes[i] = qv;
+    const int64_t aq = qv < 0 ? -int64_t(qv) : int64_t(qv);
+    nout += aq >= 32768;
+    mx = aq > mx ? aq : mx;
+  }
+  // wave reductions then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) {
+    nout += __shfl_down(nout, off, 64);
+    const int64_t o = __shfl_down(mx, off, 64);
+    mx = o > mx ? o : mx;
+    bad |= __shfl_down(bad, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (nout) atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[0]), static_cast<unsigned long long>(nout));
+    atomicMax(reinterpret_cast<unsigned long long*>(&a.counters[1]), static_cast<unsigned long long>(mx));
+    if (bad) atomicMax(reinterpret_cast<unsigned long long*>(&a.counters[2]), 1ull);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dequantize(QArgs a, const int32_t* codes, T* c) {
+  const int64_t tot = a.P[0] * a.P[1] * a.P[2];
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    const int64_t x = i % a.P[2], t = i / a.P[2], y = t % a.P[1], z = t / a.P[1];
+    double del, inv;
+    node_delta(a, z, y, x, del, inv);
+    c[i] = T(double(codes[i]) * del);
+  }
+}
+
+int64_t prod3(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
+
+// Build every per-level quantizer table on the device from the level-1 map.
+QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+  if (p.L > 8) fail(BM_EUNSUPPORTED, "more than 8 local levels");
+  QArgs a{};
+  for (int d = 0; d < 3; ++d) {
+    a.P[d] = p.pdims[d];
+    int D = 0;
+    for (auto& L : p.lv) D += L.coarsen[d] ? 1 : 0;
+    a.D[d] = D;
+  }
+  a.L = p.L;
+  a.M = p.M;
+  a.w = p.L > 0 ? p.cfg.block - 1 : 1;
+  a.counters = p.ws.counters;
+  const int T = p.L + p.M + 1;
+  const double eta = p.cfg.eta;
+  const int64_t tot = p.ws.tol_off[p.L + 1];
+  double* tau = p.ws.tolbuf;
+  double* bdel = p.ws.tolbuf + tot;
+  double* binv = p.ws.tolbuf + 2 * tot;
+  double* tg = p.ws.tolbuf + 3 * tot;    // tau_global
+  if (p.L > 0) {
+    BM_HIP(hipMemcpyAsync(tau, block_tol, size_t(prod3(p.nb1)) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int s = 1; s < p.L; ++s) {
+      PropArgs pa{tau + p.ws.tol_off[s], {}, tau + p.ws.tol_off[s + 1], {}};
+      for (int d = 0; d < 3; ++d) {
+        pa.nb[d] = p.lv[s - 1].nb[d];
+        pa.nn[d] = p.lv[s].nb[d];
+      }
+      hipLaunchKernelGGL(k_propagate, dim3(grid_for(prod3(pa.nn))), dim3(NT), 0, st, pa);
+    }
+    for (int s = 1; s <= p.L; ++s) {
+      const double kap = (2.0 * (1.0 - eta)) / (double(T) * p.lv[s - 1].gain);
+      const int64_t nbs = prod3(p.lv[s - 1].nb);
+      const int64_t off = p.ws.tol_off[s];
+      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, tau + off, nbs, kap, bdel + off,
+                         binv + off);
+      a.bdelta[s - 1] = bdel + off;
+      a.binv[s - 1] = binv + off;
+      for (int d = 0; d < 3; ++d) a.nb[s - 1][d] = p.lv[s - 1].nb[d];
+    }
+    const int64_t lastoff = p.ws.tol_off[p.L];
+    const int64_t nlast = prod3(p.lv[p.L - 1].nb);
+    if (p.M == 0) {
+      // coarsest values (no gain): Delta = tau * 2 (1 - eta) / T over the level-L blocks
+      double* cdel = tg + 8;
+      double* cinv = cdel + nlast;
+      const double kc = (2.0 * (1.0 - eta)) / double(T);
+      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nlast)), dim3(NT), 0, st, tau + lastoff, nlast, kc, cdel, cinv);
+      a.bdelta[kCoarseSlot] = cdel;
+      a.binv[kCoarseSlot] = cinv;
+      for (int d = 0; d < 3; ++d) a.nb[kCoarseSlot][d] = p.lv[p.L - 1].nb[d];
+    }
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
+    hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, tau + lastoff, nlast, tg);
+  } else {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
+    hipLaunchKernelGGL(k_min_all, dim3(1), dim3(NT), 0, st, block_tol, int64_t(1), tg);
+  }
+  ScalarArgs sa{};
+  sa.tau_global = tg;
+  sa.n = p.nlev + 1;
+  for (int s = 1; s <= p.nlev; ++s) sa.kappa[s - 1] = (2.0 * (1.0 - eta)) / (double(T) * p.lv[s - 1].gain);
+  sa.kappa[p.nlev] = (2.0 * (1.0 - eta)) / double(T);
+  sa.q = p.ws.qparam;
+  hipLaunchKernelGGL(k_scalar_delta, dim3(1), dim3(64), 0, st, sa);
+  BM_HIP(hipGetLastError());
+  a.q = p.ws.qparam;
+  return a;
+}
+
+}  // namespace
+
+void tolmap_from_boxes(bm_plan_s& p, const double* boxes, int nbox, double background, double* block_tol,
+                       hipStream_t st) {
+  if (nbox < 0 || (nbox > 0 && !boxes)) fail(BM_EINVAL, "bad box list");
+  if (!(background > 0) || !std::isfinite(background)) fail(BM_ENONFINITE, "background tolerance must be positive and finite");
+  for (int j = 0; j < nbox; ++j)
+    if (!(boxes[7 * j + 6] > 0) || !std::isfinite(boxes[7 * j + 6])) fail(BM_ENONFINITE, "box tolerance must be positive and finite");
+  if (nbox > kMaxBoxes) fail(BM_EINVAL, "at most 4096 boxes");
+  double* dbox = nullptr;
+  if (nbox) {
+    // the caller's list goes through pinned staging; the call then waits for
+    // the copy so the staging buffer can be reused
+    std::copy(boxes, boxes + 7 * nbox, p.ws.boxhost);
+    BM_HIP(hipMemcpyAsync(p.ws.boxbuf, p.ws.boxhost, size_t(nbox) * 7 * sizeof(double), hipMemcpyHostToDevice, st));
+    dbox = p.ws.boxbuf;
+  }
+  BoxArgs a{dbox, nbox, background, {p.dims[0], p.dims[1], p.dims[2]}, {p.nb1[0], p.nb1[1], p.nb1[2]},
+            p.L > 0 ? p.cfg.block - 1 : 0, block_tol};
+  hipLaunchKernelGGL(k_tol_boxes, dim3(grid_for(prod3(p.nb1))), dim3(NT), 0, st, a);
+  BM_HIP(hipGetLastError());
+  if (dbox) BM_HIP(hipStreamSynchronize(st));
+}
+
+void tolmap_from_voxels(bm_plan_s& p, const double* voxel_tol, double* block_tol, hipStream_t st) {
+  if (p.L > 0) {
+    VoxArgs a{voxel_tol, {p.dims[0], p.dims[1], p.dims[2]}, {p.nb1[0], p.nb1[1], p.nb1[2]}, p.cfg.block - 1, block_tol};
+    hipLaunchKernelGGL(k_tol_voxels, dim3(unsigned(prod3(p.nb1))), dim3(NT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, block_tol, int64_t(1), double(INFINITY));
+    hipLaunchKernelGGL(k_min_all, dim3(grid_for(prod3(p.dims))), dim3(NT), 0, st, voxel_tol, prod3(p.dims), block_tol);
+  }
+  BM_HIP(hipGetLastError());
+}
+
+void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t* codes, bm_qstats* stats,
+              hipStream_t st) {
+  const int64_t tot = prod3(p.pdims);
+  {
+    TimedScope ts(p, 2 * p.nlev, st);
+    QArgs a = prepare(p, block_tol, st);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, p.ws.counters);
+    if (p.cfg.dtype == BM_F32)
+      hipLaunchKernelGGL(k_quantize<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a, static_cast<const float*>(coeff), codes);
+    else
+      hipLaunchKernelGGL(k_quantize<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a, static_cast<const double*>(coeff), codes);
+    BM_HIP(hipGetLastError());
+  }
+  if (stats) {
+    int64_t h[4];
+    BM_HIP(hipMemcpyAsync(h, p.ws.counters, sizeof(h), hipMemcpyDeviceToHost, st));
+    BM_HIP(hipStreamSynchronize(st));
+    stats->n_codes = tot;
+    stats->n_outliers = h[0];
+    stats->max_abs_code = h[1];
+    if (h[2]) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+  }
+}
+
+void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* coeff, hipStream_t st) {
+  TimedScope ts(p, 2 * p.nlev + 1, st);
+  QArgs a = prepare(p, block_tol, st);
+  const int64_t tot = prod3(p.pdims);
+  if (p.cfg.dtype == BM_F32)
+    hipLaunchKernelGGL(k_dequantize<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a, codes, static_cast<float*>(coeff));
+  else
+    hipLaunchKernelGGL(k_dequantize<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a, codes, static_cast<double*>(coeff));
+  BM_HIP(hipGetLastError());
+}
+
+}  // namespace bm

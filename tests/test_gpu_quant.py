@@ -1,0 +1,188 @@
+"""GPU ROI quantization and lossless stage against the oracle, through the C ABI.
+
+* block tolerance maps (boxes, voxel masks) equal the oracle's exactly;
+* the per-level gains equal the oracle's (computed independently);
+* codes are bit-exact given the same coefficients (both sides decide in FP64);
+* end to end, max |x - x_hat| never exceeds the voxel's bound;
+* Huffman streams are bit-exact given equal codes and decode back;
+* compress / decompress keep every bound, raw fallback included.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import huffman as ohf
+from oracle import mgard, roi
+from paper_2609_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_00205_amd import _lib
+    _lib.lib()
+
+
+def _plan(shape, b, L, M, dt=torch.float32, eta=None):
+    from paper_2609_00205_amd import Plan
+    return Plan(shape, dtype=dt, block=b, L=L, M=M, eta=eta)
+
+
+CASES = [((33, 33, 33), 17, 1, 2), ((20, 30, 12), 9, 1, 1), ((33, 17, 65), 9, 2, 1),
+         ((65, 65, 65), 17, 0, 6), ((33, 33, 17), 9, 2, 0), ((97, 65, 129), 17, 1, 2)]
+
+
+def _boxes(shape, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(2):
+        e = [max(2, s // 5) for s in shape]
+        o = [int(rng.integers(0, s - ee + 1)) for s, ee in zip(shape, e)]
+        out.append((o[0], o[1], o[2], o[0] + e[0], o[1] + e[1], o[2] + e[2], 10.0 ** (-5 - k)))
+    return out
+
+
+@pytest.mark.parametrize("shape,b,L,M", CASES)
+def test_gains_match_oracle(shape, b, L, M):
+    p = _plan(shape, b, L, M)
+    h = mgard.hierarchy(shape, b, L, M)
+    assert p.gains == roi.level_gains(h)
+
+
+@pytest.mark.parametrize("shape,b,L,M", CASES)
+def test_tolmap_boxes_and_voxels(shape, b, L, M):
+    p = _plan(shape, b, L, M)
+    h = mgard.hierarchy(shape, b, L, M)
+    boxes = _boxes(shape, 3)
+    vt = roi.voxel_tolerance_from_boxes(shape, boxes, 1e-2)
+    ref = roi.block_tolerance(vt, h.shape_p, b) if L > 0 else np.array([[[vt.min()]]])
+    got = p.tolmap_from_boxes(boxes, 1e-2).cpu().numpy()
+    assert np.array_equal(got.reshape(ref.shape), ref)
+    rng = np.random.default_rng(1)
+    vt2 = 10.0 ** rng.uniform(-6, -2, shape)
+    ref2 = roi.block_tolerance(vt2, h.shape_p, b) if L > 0 else np.array([[[vt2.min()]]])
+    got2 = p.tolmap_from_voxels(torch.from_numpy(vt2).cuda()).cpu().numpy()
+    assert np.array_equal(got2.reshape(ref2.shape), ref2)
+
+
+@pytest.mark.parametrize("shape,b,L,M", CASES)
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_codes_bit_exact_given_equal_coefficients(shape, b, L, M, dt):
+    p = _plan(shape, b, L, M, dt)
+    h = mgard.hierarchy(shape, b, L, M)
+    boxes = _boxes(shape, 4)
+    vt = roi.voxel_tolerance_from_boxes(shape, boxes, 1e-3)
+    tol1 = roi.block_tolerance(vt, h.shape_p, b) if L > 0 else vt.min()
+    x = synth.gaussian_random_field(shape, 3.0, seed=21, dtype=np.float64)
+    coeff = mgard.decompose(x, b, L, M).astype(np.float32 if dt == torch.float32 else np.float64)
+    delta = roi.node_delta(h, tol1, p.eta)
+    ref = roi.quantize(coeff.astype(np.float64), delta)
+    bt = torch.from_numpy(np.asarray(tol1, np.float64).reshape(p.block_grid)).cuda()
+    codes, st = p.quantize(torch.from_numpy(coeff).cuda(), bt)
+    got = codes.cpu().numpy()
+    assert np.array_equal(got, ref), int((got != ref).sum())
+    assert st["n_outliers"] == int((np.abs(ref) >= 32768).sum())
+    assert st["max_abs_code"] == int(np.abs(ref).max())
+    deq = p.dequantize(codes, bt).cpu().double().numpy()
+    cast = np.float32 if dt == torch.float32 else np.float64
+    assert np.array_equal(deq, roi.dequantize(ref, delta).astype(cast).astype(np.float64))
+
+
+@pytest.mark.parametrize("shape,b,L,M", CASES)
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_end_to_end_bound_holds(shape, b, L, M, dt):
+    p = _plan(shape, b, L, M, dt)
+    boxes = _boxes(shape, 5)
+    x = synth.gaussian_random_field(shape, 3.0, seed=22, dtype=np.float64)
+    scale = np.abs(x).max()
+    boxes = [bx[:6] + (bx[6] * scale,) for bx in boxes]
+    vt = roi.voxel_tolerance_from_boxes(shape, boxes, 1e-2 * scale)
+    xd = torch.from_numpy(x).to(dt).cuda()
+    bt = p.tolmap_from_boxes(boxes, 1e-2 * scale)
+    codes, _ = p.quantize(p.decompose(xd), bt)
+    xr = p.recompose(p.dequantize(codes, bt)).cpu().double().numpy()
+    x_in = xd.cpu().double().numpy()
+    err = np.abs(xr - x_in)
+    print("worst error / bound", float((err / vt).max()))
+    assert np.all(err <= vt)
+    # codes close to the oracle's: equal except near bin edges (coefficients differ by rounding)
+    h = mgard.hierarchy(shape, b, L, M)
+    tol1 = roi.block_tolerance(vt, h.shape_p, b) if L > 0 else vt.min()
+    ref = roi.quantize(mgard.decompose(x_in, b, L, M), roi.node_delta(h, tol1, p.eta))
+    diff = np.abs(codes.cpu().numpy().astype(np.int64) - ref)
+    print("codes differing from the oracle (edge cases):", int((diff > 0).sum()), "of", diff.size)
+    assert diff.max() <= (1 if dt == torch.float64 else 3)
+
+
+def _laplace_codes(n, seed, scale=4.0):
+    rng = np.random.default_rng(seed)
+    q = np.rint(rng.laplace(0, scale, n)).astype(np.int64)
+    q[rng.choice(n, max(1, n // 5000), replace=False)] = rng.integers(-(1 << 20), 1 << 20, max(1, n // 5000))
+    return q.astype(np.int32)
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 100_000, 1_000_003])
+def test_huffman_bit_exact(n):
+    from paper_2609_00205_amd import api
+    q = _laplace_codes(n, n)
+    buf = api.huffman_encode(torch.from_numpy(q).cuda())
+    got = api.parse_huffman(buf)
+    sym, oi, ov = ohf.to_symbols(q)
+    ln = ohf.code_lengths(ohf.histogram(sym))
+    words, offs = ohf.encode(sym, ln)
+    assert got["magic"] == 0x46484D42 and got["n"] == n
+    assert np.array_equal(got["lengths"], ln.astype(np.uint8))
+    assert np.array_equal(got["offsets"].astype(np.int64), offs)
+    assert np.array_equal(got["words"], words)
+    assert np.array_equal(got["outlier_index"].astype(np.int64), oi)
+    assert np.array_equal(got["outlier_value"].astype(np.int64), ov)
+    dec = api.huffman_decode(buf, n).cpu().numpy()
+    assert np.array_equal(dec, q)
+
+
+def test_huffman_corrupt_stream_rejected():
+    from paper_2609_00205_amd import api, _lib
+    q = _laplace_codes(10000, 3)
+    buf = bytearray(api.huffman_encode(torch.from_numpy(q).cuda()))
+    buf[0] ^= 0xFF
+    with pytest.raises(_lib.BMError) as e:
+        api.huffman_decode(bytes(buf), 10000)
+    assert e.value.code == -6
+
+
+@pytest.mark.parametrize("shape,b,L,M", CASES[:4])
+def test_compress_decompress(shape, b, L, M):
+    from paper_2609_00205_amd import api
+    p = _plan(shape, b, L, M)
+    x = synth.gaussian_random_field(shape, 3.0, seed=23, dtype=np.float32)
+    scale = float(np.abs(x).max())
+    boxes = [bx[:6] + (bx[6] * scale,) for bx in _boxes(shape, 6)]
+    bt = p.tolmap_from_boxes(boxes, 1e-2 * scale)
+    xd = torch.from_numpy(x).cuda()
+    buf = p.compress(xd, bt)
+    assert api.compressed_config(buf)["shape"] == shape
+    xr = api.decompress(buf).cpu().double().numpy()
+    vt = roi.voxel_tolerance_from_boxes(shape, boxes, 1e-2 * scale)
+    assert np.all(np.abs(xr - x.astype(np.float64)) <= vt)
+    print("compression ratio", x.nbytes / len(buf))
+    assert len(buf) < x.nbytes
+    bad = bytearray(buf)
+    bad[len(bad) // 2] ^= 0x10
+    with pytest.raises(Exception):
+        api.decompress(bytes(bad))
+
+
+@pytest.mark.parametrize("tol", [1e-7, 1e-12])
+def test_raw_fallback_for_incompressible_data(tol):
+    # 1e-7: the coded stream is larger than the data; 1e-12: codes exceed 32 bits
+    from paper_2609_00205_amd import api
+    shape = (17, 17, 17)
+    p = _plan(shape, 9, 1, 1)
+    x = np.random.default_rng(0).standard_normal(shape).astype(np.float32)
+    bt = p.tolmap_from_boxes([], tol)
+    buf = p.compress(torch.from_numpy(x).cuda(), bt)
+    assert len(buf) > x.nbytes
+    xr = api.decompress(buf).cpu().numpy()
+    assert np.array_equal(xr, x)

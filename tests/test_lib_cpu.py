@@ -1,0 +1,69 @@
+"""Boundary checks that need no GPU: the library loads, exports every entry
+point the header declares, and rejects bad arguments with status codes."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "blockmgard.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:bm_status|const char\*)\s+(bm_\w+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2609_00205_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2609_00205_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def test_header_declares_the_api():
+    names = _declared()
+    for n in ["bm_plan_create", "bm_decompose", "bm_recompose", "bm_quantize_roi", "bm_dequantize",
+              "bm_compress", "bm_decompress", "bm_huffman_encode", "bm_huffman_decode",
+              "bm_decompose_adjoint", "bm_recompose_adjoint", "bm_tolmap_from_boxes", "bm_tolmap_from_voxels"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    assert lib.bm_status_string(0) == b"ok"
+    assert lib.bm_status_string(-6) == b"corrupt stream"
+    assert lib.bm_version().startswith(b"blockmgard")
+
+
+def test_bad_config_rejected_before_touching_a_device(lib):
+    from paper_2609_00205_amd._lib import BMConfig
+    h = C.c_void_p()
+    for cfg in [BMConfig(3, (C.c_int64 * 3)(0, 5, 5), 0, 17, 1, 2, 0, 0.1),      # empty axis
+                BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 7, 17, 1, 2, 0, 0.1),      # bad dtype
+                BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 12, 1, 2, 0, 0.1),      # block not 2^k+1
+                BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 0, 0, 0, 0.1),      # no levels
+                BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 1, 2, 0, 0.7)]:     # eta out of range
+        assert lib.bm_plan_create(C.byref(cfg), C.byref(h)) == -1
+        assert len(lib.bm_last_error()) > 0
+    assert lib.bm_plan_create(None, C.byref(h)) == -1
+
+
+def test_corrupt_container_rejected(lib):
+    from paper_2609_00205_amd._lib import BMConfig
+    cfg = BMConfig()
+    assert lib.bm_compressed_config(b"not a stream at all" * 10, 190, C.byref(cfg)) == -6
+    assert lib.bm_compressed_config(None, 0, C.byref(cfg)) == -6
+
+
+def test_null_plan_calls(lib):
+    assert lib.bm_decompose(None, None, None, None) == -1
+    assert lib.bm_quantize_roi(None, None, None, None, None, None) == -1
+    assert lib.bm_plan_destroy(None) == 0
