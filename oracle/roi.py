@@ -19,12 +19,16 @@ Readings (listed in the design notes)
 * "Contributes" in Eq. 2 = shares at least one node (shared-face blocks).
 * A node's tolerance at a block level is the minimum over the blocks of that
   level that contain it.
-* Budget: T = L + M + 1 equal shares.  A detail of level s gets half-width
-  e = tau (1 - eta) / (T A_s), where A_s is the exact L-infinity gain of that
-  level's detail coefficients in reconstruction (max row sum of
-  |I - P3 K3| over detail columns), rounded up to 4 decimals; the coarsest
-  values get e = tau (1 - eta) / T.  Bin width Delta = 2e,
-  q = rint(c * (1/Delta)) in FP64 (round half to even), c_hat = q * Delta.
+* Budget: level s gets the share w_s of every tolerance, w_s proportional to
+  the number of coefficients of level s (so the share tightens as levels
+  coarsen), the M global levels splitting their part equally; the coarsest
+  values get w_c = their count / the total, and the shares sum to 1.  A
+  detail of level s gets half-width e = tau (1 - eta) w_s / A_s, where A_s is
+  the exact L-infinity gain of that level's detail coefficients in
+  reconstruction (max row sum of |I - P3 K3| over detail columns), rounded up
+  to 4 decimals; the coarsest values get e = tau (1 - eta) w_c (interpolation
+  has gain 1).  Bin width Delta = 2e, q = rint(c * (1/Delta)) in FP64 (round
+  half to even), c_hat = q * Delta.
 """
 from __future__ import annotations
 
@@ -186,9 +190,28 @@ def level_gains(h: mgard.Hierarchy) -> List[float]:
     return out
 
 
-def kappa(T: int, A: float, eta: float) -> float:
-    """Bin width per unit tolerance: Delta = tau * kappa."""
-    return (2.0 * (1.0 - eta)) / (float(T) * A)
+def level_weights(h: mgard.Hierarchy) -> List[float]:
+    """Share of the L-infinity budget of each level (s = 1..L+M) and of the
+    coarsest values (last entry).
+
+    Sec. II-B: the share tightens as the level coarsens; reading: a level's
+    share is proportional to the number of coefficients it holds.  Sec. IV-C:
+    the M global levels share their part equally.
+    """
+    N = float(np.prod(h.shape_p))
+    sizes = [int(np.prod([len(p) for p in pos])) for pos in h.pos]
+    counts = [sizes[s - 1] - sizes[s] for s in range(1, h.levels + 1)]
+    w = [0.0] * (h.levels + 1)
+    nglob = sum(counts[h.L:])
+    for s in range(1, h.levels + 1):
+        w[s - 1] = counts[s - 1] / N if s <= h.L else (nglob / N) / float(h.M)
+    w[h.levels] = sizes[h.levels] / N
+    return w
+
+
+def kappa(w: float, A: float, eta: float) -> float:
+    """Bin width per unit tolerance for a level with share w and gain A: Delta = tau * kappa."""
+    return (2.0 * (1.0 - eta)) * w / A
 
 
 def node_delta(h: mgard.Hierarchy, tol1, eta: float) -> np.ndarray:
@@ -197,8 +220,8 @@ def node_delta(h: mgard.Hierarchy, tol1, eta: float) -> np.ndarray:
     ``tol1`` is the level-1 block map (L >= 1) or a scalar (L == 0).
     """
     L, M = h.L, h.M
-    T = L + M + 1
     gains = level_gains(h)
+    w = level_weights(h)
     lev = mgard.node_level(h.shape_p, L, M)
     delta = np.zeros(h.shape_p)
     if L >= 1:
@@ -221,7 +244,7 @@ def node_delta(h: mgard.Hierarchy, tol1, eta: float) -> np.ndarray:
             tau = tau[np.ix_(*(mgard.coarse_indices(len(p)) for p in h.pos[L - 1]))]
         else:
             tau = np.full([len(p) for p in h.pos[s - 1]], tau_global)
-        k = kappa(T, gains[s - 1], eta) if s <= L + M else (2.0 * (1.0 - eta)) / float(T)
+        k = kappa(w[s - 1], gains[s - 1], eta) if s <= L + M else (2.0 * (1.0 - eta)) * w[L + M]
         d = tau * k
         sub = delta[grid]
         sub[mask] = d[mask]

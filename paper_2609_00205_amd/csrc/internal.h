@@ -24,6 +24,36 @@ void check_hip(hipError_t e, const char* what);
 
 #define BM_HIP(call) ::bm::check_hip((call), #call)
 
+// Unsigned 32-bit division by a run-time constant d >= 1 with a multiply-high
+// and a shift (Granlund-Montgomery round-up method): valid for all n < 2^32.
+struct FastDiv {
+  uint32_t d = 1, m = 0, s = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t dv) : d(dv) {
+    s = 0;
+    while ((uint64_t(1) << s) < d) ++s;
+    m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1);
+  }
+  __device__ inline uint32_t div(uint32_t n) const {
+    const uint32_t t = __umulhi(n, m);
+    return uint32_t((uint64_t(t) + n) >> s);
+  }
+};
+
+// (z, y, x) of a flat index into dims (n0, n1, n2) with fewer than 2^32 entries.
+struct Unflat32 {
+  FastDiv d2, d1;
+  uint32_t n1 = 1, n2 = 1;
+  Unflat32() = default;
+  Unflat32(int64_t n1_, int64_t n2_) : d2(uint32_t(n2_)), d1(uint32_t(n1_)), n1(uint32_t(n1_)), n2(uint32_t(n2_)) {}
+  __device__ inline void operator()(uint32_t i, uint32_t& z, uint32_t& y, uint32_t& x) const {
+    const uint32_t t = d2.div(i);
+    x = i - t * n2;
+    z = d1.div(t);
+    y = t - z * n1;
+  }
+};
+
 __host__ __device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
 __host__ __device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
 
@@ -105,6 +135,7 @@ int64_t padded_length(int64_t n, int b, int L, int M);
 double level_gain_local(int b);
 double level_gain_global(const int64_t n[3]);
 void thomas_pivots_natural(int64_t m, std::vector<double>& inv);
+std::vector<double> level_weights(const bm_plan_s& p);
 
 // ---- kernels (launchers, stream-ordered) ----
 void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff,

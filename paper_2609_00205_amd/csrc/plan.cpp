@@ -196,6 +196,29 @@ void thomas_pivots_natural(int64_t m, std::vector<double>& inv) {
   }
 }
 
+// Share of the L-infinity budget per level (index s-1) and for the coarsest
+// values (index L+M).  Sec. II-B: the share tightens as levels coarsen; here
+// it is proportional to the number of coefficients a level holds (the split
+// that minimises the total code length).  Sec. IV-C: the M global levels
+// share their part equally.  The shares sum to 1.
+std::vector<double> level_weights(const bm_plan_s& p) {
+  auto prod = [](const int64_t* n) { return n[0] * n[1] * n[2]; };
+  const double N = double(prod(p.pdims));
+  std::vector<double> w(p.nlev + 1, 0.0);
+  int64_t nglob = 0;
+  for (int s = 1; s <= p.nlev; ++s) {
+    const Level& L = p.lv[s - 1];
+    const int64_t ns = prod(L.n) - prod(L.m);
+    if (L.local)
+      w[s - 1] = double(ns) / N;
+    else
+      nglob += ns;
+  }
+  for (int s = p.L + 1; s <= p.nlev; ++s) w[s - 1] = (double(nglob) / N) / double(p.M);
+  w[p.nlev] = double(prod(p.lv[p.nlev - 1].m)) / N;
+  return w;
+}
+
 TimedScope::TimedScope(bm_plan_s& p_, int slot_, hipStream_t st_) : p(p_), slot(slot_), st(st_) {
   if (!p.timing.on) return;
   BM_HIP(hipEventCreate(&a));

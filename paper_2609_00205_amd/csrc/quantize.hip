@@ -182,28 +182,29 @@ __global__ void k_zero_counters(int64_t* c) {
 }
 
 struct QArgs {
-  int64_t P[3];               // padded dims
+  uint32_t tot;               // padded node count (< 2^32)
+  Unflat32 uf;                // flat index -> (z, y, x) of the padded grid
   int L, M;
   int D[3];                   // levels each axis coarsens
-  int64_t w;                  // b - 1
+  int lw;                     // log2(b - 1)
   // per-block Delta and 1/Delta: slot s-1 for the details of local level s;
   // slot kCoarseSlot for the coarsest values when M == 0 (level-L blocks)
   const double* bdelta[9];
   const double* binv[9];
-  int64_t nb[9][3];
+  uint32_t nb[9][3];
   const double* q;            // scalar Delta / inverse per level (index s-1), coarsest at L+M
   int64_t* counters;          // [0] outliers, [1] max |q|, [2] out of range
 };
 
-__device__ inline int ctz64(int64_t v) { return v == 0 ? 64 : __builtin_ctzll(static_cast<unsigned long long>(v)); }
+__device__ inline int ctz32(uint32_t v) { return v == 0 ? 32 : __builtin_ctz(v); }
 
 // level of a node: 1..L+M for a detail of that level, L+M+1 for a coarsest value
-__device__ inline int node_level(const QArgs& a, int64_t g0, int64_t g1, int64_t g2) {
+__device__ inline int node_level(const QArgs& a, uint32_t g0, uint32_t g1, uint32_t g2) {
   int lev = a.L + a.M + 1;
-  const int64_t g[3] = {g0, g1, g2};
+  const uint32_t g[3] = {g0, g1, g2};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int t = ctz64(g[d]);
+    const int t = ctz32(g[d]);
     if (t < a.D[d] && t + 1 < lev) lev = t + 1;
   }
   return lev;
@@ -212,33 +213,40 @@ __device__ inline int node_level(const QArgs& a, int64_t g0, int64_t g1, int64_t
 constexpr int kCoarseSlot = 8;
 
 // Delta and 1/Delta of a node whose tolerance comes from the blocks of local
-// level s (grid coordinates q = g >> (s-1)), from table slot `slot`.
-__device__ inline void block_delta(const QArgs& a, int s, int slot, int64_t g0, int64_t g1, int64_t g2,
+// level s (grid coordinates q = g >> (s-1)), from table slot `slot`.  Block i
+// spans nodes [i w, (i+1) w]: a node on a shared face lies in two blocks per
+// axis.
+__device__ inline void block_delta(const QArgs& a, int s, int slot, uint32_t g0, uint32_t g1, uint32_t g2,
                                    double& del, double& inv) {
-  const int64_t q[3] = {g0 >> (s - 1), g1 >> (s - 1), g2 >> (s - 1)};
-  int64_t lo[3], hi[3];
+  const uint32_t q[3] = {g0 >> (s - 1), g1 >> (s - 1), g2 >> (s - 1)};
+  const uint32_t wm = (1u << a.lw) - 1;
+  uint32_t lo[3], hi[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int64_t nb = a.nb[slot][d];
-    const int64_t f = q[d] / a.w;
-    lo[d] = (q[d] % a.w == 0 && q[d] > 0) ? f - 1 : f;
+    const uint32_t nb = a.nb[slot][d];
+    const uint32_t f = q[d] >> a.lw;
+    lo[d] = ((q[d] & wm) == 0 && q[d] > 0) ? f - 1 : f;
     hi[d] = f < nb - 1 ? f : nb - 1;
     if (lo[d] > hi[d]) lo[d] = hi[d];
   }
-  del = INFINITY;
-  inv = 0.0;
   const double* bd = a.bdelta[slot];
   const double* bi = a.binv[slot];
-  for (int64_t z = lo[0]; z <= hi[0]; ++z)
-    for (int64_t y = lo[1]; y <= hi[1]; ++y)
-      for (int64_t x = lo[2]; x <= hi[2]; ++x) {
-        const int64_t k = (z * a.nb[slot][1] + y) * a.nb[slot][2] + x;
-        del = fmin(del, bd[k]);
-        inv = fmax(inv, bi[k]);
-      }
+  const uint32_t n1 = a.nb[slot][1], n2 = a.nb[slot][2];
+  uint32_t k = (lo[0] * n1 + lo[1]) * n2 + lo[2];
+  del = bd[k];
+  inv = bi[k];
+  if (lo[0] != hi[0] || lo[1] != hi[1] || lo[2] != hi[2]) {
+    for (uint32_t z = lo[0]; z <= hi[0]; ++z)
+      for (uint32_t y = lo[1]; y <= hi[1]; ++y)
+        for (uint32_t x = lo[2]; x <= hi[2]; ++x) {
+          k = (z * n1 + y) * n2 + x;
+          del = fmin(del, bd[k]);
+          inv = fmax(inv, bi[k]);
+        }
+  }
 }
 
-__device__ inline void node_delta(const QArgs& a, int64_t z, int64_t y, int64_t x, double& del, double& inv) {
+__device__ inline void node_delta(const QArgs& a, uint32_t z, uint32_t y, uint32_t x, double& del, double& inv) {
   const int lev = node_level(a, z, y, x);
   if (lev <= a.L) {
     block_delta(a, lev, lev - 1, z, y, x, del, inv);
@@ -252,10 +260,10 @@ __device__ inline void node_delta(const QArgs& a, int64_t z, int64_t y, int64_t 
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* codes) {
-  const int64_t tot = a.P[0] * a.P[1] * a.P[2];
   int64_t nout = 0, mx = 0, bad = 0;
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    const int64_t x = i % a.P[2], t = i / a.P[2], y = t % a.P[1], z = t / a.P[1];
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
+    uint32_t z, y, x;
+    a.uf(i, z, y, x);
     double del, inv;
     node_delta(a, z, y, x, del, inv);
     const double v = rint(double(c[i]) * inv);
@@ -287,9 +295,9 @@ __global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* c
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_dequantize(QArgs a, const int32_t* codes, T* c) {
-  const int64_t tot = a.P[0] * a.P[1] * a.P[2];
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    const int64_t x = i % a.P[2], t = i / a.P[2], y = t % a.P[1], z = t / a.P[1];
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
+    uint32_t z, y, x;
+    a.uf(i, z, y, x);
     double del, inv;
     node_delta(a, z, y, x, del, inv);
     c[i] = T(double(codes[i]) * del);
@@ -302,27 +310,31 @@ int64_t prod3(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   if (p.L > 8) fail(BM_EUNSUPPORTED, "more than 8 local levels");
   QArgs a{};
+  const int64_t npad = prod3(p.pdims);
+  if (npad >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "quantizer: padded grid of 2^32 nodes or more");
+  a.tot = uint32_t(npad);
+  a.uf = Unflat32(p.pdims[1], p.pdims[2]);
   for (int d = 0; d < 3; ++d) {
-    a.P[d] = p.pdims[d];
     int D = 0;
     for (auto& L : p.lv) D += L.coarsen[d] ? 1 : 0;
     a.D[d] = D;
   }
   a.L = p.L;
   a.M = p.M;
-  a.w = p.L > 0 ? p.cfg.block - 1 : 1;
+  a.lw = p.L > 0 ? (p.cfg.block == 17 ? 4 : 3) : 0;
   a.counters = p.ws.counters;
-  const int T = p.L + p.M + 1;
   const double eta = p.cfg.eta;
+  const std::vector<double> w = level_weights(p);
   const int64_t tot = p.ws.tol_off[p.L + 1];
   double* tau = p.ws.tolbuf;
   double* bdel = p.ws.tolbuf + tot;
   double* binv = p.ws.tolbuf + 2 * tot;
   double* tg = p.ws.tolbuf + 3 * tot;    // tau_global
+  // level-1 taus are the caller's map; deeper local levels live in tolbuf
+  auto taus = [&](int s) -> const double* { return s == 1 ? block_tol : tau + p.ws.tol_off[s]; };
   if (p.L > 0) {
-    BM_HIP(hipMemcpyAsync(tau, block_tol, size_t(prod3(p.nb1)) * sizeof(double), hipMemcpyDeviceToDevice, st));
     for (int s = 1; s < p.L; ++s) {
-      PropArgs pa{tau + p.ws.tol_off[s], {}, tau + p.ws.tol_off[s + 1], {}};
+      PropArgs pa{taus(s), {}, tau + p.ws.tol_off[s + 1], {}};
       for (int d = 0; d < 3; ++d) {
         pa.nb[d] = p.lv[s - 1].nb[d];
         pa.nn[d] = p.lv[s].nb[d];
@@ -330,29 +342,28 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       hipLaunchKernelGGL(k_propagate, dim3(grid_for(prod3(pa.nn))), dim3(NT), 0, st, pa);
     }
     for (int s = 1; s <= p.L; ++s) {
-      const double kap = (2.0 * (1.0 - eta)) / (double(T) * p.lv[s - 1].gain);
+      const double kap = (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain;
       const int64_t nbs = prod3(p.lv[s - 1].nb);
       const int64_t off = p.ws.tol_off[s];
-      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, tau + off, nbs, kap, bdel + off,
+      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, taus(s), nbs, kap, bdel + off,
                          binv + off);
       a.bdelta[s - 1] = bdel + off;
       a.binv[s - 1] = binv + off;
-      for (int d = 0; d < 3; ++d) a.nb[s - 1][d] = p.lv[s - 1].nb[d];
+      for (int d = 0; d < 3; ++d) a.nb[s - 1][d] = uint32_t(p.lv[s - 1].nb[d]);
     }
-    const int64_t lastoff = p.ws.tol_off[p.L];
     const int64_t nlast = prod3(p.lv[p.L - 1].nb);
     if (p.M == 0) {
-      // coarsest values (no gain): Delta = tau * 2 (1 - eta) / T over the level-L blocks
+      // coarsest values (no gain): Delta = tau * 2 (1 - eta) w_c over the level-L blocks
       double* cdel = tg + 8;
       double* cinv = cdel + nlast;
-      const double kc = (2.0 * (1.0 - eta)) / double(T);
-      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nlast)), dim3(NT), 0, st, tau + lastoff, nlast, kc, cdel, cinv);
+      const double kc = (2.0 * (1.0 - eta)) * w[p.nlev];
+      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, kc, cdel, cinv);
       a.bdelta[kCoarseSlot] = cdel;
       a.binv[kCoarseSlot] = cinv;
-      for (int d = 0; d < 3; ++d) a.nb[kCoarseSlot][d] = p.lv[p.L - 1].nb[d];
+      for (int d = 0; d < 3; ++d) a.nb[kCoarseSlot][d] = uint32_t(p.lv[p.L - 1].nb[d]);
     }
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
-    hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, tau + lastoff, nlast, tg);
+    hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, tg);
   } else {
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
     hipLaunchKernelGGL(k_min_all, dim3(1), dim3(NT), 0, st, block_tol, int64_t(1), tg);
@@ -360,8 +371,8 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   ScalarArgs sa{};
   sa.tau_global = tg;
   sa.n = p.nlev + 1;
-  for (int s = 1; s <= p.nlev; ++s) sa.kappa[s - 1] = (2.0 * (1.0 - eta)) / (double(T) * p.lv[s - 1].gain);
-  sa.kappa[p.nlev] = (2.0 * (1.0 - eta)) / double(T);
+  for (int s = 1; s <= p.nlev; ++s) sa.kappa[s - 1] = (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain;
+  sa.kappa[p.nlev] = (2.0 * (1.0 - eta)) * w[p.nlev];
   sa.q = p.ws.qparam;
   hipLaunchKernelGGL(k_scalar_delta, dim3(1), dim3(64), 0, st, sa);
   BM_HIP(hipGetLastError());

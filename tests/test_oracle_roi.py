@@ -139,9 +139,21 @@ def test_tau_global_is_min_of_last_local_level():
     h = mgard.hierarchy((33, 33, 33), 9, 2, 1)
     d = roi.node_delta(h, tol, 0.0)
     lev = mgard.node_level(h.shape_p, 2, 1)
-    T = 4
     A3 = roi.level_gains(h)[2]
-    assert np.allclose(d[lev == 3], 1e-6 * 2 / (T * A3))
+    w3 = (9 ** 3 - 5 ** 3) / 33 ** 3          # level-3 coefficients of the 33^3 grid
+    assert np.allclose(d[lev == 3], 1e-6 * 2 * w3 / A3)
+
+
+def test_budget_shares_tighten_as_levels_coarsen():
+    # Sec. II-B: level-dependent shares that tighten with coarser levels;
+    # Sec. IV-C: the M global levels share their part equally.
+    h = mgard.hierarchy((65, 65, 65), 9, 2, 3)
+    w = roi.level_weights(h)
+    assert sum(w) == pytest.approx(1.0, abs=1e-15)
+    assert w[0] > w[1] > w[2]                  # local levels, then the global block
+    assert w[2] == w[3] == w[4]                # equal global shares
+    assert w[0] == pytest.approx((65 ** 3 - 33 ** 3) / 65 ** 3)
+    assert w[5] == pytest.approx(3 ** 3 / 65 ** 3)   # 65 -> 33 -> 17 -> 9 -> 5 -> 3
 
 
 def test_quantizer_round_half_even_and_reciprocal():
