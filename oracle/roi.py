@@ -206,7 +206,14 @@ def level_weights(h: mgard.Hierarchy) -> List[float]:
     for s in range(1, h.levels + 1):
         w[s - 1] = counts[s - 1] / N if s <= h.L else (nglob / N) / float(h.M)
     w[h.levels] = sizes[h.levels] / N
-    return w
+    # no share below 1/(64 T), T = L+M+1: keeps the bins of small, deep
+    # levels within reach of 32-bit codes; then renormalise (sequential sum)
+    floor = 1.0 / (64.0 * float(h.levels + 1))
+    w = [v if v > floor else floor for v in w]
+    total = 0.0
+    for v in w:
+        total += v
+    return [v / total for v in w]
 
 
 def kappa(w: float, A: float, eta: float) -> float:

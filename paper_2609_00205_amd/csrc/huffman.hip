@@ -33,14 +33,18 @@ constexpr int LUTB = 10;           // decode lookup bits
 
 __device__ inline uint32_t sym_of(int32_t q) { return (q > -R && q < R) ? uint32_t(q + R) : 0u; }
 
+// LDS bins: [0, 2 HW) for symbols R-HW .. R+HW-1, bin 2 HW for the escape
+// symbol; everything else (rare) goes straight to the global histogram.
 __global__ __launch_bounds__(256) void k_hist(const int32_t* codes, int64_t n, unsigned long long* hist) {
-  __shared__ uint32_t h[2 * HW];
-  for (int i = threadIdx.x; i < 2 * HW; i += 256) h[i] = 0;
+  __shared__ uint32_t h[2 * HW + 1];
+  for (int i = threadIdx.x; i < 2 * HW + 1; i += 256) h[i] = 0;
   __syncthreads();
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
     const uint32_t s = sym_of(codes[i]);
     const int64_t k = int64_t(s) - (R - HW);
-    if (k >= 0 && k < 2 * HW)
+    if (s == 0)
+      atomicAdd(&h[2 * HW], 1u);
+    else if (k >= 0 && k < 2 * HW)
       atomicAdd(&h[k], 1u);
     else
       atomicAdd(&hist[s], 1ull);
@@ -48,6 +52,7 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t* codes, int64_t n, u
   __syncthreads();
   for (int i = threadIdx.x; i < 2 * HW; i += 256)
     if (h[i]) atomicAdd(&hist[R - HW + i], (unsigned long long)h[i]);
+  if (threadIdx.x == 0 && h[2 * HW]) atomicAdd(&hist[0], (unsigned long long)h[2 * HW]);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {

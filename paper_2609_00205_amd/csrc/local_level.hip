@@ -1,34 +1,40 @@
-// In-cache Block levels (Sec. IV-A): one workgroup per b^3 block, the whole
-// level computed in LDS between one coalesced load and one store.
+// In-cache Block levels (Sec. IV-A): every b^3 block is decomposed on chip,
+// between one coalesced load and one store.
 //
 // Block geometry: b = 2^k+1 nodes per side; neighbouring blocks share one
 // face.  Inside a block the level is the MGARD step of Sec. II-B with the
 // correction of the block's surface coarse nodes held at zero
 // ("face-fixed"): details d = u - multilinear interpolant of the coarse
-// nodes; load vector f = (P^T M)_x (P^T M)_y (P^T M)_z w over the interior
-// coarse rows (three shrinking passes b^3 -> mi b^2 -> mi^2 b -> mi^3 with
-// mi = (b+1)/2 - 2); tridiagonal solves with the coarse mass matrix along
-// x, y, z; coarse value c = u_C + z.  Face values depend on face data only,
-// so every node is written once, by the block that owns it.
+// nodes; correction z = (Mc^{-1} P^T M)_x (Mc^{-1} P^T M)_y
+// (Mc^{-1} P^T M)_z w over the interior coarse rows; c = u_C + z.  Face values
+// depend on face data only, so every node is written once, by its owner.
 //
-// The weights are compile-time constants (Sec. IV-A, compile-time index
-// resolution): interior rows of P^T M on a unit grid are
-// {1/12, 1/2, 5/6, 1/2, 1/12}; 3 Mc restricted to interior coarse nodes is
-// tridiag(1, 4, 1).
+// Mapping to gfx950: one thread owns one z-column (y, x) of a block and keeps
+// it in registers.  The multilinear interpolant needs the even-z planes of
+// the four neighbouring columns (LDS); the z pass (restriction by P^T M and
+// the tridiagonal solve) runs in registers; the y and x passes read short
+// LDS lines, one thread per line.  The weights are compile-time constants
+// (Sec. IV-A, compile-time index resolution): interior rows of P^T M on a
+// unit grid are {1/12, 1/2, 5/6, 1/2, 1/12}; 3 Mc restricted to the interior
+// coarse nodes is tridiag(1, 4, 1).  Small blocks are packed several to a
+// workgroup so wavefronts stay full.
 
 #include "internal.h"
 
 namespace bm {
 namespace {
 
-constexpr int NT = 256;
-
 template <int B>
 struct Geo {
-  static constexpr int N = B * B * B;
   static constexpr int BB = B * B;
-  static constexpr int MI = (B + 1) / 2 - 2;   // interior coarse nodes per axis
-  static constexpr int SCR = MI * BB + MI * MI * B;
+  static constexpr int MC = (B + 1) / 2;        // coarse nodes per axis
+  static constexpr int MI = MC - 2;             // interior coarse nodes per axis
+  static constexpr int NB = B <= 9 ? 3 : 1;     // blocks per workgroup
+  static constexpr int NT = ((NB * BB + 63) / 64) * 64;
+  // LDS per block: decompose UE[MC][B][B] + T1[MI][B][B] (T2 aliases UE, Z aliases T1)
+  static constexpr int DEC_LDS = MC * BB + MI * BB;
+  // recompose: UC[MC][MC][MC] + T1[MI][B][B] + T2[MI][MI][B] (Z aliases T1)
+  static constexpr int REC_LDS = MC * MC * MC + MI * BB + MI * MI * B;
 };
 
 // Reciprocal pivots of Thomas elimination for tridiag(1, 4, 1) of size MI.
@@ -44,10 +50,57 @@ struct Pivots {
   }
 };
 
-// XCD-aware block order: consecutive hardware workgroup ids go round-robin
-// over the 8 XCDs; this map gives each XCD a contiguous run of blocks so
-// shared faces are re-read from the same L2.
-__device__ inline int64_t xcd_block(int64_t wg, int64_t per) { return (wg & 7) * per + (wg >> 3); }
+// XCD-aware order: hardware workgroup ids go round-robin over the 8 XCDs;
+// this map gives each XCD a contiguous run of workgroups so shared faces are
+// re-read from the same L2.
+__device__ inline int64_t xcd_group(int64_t wg, int64_t per) { return (wg & 7) * per + (wg >> 3); }
+
+// Restriction by the interior rows of P^T M (centre 2J+2) followed by the
+// interior tridiagonal solve, on a line of B values: out[J], J < MI.
+template <typename T, int B>
+__device__ inline void restrict_solve(const T (&w)[B], T (&out)[Geo<B>::MI]) {
+  constexpr int MI = Geo<B>::MI;
+  constexpr Pivots<MI> P{};
+  const T C0 = T(5.0 / 6.0), C1 = T(0.5), C2 = T(1.0 / 12.0);
+  T d[MI];
+#pragma unroll
+  for (int J = 0; J < MI; ++J) {
+    const int c = 2 * J + 2;
+    const T r = C2 * (w[c - 2] + w[c + 2]) + C1 * (w[c - 1] + w[c + 1]) + C0 * w[c];
+    d[J] = J == 0 ? T(3) * r * T(P.v[0]) : (T(3) * r - d[J - 1]) * T(P.v[J]);
+  }
+  out[MI - 1] = d[MI - 1];
+#pragma unroll
+  for (int J = MI - 2; J >= 0; --J) out[J] = d[J] - T(P.v[J]) * out[J + 1];
+}
+
+// y and x passes of the correction: T1[MI][B][B] -> T2[MI][MI][B] -> Z[MI][MI][MI]
+template <typename T, int B>
+__device__ inline void pass_y(const T* T1, T* T2, int tb) {
+  constexpr int MI = Geo<B>::MI, BB = Geo<B>::BB;
+  if (tb < MI * B) {
+    const int J = tb / B, x = tb - (tb / B) * B;
+    T line[B], o[MI];
+#pragma unroll
+    for (int y = 0; y < B; ++y) line[y] = T1[J * BB + y * B + x];
+    restrict_solve<T, B>(line, o);
+#pragma unroll
+    for (int I = 0; I < MI; ++I) T2[(J * MI + I) * B + x] = o[I];
+  }
+}
+
+template <typename T, int B>
+__device__ inline void pass_x(const T* T2, T* Z, int tb) {
+  constexpr int MI = Geo<B>::MI;
+  if (tb < MI * MI) {
+    T line[B], o[MI];
+#pragma unroll
+    for (int x = 0; x < B; ++x) line[x] = T2[tb * B + x];
+    restrict_solve<T, B>(line, o);
+#pragma unroll
+    for (int K = 0; K < MI; ++K) Z[tb * MI + K] = o[K];
+  }
+}
 
 template <typename T>
 struct DecArgs {
@@ -58,7 +111,7 @@ struct DecArgs {
   int64_t cs[3];          // coefficient strides of this level's grid
   T* cout;                // compact coarse grid G^s
   int64_t cn[3];
-  int64_t nb[3], nblocks, per;
+  int64_t nb[3], nblocks, nwg, per;
 };
 
 template <typename T>
@@ -69,193 +122,208 @@ struct RecArgs {
   int64_t cn[3];
   T* out;                 // output grid view (cropped to on)
   int64_t on[3], os[3];
-  int64_t nb[3], nblocks, per;
+  int64_t nb[3], nblocks, nwg, per;
 };
 
-template <int B>
-__device__ inline int lidx(int z, int y, int x) {
-  return (z * B + y) * B + x;
-}
-
-// Multilinear interpolant of the block's coarse nodes at node (z, y, x):
-// the mean of the 8 corners of the coarse cell, where an even coordinate
-// uses the node itself twice (weights 1/2 per odd axis).
 template <typename T, int B>
-__device__ inline T interp(const T* U, int z, int y, int x) {
-  const int z0 = z & ~1, z1 = z0 + (z & 1) * 2;
-  const int y0 = y & ~1, y1 = y0 + (y & 1) * 2;
-  const int x0 = x & ~1, x1 = x0 + (x & 1) * 2;
-  const T s = ((U[lidx<B>(z0, y0, x0)] + U[lidx<B>(z0, y0, x1)]) + (U[lidx<B>(z0, y1, x0)] + U[lidx<B>(z0, y1, x1)])) +
-              ((U[lidx<B>(z1, y0, x0)] + U[lidx<B>(z1, y0, x1)]) + (U[lidx<B>(z1, y1, x0)] + U[lidx<B>(z1, y1, x1)]));
-  return s * T(0.125);
-}
-
-// Thomas elimination for tridiag(1,4,1) x = 3 f on MI values at stride S.
-template <typename T, int MI, int S>
-__device__ inline void solve_interior(T* x) {
-  constexpr Pivots<MI> P{};
-  T d[MI];
-  d[0] = T(3) * x[0] * T(P.v[0]);
-#pragma unroll
-  for (int i = 1; i < MI; ++i) d[i] = (T(3) * x[i * S] - d[i - 1]) * T(P.v[i]);
-  x[(MI - 1) * S] = d[MI - 1];
-#pragma unroll
-  for (int i = MI - 2; i >= 0; --i) {
-    d[i] = d[i] - T(P.v[i]) * d[i + 1];
-    x[i * S] = d[i];
-  }
-}
-
-// Correction of the interior coarse nodes from the fine-only values held in
-// U (coarse entries of U are read as zero).  Leaves z[J][I][K] in S[0, MI^3).
-template <typename T, int B>
-__device__ void correction(const T* U, T* S, int tid) {
+__global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
   using G = Geo<B>;
-  constexpr int MI = G::MI, BB = G::BB;
-  const T C0 = T(5.0 / 6.0), C1 = T(0.5), C2 = T(1.0 / 12.0);
-  T* RZ = S;                 // [MI][B][B]
-  T* RY = S + MI * BB;       // [MI][MI][B]
-  T* RX = S;                 // [MI][MI][MI], overwrites RZ after the y pass
-  for (int i = tid; i < MI * BB; i += NT) {
-    const int J = i / BB, r = i - J * BB, y = r / B, x = r - y * B;
-    const int zc = 2 * J + 2;
-    const bool xyeven = ((x | y) & 1) == 0;
-    const int base = y * B + x;
-    const T w0 = xyeven ? T(0) : U[zc * BB + base];
-    const T wm2 = xyeven ? T(0) : U[(zc - 2) * BB + base];
-    const T wp2 = xyeven ? T(0) : U[(zc + 2) * BB + base];
-    const T wm1 = U[(zc - 1) * BB + base];
-    const T wp1 = U[(zc + 1) * BB + base];
-    RZ[i] = C2 * (wm2 + wp2) + C1 * (wm1 + wp1) + C0 * w0;
-  }
-  __syncthreads();
-  for (int i = tid; i < MI * MI * B; i += NT) {
-    const int J = i / (MI * B), r = i - J * (MI * B), I = r / B, x = r - I * B;
-    const int yc = 2 * I + 2;
-    const T* p = RZ + J * BB + x;
-    RY[i] = C2 * (p[(yc - 2) * B] + p[(yc + 2) * B]) + C1 * (p[(yc - 1) * B] + p[(yc + 1) * B]) + C0 * p[yc * B];
-  }
-  __syncthreads();
-  // RZ is dead once the y pass has finished, so RX may take its space
-  for (int i = tid; i < MI * MI * MI; i += NT) {
-    const int J = i / (MI * MI), r = i - J * (MI * MI), I = r / MI, K = r - I * MI;
-    const int xc = 2 * K + 2;
-    const T* p = RY + (J * MI + I) * B;
-    RX[i] = C2 * (p[xc - 2] + p[xc + 2]) + C1 * (p[xc - 1] + p[xc + 1]) + C0 * p[xc];
-  }
-  __syncthreads();
-  static_assert(MI * MI <= NT, "one thread per interior line");
-  if (tid < MI * MI) solve_interior<T, MI, 1>(RX + tid * MI);                       // x lines
-  __syncthreads();
-  if (tid < MI * MI) {
-    const int J = tid / MI, K = tid - J * MI;
-    solve_interior<T, MI, MI>(RX + J * MI * MI + K);                                 // y lines
-  }
-  __syncthreads();
-  if (tid < MI * MI) solve_interior<T, MI, MI * MI>(RX + tid);                       // z lines
-  __syncthreads();
-}
-
-template <typename T, int B>
-__global__ __launch_bounds__(NT) void k_local_decompose(DecArgs<T> a) {
-  using G = Geo<B>;
-  constexpr int N = G::N, BB = G::BB, MI = G::MI;
-  __shared__ T U[N];
-  __shared__ T S[G::SCR];
-  const int64_t blk = xcd_block(blockIdx.x, a.per);
-  if (blk >= a.nblocks) return;
-  const int64_t bx = blk % a.nb[2], t = blk / a.nb[2], by = t % a.nb[1], bz = t / a.nb[1];
-  const int64_t oz = bz * (B - 1), oy = by * (B - 1), ox = bx * (B - 1);
+  constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
+  __shared__ T lds[NB * G::DEC_LDS];
+  const int64_t g = xcd_group(blockIdx.x, a.per);
+  if (g >= a.nwg) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) {
-    const int lz = i / BB, r = i - lz * BB, ly = r / B, lx = r - ly * B;
-    int64_t gz = oz + lz, gy = oy + ly, gx = ox + lx;
-    T v;
-    if (a.first && (gz >= a.sn[0] || gy >= a.sn[1] || gx >= a.sn[2])) {
-      if (a.zero_pad) {
-        v = T(0);
-      } else {
-        gz = gz < a.sn[0] ? gz : a.sn[0] - 1;
-        gy = gy < a.sn[1] ? gy : a.sn[1] - 1;
-        gx = gx < a.sn[2] ? gx : a.sn[2] - 1;
-        v = a.src[gz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2]];
-      }
-    } else {
-      v = a.src[gz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2]];
+  const int bl = tid / BB;                           // block within the workgroup
+  const int tb = tid - bl * BB;                      // column within the block
+  const int64_t blk = g * NB + bl;
+  const bool act = bl < NB && blk < a.nblocks;
+  T* UE = lds + (bl < NB ? bl : 0) * G::DEC_LDS;     // even-z planes [MC][B][B]
+  T* T1 = UE + MC * BB;                              // [MI][B][B]
+  T* T2 = UE;                                        // [MI][MI][B], after UE is dead
+  T* Z = T1;                                         // [MI][MI][MI], after T1 is dead
+  const int y = tb / B, x = tb - (tb / B) * B;
+  int64_t bz = 0, by = 0, bx = 0;
+  if (act) {
+    bx = blk % a.nb[2];
+    const int64_t t = blk / a.nb[2];
+    by = t % a.nb[1];
+    bz = t / a.nb[1];
+  }
+  const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  T v[B];
+  if (act) {
+    // one column: clamp or zero-fill outside the logical input on level 1
+    bool yx_in = true;
+    int64_t ry = gy, rx = gx;
+    if (a.first) {
+      yx_in = gy < a.sn[1] && gx < a.sn[2];
+      ry = gy < a.sn[1] ? gy : a.sn[1] - 1;
+      rx = gx < a.sn[2] ? gx : a.sn[2] - 1;
     }
-    U[i] = v;
+    const T* col = a.src + ry * a.ss[1] + rx * a.ss[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z) {
+      int64_t gz = oz + z;
+      bool in = yx_in;
+      if (a.first) {
+        in = in && gz < a.sn[0];
+        gz = gz < a.sn[0] ? gz : a.sn[0] - 1;
+      }
+      v[z] = (a.zero_pad && !in) ? T(0) : col[gz * a.ss[0]];
+    }
+#pragma unroll
+    for (int j = 0; j < MC; ++j) UE[j * BB + tb] = v[2 * j];
   }
   __syncthreads();
-  for (int i = tid; i < N; i += NT) {
-    const int lz = i / BB, r = i - lz * BB, ly = r / B, lx = r - ly * B;
-    if (((lz | ly | lx) & 1) == 0) continue;
-    U[i] -= interp<T, B>(U, lz, ly, lx);
+  T w[B];
+  if (act) {
+    // details: u minus the multilinear interpolant of the coarse nodes
+    const int y0 = y & ~1, y1 = y0 + (y & 1) * 2, x0 = x & ~1, x1 = x0 + (x & 1) * 2;
+    const bool ecol = ((y | x) & 1) == 0;
+    T I2[MC];
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      const T* pl = UE + j * BB;
+      I2[j] = T(0.25) * ((pl[y0 * B + x0] + pl[y0 * B + x1]) + (pl[y1 * B + x0] + pl[y1 * B + x1]));
+    }
+#pragma unroll
+    for (int z = 0; z < B; ++z) {
+      if (z & 1)
+        w[z] = v[z] - T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]);
+      else
+        w[z] = ecol ? T(0) : v[z] - I2[z >> 1];
+    }
+    T o[MI];
+    restrict_solve<T, B>(w, o);
+#pragma unroll
+    for (int J = 0; J < MI; ++J) T1[J * BB + tb] = o[J];
   }
   __syncthreads();
-  correction<T, B>(U, S, tid);
-  for (int i = tid; i < MI * MI * MI; i += NT) {
-    const int J = i / (MI * MI), r = i - J * (MI * MI), I = r / MI, K = r - I * MI;
-    U[lidx<B>(2 * J + 2, 2 * I + 2, 2 * K + 2)] += S[i];
-  }
+  if (act) pass_y<T, B>(T1, T2, tb);
   __syncthreads();
-  const bool lastz = bz == a.nb[0] - 1, lasty = by == a.nb[1] - 1, lastx = bx == a.nb[2] - 1;
-  for (int i = tid; i < N; i += NT) {
-    const int lz = i / BB, r = i - lz * BB, ly = r / B, lx = r - ly * B;
-    if ((lz == B - 1 && !lastz) || (ly == B - 1 && !lasty) || (lx == B - 1 && !lastx)) continue;
-    const int64_t gz = oz + lz, gy = oy + ly, gx = ox + lx;
-    const T v = U[i];
-    a.coeff[gz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2]] = v;
-    if (((lz | ly | lx) & 1) == 0) a.cout[((gz >> 1) * a.cn[1] + (gy >> 1)) * a.cn[2] + (gx >> 1)] = v;
+  if (act) pass_x<T, B>(T2, Z, tb);
+  __syncthreads();
+  if (act) {
+    const bool ecol = ((y | x) & 1) == 0;
+    const bool icol = ecol && y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3;
+    if (ecol) {
+      // coarse values c = u_C + z (z = 0 on the block surface)
+#pragma unroll
+      for (int j = 0; j < MC; ++j) w[2 * j] = v[2 * j];
+      if (icol) {
+        const int I = (y - 2) >> 1, K = (x - 2) >> 1;
+#pragma unroll
+        for (int J = 0; J < MI; ++J) w[2 * J + 2] += Z[(J * MI + I) * MI + K];
+      }
+    }
+    const bool owny = y < B - 1 || by == a.nb[1] - 1;
+    const bool ownx = x < B - 1 || bx == a.nb[2] - 1;
+    const bool lastz = bz == a.nb[0] - 1;
+    if (owny && ownx) {
+      T* dst = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+#pragma unroll
+      for (int z = 0; z < B; ++z)
+        if (z < B - 1 || lastz) dst[(oz + z) * a.cs[0]] = w[z];
+      if (ecol) {
+        T* cdst = a.cout + (gy >> 1) * a.cn[2] + (gx >> 1);
+#pragma unroll
+        for (int j = 0; j < MC; ++j)
+          if (j < MC - 1 || lastz) cdst[((oz >> 1) + j) * a.cn[1] * a.cn[2]] = w[2 * j];
+      }
+    }
   }
 }
 
 template <typename T, int B>
-__global__ __launch_bounds__(NT) void k_local_recompose(RecArgs<T> a) {
+__global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
   using G = Geo<B>;
-  constexpr int N = G::N, BB = G::BB, MI = G::MI;
-  __shared__ T U[N];
-  __shared__ T S[G::SCR];
-  const int64_t blk = xcd_block(blockIdx.x, a.per);
-  if (blk >= a.nblocks) return;
-  const int64_t bx = blk % a.nb[2], t = blk / a.nb[2], by = t % a.nb[1], bz = t / a.nb[1];
-  const int64_t oz = bz * (B - 1), oy = by * (B - 1), ox = bx * (B - 1);
+  constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
+  __shared__ T lds[NB * G::REC_LDS];
+  const int64_t g = xcd_group(blockIdx.x, a.per);
+  if (g >= a.nwg) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) {
-    const int lz = i / BB, r = i - lz * BB, ly = r / B, lx = r - ly * B;
-    const int64_t gz = oz + lz, gy = oy + ly, gx = ox + lx;
-    T v;
-    if (((lz | ly | lx) & 1) == 0)
-      v = a.cin[((gz >> 1) * a.cn[1] + (gy >> 1)) * a.cn[2] + (gx >> 1)];
-    else
-      v = a.coeff[gz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2]];
-    U[i] = v;
+  const int bl = tid / BB;
+  const int tb = tid - bl * BB;
+  const int64_t blk = g * NB + bl;
+  const bool act = bl < NB && blk < a.nblocks;
+  T* UC = lds + (bl < NB ? bl : 0) * G::REC_LDS;     // coarse values u_C [MC][MC][MC]
+  T* T1 = UC + MC * MC * MC;                         // [MI][B][B]
+  T* T2 = T1 + MI * BB;                              // [MI][MI][B]
+  T* Z = T1;                                         // [MI][MI][MI], after T1 is dead
+  const int y = tb / B, x = tb - (tb / B) * B;
+  const bool ecol = ((y | x) & 1) == 0;
+  int64_t bz = 0, by = 0, bx = 0;
+  if (act) {
+    bx = blk % a.nb[2];
+    const int64_t t = blk / a.nb[2];
+    by = t % a.nb[1];
+    bz = t / a.nb[1];
+  }
+  const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  T w[B], ce[MC];
+  if (act) {
+    const T* col = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z)
+      if ((z & 1) || !ecol) w[z] = col[(oz + z) * a.cs[0]];
+    if (ecol) {
+      const T* ccol = a.cin + (gy >> 1) * a.cn[2] + (gx >> 1);
+#pragma unroll
+      for (int j = 0; j < MC; ++j) {
+        ce[j] = ccol[((oz >> 1) + j) * a.cn[1] * a.cn[2]];
+        w[2 * j] = T(0);
+      }
+    }
+    T o[MI];
+    restrict_solve<T, B>(w, o);
+#pragma unroll
+    for (int J = 0; J < MI; ++J) T1[J * BB + tb] = o[J];
   }
   __syncthreads();
-  correction<T, B>(U, S, tid);
-  for (int i = tid; i < MI * MI * MI; i += NT) {
-    const int J = i / (MI * MI), r = i - J * (MI * MI), I = r / MI, K = r - I * MI;
-    U[lidx<B>(2 * J + 2, 2 * I + 2, 2 * K + 2)] -= S[i];
+  if (act) pass_y<T, B>(T1, T2, tb);
+  __syncthreads();
+  if (act) pass_x<T, B>(T2, Z, tb);
+  __syncthreads();
+  if (act && ecol) {
+    // u_C = c - z on this column's coarse nodes
+    const bool icol = y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3;
+    const int I = (y - 2) >> 1, K = (x - 2) >> 1;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      T u = ce[j];
+      if (icol && j >= 1 && j <= MC - 2) u -= Z[((j - 1) * MI + I) * MI + K];
+      UC[(j * MC + (y >> 1)) * MC + (x >> 1)] = u;
+    }
   }
   __syncthreads();
-  for (int i = tid; i < N; i += NT) {
-    const int lz = i / BB, r = i - lz * BB, ly = r / B, lx = r - ly * B;
-    if (((lz | ly | lx) & 1) == 0) continue;
-    U[i] += interp<T, B>(U, lz, ly, lx);
-  }
-  __syncthreads();
-  const bool lastz = bz == a.nb[0] - 1, lasty = by == a.nb[1] - 1, lastx = bx == a.nb[2] - 1;
-  for (int i = tid; i < N; i += NT) {
-    const int lz = i / BB, r = i - lz * BB, ly = r / B, lx = r - ly * B;
-    if ((lz == B - 1 && !lastz) || (ly == B - 1 && !lasty) || (lx == B - 1 && !lastx)) continue;
-    const int64_t gz = oz + lz, gy = oy + ly, gx = ox + lx;
-    if (gz >= a.on[0] || gy >= a.on[1] || gx >= a.on[2]) continue;
-    a.out[gz * a.os[0] + gy * a.os[1] + gx * a.os[2]] = U[i];
+  if (act) {
+    // u = interpolant(u_C) + w
+    const int cy0 = y >> 1, cy1 = (y + 1) >> 1, cx0 = x >> 1, cx1 = (x + 1) >> 1;
+    T I2[MC];
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      const T* pl = UC + j * MC * MC;
+      I2[j] = T(0.25) * ((pl[cy0 * MC + cx0] + pl[cy0 * MC + cx1]) + (pl[cy1 * MC + cx0] + pl[cy1 * MC + cx1]));
+    }
+    const bool owny = (y < B - 1 || by == a.nb[1] - 1) && gy < a.on[1];
+    const bool ownx = (x < B - 1 || bx == a.nb[2] - 1) && gx < a.on[2];
+    const bool lastz = bz == a.nb[0] - 1;
+    if (owny && ownx) {
+      T* dst = a.out + gy * a.os[1] + gx * a.os[2];
+#pragma unroll
+      for (int z = 0; z < B; ++z) {
+        const T u = (z & 1) ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) + w[z]
+                            : (ecol ? I2[z >> 1] : I2[z >> 1] + w[z]);
+        if ((z < B - 1 || lastz) && oz + z < a.on[0]) dst[(oz + z) * a.os[0]] = u;
+      }
+    }
   }
 }
 
 template <typename T, int B>
 void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout,
                 hipStream_t st) {
+  using G = Geo<B>;
   const Level& L = p.lv[s - 1];
   DecArgs<T> a{};
   a.src = static_cast<const T*>(src.ptr);
@@ -272,14 +340,16 @@ void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* c
   for (int k = 0; k < 3; ++k) a.cs[k] = cv.s[k];
   a.cout = static_cast<T*>(cout);
   a.nblocks = L.nb[0] * L.nb[1] * L.nb[2];
-  a.per = (a.nblocks + 7) / 8;
-  hipLaunchKernelGGL((k_local_decompose<T, B>), dim3(unsigned(8 * a.per)), dim3(NT), 0, st, a);
+  a.nwg = (a.nblocks + G::NB - 1) / G::NB;
+  a.per = (a.nwg + 7) / 8;
+  hipLaunchKernelGGL((k_local_decompose<T, B>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
 
 template <typename T, int B>
 void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
                 hipStream_t st) {
+  using G = Geo<B>;
   const Level& L = p.lv[s - 1];
   RecArgs<T> a{};
   a.coeff = static_cast<const T*>(coeff);
@@ -298,8 +368,9 @@ void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, v
   a.os[1] = on[2];
   a.os[2] = 1;
   a.nblocks = L.nb[0] * L.nb[1] * L.nb[2];
-  a.per = (a.nblocks + 7) / 8;
-  hipLaunchKernelGGL((k_local_recompose<T, B>), dim3(unsigned(8 * a.per)), dim3(NT), 0, st, a);
+  a.nwg = (a.nblocks + G::NB - 1) / G::NB;
+  a.per = (a.nwg + 7) / 8;
+  hipLaunchKernelGGL((k_local_recompose<T, B>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
 

@@ -216,6 +216,15 @@ std::vector<double> level_weights(const bm_plan_s& p) {
   }
   for (int s = p.L + 1; s <= p.nlev; ++s) w[s - 1] = (double(nglob) / N) / double(p.M);
   w[p.nlev] = double(prod(p.lv[p.nlev - 1].m)) / N;
+  // no share below 1/(64 T), T = L+M+1, so small deep levels keep codes in
+  // 32 bits; then renormalise so the shares sum to 1
+  const double floor_w = 1.0 / (64.0 * double(p.nlev + 1));
+  double total = 0.0;
+  for (auto& v : w) {
+    v = v > floor_w ? v : floor_w;
+    total += v;
+  }
+  for (auto& v : w) v = v / total;
   return w;
 }
 
@@ -342,7 +351,8 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     BM_HIP(hipMalloc(&p->ws.boxbuf, size_t(kMaxBoxes) * 7 * sizeof(double)));
     BM_HIP(hipHostMalloc(&p->ws.boxhost, size_t(kMaxBoxes) * 7 * sizeof(double), hipHostMallocDefault));
     BM_HIP(hipMalloc(&p->ws.qparam, size_t(4 * (p->nlev + 2)) * sizeof(double)));
-    BM_HIP(hipMalloc(&p->ws.counters, 16 * sizeof(int64_t)));
+    // 16 counters, then per-workgroup partial statistics of the quantizer (3 x 8192)
+    BM_HIP(hipMalloc(&p->ws.counters, (16 + 3 * 8192) * sizeof(int64_t)));
   } catch (...) {
     // release what was allocated, then rethrow
     for (auto& L : p->lv)

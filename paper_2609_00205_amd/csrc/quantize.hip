@@ -177,9 +177,6 @@ __global__ void k_scalar_delta(ScalarArgs a) {
   }
 }
 
-__global__ void k_zero_counters(int64_t* c) {
-  if (threadIdx.x < 4) c[threadIdx.x] = 0;
-}
 
 struct QArgs {
   uint32_t tot;               // padded node count (< 2^32)
@@ -258,49 +255,134 @@ __device__ inline void node_delta(const QArgs& a, uint32_t z, uint32_t y, uint32
   }
 }
 
+// Each thread handles QU nodes of a tile of NT*QU consecutive nodes per
+// iteration, so the independent loads of those nodes overlap.
+constexpr int QU = 4;
+constexpr int kMaxQGroups = 8192;
+
+inline unsigned qgroups(uint32_t tot) {
+  const int64_t tiles = (int64_t(tot) + NT * QU - 1) / (NT * QU);
+  return unsigned(tiles < kMaxQGroups ? (tiles > 0 ? tiles : 1) : kMaxQGroups);
+}
+
+// Per-workgroup statistics go to partials[3 * group]: outliers, max |q|,
+// out-of-range flag; k_reduce_stats folds them into counters[0..2].
 template <typename T>
-__global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* codes) {
+__global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* codes, int64_t* partials) {
   int64_t nout = 0, mx = 0, bad = 0;
-  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
-    uint32_t z, y, x;
-    a.uf(i, z, y, x);
-    double del, inv;
-    node_delta(a, z, y, x, del, inv);
-    const double v = rint(double(c[i]) * inv);
-    int32_t qv;
-    if (!(fabs(v) <= 2147483647.0)) {
-      bad = 1;
-      qv = 0;
-    } else {
-      qv = int32_t(v);
+  const uint32_t ntiles = (a.tot + NT * QU - 1) / (NT * QU);
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t base = tile * (NT * QU) + threadIdx.x;
+    double cv[QU], inv[QU];
+#pragma unroll
+    for (int k = 0; k < QU; ++k) {
+      const uint32_t i = base + k * NT;
+      cv[k] = 0.0;
+      inv[k] = 0.0;
+      if (i < a.tot) {
+        uint32_t z, y, x;
+        a.uf(i, z, y, x);
+        double del;
+        node_delta(a, z, y, x, del, inv[k]);
+        cv[k] = double(c[i]);
+      }
     }
-    codes[i] = qv;
-    const int64_t aq = qv < 0 ? -int64_t(qv) : int64_t(qv);
-    nout += aq >= 32768;
-    mx = aq > mx ? aq : mx;
+#pragma unroll
+    for (int k = 0; k < QU; ++k) {
+      const uint32_t i = base + k * NT;
+      if (i >= a.tot) continue;
+      const double v = rint(cv[k] * inv[k]);
+      int32_t qv;
+      if (!(fabs(v) <= 2147483647.0)) {
+        bad = 1;
+        qv = 0;
+      } else {
+        qv = int32_t(v);
+      }
+      codes[i] = qv;
+      const int64_t aq = qv < 0 ? -int64_t(qv) : int64_t(qv);
+      nout += aq >= 32768;
+      mx = aq > mx ? aq : mx;
+    }
   }
-  // wave reductions then one atomic per wave
+  __shared__ int64_t red[3][NT / 64];
   for (int off = 32; off > 0; off >>= 1) {
     nout += __shfl_down(nout, off, 64);
     const int64_t o = __shfl_down(mx, off, 64);
     mx = o > mx ? o : mx;
     bad |= __shfl_down(bad, off, 64);
   }
+  const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (nout) atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[0]), static_cast<unsigned long long>(nout));
-    atomicMax(reinterpret_cast<unsigned long long*>(&a.counters[1]), static_cast<unsigned long long>(mx));
-    if (bad) atomicMax(reinterpret_cast<unsigned long long*>(&a.counters[2]), 1ull);
+    red[0][wv] = nout;
+    red[1][wv] = mx;
+    red[2][wv] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s0 = 0, s1 = 0, s2 = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+      s0 += red[0][k];
+      s1 = red[1][k] > s1 ? red[1][k] : s1;
+      s2 |= red[2][k];
+    }
+    partials[3 * blockIdx.x] = s0;
+    partials[3 * blockIdx.x + 1] = s1;
+    partials[3 * blockIdx.x + 2] = s2;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_reduce_stats(const int64_t* partials, int n, int64_t* counters) {
+  __shared__ int64_t r[3][NT];
+  int64_t s0 = 0, s1 = 0, s2 = 0;
+  for (int k = threadIdx.x; k < n; k += NT) {
+    s0 += partials[3 * k];
+    s1 = partials[3 * k + 1] > s1 ? partials[3 * k + 1] : s1;
+    s2 |= partials[3 * k + 2];
+  }
+  r[0][threadIdx.x] = s0;
+  r[1][threadIdx.x] = s1;
+  r[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      r[0][threadIdx.x] += r[0][threadIdx.x + s];
+      r[1][threadIdx.x] = r[1][threadIdx.x + s] > r[1][threadIdx.x] ? r[1][threadIdx.x + s] : r[1][threadIdx.x];
+      r[2][threadIdx.x] |= r[2][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    counters[0] = r[0][0];
+    counters[1] = r[1][0];
+    counters[2] = r[2][0];
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_dequantize(QArgs a, const int32_t* codes, T* c) {
-  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
-    uint32_t z, y, x;
-    a.uf(i, z, y, x);
-    double del, inv;
-    node_delta(a, z, y, x, del, inv);
-    c[i] = T(double(codes[i]) * del);
+  const uint32_t ntiles = (a.tot + NT * QU - 1) / (NT * QU);
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t base = tile * (NT * QU) + threadIdx.x;
+    double q[QU], del[QU];
+#pragma unroll
+    for (int k = 0; k < QU; ++k) {
+      const uint32_t i = base + k * NT;
+      q[k] = 0.0;
+      del[k] = 0.0;
+      if (i < a.tot) {
+        uint32_t z, y, x;
+        a.uf(i, z, y, x);
+        double inv;
+        node_delta(a, z, y, x, del[k], inv);
+        q[k] = double(codes[i]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < QU; ++k) {
+      const uint32_t i = base + k * NT;
+      if (i < a.tot) c[i] = T(q[k] * del[k]);
+    }
   }
 }
 
@@ -421,11 +503,15 @@ void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t*
   {
     TimedScope ts(p, 2 * p.nlev, st);
     QArgs a = prepare(p, block_tol, st);
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, p.ws.counters);
+    const unsigned g = qgroups(a.tot);
+    int64_t* partials = p.ws.counters + 16;
     if (p.cfg.dtype == BM_F32)
-      hipLaunchKernelGGL(k_quantize<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a, static_cast<const float*>(coeff), codes);
+      hipLaunchKernelGGL(k_quantize<float>, dim3(g), dim3(NT), 0, st, a, static_cast<const float*>(coeff), codes,
+                         partials);
     else
-      hipLaunchKernelGGL(k_quantize<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a, static_cast<const double*>(coeff), codes);
+      hipLaunchKernelGGL(k_quantize<double>, dim3(g), dim3(NT), 0, st, a, static_cast<const double*>(coeff), codes,
+                         partials);
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(NT), 0, st, partials, int(g), p.ws.counters);
     BM_HIP(hipGetLastError());
   }
   if (stats) {
@@ -443,10 +529,12 @@ void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, voi
   TimedScope ts(p, 2 * p.nlev + 1, st);
   QArgs a = prepare(p, block_tol, st);
   const int64_t tot = prod3(p.pdims);
+  (void)tot;
+  const unsigned g = qgroups(a.tot);
   if (p.cfg.dtype == BM_F32)
-    hipLaunchKernelGGL(k_dequantize<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a, codes, static_cast<float*>(coeff));
+    hipLaunchKernelGGL(k_dequantize<float>, dim3(g), dim3(NT), 0, st, a, codes, static_cast<float*>(coeff));
   else
-    hipLaunchKernelGGL(k_dequantize<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a, codes, static_cast<double*>(coeff));
+    hipLaunchKernelGGL(k_dequantize<double>, dim3(g), dim3(NT), 0, st, a, codes, static_cast<double*>(coeff));
   BM_HIP(hipGetLastError());
 }
 

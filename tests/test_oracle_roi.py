@@ -152,8 +152,15 @@ def test_budget_shares_tighten_as_levels_coarsen():
     assert sum(w) == pytest.approx(1.0, abs=1e-15)
     assert w[0] > w[1] > w[2]                  # local levels, then the global block
     assert w[2] == w[3] == w[4]                # equal global shares
-    assert w[0] == pytest.approx((65 ** 3 - 33 ** 3) / 65 ** 3)
-    assert w[5] == pytest.approx(3 ** 3 / 65 ** 3)   # 65 -> 33 -> 17 -> 9 -> 5 -> 3
+    # 65 -> 33 -> 17 -> 9 -> 5 -> 3: the coarsest share 27 / 65^3 is below the
+    # floor 1/(64 T) and is raised to it before renormalising
+    floor = 1 / (64 * 6)
+    raw0 = (65 ** 3 - 33 ** 3) / 65 ** 3
+    nglob = 17 ** 3 - 3 ** 3
+    raw = [raw0, (33 ** 3 - 17 ** 3) / 65 ** 3] + [max(floor, nglob / 65 ** 3 / 3)] * 3 + [max(floor, 27 / 65 ** 3)]
+    assert w[0] == pytest.approx(raw0 / sum(raw))
+    assert w[5] == pytest.approx(floor / sum(raw))
+    assert min(w) >= floor / sum(raw) * (1 - 1e-12)
 
 
 def test_quantizer_round_half_even_and_reciprocal():
