@@ -5,13 +5,16 @@ Workload: one 512^3 FP32 Gaussian random field with power spectrum k^-3
 (seeded), two disjoint 64^3 ROI boxes at REL 1e-5, background REL 1e-2,
 17^3 shared-face blocks, L = 1 In-cache Block level then M = 2 global levels.
 
-One step = decompose -> ROI quantize -> dequantize -> recompose, all on the
-device with the field already resident in HBM.  `value` is
-2 * (512^3 * 4 bytes) / step time: the decompose and the recompose of the
-field, quantization included.  Per-level kernel times come from HIP events
-the library records on the same stream.  The compression ratio at the ROI
-bounds is measured once outside the timed region (full compress with the
-Huffman stage), and every reconstructed value is checked against its bound.
+One step = fused decompose + ROI quantize (codes written by the block and
+detail kernels) followed by fused dequantize + recompose, all on the device
+with the field already resident in HBM (the paper's fused pipeline, its
+default configuration).  `value` is 2 * (512^3 * 4 bytes) / step time: the
+decompose and the recompose of the field, quantization included.  The plain
+transform (decompose, recompose without quantization) is timed separately.
+Per-level kernel times come from HIP events the library records on the same
+stream.  The compression ratio at the ROI bounds is measured once outside
+the timed region (full compress with the Huffman stage), and every
+reconstructed value is checked against its bound.
 """
 from __future__ import annotations
 
@@ -96,35 +99,46 @@ def main():
     plan = Plan((n, n, n), dtype=torch.float32, block=b, L=L, M=M)
     bt = plan.tolmap_from_boxes(abs_boxes, bg)
     coeff = torch.empty(plan.coeff_shape, dtype=torch.float32, device="cuda")
-    coeff2 = torch.empty_like(coeff)
     codes = torch.empty(plan.coeff_shape, dtype=torch.int32, device="cuda")
     xr = torch.empty_like(xd)
+    xt = torch.empty_like(xd)
 
     def step():
-        plan.decompose(xd, out=coeff)
-        plan.quantize(coeff, bt, codes=codes, stats=False)
-        plan.dequantize(codes, bt, out=coeff2)
-        plan.recompose(coeff2, out=xr)
+        # fused decompose + ROI quantize, then fused dequantize + recompose
+        plan.decompose_quantize(xd, bt, codes=codes, check=False)
+        plan.dequantize_recompose(codes, bt, out=xr)
 
+    def transform():
+        plan.decompose(xd, out=coeff)
+        plan.recompose(coeff, out=xt)
+
+    K = args.steps
     for _ in range(args.warmup):
         step()
+        transform()
     torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] timing {K} steps", file=sys.stderr, flush=True)
     plan.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(K):
         step()
     e1.record()
     torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step = e0.elapsed_time(e1) / K
     t = plan.timing_get()
+    # the plain transform (no quantization), timed the same way
+    plan.timing(True)
+    for _ in range(K):
+        transform()
+    torch.cuda.synchronize()
+    tt = plan.timing_get()
     plan.timing(False)
-    K = args.steps
     dec_ms = sum(t["decompose"]) / K
     rec_ms = sum(t["recompose"]) / K
-    q_ms, dq_ms = t["quantize"] / K, t["dequantize"] / K
+    tdec_ms = sum(tt["decompose"]) / K
+    trec_ms = sum(tt["recompose"]) / K
     local_ms = t["decompose"][0] / max(1, t["calls"]["decompose"][0])
 
     in_bytes = n ** 3 * 4
@@ -189,16 +203,18 @@ def main():
         "config": {"workload": f"{n}^3 FP32 k^-3 Gaussian random field, two 64^3 ROI boxes at REL 1e-5, "
                                f"background REL 1e-2; b=17 shared-face blocks, L=1 local + M=2 global levels",
                    "block": b, "L": L, "M": M, "padded": list(plan.coeff_shape)},
-        "roofline": {"bound": "hbm", "kernel": "k_local_decompose<float,17> (level 1)",
+        "roofline": {"bound": "hbm", "kernel": "k_local_decompose<float,17,fused> (level 1)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(local_ms, 5)},
-        "phases_ms": {"decompose": round(dec_ms, 4), "quantize": round(q_ms, 4), "dequantize": round(dq_ms, 4),
-                      "recompose": round(rec_ms, 4),
+        "phases_ms": {"decompose_quantize": round(dec_ms, 4), "dequantize_recompose": round(rec_ms, 4),
                       "decompose_levels": [round(v / K, 4) for v in t["decompose"]],
-                      "recompose_levels": [round(v / K, 4) for v in t["recompose"]]},
-        "decompose_GBps": round(in_bytes / (dec_ms * 1e-3) / 1e9, 2),
-        "recompose_GBps": round(in_bytes / (rec_ms * 1e-3) / 1e9, 2),
+                      "recompose_levels": [round(v / K, 4) for v in t["recompose"]],
+                      "transform_decompose": round(tdec_ms, 4), "transform_recompose": round(trec_ms, 4)},
+        "decompose_quantize_GBps": round(in_bytes / (dec_ms * 1e-3) / 1e9, 2),
+        "dequantize_recompose_GBps": round(in_bytes / (rec_ms * 1e-3) / 1e9, 2),
+        "transform_decompose_GBps": round(in_bytes / (tdec_ms * 1e-3) / 1e9, 2),
+        "transform_recompose_GBps": round(in_bytes / (trec_ms * 1e-3) / 1e9, 2),
         "compression_ratio": round(ratio, 3),
         "compress_s": round(t1 - t0, 3),
         "decompress_s": round(t2 - t1, 3),

@@ -169,6 +169,20 @@ bm_status bm_quantize_roi(bm_plan plan, const void* coeff, const double* block_t
 bm_status bm_dequantize(bm_plan plan, const int32_t* codes, const double* block_tol, void* coeff,
                         hipStream_t stream);
 
+/* Fused decompose + quantize (the paper's fused pipeline, Sec. IV-D): the
+ * block levels write codes straight from on-chip memory; global-level
+ * details are quantized as they are produced.  codes (device int32, padded
+ * dims) equal bm_decompose followed by bm_quantize_roi with the same map.
+ * If stats is non-NULL the call synchronizes and returns BM_ERANGE for a
+ * code beyond int32 (n_outliers and max_abs_code are then -1: not counted). */
+bm_status bm_decompose_quantize(bm_plan plan, const void* x, const double* block_tol, int32_t* codes,
+                                bm_qstats* stats, hipStream_t stream);
+
+/* Fused dequantize + recompose: x equals bm_dequantize followed by
+ * bm_recompose.  Asynchronous. */
+bm_status bm_dequantize_recompose(bm_plan plan, const int32_t* codes, const double* block_tol, void* x,
+                                  hipStream_t stream);
+
 /* ---- lossless stage (Sec. IV-B lossless stages) ----------------------- */
 
 /* Canonical Huffman coding of n int32 codes (device) in raster order.

@@ -53,6 +53,8 @@ _SIGS = {
     "bm_compress": [P, P, P, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_compressed_config": [P, C.c_size_t, C.POINTER(BMConfig)],
     "bm_decompress": [P, C.c_size_t, P, P],
+    "bm_decompose_quantize": [P, P, P, P, C.POINTER(BMQStats), P],
+    "bm_dequantize_recompose": [P, P, P, P, P],
     "bm_timing": [P, C.c_int],
     "bm_timing_get": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)],
 }

@@ -146,6 +146,30 @@ class Plan:
         call("bm_dequantize", self._h, _ptr(codes), _ptr(block_tol), _ptr(out), _stream(stream))
         return out
 
+    def decompose_quantize(self, x: torch.Tensor, block_tol: torch.Tensor, codes: Optional[torch.Tensor] = None,
+                           check: bool = True, stream=None) -> torch.Tensor:
+        """Fused decompose + ROI quantize: codes equal quantize(decompose(x))."""
+        _need(x, self.dtype, self.shape, "x")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        if codes is None:
+            codes = torch.empty(self.coeff_shape, dtype=torch.int32, device=x.device)
+        _need(codes, torch.int32, self.coeff_shape, "codes")
+        st = BMQStats()
+        call("bm_decompose_quantize", self._h, _ptr(x), _ptr(block_tol), _ptr(codes),
+             C.byref(st) if check else None, _stream(stream))
+        return codes
+
+    def dequantize_recompose(self, codes: torch.Tensor, block_tol: torch.Tensor, out: Optional[torch.Tensor] = None,
+                             stream=None) -> torch.Tensor:
+        """Fused dequantize + recompose: equals recompose(dequantize(codes))."""
+        _need(codes, torch.int32, self.coeff_shape, "codes")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=codes.device)
+        _need(out, self.dtype, self.shape, "out")
+        call("bm_dequantize_recompose", self._h, _ptr(codes), _ptr(block_tol), _ptr(out), _stream(stream))
+        return out
+
     # -- per-level timing ------------------------------------------------------
     def timing(self, enable: bool) -> None:
         """Start (reset) or stop recording HIP events around each level."""

@@ -215,6 +215,23 @@ bm_status bm_dequantize(bm_plan p, const int32_t* codes, const double* block_tol
   });
 }
 
+bm_status bm_decompose_quantize(bm_plan p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
+                                hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && codes, "null argument");
+    check_device(p);
+    bm::decompose_quantize(*p, x, block_tol, codes, stats, st);
+  });
+}
+
+bm_status bm_dequantize_recompose(bm_plan p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && codes, "null argument");
+    check_device(p);
+    bm::dequantize_recompose(*p, codes, block_tol, x, st);
+  });
+}
+
 bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
                             hipStream_t st) {
   return guarded([&] {
@@ -248,11 +265,10 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
     BM_HIP(hipStreamSynchronize(st));
     for (double t : tol)
       if (!(t > 0) || !std::isfinite(t)) bm::fail(BM_ENONFINITE, "block tolerances must be positive and finite");
-    bm::decompose(*p, x, p->ws.coeff, st);
     bm_qstats qs;
     bool too_fine = false;   // codes beyond 32 bits: store the raw data
     try {
-      bm::quantize(*p, p->ws.coeff, block_tol, static_cast<int32_t*>(p->ws.codes), &qs, st);
+      bm::decompose_quantize(*p, x, block_tol, static_cast<int32_t*>(p->ws.codes), &qs, st);
     } catch (const bm::Error& e) {
       if (e.code != BM_ERANGE) throw;
       too_fine = true;
@@ -331,8 +347,7 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
     const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];
     bm::huffman_decode(pl + ntol * 8, size_t(h.payload) - size_t(ntol) * 8, static_cast<int32_t*>(p->ws.codes),
                        npad, st);
-    bm::dequantize(*p, static_cast<const int32_t*>(p->ws.codes), g.d, p->ws.coeff, st);
-    bm::recompose(*p, p->ws.coeff, x, st);
+    bm::dequantize_recompose(*p, static_cast<const int32_t*>(p->ws.codes), g.d, x, st);
     BM_HIP(hipStreamSynchronize(st));
   });
 }

@@ -44,7 +44,21 @@ struct DetArgs {
   int cm0, cm1, cm2;     // 1 if the axis coarsens at this level
   T* coeff;
   int64_t cs[3];
+  int32_t* codes;        // fused quantization: write codes instead (same strides)
+  const double* qinv;    // 1/Delta of this level (device scalar)
+  int64_t* flag;         // set when a code does not fit in int32
 };
+
+// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag
+template <typename T>
+__device__ inline int32_t quant_g(T c, double inv, int64_t* flag) {
+  const double v = rint(mul_rn(double(c), inv));
+  if (!(fabs(v) <= 2147483647.0)) {
+    atomicOr(reinterpret_cast<unsigned long long*>(flag), 1ull);
+    return 0;
+  }
+  return int32_t(v);
+}
 
 // Interpolant at (z,y,x) from a grid holding the coarse values: mean of the
 // 8 corners of the coarse cell (an axis that does not coarsen, or an even
@@ -70,7 +84,11 @@ __global__ __launch_bounds__(NT) void k_details(DetArgs<T> a) {
     if (coarse) continue;
     auto rd = [&](int64_t zz, int64_t yy, int64_t xx) { return a.u[(zz * a.n.n1 + yy) * a.n.n2 + xx]; };
     const T d = a.u[i] - interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
-    a.coeff[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]] = d;
+    const int64_t o = z * a.cs[0] + y * a.cs[1] + x * a.cs[2];
+    if (a.codes)
+      a.codes[o] = quant_g(d, *a.qinv, a.flag);
+    else
+      a.coeff[o] = d;
   }
 }
 
@@ -83,6 +101,8 @@ struct IntArgs {
   Idx3 n;                // dims of G^{s-1}
   int cm0, cm1, cm2;
   T* out;                // dense G^{s-1}
+  const int32_t* codes;  // fused dequantization: details from codes (same strides)
+  const double* qdel;    // Delta of this level (device scalar)
 };
 
 template <typename T>
@@ -100,7 +120,9 @@ __global__ __launch_bounds__(NT) void k_interp_add(IntArgs<T> a) {
     if (coarse)
       v = rd(z, y, x);
     else
-      v = a.coeff[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]] + interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
+      v = (a.codes ? T(mul_rn(double(a.codes[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]]), *a.qdel))
+                   : a.coeff[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]]) +
+          interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
     a.out[i] = v;
   }
 }
@@ -174,6 +196,8 @@ struct PassArgs {
   T* out;                // dense, dims on
   int64_t on[3];
   const T* base;         // optional: out = base - result (dense, dims on)
+  const int32_t* qin;    // optional: read codes (same strides as in) and dequantize with *qdel
+  const double* qdel;
   const double* inv;     // Thomas reciprocal pivots, length m
   int64_t nl, m;         // line length, coarse length
   int W;                 // lines per tile
@@ -231,7 +255,8 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
       i = k / wv;
       w = k - i * wv;
     }
-    T v = a.in[p * sP + (q0 + w) * sQ + i * sA];
+    const int64_t off = p * sP + (q0 + w) * sQ + i * sA;
+    T v = a.qin ? T(mul_rn(double(a.qin[off]), *a.qdel)) : a.in[off];
     if (a.mask) {
       int64_t c[3];
       c[a.axis] = i;
@@ -329,10 +354,12 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
 
 template <typename T>
 void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
-                 const void* base, hipStream_t st) {
+                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st) {
   const Level& L = p.lv[s - 1];
   PassArgs<T> a{};
   a.in = static_cast<const T*>(in.ptr);
+  a.qin = qin;
+  a.qdel = qdel;
   for (int k = 0; k < 3; ++k) {
     a.is[k] = in.s[k];
     a.n[k] = in.n[k];
@@ -363,51 +390,105 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   BM_HIP(hipGetLastError());
 }
 
-}  // namespace
-
 // ------------------------------------------------------------- launchers
 
-void global_details(const bm_plan_s& p, int s, const void* u, void* coeff, hipStream_t st) {
+template <typename T>
+void launch_details(const bm_plan_s& p, int s, const void* u, void* coeff, int32_t* codes, const double* qinv,
+                    int64_t* flag, hipStream_t st) {
   const Level& L = p.lv[s - 1];
-  const View3 cv = level_view(p, s, coeff);
+  const View3 cv = level_view(p, s, codes ? static_cast<void*>(codes) : coeff);
   const int64_t tot = L.n[0] * L.n[1] * L.n[2];
-  if (p.cfg.dtype == BM_F32) {
-    DetArgs<float> a{static_cast<const float*>(u), {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1],
-                     L.coarsen[2], static_cast<float*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}};
-    hipLaunchKernelGGL(k_details<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
-  } else {
-    DetArgs<double> a{static_cast<const double*>(u), {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1],
-                      L.coarsen[2], static_cast<double*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}};
-    hipLaunchKernelGGL(k_details<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
-  }
+  DetArgs<T> a{static_cast<const T*>(u), {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
+               static_cast<T*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, codes, qinv, flag};
+  hipLaunchKernelGGL(k_details<T>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
 
-void global_interp_add(const bm_plan_s& p, int s, const void* coeff, const void* uc, void* out, hipStream_t st) {
+template <typename T>
+void launch_interp(const bm_plan_s& p, int s, const void* coeff, const int32_t* codes, const double* qdel,
+                   const void* uc, void* out, hipStream_t st) {
   const Level& L = p.lv[s - 1];
-  const View3 cv = level_view(p, s, const_cast<void*>(coeff));
+  const View3 cv = level_view(p, s, codes ? const_cast<int32_t*>(codes) : const_cast<void*>(coeff));
   const int64_t tot = L.n[0] * L.n[1] * L.n[2];
-  if (p.cfg.dtype == BM_F32) {
-    IntArgs<float> a{static_cast<const float*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, static_cast<const float*>(uc),
-                     {L.m[0], L.m[1], L.m[2]}, {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
-                     static_cast<float*>(out)};
-    hipLaunchKernelGGL(k_interp_add<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
-  } else {
-    IntArgs<double> a{static_cast<const double*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, static_cast<const double*>(uc),
-                      {L.m[0], L.m[1], L.m[2]}, {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
-                      static_cast<double*>(out)};
-    hipLaunchKernelGGL(k_interp_add<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
-  }
+  IntArgs<T> a{static_cast<const T*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, static_cast<const T*>(uc),
+               {L.m[0], L.m[1], L.m[2]}, {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
+               static_cast<T*>(out), codes, qdel};
+  hipLaunchKernelGGL(k_interp_add<T>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
+}
+
+// quantize (to_codes) or dequantize a strided view; *scale is 1/Delta or Delta
+template <typename T>
+__global__ __launch_bounds__(NT) void k_qcopy(const T* src, int64_t ss0, int64_t ss1, int64_t ss2, const int32_t* csrc,
+                                              T* dst, int32_t* cdst, int64_t ds0, int64_t ds1, int64_t ds2, Idx3 n,
+                                              const double* scale, int64_t* flag) {
+  const int64_t tot = n.n0 * n.n1 * n.n2;
+  const double sc = *scale;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t z, y, x;
+    unflat(i, n, z, y, x);
+    const int64_t so = z * ss0 + y * ss1 + x * ss2, dO = z * ds0 + y * ds1 + x * ds2;
+    if (cdst)
+      cdst[dO] = quant_g(src[so], sc, flag);
+    else
+      dst[dO] = T(mul_rn(double(csrc[so]), sc));
+  }
+}
+
+}  // namespace
+
+void global_details(const bm_plan_s& p, int s, const void* u, void* coeff, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32)
+    launch_details<float>(p, s, u, coeff, nullptr, nullptr, nullptr, st);
+  else
+    launch_details<double>(p, s, u, coeff, nullptr, nullptr, nullptr, st);
+}
+
+void global_interp_add(const bm_plan_s& p, int s, const void* coeff, const void* uc, void* out, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32)
+    launch_interp<float>(p, s, coeff, nullptr, nullptr, uc, out, st);
+  else
+    launch_interp<double>(p, s, coeff, nullptr, nullptr, uc, out, st);
 }
 
 void line_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
                const void* base, hipStream_t st) {
   if (p.cfg.dtype == BM_F32)
-    launch_pass<float>(p, s, axis, in, cmask, out, base, st);
+    launch_pass<float>(p, s, axis, in, cmask, out, base, nullptr, nullptr, st);
   else
-    launch_pass<double>(p, s, axis, in, cmask, out, base, st);
+    launch_pass<double>(p, s, axis, in, cmask, out, base, nullptr, nullptr, st);
 }
+
+namespace {
+
+void line_pass_q(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
+                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32)
+    launch_pass<float>(p, s, axis, in, cmask, out, base, qin, qdel, st);
+  else
+    launch_pass<double>(p, s, axis, in, cmask, out, base, qin, qdel, st);
+}
+
+void qcopy(const bm_plan_s& p, const View3& src, const int32_t* csrc, const View3& dst, int32_t* cdst,
+           const double* scale, int64_t* flag, hipStream_t st) {
+  const int64_t tot = src.n[0] * src.n[1] * src.n[2];
+  const Idx3 n{src.n[0], src.n[1], src.n[2]};
+  if (p.cfg.dtype == BM_F32)
+    hipLaunchKernelGGL(k_qcopy<float>, dim3(grid_for(tot)), dim3(NT), 0, st, static_cast<const float*>(src.ptr),
+                       src.s[0], src.s[1], src.s[2], csrc, static_cast<float*>(dst.ptr), cdst, dst.s[0], dst.s[1],
+                       dst.s[2], n, scale, flag);
+  else
+    hipLaunchKernelGGL(k_qcopy<double>, dim3(grid_for(tot)), dim3(NT), 0, st, static_cast<const double*>(src.ptr),
+                       src.s[0], src.s[1], src.s[2], csrc, static_cast<double*>(dst.ptr), cdst, dst.s[0], dst.s[1],
+                       dst.s[2], n, scale, flag);
+  BM_HIP(hipGetLastError());
+}
+
+__global__ void k_zero_flag(int64_t* f) {
+  if (threadIdx.x == 0) *f = 0;
+}
+
+}  // namespace
 
 void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t st) {
   const int64_t tot = src.n[0] * src.n[1] * src.n[2];
@@ -441,7 +522,8 @@ static void pad_input(const bm_plan_s& p, const void* x, void* dst, hipStream_t 
 
 // coarse = K_z K_y K_x (in), applied as line passes over the axes that
 // coarsen; intermediate results go through the plan's temporaries.
-static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const void* base, hipStream_t st) {
+static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const void* base, hipStream_t st,
+                     const int32_t* qin = nullptr, const double* qdel = nullptr) {
   const Level& L = p.lv[s - 1];
   int axes[3], na = 0;
   for (int a : {2, 1, 0})
@@ -453,7 +535,8 @@ static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const 
     const int ax = axes[k];
     const bool last = k == na - 1;
     void* dst = last ? out : tmp[k & 1];
-    line_pass(p, s, ax, cur, (k == 0 && mask) ? cm : nullptr, dst, last ? base : nullptr, st);
+    line_pass_q(p, s, ax, cur, (k == 0 && mask) ? cm : nullptr, dst, last ? base : nullptr, k == 0 ? qin : nullptr,
+                qdel, st);
     int64_t on[3] = {cur.n[0], cur.n[1], cur.n[2]};
     on[ax] = L.m[ax];
     cur = dense_view(dst, on);
@@ -498,6 +581,87 @@ void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
       apply_K3(p, s, level_view(p, s, const_cast<void*>(coeff)), true, p.ws.grid[s], p.ws.grid[s], st);
       void* out = p.ws.grid[s - 1];
       global_interp_add(p, s, coeff, p.ws.grid[s], out, st);
+      if (s == 1) {
+        View3 src = dense_view(out, p.pdims);
+        src.n[0] = p.dims[0];
+        src.n[1] = p.dims[1];
+        src.n[2] = p.dims[2];
+        strided_copy(p.esize, src, dense_view(x, p.dims), st);
+      }
+    }
+  }
+}
+
+// Fused pipeline (the paper's BMF form, Sec. IV-D): the block levels write
+// quantization codes directly, global levels quantize their details as the
+// detail stencil produces them, and the coarsest values last.  The codes are
+// identical to bm_decompose followed by bm_quantize_roi.
+void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
+                        hipStream_t st) {
+  const QPrep q = quant_prepare(p, block_tol, st);
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, q.flag);
+  const View3 xv = dense_view(const_cast<void*>(x), p.dims);
+  for (int s = 1; s <= p.nlev; ++s) {
+    const Level& L = p.lv[s - 1];
+    TimedScope ts(p, 2 * (s - 1), st);
+    if (L.local) {
+      const View3 src = s == 1 ? xv : dense_view(p.ws.grid[s - 1], L.n);
+      local_decompose_q(p, s, src, s == 1, codes, p.ws.grid[s], q, st);
+    } else {
+      const void* u;
+      if (s == 1) {
+        pad_input(p, x, p.ws.grid[0], st);
+        u = p.ws.grid[0];
+      } else {
+        u = p.ws.grid[s - 1];
+      }
+      if (p.cfg.dtype == BM_F32)
+        launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+      else
+        launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+      apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
+    }
+  }
+  if (p.M > 0 || p.L == 0) {
+    const Level& last = p.lv[p.nlev - 1];
+    const View3 cv = coarsest_view(p, codes);
+    qcopy(p, dense_view(p.ws.grid[p.nlev], last.m), nullptr, cv, codes, q.q + 2 * p.nlev + 1, q.flag, st);
+  }
+  if (stats) {
+    int64_t f = 0;
+    BM_HIP(hipMemcpyAsync(&f, q.flag, sizeof(f), hipMemcpyDeviceToHost, st));
+    BM_HIP(hipStreamSynchronize(st));
+    stats->n_codes = p.pdims[0] * p.pdims[1] * p.pdims[2];
+    stats->n_outliers = -1;
+    stats->max_abs_code = -1;
+    if (f) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+  }
+}
+
+// Inverse of decompose_quantize: dequantize on load, then recompose.  Equal
+// to bm_dequantize followed by bm_recompose.
+void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st) {
+  const QPrep q = quant_prepare(p, block_tol, st);
+  if (p.M > 0 || p.L == 0) {
+    const Level& last = p.lv[p.nlev - 1];
+    const View3 cv = coarsest_view(p, const_cast<int32_t*>(codes));
+    qcopy(p, cv, codes, dense_view(p.ws.grid[p.nlev], last.m), nullptr, q.q + 2 * p.nlev, nullptr, st);
+  }
+  for (int s = p.nlev; s >= 1; --s) {
+    const Level& L = p.lv[s - 1];
+    TimedScope ts(p, 2 * (s - 1) + 1, st);
+    if (L.local) {
+      void* out = s == 1 ? x : p.ws.grid[s - 1];
+      local_recompose_q(p, s, codes, p.ws.grid[s], out, s == 1, q, st);
+    } else {
+      const double* qdel = q.q + 2 * (s - 1);
+      apply_K3(p, s, level_view(p, s, const_cast<int32_t*>(codes)), true, p.ws.grid[s], p.ws.grid[s], st, codes,
+               qdel);
+      void* out = p.ws.grid[s - 1];
+      if (p.cfg.dtype == BM_F32)
+        launch_interp<float>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
+      else
+        launch_interp<double>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
       if (s == 1) {
         View3 src = dense_view(out, p.pdims);
         src.n[0] = p.dims[0];

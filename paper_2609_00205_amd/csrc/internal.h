@@ -54,6 +54,14 @@ struct Unflat32 {
   }
 };
 
+// Product rounded on its own (never contracted into a neighbouring add), so
+// a dequantized value q * Delta is the same number whether it is stored to
+// memory or consumed in registers.
+__device__ inline double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 __host__ __device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
 __host__ __device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
 
@@ -156,6 +164,33 @@ void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t 
 // decompose / recompose drivers
 void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st);
 void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st);
+
+// quantization tables on the device, built from a level-1 block map:
+// per local level s (slot s-1) the per-block Delta and 1/Delta; slot 8 for
+// the coarsest values when M == 0 (level-L blocks); scalar Delta / 1/Delta
+// per global level (q[2(s-1)], q[2(s-1)+1]) and for the coarsest values
+// (q[2(L+M)], q[2(L+M)+1]).
+struct QTab {
+  const double* del = nullptr;
+  const double* inv = nullptr;
+  int64_t nb[3] = {1, 1, 1};
+};
+struct QPrep {
+  QTab lv[9];
+  const double* q = nullptr;
+  int64_t* flag = nullptr;      // set to 1 when a code does not fit in int32
+};
+constexpr int kCoarseSlotHost = 8;
+QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st);
+
+// fused decompose + quantize and dequantize + recompose (codes in place)
+void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
+                        hipStream_t st);
+void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st);
+void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, int32_t* codes, void* coarse_out,
+                       const QPrep& q, hipStream_t st);
+void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const void* coarse_in, void* out, bool last,
+                       const QPrep& q, hipStream_t st);
 
 // quantization
 void tolmap_from_boxes(bm_plan_s& p, const double* boxes, int nbox, double background, double* block_tol,

@@ -112,6 +112,12 @@ struct DecArgs {
   T* cout;                // compact coarse grid G^s
   int64_t cn[3];
   int64_t nb[3], nblocks, nwg, per;
+  // fused quantization (codes written instead of coefficients)
+  int32_t* codes;         // same layout as coeff
+  QTab tab;               // this level's block tables
+  QTab ctab;              // coarsest-value tables (last block level when M == 0)
+  int coarsest_here;
+  int64_t* flag;          // set when a code does not fit in int32
 };
 
 template <typename T>
@@ -123,9 +129,56 @@ struct RecArgs {
   T* out;                 // output grid view (cropped to on)
   int64_t on[3], os[3];
   int64_t nb[3], nblocks, nwg, per;
+  const int32_t* codes;   // fused dequantization: codes instead of coefficients
+  QTab tab, ctab;
+  int coarsest_here;
 };
 
-template <typename T, int B>
+// Delta and 1/Delta of the nodes of one z-column: a node takes the smallest
+// Delta (largest 1/Delta) of the blocks that contain it.  A node on a block
+// face (local coordinate 0 or B-1) also lies in the neighbour across it.
+// Results for z = 0, for 0 < z < B-1 and for z = B-1.
+// INV: read 1/Delta and keep the largest, else read Delta and keep the smallest.
+template <int B, bool INV>
+__device__ inline void column_tables(const QTab& t, int64_t bz, int64_t by, int64_t bx, int y, int x, double out[3]) {
+  // candidate blocks per axis: own block, plus the neighbour across a face
+  const int64_t y2 = (y == 0 && by > 0) ? by - 1 : ((y == B - 1 && by + 1 < t.nb[1]) ? by + 1 : by);
+  const int64_t x2 = (x == 0 && bx > 0) ? bx - 1 : ((x == B - 1 && bx + 1 < t.nb[2]) ? bx + 1 : bx);
+  const int64_t zc[3] = {bz > 0 ? bz - 1 : bz, bz, bz + 1 < t.nb[0] ? bz + 1 : bz};
+  const double* tab = INV ? t.inv : t.del;
+  auto pick = [](double a, double b) { return INV ? fmax(a, b) : fmin(a, b); };
+  double l[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t r0 = zc[c] * t.nb[1];
+    double v = tab[(r0 + by) * t.nb[2] + bx];
+    if (x2 != bx) v = pick(v, tab[(r0 + by) * t.nb[2] + x2]);
+    if (y2 != by) {
+      v = pick(v, tab[(r0 + y2) * t.nb[2] + bx]);
+      if (x2 != bx) v = pick(v, tab[(r0 + y2) * t.nb[2] + x2]);
+    }
+    l[c] = v;
+  }
+  out[0] = pick(l[0], l[1]);
+  out[1] = l[1];
+  out[2] = pick(l[1], l[2]);
+}
+
+template <int B>
+__device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
+
+// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag
+template <typename T>
+__device__ inline int32_t quant(T c, double inv, int64_t* flag) {
+  const double v = rint(mul_rn(double(c), inv));
+  if (!(fabs(v) <= 2147483647.0)) {
+    atomicOr(reinterpret_cast<unsigned long long*>(flag), 1ull);
+    return 0;
+  }
+  return int32_t(v);
+}
+
+template <typename T, int B, bool Q>
 __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
   using G = Geo<B>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
@@ -150,6 +203,12 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
     bz = t / a.nb[1];
   }
   const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  // fused quantization: this column's 1/Delta, loaded early so the latency hides
+  double iv[3], ci[3];
+  if (Q && act) {
+    column_tables<B, true>(a.tab, bz, by, bx, y, x, iv);
+    if (a.coarsest_here && ((y | x) & 1) == 0) column_tables<B, true>(a.ctab, bz, by, bx, y, x, ci);
+  }
   T v[B];
   if (act) {
     // one column: clamp or zero-fill outside the logical input on level 1
@@ -220,11 +279,26 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
     const bool ownx = x < B - 1 || bx == a.nb[2] - 1;
     const bool lastz = bz == a.nb[0] - 1;
     if (owny && ownx) {
-      T* dst = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+      if (!Q) {
+        T* dst = a.coeff + gy * a.cs[1] + gx * a.cs[2];
 #pragma unroll
-      for (int z = 0; z < B; ++z)
-        if (z < B - 1 || lastz) dst[(oz + z) * a.cs[0]] = w[z];
-      if (ecol) {
+        for (int z = 0; z < B; ++z)
+          if (z < B - 1 || lastz) dst[(oz + z) * a.cs[0]] = w[z];
+      } else {
+        // fused quantization: codes for the details of this level (and for
+        // the coarsest values when this is the last level of the hierarchy)
+        int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
+#pragma unroll
+        for (int z = 0; z < B; ++z) {
+          if (z == B - 1 && !lastz) continue;
+          const bool coarse = ecol && (z & 1) == 0;
+          if (!coarse)
+            dst[(oz + z) * a.cs[0]] = quant(w[z], iv[zcase<B>(z)], a.flag);
+          else if (a.coarsest_here)
+            dst[(oz + z) * a.cs[0]] = quant(w[z], ci[zcase<B>(z)], a.flag);
+        }
+      }
+      if (ecol && !(Q && a.coarsest_here)) {
         T* cdst = a.cout + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
         for (int j = 0; j < MC; ++j)
@@ -234,7 +308,7 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
   }
 }
 
-template <typename T, int B>
+template <typename T, int B, bool Q>
 __global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
   using G = Geo<B>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
@@ -262,17 +336,40 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
   const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
   T w[B], ce[MC];
   if (act) {
-    const T* col = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+    if (!Q) {
+      const T* col = a.coeff + gy * a.cs[1] + gx * a.cs[2];
 #pragma unroll
-    for (int z = 0; z < B; ++z)
-      if ((z & 1) || !ecol) w[z] = col[(oz + z) * a.cs[0]];
+      for (int z = 0; z < B; ++z)
+        if ((z & 1) || !ecol) w[z] = col[(oz + z) * a.cs[0]];
+    } else {
+      // fused dequantization: c_hat = (T)(q * Delta); codes and tables load together
+      const int32_t* col = a.codes + gy * a.cs[1] + gx * a.cs[2];
+      int32_t qv[B];
+#pragma unroll
+      for (int z = 0; z < B; ++z) qv[z] = ((z & 1) || !ecol) ? col[(oz + z) * a.cs[0]] : 0;
+      double dd[3];
+      column_tables<B, false>(a.tab, bz, by, bx, y, x, dd);
+#pragma unroll
+      for (int z = 0; z < B; ++z)
+        if ((z & 1) || !ecol) w[z] = T(mul_rn(double(qv[z]), dd[zcase<B>(z)]));
+    }
     if (ecol) {
-      const T* ccol = a.cin + (gy >> 1) * a.cn[2] + (gx >> 1);
+      if (Q && a.coarsest_here) {
+        const int32_t* col = a.codes + gy * a.cs[1] + gx * a.cs[2];
+        int32_t qc[MC];
 #pragma unroll
-      for (int j = 0; j < MC; ++j) {
-        ce[j] = ccol[((oz >> 1) + j) * a.cn[1] * a.cn[2]];
-        w[2 * j] = T(0);
+        for (int j = 0; j < MC; ++j) qc[j] = col[(oz + 2 * j) * a.cs[0]];
+        double cd[3];
+        column_tables<B, false>(a.ctab, bz, by, bx, y, x, cd);
+#pragma unroll
+        for (int j = 0; j < MC; ++j) ce[j] = T(mul_rn(double(qc[j]), cd[zcase<B>(2 * j)]));
+      } else {
+        const T* ccol = a.cin + (gy >> 1) * a.cn[2] + (gx >> 1);
+#pragma unroll
+        for (int j = 0; j < MC; ++j) ce[j] = ccol[((oz >> 1) + j) * a.cn[1] * a.cn[2]];
       }
+#pragma unroll
+      for (int j = 0; j < MC; ++j) w[2 * j] = T(0);
     }
     T o[MI];
     restrict_solve<T, B>(w, o);
@@ -321,8 +418,8 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
 }
 
 template <typename T, int B>
-void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout,
-                hipStream_t st) {
+void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                const QPrep* q, hipStream_t st) {
   using G = Geo<B>;
   const Level& L = p.lv[s - 1];
   DecArgs<T> a{};
@@ -336,24 +433,33 @@ void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* c
   a.first = first;
   a.zero_pad = p.cfg.pad_mode == 1;
   a.coeff = static_cast<T*>(coeff);
-  const View3 cv = level_view(p, s, coeff);
+  const View3 cv = level_view(p, s, q ? static_cast<void*>(codes) : coeff);
   for (int k = 0; k < 3; ++k) a.cs[k] = cv.s[k];
   a.cout = static_cast<T*>(cout);
   a.nblocks = L.nb[0] * L.nb[1] * L.nb[2];
   a.nwg = (a.nblocks + G::NB - 1) / G::NB;
   a.per = (a.nwg + 7) / 8;
-  hipLaunchKernelGGL((k_local_decompose<T, B>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  if (q) {
+    a.codes = codes;
+    a.tab = q->lv[s - 1];
+    a.coarsest_here = (p.M == 0 && s == p.L) ? 1 : 0;
+    if (a.coarsest_here) a.ctab = q->lv[kCoarseSlotHost];
+    a.flag = q->flag;
+    hipLaunchKernelGGL((k_local_decompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_local_decompose<T, B, false>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  }
   BM_HIP(hipGetLastError());
 }
 
 template <typename T, int B>
 void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
-                hipStream_t st) {
+                const int32_t* codes, const QPrep* q, hipStream_t st) {
   using G = Geo<B>;
   const Level& L = p.lv[s - 1];
   RecArgs<T> a{};
   a.coeff = static_cast<const T*>(coeff);
-  const View3 cv = level_view(p, s, const_cast<void*>(coeff));
+  const View3 cv = level_view(p, s, q ? const_cast<int32_t*>(codes) : const_cast<void*>(coeff));
   for (int k = 0; k < 3; ++k) {
     a.cs[k] = cv.s[k];
     a.cn[k] = L.m[k];
@@ -370,34 +476,68 @@ void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, v
   a.nblocks = L.nb[0] * L.nb[1] * L.nb[2];
   a.nwg = (a.nblocks + G::NB - 1) / G::NB;
   a.per = (a.nwg + 7) / 8;
-  hipLaunchKernelGGL((k_local_recompose<T, B>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  if (q) {
+    a.codes = codes;
+    a.tab = q->lv[s - 1];
+    a.coarsest_here = (p.M == 0 && s == p.L) ? 1 : 0;
+    if (a.coarsest_here) a.ctab = q->lv[kCoarseSlotHost];
+    hipLaunchKernelGGL((k_local_recompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_local_recompose<T, B, false>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  }
   BM_HIP(hipGetLastError());
+}
+
+template <int B>
+void dispatch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                  const QPrep* q, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32)
+    launch_dec<float, B>(p, s, src, first, coeff, cout, codes, q, st);
+  else
+    launch_dec<double, B>(p, s, src, first, coeff, cout, codes, q, st);
+}
+
+template <int B>
+void dispatch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
+                  const int32_t* codes, const QPrep* q, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32)
+    launch_rec<float, B>(p, s, coeff, cin, out, last, codes, q, st);
+  else
+    launch_rec<double, B>(p, s, coeff, cin, out, last, codes, q, st);
 }
 
 }  // namespace
 
 void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* coarse_out,
                      hipStream_t st) {
-  const int b = p.cfg.block;
-  if (p.cfg.dtype == BM_F32) {
-    if (b == 9) launch_dec<float, 9>(p, s, src, first, coeff, coarse_out, st);
-    else launch_dec<float, 17>(p, s, src, first, coeff, coarse_out, st);
-  } else {
-    if (b == 9) launch_dec<double, 9>(p, s, src, first, coeff, coarse_out, st);
-    else launch_dec<double, 17>(p, s, src, first, coeff, coarse_out, st);
-  }
+  if (p.cfg.block == 9)
+    dispatch_dec<9>(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
+  else
+    dispatch_dec<17>(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
 }
 
 void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* coarse_in, void* out, bool last,
                      hipStream_t st) {
-  const int b = p.cfg.block;
-  if (p.cfg.dtype == BM_F32) {
-    if (b == 9) launch_rec<float, 9>(p, s, coeff, coarse_in, out, last, st);
-    else launch_rec<float, 17>(p, s, coeff, coarse_in, out, last, st);
-  } else {
-    if (b == 9) launch_rec<double, 9>(p, s, coeff, coarse_in, out, last, st);
-    else launch_rec<double, 17>(p, s, coeff, coarse_in, out, last, st);
-  }
+  if (p.cfg.block == 9)
+    dispatch_rec<9>(p, s, coeff, coarse_in, out, last, nullptr, nullptr, st);
+  else
+    dispatch_rec<17>(p, s, coeff, coarse_in, out, last, nullptr, nullptr, st);
+}
+
+void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, int32_t* codes, void* coarse_out,
+                       const QPrep& q, hipStream_t st) {
+  if (p.cfg.block == 9)
+    dispatch_dec<9>(p, s, src, first, nullptr, coarse_out, codes, &q, st);
+  else
+    dispatch_dec<17>(p, s, src, first, nullptr, coarse_out, codes, &q, st);
+}
+
+void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const void* coarse_in, void* out, bool last,
+                       const QPrep& q, hipStream_t st) {
+  if (p.cfg.block == 9)
+    dispatch_rec<9>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
+  else
+    dispatch_rec<17>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
 }
 
 }  // namespace bm

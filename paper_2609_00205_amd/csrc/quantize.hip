@@ -7,10 +7,12 @@
 // blocks that share a node with it.  Global levels use tau_global, the
 // minimum over the last local level.
 //
-// Budget (the L-infinity bound of Sec. II-B, with T = L + M + 1 shares):
+// Budget (the L-infinity bound of Sec. II-B): level s gets the share w_s of
+// every tolerance (proportional to its coefficient count, equal among the
+// global levels, floored at 1/(64 T) and renormalised; see level_weights);
 // a detail of level s on a node with tolerance tau gets bin width
-// Delta = tau * kappa_s, kappa_s = 2 (1 - eta) / (T A_s), where A_s is the
-// level's L-infinity gain; the coarsest values get kappa = 2 (1 - eta) / T.
+// Delta = tau * kappa_s, kappa_s = 2 (1 - eta) w_s / A_s, where A_s is the
+// level's L-infinity gain; the coarsest values get kappa = 2 (1 - eta) w_c.
 // q = rint(c * (1/Delta)) in FP64 (the per-block reciprocal quantizer of
 // Sec. IV-D), c_hat = q * Delta.  A node inside several blocks of its level
 // uses the smallest Delta (largest reciprocal) of those blocks; because
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* c
     for (int k = 0; k < QU; ++k) {
       const uint32_t i = base + k * NT;
       if (i >= a.tot) continue;
-      const double v = rint(cv[k] * inv[k]);
+      const double v = rint(mul_rn(cv[k], inv[k]));
       int32_t qv;
       if (!(fabs(v) <= 2147483647.0)) {
         bad = 1;
@@ -381,30 +383,20 @@ __global__ __launch_bounds__(NT) void k_dequantize(QArgs a, const int32_t* codes
 #pragma unroll
     for (int k = 0; k < QU; ++k) {
       const uint32_t i = base + k * NT;
-      if (i < a.tot) c[i] = T(q[k] * del[k]);
+      if (i < a.tot) c[i] = T(mul_rn(q[k], del[k]));
     }
   }
 }
 
 int64_t prod3(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 
+}  // namespace
+
 // Build every per-level quantizer table on the device from the level-1 map.
-QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   if (p.L > 8) fail(BM_EUNSUPPORTED, "more than 8 local levels");
-  QArgs a{};
-  const int64_t npad = prod3(p.pdims);
-  if (npad >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "quantizer: padded grid of 2^32 nodes or more");
-  a.tot = uint32_t(npad);
-  a.uf = Unflat32(p.pdims[1], p.pdims[2]);
-  for (int d = 0; d < 3; ++d) {
-    int D = 0;
-    for (auto& L : p.lv) D += L.coarsen[d] ? 1 : 0;
-    a.D[d] = D;
-  }
-  a.L = p.L;
-  a.M = p.M;
-  a.lw = p.L > 0 ? (p.cfg.block == 17 ? 4 : 3) : 0;
-  a.counters = p.ws.counters;
+  QPrep a{};
+  a.flag = p.ws.counters + 2;
   const double eta = p.cfg.eta;
   const std::vector<double> w = level_weights(p);
   const int64_t tot = p.ws.tol_off[p.L + 1];
@@ -429,9 +421,9 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       const int64_t off = p.ws.tol_off[s];
       hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, taus(s), nbs, kap, bdel + off,
                          binv + off);
-      a.bdelta[s - 1] = bdel + off;
-      a.binv[s - 1] = binv + off;
-      for (int d = 0; d < 3; ++d) a.nb[s - 1][d] = uint32_t(p.lv[s - 1].nb[d]);
+      a.lv[s - 1].del = bdel + off;
+      a.lv[s - 1].inv = binv + off;
+      for (int d = 0; d < 3; ++d) a.lv[s - 1].nb[d] = p.lv[s - 1].nb[d];
     }
     const int64_t nlast = prod3(p.lv[p.L - 1].nb);
     if (p.M == 0) {
@@ -440,9 +432,9 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       double* cinv = cdel + nlast;
       const double kc = (2.0 * (1.0 - eta)) * w[p.nlev];
       hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, kc, cdel, cinv);
-      a.bdelta[kCoarseSlot] = cdel;
-      a.binv[kCoarseSlot] = cinv;
-      for (int d = 0; d < 3; ++d) a.nb[kCoarseSlot][d] = uint32_t(p.lv[p.L - 1].nb[d]);
+      a.lv[kCoarseSlotHost].del = cdel;
+      a.lv[kCoarseSlotHost].inv = cinv;
+      for (int d = 0; d < 3; ++d) a.lv[kCoarseSlotHost].nb[d] = p.lv[p.L - 1].nb[d];
     }
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
     hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, tg);
@@ -459,6 +451,33 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar_delta, dim3(1), dim3(64), 0, st, sa);
   BM_HIP(hipGetLastError());
   a.q = p.ws.qparam;
+  return a;
+}
+
+namespace {
+
+QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+  const QPrep qp = quant_prepare(p, block_tol, st);
+  QArgs a{};
+  const int64_t npad = prod3(p.pdims);
+  if (npad >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "quantizer: padded grid of 2^32 nodes or more");
+  a.tot = uint32_t(npad);
+  a.uf = Unflat32(p.pdims[1], p.pdims[2]);
+  for (int d = 0; d < 3; ++d) {
+    int D = 0;
+    for (auto& L : p.lv) D += L.coarsen[d] ? 1 : 0;
+    a.D[d] = D;
+  }
+  a.L = p.L;
+  a.M = p.M;
+  a.lw = p.L > 0 ? (p.cfg.block == 17 ? 4 : 3) : 0;
+  a.counters = p.ws.counters;
+  for (int k = 0; k < 9; ++k) {
+    a.bdelta[k] = qp.lv[k].del;
+    a.binv[k] = qp.lv[k].inv;
+    for (int d = 0; d < 3; ++d) a.nb[k][d] = uint32_t(qp.lv[k].nb[d]);
+  }
+  a.q = qp.q;
   return a;
 }
 

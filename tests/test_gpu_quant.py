@@ -121,6 +121,24 @@ def test_end_to_end_bound_holds(shape, b, L, M, dt):
     assert np.all(diff <= slack)
 
 
+@pytest.mark.parametrize("shape,b,L,M", CASES)
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_fused_equals_unfused(shape, b, L, M, dt):
+    # decompose_quantize == quantize(decompose(.)), dequantize_recompose == recompose(dequantize(.)), bit for bit
+    p = _plan(shape, b, L, M, dt)
+    x = synth.gaussian_random_field(shape, 3.0, seed=24, dtype=np.float64)
+    scale = np.abs(x).max()
+    boxes = [bx[:6] + (bx[6] * 100 * scale,) for bx in _boxes(shape, 7)]
+    xd = torch.from_numpy(x).to(dt).cuda()
+    bt = p.tolmap_from_boxes(boxes, 1e-2 * scale)
+    codes_u, _ = p.quantize(p.decompose(xd), bt)
+    codes_f = p.decompose_quantize(xd, bt)
+    assert torch.equal(codes_u, codes_f), int((codes_u != codes_f).sum())
+    xr_u = p.recompose(p.dequantize(codes_u, bt))
+    xr_f = p.dequantize_recompose(codes_f, bt)
+    assert torch.equal(xr_u, xr_f)
+
+
 def _laplace_codes(n, seed, scale=4.0):
     rng = np.random.default_rng(seed)
     q = np.rint(rng.laplace(0, scale, n)).astype(np.int64)
