@@ -169,13 +169,11 @@ __device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
 
 // q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag
 template <typename T>
-__device__ inline int32_t quant(T c, double inv, int64_t* flag) {
+__device__ inline int32_t quant(T c, double inv, bool& bad) {
   const double v = rint(mul_rn(double(c), inv));
-  if (!(fabs(v) <= 2147483647.0)) {
-    atomicOr(reinterpret_cast<unsigned long long*>(flag), 1ull);
-    return 0;
-  }
-  return int32_t(v);
+  const bool ok = fabs(v) <= 2147483647.0;
+  bad |= !ok;
+  return ok ? int32_t(v) : 0;
 }
 
 template <typename T, int B, bool Q>
@@ -288,15 +286,17 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
         // fused quantization: codes for the details of this level (and for
         // the coarsest values when this is the last level of the hierarchy)
         int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
+        bool bad = false;
 #pragma unroll
         for (int z = 0; z < B; ++z) {
           if (z == B - 1 && !lastz) continue;
           const bool coarse = ecol && (z & 1) == 0;
           if (!coarse)
-            dst[(oz + z) * a.cs[0]] = quant(w[z], iv[zcase<B>(z)], a.flag);
+            dst[(oz + z) * a.cs[0]] = quant(w[z], iv[zcase<B>(z)], bad);
           else if (a.coarsest_here)
-            dst[(oz + z) * a.cs[0]] = quant(w[z], ci[zcase<B>(z)], a.flag);
+            dst[(oz + z) * a.cs[0]] = quant(w[z], ci[zcase<B>(z)], bad);
         }
+        if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
       }
       if (ecol && !(Q && a.coarsest_here)) {
         T* cdst = a.cout + (gy >> 1) * a.cn[2] + (gx >> 1);
