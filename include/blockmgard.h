@@ -126,11 +126,20 @@ bm_status bm_decompose(bm_plan plan, const void* x, void* coeff, hipStream_t str
 /* x = R(coeff) = D^{-1}(coeff), cropped to the logical dims.  Asynchronous. */
 bm_status bm_recompose(bm_plan plan, const void* coeff, void* x, hipStream_t stream);
 
-/* gx = D^T(gcoeff): gradient of <D(x), gcoeff> with respect to x.  gcoeff has
- * padded dims, gx logical dims.  Asynchronous. */
+/* gx = D^T(gcoeff): gradient of <D(x), gcoeff> with respect to x, the
+ * transpose of the linear map of bm_decompose (the levels of Sec. II-B and
+ * the block levels of Sec. IV-A, applied in reverse order).  gcoeff: device,
+ * padded dims, in-place layout as bm_decompose writes it; gx: device, logical
+ * dims, dtype of the plan (overwritten).  Padded nodes' gradients are added
+ * into the nodes their clamped value came from (dropped under zero fill).
+ * Uses the plan's grid buffers (and, on a padded grid with block levels, one
+ * padded-size buffer allocated on first use).  Asynchronous on stream. */
 bm_status bm_decompose_adjoint(bm_plan plan, const void* gcoeff, void* gx, hipStream_t stream);
 
-/* gcoeff = R^T(gx).  gx logical dims, gcoeff padded dims.  Asynchronous. */
+/* gcoeff = R^T(gx): gradient of <R(coeff), gx> with respect to coeff, e.g. the
+ * sensitivities of a linear quantity of interest of the reconstruction.
+ * gx: device, logical dims; gcoeff: device, padded dims, in-place layout
+ * (overwritten).  Asynchronous on stream. */
 bm_status bm_recompose_adjoint(bm_plan plan, const void* gx, void* gcoeff, hipStream_t stream);
 
 /* ---- ROI tolerance maps (Sec. IV-C) ------------------------------------- */

@@ -5,10 +5,14 @@ behind the C ABI in ``include/blockmgard.h``); this package only marshals
 arguments.  Importing it does not load the library; the first call does,
 and raises if the library has not been built.
 """
-__all__ = ["Plan", "decompress", "compressed_config", "huffman_encode", "huffman_decode"]
+__all__ = ["Plan", "decompress", "compressed_config", "huffman_encode", "huffman_decode",
+           "DecomposeFn", "RecomposeFn"]
 
 
 def __getattr__(name):
+    if name in ("DecomposeFn", "RecomposeFn"):
+        from . import autograd
+        return getattr(autograd, name)
     if name in __all__:
         from . import api
         return getattr(api, name)

@@ -170,14 +170,16 @@ bm_status bm_recompose(bm_plan p, const void* coeff, void* x, hipStream_t st) {
 bm_status bm_decompose_adjoint(bm_plan p, const void* gcoeff, void* gx, hipStream_t st) {
   return guarded([&] {
     need(p && gcoeff && gx, "null argument");
-    bm::fail(BM_EUNSUPPORTED, "adjoint not built yet");
+    check_device(p);
+    bm::decompose_adjoint(*p, gcoeff, gx, st);
   });
 }
 
 bm_status bm_recompose_adjoint(bm_plan p, const void* gx, void* gcoeff, hipStream_t st) {
   return guarded([&] {
     need(p && gcoeff && gx, "null argument");
-    bm::fail(BM_EUNSUPPORTED, "adjoint not built yet");
+    check_device(p);
+    bm::recompose_adjoint(*p, gx, gcoeff, st);
   });
 }
 

@@ -17,12 +17,12 @@
 // by a lane-local pass and a 64-lane scan of affine maps with wave shuffles.
 
 #include "internal.h"
+#include "line_solve.h"
 
 namespace bm {
 namespace {
 
 constexpr int NT = 256;
-constexpr int QMAX = 9;     // coarse values per lane: lines up to 64 * 9 coarse nodes
 
 // ------------------------------------------------------------- elementwise
 
@@ -205,33 +205,6 @@ struct PassArgs {
   int pa, qa;            // the two other axes (q fastest)
 };
 
-// Affine map x -> A x + B; compose(prev then cur).
-template <typename T>
-__device__ inline void scan_up(T& A, T& B, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T Ap = __shfl_up(A, off, 64);
-    const T Bp = __shfl_up(B, off, 64);
-    if (lane >= off) {
-      B = A * Bp + B;
-      A = A * Ap;
-    }
-  }
-}
-
-template <typename T>
-__device__ inline void scan_down(T& A, T& B, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T An = __shfl_down(A, off, 64);
-    const T Bn = __shfl_down(B, off, 64);
-    if (lane + off < 64) {
-      B = A * Bn + B;
-      A = A * An;
-    }
-  }
-}
-
 template <typename T>
 __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   extern __shared__ unsigned char smem[];
@@ -270,67 +243,23 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t m = a.m, nl = a.nl;
-  const int q = int((m + 63) / 64);
-  const int64_t J0 = int64_t(lane) * q;
   for (int w = wave; w < wv; w += NT / 64) {
     const T* col = tin + w;
-    T f[QMAX], al[QMAX];
-    T A = T(1), B = T(0);
-#pragma unroll
-    for (int j = 0; j < QMAX; ++j) {
-      const int64_t J = J0 + j;
-      if (j < q && J < m) {
-        const int64_t c = 2 * J;
-        T r;
-        if (J == 0) {
-          r = T(5.0 / 12.0) * col[0] + T(0.5) * col[WP] + T(1.0 / 12.0) * col[2 * WP];
-        } else if (J == m - 1) {
-          r = T(1.0 / 12.0) * col[(nl - 3) * WP] + T(0.5) * col[(nl - 2) * WP] + T(5.0 / 12.0) * col[(nl - 1) * WP];
-        } else {
-          r = T(1.0 / 12.0) * (col[(c - 2) * WP] + col[(c + 2) * WP]) + T(0.5) * (col[(c - 1) * WP] + col[(c + 1) * WP]) +
-              T(5.0 / 6.0) * col[c * WP];
-        }
-        const T iv = T(a.inv[J]);
-        al[j] = J == 0 ? T(0) : -iv;
-        f[j] = T(3) * r * iv;
-        A = al[j] * A;
-        B = al[j] * B + f[j];
+    // right-hand side 3 (P^T M u)_J: 5-point interior rows, 3-point end rows
+    auto rhs = [&](int64_t J) {
+      const int64_t c = 2 * J;
+      T r;
+      if (J == 0) {
+        r = T(5.0 / 12.0) * col[0] + T(0.5) * col[WP] + T(1.0 / 12.0) * col[2 * WP];
+      } else if (J == m - 1) {
+        r = T(1.0 / 12.0) * col[(nl - 3) * WP] + T(0.5) * col[(nl - 2) * WP] + T(5.0 / 12.0) * col[(nl - 1) * WP];
+      } else {
+        r = T(1.0 / 12.0) * (col[(c - 2) * WP] + col[(c + 2) * WP]) + T(0.5) * (col[(c - 1) * WP] + col[(c + 1) * WP]) +
+            T(5.0 / 6.0) * col[c * WP];
       }
-    }
-    // forward sweep: d_J = al_J d_{J-1} + f_J
-    scan_up(A, B, lane);
-    T din = __shfl_up(B, 1, 64);
-    if (lane == 0) din = T(0);
-#pragma unroll
-    for (int j = 0; j < QMAX; ++j) {
-      if (j < q && J0 + j < m) {
-        din = al[j] * din + f[j];
-        f[j] = din;                 // f now holds d_J
-      }
-    }
-    // backward sweep: x_J = g_J x_{J+1} + d_J, g_J = -inv_J (J < m-1), g_{m-1} = 0
-    A = T(1);
-    B = T(0);
-#pragma unroll
-    for (int j = QMAX - 1; j >= 0; --j) {
-      const int64_t J = J0 + j;
-      if (j < q && J < m) {
-        al[j] = J == m - 1 ? T(0) : -T(a.inv[J]);
-        A = al[j] * A;
-        B = al[j] * B + f[j];
-      }
-    }
-    scan_down(A, B, lane);
-    T xin = __shfl_down(B, 1, 64);
-    if (lane == 63) xin = T(0);
-#pragma unroll
-    for (int j = QMAX - 1; j >= 0; --j) {
-      const int64_t J = J0 + j;
-      if (j < q && J < m) {
-        xin = al[j] * xin + f[j];
-        tout[J * WP + w] = xin;
-      }
-    }
+      return T(3) * r;
+    };
+    wave_thomas<T>(m, a.inv, lane, rhs, [&](int64_t J, T x) { tout[J * WP + w] = x; });
   }
   __syncthreads();
   const int64_t totm = m * wv;
@@ -371,7 +300,7 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.nl = in.n[axis];
   a.m = L.m[axis];
   a.on[axis] = a.m;
-  if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * QMAX) fail(BM_EUNSUPPORTED, "line length not supported");
+  if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * kLineQ) fail(BM_EUNSUPPORTED, "line length not supported");
   a.out = static_cast<T*>(out);
   a.base = static_cast<const T*>(base);
   a.inv = L.d_inv[axis];
@@ -504,15 +433,15 @@ void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t 
   BM_HIP(hipGetLastError());
 }
 
-static void pad_input(const bm_plan_s& p, const void* x, void* dst, hipStream_t st) {
+void pad_input(const bm_plan_s& p, const void* x, void* dst, bool zero, hipStream_t st) {
   const int64_t tot = p.pdims[0] * p.pdims[1] * p.pdims[2];
   if (p.cfg.dtype == BM_F32) {
     PadArgs<float> a{static_cast<const float*>(x), {p.dims[0], p.dims[1], p.dims[2]}, static_cast<float*>(dst),
-                     {p.pdims[0], p.pdims[1], p.pdims[2]}, p.cfg.pad_mode == 1};
+                     {p.pdims[0], p.pdims[1], p.pdims[2]}, zero};
     hipLaunchKernelGGL(k_pad<float>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
   } else {
     PadArgs<double> a{static_cast<const double*>(x), {p.dims[0], p.dims[1], p.dims[2]}, static_cast<double*>(dst),
-                      {p.pdims[0], p.pdims[1], p.pdims[2]}, p.cfg.pad_mode == 1};
+                      {p.pdims[0], p.pdims[1], p.pdims[2]}, zero};
     hipLaunchKernelGGL(k_pad<double>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
   }
   BM_HIP(hipGetLastError());
@@ -554,7 +483,7 @@ void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
     } else {
       const void* u;
       if (s == 1) {
-        pad_input(p, x, p.ws.grid[0], st);
+        pad_input(p, x, p.ws.grid[0], p.cfg.pad_mode == 1, st);
         u = p.ws.grid[0];
       } else {
         u = p.ws.grid[s - 1];
@@ -610,7 +539,7 @@ void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, in
     } else {
       const void* u;
       if (s == 1) {
-        pad_input(p, x, p.ws.grid[0], st);
+        pad_input(p, x, p.ws.grid[0], p.cfg.pad_mode == 1, st);
         u = p.ws.grid[0];
       } else {
         u = p.ws.grid[s - 1];

@@ -106,6 +106,7 @@ struct Workspace {
   int64_t* counters = nullptr;   // device scratch counters (stats)
   double* boxbuf = nullptr;      // device copy of an ROI box list (kMaxBoxes x 7)
   double* boxhost = nullptr;     // pinned staging for the box list
+  void* gpad = nullptr;          // dtype, padded grid: level-1 gradient before the pad transpose
 };
 
 }  // namespace bm
@@ -160,10 +161,15 @@ void global_interp_add(const bm_plan_s& p, int s, const void* coeff, const void*
 void line_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
                const void* base, hipStream_t st);
 void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t st);
+// logical input -> padded grid (clamp, or zero fill when zero is set)
+void pad_input(const bm_plan_s& p, const void* x, void* dst, bool zero, hipStream_t st);
 
 // decompose / recompose drivers
 void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st);
 void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st);
+// transposes: gx = D^T gcoeff, gcoeff = R^T gx
+void decompose_adjoint(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t st);
+void recompose_adjoint(bm_plan_s& p, const void* gx, void* gcoeff, hipStream_t st);
 
 // quantization tables on the device, built from a level-1 block map:
 // per local level s (slot s-1) the per-block Delta and 1/Delta; slot 8 for

@@ -19,41 +19,11 @@
 // coarse nodes is tridiag(1, 4, 1).  Small blocks are packed several to a
 // workgroup so wavefronts stay full.
 
+#include "block.h"
 #include "internal.h"
 
 namespace bm {
 namespace {
-
-template <int B>
-struct Geo {
-  static constexpr int BB = B * B;
-  static constexpr int MC = (B + 1) / 2;        // coarse nodes per axis
-  static constexpr int MI = MC - 2;             // interior coarse nodes per axis
-  static constexpr int NB = B <= 9 ? 3 : 1;     // blocks per workgroup
-  static constexpr int NT = ((NB * BB + 63) / 64) * 64;
-  // LDS per block: decompose UE[MC][B][B] + T1[MI][B][B] (T2 aliases UE, Z aliases T1)
-  static constexpr int DEC_LDS = MC * BB + MI * BB;
-  // recompose: UC[MC][MC][MC] + T1[MI][B][B] + T2[MI][MI][B] (Z aliases T1)
-  static constexpr int REC_LDS = MC * MC * MC + MI * BB + MI * MI * B;
-};
-
-// Reciprocal pivots of Thomas elimination for tridiag(1, 4, 1) of size MI.
-template <int MI>
-struct Pivots {
-  double v[MI];
-  constexpr Pivots() : v() {
-    double c = 0.0;
-    for (int i = 0; i < MI; ++i) {
-      v[i] = 1.0 / (4.0 - c);
-      c = v[i];
-    }
-  }
-};
-
-// XCD-aware order: hardware workgroup ids go round-robin over the 8 XCDs;
-// this map gives each XCD a contiguous run of workgroups so shared faces are
-// re-read from the same L2.
-__device__ inline int64_t xcd_group(int64_t wg, int64_t per) { return (wg & 7) * per + (wg >> 3); }
 
 // Restriction by the interior rows of P^T M (centre 2J+2) followed by the
 // interior tridiagonal solve, on a line of B values: out[J], J < MI.
