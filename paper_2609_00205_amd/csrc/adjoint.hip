@@ -414,7 +414,7 @@ struct PassTArgs {
   int cm[3];
   const double* inv;      // reciprocal Thomas pivots of 3 Mc (natural ends), length m
   int64_t nl, m;
-  int W;                  // lines per tile
+  int W, lw;              // lines per tile (a power of two) and its log2
   int64_t nq, ntq;        // extent of the fastest other axis, tiles along it
   int pa, qa;             // the two other axes (q fastest)
 };
@@ -424,44 +424,37 @@ __global__ __launch_bounds__(NT) void k_line_pass_T(PassTArgs<T> a) {
   extern __shared__ unsigned char smem[];
   T* tin = reinterpret_cast<T*>(smem);               // [m][W+1]
   const int WP = a.W + 1;
-  const int64_t tile = blockIdx.x;
-  const int64_t p = tile / a.ntq;
-  const int64_t q0 = (tile - p * a.ntq) * a.W;
+  T* piv = tin + int(a.m) * WP;                      // [m] reciprocal pivots
+  const uint32_t tile = blockIdx.x;
+  const uint32_t p = tile / uint32_t(a.ntq);
+  const int64_t q0 = int64_t(tile - p * uint32_t(a.ntq)) * a.W;
   const int wv = int(i64min(a.W, a.nq - q0));
   const int tid = threadIdx.x;
-  const int64_t m = a.m, nl = a.nl;
-  for (int64_t k = tid; k < m * wv; k += NT) {
-    int64_t J, w;
-    if (a.axis == 2) {
-      w = k / m;
-      J = k - w * m;
-    } else {
-      J = k / wv;
-      w = k - J * wv;
-    }
-    tin[J * WP + w] = a.in[p * a.is[a.pa] + (q0 + w) * a.is[a.qa] + J * a.is[a.axis]];
-  }
-  __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
-  for (int w = wave; w < wv; w += NT / 64) {
-    T* col = tin + w;
-    wave_thomas<T>(m, a.inv, lane, [&](int64_t J) { return T(3) * col[J * WP]; },
-                   [&](int64_t J, T x) { col[J * WP] = x; });
+  const int m = int(a.m), nl = int(a.nl);
+  const int64_t ibase = int64_t(p) * a.is[a.pa] + q0 * a.is[a.qa];
+  for (int J = tid; J < m; J += NT) piv[J] = T(a.inv[J]);
+  auto load = [&](int J, int w) { tin[J * WP + w] = a.in[ibase + w * a.is[a.qa] + J * a.is[a.axis]]; };
+  if (a.axis == 2) {
+    for (int w = wave; w < wv; w += NT / 64)
+      for (int J = lane; J < m; J += 64) load(J, w);
+  } else {
+    const int w = tid & (a.W - 1);
+    if (w < wv)
+      for (int J = tid >> a.lw; J < m; J += NT >> a.lw) load(J, w);
   }
   __syncthreads();
-  for (int64_t k = tid; k < nl * wv; k += NT) {
-    int64_t i, w;
-    if (a.axis == 2) {
-      w = k / nl;
-      i = k - w * nl;
-    } else {
-      i = k / wv;
-      w = k - i * wv;
-    }
+  // in place: each lane reads, and later overwrites, only its own rows
+  solve_lines<T, NT>(m, piv, wv, tid, [&](int w, int J) { return T(3) * tin[J * WP + w]; },
+                     [&](int w, int J, T x) { tin[J * WP + w] = x; });
+  __syncthreads();
+  const bool pe = !(a.cm[a.pa] && (p & 1));
+  const int cmA = a.cm[a.axis], cmQ = a.cm[a.qa];
+  auto store = [&](int i, int w) {
     // transposed rows of P^T M: row J has 5/6 (5/12 at the two ends) at
     // node 2J, 1/2 at 2J +- 1 and 1/12 at 2J +- 2
     const T* col = tin + w;
-    const int64_t h = i >> 1;
+    const int h = i >> 1;
     T v;
     if (i & 1) {
       v = T(0.5) * (col[h * WP] + col[(h + 1) * WP]);
@@ -476,9 +469,17 @@ __global__ __launch_bounds__(NT) void k_line_pass_T(PassTArgs<T> a) {
     c[a.axis] = i;
     c[a.pa] = p;
     c[a.qa] = q0 + w;
-    if (a.mask && !((a.cm[0] && (c[0] & 1)) || (a.cm[1] && (c[1] & 1)) || (a.cm[2] && (c[2] & 1)))) v = T(0);
+    if (a.mask && pe && !(cmA && (i & 1)) && !(cmQ && ((q0 + w) & 1))) v = T(0);
     else if (a.base) v = a.base[c[0] * a.bs[0] + c[1] * a.bs[1] + c[2] * a.bs[2]] + a.sgn * v;
     a.out[c[0] * a.os[0] + c[1] * a.os[1] + c[2] * a.os[2]] = v;
+  };
+  if (a.axis == 2) {
+    for (int w = wave; w < wv; w += NT / 64)
+      for (int i = lane; i < nl; i += 64) store(i, w);
+  } else {
+    const int w = tid & (a.W - 1);
+    if (w < wv)
+      for (int i = tid >> a.lw; i < nl; i += NT >> a.lw) store(i, w);
   }
 }
 
@@ -506,13 +507,14 @@ void launch_pass_T(const bm_plan_s& p, int s, int axis, const View3& in, const V
   a.pa = axis == 0 ? 1 : 0;
   a.qa = axis == 2 ? 1 : 2;
   a.nq = out.n[a.qa];
-  const int64_t per_line = a.m * int64_t(sizeof(T));
-  int W = int(std::min<int64_t>(64, std::max<int64_t>(1, 32768 / per_line - 1)));
-  W = int(std::min<int64_t>(W, a.nq));
-  a.W = W;
-  a.ntq = (a.nq + W - 1) / W;
-  const int64_t tiles = out.n[a.pa] * a.ntq;
-  const size_t shm = size_t(a.m) * (W + 1) * sizeof(T);
+  const int64_t np = out.n[a.pa];
+  a.W = tile_width(a.m + 1, sizeof(T), np, a.nq);
+  a.lw = 0;
+  while ((1 << a.lw) < a.W) ++a.lw;
+  a.ntq = (a.nq + a.W - 1) / a.W;
+  const int64_t tiles = np * a.ntq;
+  if (tiles >= (int64_t(1) << 31)) fail(BM_EUNSUPPORTED, "too many lines");
+  const size_t shm = (size_t(a.m) * (a.W + 1) + size_t(a.m)) * sizeof(T);
   hipLaunchKernelGGL(k_line_pass_T<T>, dim3(unsigned(tiles)), dim3(NT), shm, st, a);
   BM_HIP(hipGetLastError());
 }
@@ -533,15 +535,16 @@ struct RestrArgs {
   T* out;
   int64_t os[3];
   int64_t m[3];
+  Unflat32 uf;            // over dims m
 };
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_restrict_T(RestrArgs<T> a) {
   const int64_t tot = a.m[0] * a.m[1] * a.m[2];
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    const int64_t cx = i % a.m[2];
-    const int64_t t = i / a.m[2];
-    const int64_t cy = t % a.m[1], cz = t / a.m[1];
+    uint32_t uz, uy, ux;
+    a.uf(uint32_t(i), uz, uy, ux);
+    const int64_t cz = uz, cy = uy, cx = ux;
     const int64_t fz = a.cm[0] ? 2 * cz : cz, fy = a.cm[1] ? 2 * cy : cy, fx = a.cm[2] ? 2 * cx : cx;
     T acc = T(0);
     for (int dz = -a.cm[0]; dz <= a.cm[0]; ++dz) {
@@ -577,6 +580,8 @@ void launch_restrict_T(const Level& L, const void* src, bool self, const void* c
     a.os[k] = out.s[k];
     a.m[k] = L.m[k];
   }
+  if (a.m[0] * a.m[1] * a.m[2] >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "coarse grid too large");
+  a.uf = Unflat32(a.m[1], a.m[2]);
   hipLaunchKernelGGL(k_restrict_T<T>, dim3(grid_for(a.m[0] * a.m[1] * a.m[2])), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
@@ -636,12 +641,12 @@ void global_rec_T(bm_plan_s& p, int s, const void* gin, void* gcoeff, hipStream_
 // nodes that read each logical node (clamp), or the crop (zero fill)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_unpad_T(const T* gp, int64_t p0, int64_t p1, int64_t p2, T* gx, int64_t n0,
-                                                int64_t n1, int64_t n2, int zero) {
+                                                int64_t n1, int64_t n2, Unflat32 uf, int zero) {
   const int64_t tot = n0 * n1 * n2;
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    const int64_t x = i % n2;
-    const int64_t t = i / n2;
-    const int64_t y = t % n1, z = t / n1;
+    uint32_t uz, uy, ux;
+    uf(uint32_t(i), uz, uy, ux);
+    const int64_t z = uz, y = uy, x = ux;
     const int64_t ze = (!zero && z == n0 - 1) ? p0 : z + 1;
     const int64_t ye = (!zero && y == n1 - 1) ? p1 : y + 1;
     const int64_t xe = (!zero && x == n2 - 1) ? p2 : x + 1;
@@ -677,9 +682,10 @@ void decompose_adjoint_t(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t
   }
   if (padded) {
     const int64_t tot = p.dims[0] * p.dims[1] * p.dims[2];
+    if (tot >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "grid too large for the pad transpose");
     hipLaunchKernelGGL(k_unpad_T<T>, dim3(grid_for(tot)), dim3(NT), 0, st, static_cast<const T*>(top), p.pdims[0],
                        p.pdims[1], p.pdims[2], static_cast<T*>(gx), p.dims[0], p.dims[1], p.dims[2],
-                       p.cfg.pad_mode == 1 ? 1 : 0);
+                       Unflat32(p.dims[1], p.dims[2]), p.cfg.pad_mode == 1 ? 1 : 0);
     BM_HIP(hipGetLastError());
   }
 }

@@ -26,15 +26,23 @@ constexpr int NT = 256;
 
 // ------------------------------------------------------------- elementwise
 
+// Grid dims plus a 32-bit multiply-high unflattening of node indices (a
+// 64-bit division per element would dominate these memory-bound kernels).
 struct Idx3 {
-  int64_t n0, n1, n2;
+  int64_t n0 = 0, n1 = 0, n2 = 0;
+  Unflat32 uf;
+  Idx3() = default;
+  Idx3(int64_t a, int64_t b, int64_t c) : n0(a), n1(b), n2(c), uf(b, c) {
+    if (a * b * c >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "a global level grid must have fewer than 2^32 nodes");
+  }
 };
 
 __device__ inline void unflat(int64_t i, const Idx3& d, int64_t& z, int64_t& y, int64_t& x) {
-  x = i % d.n2;
-  const int64_t t = i / d.n2;
-  y = t % d.n1;
-  z = t / d.n1;
+  uint32_t zz, yy, xx;
+  d.uf(uint32_t(i), zz, yy, xx);
+  z = zz;
+  y = yy;
+  x = xx;
 }
 
 template <typename T>
@@ -200,7 +208,7 @@ struct PassArgs {
   const double* qdel;
   const double* inv;     // Thomas reciprocal pivots, length m
   int64_t nl, m;         // line length, coarse length
-  int W;                 // lines per tile
+  int W, lw;             // lines per tile (a power of two) and its log2
   int64_t nq, ntq;       // extent of the fastest other axis, tiles per row along it
   int pa, qa;            // the two other axes (q fastest)
 };
@@ -210,74 +218,70 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   extern __shared__ unsigned char smem[];
   T* tin = reinterpret_cast<T*>(smem);                 // [nl][W+1]
   const int WP = a.W + 1;
-  T* tout = tin + a.nl * WP;                           // [m][W+1]
-  const int64_t tile = blockIdx.x;
-  const int64_t p = tile / a.ntq;
-  const int64_t q0 = (tile - p * a.ntq) * a.W;
+  const int nl = int(a.nl), m = int(a.m);
+  T* tout = tin + nl * WP;                             // [m][W+1]
+  T* piv = tout + m * WP;                              // [m] reciprocal pivots
+  const uint32_t tile = blockIdx.x;
+  const uint32_t p = tile / uint32_t(a.ntq);
+  const int64_t q0 = int64_t(tile - p * uint32_t(a.ntq)) * a.W;
   const int wv = int(i64min(a.W, a.nq - q0));   // valid lines in this tile
   const int tid = threadIdx.x;
-  const int64_t sA = a.is[a.axis], sP = a.is[a.pa], sQ = a.is[a.qa];
-  const int64_t total = a.nl * wv;
-  // load: along the line fastest when lines are rows (x), across lines otherwise
-  for (int64_t k = tid; k < total; k += NT) {
-    int64_t i, w;
-    if (a.axis == 2) {
-      w = k / a.nl;
-      i = k - w * a.nl;
-    } else {
-      i = k / wv;
-      w = k - i * wv;
-    }
-    const int64_t off = p * sP + (q0 + w) * sQ + i * sA;
-    T v = a.qin ? T(mul_rn(double(a.qin[off]), *a.qdel)) : a.in[off];
-    if (a.mask) {
-      int64_t c[3];
-      c[a.axis] = i;
-      c[a.pa] = p;
-      c[a.qa] = q0 + w;
-      const bool coarse = !((a.cm[0] && (c[0] & 1)) || (a.cm[1] && (c[1] & 1)) || (a.cm[2] && (c[2] & 1)));
-      if (coarse) v = T(0);
-    }
-    tin[i * WP + w] = v;
-  }
-  __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t m = a.m, nl = a.nl;
-  for (int w = wave; w < wv; w += NT / 64) {
-    const T* col = tin + w;
-    // right-hand side 3 (P^T M u)_J: 5-point interior rows, 3-point end rows
-    auto rhs = [&](int64_t J) {
-      const int64_t c = 2 * J;
-      T r;
-      if (J == 0) {
-        r = T(5.0 / 12.0) * col[0] + T(0.5) * col[WP] + T(1.0 / 12.0) * col[2 * WP];
-      } else if (J == m - 1) {
-        r = T(1.0 / 12.0) * col[(nl - 3) * WP] + T(0.5) * col[(nl - 2) * WP] + T(5.0 / 12.0) * col[(nl - 1) * WP];
-      } else {
-        r = T(1.0 / 12.0) * (col[(c - 2) * WP] + col[(c + 2) * WP]) + T(0.5) * (col[(c - 1) * WP] + col[(c + 1) * WP]) +
-            T(5.0 / 6.0) * col[c * WP];
-      }
-      return T(3) * r;
-    };
-    wave_thomas<T>(m, a.inv, lane, rhs, [&](int64_t J, T x) { tout[J * WP + w] = x; });
+  const int64_t sA = a.is[a.axis], sQ = a.is[a.qa];
+  const int64_t ibase = int64_t(p) * a.is[a.pa] + q0 * sQ;
+  // coarse-node test: every coarsening coordinate even
+  const bool pe = !(a.cm[a.pa] && (p & 1));
+  const int cmA = a.cm[a.axis], cmQ = a.cm[a.qa];
+  auto load = [&](int i, int w) {
+    const int64_t off = ibase + w * sQ + i * sA;
+    T v = a.qin ? T(mul_rn(double(a.qin[off]), *a.qdel)) : a.in[off];
+    if (a.mask && pe && !(cmA && (i & 1)) && !(cmQ && ((q0 + w) & 1))) v = T(0);
+    tin[i * WP + w] = v;
+  };
+  for (int J = tid; J < m; J += NT) piv[J] = T(a.inv[J]);
+  // load: a wavefront per line when lines are rows (x, contiguous); else the
+  // W lines of the tile side by side (W a power of two)
+  if (a.axis == 2) {
+    for (int w = wave; w < wv; w += NT / 64)
+      for (int i = lane; i < nl; i += 64) load(i, w);
+  } else {
+    const int w = tid & (a.W - 1);
+    if (w < wv)
+      for (int i = tid >> a.lw; i < nl; i += NT >> a.lw) load(i, w);
   }
   __syncthreads();
-  const int64_t totm = m * wv;
-  const int64_t oA = a.axis == 0 ? a.on[1] * a.on[2] : (a.axis == 1 ? a.on[2] : 1);
-  const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
-  const int64_t oP = os[a.pa], oQ = os[a.qa];
-  for (int64_t k = tid; k < totm; k += NT) {
-    int64_t J, w;
-    if (a.axis == 2) {
-      w = k / m;
-      J = k - w * m;
+  // right-hand side 3 (P^T M u)_J: 5-point interior rows, 3-point end rows
+  auto rhs = [&](int w, int J) {
+    const T* col = tin + w;
+    const int c = 2 * J;
+    T r;
+    if (J == 0) {
+      r = T(5.0 / 12.0) * col[0] + T(0.5) * col[WP] + T(1.0 / 12.0) * col[2 * WP];
+    } else if (J == m - 1) {
+      r = T(1.0 / 12.0) * col[(nl - 3) * WP] + T(0.5) * col[(nl - 2) * WP] + T(5.0 / 12.0) * col[(nl - 1) * WP];
     } else {
-      J = k / wv;
-      w = k - J * wv;
+      r = T(1.0 / 12.0) * (col[(c - 2) * WP] + col[(c + 2) * WP]) + T(0.5) * (col[(c - 1) * WP] + col[(c + 1) * WP]) +
+          T(5.0 / 6.0) * col[c * WP];
     }
-    const int64_t o = p * oP + (q0 + w) * oQ + J * oA;
+    return T(3) * r;
+  };
+  solve_lines<T, NT>(m, piv, wv, tid, rhs, [&](int w, int J, T x) { tout[J * WP + w] = x; });
+  __syncthreads();
+  const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
+  const int64_t oA = os[a.axis], oQ = os[a.qa];
+  const int64_t obase = int64_t(p) * os[a.pa] + q0 * oQ;
+  auto store = [&](int J, int w) {
+    const int64_t o = obase + w * oQ + J * oA;
     const T v = tout[J * WP + w];
     a.out[o] = a.base ? a.base[o] - v : v;
+  };
+  if (a.axis == 2) {
+    for (int w = wave; w < wv; w += NT / 64)
+      for (int J = lane; J < m; J += 64) store(J, w);
+  } else {
+    const int w = tid & (a.W - 1);
+    if (w < wv)
+      for (int J = tid >> a.lw; J < m; J += NT >> a.lw) store(J, w);
   }
 }
 
@@ -307,14 +311,14 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.pa = axis == 0 ? 1 : 0;
   a.qa = axis == 2 ? 1 : 2;
   a.nq = in.n[a.qa];
-  // tile width: keep the LDS tile near 40 KiB
-  const int64_t per_line = (a.nl + a.m) * int64_t(sizeof(T));
-  int W = int(std::min<int64_t>(64, std::max<int64_t>(1, 40960 / per_line - 1)));
-  W = int(std::min<int64_t>(W, a.nq));
-  a.W = W;
-  a.ntq = (a.nq + W - 1) / W;
-  const int64_t tiles = in.n[a.pa] * a.ntq;
-  const size_t shm = size_t(a.nl + a.m) * (W + 1) * sizeof(T);
+  const int64_t np = in.n[a.pa];
+  a.W = tile_width(a.nl + a.m + 1, sizeof(T), np, a.nq);
+  a.lw = 0;
+  while ((1 << a.lw) < a.W) ++a.lw;
+  a.ntq = (a.nq + a.W - 1) / a.W;
+  const int64_t tiles = np * a.ntq;
+  if (tiles >= (int64_t(1) << 31)) fail(BM_EUNSUPPORTED, "too many lines");
+  const size_t shm = (size_t(a.nl + a.m) * (a.W + 1) + size_t(a.m)) * sizeof(T);
   hipLaunchKernelGGL(k_line_pass<T>, dim3(unsigned(tiles)), dim3(NT), shm, st, a);
   BM_HIP(hipGetLastError());
 }

@@ -134,6 +134,12 @@ __device__ inline void column_tables(const QTab& t, int64_t bz, int64_t by, int6
   out[2] = pick(l[1], l[2]);
 }
 
+// Register budget of the block decomposition: FP32 fits 64 VGPRs (8 waves per
+// SIMD), so more blocks are in flight to cover HBM latency; FP64 columns need
+// twice the space.
+template <typename T>
+constexpr int kWavesPerEU = sizeof(T) == 4 ? 8 : 4;
+
 template <int B>
 __device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
 
@@ -147,7 +153,7 @@ __device__ inline int32_t quant(T c, double inv, bool& bad) {
 }
 
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
+__global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
   using G = Geo<B>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   __shared__ T lds[NB * G::DEC_LDS];
@@ -163,6 +169,7 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
   T* T2 = UE;                                        // [MI][MI][B], after UE is dead
   T* Z = T1;                                         // [MI][MI][MI], after T1 is dead
   const int y = tb / B, x = tb - (tb / B) * B;
+  const bool ecol = ((y | x) & 1) == 0;
   int64_t bz = 0, by = 0, bx = 0;
   if (act) {
     bx = blk % a.nb[2];
@@ -171,12 +178,12 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
     bz = t / a.nb[1];
   }
   const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  // a node on a shared face is written by the block that starts on it
+  const bool owned = (y < B - 1 || by == a.nb[1] - 1) && (x < B - 1 || bx == a.nb[2] - 1);
+  const bool lastz = bz == a.nb[0] - 1;
   // fused quantization: this column's 1/Delta, loaded early so the latency hides
-  double iv[3], ci[3];
-  if (Q && act) {
-    column_tables<B, true>(a.tab, bz, by, bx, y, x, iv);
-    if (a.coarsest_here && ((y | x) & 1) == 0) column_tables<B, true>(a.ctab, bz, by, bx, y, x, ci);
-  }
+  double iv[3];
+  if (Q && act) column_tables<B, true>(a.tab, bz, by, bx, y, x, iv);
   T v[B];
   if (act) {
     // one column: clamp or zero-fill outside the logical input on level 1
@@ -202,11 +209,10 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
     for (int j = 0; j < MC; ++j) UE[j * BB + tb] = v[2 * j];
   }
   __syncthreads();
-  T w[B];
   if (act) {
-    // details: u minus the multilinear interpolant of the coarse nodes
+    // details: u minus the multilinear interpolant of the coarse nodes.  They
+    // are final, so they are stored at once; v keeps u_C on the coarse nodes.
     const int y0 = y & ~1, y1 = y0 + (y & 1) * 2, x0 = x & ~1, x1 = x0 + (x & 1) * 2;
-    const bool ecol = ((y | x) & 1) == 0;
     T I2[MC];
 #pragma unroll
     for (int j = 0; j < MC; ++j) {
@@ -216,11 +222,29 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
 #pragma unroll
     for (int z = 0; z < B; ++z) {
       if (z & 1)
-        w[z] = v[z] - T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]);
-      else
-        w[z] = ecol ? T(0) : v[z] - I2[z >> 1];
+        v[z] = v[z] - T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]);
+      else if (!ecol)
+        v[z] = v[z] - I2[z >> 1];
     }
-    T o[MI];
+    if (owned) {
+      if (!Q) {
+        T* dst = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+#pragma unroll
+        for (int z = 0; z < B; ++z)
+          if (((z & 1) || !ecol) && (z < B - 1 || lastz)) dst[(oz + z) * a.cs[0]] = v[z];
+      } else {
+        int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
+        bool bad = false;
+#pragma unroll
+        for (int z = 0; z < B; ++z)
+          if (((z & 1) || !ecol) && (z < B - 1 || lastz)) dst[(oz + z) * a.cs[0]] = quant(v[z], iv[zcase<B>(z)], bad);
+        if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+      }
+    }
+    // correction, z pass: w is zero on the coarse nodes
+    T w[B], o[MI];
+#pragma unroll
+    for (int z = 0; z < B; ++z) w[z] = ((z & 1) || !ecol) ? v[z] : T(0);
     restrict_solve<T, B>(w, o);
 #pragma unroll
     for (int J = 0; J < MI; ++J) T1[J * BB + tb] = o[J];
@@ -230,50 +254,33 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose(DecArgs<T> a) {
   __syncthreads();
   if (act) pass_x<T, B>(T2, Z, tb);
   __syncthreads();
-  if (act) {
-    const bool ecol = ((y | x) & 1) == 0;
-    const bool icol = ecol && y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3;
-    if (ecol) {
-      // coarse values c = u_C + z (z = 0 on the block surface)
+  if (act && ecol && owned) {
+    // coarse values c = u_C + z (z = 0 on the block surface).  The coefficient
+    // array gets them from a later level (or from the coarsest copy); the
+    // compact coarse grid feeds the next level.
+    T c[MC];
 #pragma unroll
-      for (int j = 0; j < MC; ++j) w[2 * j] = v[2 * j];
-      if (icol) {
-        const int I = (y - 2) >> 1, K = (x - 2) >> 1;
+    for (int j = 0; j < MC; ++j) c[j] = v[2 * j];
+    if (y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3) {
+      const int I = (y - 2) >> 1, K = (x - 2) >> 1;
 #pragma unroll
-        for (int J = 0; J < MI; ++J) w[2 * J + 2] += Z[(J * MI + I) * MI + K];
-      }
+      for (int J = 0; J < MI; ++J) c[J + 1] += Z[(J * MI + I) * MI + K];
     }
-    const bool owny = y < B - 1 || by == a.nb[1] - 1;
-    const bool ownx = x < B - 1 || bx == a.nb[2] - 1;
-    const bool lastz = bz == a.nb[0] - 1;
-    if (owny && ownx) {
-      if (!Q) {
-        T* dst = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+    if (Q && a.coarsest_here) {
+      // last level of the hierarchy: codes for the coarsest values
+      double ci[3];
+      column_tables<B, true>(a.ctab, bz, by, bx, y, x, ci);
+      int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
+      bool bad = false;
 #pragma unroll
-        for (int z = 0; z < B; ++z)
-          if (z < B - 1 || lastz) dst[(oz + z) * a.cs[0]] = w[z];
-      } else {
-        // fused quantization: codes for the details of this level (and for
-        // the coarsest values when this is the last level of the hierarchy)
-        int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
-        bool bad = false;
+      for (int j = 0; j < MC; ++j)
+        if (j < MC - 1 || lastz) dst[(oz + 2 * j) * a.cs[0]] = quant(c[j], ci[zcase<B>(2 * j)], bad);
+      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+    } else {
+      T* cdst = a.cout + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
-        for (int z = 0; z < B; ++z) {
-          if (z == B - 1 && !lastz) continue;
-          const bool coarse = ecol && (z & 1) == 0;
-          if (!coarse)
-            dst[(oz + z) * a.cs[0]] = quant(w[z], iv[zcase<B>(z)], bad);
-          else if (a.coarsest_here)
-            dst[(oz + z) * a.cs[0]] = quant(w[z], ci[zcase<B>(z)], bad);
-        }
-        if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
-      }
-      if (ecol && !(Q && a.coarsest_here)) {
-        T* cdst = a.cout + (gy >> 1) * a.cn[2] + (gx >> 1);
-#pragma unroll
-        for (int j = 0; j < MC; ++j)
-          if (j < MC - 1 || lastz) cdst[((oz >> 1) + j) * a.cn[1] * a.cn[2]] = w[2 * j];
-      }
+      for (int j = 0; j < MC; ++j)
+        if (j < MC - 1 || lastz) cdst[((oz >> 1) + j) * a.cn[1] * a.cn[2]] = c[j];
     }
   }
 }
