@@ -419,7 +419,7 @@ struct PassTArgs {
   int pa, qa;             // the two other axes (q fastest)
 };
 
-template <typename T>
+template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_line_pass_T(PassTArgs<T> a) {
   extern __shared__ unsigned char smem[];
   T* tin = reinterpret_cast<T*>(smem);               // [m][W+1]
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(NT) void k_line_pass_T(PassTArgs<T> a) {
   }
   __syncthreads();
   // in place: each lane reads, and later overwrites, only its own rows
-  solve_lines<T, NT>(m, piv, wv, tid, [&](int w, int J) { return T(3) * tin[J * WP + w]; },
+  solve_lines<T, NT, Q>(m, piv, wv, tid, [&](int w, int J) { return T(3) * tin[J * WP + w]; },
                      [&](int w, int J, T x) { tin[J * WP + w] = x; });
   __syncthreads();
   const bool pe = !(a.cm[a.pa] && (p & 1));
@@ -515,7 +515,13 @@ void launch_pass_T(const bm_plan_s& p, int s, int axis, const View3& in, const V
   const int64_t tiles = np * a.ntq;
   if (tiles >= (int64_t(1) << 31)) fail(BM_EUNSUPPORTED, "too many lines");
   const size_t shm = (size_t(a.m) * (a.W + 1) + size_t(a.m)) * sizeof(T);
-  hipLaunchKernelGGL(k_line_pass_T<T>, dim3(unsigned(tiles)), dim3(NT), shm, st, a);
+  switch (row_q_for(a.m)) {
+    case 3: hipLaunchKernelGGL((k_line_pass_T<T, 3>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case 5: hipLaunchKernelGGL((k_line_pass_T<T, 5>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case 9: hipLaunchKernelGGL((k_line_pass_T<T, 9>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case kRowQ: hipLaunchKernelGGL((k_line_pass_T<T, kRowQ>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    default: hipLaunchKernelGGL((k_line_pass_T<T, 0>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+  }
   BM_HIP(hipGetLastError());
 }
 

@@ -49,6 +49,7 @@ template <typename T>
 struct DetArgs {
   const T* u;            // compact G^{s-1}
   Idx3 n;
+  Idx3 m;                // dims of G^s: one thread per coarse cell
   int cm0, cm1, cm2;     // 1 if the axis coarsens at this level
   T* coeff;
   int64_t cs[3];
@@ -68,35 +69,65 @@ __device__ inline int32_t quant_g(T c, double inv, int64_t* flag) {
   return int32_t(v);
 }
 
-// Interpolant at (z,y,x) from a grid holding the coarse values: mean of the
-// 8 corners of the coarse cell (an axis that does not coarsen, or an even
-// coordinate, uses the node itself twice).  read(zz, yy, xx) fetches a
-// coarse node in full-grid coordinates.
+// The fine-only nodes of a global level are handled per coarse cell: the
+// thread of coarse node (cz, cy, cx) takes the nodes 2c + d, d in {0,1}^3
+// (d = 1 only along axes that coarsen and stay inside the grid), so the 8
+// cell corners are read once for its 7 nodes.  The interpolant at 2c + d is
+// the mean of the corners c + {0, d} per axis, summed in the order z-plane,
+// y-row, x-pair.
+template <typename T>
+struct Cell {
+  T c[2][2][2];   // corners c + (0|1, 0|1, 0|1); index 1 only where the offset exists
+  int oz, oy, ox; // offset 1 exists along the axis
+  __device__ inline T interp(int dz, int dy, int dx) const {
+    const T s = ((c[0][0][0] + c[0][0][dx]) + (c[0][dy][0] + c[0][dy][dx])) +
+                ((c[dz][0][0] + c[dz][0][dx]) + (c[dz][dy][0] + c[dz][dy][dx]));
+    return s * T(0.125);
+  }
+};
+
+// corners from a reader of coarse-grid values at coarse coordinates
 template <typename T, typename F>
-__device__ inline T interp8(int64_t z, int64_t y, int64_t x, int cm0, int cm1, int cm2, F read) {
-  const int64_t z0 = (cm0 && (z & 1)) ? z - 1 : z, z1 = (cm0 && (z & 1)) ? z + 1 : z;
-  const int64_t y0 = (cm1 && (y & 1)) ? y - 1 : y, y1 = (cm1 && (y & 1)) ? y + 1 : y;
-  const int64_t x0 = (cm2 && (x & 1)) ? x - 1 : x, x1 = (cm2 && (x & 1)) ? x + 1 : x;
-  const T s = ((read(z0, y0, x0) + read(z0, y0, x1)) + (read(z0, y1, x0) + read(z0, y1, x1))) +
-              ((read(z1, y0, x0) + read(z1, y0, x1)) + (read(z1, y1, x0) + read(z1, y1, x1)));
-  return s * T(0.125);
+__device__ inline void load_corners(Cell<T>& k, int64_t cz, int64_t cy, int64_t cx, F rd) {
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx)
+        k.c[dz][dy][dx] = (dz <= k.oz && dy <= k.oy && dx <= k.ox) ? rd(cz + dz, cy + dy, cx + dx) : T(0);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_details(DetArgs<T> a) {
-  const int64_t tot = a.n.n0 * a.n.n1 * a.n.n2;
+  const int64_t tot = a.m.n0 * a.m.n1 * a.m.n2;
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    int64_t z, y, x;
-    unflat(i, a.n, z, y, x);
-    const bool coarse = !((a.cm0 && (z & 1)) || (a.cm1 && (y & 1)) || (a.cm2 && (x & 1)));
-    if (coarse) continue;
-    auto rd = [&](int64_t zz, int64_t yy, int64_t xx) { return a.u[(zz * a.n.n1 + yy) * a.n.n2 + xx]; };
-    const T d = a.u[i] - interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
-    const int64_t o = z * a.cs[0] + y * a.cs[1] + x * a.cs[2];
-    if (a.codes)
-      a.codes[o] = quant_g(d, *a.qinv, a.flag);
-    else
-      a.coeff[o] = d;
+    int64_t cz, cy, cx;
+    unflat(i, a.m, cz, cy, cx);
+    const int64_t z = a.cm0 ? 2 * cz : cz, y = a.cm1 ? 2 * cy : cy, x = a.cm2 ? 2 * cx : cx;
+    Cell<T> k;
+    k.oz = a.cm0 && z + 1 < a.n.n0;
+    k.oy = a.cm1 && y + 1 < a.n.n1;
+    k.ox = a.cm2 && x + 1 < a.n.n2;
+    auto U = [&](int64_t zz, int64_t yy, int64_t xx) { return a.u[(zz * a.n.n1 + yy) * a.n.n2 + xx]; };
+    load_corners(k, cz, cy, cx, [&](int64_t zz, int64_t yy, int64_t xx) {
+      return U(a.cm0 ? 2 * zz : zz, a.cm1 ? 2 * yy : yy, a.cm2 ? 2 * xx : xx);
+    });
+    const double inv = a.codes ? *a.qinv : 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          if ((dz | dy | dx) == 0 || dz > k.oz || dy > k.oy || dx > k.ox) continue;
+          const T d = U(z + dz, y + dy, x + dx) - k.interp(dz, dy, dx);
+          const int64_t o = (z + dz) * a.cs[0] + (y + dy) * a.cs[1] + (x + dx) * a.cs[2];
+          if (a.codes)
+            a.codes[o] = quant_g(d, inv, a.flag);
+          else
+            a.coeff[o] = d;
+        }
   }
 }
 
@@ -115,23 +146,34 @@ struct IntArgs {
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_interp_add(IntArgs<T> a) {
-  const int64_t tot = a.n.n0 * a.n.n1 * a.n.n2;
+  const int64_t tot = a.m.n0 * a.m.n1 * a.m.n2;
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    int64_t z, y, x;
-    unflat(i, a.n, z, y, x);
-    auto rd = [&](int64_t zz, int64_t yy, int64_t xx) {
-      const int64_t cz = a.cm0 ? zz >> 1 : zz, cy = a.cm1 ? yy >> 1 : yy, cx = a.cm2 ? xx >> 1 : xx;
-      return a.uc[(cz * a.m.n1 + cy) * a.m.n2 + cx];
-    };
-    const bool coarse = !((a.cm0 && (z & 1)) || (a.cm1 && (y & 1)) || (a.cm2 && (x & 1)));
-    T v;
-    if (coarse)
-      v = rd(z, y, x);
-    else
-      v = (a.codes ? T(mul_rn(double(a.codes[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]]), *a.qdel))
-                   : a.coeff[z * a.cs[0] + y * a.cs[1] + x * a.cs[2]]) +
-          interp8<T>(z, y, x, a.cm0, a.cm1, a.cm2, rd);
-    a.out[i] = v;
+    int64_t cz, cy, cx;
+    unflat(i, a.m, cz, cy, cx);
+    const int64_t z = a.cm0 ? 2 * cz : cz, y = a.cm1 ? 2 * cy : cy, x = a.cm2 ? 2 * cx : cx;
+    Cell<T> k;
+    k.oz = a.cm0 && z + 1 < a.n.n0;
+    k.oy = a.cm1 && y + 1 < a.n.n1;
+    k.ox = a.cm2 && x + 1 < a.n.n2;
+    load_corners(k, cz, cy, cx,
+                 [&](int64_t zz, int64_t yy, int64_t xx) { return a.uc[(zz * a.m.n1 + yy) * a.m.n2 + xx]; });
+    const double del = a.codes ? *a.qdel : 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          if (dz > k.oz || dy > k.oy || dx > k.ox) continue;
+          const int64_t o = ((z + dz) * a.n.n1 + (y + dy)) * a.n.n2 + (x + dx);
+          if ((dz | dy | dx) == 0) {
+            a.out[o] = k.c[0][0][0];
+            continue;
+          }
+          const int64_t co = (z + dz) * a.cs[0] + (y + dy) * a.cs[1] + (x + dx) * a.cs[2];
+          const T w = a.codes ? T(mul_rn(double(a.codes[co]), del)) : a.coeff[co];
+          a.out[o] = w + k.interp(dz, dy, dx);
+        }
   }
 }
 
@@ -213,7 +255,7 @@ struct PassArgs {
   int pa, qa;            // the two other axes (q fastest)
 };
 
-template <typename T>
+template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   extern __shared__ unsigned char smem[];
   T* tin = reinterpret_cast<T*>(smem);                 // [nl][W+1]
@@ -265,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
     }
     return T(3) * r;
   };
-  solve_lines<T, NT>(m, piv, wv, tid, rhs, [&](int w, int J, T x) { tout[J * WP + w] = x; });
+  solve_lines<T, NT, Q>(m, piv, wv, tid, rhs, [&](int w, int J, T x) { tout[J * WP + w] = x; });
   __syncthreads();
   const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
   const int64_t oA = os[a.axis], oQ = os[a.qa];
@@ -319,7 +361,13 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   const int64_t tiles = np * a.ntq;
   if (tiles >= (int64_t(1) << 31)) fail(BM_EUNSUPPORTED, "too many lines");
   const size_t shm = (size_t(a.nl + a.m) * (a.W + 1) + size_t(a.m)) * sizeof(T);
-  hipLaunchKernelGGL(k_line_pass<T>, dim3(unsigned(tiles)), dim3(NT), shm, st, a);
+  switch (row_q_for(a.m)) {
+    case 3: hipLaunchKernelGGL((k_line_pass<T, 3>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case 5: hipLaunchKernelGGL((k_line_pass<T, 5>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case 9: hipLaunchKernelGGL((k_line_pass<T, 9>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case kRowQ: hipLaunchKernelGGL((k_line_pass<T, kRowQ>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    default: hipLaunchKernelGGL((k_line_pass<T, 0>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+  }
   BM_HIP(hipGetLastError());
 }
 
@@ -330,10 +378,9 @@ void launch_details(const bm_plan_s& p, int s, const void* u, void* coeff, int32
                     int64_t* flag, hipStream_t st) {
   const Level& L = p.lv[s - 1];
   const View3 cv = level_view(p, s, codes ? static_cast<void*>(codes) : coeff);
-  const int64_t tot = L.n[0] * L.n[1] * L.n[2];
-  DetArgs<T> a{static_cast<const T*>(u), {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
-               static_cast<T*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, codes, qinv, flag};
-  hipLaunchKernelGGL(k_details<T>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  DetArgs<T> a{static_cast<const T*>(u), {L.n[0], L.n[1], L.n[2]}, {L.m[0], L.m[1], L.m[2]}, L.coarsen[0],
+               L.coarsen[1], L.coarsen[2], static_cast<T*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, codes, qinv, flag};
+  hipLaunchKernelGGL(k_details<T>, dim3(grid_for(L.m[0] * L.m[1] * L.m[2])), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
 
@@ -342,11 +389,10 @@ void launch_interp(const bm_plan_s& p, int s, const void* coeff, const int32_t* 
                    const void* uc, void* out, hipStream_t st) {
   const Level& L = p.lv[s - 1];
   const View3 cv = level_view(p, s, codes ? const_cast<int32_t*>(codes) : const_cast<void*>(coeff));
-  const int64_t tot = L.n[0] * L.n[1] * L.n[2];
   IntArgs<T> a{static_cast<const T*>(coeff), {cv.s[0], cv.s[1], cv.s[2]}, static_cast<const T*>(uc),
                {L.m[0], L.m[1], L.m[2]}, {L.n[0], L.n[1], L.n[2]}, L.coarsen[0], L.coarsen[1], L.coarsen[2],
                static_cast<T*>(out), codes, qdel};
-  hipLaunchKernelGGL(k_interp_add<T>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL(k_interp_add<T>, dim3(grid_for(L.m[0] * L.m[1] * L.m[2])), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
 

@@ -150,15 +150,15 @@ __device__ inline void wave_thomas(int64_t m, const T* inv, int lane, Rhs rhs, O
   }
 }
 
-// The same solve by a 16-lane row (r = lane within the row), m <= 16 * kRowQ.
-template <typename T, typename Rhs, typename Out>
+// The same solve by a 16-lane row (r = lane within the row), m <= 16 * Q.
+template <typename T, int Q, typename Rhs, typename Out>
 __device__ inline void row_thomas(int m, const T* inv, int r, Rhs rhs, Out out) {
   const int q = (m + 15) >> 4;
   const int J0 = r * q;
-  T f[kRowQ], al[kRowQ];
+  T f[Q], al[Q];
   T A = T(1), B = T(0);
 #pragma unroll
-  for (int j = 0; j < kRowQ; ++j) {
+  for (int j = 0; j < Q; ++j) {
     const int J = J0 + j;
     if (j < q && J < m) {
       const T iv = inv[J];
@@ -171,7 +171,7 @@ __device__ inline void row_thomas(int m, const T* inv, int r, Rhs rhs, Out out) 
   row_scan_up(A, B);
   T din = dpp_row<0x111>(T(0), B);
 #pragma unroll
-  for (int j = 0; j < kRowQ; ++j) {
+  for (int j = 0; j < Q; ++j) {
     if (j < q && J0 + j < m) {
       din = al[j] * din + f[j];
       f[j] = din;
@@ -180,7 +180,7 @@ __device__ inline void row_thomas(int m, const T* inv, int r, Rhs rhs, Out out) 
   A = T(1);
   B = T(0);
 #pragma unroll
-  for (int j = kRowQ - 1; j >= 0; --j) {
+  for (int j = Q - 1; j >= 0; --j) {
     const int J = J0 + j;
     if (j < q && J < m) {
       al[j] = J == m - 1 ? T(0) : -inv[J];
@@ -191,7 +191,7 @@ __device__ inline void row_thomas(int m, const T* inv, int r, Rhs rhs, Out out) 
   row_scan_down(A, B);
   T xin = dpp_row<0x101>(T(0), B);
 #pragma unroll
-  for (int j = kRowQ - 1; j >= 0; --j) {
+  for (int j = Q - 1; j >= 0; --j) {
     const int J = J0 + j;
     if (j < q && J < m) {
       xin = al[j] * xin + f[j];
@@ -202,19 +202,25 @@ __device__ inline void row_thomas(int m, const T* inv, int r, Rhs rhs, Out out) 
 
 // Solves lines 0..wv-1 of a tile with the NTHREADS / 64 wavefronts of a
 // workgroup.  rhs(w, J) reads the right-hand side of row J of line w;
-// out(w, J, x) receives the solution.  Every lane of a wavefront takes part
-// in its scans: a row past the last line repeats a valid line and writes
-// nothing.
-template <typename T, int NTHREADS, typename Rhs, typename Out>
+// out(w, J, x) receives the solution.  Q > 0: 16-lane rows with up to Q
+// unknowns per lane (m <= 16 Q; registers scale with Q, so the launcher picks
+// the smallest Q that fits); Q = 0: a wavefront per line.  Every lane of a
+// wavefront takes part in its scans: a row past the last line repeats a
+// valid line and writes nothing.
+inline int row_q_for(int64_t m) {
+  return m <= 48 ? 3 : m <= 80 ? 5 : m <= 144 ? 9 : m <= 16 * kRowQ ? kRowQ : 0;
+}
+
+template <typename T, int NTHREADS, int Q, typename Rhs, typename Out>
 __device__ inline void solve_lines(int m, const T* inv, int wv, int tid, Rhs rhs, Out out) {
   constexpr int NW = NTHREADS / 64;
   const int lane = tid & 63, wave = tid >> 6;
-  if (m <= 16 * kRowQ) {
+  if constexpr (Q > 0) {
     const int r = lane & 15;
     for (int w0 = wave * 4; w0 < wv; w0 += NW * 4) {
       const int w = w0 + (lane >> 4);
       const int wr = w < wv ? w : w0;
-      row_thomas<T>(m, inv, r, [&](int J) { return rhs(wr, J); }, [&](int J, T x) {
+      row_thomas<T, Q>(m, inv, r, [&](int J) { return rhs(wr, J); }, [&](int J, T x) {
         if (w < wv) out(w, J, x);
       });
     }
