@@ -179,6 +179,11 @@ void recompose_adjoint(bm_plan_s& p, const void* gx, void* gcoeff, hipStream_t s
 struct QTab {
   const double* del = nullptr;
   const double* inv = nullptr;
+  // per block, per class of node position (first face / interior / last face
+  // along z, y, x: 27 classes, index 9 cz + 3 cy + cx) the smallest Delta and
+  // the largest 1/Delta over the blocks that contain such a node
+  const double* cdel = nullptr;
+  const double* cinv = nullptr;
   int64_t nb[3] = {1, 1, 1};
 };
 struct QPrep {

@@ -76,12 +76,16 @@ template <typename T>
 struct DecArgs {
   const T* src;
   int64_t sn[3], ss[3];   // source grid dims and strides (level 1: logical dims)
+  uint32_t ss0;           // z stride of the source, 32-bit (within one column)
   int first, zero_pad;    // level 1 reads the unpadded input with clamp / zero fill
   T* coeff;
   int64_t cs[3];          // coefficient strides of this level's grid
+  uint32_t cs0;           // z stride of the coefficients, 32-bit
   T* cout;                // compact coarse grid G^s
   int64_t cn[3];
+  uint32_t cpl;           // plane size of the coarse grid
   int64_t nb[3], nblocks, nwg, per;
+  FastDiv fnb2, fnb1;     // block index -> (bz, by, bx)
   // fused quantization (codes written instead of coefficients)
   int32_t* codes;         // same layout as coeff
   QTab tab;               // this level's block tables
@@ -94,44 +98,58 @@ template <typename T>
 struct RecArgs {
   const T* coeff;
   int64_t cs[3];
+  uint32_t cs0;
   const T* cin;           // compact coarse grid G^s
   int64_t cn[3];
+  uint32_t cpl;
   T* out;                 // output grid view (cropped to on)
   int64_t on[3], os[3];
+  uint32_t os0;
   int64_t nb[3], nblocks, nwg, per;
+  FastDiv fnb2, fnb1;
   const int32_t* codes;   // fused dequantization: codes instead of coefficients
   QTab tab, ctab;
   int coarsest_here;
 };
 
-// Delta and 1/Delta of the nodes of one z-column: a node takes the smallest
-// Delta (largest 1/Delta) of the blocks that contain it.  A node on a block
-// face (local coordinate 0 or B-1) also lies in the neighbour across it.
-// Results for z = 0, for 0 < z < B-1 and for z = B-1.
-// INV: read 1/Delta and keep the largest, else read Delta and keep the smallest.
-template <int B, bool INV>
-__device__ inline void column_tables(const QTab& t, int64_t bz, int64_t by, int64_t bx, int y, int x, double out[3]) {
-  // candidate blocks per axis: own block, plus the neighbour across a face
-  const int64_t y2 = (y == 0 && by > 0) ? by - 1 : ((y == B - 1 && by + 1 < t.nb[1]) ? by + 1 : by);
-  const int64_t x2 = (x == 0 && bx > 0) ? bx - 1 : ((x == B - 1 && bx + 1 < t.nb[2]) ? bx + 1 : bx);
-  const int64_t zc[3] = {bz > 0 ? bz - 1 : bz, bz, bz + 1 < t.nb[0] ? bz + 1 : bz};
-  const double* tab = INV ? t.inv : t.del;
-  auto pick = [](double a, double b) { return INV ? fmax(a, b) : fmin(a, b); };
-  double l[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int64_t r0 = zc[c] * t.nb[1];
-    double v = tab[(r0 + by) * t.nb[2] + bx];
-    if (x2 != bx) v = pick(v, tab[(r0 + by) * t.nb[2] + x2]);
-    if (y2 != by) {
-      v = pick(v, tab[(r0 + y2) * t.nb[2] + bx]);
-      if (x2 != bx) v = pick(v, tab[(r0 + y2) * t.nb[2] + x2]);
-    }
-    l[c] = v;
-  }
-  out[0] = pick(l[0], l[1]);
-  out[1] = l[1];
-  out[2] = pick(l[1], l[2]);
+// block coordinates of block index blk
+__device__ inline void block_coords(uint32_t blk, const FastDiv& f2, const FastDiv& f1, const int64_t nb[3],
+                                    int64_t& bz, int64_t& by, int64_t& bx) {
+  const uint32_t t = f2.div(blk);
+  bx = int64_t(blk) - int64_t(t) * nb[2];
+  const uint32_t z = f1.div(t);
+  by = int64_t(t) - int64_t(z) * nb[1];
+  bz = z;
+}
+
+// position class of a local coordinate: first face 0, interior 1, last face 2
+template <int B>
+__device__ inline int pos_class(int c) {
+  return c == 0 ? 0 : (c == B - 1 ? 2 : 1);
+}
+
+// The Delta-table entries (27 classes per block) of one z-column: a node takes
+// the smallest Delta (largest 1/Delta) of the blocks that contain it.  Entries
+// for z = 0, for 0 < z < B-1 and for z = B-1.
+template <int B>
+__device__ inline void column_class(const double* tab, int64_t blk, int y, int x, double out[3]) {
+  const double* t = tab + blk * 27 + pos_class<B>(y) * 3 + pos_class<B>(x);
+  out[0] = t[0];
+  out[1] = t[9];
+  out[2] = t[18];
+}
+
+template <int B>
+__device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
+
+// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag.
+// skip: a placeholder (zero) is written instead and nothing is checked.
+template <typename T>
+__device__ inline int32_t quant(T c, double inv, bool skip, bool& bad) {
+  const double v = rint(mul_rn(double(c), inv));
+  const bool ok = fabs(v) <= 2147483647.0;
+  bad |= !ok && !skip;
+  return (ok && !skip) ? int32_t(v) : 0;
 }
 
 // Register budget of the block decomposition: FP32 fits 64 VGPRs (8 waves per
@@ -139,18 +157,6 @@ __device__ inline void column_tables(const QTab& t, int64_t bz, int64_t by, int6
 // twice the space.
 template <typename T>
 constexpr int kWavesPerEU = sizeof(T) == 4 ? 8 : 4;
-
-template <int B>
-__device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
-
-// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag
-template <typename T>
-__device__ inline int32_t quant(T c, double inv, bool& bad) {
-  const double v = rint(mul_rn(double(c), inv));
-  const bool ok = fabs(v) <= 2147483647.0;
-  bad |= !ok;
-  return ok ? int32_t(v) : 0;
-}
 
 template <typename T, int B, bool Q>
 __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
@@ -171,39 +177,32 @@ __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWav
   const int y = tb / B, x = tb - (tb / B) * B;
   const bool ecol = ((y | x) & 1) == 0;
   int64_t bz = 0, by = 0, bx = 0;
-  if (act) {
-    bx = blk % a.nb[2];
-    const int64_t t = blk / a.nb[2];
-    by = t % a.nb[1];
-    bz = t / a.nb[1];
-  }
+  if (act) block_coords(uint32_t(blk), a.fnb2, a.fnb1, a.nb, bz, by, bx);
   const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
   // a node on a shared face is written by the block that starts on it
   const bool owned = (y < B - 1 || by == a.nb[1] - 1) && (x < B - 1 || bx == a.nb[2] - 1);
   const bool lastz = bz == a.nb[0] - 1;
   // fused quantization: this column's 1/Delta, loaded early so the latency hides
   double iv[3];
-  if (Q && act) column_tables<B, true>(a.tab, bz, by, bx, y, x, iv);
+  if (Q && act) column_class<B>(a.tab.cinv, blk, y, x, iv);
   T v[B];
   if (act) {
-    // one column: clamp or zero-fill outside the logical input on level 1
-    bool yx_in = true;
-    int64_t ry = gy, rx = gx;
-    if (a.first) {
-      yx_in = gy < a.sn[1] && gx < a.sn[2];
-      ry = gy < a.sn[1] ? gy : a.sn[1] - 1;
-      rx = gx < a.sn[2] ? gx : a.sn[2] - 1;
-    }
-    const T* col = a.src + ry * a.ss[1] + rx * a.ss[2];
+    if (!a.first || (oz + B <= a.sn[0] && gy < a.sn[1] && gx < a.sn[2])) {
+      const T* col = a.src + oz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2];
 #pragma unroll
-    for (int z = 0; z < B; ++z) {
-      int64_t gz = oz + z;
-      bool in = yx_in;
-      if (a.first) {
-        in = in && gz < a.sn[0];
-        gz = gz < a.sn[0] ? gz : a.sn[0] - 1;
+      for (int z = 0; z < B; ++z) v[z] = col[z * a.ss0];
+    } else {
+      // level 1 at the far faces: clamp or zero-fill outside the logical input
+      const bool yx_in = gy < a.sn[1] && gx < a.sn[2];
+      const int64_t ry = gy < a.sn[1] ? gy : a.sn[1] - 1;
+      const int64_t rx = gx < a.sn[2] ? gx : a.sn[2] - 1;
+      const T* col = a.src + ry * a.ss[1] + rx * a.ss[2];
+#pragma unroll
+      for (int z = 0; z < B; ++z) {
+        const int64_t gz = oz + z;
+        const bool in = yx_in && gz < a.sn[0];
+        v[z] = (a.zero_pad && !in) ? T(0) : col[(gz < a.sn[0] ? gz : a.sn[0] - 1) * a.ss[0]];
       }
-      v[z] = (a.zero_pad && !in) ? T(0) : col[gz * a.ss[0]];
     }
 #pragma unroll
     for (int j = 0; j < MC; ++j) UE[j * BB + tb] = v[2 * j];
@@ -227,17 +226,20 @@ __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWav
         v[z] = v[z] - I2[z >> 1];
     }
     if (owned) {
+      // The coarse nodes of an even column get a placeholder (u_C, or code
+      // 0): a later level (or the coarsest copy) overwrites them.  The plane
+      // z = B-1 belongs to the next block unless this is the last one.
       if (!Q) {
-        T* dst = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+        T* dst = a.coeff + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
 #pragma unroll
-        for (int z = 0; z < B; ++z)
-          if (((z & 1) || !ecol) && (z < B - 1 || lastz)) dst[(oz + z) * a.cs[0]] = v[z];
+        for (int z = 0; z < B - 1; ++z) dst[z * a.cs0] = v[z];
+        if (lastz) dst[(B - 1) * a.cs0] = v[B - 1];
       } else {
-        int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
+        int32_t* dst = a.codes + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
         bool bad = false;
 #pragma unroll
-        for (int z = 0; z < B; ++z)
-          if (((z & 1) || !ecol) && (z < B - 1 || lastz)) dst[(oz + z) * a.cs[0]] = quant(v[z], iv[zcase<B>(z)], bad);
+        for (int z = 0; z < B - 1; ++z) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], ecol && !(z & 1), bad);
+        if (lastz) dst[(B - 1) * a.cs0] = quant(v[B - 1], iv[2], ecol, bad);
         if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
       }
     }
@@ -255,9 +257,8 @@ __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWav
   if (act) pass_x<T, B>(T2, Z, tb);
   __syncthreads();
   if (act && ecol && owned) {
-    // coarse values c = u_C + z (z = 0 on the block surface).  The coefficient
-    // array gets them from a later level (or from the coarsest copy); the
-    // compact coarse grid feeds the next level.
+    // coarse values c = u_C + z (z = 0 on the block surface); the compact
+    // coarse grid feeds the next level
     T c[MC];
 #pragma unroll
     for (int j = 0; j < MC; ++j) c[j] = v[2 * j];
@@ -269,18 +270,18 @@ __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWav
     if (Q && a.coarsest_here) {
       // last level of the hierarchy: codes for the coarsest values
       double ci[3];
-      column_tables<B, true>(a.ctab, bz, by, bx, y, x, ci);
-      int32_t* dst = a.codes + gy * a.cs[1] + gx * a.cs[2];
+      column_class<B>(a.ctab.cinv, blk, y, x, ci);
+      int32_t* dst = a.codes + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
       bool bad = false;
 #pragma unroll
-      for (int j = 0; j < MC; ++j)
-        if (j < MC - 1 || lastz) dst[(oz + 2 * j) * a.cs[0]] = quant(c[j], ci[zcase<B>(2 * j)], bad);
+      for (int j = 0; j < MC - 1; ++j) dst[2 * j * a.cs0] = quant(c[j], ci[zcase<B>(2 * j)], false, bad);
+      if (lastz) dst[(B - 1) * a.cs0] = quant(c[MC - 1], ci[2], false, bad);
       if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
     } else {
-      T* cdst = a.cout + (gy >> 1) * a.cn[2] + (gx >> 1);
+      T* cdst = a.cout + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
-      for (int j = 0; j < MC; ++j)
-        if (j < MC - 1 || lastz) cdst[((oz >> 1) + j) * a.cn[1] * a.cn[2]] = c[j];
+      for (int j = 0; j < MC - 1; ++j) cdst[j * a.cpl] = c[j];
+      if (lastz) cdst[(MC - 1) * a.cpl] = c[MC - 1];
     }
   }
 }
@@ -304,46 +305,41 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
   const int y = tb / B, x = tb - (tb / B) * B;
   const bool ecol = ((y | x) & 1) == 0;
   int64_t bz = 0, by = 0, bx = 0;
-  if (act) {
-    bx = blk % a.nb[2];
-    const int64_t t = blk / a.nb[2];
-    by = t % a.nb[1];
-    bz = t / a.nb[1];
-  }
+  if (act) block_coords(uint32_t(blk), a.fnb2, a.fnb1, a.nb, bz, by, bx);
   const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
   T w[B], ce[MC];
   if (act) {
+    // the whole column is read (coarse nodes too, then zeroed): one load per node
+    const int64_t off = oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
     if (!Q) {
-      const T* col = a.coeff + gy * a.cs[1] + gx * a.cs[2];
+      const T* col = a.coeff + off;
 #pragma unroll
-      for (int z = 0; z < B; ++z)
-        if ((z & 1) || !ecol) w[z] = col[(oz + z) * a.cs[0]];
+      for (int z = 0; z < B; ++z) w[z] = col[z * a.cs0];
     } else {
-      // fused dequantization: c_hat = (T)(q * Delta); codes and tables load together
-      const int32_t* col = a.codes + gy * a.cs[1] + gx * a.cs[2];
+      // fused dequantization: c_hat = (T)(q * Delta)
+      const int32_t* col = a.codes + off;
       int32_t qv[B];
 #pragma unroll
-      for (int z = 0; z < B; ++z) qv[z] = ((z & 1) || !ecol) ? col[(oz + z) * a.cs[0]] : 0;
+      for (int z = 0; z < B; ++z) qv[z] = col[z * a.cs0];
       double dd[3];
-      column_tables<B, false>(a.tab, bz, by, bx, y, x, dd);
+      column_class<B>(a.tab.cdel, blk, y, x, dd);
 #pragma unroll
-      for (int z = 0; z < B; ++z)
-        if ((z & 1) || !ecol) w[z] = T(mul_rn(double(qv[z]), dd[zcase<B>(z)]));
+      for (int z = 0; z < B; ++z) w[z] = T(mul_rn(double(qv[z]), dd[zcase<B>(z)]));
     }
     if (ecol) {
       if (Q && a.coarsest_here) {
-        const int32_t* col = a.codes + gy * a.cs[1] + gx * a.cs[2];
+        const int32_t* col = a.codes + off;
         int32_t qc[MC];
 #pragma unroll
-        for (int j = 0; j < MC; ++j) qc[j] = col[(oz + 2 * j) * a.cs[0]];
+        for (int j = 0; j < MC; ++j) qc[j] = col[2 * j * a.cs0];
         double cd[3];
-        column_tables<B, false>(a.ctab, bz, by, bx, y, x, cd);
+        column_class<B>(a.ctab.cdel, blk, y, x, cd);
 #pragma unroll
         for (int j = 0; j < MC; ++j) ce[j] = T(mul_rn(double(qc[j]), cd[zcase<B>(2 * j)]));
       } else {
-        const T* ccol = a.cin + (gy >> 1) * a.cn[2] + (gx >> 1);
+        const T* ccol = a.cin + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
-        for (int j = 0; j < MC; ++j) ce[j] = ccol[((oz >> 1) + j) * a.cn[1] * a.cn[2]];
+        for (int j = 0; j < MC; ++j) ce[j] = ccol[j * a.cpl];
       }
 #pragma unroll
       for (int j = 0; j < MC; ++j) w[2 * j] = T(0);
@@ -383,15 +379,28 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
     const bool ownx = (x < B - 1 || bx == a.nb[2] - 1) && gx < a.on[2];
     const bool lastz = bz == a.nb[0] - 1;
     if (owny && ownx) {
-      T* dst = a.out + gy * a.os[1] + gx * a.os[2];
+      T* dst = a.out + oz * a.os[0] + gy * a.os[1] + gx * a.os[2];
+      auto val = [&](int z) {
+        return (z & 1) ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) + w[z] : (ecol ? I2[z >> 1] : I2[z >> 1] + w[z]);
+      };
+      if (oz + B <= a.on[0]) {
 #pragma unroll
-      for (int z = 0; z < B; ++z) {
-        const T u = (z & 1) ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) + w[z]
-                            : (ecol ? I2[z >> 1] : I2[z >> 1] + w[z]);
-        if ((z < B - 1 || lastz) && oz + z < a.on[0]) dst[(oz + z) * a.os[0]] = u;
+        for (int z = 0; z < B - 1; ++z) dst[z * a.os0] = val(z);
+        if (lastz) dst[(B - 1) * a.os0] = val(B - 1);
+      } else {
+        // the block reaches past the (cropped) output
+#pragma unroll
+        for (int z = 0; z < B; ++z)
+          if ((z < B - 1 || lastz) && oz + z < a.on[0]) dst[z * a.os0] = val(z);
       }
     }
   }
+}
+
+// 32-bit z stride within one block column
+inline uint32_t column_stride(int64_t s, int B) {
+  if (s * (B - 1) >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "grid planes too large for 32-bit column offsets");
+  return uint32_t(s);
 }
 
 template <typename T, int B>
@@ -407,13 +416,19 @@ void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* c
     a.cn[k] = L.m[k];
     a.nb[k] = L.nb[k];
   }
+  a.ss0 = column_stride(src.s[0], B);
   a.first = first;
   a.zero_pad = p.cfg.pad_mode == 1;
   a.coeff = static_cast<T*>(coeff);
   const View3 cv = level_view(p, s, q ? static_cast<void*>(codes) : coeff);
   for (int k = 0; k < 3; ++k) a.cs[k] = cv.s[k];
+  a.cs0 = column_stride(cv.s[0], B);
   a.cout = static_cast<T*>(cout);
+  a.cpl = column_stride(L.m[1] * L.m[2], B);
   a.nblocks = L.nb[0] * L.nb[1] * L.nb[2];
+  if (a.nblocks >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "too many blocks");
+  a.fnb2 = FastDiv(uint32_t(L.nb[2]));
+  a.fnb1 = FastDiv(uint32_t(L.nb[1]));
   a.nwg = (a.nblocks + G::NB - 1) / G::NB;
   a.per = (a.nwg + 7) / 8;
   if (q) {
@@ -442,6 +457,8 @@ void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, v
     a.cn[k] = L.m[k];
     a.nb[k] = L.nb[k];
   }
+  a.cs0 = column_stride(cv.s[0], B);
+  a.cpl = column_stride(L.m[1] * L.m[2], B);
   a.cin = static_cast<const T*>(cin);
   a.out = static_cast<T*>(out);
   // last: writing the caller's output with the logical (unpadded) dims
@@ -450,7 +467,11 @@ void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, v
   a.os[0] = on[1] * on[2];
   a.os[1] = on[2];
   a.os[2] = 1;
+  a.os0 = column_stride(a.os[0], B);
   a.nblocks = L.nb[0] * L.nb[1] * L.nb[2];
+  if (a.nblocks >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "too many blocks");
+  a.fnb2 = FastDiv(uint32_t(L.nb[2]));
+  a.fnb1 = FastDiv(uint32_t(L.nb[1]));
   a.nwg = (a.nblocks + G::NB - 1) / G::NB;
   a.per = (a.nwg + 7) / 8;
   if (q) {

@@ -345,9 +345,10 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
       tot += prod3(p->lv[s - 1].nb);
     }
     p->ws.tol_off[c->L + 1] = tot;
-    // tau, Delta, 1/Delta per local-level block; tau_global; coarsest Delta tables (M == 0)
     const int64_t nlastb = c->L > 0 ? prod3(p->lv[c->L - 1].nb) : 0;
-    BM_HIP(hipMalloc(&p->ws.tolbuf, size_t(3 * tot + 8 + 2 * nlastb + 8) * sizeof(double)));
+    // propagated taus, Delta, 1/Delta per block; tau_global; coarsest-value
+    // Delta and 1/Delta; then the 27-class Delta and 1/Delta tables
+    BM_HIP(hipMalloc(&p->ws.tolbuf, size_t(3 * tot + 8 + 2 * nlastb + 8 + 54 * (tot + nlastb)) * sizeof(double)));
     BM_HIP(hipMalloc(&p->ws.boxbuf, size_t(kMaxBoxes) * 7 * sizeof(double)));
     BM_HIP(hipHostMalloc(&p->ws.boxhost, size_t(kMaxBoxes) * 7 * sizeof(double), hipHostMallocDefault));
     BM_HIP(hipMalloc(&p->ws.qparam, size_t(4 * (p->nlev + 2)) * sizeof(double)));

@@ -162,6 +162,38 @@ __global__ void k_block_delta(const double* tau, int64_t n, double kappa, double
   }
 }
 
+// Per block and per class of node position (27 classes: first face,
+// interior, last face along z, y and x) the smallest Delta and the largest
+// 1/Delta over the blocks that contain a node of that class: the block
+// itself plus its neighbour across each face the class lies on.
+__global__ void k_class_tables(const double* del, const double* inv, int64_t nb0, int64_t nb1, int64_t nb2,
+                               double* cdel, double* cinv) {
+  const int64_t tot = nb0 * nb1 * nb2 * 27;
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < tot; k += int64_t(gridDim.x) * NT) {
+    const int64_t blk = k / 27;
+    const int c = int(k - blk * 27);
+    const int cls[3] = {c / 9, (c / 3) % 3, c % 3};
+    const int64_t bx = blk % nb2, t = blk / nb2;
+    const int64_t b[3] = {t / nb1, t % nb1, bx};
+    const int64_t nb[3] = {nb0, nb1, nb2};
+    int64_t lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = (cls[d] == 0 && b[d] > 0) ? b[d] - 1 : b[d];
+      hi[d] = (cls[d] == 2 && b[d] + 1 < nb[d]) ? b[d] + 1 : b[d];
+    }
+    double dm = INFINITY, im = 0.0;
+    for (int64_t z = lo[0]; z <= hi[0]; ++z)
+      for (int64_t y = lo[1]; y <= hi[1]; ++y)
+        for (int64_t x = lo[2]; x <= hi[2]; ++x) {
+          const int64_t i = (z * nb1 + y) * nb2 + x;
+          dm = fmin(dm, del[i]);
+          im = fmax(im, inv[i]);
+        }
+    cdel[k] = dm;
+    cinv[k] = im;
+  }
+}
+
 // scalar Delta for the global levels and the coarsest values from tau_global
 struct ScalarArgs {
   const double* tau_global;
@@ -404,6 +436,8 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   double* bdel = p.ws.tolbuf + tot;
   double* binv = p.ws.tolbuf + 2 * tot;
   double* tg = p.ws.tolbuf + 3 * tot;    // tau_global
+  const int64_t nlastb = p.L > 0 ? prod3(p.lv[p.L - 1].nb) : 0;
+  double* cls = tg + 8 + 2 * nlastb + 8;  // 27-class tables: level s at 54 tol_off[s], coarsest at 54 tot
   // level-1 taus are the caller's map; deeper local levels live in tolbuf
   auto taus = [&](int s) -> const double* { return s == 1 ? block_tol : tau + p.ws.tol_off[s]; };
   if (p.L > 0) {
@@ -424,6 +458,11 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       a.lv[s - 1].del = bdel + off;
       a.lv[s - 1].inv = binv + off;
       for (int d = 0; d < 3; ++d) a.lv[s - 1].nb[d] = p.lv[s - 1].nb[d];
+      double* cd = cls + 54 * off;
+      hipLaunchKernelGGL(k_class_tables, dim3(grid_for(27 * nbs)), dim3(NT), 0, st, bdel + off, binv + off,
+                         p.lv[s - 1].nb[0], p.lv[s - 1].nb[1], p.lv[s - 1].nb[2], cd, cd + 27 * nbs);
+      a.lv[s - 1].cdel = cd;
+      a.lv[s - 1].cinv = cd + 27 * nbs;
     }
     const int64_t nlast = prod3(p.lv[p.L - 1].nb);
     if (p.M == 0) {
@@ -435,6 +474,11 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       a.lv[kCoarseSlotHost].del = cdel;
       a.lv[kCoarseSlotHost].inv = cinv;
       for (int d = 0; d < 3; ++d) a.lv[kCoarseSlotHost].nb[d] = p.lv[p.L - 1].nb[d];
+      double* cd = cls + 54 * tot;
+      hipLaunchKernelGGL(k_class_tables, dim3(grid_for(27 * nlast)), dim3(NT), 0, st, cdel, cinv,
+                         p.lv[p.L - 1].nb[0], p.lv[p.L - 1].nb[1], p.lv[p.L - 1].nb[2], cd, cd + 27 * nlast);
+      a.lv[kCoarseSlotHost].cdel = cd;
+      a.lv[kCoarseSlotHost].cinv = cd + 27 * nlast;
     }
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
     hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, tg);
