@@ -231,6 +231,41 @@ bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg);
  * buffer written by bm_compress.  Synchronous.  Errors: BM_ECORRUPT. */
 bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t stream);
 
+/* ---- many fields (the paper's batched multi-field workloads, Sec. V) ------- */
+
+/* A batch of independent fields sharing dtype and block size (each its own
+ * dims and L, M).  The fused pipeline of all fields runs as one launch per
+ * stage of the quantizer-table preparation, one persistent launch per block
+ * level covering the blocks of every field that has that level, and each
+ * field's global levels.  With use_graph the sequence is captured once in a
+ * HIP graph (per set of bound pointers) and replayed; use_graph needs a
+ * stream other than the null stream.  The batch owns one plan per field
+ * (bm_batch_plan borrows it: coefficient shapes, tolerance maps); a batch is
+ * used from one stream at a time.  Errors: BM_EINVAL (mixed dtype or block
+ * size, null pointers), BM_ENOMEM. */
+typedef struct bm_batch_s* bm_batch;
+bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out);
+bm_status bm_batch_destroy(bm_batch batch);
+bm_status bm_batch_plan(bm_batch batch, int field, bm_plan* out);
+
+/* codes[f] = the fused decompose + ROI quantize of x[f] with block_tol[f]
+ * (arrays of nfields device pointers; layouts as bm_decompose_quantize).
+ * Asynchronous, unless n_overflow is non-null: then the call waits and
+ * stores the number of fields whose codes did not fit in 32 bits. */
+bm_status bm_batch_decompose_quantize(bm_batch batch, const void* const* x, const double* const* block_tol,
+                                      int32_t* const* codes, int use_graph, int* n_overflow, hipStream_t stream);
+
+/* x[f] = the fused dequantize + recompose of codes[f].  Asynchronous. */
+bm_status bm_batch_dequantize_recompose(bm_batch batch, const int32_t* const* codes, const double* const* block_tol,
+                                        void* const* x, int use_graph, hipStream_t stream);
+
+/* bm_compress of every field: out[f] (host) receives field f's container
+ * (capacity[f] bytes available, out_bytes[f] written or needed); a field
+ * whose codes overflow is stored raw.  Synchronous.  BM_ECAPACITY if any
+ * buffer is too small (out_bytes then holds every needed size). */
+bm_status bm_batch_compress(bm_batch batch, const void* const* x, const double* const* block_tol, void* const* out,
+                            const size_t* capacity, size_t* out_bytes, int use_graph, hipStream_t stream);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 
 /* Per-level timing.  bm_timing(plan, 1) resets the counters and makes every

@@ -55,6 +55,13 @@ _SIGS = {
     "bm_decompress": [P, C.c_size_t, P, P],
     "bm_decompose_quantize": [P, P, P, P, C.POINTER(BMQStats), P],
     "bm_dequantize_recompose": [P, P, P, P, P],
+    "bm_batch_create": [C.c_int, C.POINTER(BMConfig), C.POINTER(P)],
+    "bm_batch_destroy": [P],
+    "bm_batch_plan": [P, C.c_int, C.POINTER(P)],
+    "bm_batch_decompose_quantize": [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.c_int, C.POINTER(C.c_int), P],
+    "bm_batch_dequantize_recompose": [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.c_int, P],
+    "bm_batch_compress": [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(C.c_size_t),
+                          C.POINTER(C.c_size_t), C.c_int, P],
     "bm_timing": [P, C.c_int],
     "bm_timing_get": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)],
 }

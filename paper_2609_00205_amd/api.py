@@ -57,6 +57,26 @@ class Plan:
         with torch.cuda.device(self.device):
             call("bm_plan_create", C.byref(cfg), C.byref(h))
         self._h = h
+        self._owned = True
+        self._query()
+
+    @classmethod
+    def _borrow(cls, handle: C.c_void_p, cfg: BMConfig, device) -> "Plan":
+        """A view of a plan owned elsewhere (a field of a Batch)."""
+        self = cls.__new__(cls)
+        self.shape = tuple(int(v) for v in cfg.dims)
+        self.dtype = _TD[cfg.dtype]
+        self.block, self.L, self.M = cfg.block, cfg.L, cfg.M
+        self.eta = cfg.eta
+        self.device = device
+        self._cfg = cfg
+        self._h = handle
+        self._owned = False
+        self._query()
+        return self
+
+    def _query(self):
+        h, L, M = self._h, self.L, self.M
         pd = (C.c_int64 * 3)()
         call("bm_coeff_shape", h, pd)
         self.coeff_shape = tuple(pd)
@@ -69,7 +89,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and getattr(self, "_owned", False):
             try:
                 _lib.lib().bm_plan_destroy(h)
             except Exception:
@@ -261,3 +281,120 @@ def parse_huffman(buf: bytes) -> dict:
     oval = np.frombuffer(buf, np.int32, nout, o)
     return {"magic": magic, "n": n, "nchunks": nch, "lengths": lengths, "offsets": offsets, "words": words,
             "outlier_index": oidx, "outlier_value": oval}
+
+
+def max_block_levels(shape: Sequence[int], block: int) -> int:
+    """The most block levels a shape tiles without padding (at least 1)."""
+    L = 1
+    while all(((n - 1) >> L) >= block - 1 and (n - 1) % ((block - 1) << L) == 0 for n in shape):
+        L += 1
+    return L
+
+
+class Batch:
+    """Many fields of one dtype and block size through the fused pipeline in
+    few launches (one persistent launch per block level for all fields),
+    optionally captured once in a HIP graph and replayed.
+
+    L: per-field block levels (default: the most each shape tiles without
+    padding); M: global levels (int or per field).
+    """
+
+    def __init__(self, shapes: Sequence[Sequence[int]], dtype=torch.float32, block: int = 17, L=None, M=0,
+                 pad_mode: str = "clamp", eta: Optional[float] = None, device=None):
+        shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        nf = len(shapes)
+        Ls = [max_block_levels(sh, block) for sh in shapes] if L is None else (
+            [int(L)] * nf if isinstance(L, int) else [int(v) for v in L])
+        Ms = [int(M)] * nf if isinstance(M, int) else [int(v) for v in M]
+        self.dtype = dtype
+        self.eta = DEFAULT_ETA[dtype] if eta is None else float(eta)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        cfgs = (BMConfig * nf)()
+        for i, sh in enumerate(shapes):
+            cfgs[i] = BMConfig(3, (C.c_int64 * 3)(*sh), _DT[dtype], block, Ls[i], Ms[i],
+                               1 if pad_mode == "zero" else 0, self.eta)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            call("bm_batch_create", nf, cfgs, C.byref(h))
+        self._h = h
+        self._cfgs = cfgs
+        self.plans = []
+        for i in range(nf):
+            ph = C.c_void_p()
+            call("bm_batch_plan", h, i, C.byref(ph))
+            self.plans.append(Plan._borrow(ph, cfgs[i], self.device))
+        self._graph_stream = None
+
+    def __len__(self):
+        return len(self.plans)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.lib().bm_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @staticmethod
+    def _ptrs(ts) -> "C.Array":
+        return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def _run(self, fn, use_graph: bool, stream):
+        """Graph capture needs a stream other than the null stream: use a side
+        stream ordered after the caller's."""
+        cur = stream if stream is not None else torch.cuda.current_stream()
+        if not use_graph or cur.cuda_stream != 0:
+            return fn(C.c_void_p(cur.cuda_stream))
+        if self._graph_stream is None:
+            self._graph_stream = torch.cuda.Stream()
+        side = self._graph_stream
+        side.wait_stream(cur)
+        r = fn(C.c_void_p(side.cuda_stream))
+        cur.wait_stream(side)
+        return r
+
+    def decompose_quantize(self, xs, block_tols, codes=None, use_graph: bool = False, check: bool = False,
+                           stream=None):
+        """codes[f] = fused decompose + ROI quantize of xs[f]; with check, the
+        number of fields whose codes overflowed int32 is returned as well."""
+        for p, x, t in zip(self.plans, xs, block_tols):
+            _need(x, p.dtype, p.shape, "x")
+            _need(t, torch.float64, p.block_grid, "block_tol")
+        if codes is None:
+            codes = [torch.empty(p.coeff_shape, dtype=torch.int32, device=x.device) for p, x in zip(self.plans, xs)]
+        for p, c in zip(self.plans, codes):
+            _need(c, torch.int32, p.coeff_shape, "codes")
+        nbad = C.c_int(0)
+        self._run(lambda st: call("bm_batch_decompose_quantize", self._h, self._ptrs(xs), self._ptrs(block_tols),
+                                  self._ptrs(codes), int(use_graph), C.byref(nbad) if check else None, st),
+                  use_graph, stream)
+        return (codes, nbad.value) if check else codes
+
+    def dequantize_recompose(self, codes, block_tols, outs=None, use_graph: bool = False, stream=None):
+        for p, c, t in zip(self.plans, codes, block_tols):
+            _need(c, torch.int32, p.coeff_shape, "codes")
+            _need(t, torch.float64, p.block_grid, "block_tol")
+        if outs is None:
+            outs = [torch.empty(p.shape, dtype=p.dtype, device=c.device) for p, c in zip(self.plans, codes)]
+        for p, o in zip(self.plans, outs):
+            _need(o, p.dtype, p.shape, "out")
+        self._run(lambda st: call("bm_batch_dequantize_recompose", self._h, self._ptrs(codes),
+                                  self._ptrs(block_tols), self._ptrs(outs), int(use_graph), st), use_graph, stream)
+        return outs
+
+    def compress(self, xs, block_tols, use_graph: bool = False, stream=None) -> list:
+        nf = len(self.plans)
+        for p, x, t in zip(self.plans, xs, block_tols):
+            _need(x, p.dtype, p.shape, "x")
+            _need(t, torch.float64, p.block_grid, "block_tol")
+        cap = (C.c_size_t * nf)(*[64 + int(x.numel()) * x.element_size() * 2 + 8 * int(t.numel()) + (1 << 20)
+                                  for x, t in zip(xs, block_tols)])
+        bufs = [C.create_string_buffer(int(c)) for c in cap]
+        outp = (C.c_void_p * nf)(*[C.cast(b, C.c_void_p).value for b in bufs])
+        got = (C.c_size_t * nf)()
+        self._run(lambda st: call("bm_batch_compress", self._h, self._ptrs(xs), self._ptrs(block_tols), outp, cap,
+                                  got, int(use_graph), st), use_graph, stream)
+        return [b.raw[: got[i]] for i, b in enumerate(bufs)]

@@ -79,12 +79,6 @@ struct CHeader {
 };
 constexpr uint32_t kMagic = 0x44474D42u;   // "BMGD"
 
-void ensure_pipeline_buffers(bm_plan_s& p) {
-  const size_t n = size_t(p.pdims[0]) * p.pdims[1] * p.pdims[2];
-  if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, n * p.esize));
-  if (!p.ws.codes) BM_HIP(hipMalloc(&p.ws.codes, n * sizeof(int32_t)));
-}
-
 bm_config header_config(const CHeader& h) {
   bm_config c{};
   c.ndim = 3;
@@ -116,6 +110,70 @@ CHeader parse(const void* in, size_t in_bytes) {
 }
 
 }  // namespace
+
+namespace bm {
+
+void ensure_pipeline_buffers(bm_plan_s& p) {
+  const size_t n = size_t(p.pdims[0]) * p.pdims[1] * p.pdims[2];
+  if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, n * p.esize));
+  if (!p.ws.codes) BM_HIP(hipMalloc(&p.ws.codes, n * sizeof(int32_t)));
+}
+
+void check_block_tol(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+  const int64_t ntol = p.nb1[0] * p.nb1[1] * p.nb1[2];
+  std::vector<double> tol(ntol);
+  BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  for (double t : tol)
+    if (!(t > 0) || !std::isfinite(t)) fail(BM_ENONFINITE, "block tolerances must be positive and finite");
+}
+
+bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine, void* out,
+                     size_t capacity, size_t* needed, hipStream_t st) {
+  const int64_t npad = p.pdims[0] * p.pdims[1] * p.pdims[2];
+  const int64_t nlog = p.dims[0] * p.dims[1] * p.dims[2];
+  const int64_t ntol = p.nb1[0] * p.nb1[1] * p.nb1[2];
+  std::vector<double> tol(ntol);
+  BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
+  std::vector<uint8_t> huff;
+  if (!too_fine) huffman_encode(static_cast<const int32_t*>(p.ws.codes), npad, huff, st);
+  BM_HIP(hipStreamSynchronize(st));
+  CHeader h{};
+  h.magic = kMagic;
+  h.version = 1;
+  h.dtype = p.cfg.dtype;
+  h.block = p.cfg.block;
+  h.L = p.L;
+  h.M = p.M;
+  h.pad_mode = p.cfg.pad_mode;
+  h.ndim = 3;
+  for (int a = 0; a < 3; ++a) h.dims[a] = p.dims[a];
+  h.eta = p.cfg.eta;
+  h.ntol = ntol;
+  const size_t coded = size_t(ntol) * 8 + huff.size();
+  const size_t raw = size_t(nlog) * p.esize;
+  h.flags = (too_fine || coded >= raw) ? 1u : 0u;
+  h.payload = h.flags ? raw : coded;
+  const size_t total = sizeof(CHeader) + size_t(h.payload);
+  *needed = total;
+  if (!out || capacity < total) return false;
+  uint8_t* o = static_cast<uint8_t*>(out) + sizeof(CHeader);
+  if (h.flags) {
+    BM_HIP(hipMemcpyAsync(o, x, raw, hipMemcpyDeviceToHost, st));
+    BM_HIP(hipStreamSynchronize(st));
+  } else {
+    std::memcpy(o, tol.data(), size_t(ntol) * 8);
+    std::memcpy(o + size_t(ntol) * 8, huff.data(), huff.size());
+  }
+  h.crc = 0;
+  uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
+  c = crc32(o, size_t(h.payload), c);
+  h.crc = c;
+  std::memcpy(out, &h, sizeof(h));
+  return true;
+}
+
+}  // namespace bm
 
 extern "C" {
 
@@ -258,57 +316,90 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
   return guarded([&] {
     need(p && x && block_tol && out_bytes, "null argument");
     check_device(p);
-    ensure_pipeline_buffers(*p);
-    const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];
-    const int64_t nlog = p->dims[0] * p->dims[1] * p->dims[2];
-    const int64_t ntol = p->nb1[0] * p->nb1[1] * p->nb1[2];
-    std::vector<double> tol(ntol);
-    BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
-    BM_HIP(hipStreamSynchronize(st));
-    for (double t : tol)
-      if (!(t > 0) || !std::isfinite(t)) bm::fail(BM_ENONFINITE, "block tolerances must be positive and finite");
-    bm_qstats qs;
+    bm::ensure_pipeline_buffers(*p);
     bool too_fine = false;   // codes beyond 32 bits: store the raw data
+    bm::check_block_tol(*p, block_tol, st);
     try {
+      bm_qstats qs;
       bm::decompose_quantize(*p, x, block_tol, static_cast<int32_t*>(p->ws.codes), &qs, st);
     } catch (const bm::Error& e) {
       if (e.code != BM_ERANGE) throw;
       too_fine = true;
     }
-    std::vector<uint8_t> huff;
-    if (!too_fine) bm::huffman_encode(static_cast<const int32_t*>(p->ws.codes), npad, huff, st);
-    CHeader h{};
-    h.magic = kMagic;
-    h.version = 1;
-    h.dtype = p->cfg.dtype;
-    h.block = p->cfg.block;
-    h.L = p->L;
-    h.M = p->M;
-    h.pad_mode = p->cfg.pad_mode;
-    h.ndim = 3;
-    for (int a = 0; a < 3; ++a) h.dims[a] = p->dims[a];
-    h.eta = p->cfg.eta;
-    h.ntol = ntol;
-    const size_t coded = size_t(ntol) * 8 + huff.size();
-    const size_t raw = size_t(nlog) * p->esize;
-    h.flags = (too_fine || coded >= raw) ? 1u : 0u;
-    h.payload = h.flags ? raw : coded;
-    const size_t total = sizeof(CHeader) + size_t(h.payload);
-    *out_bytes = total;
-    if (!out || capacity < total) bm::fail(BM_ECAPACITY, "output buffer too small");
-    uint8_t* o = static_cast<uint8_t*>(out) + sizeof(CHeader);
-    if (h.flags) {
-      BM_HIP(hipMemcpyAsync(o, x, raw, hipMemcpyDeviceToHost, st));
-      BM_HIP(hipStreamSynchronize(st));
-    } else {
-      std::memcpy(o, tol.data(), size_t(ntol) * 8);
-      std::memcpy(o + size_t(ntol) * 8, huff.data(), huff.size());
+    if (!bm::write_container(*p, x, block_tol, too_fine, out, capacity, out_bytes, st))
+      bm::fail(BM_ECAPACITY, "output buffer too small");
+  });
+}
+
+bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
+  return guarded([&] {
+    need(cfgs && out && nfields > 0, "null argument or empty batch");
+    *out = bm::batch_build(nfields, cfgs);
+  });
+}
+
+bm_status bm_batch_destroy(bm_batch b) {
+  return guarded([&] { bm::batch_free(b); });
+}
+
+bm_status bm_batch_plan(bm_batch b, int field, bm_plan* out) {
+  return guarded([&] {
+    need(b && out, "null argument");
+    need(field >= 0 && field < bm::batch_size(*b), "field index out of range");
+    *out = bm::batch_plan(*b, field);
+  });
+}
+
+bm_status bm_batch_decompose_quantize(bm_batch b, const void* const* x, const double* const* block_tol,
+                                      int32_t* const* codes, int use_graph, int* n_overflow, hipStream_t st) {
+  return guarded([&] {
+    need(b && x && block_tol && codes, "null argument");
+    for (int f = 0; f < bm::batch_size(*b); ++f) {
+      need(x[f] && block_tol[f] && codes[f], "null field pointer");
+      check_device(bm::batch_plan(*b, f));
     }
-    h.crc = 0;
-    uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
-    c = crc32(o, size_t(h.payload), c);
-    h.crc = c;
-    std::memcpy(out, &h, sizeof(h));
+    bm::batch_decompose_quantize(*b, x, block_tol, codes, use_graph != 0, st);
+    if (n_overflow) {
+      std::vector<int> bad;
+      *n_overflow = bm::batch_overflows(*b, bad, st);
+    }
+  });
+}
+
+bm_status bm_batch_dequantize_recompose(bm_batch b, const int32_t* const* codes, const double* const* block_tol,
+                                        void* const* x, int use_graph, hipStream_t st) {
+  return guarded([&] {
+    need(b && x && block_tol && codes, "null argument");
+    for (int f = 0; f < bm::batch_size(*b); ++f) {
+      need(x[f] && block_tol[f] && codes[f], "null field pointer");
+      check_device(bm::batch_plan(*b, f));
+    }
+    bm::batch_dequantize_recompose(*b, codes, block_tol, x, use_graph != 0, st);
+  });
+}
+
+bm_status bm_batch_compress(bm_batch b, const void* const* x, const double* const* block_tol, void* const* out,
+                            const size_t* capacity, size_t* out_bytes, int use_graph, hipStream_t st) {
+  return guarded([&] {
+    need(b && x && block_tol && out && capacity && out_bytes, "null argument");
+    const int nf = bm::batch_size(*b);
+    std::vector<int32_t*> codes(nf);
+    for (int f = 0; f < nf; ++f) {
+      need(x[f] && block_tol[f], "null field pointer");
+      bm_plan_s& p = *bm::batch_plan(*b, f);
+      check_device(&p);
+      bm::check_block_tol(p, block_tol[f], st);
+      bm::ensure_pipeline_buffers(p);
+      codes[f] = static_cast<int32_t*>(p.ws.codes);
+    }
+    bm::batch_decompose_quantize(*b, x, block_tol, codes.data(), use_graph != 0, st);
+    std::vector<int> bad;
+    bm::batch_overflows(*b, bad, st);
+    bool short_buf = false;
+    for (int f = 0; f < nf; ++f)
+      if (!bm::write_container(*bm::batch_plan(*b, f), x[f], block_tol[f], bad[f] != 0, out[f], capacity[f], &out_bytes[f], st))
+        short_buf = true;
+    if (short_buf) bm::fail(BM_ECAPACITY, "an output buffer is too small (out_bytes holds the sizes needed)");
   });
 }
 
@@ -343,7 +434,7 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
     }
     const int64_t ntol = p->nb1[0] * p->nb1[1] * p->nb1[2];
     if (h.ntol != ntol || h.payload < uint64_t(ntol) * 8) bm::fail(BM_ECORRUPT, "tolerance map size mismatch");
-    ensure_pipeline_buffers(*p);
+    bm::ensure_pipeline_buffers(*p);
     BM_HIP(hipMalloc(&g.d, size_t(ntol) * sizeof(double)));
     BM_HIP(hipMemcpyAsync(g.d, pl, size_t(ntol) * 8, hipMemcpyHostToDevice, st));
     const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];

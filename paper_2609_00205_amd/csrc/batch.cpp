@@ -1,0 +1,265 @@
+// Many independent fields of one dtype and block size, in few launches.
+//
+// The fused pipeline of every field (decompose + ROI quantize, or dequantize
+// + recompose) is issued as: one launch per stage of the quantizer-table
+// preparation for all fields, one persistent launch per block level
+// covering the blocks of every field that has that level, and the (small)
+// global levels of each field.  The whole sequence can be captured once in
+// a HIP graph and replayed while the bound buffers stay the same.
+//
+// Per-field kernel arguments and task lists are built on the host and
+// uploaded into a device arena when the binding (the set of buffer
+// pointers) changes; capture and replay never copy from the host.
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+bm_plan_s* bm_plan_build(const bm_config* c);
+void bm_plan_free(bm_plan_s* p);
+
+namespace bm {
+namespace {
+
+constexpr int kMaxLev = 9;
+
+// one bound direction (decompose+quantize or dequantize+recompose)
+struct Bound {
+  std::vector<const void*> key;   // bound pointers, in order
+  std::vector<QPrep> q;
+  PrepStages stages;
+  const PrepField* fields = nullptr;
+  const void* args[kMaxLev] = {};  // per block level: packed kernel arguments
+  const int64_t* first[kMaxLev] = {};
+  int nf[kMaxLev] = {};
+  int64_t ntasks[kMaxLev] = {};
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  hipGraphExec_t graph = nullptr;
+  std::vector<const void*> x, tol, codes;   // as bound
+};
+
+void free_bound(Bound& b) {
+  if (b.graph) (void)hipGraphExecDestroy(b.graph);
+  if (b.arena) (void)hipFree(b.arena);
+  b = Bound{};
+}
+
+// host image of the arena, assembled with 16-byte alignment
+struct Image {
+  std::vector<uint8_t> bytes;
+  size_t put(const void* p, size_t n) {
+    const size_t off = (bytes.size() + 15) & ~size_t(15);
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, p, n);
+    return off;
+  }
+};
+
+}  // namespace
+}  // namespace bm
+
+struct bm_batch_s {
+  std::vector<bm_plan_s*> plans;
+  int block = 0, dtype = 0, Lmax = 0, device = 0;
+  bm::Bound dq, rq;
+};
+
+namespace bm {
+namespace {
+
+int64_t prod(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
+
+// Builds (or reuses) the binding of one direction: quantizer layout per
+// field, prep task lists, per-level kernel arguments, uploaded to the arena.
+void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double* const* tol, int32_t* const* codes,
+          hipStream_t st) {
+  const int nf = int(b.plans.size());
+  std::vector<const void*> key;
+  key.reserve(3 * nf);
+  for (int f = 0; f < nf; ++f) {
+    key.push_back(x[f]);
+    key.push_back(tol[f]);
+    key.push_back(codes[f]);
+  }
+  if (key == B.key && B.arena) return;
+  free_bound(B);
+  B.key = key;
+  Image im;
+  // quantizer tables
+  B.q.resize(nf);
+  std::vector<PrepField> pf(nf);
+  for (int f = 0; f < nf; ++f) {
+    B.q[f] = qprep_layout(*b.plans[f], tol[f]);
+    pf[f] = prep_field(*b.plans[f], tol[f], B.q[f]);
+  }
+  const size_t off_fields = im.put(pf.data(), pf.size() * sizeof(PrepField));
+  size_t off_prop[kMaxLev] = {}, off_tab[kMaxLev] = {};
+  for (int s = 0; s < kMaxLev; ++s) {
+    std::vector<int64_t> fp(nf + 1, 0), ft(nf + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+      const bm_plan_s& p = *b.plans[f];
+      const int64_t np = (s >= 1 && p.L > s) ? prod(p.lv[s].nb) : 0;                        // into level s+1
+      const int64_t nt = s >= 1 ? (p.L >= s ? 27 * prod(p.lv[s - 1].nb) : 0)
+                                : ((p.L > 0 && p.M == 0) ? 27 * prod(p.lv[p.L - 1].nb) : 0);  // coarsest values
+      fp[f + 1] = fp[f] + np;
+      ft[f + 1] = ft[f] + nt;
+    }
+    B.stages.prop_n[s] = fp[nf];
+    B.stages.tab_n[s] = ft[nf];
+    off_prop[s] = im.put(fp.data(), fp.size() * sizeof(int64_t));
+    off_tab[s] = im.put(ft.data(), ft.size() * sizeof(int64_t));
+  }
+  // block levels: arguments of the fields that have level s, in field order
+  size_t off_args[kMaxLev] = {}, off_first[kMaxLev] = {};
+  for (int s = 1; s <= b.Lmax; ++s) {
+    std::vector<uint8_t> args;
+    std::vector<int64_t> first(1, 0);
+    for (int f = 0; f < nf; ++f) {
+      bm_plan_s& p = *b.plans[f];
+      if (p.L < s) continue;
+      const size_t sz = block_args_size(p, dec);
+      args.resize(args.size() + sz);
+      uint8_t* dst = args.data() + args.size() - sz;
+      if (dec) {
+        const View3 src = s == 1 ? dense_view(const_cast<void*>(x[f]), p.dims) : dense_view(p.ws.grid[s - 1], p.lv[s - 1].n);
+        block_dec_args(p, s, src, s == 1, nullptr, p.ws.grid[s], codes[f], &B.q[f], dst);
+      } else {
+        void* out = s == 1 ? const_cast<void*>(x[f]) : p.ws.grid[s - 1];
+        block_rec_args(p, s, nullptr, p.ws.grid[s], out, s == 1, codes[f], &B.q[f], dst);
+      }
+      first.push_back(first.back() + block_groups(p, s));
+    }
+    B.nf[s] = int(first.size()) - 1;
+    B.ntasks[s] = first.back();
+    off_args[s] = im.put(args.data(), args.size());
+    off_first[s] = im.put(first.data(), first.size() * sizeof(int64_t));
+  }
+  B.arena_bytes = im.bytes.size();
+  BM_HIP(hipMalloc(&B.arena, B.arena_bytes));
+  BM_HIP(hipMemcpyAsync(B.arena, im.bytes.data(), B.arena_bytes, hipMemcpyHostToDevice, st));
+  BM_HIP(hipStreamSynchronize(st));
+  auto at = [&](size_t off) { return static_cast<const void*>(static_cast<const uint8_t*>(B.arena) + off); };
+  B.fields = static_cast<const PrepField*>(at(off_fields));
+  for (int s = 0; s < kMaxLev; ++s) {
+    B.stages.prop_first[s] = static_cast<const int64_t*>(at(off_prop[s]));
+    B.stages.tab_first[s] = static_cast<const int64_t*>(at(off_tab[s]));
+  }
+  for (int s = 1; s <= b.Lmax; ++s) {
+    B.args[s] = at(off_args[s]);
+    B.first[s] = static_cast<const int64_t*>(at(off_first[s]));
+  }
+  B.x.assign(x, x + nf);
+  B.tol.assign(tol, tol + nf);
+  B.codes.assign(codes, codes + nf);
+}
+
+void enqueue(bm_batch_s& b, Bound& B, bool dec, hipStream_t st) {
+  const int nf = int(b.plans.size());
+  launch_prep_batch(B.stages, B.fields, nf, st);
+  if (dec) {
+    for (int s = 1; s <= b.Lmax; ++s)
+      launch_block_batch(b.block, b.dtype, true, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+    for (int f = 0; f < nf; ++f)
+      decompose_quantize_global(*b.plans[f], B.x[f], static_cast<int32_t*>(const_cast<void*>(B.codes[f])), B.q[f], st);
+  } else {
+    for (int f = 0; f < nf; ++f)
+      dequantize_recompose_global(*b.plans[f], static_cast<const int32_t*>(B.codes[f]), B.q[f],
+                                  const_cast<void*>(B.x[f]), st);
+    for (int s = b.Lmax; s >= 1; --s)
+      launch_block_batch(b.block, b.dtype, false, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+  }
+}
+
+void run(bm_batch_s& b, Bound& B, bool dec, bool graph, hipStream_t st) {
+  if (graph && st == nullptr) fail(BM_EINVAL, "graph capture needs a stream other than the null stream");
+  if (!graph) {
+    enqueue(b, B, dec, st);
+    return;
+  }
+  if (!B.graph) {
+    hipGraph_t g = nullptr;
+    BM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    try {
+      enqueue(b, B, dec, st);
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    BM_HIP(hipStreamEndCapture(st, &g));
+    const hipError_t e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BM_HIP(e);
+  }
+  BM_HIP(hipGraphLaunch(B.graph, st));
+}
+
+}  // namespace
+
+bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
+  if (nfields <= 0 || !cfgs) fail(BM_EINVAL, "empty batch");
+  auto* b = new bm_batch_s();
+  try {
+    BM_HIP(hipGetDevice(&b->device));
+    for (int f = 0; f < nfields; ++f) {
+      if (f > 0 && (cfgs[f].dtype != cfgs[0].dtype || cfgs[f].block != cfgs[0].block))
+        fail(BM_EINVAL, "all fields of a batch share dtype and block size");
+      b->plans.push_back(bm_plan_build(&cfgs[f]));
+      b->Lmax = std::max(b->Lmax, b->plans.back()->L);
+    }
+    b->block = cfgs[0].block;
+    b->dtype = cfgs[0].dtype;
+    if (b->Lmax >= kMaxLev) fail(BM_EUNSUPPORTED, "too many block levels");
+  } catch (...) {
+    for (auto* p : b->plans) bm_plan_free(p);
+    delete b;
+    throw;
+  }
+  return b;
+}
+
+void batch_free(bm_batch_s* b) {
+  if (!b) return;
+  free_bound(b->dq);
+  free_bound(b->rq);
+  for (auto* p : b->plans) bm_plan_free(p);
+  delete b;
+}
+
+int batch_size(const bm_batch_s& b) { return int(b.plans.size()); }
+
+bm_plan_s* batch_plan(bm_batch_s& b, int field) { return b.plans[field]; }
+
+void batch_decompose_quantize(bm_batch_s& b, const void* const* x, const double* const* tol, int32_t* const* codes,
+                              bool graph, hipStream_t st) {
+  bind(b, b.dq, true, x, tol, codes, st);
+  run(b, b.dq, true, graph, st);
+}
+
+void batch_dequantize_recompose(bm_batch_s& b, const int32_t* const* codes, const double* const* tol, void* const* x,
+                                bool graph, hipStream_t st) {
+  std::vector<const void*> xs(x, x + b.plans.size());
+  bind(b, b.rq, false, xs.data(), tol, const_cast<int32_t* const*>(codes), st);
+  run(b, b.rq, false, graph, st);
+}
+
+int batch_overflows(bm_batch_s& b, std::vector<int>& bad, hipStream_t st) {
+  const int nf = int(b.plans.size());
+  std::vector<int64_t> flags(nf, 0);
+  for (int f = 0; f < nf; ++f)
+    BM_HIP(hipMemcpyAsync(&flags[f], b.plans[f]->ws.counters + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  bad.assign(nf, 0);
+  int n = 0;
+  for (int f = 0; f < nf; ++f)
+    if (flags[f]) {
+      bad[f] = 1;
+      ++n;
+    }
+  return n;
+}
+
+}  // namespace bm

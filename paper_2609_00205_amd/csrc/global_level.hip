@@ -575,37 +575,42 @@ void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
 // quantization codes directly, global levels quantize their details as the
 // detail stencil produces them, and the coarsest values last.  The codes are
 // identical to bm_decompose followed by bm_quantize_roi.
-void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
-                        hipStream_t st) {
-  const QPrep q = quant_prepare(p, block_tol, st);
-  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, q.flag);
-  const View3 xv = dense_view(const_cast<void*>(x), p.dims);
-  for (int s = 1; s <= p.nlev; ++s) {
+void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, const QPrep& q, hipStream_t st) {
+  for (int s = p.L + 1; s <= p.nlev; ++s) {
     const Level& L = p.lv[s - 1];
     TimedScope ts(p, 2 * (s - 1), st);
-    if (L.local) {
-      const View3 src = s == 1 ? xv : dense_view(p.ws.grid[s - 1], L.n);
-      local_decompose_q(p, s, src, s == 1, codes, p.ws.grid[s], q, st);
+    const void* u;
+    if (s == 1) {
+      pad_input(p, x, p.ws.grid[0], p.cfg.pad_mode == 1, st);
+      u = p.ws.grid[0];
     } else {
-      const void* u;
-      if (s == 1) {
-        pad_input(p, x, p.ws.grid[0], p.cfg.pad_mode == 1, st);
-        u = p.ws.grid[0];
-      } else {
-        u = p.ws.grid[s - 1];
-      }
-      if (p.cfg.dtype == BM_F32)
-        launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
-      else
-        launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
-      apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
+      u = p.ws.grid[s - 1];
     }
+    if (p.cfg.dtype == BM_F32)
+      launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+    else
+      launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+    apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
   }
   if (p.M > 0 || p.L == 0) {
     const Level& last = p.lv[p.nlev - 1];
     const View3 cv = coarsest_view(p, codes);
     qcopy(p, dense_view(p.ws.grid[p.nlev], last.m), nullptr, cv, codes, q.q + 2 * p.nlev + 1, q.flag, st);
   }
+}
+
+void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
+                        hipStream_t st) {
+  const QPrep q = quant_prepare(p, block_tol, st);
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, q.flag);
+  const View3 xv = dense_view(const_cast<void*>(x), p.dims);
+  for (int s = 1; s <= p.L; ++s) {
+    const Level& L = p.lv[s - 1];
+    TimedScope ts(p, 2 * (s - 1), st);
+    const View3 src = s == 1 ? xv : dense_view(p.ws.grid[s - 1], L.n);
+    local_decompose_q(p, s, src, s == 1, codes, p.ws.grid[s], q, st);
+  }
+  decompose_quantize_global(p, x, codes, q, st);
   if (stats) {
     int64_t f = 0;
     BM_HIP(hipMemcpyAsync(&f, q.flag, sizeof(f), hipMemcpyDeviceToHost, st));
@@ -617,38 +622,41 @@ void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, in
   }
 }
 
-// Inverse of decompose_quantize: dequantize on load, then recompose.  Equal
-// to bm_dequantize followed by bm_recompose.
-void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st) {
-  const QPrep q = quant_prepare(p, block_tol, st);
+void dequantize_recompose_global(bm_plan_s& p, const int32_t* codes, const QPrep& q, void* x, hipStream_t st) {
   if (p.M > 0 || p.L == 0) {
     const Level& last = p.lv[p.nlev - 1];
     const View3 cv = coarsest_view(p, const_cast<int32_t*>(codes));
     qcopy(p, cv, codes, dense_view(p.ws.grid[p.nlev], last.m), nullptr, q.q + 2 * p.nlev, nullptr, st);
   }
-  for (int s = p.nlev; s >= 1; --s) {
+  for (int s = p.nlev; s > p.L; --s) {
     const Level& L = p.lv[s - 1];
     TimedScope ts(p, 2 * (s - 1) + 1, st);
-    if (L.local) {
-      void* out = s == 1 ? x : p.ws.grid[s - 1];
-      local_recompose_q(p, s, codes, p.ws.grid[s], out, s == 1, q, st);
-    } else {
-      const double* qdel = q.q + 2 * (s - 1);
-      apply_K3(p, s, level_view(p, s, const_cast<int32_t*>(codes)), true, p.ws.grid[s], p.ws.grid[s], st, codes,
-               qdel);
-      void* out = p.ws.grid[s - 1];
-      if (p.cfg.dtype == BM_F32)
-        launch_interp<float>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
-      else
-        launch_interp<double>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
-      if (s == 1) {
-        View3 src = dense_view(out, p.pdims);
-        src.n[0] = p.dims[0];
-        src.n[1] = p.dims[1];
-        src.n[2] = p.dims[2];
-        strided_copy(p.esize, src, dense_view(x, p.dims), st);
-      }
+    const double* qdel = q.q + 2 * (s - 1);
+    apply_K3(p, s, level_view(p, s, const_cast<int32_t*>(codes)), true, p.ws.grid[s], p.ws.grid[s], st, codes, qdel);
+    void* out = p.ws.grid[s - 1];
+    if (p.cfg.dtype == BM_F32)
+      launch_interp<float>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
+    else
+      launch_interp<double>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
+    if (s == 1) {
+      View3 src = dense_view(out, p.pdims);
+      src.n[0] = p.dims[0];
+      src.n[1] = p.dims[1];
+      src.n[2] = p.dims[2];
+      strided_copy(p.esize, src, dense_view(x, p.dims), st);
     }
+  }
+}
+
+// Inverse of decompose_quantize: dequantize on load, then recompose.  Equal
+// to bm_dequantize followed by bm_recompose.
+void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st) {
+  const QPrep q = quant_prepare(p, block_tol, st);
+  dequantize_recompose_global(p, codes, q, x, st);
+  for (int s = p.L; s >= 1; --s) {
+    TimedScope ts(p, 2 * (s - 1) + 1, st);
+    void* out = s == 1 ? x : p.ws.grid[s - 1];
+    local_recompose_q(p, s, codes, p.ws.grid[s], out, s == 1, q, st);
   }
 }
 

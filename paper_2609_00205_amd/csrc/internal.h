@@ -192,16 +192,59 @@ struct QPrep {
   int64_t* flag = nullptr;      // set to 1 when a code does not fit in int32
 };
 constexpr int kCoarseSlotHost = 8;
+// where a plan's quantizer tables live (host arithmetic, no launches)
+QPrep qprep_layout(bm_plan_s& p, const double* block_tol);
+// builds the tables on the device (stream-ordered) and returns their layout
 QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st);
+
+// The same preparation for many fields at once: one field's inputs...
+struct PrepField {
+  const double* tau[9];       // block taus of local level s at [s-1] (level 1: the caller's map)
+  int64_t nb[9][3];           // blocks per axis of local level s at [s-1]
+  double kap[9];              // kappa of local level s at [s-1]
+  double kapc;                // kappa of the coarsest values (M == 0)
+  QTab tab[9];                // output tables (layout of qprep_layout); [8]: coarsest values
+  double* tg;                 // tau_global
+  double* q;                  // scalar Delta, 1/Delta per level and for the coarsest values
+  double kq[26];              // kappa per level and for the coarsest values
+  int L, M, nlev;
+  int64_t* flag;              // overflow flag, cleared here
+};
+PrepField prep_field(bm_plan_s& p, const double* block_tol, const QPrep& q);
+// ...and the task lists of its launches: propagation into level s+1 (index
+// s), tables of level s (index s; index 0: coarsest values), each a device
+// prefix array over the fields (first[nf] = total tasks)
+struct PrepStages {
+  const int64_t* prop_first[9] = {};
+  int64_t prop_n[9] = {};
+  const int64_t* tab_first[9] = {};
+  int64_t tab_n[9] = {};
+};
+void launch_prep_batch(const PrepStages& g, const PrepField* F, int nf, hipStream_t st);
 
 // fused decompose + quantize and dequantize + recompose (codes in place)
 void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
                         hipStream_t st);
 void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st);
+// the global levels (s > L) and the coarsest values of the fused pipeline
+void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, const QPrep& q, hipStream_t st);
+void dequantize_recompose_global(bm_plan_s& p, const int32_t* codes, const QPrep& q, void* x, hipStream_t st);
 void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, int32_t* codes, void* coarse_out,
                        const QPrep& q, hipStream_t st);
 void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const void* coarse_in, void* out, bool last,
                        const QPrep& q, hipStream_t st);
+
+// many fields per launch (block levels): per-field kernel arguments are
+// built on the host (block_*_args writes block_args_size bytes), uploaded,
+// and one persistent launch covers block_groups(p_f, s) groups of every field
+int64_t block_groups(const bm_plan_s& p, int s);
+size_t block_args_size(const bm_plan_s& p, bool dec);
+void block_dec_args(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                    const QPrep* q, void* out);
+void block_rec_args(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* outp, bool last,
+                    const int32_t* codes, const QPrep* q, void* out);
+void launch_block_batch(int block, int dtype, bool dec, bool quant, const void* args, const int64_t* first, int nf,
+                        int64_t ntasks, hipStream_t st);
 
 // quantization
 void tolmap_from_boxes(bm_plan_s& p, const double* boxes, int nbox, double background, double* block_tol,
@@ -210,6 +253,27 @@ void tolmap_from_voxels(bm_plan_s& p, const double* voxel_tol, double* block_tol
 void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t* codes, bm_qstats* stats,
               hipStream_t st);
 void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* coeff, hipStream_t st);
+
+// compress path: lazily allocated code / coefficient buffers of a plan, the
+// tolerance-map check, and the container writer (false: capacity too small,
+// *needed holds the size)
+void ensure_pipeline_buffers(bm_plan_s& p);
+void check_block_tol(bm_plan_s& p, const double* block_tol, hipStream_t st);
+bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine, void* out, size_t capacity,
+                     size_t* needed, hipStream_t st);
+
+// batches of fields (one dtype and block size): build / free, the fused
+// pipeline both ways (graph: capture once per binding, then replay), and the
+// fields whose codes overflowed int32 (synchronizes)
+bm_batch_s* batch_build(int nfields, const bm_config* cfgs);
+void batch_free(bm_batch_s* b);
+int batch_size(const bm_batch_s& b);
+bm_plan_s* batch_plan(bm_batch_s& b, int field);
+void batch_decompose_quantize(bm_batch_s& b, const void* const* x, const double* const* tol, int32_t* const* codes,
+                              bool graph, hipStream_t st);
+void batch_dequantize_recompose(bm_batch_s& b, const int32_t* const* codes, const double* const* tol, void* const* x,
+                                bool graph, hipStream_t st);
+int batch_overflows(bm_batch_s& b, std::vector<int>& bad, hipStream_t st);
 
 // huffman (host buffers)
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);

@@ -19,6 +19,9 @@
 // coarse nodes is tridiag(1, 4, 1).  Small blocks are packed several to a
 // workgroup so wavefronts stay full.
 
+#include <algorithm>
+#include <cstring>
+
 #include "block.h"
 #include "internal.h"
 
@@ -158,13 +161,11 @@ __device__ inline int32_t quant(T c, double inv, bool skip, bool& bad) {
 template <typename T>
 constexpr int kWavesPerEU = sizeof(T) == 4 ? 8 : 4;
 
+// One workgroup's block group g (NB blocks) of a decomposition level.
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
+__device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
-  __shared__ T lds[NB * G::DEC_LDS];
-  const int64_t g = xcd_group(blockIdx.x, a.per);
-  if (g >= a.nwg) return;
   const int tid = threadIdx.x;
   const int bl = tid / BB;                           // block within the workgroup
   const int tb = tid - bl * BB;                      // column within the block
@@ -286,13 +287,11 @@ __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWav
   }
 }
 
+// One workgroup's block group g of a recomposition level.
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
+__device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
-  __shared__ T lds[NB * G::REC_LDS];
-  const int64_t g = xcd_group(blockIdx.x, a.per);
-  if (g >= a.nwg) return;
   const int tid = threadIdx.x;
   const int bl = tid / BB;
   const int tb = tid - bl * BB;
@@ -397,6 +396,59 @@ __global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
   }
 }
 
+template <typename T, int B, bool Q>
+__global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
+  __shared__ T lds[Geo<B>::NB * Geo<B>::DEC_LDS];
+  const int64_t g = xcd_group(blockIdx.x, a.per);
+  if (g >= a.nwg) return;
+  decompose_group<T, B, Q>(a, g, lds);
+}
+
+template <typename T, int B, bool Q>
+__global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
+  __shared__ T lds[Geo<B>::NB * Geo<B>::REC_LDS];
+  const int64_t g = xcd_group(blockIdx.x, a.per);
+  if (g >= a.nwg) return;
+  recompose_group<T, B, Q>(a, g, lds);
+}
+
+// Many fields in one persistent launch: task k is block group k - first[f]
+// of field f (first[] ascending, first[nf] = total); workgroups stride over
+// the tasks.
+__device__ inline int field_of(const int64_t* first, int nf, int64_t k) {
+  int lo = 0, hi = nf;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, int B, bool Q>
+__global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_batch_decompose(
+    const DecArgs<T>* fa, const int64_t* first, int nf, int64_t ntasks) {
+  __shared__ T lds[Geo<B>::NB * Geo<B>::DEC_LDS];
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = field_of(first, nf, k);
+    decompose_group<T, B, Q>(fa[f], k - first[f], lds);
+    __syncthreads();
+  }
+}
+
+template <typename T, int B, bool Q>
+__global__ __launch_bounds__(Geo<B>::NT) void k_batch_recompose(const RecArgs<T>* fa, const int64_t* first, int nf,
+                                                                int64_t ntasks) {
+  __shared__ T lds[Geo<B>::NB * Geo<B>::REC_LDS];
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = field_of(first, nf, k);
+    recompose_group<T, B, Q>(fa[f], k - first[f], lds);
+    __syncthreads();
+  }
+}
+
 // 32-bit z stride within one block column
 inline uint32_t column_stride(int64_t s, int B) {
   if (s * (B - 1) >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "grid planes too large for 32-bit column offsets");
@@ -404,8 +456,8 @@ inline uint32_t column_stride(int64_t s, int B) {
 }
 
 template <typename T, int B>
-void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
-                const QPrep* q, hipStream_t st) {
+DecArgs<T> dec_args(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                    const QPrep* q) {
   using G = Geo<B>;
   const Level& L = p.lv[s - 1];
   DecArgs<T> a{};
@@ -437,16 +489,25 @@ void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* c
     a.coarsest_here = (p.M == 0 && s == p.L) ? 1 : 0;
     if (a.coarsest_here) a.ctab = q->lv[kCoarseSlotHost];
     a.flag = q->flag;
-    hipLaunchKernelGGL((k_local_decompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_local_decompose<T, B, false>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
   }
+  return a;
+}
+
+template <typename T, int B>
+void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                const QPrep* q, hipStream_t st) {
+  using G = Geo<B>;
+  const DecArgs<T> a = dec_args<T, B>(p, s, src, first, coeff, cout, codes, q);
+  if (q)
+    hipLaunchKernelGGL((k_local_decompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_local_decompose<T, B, false>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
   BM_HIP(hipGetLastError());
 }
 
 template <typename T, int B>
-void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
-                const int32_t* codes, const QPrep* q, hipStream_t st) {
+RecArgs<T> rec_args(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
+                    const int32_t* codes, const QPrep* q) {
   using G = Geo<B>;
   const Level& L = p.lv[s - 1];
   RecArgs<T> a{};
@@ -479,9 +540,56 @@ void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, v
     a.tab = q->lv[s - 1];
     a.coarsest_here = (p.M == 0 && s == p.L) ? 1 : 0;
     if (a.coarsest_here) a.ctab = q->lv[kCoarseSlotHost];
+  }
+  return a;
+}
+
+template <typename T, int B>
+void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
+                const int32_t* codes, const QPrep* q, hipStream_t st) {
+  using G = Geo<B>;
+  const RecArgs<T> a = rec_args<T, B>(p, s, coeff, cin, out, last, codes, q);
+  if (q)
     hipLaunchKernelGGL((k_local_recompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
-  } else {
+  else
     hipLaunchKernelGGL((k_local_recompose<T, B, false>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
+  BM_HIP(hipGetLastError());
+}
+
+// workgroups of a persistent batched launch: as many as stay resident
+template <typename K>
+unsigned resident_grid(K kernel, int nt, int64_t ntasks) {
+  int dev = 0, per_cu = 0, cus = 0;
+  BM_HIP(hipGetDevice(&dev));
+  BM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0));
+  BM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t g = std::max<int64_t>(1, int64_t(per_cu) * cus);
+  return unsigned(std::min<int64_t>(g, ntasks));
+}
+
+template <typename T, int B>
+void launch_batch(bool dec, bool quant, const void* args, const int64_t* first, int nf, int64_t ntasks,
+                  hipStream_t st) {
+  using G = Geo<B>;
+  if (ntasks <= 0) return;
+  if (dec) {
+    const auto* fa = static_cast<const DecArgs<T>*>(args);
+    if (quant) {
+      auto k = k_batch_decompose<T, B, true>;
+      hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
+    } else {
+      auto k = k_batch_decompose<T, B, false>;
+      hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
+    }
+  } else {
+    const auto* fa = static_cast<const RecArgs<T>*>(args);
+    if (quant) {
+      auto k = k_batch_recompose<T, B, true>;
+      hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
+    } else {
+      auto k = k_batch_recompose<T, B, false>;
+      hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
+    }
   }
   BM_HIP(hipGetLastError());
 }
@@ -536,6 +644,58 @@ void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const vo
     dispatch_rec<9>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
   else
     dispatch_rec<17>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
+}
+
+int64_t block_groups(const bm_plan_s& p, int s) {
+  const int nbw = p.cfg.block <= 9 ? Geo<9>::NB : Geo<17>::NB;
+  const int64_t* nb = p.lv[s - 1].nb;
+  return (nb[0] * nb[1] * nb[2] + nbw - 1) / nbw;
+}
+
+size_t block_args_size(const bm_plan_s& p, bool dec) {
+  if (p.cfg.dtype == BM_F32) return dec ? sizeof(DecArgs<float>) : sizeof(RecArgs<float>);
+  return dec ? sizeof(DecArgs<double>) : sizeof(RecArgs<double>);
+}
+
+void block_dec_args(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                    const QPrep* q, void* out) {
+  if (p.cfg.dtype == BM_F32) {
+    const auto a = p.cfg.block == 9 ? dec_args<float, 9>(p, s, src, first, coeff, cout, codes, q)
+                                    : dec_args<float, 17>(p, s, src, first, coeff, cout, codes, q);
+    std::memcpy(out, &a, sizeof(a));
+  } else {
+    const auto a = p.cfg.block == 9 ? dec_args<double, 9>(p, s, src, first, coeff, cout, codes, q)
+                                    : dec_args<double, 17>(p, s, src, first, coeff, cout, codes, q);
+    std::memcpy(out, &a, sizeof(a));
+  }
+}
+
+void block_rec_args(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* outp, bool last,
+                    const int32_t* codes, const QPrep* q, void* out) {
+  if (p.cfg.dtype == BM_F32) {
+    const auto a = p.cfg.block == 9 ? rec_args<float, 9>(p, s, coeff, cin, outp, last, codes, q)
+                                    : rec_args<float, 17>(p, s, coeff, cin, outp, last, codes, q);
+    std::memcpy(out, &a, sizeof(a));
+  } else {
+    const auto a = p.cfg.block == 9 ? rec_args<double, 9>(p, s, coeff, cin, outp, last, codes, q)
+                                    : rec_args<double, 17>(p, s, coeff, cin, outp, last, codes, q);
+    std::memcpy(out, &a, sizeof(a));
+  }
+}
+
+void launch_block_batch(int block, int dtype, bool dec, bool quant, const void* args, const int64_t* first, int nf,
+                        int64_t ntasks, hipStream_t st) {
+  if (dtype == BM_F32) {
+    if (block == 9)
+      launch_batch<float, 9>(dec, quant, args, first, nf, ntasks, st);
+    else
+      launch_batch<float, 17>(dec, quant, args, first, nf, ntasks, st);
+  } else {
+    if (block == 9)
+      launch_batch<double, 9>(dec, quant, args, first, nf, ntasks, st);
+    else
+      launch_batch<double, 17>(dec, quant, args, first, nf, ntasks, st);
+  }
 }
 
 }  // namespace bm

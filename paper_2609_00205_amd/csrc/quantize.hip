@@ -425,19 +425,46 @@ int64_t prod3(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 }  // namespace
 
 // Build every per-level quantizer table on the device from the level-1 map.
-QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+QPrep qprep_layout(bm_plan_s& p, const double* block_tol) {
+  (void)block_tol;
   if (p.L > 8) fail(BM_EUNSUPPORTED, "more than 8 local levels");
   QPrep a{};
   a.flag = p.ws.counters + 2;
-  const double eta = p.cfg.eta;
-  const std::vector<double> w = level_weights(p);
   const int64_t tot = p.ws.tol_off[p.L + 1];
-  double* tau = p.ws.tolbuf;
   double* bdel = p.ws.tolbuf + tot;
   double* binv = p.ws.tolbuf + 2 * tot;
-  double* tg = p.ws.tolbuf + 3 * tot;    // tau_global
+  double* tg = p.ws.tolbuf + 3 * tot;     // tau_global
   const int64_t nlastb = p.L > 0 ? prod3(p.lv[p.L - 1].nb) : 0;
   double* cls = tg + 8 + 2 * nlastb + 8;  // 27-class tables: level s at 54 tol_off[s], coarsest at 54 tot
+  for (int s = 1; s <= p.L; ++s) {
+    const int64_t nbs = prod3(p.lv[s - 1].nb);
+    const int64_t off = p.ws.tol_off[s];
+    QTab& t = a.lv[s - 1];
+    t.del = bdel + off;
+    t.inv = binv + off;
+    t.cdel = cls + 54 * off;
+    t.cinv = cls + 54 * off + 27 * nbs;
+    for (int d = 0; d < 3; ++d) t.nb[d] = p.lv[s - 1].nb[d];
+  }
+  if (p.L > 0 && p.M == 0) {
+    // coarsest values (no gain), over the level-L blocks
+    QTab& t = a.lv[kCoarseSlotHost];
+    t.del = tg + 8;
+    t.inv = tg + 8 + nlastb;
+    t.cdel = cls + 54 * tot;
+    t.cinv = cls + 54 * tot + 27 * nlastb;
+    for (int d = 0; d < 3; ++d) t.nb[d] = p.lv[p.L - 1].nb[d];
+  }
+  a.q = p.ws.qparam;
+  return a;
+}
+
+QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+  const QPrep a = qprep_layout(p, block_tol);
+  const double eta = p.cfg.eta;
+  const std::vector<double> w = level_weights(p);
+  double* tau = p.ws.tolbuf;
+  double* tg = p.ws.tolbuf + 3 * p.ws.tol_off[p.L + 1];
   // level-1 taus are the caller's map; deeper local levels live in tolbuf
   auto taus = [&](int s) -> const double* { return s == 1 ? block_tol : tau + p.ws.tol_off[s]; };
   if (p.L > 0) {
@@ -449,38 +476,18 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       }
       hipLaunchKernelGGL(k_propagate, dim3(grid_for(prod3(pa.nn))), dim3(NT), 0, st, pa);
     }
-    for (int s = 1; s <= p.L; ++s) {
-      const double kap = (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain;
-      const int64_t nbs = prod3(p.lv[s - 1].nb);
-      const int64_t off = p.ws.tol_off[s];
-      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, taus(s), nbs, kap, bdel + off,
-                         binv + off);
-      a.lv[s - 1].del = bdel + off;
-      a.lv[s - 1].inv = binv + off;
-      for (int d = 0; d < 3; ++d) a.lv[s - 1].nb[d] = p.lv[s - 1].nb[d];
-      double* cd = cls + 54 * off;
-      hipLaunchKernelGGL(k_class_tables, dim3(grid_for(27 * nbs)), dim3(NT), 0, st, bdel + off, binv + off,
-                         p.lv[s - 1].nb[0], p.lv[s - 1].nb[1], p.lv[s - 1].nb[2], cd, cd + 27 * nbs);
-      a.lv[s - 1].cdel = cd;
-      a.lv[s - 1].cinv = cd + 27 * nbs;
-    }
-    const int64_t nlast = prod3(p.lv[p.L - 1].nb);
-    if (p.M == 0) {
-      // coarsest values (no gain): Delta = tau * 2 (1 - eta) w_c over the level-L blocks
-      double* cdel = tg + 8;
-      double* cinv = cdel + nlast;
-      const double kc = (2.0 * (1.0 - eta)) * w[p.nlev];
-      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, kc, cdel, cinv);
-      a.lv[kCoarseSlotHost].del = cdel;
-      a.lv[kCoarseSlotHost].inv = cinv;
-      for (int d = 0; d < 3; ++d) a.lv[kCoarseSlotHost].nb[d] = p.lv[p.L - 1].nb[d];
-      double* cd = cls + 54 * tot;
-      hipLaunchKernelGGL(k_class_tables, dim3(grid_for(27 * nlast)), dim3(NT), 0, st, cdel, cinv,
-                         p.lv[p.L - 1].nb[0], p.lv[p.L - 1].nb[1], p.lv[p.L - 1].nb[2], cd, cd + 27 * nlast);
-      a.lv[kCoarseSlotHost].cdel = cd;
-      a.lv[kCoarseSlotHost].cinv = cd + 27 * nlast;
-    }
+    auto tables = [&](const QTab& t, const double* ts, double kap) {
+      const int64_t nbs = prod3(t.nb);
+      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, ts, nbs, kap, const_cast<double*>(t.del),
+                         const_cast<double*>(t.inv));
+      hipLaunchKernelGGL(k_class_tables, dim3(grid_for(27 * nbs)), dim3(NT), 0, st, t.del, t.inv, t.nb[0], t.nb[1],
+                         t.nb[2], const_cast<double*>(t.cdel), const_cast<double*>(t.cinv));
+    };
+    for (int s = 1; s <= p.L; ++s) tables(a.lv[s - 1], taus(s), (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain);
+    // coarsest values when M == 0: Delta = tau * 2 (1 - eta) w_c
+    if (p.M == 0) tables(a.lv[kCoarseSlotHost], taus(p.L), (2.0 * (1.0 - eta)) * w[p.nlev]);
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
+    const int64_t nlast = prod3(p.lv[p.L - 1].nb);
     hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, tg);
   } else {
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
@@ -494,8 +501,151 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   sa.q = p.ws.qparam;
   hipLaunchKernelGGL(k_scalar_delta, dim3(1), dim3(64), 0, st, sa);
   BM_HIP(hipGetLastError());
-  a.q = p.ws.qparam;
   return a;
+}
+
+// ---- many fields per launch -------------------------------------------------
+
+namespace {
+
+__device__ inline int field_of(const int64_t* first, int nf, int64_t k) {
+  int lo = 0, hi = nf;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Eq. 2 from level s to level s+1 (s 1-based) for every field that has it
+__global__ void k_batch_propagate(const PrepField* F, const int64_t* first, int nf, int64_t ntot, int s) {
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT) {
+    const int f = field_of(first, nf, k);
+    const PrepField& P = F[f];
+    const int64_t i = k - first[f];
+    const int64_t* nb = P.nb[s - 1];
+    const int64_t* nn = P.nb[s];
+    const int64_t X = i % nn[2], t = i / nn[2], Y = t % nn[1], Z = t / nn[1];
+    double v = INFINITY;
+    for (int64_t z = i64max(0, 2 * Z - 1); z <= i64min(nb[0] - 1, 2 * Z + 2); ++z)
+      for (int64_t y = i64max(0, 2 * Y - 1); y <= i64min(nb[1] - 1, 2 * Y + 2); ++y)
+        for (int64_t x = i64max(0, 2 * X - 1); x <= i64min(nb[2] - 1, 2 * X + 2); ++x)
+          v = fmin(v, P.tau[s - 1][(z * nb[1] + y) * nb[2] + x]);
+    const_cast<double*>(P.tau[s])[i] = v;
+  }
+}
+
+// Per-block Delta, 1/Delta and 27-class tables of local level s (s = 0: the
+// coarsest values of a field with M == 0) straight from the taus: rounding
+// of tau * kappa is monotone, so the smallest Delta over a set of blocks is
+// the smallest tau times kappa, and its reciprocal is the largest 1/Delta.
+// Task = (block, class); class 13 (interior) also writes the block's own entry.
+__global__ void k_batch_tables(const PrepField* F, const int64_t* first, int nf, int64_t ntot, int s) {
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT) {
+    const int f = field_of(first, nf, k);
+    const PrepField& P = F[f];
+    const int li = s > 0 ? s - 1 : P.L - 1;
+    const QTab& T = s > 0 ? P.tab[li] : P.tab[kCoarseSlotHost];
+    const double kap = s > 0 ? P.kap[li] : P.kapc;
+    const double* tau = P.tau[li];
+    const int64_t i = k - first[f];
+    const int64_t blk = i / 27;
+    const int c = int(i - blk * 27);
+    const int cls[3] = {c / 9, (c / 3) % 3, c % 3};
+    const int64_t* nb = P.nb[li];
+    const int64_t bx = blk % nb[2], t = blk / nb[2];
+    const int64_t b[3] = {t / nb[1], t % nb[1], bx};
+    int64_t lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = (cls[d] == 0 && b[d] > 0) ? b[d] - 1 : b[d];
+      hi[d] = (cls[d] == 2 && b[d] + 1 < nb[d]) ? b[d] + 1 : b[d];
+    }
+    double m = INFINITY;
+    for (int64_t z = lo[0]; z <= hi[0]; ++z)
+      for (int64_t y = lo[1]; y <= hi[1]; ++y)
+        for (int64_t x = lo[2]; x <= hi[2]; ++x) m = fmin(m, tau[(z * nb[1] + y) * nb[2] + x]);
+    const double d = m * kap, iv = 1.0 / d;
+    const_cast<double*>(T.cdel)[i] = d;
+    const_cast<double*>(T.cinv)[i] = iv;
+    if (c == 13) {
+      const_cast<double*>(T.del)[blk] = d;
+      const_cast<double*>(T.inv)[blk] = iv;
+    }
+  }
+}
+
+// tau_global (minimum over the last block level, or the single map value
+// when there is none) and the scalar Deltas; one workgroup per field, which
+// also clears the field's overflow flag.
+__global__ __launch_bounds__(NT) void k_batch_scalar(const PrepField* F) {
+  __shared__ double red[NT];
+  const PrepField& P = F[blockIdx.x];
+  double m = INFINITY;
+  if (P.L > 0) {
+    const int64_t* nb = P.nb[P.L - 1];
+    const int64_t n = nb[0] * nb[1] * nb[2];
+    for (int64_t i = threadIdx.x; i < n; i += NT) m = fmin(m, P.tau[P.L - 1][i]);
+  } else if (threadIdx.x == 0) {
+    m = P.tau[0][0];
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *P.tg = red[0];
+    *P.flag = 0;
+  }
+  if (threadIdx.x <= P.nlev) {
+    const double d = red[0] * P.kq[threadIdx.x];
+    P.q[2 * threadIdx.x] = d;
+    P.q[2 * threadIdx.x + 1] = 1.0 / d;
+  }
+}
+
+}  // namespace
+
+PrepField prep_field(bm_plan_s& p, const double* block_tol, const QPrep& q) {
+  PrepField f{};
+  const double eta = p.cfg.eta;
+  const std::vector<double> w = level_weights(p);
+  f.L = p.L;
+  f.M = p.M;
+  f.nlev = p.nlev;
+  if (p.nlev + 1 > 26) fail(BM_EUNSUPPORTED, "too many levels");
+  for (int s = 1; s <= p.L; ++s) {
+    f.tau[s - 1] = s == 1 ? block_tol : p.ws.tolbuf + p.ws.tol_off[s];
+    for (int d = 0; d < 3; ++d) f.nb[s - 1][d] = p.lv[s - 1].nb[d];
+    f.kap[s - 1] = (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain;
+    f.tab[s - 1] = q.lv[s - 1];
+  }
+  if (p.L == 0) f.tau[0] = block_tol;
+  f.kapc = (2.0 * (1.0 - eta)) * w[p.nlev];
+  f.tab[kCoarseSlotHost] = q.lv[kCoarseSlotHost];
+  f.tg = p.ws.tolbuf + 3 * p.ws.tol_off[p.L + 1];
+  f.q = p.ws.qparam;
+  for (int s = 1; s <= p.nlev; ++s) f.kq[s - 1] = (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain;
+  f.kq[p.nlev] = (2.0 * (1.0 - eta)) * w[p.nlev];
+  f.flag = q.flag;
+  return f;
+}
+
+void launch_prep_batch(const PrepStages& g, const PrepField* F, int nf, hipStream_t st) {
+  for (int s = 1; s < 9; ++s)
+    if (g.prop_n[s] > 0)
+      hipLaunchKernelGGL(k_batch_propagate, dim3(grid_for(g.prop_n[s])), dim3(NT), 0, st, F, g.prop_first[s], nf,
+                         g.prop_n[s], s);
+  for (int s = 0; s < 9; ++s)
+    if (g.tab_n[s] > 0)
+      hipLaunchKernelGGL(k_batch_tables, dim3(grid_for(g.tab_n[s])), dim3(NT), 0, st, F, g.tab_first[s], nf,
+                         g.tab_n[s], s);
+  hipLaunchKernelGGL(k_batch_scalar, dim3(unsigned(nf)), dim3(NT), 0, st, F);
+  BM_HIP(hipGetLastError());
 }
 
 namespace {
