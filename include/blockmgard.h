@@ -178,6 +178,27 @@ bm_status bm_quantize_roi(bm_plan plan, const void* coeff, const double* block_t
 bm_status bm_dequantize(bm_plan plan, const int32_t* codes, const double* block_tol, void* coeff,
                         hipStream_t stream);
 
+/* Per-coefficient bin widths for a linear quantity of interest Q(x) = <g, x>
+ * (the adjoint-guided bounds): s = R^T g gives each coefficient's
+ * sensitivity; the N coefficients with s_i != 0 get equal shares,
+ * Delta_i = 2 (1 - eta) tol_q / (N |s_i|), so the dequantization errors move Q
+ * by at most (1 - eta) tol_q; every Delta_i is also capped by the node's L-inf
+ * Delta from block_tol (so that map's bounds still hold).  g: device, logical
+ * dims, dtype of the plan; delta: device, padded dims, FP64 (written);
+ * *n_sensitive = N if non-NULL.  Synchronous (N is needed on the host).
+ * Errors: BM_ENONFINITE (tol_q not positive and finite). */
+bm_status bm_qoi_deltas(bm_plan plan, const void* g, double tol_q, const double* block_tol, double* delta,
+                        int64_t* n_sensitive, hipStream_t stream);
+
+/* Quantization with an explicit per-node Delta (device, padded dims, FP64):
+ * q = rint(c * (1 / Delta_i)) in FP64; stats as bm_quantize_roi. */
+bm_status bm_quantize_delta(bm_plan plan, const void* coeff, const double* delta, int32_t* codes,
+                            bm_qstats* stats, hipStream_t stream);
+
+/* coeff = (dtype)(codes * Delta_i).  Asynchronous. */
+bm_status bm_dequantize_delta(bm_plan plan, const int32_t* codes, const double* delta, void* coeff,
+                              hipStream_t stream);
+
 /* Fused decompose + quantize (the paper's fused pipeline, Sec. IV-D): the
  * block levels write codes straight from on-chip memory; global-level
  * details are quantized as they are produced.  codes (device int32, padded

@@ -55,6 +55,9 @@ _SIGS = {
     "bm_decompress": [P, C.c_size_t, P, P],
     "bm_decompose_quantize": [P, P, P, P, C.POINTER(BMQStats), P],
     "bm_dequantize_recompose": [P, P, P, P, P],
+    "bm_qoi_deltas": [P, P, C.c_double, P, P, C.POINTER(C.c_int64), P],
+    "bm_quantize_delta": [P, P, P, P, C.POINTER(BMQStats), P],
+    "bm_dequantize_delta": [P, P, P, P, P],
     "bm_batch_create": [C.c_int, C.POINTER(BMConfig), C.POINTER(P)],
     "bm_batch_destroy": [P],
     "bm_batch_plan": [P, C.c_int, C.POINTER(P)],

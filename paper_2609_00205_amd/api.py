@@ -166,6 +166,41 @@ class Plan:
         call("bm_dequantize", self._h, _ptr(codes), _ptr(block_tol), _ptr(out), _stream(stream))
         return out
 
+    # -- adjoint-guided bounds for a linear quantity of interest ---------------
+    def qoi_deltas(self, g: torch.Tensor, tol_q: float, block_tol: torch.Tensor, stream=None):
+        """Per-node Delta keeping <g, x> within tol_q (capped by the block map's
+        L-inf Delta); returns (delta, number of sensitive coefficients)."""
+        _need(g, self.dtype, self.shape, "g")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        delta = torch.empty(self.coeff_shape, dtype=torch.float64, device=g.device)
+        n = C.c_int64(0)
+        call("bm_qoi_deltas", self._h, _ptr(g), float(tol_q), _ptr(block_tol), _ptr(delta), C.byref(n),
+             _stream(stream))
+        return delta, n.value
+
+    def quantize_delta(self, coeff: torch.Tensor, delta: torch.Tensor, codes: Optional[torch.Tensor] = None,
+                       stats: bool = True, stream=None):
+        _need(coeff, self.dtype, self.coeff_shape, "coeff")
+        _need(delta, torch.float64, self.coeff_shape, "delta")
+        if codes is None:
+            codes = torch.empty(self.coeff_shape, dtype=torch.int32, device=coeff.device)
+        _need(codes, torch.int32, self.coeff_shape, "codes")
+        st = BMQStats()
+        call("bm_quantize_delta", self._h, _ptr(coeff), _ptr(delta), _ptr(codes), C.byref(st) if stats else None,
+             _stream(stream))
+        return codes, ({"n_codes": st.n_codes, "n_outliers": st.n_outliers, "max_abs_code": st.max_abs_code}
+                       if stats else None)
+
+    def dequantize_delta(self, codes: torch.Tensor, delta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         stream=None) -> torch.Tensor:
+        _need(codes, torch.int32, self.coeff_shape, "codes")
+        _need(delta, torch.float64, self.coeff_shape, "delta")
+        if out is None:
+            out = torch.empty(self.coeff_shape, dtype=self.dtype, device=codes.device)
+        _need(out, self.dtype, self.coeff_shape, "out")
+        call("bm_dequantize_delta", self._h, _ptr(codes), _ptr(delta), _ptr(out), _stream(stream))
+        return out
+
     def decompose_quantize(self, x: torch.Tensor, block_tol: torch.Tensor, codes: Optional[torch.Tensor] = None,
                            check: bool = True, stream=None) -> torch.Tensor:
         """Fused decompose + ROI quantize: codes equal quantize(decompose(x))."""

@@ -331,6 +331,33 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
   });
 }
 
+bm_status bm_qoi_deltas(bm_plan p, const void* g, double tol_q, const double* block_tol, double* delta,
+                        int64_t* n_sensitive, hipStream_t st) {
+  return guarded([&] {
+    need(p && g && block_tol && delta, "null argument");
+    check_device(p);
+    const int64_t n = bm::qoi_deltas(*p, g, tol_q, block_tol, delta, st);
+    if (n_sensitive) *n_sensitive = n;
+  });
+}
+
+bm_status bm_quantize_delta(bm_plan p, const void* coeff, const double* delta, int32_t* codes, bm_qstats* stats,
+                            hipStream_t st) {
+  return guarded([&] {
+    need(p && coeff && delta && codes, "null argument");
+    check_device(p);
+    bm::quantize_delta(*p, coeff, delta, codes, stats, st);
+  });
+}
+
+bm_status bm_dequantize_delta(bm_plan p, const int32_t* codes, const double* delta, void* coeff, hipStream_t st) {
+  return guarded([&] {
+    need(p && coeff && delta && codes, "null argument");
+    check_device(p);
+    bm::dequantize_delta(*p, codes, delta, coeff, st);
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");

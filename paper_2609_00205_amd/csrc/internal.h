@@ -253,6 +253,13 @@ void tolmap_from_voxels(bm_plan_s& p, const double* voxel_tol, double* block_tol
 void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t* codes, bm_qstats* stats,
               hipStream_t st);
 void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* coeff, hipStream_t st);
+// per-node Delta for a linear quantity of interest <g, x> (returns the number
+// of coefficients it depends on; synchronizes), and quantization with an
+// explicit per-node Delta
+int64_t qoi_deltas(bm_plan_s& p, const void* g, double tol_q, const double* block_tol, double* delta, hipStream_t st);
+void quantize_delta(bm_plan_s& p, const void* coeff, const double* delta, int32_t* codes, bm_qstats* stats,
+                    hipStream_t st);
+void dequantize_delta(bm_plan_s& p, const int32_t* codes, const double* delta, void* coeff, hipStream_t st);
 
 // compress path: lazily allocated code / coefficient buffers of a plan, the
 // tolerance-map check, and the container writer (false: capacity too small,

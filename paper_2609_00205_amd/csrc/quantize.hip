@@ -40,6 +40,10 @@ __device__ inline void atomic_min_pos(double* p, double v) {
   atomicMin(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
+__global__ void k_fill_u64(unsigned long long* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
 __global__ void k_fill(double* p, int64_t n, double v) {
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) p[i] = v;
 }
@@ -225,6 +229,7 @@ struct QArgs {
   uint32_t nb[9][3];
   const double* q;            // scalar Delta / inverse per level (index s-1), coarsest at L+M
   int64_t* counters;          // [0] outliers, [1] max |q|, [2] out of range
+  const double* pdel;         // optional per-node Delta (padded grid); 1/Delta is its IEEE reciprocal
 };
 
 __device__ inline int ctz32(uint32_t v) { return v == 0 ? 32 : __builtin_ctz(v); }
@@ -317,7 +322,11 @@ __global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* c
         uint32_t z, y, x;
         a.uf(i, z, y, x);
         double del;
-        node_delta(a, z, y, x, del, inv[k]);
+        if (a.pdel) {
+          inv[k] = 1.0 / a.pdel[i];
+        } else {
+          node_delta(a, z, y, x, del, inv[k]);
+        }
         cv[k] = double(c[i]);
       }
     }
@@ -408,7 +417,10 @@ __global__ __launch_bounds__(NT) void k_dequantize(QArgs a, const int32_t* codes
         uint32_t z, y, x;
         a.uf(i, z, y, x);
         double inv;
-        node_delta(a, z, y, x, del[k], inv);
+        if (a.pdel)
+          del[k] = a.pdel[i];
+        else
+          node_delta(a, z, y, x, del[k], inv);
         q[k] = double(codes[i]);
       }
     }
@@ -425,6 +437,38 @@ int64_t prod3(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 }  // namespace
 
 // Build every per-level quantizer table on the device from the level-1 map.
+// number of nonzero entries (one atomic add per workgroup)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_count_nonzero(const T* v, int64_t n, unsigned long long* out) {
+  __shared__ unsigned long long red[NT];
+  unsigned long long c = 0;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) c += v[i] != T(0);
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0]) atomicAdd(out, red[0]);
+}
+
+// Per-node Delta keeping a linear quantity of interest within its tolerance:
+// with s the sensitivities of the quantity to the coefficients, the share of
+// coefficient i is e_i = tol / (N |s_i|) (N nonzero s_i), so the errors
+// |s_i| Delta_i / 2 add up to at most tol (1 - eta); the node's L-inf Delta
+// from the tolerance map caps it.  kq = 2 (1 - eta) tol / N.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_qoi_delta(QArgs a, const T* s, double kq, double* delta) {
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
+    uint32_t z, y, x;
+    a.uf(i, z, y, x);
+    double del, inv;
+    node_delta(a, z, y, x, del, inv);
+    const double sv = fabs(double(s[i]));
+    delta[i] = sv > 0.0 ? fmin(del, kq / sv) : del;
+  }
+}
+
 QPrep qprep_layout(bm_plan_s& p, const double* block_tol) {
   (void)block_tol;
   if (p.L > 8) fail(BM_EUNSUPPORTED, "more than 8 local levels");
@@ -650,8 +694,8 @@ void launch_prep_batch(const PrepStages& g, const PrepField* F, int nf, hipStrea
 
 namespace {
 
-QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
-  const QPrep qp = quant_prepare(p, block_tol, st);
+QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool tables = true) {
+  const QPrep qp = tables ? quant_prepare(p, block_tol, st) : qprep_layout(p, block_tol);
   QArgs a{};
   const int64_t npad = prod3(p.pdims);
   if (npad >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "quantizer: padded grid of 2^32 nodes or more");
@@ -743,6 +787,72 @@ void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, voi
   QArgs a = prepare(p, block_tol, st);
   const int64_t tot = prod3(p.pdims);
   (void)tot;
+  const unsigned g = qgroups(a.tot);
+  if (p.cfg.dtype == BM_F32)
+    hipLaunchKernelGGL(k_dequantize<float>, dim3(g), dim3(NT), 0, st, a, codes, static_cast<float*>(coeff));
+  else
+    hipLaunchKernelGGL(k_dequantize<double>, dim3(g), dim3(NT), 0, st, a, codes, static_cast<double*>(coeff));
+  BM_HIP(hipGetLastError());
+}
+
+int64_t qoi_deltas(bm_plan_s& p, const void* g, double tol_q, const double* block_tol, double* delta,
+                   hipStream_t st) {
+  if (!(tol_q > 0) || !std::isfinite(tol_q)) fail(BM_ENONFINITE, "tol_q must be positive and finite");
+  const size_t npad = size_t(prod3(p.pdims));
+  if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, npad * p.esize));
+  // sensitivities s = R^T g of the quantity to the coefficients
+  recompose_adjoint(p, g, p.ws.coeff, st);
+  auto* cnt = reinterpret_cast<unsigned long long*>(p.ws.counters + 3);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, cnt);
+  if (p.cfg.dtype == BM_F32)
+    hipLaunchKernelGGL(k_count_nonzero<float>, dim3(grid_for(int64_t(npad))), dim3(NT), 0, st,
+                       static_cast<const float*>(p.ws.coeff), int64_t(npad), cnt);
+  else
+    hipLaunchKernelGGL(k_count_nonzero<double>, dim3(grid_for(int64_t(npad))), dim3(NT), 0, st,
+                       static_cast<const double*>(p.ws.coeff), int64_t(npad), cnt);
+  unsigned long long nnz = 0;
+  BM_HIP(hipMemcpyAsync(&nnz, cnt, sizeof(nnz), hipMemcpyDeviceToHost, st));
+  QArgs a = prepare(p, block_tol, st);
+  BM_HIP(hipStreamSynchronize(st));
+  const double kq = nnz ? (2.0 * (1.0 - p.cfg.eta)) * tol_q / double(nnz) : 0.0;
+  const unsigned gq = grid_for(int64_t(a.tot));
+  if (p.cfg.dtype == BM_F32)
+    hipLaunchKernelGGL(k_qoi_delta<float>, dim3(gq), dim3(NT), 0, st, a, static_cast<const float*>(p.ws.coeff), kq,
+                       delta);
+  else
+    hipLaunchKernelGGL(k_qoi_delta<double>, dim3(gq), dim3(NT), 0, st, a, static_cast<const double*>(p.ws.coeff),
+                       kq, delta);
+  BM_HIP(hipGetLastError());
+  return int64_t(nnz);
+}
+
+void quantize_delta(bm_plan_s& p, const void* coeff, const double* delta, int32_t* codes, bm_qstats* stats,
+                    hipStream_t st) {
+  QArgs a = prepare(p, nullptr, st, false);
+  a.pdel = delta;
+  const unsigned g = qgroups(a.tot);
+  int64_t* partials = p.ws.counters + 16;
+  if (p.cfg.dtype == BM_F32)
+    hipLaunchKernelGGL(k_quantize<float>, dim3(g), dim3(NT), 0, st, a, static_cast<const float*>(coeff), codes, partials);
+  else
+    hipLaunchKernelGGL(k_quantize<double>, dim3(g), dim3(NT), 0, st, a, static_cast<const double*>(coeff), codes,
+                       partials);
+  hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(NT), 0, st, partials, int(g), p.ws.counters);
+  BM_HIP(hipGetLastError());
+  if (stats) {
+    int64_t h[4];
+    BM_HIP(hipMemcpyAsync(h, p.ws.counters, sizeof(h), hipMemcpyDeviceToHost, st));
+    BM_HIP(hipStreamSynchronize(st));
+    stats->n_codes = int64_t(a.tot);
+    stats->n_outliers = h[0];
+    stats->max_abs_code = h[1];
+    if (h[2]) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (Delta too small for the data)");
+  }
+}
+
+void dequantize_delta(bm_plan_s& p, const int32_t* codes, const double* delta, void* coeff, hipStream_t st) {
+  QArgs a = prepare(p, nullptr, st, false);
+  a.pdel = delta;
   const unsigned g = qgroups(a.tot);
   if (p.cfg.dtype == BM_F32)
     hipLaunchKernelGGL(k_dequantize<float>, dim3(g), dim3(NT), 0, st, a, codes, static_cast<float*>(coeff));
