@@ -216,16 +216,17 @@ bm_status bm_dequantize_recompose(bm_plan plan, const int32_t* codes, const doub
 /* ---- lossless stage (Sec. IV-B lossless stages) ----------------------- */
 
 /* Canonical Huffman coding of n int32 codes (device) in raster order.
- * Symbols are q + 2^15 for |q| < 2^15, else the escape symbol 0 with the
- * (index, q) pair kept as an outlier.  Output (host) layout, little endian:
- *   uint32 magic 0x46484D42 ("BMHF"), uint32 version 2,
+ * Symbols are q + 2^15 for |q| < 2^15, else the escape symbol 0; the value q
+ * of every escaped code is kept as an outlier, in raster order (its position
+ * is that of its escape symbol).  Output (host) layout, little endian:
+ *   uint32 magic 0x46484D42 ("BMHF"), uint32 version 3,
  *   int64 n, int64 nchunks, int64 nwords, int64 noutliers, int64 npresent,
  *   uint16 symbol[npresent] (ascending), uint8 length[npresent] (code
  *   lengths of the symbols that occur; absent symbols have no code),
  *   uint64 chunk_offsets[nchunks+1] (in words),
+ *   uint64 outlier_offsets[nchunks+1] (outliers before each chunk),
  *   uint32 words[nwords] (each chunk of 4096 symbols packed MSB-first,
- *   starting on a word), uint64 outlier_index[noutliers],
- *   int32 outlier_value[noutliers].
+ *   starting on a word), int32 outlier_value[noutliers].
  * Synchronous.  BM_ECAPACITY sets *out_bytes to the size needed. */
 bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity,
                             size_t* out_bytes, hipStream_t stream);
@@ -286,6 +287,28 @@ bm_status bm_batch_dequantize_recompose(bm_batch batch, const int32_t* const* co
  * buffer is too small (out_bytes then holds every needed size). */
 bm_status bm_batch_compress(bm_batch batch, const void* const* x, const double* const* block_tol, void* const* out,
                             const size_t* capacity, size_t* out_bytes, int use_graph, hipStream_t stream);
+
+/* ---- choice of (b, L, M) (the hybrid split of Sec. IV-B, by measurement) -- */
+
+typedef struct {
+  int block, L, M;        /* block 0: no block levels */
+  int status;             /* BM_OK, or BM_ERANGE: codes overflow, stored raw */
+  double ms;              /* fused decompose + quantize, median of the repetitions */
+  double ratio;           /* raw bytes / container bytes at the given tolerances */
+} bm_candidate;
+
+/* Chooses block size and level split for field x (device, logical dims and
+ * dtype of *in) under a per-voxel absolute tolerance (device, logical dims,
+ * FP64).  Candidates: pure global M = 1..6; b in {9, 17} with L = 1..4 and
+ * M = 0..4; those the dims admit (a valid plan padding the volume by at most
+ * 1/8).  Each is run: median time of `reps` fused decompose + quantize runs
+ * and the exact Huffman-coded size.  The fastest candidate whose ratio is at
+ * least (1 - slack) times the best ratio wins; *out is *in with block, L, M
+ * set.  cands (optional, room for cap entries) receives the measured table
+ * and *ncands its length.  Synchronous.  Errors: BM_EINVAL (no admissible
+ * candidate, slack outside [0, 1)). */
+bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_tol, double slack, int reps,
+                      bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
 
 /* ---- diagnostics ---------------------------------------------------------- */
 

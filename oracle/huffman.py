@@ -6,8 +6,9 @@ The paper names the lossless stage only by its parts (outlier handling,
 histogram, codebook build, encode; Sec. IV-B, citing a GPU Huffman coder).
 The format here is the reading used by the library:
 
-* symbol = q + R for |q| < R with R = 2^15; symbol 0 is the escape and the
-  outlier (index, q) is stored on the side;
+* symbol = q + R for |q| < R with R = 2^15; symbol 0 is the escape, and the
+  value q of each escaped code is stored on the side in raster order (its
+  position is that of its escape symbol; per-chunk counts locate them);
 * code lengths from Huffman's algorithm, always merging the two smallest
   (weight, smallest symbol in the subtree) keys, so the tree is unique;
   lengths above 32 are cut to 32 and the longest codes still below 32 are
@@ -43,6 +44,13 @@ def from_symbols(sym: np.ndarray, oidx: np.ndarray, oval: np.ndarray) -> np.ndar
     q = np.asarray(sym, np.int64) - RADIUS
     q[np.asarray(oidx, np.int64)] = oval
     return q
+
+
+def outlier_offsets(oidx: np.ndarray, n: int, chunk: int = CHUNK) -> np.ndarray:
+    """Number of outliers before each chunk (nchunks + 1 entries)."""
+    nch = (n + chunk - 1) // chunk
+    counts = np.bincount(np.asarray(oidx, np.int64) // chunk, minlength=nch)[:nch]
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
 
 
 def histogram(sym: np.ndarray) -> np.ndarray:

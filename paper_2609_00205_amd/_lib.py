@@ -24,6 +24,11 @@ class BMQStats(C.Structure):
     _fields_ = [("n_codes", C.c_int64), ("n_outliers", C.c_int64), ("max_abs_code", C.c_int64)]
 
 
+class BMCandidate(C.Structure):
+    _fields_ = [("block", C.c_int), ("L", C.c_int), ("M", C.c_int), ("status", C.c_int), ("ms", C.c_double),
+                ("ratio", C.c_double)]
+
+
 class BMError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -58,6 +63,8 @@ _SIGS = {
     "bm_qoi_deltas": [P, P, C.c_double, P, P, C.POINTER(C.c_int64), P],
     "bm_quantize_delta": [P, P, P, P, C.POINTER(BMQStats), P],
     "bm_dequantize_delta": [P, P, P, P, P],
+    "bm_autotune": [C.POINTER(BMConfig), P, P, C.c_double, C.c_int, C.POINTER(BMConfig), C.POINTER(BMCandidate),
+                    C.c_int, C.POINTER(C.c_int), P],
     "bm_batch_create": [C.c_int, C.POINTER(BMConfig), C.POINTER(P)],
     "bm_batch_destroy": [P],
     "bm_batch_plan": [P, C.c_int, C.POINTER(P)],

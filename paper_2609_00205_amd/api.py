@@ -311,11 +311,33 @@ def parse_huffman(buf: bytes) -> dict:
     lengths = np.zeros(65536, np.uint8)
     lengths[psym.astype(np.int64)] = plen
     offsets = np.frombuffer(buf, np.uint64, nch + 1, o); o += 8 * (nch + 1)
+    ooffsets = np.frombuffer(buf, np.uint64, nch + 1, o); o += 8 * (nch + 1)
     words = np.frombuffer(buf, np.uint32, nw, o); o += 4 * nw
-    oidx = np.frombuffer(buf, np.uint64, nout, o); o += 8 * nout
     oval = np.frombuffer(buf, np.int32, nout, o)
     return {"magic": magic, "n": n, "nchunks": nch, "lengths": lengths, "offsets": offsets, "words": words,
-            "outlier_index": oidx, "outlier_value": oval}
+            "outlier_offsets": ooffsets, "outlier_value": oval}
+
+
+def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps: int = 3,
+             pad_mode: str = "clamp", eta: Optional[float] = None, stream=None):
+    """Measured choice of (block, L, M) for field x under the per-voxel absolute
+    tolerance voxel_tol (FP64, same shape).  Returns (choice, candidates):
+    choice = {"block", "L", "M"}; candidates = the measured table."""
+    if x.dtype not in _DT:
+        raise ValueError("x must be float32 or float64")
+    _need(x, x.dtype, None, "x")
+    _need(voxel_tol, torch.float64, tuple(x.shape), "voxel_tol")
+    eta = DEFAULT_ETA[x.dtype] if eta is None else float(eta)
+    cfg = BMConfig(3, (C.c_int64 * 3)(*x.shape), _DT[x.dtype], 17, 1, 1, 1 if pad_mode == "zero" else 0, eta)
+    out = BMConfig()
+    cap = 128
+    table = (_lib.BMCandidate * cap)()
+    n = C.c_int(0)
+    call("bm_autotune", C.byref(cfg), _ptr(x), _ptr(voxel_tol), float(slack), int(reps), C.byref(out), table, cap,
+         C.byref(n), _stream(stream))
+    cands = [{"block": table[i].block, "L": table[i].L, "M": table[i].M, "status": table[i].status,
+              "ms": table[i].ms, "ratio": table[i].ratio} for i in range(min(n.value, cap))]
+    return {"block": out.block, "L": out.L, "M": out.M}, cands
 
 
 def max_block_levels(shape: Sequence[int], block: int) -> int:

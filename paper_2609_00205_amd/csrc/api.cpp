@@ -358,6 +358,19 @@ bm_status bm_dequantize_delta(bm_plan p, const int32_t* codes, const double* del
   });
 }
 
+bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_tol, double slack, int reps,
+                      bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t st) {
+  return guarded([&] {
+    need(in && x && voxel_tol && out, "null argument");
+    need(cap >= 0 && (cap == 0 || cands), "null candidate table");
+    bm_config o{};
+    const std::vector<bm_candidate> all = bm::autotune(*in, x, voxel_tol, slack, reps, o, st);
+    for (int i = 0; i < cap && i < int(all.size()); ++i) cands[i] = all[i];
+    if (ncands) *ncands = int(all.size());
+    *out = o;
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");

@@ -1,0 +1,124 @@
+// Choice of block size and level split (b, L, M) by measurement.
+//
+// The hybrid hierarchy trades block levels (on chip, one sweep each) against
+// global levels (whole-grid line solves); the paper picks (L, M) from a
+// fitted throughput model under a time budget (Sec. IV-B, Algorithm 1).  Here
+// every admissible candidate is run on the caller's field and tolerance:
+// the fused decompose + quantize is timed with HIP events (median over
+// repetitions) and the coded size is the exact Huffman stream size of its
+// codes.  The fastest candidate whose compression ratio is within a slack of
+// the best ratio wins.
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+bm_plan_s* bm_plan_build(const bm_config* c);
+void bm_plan_free(bm_plan_s* p);
+
+namespace bm {
+
+namespace {
+
+struct PlanGuard {
+  bm_plan_s* p = nullptr;
+  double* tol = nullptr;
+  ~PlanGuard() {
+    if (tol) (void)hipFree(tol);
+    if (p) bm_plan_free(p);
+  }
+};
+
+// one candidate: time (ms) and ratio; status BM_OK, or BM_ERANGE when codes
+// overflow (the container would store the raw data: ratio 1)
+void measure(const bm_config& cfg, const void* x, const double* voxel_tol, int reps, bm_candidate& c,
+             hipStream_t st) {
+  PlanGuard g;
+  g.p = bm_plan_build(&cfg);
+  bm_plan_s& p = *g.p;
+  const int64_t npad = p.pdims[0] * p.pdims[1] * p.pdims[2];
+  const int64_t nlog = p.dims[0] * p.dims[1] * p.dims[2];
+  const int64_t ntol = p.nb1[0] * p.nb1[1] * p.nb1[2];
+  BM_HIP(hipMalloc(&g.tol, size_t(ntol) * sizeof(double)));
+  BM_HIP(hipMalloc(&p.ws.codes, size_t(npad) * sizeof(int32_t)));
+  int32_t* codes = static_cast<int32_t*>(p.ws.codes);
+  tolmap_from_voxels(p, voxel_tol, g.tol, st);
+  bm_qstats qs;
+  c.status = BM_OK;
+  try {
+    decompose_quantize(p, x, g.tol, codes, &qs, st);   // warm-up, and the overflow check
+  } catch (const Error& e) {
+    if (e.code != BM_ERANGE) throw;
+    c.status = BM_ERANGE;
+  }
+  std::vector<float> ms;
+  hipEvent_t a, b;
+  BM_HIP(hipEventCreate(&a));
+  BM_HIP(hipEventCreate(&b));
+  for (int r = 0; r < std::max(1, reps); ++r) {
+    BM_HIP(hipEventRecord(a, st));
+    decompose_quantize(p, x, g.tol, codes, nullptr, st);
+    BM_HIP(hipEventRecord(b, st));
+    BM_HIP(hipEventSynchronize(b));
+    float t = 0;
+    BM_HIP(hipEventElapsedTime(&t, a, b));
+    ms.push_back(t);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(ms.begin(), ms.end());
+  c.ms = ms[ms.size() / 2];
+  const double raw = double(nlog) * double(p.esize);
+  const double coded = c.status == BM_OK ? double(huffman_size(codes, npad, st)) + 8.0 * double(ntol) + 128.0 : raw;
+  c.ratio = raw / std::min(coded, raw);
+}
+
+}  // namespace
+
+std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const double* voxel_tol, double slack, int reps,
+                                   bm_config& out, hipStream_t st) {
+  if (!(slack >= 0.0 && slack < 1.0)) fail(BM_EINVAL, "slack must lie in [0, 1)");
+  std::vector<bm_candidate> cands;
+  int64_t nlog = 1;
+  for (int a = 0; a < in.ndim; ++a) nlog *= in.dims[a];
+  auto consider = [&](int block, int L, int M) {
+    bm_config c = in;
+    c.block = block;
+    c.L = L;
+    c.M = M;
+    // admissible: the plan exists and pads the volume by at most 1/8
+    bm_plan_s* probe = nullptr;
+    try {
+      probe = bm_plan_build(&c);
+    } catch (const Error&) {
+      return;
+    }
+    const int64_t npad = probe->pdims[0] * probe->pdims[1] * probe->pdims[2];
+    bm_plan_free(probe);
+    if (double(npad) > 1.125 * double(nlog)) return;
+    bm_candidate k{};
+    k.block = block;
+    k.L = L;
+    k.M = M;
+    measure(c, x, voxel_tol, reps, k, st);
+    cands.push_back(k);
+  };
+  for (int M = 1; M <= 6; ++M) consider(0, 0, M);
+  for (int block : {9, 17})
+    for (int L = 1; L <= 4; ++L)
+      for (int M = 0; M <= 4; ++M) consider(block, L, M);
+  if (cands.empty()) fail(BM_EINVAL, "no admissible (block, L, M) for these dims");
+  double best = 0;
+  for (auto& k : cands) best = std::max(best, k.ratio);
+  const bm_candidate* win = nullptr;
+  for (auto& k : cands)
+    if (k.ratio >= (1.0 - slack) * best && (!win || k.ms < win->ms)) win = &k;
+  out = in;
+  out.block = win->block == 0 ? in.block : win->block;
+  out.L = win->L;
+  out.M = win->M;
+  return cands;
+}
+
+}  // namespace bm

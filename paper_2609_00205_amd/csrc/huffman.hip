@@ -93,7 +93,7 @@ __device__ inline uint32_t wave_excl_scan(uint32_t v, int lane) {
 // one wavefront per chunk; lane l codes symbols [64 l, 64 l + 64) of the chunk
 __global__ __launch_bounds__(64) void k_encode(const int32_t* codes, int64_t n, const uint8_t* len,
                                                const uint32_t* cw, const uint64_t* woff, const uint64_t* ooff,
-                                               uint32_t* words, uint64_t* oidx, int32_t* oval) {
+                                               uint32_t* words, int32_t* oval) {
   __shared__ uint32_t sym[64 * 65];
   __shared__ uint32_t out[CHUNK];
   const int lane = threadIdx.x;
@@ -126,12 +126,7 @@ __global__ __launch_bounds__(64) void k_encode(const int32_t* codes, int64_t n, 
       atomicOr(&out[w + 1], v << (64 - o - l));
     }
     p += l;
-    if (s == 0) {
-      const int64_t idx = b0 + lane * 64 + k;
-      oidx[e] = uint64_t(idx);
-      oval[e] = codes[idx];
-      ++e;
-    }
+    if (s == 0) oval[e++] = codes[b0 + lane * 64 + k];
   }
   __syncthreads();
   for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = out[i];
@@ -147,20 +142,16 @@ struct DecTables {
 
 // one thread per chunk
 __global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint64_t* woff, int64_t nch, int64_t n,
-                                               DecTables t, const uint64_t* oidx, const int32_t* oval, int64_t nout,
+                                               DecTables t, const uint64_t* ooff, const int32_t* oval,
                                                int32_t* codes, int* err) {
   const int64_t c = int64_t(blockIdx.x) * 64 + threadIdx.x;
   if (c >= nch) return;
   const int64_t b0 = c * CHUNK;
   const int cnt = int(b0 + CHUNK < n ? CHUNK : n - b0);
   const uint64_t w0 = woff[c], w1 = woff[c + 1];
-  // first outlier at or after this chunk
-  int64_t lo = 0, hi = nout;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (int64_t(oidx[mid]) < b0) lo = mid + 1; else hi = mid;
-  }
-  int64_t e = lo;
+  // this chunk's outliers, in the order of its escape symbols
+  uint64_t e = ooff[c];
+  const uint64_t e1 = ooff[c + 1];
   uint64_t buf = 0;
   int avail = 0;
   uint64_t wp = w0;
@@ -196,7 +187,7 @@ __global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint
     avail -= int(l);
     int32_t q;
     if (s == 0) {
-      if (e >= nout) {
+      if (e >= e1) {
         atomicOr(err, 1);
         return;
       }
@@ -206,6 +197,7 @@ __global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint
     }
     codes[b0 + k] = q;
   }
+  if (e != e1) atomicOr(err, 1);
 }
 
 // ------------------------------------------------------------------ host codebook
@@ -306,9 +298,23 @@ struct DevBuf {
 
 }  // namespace
 
-size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st) {
+namespace {
+
+// Code table and stream layout of a code array: histogram (device), code
+// lengths and canonical codes (host), per-chunk bit and escape counts
+// (device), word and outlier offsets (host).
+struct StreamPlan {
+  std::vector<uint8_t> len;
+  std::vector<uint32_t> cw, sorted;
+  std::vector<uint64_t> woff, ooff;
+  int64_t nch = 0;
+};
+
+StreamPlan plan_stream(const int32_t* codes, int64_t n, hipStream_t st, DevBuf<uint8_t>& dlen, DevBuf<uint32_t>& dcw) {
   if (n < 0 || (n > 0 && !codes)) fail(BM_EINVAL, "bad code array");
+  StreamPlan sp;
   const int64_t nch = (n + CHUNK - 1) / CHUNK;
+  sp.nch = nch;
   DevBuf<unsigned long long> hist(NSYM);
   hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, hist.p, int64_t(NSYM));
   if (n) {
@@ -319,14 +325,10 @@ size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out
   std::vector<uint64_t> h(NSYM);
   BM_HIP(hipMemcpyAsync(h.data(), hist.p, NSYM * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
-  std::vector<uint8_t> len;
-  std::vector<uint32_t> cw, sorted;
-  code_lengths(h, len);
-  canonical(len, cw, sorted);
-  DevBuf<uint8_t> dlen(NSYM);
-  DevBuf<uint32_t> dcw(NSYM);
-  BM_HIP(hipMemcpyAsync(dlen.p, len.data(), NSYM, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dcw.p, cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  code_lengths(h, sp.len);
+  canonical(sp.len, sp.cw, sp.sorted);
+  BM_HIP(hipMemcpyAsync(dlen.p, sp.len.data(), NSYM, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dcw.p, sp.cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   DevBuf<uint32_t> bits(size_t(std::max<int64_t>(nch, 1))), esc(size_t(std::max<int64_t>(nch, 1)));
   if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, bits.p, esc.p);
   BM_HIP(hipGetLastError());
@@ -336,21 +338,47 @@ size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out
     BM_HIP(hipMemcpyAsync(he.data(), esc.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   }
   BM_HIP(hipStreamSynchronize(st));
-  std::vector<uint64_t> woff(nch + 1, 0), ooff(nch + 1, 0);
+  sp.woff.assign(nch + 1, 0);
+  sp.ooff.assign(nch + 1, 0);
   for (int64_t c = 0; c < nch; ++c) {
-    woff[c + 1] = woff[c] + (uint64_t(hb[c]) + 31) / 32;
-    ooff[c + 1] = ooff[c] + he[c];
+    sp.woff[c + 1] = sp.woff[c] + (uint64_t(hb[c]) + 31) / 32;
+    sp.ooff[c + 1] = sp.ooff[c] + he[c];
   }
+  return sp;
+}
+
+size_t stream_bytes(const StreamPlan& sp) {
+  int64_t np = 0;
+  for (int s = 0; s < NSYM; ++s) np += sp.len[s] != 0;
+  return sizeof(HuffHeader) + size_t(np) * 3 + size_t(sp.nch + 1) * 16 + size_t(sp.woff[sp.nch]) * 4 +
+         size_t(sp.ooff[sp.nch]) * 4;
+}
+
+}  // namespace
+
+size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st) {
+  DevBuf<uint8_t> dlen(NSYM);
+  DevBuf<uint32_t> dcw(NSYM);
+  return stream_bytes(plan_stream(codes, n, st, dlen, dcw));
+}
+
+size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st) {
+  DevBuf<uint8_t> dlen(NSYM);
+  DevBuf<uint32_t> dcw(NSYM);
+  const StreamPlan sp = plan_stream(codes, n, st, dlen, dcw);
+  const int64_t nch = sp.nch;
+  const std::vector<uint8_t>& len = sp.len;
+  const std::vector<uint64_t>& woff = sp.woff;
+  const std::vector<uint64_t>& ooff = sp.ooff;
   const int64_t nw = int64_t(woff[nch]), nout = int64_t(ooff[nch]);
   DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
   DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
-  DevBuf<uint64_t> doidx(size_t(std::max<int64_t>(nout, 1)));
   DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
   BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   if (nch)
     hipLaunchKernelGGL(k_encode, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p, dooff.p,
-                       dwords.p, doidx.p, doval.p);
+                       dwords.p, doval.p);
   BM_HIP(hipGetLastError());
   std::vector<uint16_t> psym;
   std::vector<uint8_t> plen;
@@ -360,8 +388,8 @@ size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out
       plen.push_back(len[s]);
     }
   const int64_t np = int64_t(psym.size());
-  HuffHeader hh{kHuffMagic, 2, n, nch, nw, nout, np};
-  const size_t bytes = sizeof(hh) + size_t(np) * 3 + (nch + 1) * 8 + size_t(nw) * 4 + size_t(nout) * 12;
+  HuffHeader hh{kHuffMagic, 3, n, nch, nw, nout, np};
+  const size_t bytes = sizeof(hh) + size_t(np) * 3 + (nch + 1) * 16 + size_t(nw) * 4 + size_t(nout) * 4;
   out.resize(bytes);
   uint8_t* o = out.data();
   std::memcpy(o, &hh, sizeof(hh));
@@ -372,10 +400,10 @@ size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out
   o += size_t(np);
   std::memcpy(o, woff.data(), (nch + 1) * 8);
   o += (nch + 1) * 8;
+  std::memcpy(o, ooff.data(), (nch + 1) * 8);
+  o += (nch + 1) * 8;
   if (nw) BM_HIP(hipMemcpyAsync(o, dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, st));
   o += size_t(nw) * 4;
-  if (nout) BM_HIP(hipMemcpyAsync(o, doidx.p, size_t(nout) * 8, hipMemcpyDeviceToHost, st));
-  o += size_t(nout) * 8;
   if (nout) BM_HIP(hipMemcpyAsync(o, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
   return bytes;
@@ -385,13 +413,13 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   if (!in || in_bytes < sizeof(HuffHeader)) fail(BM_ECORRUPT, "Huffman stream too short");
   HuffHeader hh;
   std::memcpy(&hh, in, sizeof(hh));
-  if (hh.magic != kHuffMagic || hh.version != 2) fail(BM_ECORRUPT, "bad Huffman stream header");
+  if (hh.magic != kHuffMagic || hh.version != 3) fail(BM_ECORRUPT, "bad Huffman stream header");
   if (hh.n != n) fail(BM_EINVAL, "symbol count does not match the destination");
   if (hh.nchunks != (n + CHUNK - 1) / CHUNK || hh.nwords < 0 || hh.noutliers < 0 || hh.noutliers > n ||
       hh.npresent < 0 || hh.npresent > NSYM || hh.nwords > (int64_t(1) << 40))
     fail(BM_ECORRUPT, "inconsistent Huffman stream header");
   const int64_t nch = hh.nchunks, nw = hh.nwords, nout = hh.noutliers, np = hh.npresent;
-  const size_t need = sizeof(hh) + size_t(np) * 3 + size_t(nch + 1) * 8 + size_t(nw) * 4 + size_t(nout) * 12;
+  const size_t need = sizeof(hh) + size_t(np) * 3 + size_t(nch + 1) * 16 + size_t(nw) * 4 + size_t(nout) * 4;
   if (in_bytes < need) fail(BM_ECORRUPT, "Huffman stream truncated");
   const uint8_t* p = in + sizeof(hh);
   std::vector<uint8_t> len(NSYM, 0);
@@ -408,8 +436,14 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   std::vector<uint64_t> woff(nch + 1);
   std::memcpy(woff.data(), p, (nch + 1) * 8);
   p += (nch + 1) * 8;
+  std::vector<uint64_t> ooff(nch + 1);
+  std::memcpy(ooff.data(), p, (nch + 1) * 8);
+  p += (nch + 1) * 8;
+  if (woff[0] != 0 || ooff[0] != 0 || ooff[nch] != uint64_t(nout)) fail(BM_ECORRUPT, "bad chunk offsets");
   for (int64_t c = 0; c < nch; ++c)
-    if (woff[c + 1] < woff[c] || woff[c + 1] > uint64_t(nw)) fail(BM_ECORRUPT, "bad chunk offsets");
+    if (woff[c + 1] < woff[c] || woff[c + 1] > uint64_t(nw) || ooff[c + 1] < ooff[c] ||
+        ooff[c + 1] - ooff[c] > uint64_t(CHUNK))
+      fail(BM_ECORRUPT, "bad chunk offsets");
   uint64_t kraft = 0;
   for (int s = 0; s < NSYM; ++s) {
     if (len[s] > LMAX) fail(BM_ECORRUPT, "code length above 32");
@@ -433,9 +467,8 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   }
   DevBuf<uint32_t> dlut(lut.size()), dfirst(LMAX + 1), dcount(LMAX + 1), dbase(LMAX + 1),
       dsorted(std::max<size_t>(sorted.size(), 1));
-  DevBuf<uint64_t> dwoff(nch + 1);
+  DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
   DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
-  DevBuf<uint64_t> doidx(size_t(std::max<int64_t>(nout, 1)));
   DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
   DevBuf<int> derr(1);
   BM_HIP(hipMemcpyAsync(dlut.p, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
@@ -444,17 +477,16 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   BM_HIP(hipMemcpyAsync(dbase.p, base.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
   if (!sorted.empty()) BM_HIP(hipMemcpyAsync(dsorted.p, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
   if (nw) BM_HIP(hipMemcpyAsync(dwords.p, p, size_t(nw) * 4, hipMemcpyHostToDevice, st));
   p += size_t(nw) * 4;
-  if (nout) BM_HIP(hipMemcpyAsync(doidx.p, p, size_t(nout) * 8, hipMemcpyHostToDevice, st));
-  p += size_t(nout) * 8;
   if (nout) BM_HIP(hipMemcpyAsync(doval.p, p, size_t(nout) * 4, hipMemcpyHostToDevice, st));
   const int zero = 0;
   BM_HIP(hipMemcpyAsync(derr.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
   DecTables t{dlut.p, dfirst.p, dcount.p, dbase.p, dsorted.p};
   if (nch)
     hipLaunchKernelGGL(k_decode, dim3(unsigned((nch + 63) / 64)), dim3(64), 0, st, dwords.p, dwoff.p, nch, n, t,
-                       doidx.p, doval.p, nout, codes, derr.p);
+                       dooff.p, doval.p, codes, derr.p);
   BM_HIP(hipGetLastError());
   int herr = 0;
   BM_HIP(hipMemcpyAsync(&herr, derr.p, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -282,8 +282,14 @@ void batch_dequantize_recompose(bm_batch_s& b, const int32_t* const* codes, cons
                                 bool graph, hipStream_t st);
 int batch_overflows(bm_batch_s& b, std::vector<int>& bad, hipStream_t st);
 
+// measured choice of (b, L, M); returns every measured candidate
+std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const double* voxel_tol, double slack, int reps,
+                                   bm_config& out, hipStream_t st);
+
 // huffman (host buffers)
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);
+// exact size of the stream huffman_encode would write (synchronizes)
+size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);
 
 // RAII event pair around the work of one timing slot (no-op unless timing is on)

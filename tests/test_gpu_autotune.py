@@ -1,0 +1,47 @@
+"""Measured choice of (block, L, M) through the C ABI.
+
+Checks: the candidate table covers the admissible schedules; the choice is
+the fastest candidate within the slack of the best ratio (the documented
+rule, re-applied to the returned table); the chosen plan compresses the
+field with every voxel within its own tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_00205_amd import _lib
+    _lib.lib()
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_autotune_rule_and_bounds(dt):
+    from paper_2609_00205_amd import Plan, autotune, decompress
+    shape = (65, 65, 33)
+    x = synth.turbulence_with_front(shape, seed=3)
+    mask = synth.gradient_percentile_mask(x, 95.0)
+    sc = float(np.abs(x).max())
+    vt = np.where(mask, 1e-6 if dt == torch.float64 else 1e-5, 1e-3) * sc
+    xd = torch.from_numpy(x).to(dt).cuda()
+    vtd = torch.from_numpy(vt).cuda()
+    choice, cands = autotune(xd, vtd, slack=0.05, reps=2)
+    assert len(cands) >= 10
+    assert {(c["block"], c["L"], c["M"]) for c in cands} >= {(0, 0, 1), (9, 1, 0), (17, 1, 0)}
+    best = max(c["ratio"] for c in cands)
+    elig = [c for c in cands if c["ratio"] >= 0.95 * best]
+    win = min(elig, key=lambda c: c["ms"])
+    assert (choice["L"], choice["M"]) == (win["L"], win["M"])
+    if win["L"] > 0:
+        assert choice["block"] == win["block"]
+    p = Plan(shape, dtype=dt, block=choice["block"] if choice["L"] else 17, L=choice["L"], M=choice["M"])
+    bt = p.tolmap_from_voxels(vtd)
+    xr = decompress(p.compress(xd, bt))
+    err = (xr.double() - xd.double()).abs()
+    assert bool((err <= vtd).all())

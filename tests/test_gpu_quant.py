@@ -159,7 +159,7 @@ def test_huffman_bit_exact(n):
     assert np.array_equal(got["lengths"], ln.astype(np.uint8))
     assert np.array_equal(got["offsets"].astype(np.int64), offs)
     assert np.array_equal(got["words"], words)
-    assert np.array_equal(got["outlier_index"].astype(np.int64), oi)
+    assert np.array_equal(got["outlier_offsets"].astype(np.int64), ohf.outlier_offsets(oi, n))
     assert np.array_equal(got["outlier_value"].astype(np.int64), ov)
     dec = api.huffman_decode(buf, n).cpu().numpy()
     assert np.array_equal(dec, q)

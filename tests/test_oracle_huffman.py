@@ -102,3 +102,18 @@ def test_single_symbol():
     assert ln[hf.RADIUS] == 1
     stream, off = hf.encode(sym, ln)
     assert np.array_equal(hf.decode(stream, off, ln, len(sym)), sym)
+
+
+def test_outlier_offsets_brute_force():
+    """Per-chunk outlier offsets equal a direct count of escapes before each chunk."""
+    rng = np.random.default_rng(7)
+    n, chunk = 1000, 64
+    q = rng.integers(-10, 10, n)
+    q[rng.choice(n, 37, replace=False)] = 1 << 20
+    sym, oi, ov = hf.to_symbols(q)
+    off = hf.outlier_offsets(oi, n, chunk)
+    nch = (n + chunk - 1) // chunk
+    assert len(off) == nch + 1
+    for c in range(nch + 1):
+        assert off[c] == sum(1 for i in range(min(c * chunk, n)) if sym[i] == 0)
+    assert np.array_equal(hf.from_symbols(sym, oi, ov), q)
