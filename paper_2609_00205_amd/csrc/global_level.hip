@@ -463,10 +463,6 @@ void qcopy(const bm_plan_s& p, const View3& src, const int32_t* csrc, const View
   BM_HIP(hipGetLastError());
 }
 
-__global__ void k_zero_flag(int64_t* f) {
-  if (threadIdx.x == 0) *f = 0;
-}
-
 }  // namespace
 
 void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t st) {
@@ -601,8 +597,7 @@ void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, cons
 
 void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, int32_t* codes, bm_qstats* stats,
                         hipStream_t st) {
-  const QPrep q = quant_prepare(p, block_tol, st);
-  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, q.flag);
+  const QPrep q = quant_prepare(p, block_tol, st);   // also clears the overflow flag
   const View3 xv = dense_view(const_cast<void*>(x), p.dims);
   for (int s = 1; s <= p.L; ++s) {
     const Level& L = p.lv[s - 1];

@@ -107,6 +107,8 @@ struct Workspace {
   double* boxbuf = nullptr;      // device copy of an ROI box list (kMaxBoxes x 7)
   double* boxhost = nullptr;     // pinned staging for the box list
   void* gpad = nullptr;          // dtype, padded grid: level-1 gradient before the pad transpose
+  void* prep_dev = nullptr;      // quantizer preparation of this plan: field record + task prefixes (device)
+  std::vector<uint8_t> prep_key; // field record last uploaded
 };
 
 }  // namespace bm

@@ -387,7 +387,7 @@ void bm_plan_free(bm_plan_s* p) {
   for (void* g : p->ws.grid)
     if (g) (void)hipFree(g);
   for (void* q : {p->ws.t1, p->ws.t2, p->ws.codes, p->ws.coeff, (void*)p->ws.tolbuf, (void*)p->ws.qparam,
-                  (void*)p->ws.counters, (void*)p->ws.boxbuf, p->ws.gpad})
+                  (void*)p->ws.counters, (void*)p->ws.boxbuf, p->ws.gpad, p->ws.prep_dev})
     if (q) (void)hipFree(q);
   if (p->ws.boxhost) (void)hipHostFree(p->ws.boxhost);
   delete p;

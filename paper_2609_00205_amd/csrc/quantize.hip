@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <cstring>
+
 #include "internal.h"
 
 namespace bm {
@@ -136,84 +138,6 @@ __global__ __launch_bounds__(NT) void k_min_all(const double* v, int64_t n, doub
   if (threadIdx.x == 0) atomic_min_pos(out, red[0]);
 }
 
-struct PropArgs {
-  const double* in;
-  int64_t nb[3];        // level s blocks
-  double* out;
-  int64_t nn[3];        // level s+1 blocks
-};
-
-// Eq. 2: next-level block I spans blocks 2I, 2I+1 and touches 2I-1, 2I+2 in a face.
-__global__ void k_propagate(PropArgs a) {
-  const int64_t tot = a.nn[0] * a.nn[1] * a.nn[2];
-  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < tot; k += int64_t(gridDim.x) * NT) {
-    const int64_t X = k % a.nn[2], t = k / a.nn[2], Y = t % a.nn[1], Z = t / a.nn[1];
-    double v = INFINITY;
-    for (int64_t z = i64max(0, 2 * Z - 1); z <= i64min(a.nb[0] - 1, 2 * Z + 2); ++z)
-      for (int64_t y = i64max(0, 2 * Y - 1); y <= i64min(a.nb[1] - 1, 2 * Y + 2); ++y)
-        for (int64_t x = i64max(0, 2 * X - 1); x <= i64min(a.nb[2] - 1, 2 * X + 2); ++x)
-          v = fmin(v, a.in[(z * a.nb[1] + y) * a.nb[2] + x]);
-    a.out[k] = v;
-  }
-}
-
-// per-block Delta and 1/Delta of one local level
-__global__ void k_block_delta(const double* tau, int64_t n, double kappa, double* delta, double* inv) {
-  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT) {
-    const double d = tau[k] * kappa;
-    delta[k] = d;
-    inv[k] = 1.0 / d;
-  }
-}
-
-// Per block and per class of node position (27 classes: first face,
-// interior, last face along z, y and x) the smallest Delta and the largest
-// 1/Delta over the blocks that contain a node of that class: the block
-// itself plus its neighbour across each face the class lies on.
-__global__ void k_class_tables(const double* del, const double* inv, int64_t nb0, int64_t nb1, int64_t nb2,
-                               double* cdel, double* cinv) {
-  const int64_t tot = nb0 * nb1 * nb2 * 27;
-  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < tot; k += int64_t(gridDim.x) * NT) {
-    const int64_t blk = k / 27;
-    const int c = int(k - blk * 27);
-    const int cls[3] = {c / 9, (c / 3) % 3, c % 3};
-    const int64_t bx = blk % nb2, t = blk / nb2;
-    const int64_t b[3] = {t / nb1, t % nb1, bx};
-    const int64_t nb[3] = {nb0, nb1, nb2};
-    int64_t lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = (cls[d] == 0 && b[d] > 0) ? b[d] - 1 : b[d];
-      hi[d] = (cls[d] == 2 && b[d] + 1 < nb[d]) ? b[d] + 1 : b[d];
-    }
-    double dm = INFINITY, im = 0.0;
-    for (int64_t z = lo[0]; z <= hi[0]; ++z)
-      for (int64_t y = lo[1]; y <= hi[1]; ++y)
-        for (int64_t x = lo[2]; x <= hi[2]; ++x) {
-          const int64_t i = (z * nb1 + y) * nb2 + x;
-          dm = fmin(dm, del[i]);
-          im = fmax(im, inv[i]);
-        }
-    cdel[k] = dm;
-    cinv[k] = im;
-  }
-}
-
-// scalar Delta for the global levels and the coarsest values from tau_global
-struct ScalarArgs {
-  const double* tau_global;
-  int n;
-  double kappa[26];
-  double* q;            // q[2 i] = Delta, q[2 i + 1] = 1 / Delta
-};
-
-__global__ void k_scalar_delta(ScalarArgs a) {
-  const int i = threadIdx.x;
-  if (i < a.n) {
-    const double d = a.tau_global[0] * a.kappa[i];
-    a.q[2 * i] = d;
-    a.q[2 * i + 1] = 1.0 / d;
-  }
-}
 
 
 struct QArgs {
@@ -503,48 +427,46 @@ QPrep qprep_layout(bm_plan_s& p, const double* block_tol) {
   return a;
 }
 
+// One plan's tables are built by the many-field kernels with one field: one
+// launch per propagation step, one per table level, one for tau_global and
+// the scalar Deltas (which also clears the overflow flag).  The field record
+// is uploaded only when it changes (a new tolerance map pointer).
 QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   const QPrep a = qprep_layout(p, block_tol);
-  const double eta = p.cfg.eta;
-  const std::vector<double> w = level_weights(p);
-  double* tau = p.ws.tolbuf;
-  double* tg = p.ws.tolbuf + 3 * p.ws.tol_off[p.L + 1];
-  // level-1 taus are the caller's map; deeper local levels live in tolbuf
-  auto taus = [&](int s) -> const double* { return s == 1 ? block_tol : tau + p.ws.tol_off[s]; };
-  if (p.L > 0) {
-    for (int s = 1; s < p.L; ++s) {
-      PropArgs pa{taus(s), {}, tau + p.ws.tol_off[s + 1], {}};
-      for (int d = 0; d < 3; ++d) {
-        pa.nb[d] = p.lv[s - 1].nb[d];
-        pa.nn[d] = p.lv[s].nb[d];
-      }
-      hipLaunchKernelGGL(k_propagate, dim3(grid_for(prod3(pa.nn))), dim3(NT), 0, st, pa);
+  const PrepField f = prep_field(p, block_tol, a);
+  constexpr size_t kFirst = 2048;                   // offset of the task prefix arrays
+  static_assert(sizeof(PrepField) <= kFirst, "field record too large");
+  int64_t cnt_prop[9] = {}, cnt_tab[9] = {};
+  for (int s = 1; s < 9; ++s) cnt_prop[s] = p.L > s ? prod3(p.lv[s].nb) : 0;
+  for (int s = 1; s < 9; ++s) cnt_tab[s] = p.L >= s ? 27 * prod3(p.lv[s - 1].nb) : 0;
+  cnt_tab[0] = (p.L > 0 && p.M == 0) ? 27 * prod3(p.lv[p.L - 1].nb) : 0;
+  if (!p.ws.prep_dev) {
+    std::vector<int64_t> first(4 * 9);
+    for (int s = 0; s < 9; ++s) {
+      first[2 * s] = 0;
+      first[2 * s + 1] = cnt_prop[s];
+      first[18 + 2 * s] = 0;
+      first[18 + 2 * s + 1] = cnt_tab[s];
     }
-    auto tables = [&](const QTab& t, const double* ts, double kap) {
-      const int64_t nbs = prod3(t.nb);
-      hipLaunchKernelGGL(k_block_delta, dim3(grid_for(nbs)), dim3(NT), 0, st, ts, nbs, kap, const_cast<double*>(t.del),
-                         const_cast<double*>(t.inv));
-      hipLaunchKernelGGL(k_class_tables, dim3(grid_for(27 * nbs)), dim3(NT), 0, st, t.del, t.inv, t.nb[0], t.nb[1],
-                         t.nb[2], const_cast<double*>(t.cdel), const_cast<double*>(t.cinv));
-    };
-    for (int s = 1; s <= p.L; ++s) tables(a.lv[s - 1], taus(s), (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain);
-    // coarsest values when M == 0: Delta = tau * 2 (1 - eta) w_c
-    if (p.M == 0) tables(a.lv[kCoarseSlotHost], taus(p.L), (2.0 * (1.0 - eta)) * w[p.nlev]);
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
-    const int64_t nlast = prod3(p.lv[p.L - 1].nb);
-    hipLaunchKernelGGL(k_min_all, dim3(grid_for(nlast)), dim3(NT), 0, st, taus(p.L), nlast, tg);
-  } else {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(NT), 0, st, tg, int64_t(1), double(INFINITY));
-    hipLaunchKernelGGL(k_min_all, dim3(1), dim3(NT), 0, st, block_tol, int64_t(1), tg);
+    BM_HIP(hipMalloc(&p.ws.prep_dev, kFirst + first.size() * sizeof(int64_t)));
+    BM_HIP(hipMemcpy(static_cast<uint8_t*>(p.ws.prep_dev) + kFirst, first.data(), first.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice));
   }
-  ScalarArgs sa{};
-  sa.tau_global = tg;
-  sa.n = p.nlev + 1;
-  for (int s = 1; s <= p.nlev; ++s) sa.kappa[s - 1] = (2.0 * (1.0 - eta)) * w[s - 1] / p.lv[s - 1].gain;
-  sa.kappa[p.nlev] = (2.0 * (1.0 - eta)) * w[p.nlev];
-  sa.q = p.ws.qparam;
-  hipLaunchKernelGGL(k_scalar_delta, dim3(1), dim3(64), 0, st, sa);
-  BM_HIP(hipGetLastError());
+  const uint8_t* fb = reinterpret_cast<const uint8_t*>(&f);
+  if (p.ws.prep_key.size() != sizeof(f) || std::memcmp(p.ws.prep_key.data(), fb, sizeof(f)) != 0) {
+    BM_HIP(hipMemcpyAsync(p.ws.prep_dev, fb, sizeof(f), hipMemcpyHostToDevice, st));
+    BM_HIP(hipStreamSynchronize(st));
+    p.ws.prep_key.assign(fb, fb + sizeof(f));
+  }
+  PrepStages g;
+  const int64_t* first = reinterpret_cast<const int64_t*>(static_cast<uint8_t*>(p.ws.prep_dev) + kFirst);
+  for (int s = 0; s < 9; ++s) {
+    g.prop_first[s] = first + 2 * s;
+    g.prop_n[s] = cnt_prop[s];
+    g.tab_first[s] = first + 18 + 2 * s;
+    g.tab_n[s] = cnt_tab[s];
+  }
+  launch_prep_batch(g, static_cast<const PrepField*>(p.ws.prep_dev), 1, st);
   return a;
 }
 
