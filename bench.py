@@ -33,8 +33,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_local_decompose_512cubed_
 
 
 def _src_hash() -> str:
-    p = os.path.join(ROOT, "paper_2609_00205_amd", "csrc", "local_level.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the block kernel is built from."""
+    h = hashlib.sha256()
+    for name in ("local_level.hip", "block.h"):
+        h.update(open(os.path.join(ROOT, "paper_2609_00205_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(nbytes_alg: float):

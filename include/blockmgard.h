@@ -65,9 +65,12 @@ typedef enum { BM_F32 = 0, BM_F64 = 1 } bm_dtype;
  *   ndim     3 (1 and 2 are accepted as 3D with leading unit dims)
  *   dims     logical dims {nz, ny, nx}
  *   dtype    BM_F32 or BM_F64: the type of data and coefficients
- *   block    b in {9, 17}: nodes per block side of the local levels
+ *   block    b in {9, 17, 33}: nodes per block side of the local levels
  *            (blocks of 2^k+1 nodes share one face with each neighbour);
- *            ignored when L == 0
+ *            ignored when L == 0.  b = 33 runs each block level as two
+ *            launches (three when recomposing) through a plan-owned scratch
+ *            array, and is not taken by the transposes (bm_*_adjoint,
+ *            bm_qoi_deltas) or by batches: those return BM_EUNSUPPORTED
  *   L, M     number of local (In-cache Block) and global levels (Sec. IV-B)
  *   pad_mode 0 = clamp (padded nodes copy the nearest node), 1 = zero fill
  *   eta      safety share of every tolerance kept back for working-precision
@@ -264,7 +267,8 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
  * stream other than the null stream.  The batch owns one plan per field
  * (bm_batch_plan borrows it: coefficient shapes, tolerance maps); a batch is
  * used from one stream at a time.  Errors: BM_EINVAL (mixed dtype or block
- * size, null pointers), BM_ENOMEM. */
+ * size, null pointers), BM_EUNSUPPORTED (b = 33 with block levels),
+ * BM_ENOMEM. */
 typedef struct bm_batch_s* bm_batch;
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out);
 bm_status bm_batch_destroy(bm_batch batch);

@@ -174,8 +174,8 @@ struct DecTArgs {
 };
 
 template <typename T, int B>
-__global__ __launch_bounds__(Geo<B>::NT) void k_local_decompose_T(DecTArgs<T> a) {
-  using G = Geo<B>;
+__global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) void k_local_decompose_T(DecTArgs<T> a) {
+  using G = Geo<B, sizeof(T)>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   __shared__ T lds[NB * G::ADJ_LDS];
   const int64_t g = xcd_group(blockIdx.x, a.c.per);
@@ -254,8 +254,8 @@ struct RecTArgs {
 };
 
 template <typename T, int B>
-__global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose_T(RecTArgs<T> a) {
-  using G = Geo<B>;
+__global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) void k_local_recompose_T(RecTArgs<T> a) {
+  using G = Geo<B, sizeof(T)>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   __shared__ T lds[NB * G::ADJ_LDS];
   const int64_t g = xcd_group(blockIdx.x, a.c.per);
@@ -336,7 +336,7 @@ ColorSet color_set(const Level& L, int color, int nb_per_wg) {
 
 template <typename T, int B>
 void launch_local_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out, hipStream_t st) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T)>;
   const Level& L = p.lv[s - 1];
   DecTArgs<T> a{};
   const View3 cv = level_view(p, s, const_cast<void*>(gcoeff));
@@ -359,7 +359,7 @@ void launch_local_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out
 template <typename T, int B>
 void launch_local_rec_T(const bm_plan_s& p, int s, const void* gin, const int64_t in[3], const int64_t lim[3],
                         void* gcoeff, hipStream_t st) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T)>;
   const Level& L = p.lv[s - 1];
   RecTArgs<T> a{};
   const View3 cv = level_view(p, s, gcoeff);
@@ -724,6 +724,7 @@ void recompose_adjoint_t(bm_plan_s& p, const void* gx, void* gcoeff, hipStream_t
 }  // namespace
 
 void decompose_adjoint(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t st) {
+  if (p.L > 0 && p.cfg.block == 33) fail(BM_EUNSUPPORTED, "the transposes take b = 9 or 17");
   if (p.cfg.dtype == BM_F32)
     decompose_adjoint_t<float>(p, gcoeff, gx, st);
   else
@@ -731,6 +732,7 @@ void decompose_adjoint(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t s
 }
 
 void recompose_adjoint(bm_plan_s& p, const void* gx, void* gcoeff, hipStream_t st) {
+  if (p.L > 0 && p.cfg.block == 33) fail(BM_EUNSUPPORTED, "the transposes take b = 9 or 17");
   if (p.cfg.dtype == BM_F32)
     recompose_adjoint_t<float>(p, gx, gcoeff, st);
   else

@@ -105,7 +105,7 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
     cands.push_back(k);
   };
   for (int M = 1; M <= 6; ++M) consider(0, 0, M);
-  for (int block : {9, 17})
+  for (int block : {9, 17, 33})
     for (int L = 1; L <= 4; ++L)
       for (int M = 0; M <= 4; ++M) consider(block, L, M);
   if (cands.empty()) fail(BM_EINVAL, "no admissible (block, L, M) for these dims");

@@ -130,7 +130,7 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
         void* out = s == 1 ? const_cast<void*>(x[f]) : p.ws.grid[s - 1];
         block_rec_args(p, s, nullptr, p.ws.grid[s], out, s == 1, codes[f], &B.q[f], dst);
       }
-      first.push_back(first.back() + block_groups(p, s));
+      first.push_back(first.back() + block_groups(p, s, dec));
     }
     B.nf[s] = int(first.size()) - 1;
     B.ntasks[s] = first.back();
@@ -207,6 +207,8 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
     for (int f = 0; f < nfields; ++f) {
       if (f > 0 && (cfgs[f].dtype != cfgs[0].dtype || cfgs[f].block != cfgs[0].block))
         fail(BM_EINVAL, "all fields of a batch share dtype and block size");
+      if (cfgs[f].L > 0 && cfgs[f].block == 33)
+        fail(BM_EUNSUPPORTED, "batched block levels take b = 9 or 17 (a 33^3 block needs several launches)");
       b->plans.push_back(bm_plan_build(&cfgs[f]));
       b->Lmax = std::max(b->Lmax, b->plans.back()->L);
     }

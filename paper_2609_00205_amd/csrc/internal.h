@@ -154,6 +154,17 @@ void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, vo
 void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* coarse_in, void* out,
                      bool last, hipStream_t st);
 
+// block levels with b = 33 (local_decompose / local_recompose and their
+// quantized forms dispatch here): scratch values the plan keeps in ws.t1 for
+// a level of nb blocks; the recomposition turns the compact coarse grid cin
+// into u_C in place
+struct QPrep;
+size_t wide_scratch_elems(const int64_t nb[3]);
+void wide_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
+                    const QPrep* q, hipStream_t st);
+void wide_recompose(const bm_plan_s& p, int s, const void* coeff, void* cin, void* out, bool last,
+                    const int32_t* codes, const QPrep* q, hipStream_t st);
+
 // global level pieces
 void global_details(const bm_plan_s& p, int s, const void* u, void* coeff, hipStream_t st);
 void global_interp_add(const bm_plan_s& p, int s, const void* coeff, const void* uc, void* out,
@@ -239,7 +250,7 @@ void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const vo
 // many fields per launch (block levels): per-field kernel arguments are
 // built on the host (block_*_args writes block_args_size bytes), uploaded,
 // and one persistent launch covers block_groups(p_f, s) groups of every field
-int64_t block_groups(const bm_plan_s& p, int s);
+int64_t block_groups(const bm_plan_s& p, int s, bool dec);
 size_t block_args_size(const bm_plan_s& p, bool dec);
 void block_dec_args(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
                     const QPrep* q, void* out);

@@ -28,25 +28,6 @@
 namespace bm {
 namespace {
 
-// Restriction by the interior rows of P^T M (centre 2J+2) followed by the
-// interior tridiagonal solve, on a line of B values: out[J], J < MI.
-template <typename T, int B>
-__device__ inline void restrict_solve(const T (&w)[B], T (&out)[Geo<B>::MI]) {
-  constexpr int MI = Geo<B>::MI;
-  constexpr Pivots<MI> P{};
-  const T C0 = T(5.0 / 6.0), C1 = T(0.5), C2 = T(1.0 / 12.0);
-  T d[MI];
-#pragma unroll
-  for (int J = 0; J < MI; ++J) {
-    const int c = 2 * J + 2;
-    const T r = C2 * (w[c - 2] + w[c + 2]) + C1 * (w[c - 1] + w[c + 1]) + C0 * w[c];
-    d[J] = J == 0 ? T(3) * r * T(P.v[0]) : (T(3) * r - d[J - 1]) * T(P.v[J]);
-  }
-  out[MI - 1] = d[MI - 1];
-#pragma unroll
-  for (int J = MI - 2; J >= 0; --J) out[J] = d[J] - T(P.v[J]) * out[J + 1];
-}
-
 // y and x passes of the correction: T1[MI][B][B] -> T2[MI][MI][B] -> Z[MI][MI][MI]
 template <typename T, int B>
 __device__ inline void pass_y(const T* T1, T* T2, int tb) {
@@ -115,46 +96,6 @@ struct RecArgs {
   int coarsest_here;
 };
 
-// block coordinates of block index blk
-__device__ inline void block_coords(uint32_t blk, const FastDiv& f2, const FastDiv& f1, const int64_t nb[3],
-                                    int64_t& bz, int64_t& by, int64_t& bx) {
-  const uint32_t t = f2.div(blk);
-  bx = int64_t(blk) - int64_t(t) * nb[2];
-  const uint32_t z = f1.div(t);
-  by = int64_t(t) - int64_t(z) * nb[1];
-  bz = z;
-}
-
-// position class of a local coordinate: first face 0, interior 1, last face 2
-template <int B>
-__device__ inline int pos_class(int c) {
-  return c == 0 ? 0 : (c == B - 1 ? 2 : 1);
-}
-
-// The Delta-table entries (27 classes per block) of one z-column: a node takes
-// the smallest Delta (largest 1/Delta) of the blocks that contain it.  Entries
-// for z = 0, for 0 < z < B-1 and for z = B-1.
-template <int B>
-__device__ inline void column_class(const double* tab, int64_t blk, int y, int x, double out[3]) {
-  const double* t = tab + blk * 27 + pos_class<B>(y) * 3 + pos_class<B>(x);
-  out[0] = t[0];
-  out[1] = t[9];
-  out[2] = t[18];
-}
-
-template <int B>
-__device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
-
-// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag.
-// skip: a placeholder (zero) is written instead and nothing is checked.
-template <typename T>
-__device__ inline int32_t quant(T c, double inv, bool skip, bool& bad) {
-  const double v = rint(mul_rn(double(c), inv));
-  const bool ok = fabs(v) <= 2147483647.0;
-  bad |= !ok && !skip;
-  return (ok && !skip) ? int32_t(v) : 0;
-}
-
 // Register budget of the block decomposition: FP32 fits 64 VGPRs (8 waves per
 // SIMD), so more blocks are in flight to cover HBM latency; FP64 columns need
 // twice the space.
@@ -164,7 +105,7 @@ constexpr int kWavesPerEU = sizeof(T) == 4 ? 8 : 4;
 // One workgroup's block group g (NB blocks) of a decomposition level.
 template <typename T, int B, bool Q>
 __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T)>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   const int tid = threadIdx.x;
   const int bl = tid / BB;                           // block within the workgroup
@@ -290,7 +231,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
 // One workgroup's block group g of a recomposition level.
 template <typename T, int B, bool Q>
 __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T), false>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   const int tid = threadIdx.x;
   const int bl = tid / BB;
@@ -397,16 +338,16 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
 }
 
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
-  __shared__ T lds[Geo<B>::NB * Geo<B>::DEC_LDS];
+__global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
+  __shared__ T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];
   const int64_t g = xcd_group(blockIdx.x, a.per);
   if (g >= a.nwg) return;
   decompose_group<T, B, Q>(a, g, lds);
 }
 
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) void k_local_recompose(RecArgs<T> a) {
-  __shared__ T lds[Geo<B>::NB * Geo<B>::REC_LDS];
+__global__ __launch_bounds__((Geo<B, sizeof(T), false>::NT)) void k_local_recompose(RecArgs<T> a) {
+  __shared__ T lds[Geo<B, sizeof(T), false>::NB * Geo<B>::REC_LDS];
   const int64_t g = xcd_group(blockIdx.x, a.per);
   if (g >= a.nwg) return;
   recompose_group<T, B, Q>(a, g, lds);
@@ -428,9 +369,9 @@ __device__ inline int field_of(const int64_t* first, int nf, int64_t k) {
 }
 
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_batch_decompose(
+__global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_batch_decompose(
     const DecArgs<T>* fa, const int64_t* first, int nf, int64_t ntasks) {
-  __shared__ T lds[Geo<B>::NB * Geo<B>::DEC_LDS];
+  __shared__ T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const int f = field_of(first, nf, k);
     decompose_group<T, B, Q>(fa[f], k - first[f], lds);
@@ -439,9 +380,10 @@ __global__ __launch_bounds__(Geo<B>::NT) __attribute__((amdgpu_waves_per_eu(kWav
 }
 
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__(Geo<B>::NT) void k_batch_recompose(const RecArgs<T>* fa, const int64_t* first, int nf,
-                                                                int64_t ntasks) {
-  __shared__ T lds[Geo<B>::NB * Geo<B>::REC_LDS];
+__global__ __launch_bounds__((Geo<B, sizeof(T), false>::NT)) void k_batch_recompose(const RecArgs<T>* fa,
+                                                                              const int64_t* first, int nf,
+                                                                              int64_t ntasks) {
+  __shared__ T lds[Geo<B, sizeof(T), false>::NB * Geo<B>::REC_LDS];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const int f = field_of(first, nf, k);
     recompose_group<T, B, Q>(fa[f], k - first[f], lds);
@@ -458,7 +400,7 @@ inline uint32_t column_stride(int64_t s, int B) {
 template <typename T, int B>
 DecArgs<T> dec_args(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
                     const QPrep* q) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T)>;
   const Level& L = p.lv[s - 1];
   DecArgs<T> a{};
   a.src = static_cast<const T*>(src.ptr);
@@ -496,7 +438,7 @@ DecArgs<T> dec_args(const bm_plan_s& p, int s, const View3& src, bool first, voi
 template <typename T, int B>
 void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
                 const QPrep* q, hipStream_t st) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T)>;
   const DecArgs<T> a = dec_args<T, B>(p, s, src, first, coeff, cout, codes, q);
   if (q)
     hipLaunchKernelGGL((k_local_decompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
@@ -508,7 +450,7 @@ void launch_dec(const bm_plan_s& p, int s, const View3& src, bool first, void* c
 template <typename T, int B>
 RecArgs<T> rec_args(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
                     const int32_t* codes, const QPrep* q) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T), false>;
   const Level& L = p.lv[s - 1];
   RecArgs<T> a{};
   a.coeff = static_cast<const T*>(coeff);
@@ -547,7 +489,7 @@ RecArgs<T> rec_args(const bm_plan_s& p, int s, const void* coeff, const void* ci
 template <typename T, int B>
 void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
                 const int32_t* codes, const QPrep* q, hipStream_t st) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T), false>;
   const RecArgs<T> a = rec_args<T, B>(p, s, coeff, cin, out, last, codes, q);
   if (q)
     hipLaunchKernelGGL((k_local_recompose<T, B, true>), dim3(unsigned(8 * a.per)), dim3(G::NT), 0, st, a);
@@ -570,7 +512,7 @@ unsigned resident_grid(K kernel, int nt, int64_t ntasks) {
 template <typename T, int B>
 void launch_batch(bool dec, bool quant, const void* args, const int64_t* first, int nf, int64_t ntasks,
                   hipStream_t st) {
-  using G = Geo<B>;
+  using G = Geo<B, sizeof(T)>;
   if (ntasks <= 0) return;
   if (dec) {
     const auto* fa = static_cast<const DecArgs<T>*>(args);
@@ -582,13 +524,14 @@ void launch_batch(bool dec, bool quant, const void* args, const int64_t* first, 
       hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
     }
   } else {
+    using R = Geo<B, sizeof(T), false>;
     const auto* fa = static_cast<const RecArgs<T>*>(args);
     if (quant) {
       auto k = k_batch_recompose<T, B, true>;
-      hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
+      hipLaunchKernelGGL(k, dim3(resident_grid(k, R::NT, ntasks)), dim3(R::NT), 0, st, fa, first, nf, ntasks);
     } else {
       auto k = k_batch_recompose<T, B, false>;
-      hipLaunchKernelGGL(k, dim3(resident_grid(k, G::NT, ntasks)), dim3(G::NT), 0, st, fa, first, nf, ntasks);
+      hipLaunchKernelGGL(k, dim3(resident_grid(k, R::NT, ntasks)), dim3(R::NT), 0, st, fa, first, nf, ntasks);
     }
   }
   BM_HIP(hipGetLastError());
@@ -616,7 +559,9 @@ void dispatch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin,
 
 void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* coarse_out,
                      hipStream_t st) {
-  if (p.cfg.block == 9)
+  if (p.cfg.block == 33)
+    wide_decompose(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
+  else if (p.cfg.block == 9)
     dispatch_dec<9>(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
   else
     dispatch_dec<17>(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
@@ -624,7 +569,9 @@ void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, vo
 
 void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* coarse_in, void* out, bool last,
                      hipStream_t st) {
-  if (p.cfg.block == 9)
+  if (p.cfg.block == 33)
+    wide_recompose(p, s, coeff, const_cast<void*>(coarse_in), out, last, nullptr, nullptr, st);
+  else if (p.cfg.block == 9)
     dispatch_rec<9>(p, s, coeff, coarse_in, out, last, nullptr, nullptr, st);
   else
     dispatch_rec<17>(p, s, coeff, coarse_in, out, last, nullptr, nullptr, st);
@@ -632,7 +579,9 @@ void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* c
 
 void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, int32_t* codes, void* coarse_out,
                        const QPrep& q, hipStream_t st) {
-  if (p.cfg.block == 9)
+  if (p.cfg.block == 33)
+    wide_decompose(p, s, src, first, nullptr, coarse_out, codes, &q, st);
+  else if (p.cfg.block == 9)
     dispatch_dec<9>(p, s, src, first, nullptr, coarse_out, codes, &q, st);
   else
     dispatch_dec<17>(p, s, src, first, nullptr, coarse_out, codes, &q, st);
@@ -640,14 +589,17 @@ void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, 
 
 void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const void* coarse_in, void* out, bool last,
                        const QPrep& q, hipStream_t st) {
-  if (p.cfg.block == 9)
+  if (p.cfg.block == 33)
+    wide_recompose(p, s, nullptr, const_cast<void*>(coarse_in), out, last, codes, &q, st);
+  else if (p.cfg.block == 9)
     dispatch_rec<9>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
   else
     dispatch_rec<17>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
 }
 
-int64_t block_groups(const bm_plan_s& p, int s) {
-  const int nbw = p.cfg.block <= 9 ? Geo<9>::NB : Geo<17>::NB;
+int64_t block_groups(const bm_plan_s& p, int s, bool dec) {
+  const int nbw = p.cfg.block <= 9 ? Geo<9>::NB
+                                   : (p.esize == 4 ? (dec ? Geo<17, 4, true>::NB : Geo<17, 4, false>::NB) : Geo<17, 8>::NB);
   const int64_t* nb = p.lv[s - 1].nb;
   return (nb[0] * nb[1] * nb[2] + nbw - 1) / nbw;
 }

@@ -266,7 +266,7 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
   if (c->ndim < 1 || c->ndim > 3) fail(BM_EINVAL, "ndim must be 1, 2 or 3");
   if (c->dtype != BM_F32 && c->dtype != BM_F64) fail(BM_EINVAL, "dtype must be BM_F32 or BM_F64");
   if (c->L < 0 || c->M < 0 || c->L + c->M < 1 || c->L + c->M > 24) fail(BM_EINVAL, "need 1 <= L+M <= 24");
-  if (c->L > 0 && c->block != 9 && c->block != 17) fail(BM_EINVAL, "block must be 9 or 17");
+  if (c->L > 0 && c->block != 9 && c->block != 17 && c->block != 33) fail(BM_EINVAL, "block must be 9, 17 or 33");
   if (c->pad_mode != 0 && c->pad_mode != 1) fail(BM_EINVAL, "pad_mode must be 0 (clamp) or 1 (zero)");
   if (!(c->eta >= 0.0 && c->eta < 0.5)) fail(BM_EINVAL, "eta must lie in [0, 0.5)");
   // ndim < 3: dims[0..ndim-1] become the trailing axes
@@ -329,7 +329,10 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
       BM_HIP(hipMalloc(&p->ws.grid[s], size_t(prod3(p->lv[s - 1].m)) * p->esize));
     size_t t = 0;
     for (auto& L : p->lv) {
-      if (L.local) continue;
+      if (L.local) {
+        if (b == 33) t = std::max(t, wide_scratch_elems(L.nb));   // y-pass result of the 33^3 blocks
+        continue;
+      }
       t = std::max<size_t>(t, size_t(L.n[0]) * L.n[1] * L.m[2]);
       t = std::max<size_t>(t, size_t(L.n[0]) * L.m[1] * L.m[2]);
     }

@@ -630,7 +630,9 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool tables
   }
   a.L = p.L;
   a.M = p.M;
-  a.lw = p.L > 0 ? (p.cfg.block == 17 ? 4 : 3) : 0;
+  a.lw = 0;
+  if (p.L > 0)
+    while ((1 << a.lw) < p.cfg.block - 1) ++a.lw;
   a.counters = p.ws.counters;
   for (int k = 0; k < 9; ++k) {
     a.bdelta[k] = qp.lv[k].del;

@@ -28,6 +28,11 @@ CASES = [
     ((65, 33, 49), 17, 1, 0, torch.float32, "clamp"),     # pure local
     ((97, 65, 129), 17, 1, 2, torch.float32, "clamp"),    # 6 x 4 x 8 blocks, global lines of 65
     ((40, 50, 61), 9, 2, 2, torch.float32, "clamp"),      # ragged everywhere
+    ((65, 65, 65), 33, 1, 2, torch.float32, "clamp"),     # 33^3 blocks
+    ((70, 40, 100), 33, 1, 1, torch.float64, "zero"),     # 33^3 blocks, ragged: padded to 97 x 65 x 129
+    ((70, 40, 100), 33, 1, 1, torch.float32, "clamp"),
+    ((65, 65, 129), 33, 2, 1, torch.float64, "clamp"),    # two 33^3 block levels
+    ((65, 33, 65), 33, 1, 0, torch.float32, "clamp"),     # 33^3 blocks, pure local
 ]
 
 

@@ -80,9 +80,9 @@ def _multilinear(shape):
     return 1.5 + 2 * x + 3 * y - z + 0.5 * x * y - 0.25 * y * z + 0.1 * x * z + 0.01 * x * y * z
 
 
-@pytest.mark.parametrize("b,L,M", [(9, 1, 1), (17, 1, 2), (9, 2, 1), (9, 0, 3)])
+@pytest.mark.parametrize("b,L,M", [(9, 1, 1), (17, 1, 2), (9, 2, 1), (9, 0, 3), (33, 1, 1)])
 def test_multilinear_details_vanish(b, L, M):
-    shape = (33, 33, 33) if b == 17 else (33, 17, 33)
+    shape = {17: (33, 33, 33), 33: (65, 33, 65)}.get(b, (33, 17, 33))
     f = _multilinear(shape)
     c = mgard.decompose(f, b, L, M)
     lev = mgard.node_level(c.shape, L, M)
@@ -142,9 +142,34 @@ def test_block_level_is_dirichlet_constrained_projection(b, rng):
     assert np.allclose(out[cid].ravel(), c, atol=1e-12)
 
 
+def test_block_level_33_is_dirichlet_constrained_projection(rng):
+    # b = 33: the same constrained projection, with the tensor-product
+    # operators applied axis by axis (the dense P3 would hold 35937 x 4913 entries)
+    b = 33
+    u = rng.standard_normal((b, b, b))
+    coords = [np.arange(float(b))] * 3
+    out = mgard.level_decompose(u, coords, True)
+    o = mgard.axis_ops(coords[0], False)
+    m = len(o.cidx)
+    M1 = mgard.mass_matrix(coords[0])
+    A1 = o.P.T @ M1 @ o.P
+    A = _kron3([A1] * 3)
+    R = o.P.T @ M1
+    rhs = np.einsum("ai,bj,ck,ijk->abc", R, R, R, u, optimize=True).ravel()
+    ci = np.arange(m)
+    inner1 = (ci > 0) & (ci < m - 1)
+    inner = (inner1[:, None, None] & inner1[None, :, None] & inner1[None, None, :]).ravel()
+    uc = u[np.ix_(o.cidx, o.cidx, o.cidx)].ravel()
+    c = uc.copy()
+    c[inner] = np.linalg.solve(A[np.ix_(inner, inner)], rhs[inner] - A[np.ix_(inner, ~inner)] @ uc[~inner])
+    cid = np.ix_(o.cidx, o.cidx, o.cidx)
+    assert np.allclose(out[cid].ravel(), c, atol=1e-12)
+
+
 @pytest.mark.parametrize("shape,b,L,M", [((33, 33, 33), 17, 1, 2), ((33, 17, 65), 9, 2, 1),
                                           ((9, 9, 9), 9, 0, 3), ((20, 30, 12), 9, 1, 1),
-                                          ((65, 33, 33), 17, 1, 0), ((17, 17, 17), 9, 1, 1)])
+                                          ((65, 33, 33), 17, 1, 0), ((17, 17, 17), 9, 1, 1),
+                                          ((70, 40, 100), 33, 1, 1), ((65, 65, 129), 33, 2, 1)])
 def test_reconstruction(shape, b, L, M, rng):
     x = rng.standard_normal(shape)
     c = mgard.decompose(x, b, L, M)
@@ -194,7 +219,8 @@ def test_block_coarse_grid_is_global_coarse_grid():
 
 
 @pytest.mark.parametrize("n,b,L,M,expect", [(512, 17, 1, 2, 513), (65, 17, 0, 6, 65), (500, 9, 1, 2, 505),
-                                            (100, 17, 1, 4, 129), (33, 17, 1, 5, 33)])
+                                            (100, 17, 1, 4, 129), (33, 17, 1, 5, 33), (512, 33, 1, 2, 513),
+                                            (1000, 33, 1, 2, 1025), (70, 33, 1, 1, 97)])
 def test_padding_rule(n, b, L, M, expect):
     assert mgard.padded_length(n, b, L, M) == expect
 
