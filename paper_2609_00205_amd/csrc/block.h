@@ -72,6 +72,22 @@ __device__ inline void restrict_solve(const T (&w)[B], T (&out)[Geo<B>::MI]) {
   for (int J = MI - 2; J >= 0; --J) out[J] = d[J] - T(P.v[J]) * out[J + 1];
 }
 
+// The next level's interpolant along one column (p, q) of a block's coarse
+// grid (MC nodes per axis): out[j], j < MC.  rd(J, P, Q) reads the next
+// level's coarse node (2J, 2P, 2Q).  The y-x means of the even planes come
+// first (x pairs, then y), then pairs along z; the scalings by 1/4 and 1/2
+// are exact, so out[j] equals cell_mean over the node's cell bit for bit.
+template <typename T, int MC, typename F>
+__device__ inline void column_interp(int p, int q, F rd, T (&out)[MC]) {
+  constexpr int H = (MC + 1) / 2;
+  const int p0 = p >> 1, p1 = (p + 1) >> 1, q0 = q >> 1, q1 = (q + 1) >> 1;
+  T I2[H];
+#pragma unroll
+  for (int J = 0; J < H; ++J) I2[J] = T(0.25) * ((rd(J, p0, q0) + rd(J, p0, q1)) + (rd(J, p1, q0) + rd(J, p1, q1)));
+#pragma unroll
+  for (int j = 0; j < MC; ++j) out[j] = (j & 1) ? T(0.5) * (I2[j >> 1] + I2[(j >> 1) + 1]) : I2[j >> 1];
+}
+
 // block coordinates of block index blk
 __device__ inline void block_coords(uint32_t blk, const FastDiv& f2, const FastDiv& f1, const int64_t nb[3],
                                     int64_t& bz, int64_t& by, int64_t& bx) {

@@ -80,9 +80,7 @@ struct Cell {
   T c[2][2][2];   // corners c + (0|1, 0|1, 0|1); index 1 only where the offset exists
   int oz, oy, ox; // offset 1 exists along the axis
   __device__ inline T interp(int dz, int dy, int dx) const {
-    const T s = ((c[0][0][0] + c[0][0][dx]) + (c[0][dy][0] + c[0][dy][dx])) +
-                ((c[dz][0][0] + c[dz][0][dx]) + (c[dz][dy][0] + c[dz][dy][dx]));
-    return s * T(0.125);
+    return cell_mean<T>(dz, dy, dx, [&](int az, int ay, int ax) { return c[az][ay][ax]; });
   }
 };
 
@@ -534,7 +532,8 @@ void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
       } else {
         u = p.ws.grid[s - 1];
       }
-      global_details(p, s, u, coeff, st);
+      // (the first global level's details come from the last block level when fused)
+      if (!(p.fuse_next && s == p.L + 1)) global_details(p, s, u, coeff, st);
       apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
     }
   }
@@ -552,8 +551,10 @@ void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
       void* out = s == 1 ? x : p.ws.grid[s - 1];
       local_recompose(p, s, coeff, p.ws.grid[s], out, s == 1, st);
     } else {
-      // u_C = c - K3 w in place in grid[s], then u = interpolant + w
+      // u_C = c - K3 w in place in grid[s], then u = interpolant + w (which
+      // the last block level does itself when fused)
       apply_K3(p, s, level_view(p, s, const_cast<void*>(coeff)), true, p.ws.grid[s], p.ws.grid[s], st);
+      if (p.fuse_next && s == p.L + 1) continue;
       void* out = p.ws.grid[s - 1];
       global_interp_add(p, s, coeff, p.ws.grid[s], out, st);
       if (s == 1) {
@@ -582,10 +583,13 @@ void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, cons
     } else {
       u = p.ws.grid[s - 1];
     }
-    if (p.cfg.dtype == BM_F32)
+    if (p.fuse_next && s == p.L + 1) {
+      // details (codes) already written by the last block level
+    } else if (p.cfg.dtype == BM_F32) {
       launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
-    else
+    } else {
       launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+    }
     apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
   }
   if (p.M > 0 || p.L == 0) {
@@ -628,6 +632,7 @@ void dequantize_recompose_global(bm_plan_s& p, const int32_t* codes, const QPrep
     TimedScope ts(p, 2 * (s - 1) + 1, st);
     const double* qdel = q.q + 2 * (s - 1);
     apply_K3(p, s, level_view(p, s, const_cast<int32_t*>(codes)), true, p.ws.grid[s], p.ws.grid[s], st, codes, qdel);
+    if (p.fuse_next && s == p.L + 1) continue;   // the last block level interpolates
     void* out = p.ws.grid[s - 1];
     if (p.cfg.dtype == BM_F32)
       launch_interp<float>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);

@@ -62,6 +62,18 @@ __device__ inline double mul_rn(double a, double b) {
   return a * b;
 }
 
+// Multilinear interpolant at offset (dz, dy, dx) in {0,1}^3 of a cell of a
+// level's coarse grid: rd(az, ay, ax) reads corner (az, ay, ax), and only
+// az <= dz, ay <= dy, ax <= dx are read.  The 8-term sum in this fixed order
+// (pairs along x, then y, then z) is used wherever a level's details or its
+// inverse are formed, so every kernel produces the same bits.
+template <typename T, typename F>
+__device__ inline T cell_mean(int dz, int dy, int dx, F rd) {
+  const T s = ((rd(0, 0, 0) + rd(0, 0, dx)) + (rd(0, dy, 0) + rd(0, dy, dx))) +
+              ((rd(dz, 0, 0) + rd(dz, 0, dx)) + (rd(dz, dy, 0) + rd(dz, dy, dx)));
+  return s * T(0.125);
+}
+
 __host__ __device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
 __host__ __device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
 
@@ -138,6 +150,10 @@ struct bm_plan_s {
   std::vector<bm::Level> lv;     // lv[0] is level 1
   bm::Workspace ws;
   int64_t nb1[3];                // level-1 block grid (1,1,1 when L == 0)
+  // the last block level also forms the details of the first global level
+  // (decomposition) and its interpolation (recomposition): a global cell of
+  // that level never crosses a block face (b = 9, 17 with M >= 1)
+  bool fuse_next = false;
 };
 
 namespace bm {

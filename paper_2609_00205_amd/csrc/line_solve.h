@@ -233,12 +233,13 @@ __device__ inline void solve_lines(int m, const T* inv, int wv, int tid, Rhs rhs
 
 // Lines per workgroup tile of a line pass: a power of two <= 64 whose LDS
 // tile (line_elems values per line) stays within 40 KiB, halved while the
-// launch would have fewer than 2048 tiles (short grids still spread over the
-// 256 CUs), and no wider than the nq lines available.
+// launch would have fewer than 1024 tiles (four per CU; short grids still
+// spread over the 256 CUs, and wider tiles keep more lines per load), and no
+// wider than the nq lines available.
 inline int tile_width(int64_t line_elems, size_t esize, int64_t np, int64_t nq) {
   int W = 64;
   while (W > 1 && line_elems * (W + 1) * int64_t(esize) > 40960) W >>= 1;
-  while (W > 1 && np * ((nq + W - 1) / W) < 2048) W >>= 1;
+  while (W > 1 && np * ((nq + W - 1) / W) < 1024) W >>= 1;
   while (W > 1 && W / 2 >= nq) W >>= 1;
   return W;
 }

@@ -76,6 +76,10 @@ struct DecArgs {
   QTab ctab;              // coarsest-value tables (last block level when M == 0)
   int coarsest_here;
   int64_t* flag;          // set when a code does not fit in int32
+  // last block level followed by a global level: its details are formed
+  // here from the block's coarse values (codes with that level's 1/Delta)
+  int fuse;
+  const double* nqinv;
 };
 
 template <typename T>
@@ -94,6 +98,13 @@ struct RecArgs {
   const int32_t* codes;   // fused dequantization: codes instead of coefficients
   QTab tab, ctab;
   int coarsest_here;
+  // last block level under a global level: the coarse values of G^s are
+  // interpolated here from the next level's coarse grid G^{s+1} plus its
+  // details (dequantized with that level's Delta), instead of read from cin
+  int fuse;
+  const T* cin2;
+  int64_t cn2[3];
+  const double* nqdel;
 };
 
 // Register budget of the block decomposition: FP32 fits 64 VGPRs (8 waves per
@@ -171,17 +182,21 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       // The coarse nodes of an even column get a placeholder (u_C, or code
       // 0): a later level (or the coarsest copy) overwrites them.  The plane
       // z = B-1 belongs to the next block unless this is the last one.
+      // (fused with the next level: the coarse nodes are written at the end)
+      const bool later = a.fuse && ecol;
       if (!Q) {
         T* dst = a.coeff + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
 #pragma unroll
-        for (int z = 0; z < B - 1; ++z) dst[z * a.cs0] = v[z];
-        if (lastz) dst[(B - 1) * a.cs0] = v[B - 1];
+        for (int z = 0; z < B - 1; ++z)
+          if (!(later && !(z & 1))) dst[z * a.cs0] = v[z];
+        if (lastz && !later) dst[(B - 1) * a.cs0] = v[B - 1];
       } else {
         int32_t* dst = a.codes + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
         bool bad = false;
 #pragma unroll
-        for (int z = 0; z < B - 1; ++z) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], ecol && !(z & 1), bad);
-        if (lastz) dst[(B - 1) * a.cs0] = quant(v[B - 1], iv[2], ecol, bad);
+        for (int z = 0; z < B - 1; ++z)
+          if (!(later && !(z & 1))) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], ecol && !(z & 1), bad);
+        if (lastz && !later) dst[(B - 1) * a.cs0] = quant(v[B - 1], iv[2], ecol, bad);
         if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
       }
     }
@@ -198,10 +213,11 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   __syncthreads();
   if (act) pass_x<T, B>(T2, Z, tb);
   __syncthreads();
-  if (act && ecol && owned) {
-    // coarse values c = u_C + z (z = 0 on the block surface); the compact
-    // coarse grid feeds the next level
-    T c[MC];
+  // coarse values c = u_C + z (z = 0 on the block surface); the compact
+  // coarse grid feeds the next level
+  T c[MC];
+  T* CC = UE;                                        // [MC][MC][MC] when fused (T2 is dead)
+  if (act && ecol) {
 #pragma unroll
     for (int j = 0; j < MC; ++j) c[j] = v[2 * j];
     if (y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3) {
@@ -209,6 +225,12 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
 #pragma unroll
       for (int J = 0; J < MI; ++J) c[J + 1] += Z[(J * MI + I) * MI + K];
     }
+    if (a.fuse) {
+#pragma unroll
+      for (int j = 0; j < MC; ++j) CC[(j * MC + (y >> 1)) * MC + (x >> 1)] = c[j];
+    }
+  }
+  if (act && ecol && owned) {
     if (Q && a.coarsest_here) {
       // last level of the hierarchy: codes for the coarsest values
       double ci[3];
@@ -224,6 +246,32 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
 #pragma unroll
       for (int j = 0; j < MC - 1; ++j) cdst[j * a.cpl] = c[j];
       if (lastz) cdst[(MC - 1) * a.cpl] = c[MC - 1];
+    }
+  }
+  if (a.fuse) {
+    // details of the next (global) level at this column's coarse nodes: c
+    // minus the interpolant over the cell of the next coarse grid (every
+    // such cell lies inside the block); its coarse nodes get a placeholder
+    // (c, or code 0) that a later level or the coarsest values overwrite
+    __syncthreads();
+    if (act && ecol && owned) {
+      const int p = y >> 1, q = x >> 1, op = p & 1, oq = q & 1;
+      const double inv = Q ? *a.nqinv : 0.0;
+      T in[MC];
+      column_interp<T, MC>(p, q, [&](int J, int P, int K) { return CC[((2 * J) * MC + 2 * P) * MC + 2 * K]; }, in);
+      bool bad = false;
+#pragma unroll
+      for (int j = 0; j < MC; ++j) {
+        if (j == MC - 1 && !lastz) continue;
+        const bool cn = ((j & 1) | op | oq) == 0;
+        const T d = cn ? c[j] : c[j] - in[j];
+        const int64_t o = oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2] + int64_t(2 * j) * a.cs0;
+        if (Q)
+          a.codes[o] = quant(d, inv, cn, bad);
+        else
+          a.coeff[o] = d;
+      }
+      if (Q && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
     }
   }
 }
@@ -247,6 +295,21 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
   int64_t bz = 0, by = 0, bx = 0;
   if (act) block_coords(uint32_t(blk), a.fnb2, a.fnb1, a.nb, bz, by, bx);
   const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  // fused with the next (global) level: its coarse values over this block,
+  // UC2[H][H][H] (in T2, which is first written by the y pass)
+  constexpr int H = (MC + 1) / 2;
+  T* UC2 = T2;
+  if (a.fuse) {
+    if (act) {
+      const int64_t h0 = (MC - 1) / 2, pl2 = a.cn2[1] * a.cn2[2];
+      const T* src = a.cin2 + bz * h0 * pl2 + by * h0 * a.cn2[2] + bx * h0;
+      for (int i = tb; i < H * H * H; i += BB) {
+        const int k0 = i / (H * H), r = i - k0 * H * H, k1 = r / H, k2 = r - k1 * H;
+        UC2[i] = src[k0 * pl2 + k1 * a.cn2[2] + k2];
+      }
+    }
+    __syncthreads();
+  }
   T w[B], ce[MC];
   if (act) {
     // the whole column is read (coarse nodes too, then zeroed): one load per node
@@ -276,6 +339,23 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
         column_class<B>(a.ctab.cdel, blk, y, x, cd);
 #pragma unroll
         for (int j = 0; j < MC; ++j) ce[j] = T(mul_rn(double(qc[j]), cd[zcase<B>(2 * j)]));
+      } else if (a.fuse) {
+        // u at this column's coarse nodes = next level's detail + interpolant
+        // of its coarse values (exactly the next level's recomposition)
+        const int p = y >> 1, q = x >> 1, op = p & 1, oq = q & 1;
+        const double del2 = Q ? *a.nqdel : 0.0;
+        const int32_t* qcol = a.codes + off;
+        T in[MC];
+        column_interp<T, MC>(p, q, [&](int J, int P, int K) { return UC2[(J * H + P) * H + K]; }, in);
+#pragma unroll
+        for (int j = 0; j < MC; ++j) {
+          if (((j & 1) | op | oq) == 0) {
+            ce[j] = in[j];   // the next level's coarse value itself (exact)
+          } else {
+            const T w2 = Q ? T(mul_rn(double(qcol[2 * j * a.cs0]), del2)) : w[2 * j];
+            ce[j] = w2 + in[j];
+          }
+        }
       } else {
         const T* ccol = a.cin + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
@@ -432,6 +512,8 @@ DecArgs<T> dec_args(const bm_plan_s& p, int s, const View3& src, bool first, voi
     if (a.coarsest_here) a.ctab = q->lv[kCoarseSlotHost];
     a.flag = q->flag;
   }
+  a.fuse = (p.fuse_next && s == p.L) ? 1 : 0;
+  if (a.fuse && q) a.nqinv = q->q + 2 * s + 1;   // 1/Delta of level s+1
   return a;
 }
 
@@ -482,6 +564,12 @@ RecArgs<T> rec_args(const bm_plan_s& p, int s, const void* coeff, const void* ci
     a.tab = q->lv[s - 1];
     a.coarsest_here = (p.M == 0 && s == p.L) ? 1 : 0;
     if (a.coarsest_here) a.ctab = q->lv[kCoarseSlotHost];
+  }
+  a.fuse = (p.fuse_next && s == p.L) ? 1 : 0;
+  if (a.fuse) {
+    a.cin2 = static_cast<const T*>(p.ws.grid[s + 1]);
+    for (int k = 0; k < 3; ++k) a.cn2[k] = p.lv[s].m[k];
+    if (q) a.nqdel = q->q + 2 * s;                // Delta of level s+1
   }
   return a;
 }

@@ -322,6 +322,7 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
       }
     }
     for (int a = 0; a < 3; ++a) p->nb1[a] = c->L > 0 ? p->lv[0].nb[a] : 1;
+    p->fuse_next = c->L > 0 && c->M > 0 && b != 33;
     // workspace
     p->ws.grid.assign(p->nlev + 1, nullptr);
     if (c->L == 0) BM_HIP(hipMalloc(&p->ws.grid[0], size_t(prod3(p->pdims)) * p->esize));
