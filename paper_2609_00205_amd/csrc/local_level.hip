@@ -119,8 +119,12 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B, sizeof(T)>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   const int tid = threadIdx.x;
-  const int bl = tid / BB;                           // block within the workgroup
-  const int tb = tid - bl * BB;                      // column within the block
+  // lanes run along the rows of the group's x-neighbouring blocks (NB
+  // columns x of row y side by side), so a wavefront reads and writes
+  // contiguous runs of NB * B values
+  const int row = tid / (NB * B), rr = tid - row * (NB * B);
+  const int bl = row < B ? rr / B : NB;              // block within the workgroup
+  const int tb = row < B ? row * B + (rr - (rr / B) * B) : 0;   // column within the block
   const int64_t blk = g * NB + bl;
   const bool act = bl < NB && blk < a.nblocks;
   T* UE = lds + (bl < NB ? bl : 0) * G::DEC_LDS;     // even-z planes [MC][B][B]
@@ -282,8 +286,9 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B, sizeof(T), false>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
   const int tid = threadIdx.x;
-  const int bl = tid / BB;
-  const int tb = tid - bl * BB;
+  const int row = tid / (NB * B), rr = tid - row * (NB * B);   // as in decompose_group
+  const int bl = row < B ? rr / B : NB;
+  const int tb = row < B ? row * B + (rr - (rr / B) * B) : 0;
   const int64_t blk = g * NB + bl;
   const bool act = bl < NB && blk < a.nblocks;
   T* UC = lds + (bl < NB ? bl : 0) * G::REC_LDS;     // coarse values u_C [MC][MC][MC]
