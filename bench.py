@@ -459,6 +459,11 @@ def run_turbo(args):
     buf = plan.compress(xd, bt)
     in_bytes = xd.numel() * 8
     top = sorted(cands, key=lambda c: c["ms"])[:8]
+    by_block = {}
+    for b in sorted({c["block"] for c in cands}):
+        cb = [c for c in cands if c["block"] == b]
+        by_block[str(b)] = {"candidates": len(cb), "fastest": min(cb, key=lambda c: c["ms"]),
+                            "best_ratio": max(cb, key=lambda c: c["ratio"])}
     out = {
         "metric": "decompose/recompose GB/s at (1024,1024,512) FP64 with the autotuned schedule (gradient ROI)",
         "value": round(2 * in_bytes / (ms * 1e-3) / 1e9, 3),
@@ -481,6 +486,7 @@ def run_turbo(args):
         "autotune_s": round(t_tune, 2),
         "candidates": len(cands),
         "fastest_candidates": top,
+        "by_block": by_block,
     }
     print(json.dumps(out), flush=True)
 

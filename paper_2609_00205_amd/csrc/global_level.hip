@@ -249,7 +249,9 @@ struct PassArgs {
   const double* inv;     // Thomas reciprocal pivots, length m
   int64_t nl, m;         // line length, coarse length
   int W, lw;             // lines per tile (a power of two) and its log2
-  int64_t nq, ntq;       // extent of the fastest other axis, tiles per row along it
+  int64_t nq;            // extent of the fastest other axis
+  int64_t nlines;        // lines in all: tile t takes lines t*W .. t*W+W-1 of (p, q) in row order
+  FastDiv fq;            // line index -> (p, q)
   int pa, qa;            // the two other axes (q fastest)
 };
 
@@ -261,33 +263,39 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   const int nl = int(a.nl), m = int(a.m);
   T* tout = tin + nl * WP;                             // [m][W+1]
   T* piv = tout + m * WP;                              // [m] reciprocal pivots
-  const uint32_t tile = blockIdx.x;
-  const uint32_t p = tile / uint32_t(a.ntq);
-  const int64_t q0 = int64_t(tile - p * uint32_t(a.ntq)) * a.W;
-  const int wv = int(i64min(a.W, a.nq - q0));   // valid lines in this tile
+  const int64_t L0 = int64_t(blockIdx.x) * a.W;
+  const int wv = int(i64min(a.W, a.nlines - L0));   // valid lines in this tile
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t sA = a.is[a.axis], sQ = a.is[a.qa];
-  const int64_t ibase = int64_t(p) * a.is[a.pa] + q0 * sQ;
-  // coarse-node test: every coarsening coordinate even
-  const bool pe = !(a.cm[a.pa] && (p & 1));
-  const int cmA = a.cm[a.axis], cmQ = a.cm[a.qa];
-  auto load = [&](int i, int w) {
-    const int64_t off = ibase + w * sQ + i * sA;
-    T v = a.qin ? T(mul_rn(double(a.qin[off]), *a.qdel)) : a.in[off];
-    if (a.mask && pe && !(cmA && (i & 1)) && !(cmQ && ((q0 + w) & 1))) v = T(0);
-    tin[i * WP + w] = v;
+  const int64_t sA = a.is[a.axis], sQ = a.is[a.qa], sP = a.is[a.pa];
+  const int cmA = a.cm[a.axis], cmQ = a.cm[a.qa], cmP = a.cm[a.pa];
+  // line w of the tile: (p, q) and whether its p and q are even where they coarsen
+  auto line = [&](int w, uint32_t& p, uint32_t& q) {
+    const uint32_t l = uint32_t(L0 + w);
+    p = a.fq.div(l);
+    q = l - p * uint32_t(a.nq);
+  };
+  auto load_line = [&](int w, int i0, int di) {
+    uint32_t p, q;
+    line(w, p, q);
+    const int64_t lb = int64_t(p) * sP + int64_t(q) * sQ;
+    // coarse-node test: every coarsening coordinate even
+    const bool pq_even = !(cmP && (p & 1)) && !(cmQ && (q & 1));
+    for (int i = i0; i < nl; i += di) {
+      const int64_t off = lb + i * sA;
+      T v = a.qin ? T(mul_rn(double(a.qin[off]), *a.qdel)) : a.in[off];
+      if (a.mask && pq_even && !(cmA && (i & 1))) v = T(0);
+      tin[i * WP + w] = v;
+    }
   };
   for (int J = tid; J < m; J += NT) piv[J] = T(a.inv[J]);
   // load: a wavefront per line when lines are rows (x, contiguous); else the
   // W lines of the tile side by side (W a power of two)
   if (a.axis == 2) {
-    for (int w = wave; w < wv; w += NT / 64)
-      for (int i = lane; i < nl; i += 64) load(i, w);
+    for (int w = wave; w < wv; w += NT / 64) load_line(w, lane, 64);
   } else {
     const int w = tid & (a.W - 1);
-    if (w < wv)
-      for (int i = tid >> a.lw; i < nl; i += NT >> a.lw) load(i, w);
+    if (w < wv) load_line(w, tid >> a.lw, NT >> a.lw);
   }
   __syncthreads();
   // right-hand side 3 (P^T M u)_J: 5-point interior rows, 3-point end rows
@@ -308,20 +316,22 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   solve_lines<T, NT, Q>(m, piv, wv, tid, rhs, [&](int w, int J, T x) { tout[J * WP + w] = x; });
   __syncthreads();
   const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
-  const int64_t oA = os[a.axis], oQ = os[a.qa];
-  const int64_t obase = int64_t(p) * os[a.pa] + q0 * oQ;
-  auto store = [&](int J, int w) {
-    const int64_t o = obase + w * oQ + J * oA;
-    const T v = tout[J * WP + w];
-    a.out[o] = a.base ? a.base[o] - v : v;
+  const int64_t oA = os[a.axis], oQ = os[a.qa], oP = os[a.pa];
+  auto store_line = [&](int w, int J0, int dJ) {
+    uint32_t p, q;
+    line(w, p, q);
+    const int64_t ob = int64_t(p) * oP + int64_t(q) * oQ;
+    for (int J = J0; J < m; J += dJ) {
+      const int64_t o = ob + J * oA;
+      const T v = tout[J * WP + w];
+      a.out[o] = a.base ? a.base[o] - v : v;
+    }
   };
   if (a.axis == 2) {
-    for (int w = wave; w < wv; w += NT / 64)
-      for (int J = lane; J < m; J += 64) store(J, w);
+    for (int w = wave; w < wv; w += NT / 64) store_line(w, lane, 64);
   } else {
     const int w = tid & (a.W - 1);
-    if (w < wv)
-      for (int J = tid >> a.lw; J < m; J += NT >> a.lw) store(J, w);
+    if (w < wv) store_line(w, tid >> a.lw, NT >> a.lw);
   }
 }
 
@@ -355,9 +365,10 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.W = tile_width(a.nl + a.m + 1, sizeof(T), np, a.nq);
   a.lw = 0;
   while ((1 << a.lw) < a.W) ++a.lw;
-  a.ntq = (a.nq + a.W - 1) / a.W;
-  const int64_t tiles = np * a.ntq;
-  if (tiles >= (int64_t(1) << 31)) fail(BM_EUNSUPPORTED, "too many lines");
+  a.nlines = np * a.nq;
+  if (a.nlines >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "too many lines");
+  a.fq = FastDiv(uint32_t(a.nq));
+  const int64_t tiles = (a.nlines + a.W - 1) / a.W;
   const size_t shm = (size_t(a.nl + a.m) * (a.W + 1) + size_t(a.m)) * sizeof(T);
   switch (row_q_for(a.m)) {
     case 3: hipLaunchKernelGGL((k_line_pass<T, 3>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;

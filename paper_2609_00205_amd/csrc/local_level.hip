@@ -191,16 +191,22 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       if (!Q) {
         T* dst = a.coeff + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
 #pragma unroll
-        for (int z = 0; z < B - 1; ++z)
-          if (!(later && !(z & 1))) dst[z * a.cs0] = v[z];
-        if (lastz && !later) dst[(B - 1) * a.cs0] = v[B - 1];
+        for (int z = 1; z < B - 1; z += 2) dst[z * a.cs0] = v[z];
+        if (!later) {
+#pragma unroll
+          for (int z = 0; z < B - 1; z += 2) dst[z * a.cs0] = v[z];
+          if (lastz) dst[(B - 1) * a.cs0] = v[B - 1];
+        }
       } else {
         int32_t* dst = a.codes + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
         bool bad = false;
 #pragma unroll
-        for (int z = 0; z < B - 1; ++z)
-          if (!(later && !(z & 1))) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], ecol && !(z & 1), bad);
-        if (lastz && !later) dst[(B - 1) * a.cs0] = quant(v[B - 1], iv[2], ecol, bad);
+        for (int z = 1; z < B - 1; z += 2) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], false, bad);
+        if (!later) {   // even planes in one branch
+#pragma unroll
+          for (int z = 0; z < B - 1; z += 2) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], ecol, bad);
+          if (lastz) dst[(B - 1) * a.cs0] = quant(v[B - 1], iv[2], ecol, bad);
+        }
         if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
       }
     }

@@ -32,7 +32,8 @@ def _plan(shape, b, L, M, dt=torch.float32, eta=None):
 
 CASES = [((33, 33, 33), 17, 1, 2), ((20, 30, 12), 9, 1, 1), ((33, 17, 65), 9, 2, 1),
          ((65, 65, 65), 17, 0, 6), ((33, 33, 17), 9, 2, 0), ((97, 65, 129), 17, 1, 2),
-         ((70, 40, 100), 33, 1, 1), ((65, 65, 65), 33, 1, 0), ((65, 65, 129), 33, 2, 1)]
+         ((70, 40, 100), 33, 1, 1), ((65, 65, 65), 33, 1, 0), ((65, 65, 129), 33, 2, 1),
+         ((129, 129, 129), 17, 1, 2)]
 
 
 def _boxes(shape, seed):

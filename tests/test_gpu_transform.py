@@ -33,6 +33,8 @@ CASES = [
     ((70, 40, 100), 33, 1, 1, torch.float32, "clamp"),
     ((65, 65, 129), 33, 2, 1, torch.float64, "clamp"),    # two 33^3 block levels
     ((65, 33, 65), 33, 1, 0, torch.float32, "clamp"),     # 33^3 blocks, pure local
+    ((129, 97, 97), 17, 0, 2, torch.float32, "clamp"),    # x and y passes fused per z-plane (both levels)
+    ((129, 129, 129), 17, 1, 2, torch.float32, "clamp"),  # the same after a block level
 ]
 
 
