@@ -35,6 +35,12 @@ CASES = [
     ((65, 33, 65), 33, 1, 0, torch.float32, "clamp"),     # 33^3 blocks, pure local
     ((129, 97, 97), 17, 0, 2, torch.float32, "clamp"),    # x and y passes fused per z-plane (both levels)
     ((129, 129, 129), 17, 1, 2, torch.float32, "clamp"),  # the same after a block level
+    ((1, 40, 70), 9, 1, 1, torch.float32, "clamp"),       # a 2D field: unit z axis padded to one block
+    ((1, 40, 70), 9, 1, 1, torch.float64, "zero"),
+    ((1, 1, 200), 17, 1, 2, torch.float32, "clamp"),      # a 1D field
+    ((3, 3, 3), 9, 0, 1, torch.float64, "clamp"),         # smallest grid that has a level
+    ((5, 2, 9), 9, 0, 2, torch.float32, "clamp"),         # an axis of 2 nodes never coarsens
+    ((17, 17, 17), 17, 1, 0, torch.float32, "clamp"),     # a single block
 ]
 
 

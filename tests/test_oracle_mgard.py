@@ -169,7 +169,8 @@ def test_block_level_33_is_dirichlet_constrained_projection(rng):
 @pytest.mark.parametrize("shape,b,L,M", [((33, 33, 33), 17, 1, 2), ((33, 17, 65), 9, 2, 1),
                                           ((9, 9, 9), 9, 0, 3), ((20, 30, 12), 9, 1, 1),
                                           ((65, 33, 33), 17, 1, 0), ((17, 17, 17), 9, 1, 1),
-                                          ((70, 40, 100), 33, 1, 1), ((65, 65, 129), 33, 2, 1)])
+                                          ((70, 40, 100), 33, 1, 1), ((65, 65, 129), 33, 2, 1),
+                                          ((1, 40, 70), 9, 1, 1), ((5, 2, 9), 9, 0, 2), ((3, 3, 3), 9, 0, 1)])
 def test_reconstruction(shape, b, L, M, rng):
     x = rng.standard_normal(shape)
     c = mgard.decompose(x, b, L, M)
