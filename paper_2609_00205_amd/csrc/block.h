@@ -88,6 +88,24 @@ __device__ inline void column_interp(int p, int q, F rd, T (&out)[MC]) {
   for (int j = 0; j < MC; ++j) out[j] = (j & 1) ? T(0.5) * (I2[j >> 1] + I2[(j >> 1) + 1]) : I2[j >> 1];
 }
 
+// 3 (P^T M v) at coarse node k (k < (MC+1)/2) of a line of MC values read
+// by v(t) (unit spacing): interior rows {1/12, 1/2, 5/6, 1/2, 1/12} around
+// node 2k; the two end rows keep the half on the line's side, 5/12 at the
+// end node.
+template <typename T, int MC, typename V>
+__device__ inline T restrict_half(int k, V v) {
+  constexpr int H = (MC + 1) / 2;
+  const int c = 2 * k;
+  T r;
+  if (k == 0)
+    r = T(5.0 / 12.0) * v(0) + T(0.5) * v(1) + T(1.0 / 12.0) * v(2);
+  else if (k == H - 1)
+    r = T(1.0 / 12.0) * v(MC - 3) + T(0.5) * v(MC - 2) + T(5.0 / 12.0) * v(MC - 1);
+  else
+    r = T(1.0 / 12.0) * (v(c - 2) + v(c + 2)) + T(0.5) * (v(c - 1) + v(c + 1)) + T(5.0 / 6.0) * v(c);
+  return T(3) * r;
+}
+
 // block coordinates of block index blk
 __device__ inline void block_coords(uint32_t blk, const FastDiv& f2, const FastDiv& f1, const int64_t nb[3],
                                     int64_t& bz, int64_t& by, int64_t& bx) {

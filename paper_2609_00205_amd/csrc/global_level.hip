@@ -253,6 +253,7 @@ struct PassArgs {
   int64_t nlines;        // lines in all: tile t takes lines t*W .. t*W+W-1 of (p, q) in row order
   FastDiv fq;            // line index -> (p, q)
   int pa, qa;            // the two other axes (q fastest)
+  int solve_only;        // lines of m values that already hold 3 P^T M u: solve only
 };
 
 template <typename T, int Q>
@@ -301,6 +302,7 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   // right-hand side 3 (P^T M u)_J: 5-point interior rows, 3-point end rows
   auto rhs = [&](int w, int J) {
     const T* col = tin + w;
+    if (a.solve_only) return col[J * WP];
     const int c = 2 * J;
     T r;
     if (J == 0) {
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
 
 template <typename T>
 void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
-                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st) {
+                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st, bool solve_only = false) {
   const Level& L = p.lv[s - 1];
   PassArgs<T> a{};
   a.in = static_cast<const T*>(in.ptr);
@@ -354,7 +356,12 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.nl = in.n[axis];
   a.m = L.m[axis];
   a.on[axis] = a.m;
-  if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * kLineQ) fail(BM_EUNSUPPORTED, "line length not supported");
+  a.solve_only = solve_only ? 1 : 0;
+  if (solve_only) {
+    if (a.nl != a.m || a.m < 2 || a.m > 64 * kLineQ) fail(BM_EUNSUPPORTED, "line length not supported");
+  } else if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * kLineQ) {
+    fail(BM_EUNSUPPORTED, "line length not supported");
+  }
   a.out = static_cast<T*>(out);
   a.base = static_cast<const T*>(base);
   a.inv = L.d_inv[axis];
@@ -378,6 +385,58 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
     default: hipLaunchKernelGGL((k_line_pass<T, 0>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
   }
   BM_HIP(hipGetLastError());
+}
+
+// The first global level's load vector when the last block level is fused
+// with it: every block left partial sums, over its own coarse nodes, at the
+// H^3 coarse nodes of the next level inside it; node c along an axis lies in
+// block c / (H-1), and a node on a shared face also in the block before.
+// The partials are added in a fixed order (lower blocks first).
+template <typename T>
+struct GatherArgs {
+  const double* part;     // [block][H][H][H]
+  int64_t nb[3];
+  Idx3 m;                 // dims of the level's coarse grid
+  T* out;                 // dense, dims m
+};
+
+template <typename T, int H>
+__global__ __launch_bounds__(NT) void k_gather_part(GatherArgs<T> a) {
+  const int64_t tot = a.m.n0 * a.m.n1 * a.m.n2;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t c[3];
+    unflat(i, a.m, c[0], c[1], c[2]);
+    int64_t b[3][2];
+    int k[3][2], n[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t bb = c[d] / (H - 1);
+      const int kk = int(c[d] - bb * (H - 1));
+      if (bb == a.nb[d]) {            // the far end node
+        n[d] = 1;
+        b[d][0] = bb - 1;
+        k[d][0] = H - 1;
+      } else if (kk == 0 && bb > 0) { // a shared face: the block before, then this one
+        n[d] = 2;
+        b[d][0] = bb - 1;
+        k[d][0] = H - 1;
+        b[d][1] = bb;
+        k[d][1] = 0;
+      } else {
+        n[d] = 1;
+        b[d][0] = bb;
+        k[d][0] = kk;
+      }
+    }
+    double sum = 0.0;
+    for (int iz = 0; iz < n[0]; ++iz)
+      for (int iy = 0; iy < n[1]; ++iy)
+        for (int ix = 0; ix < n[2]; ++ix) {
+          const int64_t blk = (b[0][iz] * a.nb[1] + b[1][iy]) * a.nb[2] + b[2][ix];
+          sum += a.part[blk * (H * H * H) + (k[0][iz] * H + k[1][iy]) * H + k[2][ix]];
+        }
+    a.out[i] = T(sum);
+  }
 }
 
 // ------------------------------------------------------------- launchers
@@ -527,6 +586,42 @@ static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const 
   }
 }
 
+// Coarse values of the first global level (s = L+1) when the last block level
+// is fused with it: the gathered load vector 27 (P^T M)^3 u, then the three
+// tridiagonal solves along x, y and z.  Gather and solves run in FP64 (the
+// values are rounded once, to the plan's type, at the end): a level-wide
+// restriction followed by three solves would otherwise round more often
+// than the interleaved restriction + solve passes it replaces.
+__global__ __launch_bounds__(NT) void k_narrow(const double* src, float* dst, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) dst[i] = float(src[i]);
+}
+
+static void global_from_parts(bm_plan_s& p, int s, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  const Level& B = p.lv[s - 2];
+  const int64_t* m = L.m;
+  const int64_t tot = m[0] * m[1] * m[2];
+  if (size_t(tot) * sizeof(double) > p.ws.t_elems * p.esize) fail(BM_EINVAL, "plan workspace too small");
+  double* t1 = static_cast<double*>(p.ws.t1);
+  double* t2 = static_cast<double*>(p.ws.t2);
+  GatherArgs<double> a{static_cast<const double*>(p.ws.part), {B.nb[0], B.nb[1], B.nb[2]}, {m[0], m[1], m[2]}, t1};
+  if (p.cfg.block == 9)
+    hipLaunchKernelGGL((k_gather_part<double, 3>), dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_gather_part<double, 5>), dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  BM_HIP(hipGetLastError());
+  // x: t1 -> t2, y: t2 -> t1, z: t1 -> the coarse grid (FP64) or t2 (FP32, narrowed after)
+  const bool f64 = p.cfg.dtype == BM_F64;
+  launch_pass<double>(p, s, 2, dense_view(t1, m), nullptr, t2, nullptr, nullptr, nullptr, st, true);
+  launch_pass<double>(p, s, 1, dense_view(t2, m), nullptr, t1, nullptr, nullptr, nullptr, st, true);
+  launch_pass<double>(p, s, 0, dense_view(t1, m), nullptr, f64 ? p.ws.grid[s] : t2, nullptr, nullptr, nullptr, st,
+                      true);
+  if (!f64) {
+    hipLaunchKernelGGL(k_narrow, dim3(grid_for(tot)), dim3(NT), 0, st, t2, static_cast<float*>(p.ws.grid[s]), tot);
+    BM_HIP(hipGetLastError());
+  }
+}
+
 void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
   const View3 xv = dense_view(const_cast<void*>(x), p.dims);
   for (int s = 1; s <= p.nlev; ++s) {
@@ -543,8 +638,13 @@ void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
       } else {
         u = p.ws.grid[s - 1];
       }
-      // (the first global level's details come from the last block level when fused)
-      if (!(p.fuse_next && s == p.L + 1)) global_details(p, s, u, coeff, st);
+      // (the first global level's details and load vector come from the
+      // last block level when fused)
+      if (p.fuse_next && s == p.L + 1) {
+        global_from_parts(p, s, st);
+        continue;
+      }
+      global_details(p, s, u, coeff, st);
       apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
     }
   }
@@ -595,12 +695,14 @@ void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, cons
       u = p.ws.grid[s - 1];
     }
     if (p.fuse_next && s == p.L + 1) {
-      // details (codes) already written by the last block level
-    } else if (p.cfg.dtype == BM_F32) {
-      launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
-    } else {
-      launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+      // details (codes) and load vector from the last block level
+      global_from_parts(p, s, st);
+      continue;
     }
+    if (p.cfg.dtype == BM_F32)
+      launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
+    else
+      launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
     apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
   }
   if (p.M > 0 || p.L == 0) {

@@ -120,6 +120,7 @@ struct Workspace {
   double* boxhost = nullptr;     // pinned staging for the box list
   void* gpad = nullptr;          // dtype, padded grid: level-1 gradient before the pad transpose
   void* prep_dev = nullptr;      // quantizer preparation of this plan: field record + task prefixes (device)
+  void* part = nullptr;          // double: per-block partial load vectors of the first global level (fused)
   std::vector<uint8_t> prep_key; // field record last uploaded
 };
 

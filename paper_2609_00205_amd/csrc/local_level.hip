@@ -80,6 +80,7 @@ struct DecArgs {
   // here from the block's coarse values (codes with that level's 1/Delta)
   int fuse;
   const double* nqinv;
+  double* part;           // per block: the next level's partial load vector [H][H][H] (FP64)
 };
 
 template <typename T>
@@ -227,6 +228,11 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   // coarse grid feeds the next level
   T c[MC];
   T* CC = UE;                                        // [MC][MC][MC] when fused (T2 is dead)
+  // fused: the next level's load vector, in FP64 (see below): z pass in
+  // registers, then y and x passes in LDS after CC
+  constexpr int H = (MC + 1) / 2;
+  double* Z1 = reinterpret_cast<double*>(CC + ((MC * MC * MC * sizeof(T) + 7) / 8) * (8 / sizeof(T)));   // [H][MC][MC]
+  double* Y1 = Z1 + H * MC * MC;                     // [H][H][MC]
   if (act && ecol) {
 #pragma unroll
     for (int j = 0; j < MC; ++j) c[j] = v[2 * j];
@@ -238,6 +244,9 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
     if (a.fuse) {
 #pragma unroll
       for (int j = 0; j < MC; ++j) CC[(j * MC + (y >> 1)) * MC + (x >> 1)] = c[j];
+#pragma unroll
+      for (int k = 0; k < H; ++k)
+        Z1[(k * MC + (y >> 1)) * MC + (x >> 1)] = restrict_half<double, MC>(k, [&](int t) { return double(c[t]); });
     }
   }
   if (act && ecol && owned) {
@@ -251,7 +260,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       for (int j = 0; j < MC - 1; ++j) dst[2 * j * a.cs0] = quant(c[j], ci[zcase<B>(2 * j)], false, bad);
       if (lastz) dst[(B - 1) * a.cs0] = quant(c[MC - 1], ci[2], false, bad);
       if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
-    } else {
+    } else if (!a.fuse) {
       T* cdst = a.cout + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
       for (int j = 0; j < MC - 1; ++j) cdst[j * a.cpl] = c[j];
@@ -282,6 +291,28 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
           a.coeff[o] = d;
       }
       if (Q && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+    }
+    // The next level's load vector 3 P^T M (per axis) at its coarse nodes in
+    // this block, from the block's own coarse values only: rows on the block
+    // faces take the half of the stencil on this side ({5/12, 1/2, 1/12}, the
+    // natural end row), the neighbour adds the other half.  Shrinking passes
+    // z (in registers, above), y and x (LDS), in FP64 so that the sum of 125
+    // terms and the gather of up to 8 partials round once; the partial sums
+    // go to a per-block array that a gather completes, so the global level
+    // needs no pass over G^s.
+    if (act) {
+      for (int i = tb; i < H * H * MC; i += BB) {
+        const int k0 = i / (H * MC), r = i - k0 * (H * MC), k1 = r / MC, q = r - k1 * MC;
+        Y1[i] = restrict_half<double, MC>(k1, [&](int t) { return Z1[(k0 * MC + t) * MC + q]; });
+      }
+    }
+    __syncthreads();
+    if (act) {
+      double* dst = a.part + blk * (H * H * H);
+      for (int i = tb; i < H * H * H; i += BB) {
+        const int r = i / H, k2 = i - r * H;
+        dst[i] = restrict_half<double, MC>(k2, [&](int t) { return Y1[r * MC + t]; });
+      }
     }
   }
 }
@@ -430,7 +461,7 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
 
 template <typename T, int B, bool Q>
 __global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose(DecArgs<T> a) {
-  __shared__ T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];
+  __shared__ __attribute__((aligned(16))) T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];   // FP64 scratch inside
   const int64_t g = xcd_group(blockIdx.x, a.per);
   if (g >= a.nwg) return;
   decompose_group<T, B, Q>(a, g, lds);
@@ -459,10 +490,12 @@ __device__ inline int field_of(const int64_t* first, int nf, int64_t k) {
   return lo;
 }
 
+// (no wave target here: the per-field arguments come from memory and the
+// extra registers are cheaper than spills)
 template <typename T, int B, bool Q>
-__global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_batch_decompose(
+__global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) void k_batch_decompose(
     const DecArgs<T>* fa, const int64_t* first, int nf, int64_t ntasks) {
-  __shared__ T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];
+  __shared__ __attribute__((aligned(16))) T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];   // FP64 scratch inside
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const int f = field_of(first, nf, k);
     decompose_group<T, B, Q>(fa[f], k - first[f], lds);
@@ -525,6 +558,7 @@ DecArgs<T> dec_args(const bm_plan_s& p, int s, const View3& src, bool first, voi
   }
   a.fuse = (p.fuse_next && s == p.L) ? 1 : 0;
   if (a.fuse && q) a.nqinv = q->q + 2 * s + 1;   // 1/Delta of level s+1
+  if (a.fuse) a.part = static_cast<double*>(p.ws.part);
   return a;
 }
 

@@ -323,6 +323,11 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     }
     for (int a = 0; a < 3; ++a) p->nb1[a] = c->L > 0 ? p->lv[0].nb[a] : 1;
     p->fuse_next = c->L > 0 && c->M > 0 && b != 33;
+    if (p->fuse_next) {
+      // per-block partial load vectors of the first global level (FP64): H^3 per block, H = (b+3)/4
+      const int64_t h = (b + 3) / 4;
+      BM_HIP(hipMalloc(&p->ws.part, size_t(prod3(p->lv[c->L - 1].nb)) * h * h * h * sizeof(double)));
+    }
     // workspace
     p->ws.grid.assign(p->nlev + 1, nullptr);
     if (c->L == 0) BM_HIP(hipMalloc(&p->ws.grid[0], size_t(prod3(p->pdims)) * p->esize));
@@ -372,6 +377,7 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     if (p->ws.counters) (void)hipFree(p->ws.counters);
     if (p->ws.boxbuf) (void)hipFree(p->ws.boxbuf);
     if (p->ws.boxhost) (void)hipHostFree(p->ws.boxhost);
+    if (p->ws.part) (void)hipFree(p->ws.part);
     delete p;
     throw;
   }
@@ -391,7 +397,7 @@ void bm_plan_free(bm_plan_s* p) {
   for (void* g : p->ws.grid)
     if (g) (void)hipFree(g);
   for (void* q : {p->ws.t1, p->ws.t2, p->ws.codes, p->ws.coeff, (void*)p->ws.tolbuf, (void*)p->ws.qparam,
-                  (void*)p->ws.counters, (void*)p->ws.boxbuf, p->ws.gpad, p->ws.prep_dev})
+                  (void*)p->ws.counters, (void*)p->ws.boxbuf, p->ws.gpad, p->ws.prep_dev, p->ws.part})
     if (q) (void)hipFree(q);
   if (p->ws.boxhost) (void)hipHostFree(p->ws.boxhost);
   delete p;
