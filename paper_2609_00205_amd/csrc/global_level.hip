@@ -254,6 +254,7 @@ struct PassArgs {
   FastDiv fq;            // line index -> (p, q)
   int pa, qa;            // the two other axes (q fastest)
   int solve_only;        // lines of m values that already hold 3 P^T M u: solve only
+  float* out_f32;        // optional: the result narrowed to FP32 here instead of out
 };
 
 template <typename T, int Q>
@@ -326,7 +327,10 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
     for (int J = J0; J < m; J += dJ) {
       const int64_t o = ob + J * oA;
       const T v = tout[J * WP + w];
-      a.out[o] = a.base ? a.base[o] - v : v;
+      if (a.out_f32)
+        a.out_f32[o] = float(v);
+      else
+        a.out[o] = a.base ? a.base[o] - v : v;
     }
   };
   if (a.axis == 2) {
@@ -339,7 +343,8 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
 
 template <typename T>
 void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
-                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st, bool solve_only = false) {
+                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st, bool solve_only = false,
+                 float* out_f32 = nullptr) {
   const Level& L = p.lv[s - 1];
   PassArgs<T> a{};
   a.in = static_cast<const T*>(in.ptr);
@@ -357,6 +362,7 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.m = L.m[axis];
   a.on[axis] = a.m;
   a.solve_only = solve_only ? 1 : 0;
+  a.out_f32 = out_f32;
   if (solve_only) {
     if (a.nl != a.m || a.m < 2 || a.m > 64 * kLineQ) fail(BM_EUNSUPPORTED, "line length not supported");
   } else if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * kLineQ) {
@@ -395,45 +401,47 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
 template <typename T>
 struct GatherArgs {
   const double* part;     // [block][H][H][H]
-  int64_t nb[3];
+  uint32_t nb[3];
   Idx3 m;                 // dims of the level's coarse grid
   T* out;                 // dense, dims m
 };
 
 template <typename T, int H>
 __global__ __launch_bounds__(NT) void k_gather_part(GatherArgs<T> a) {
-  const int64_t tot = a.m.n0 * a.m.n1 * a.m.n2;
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
-    int64_t c[3];
-    unflat(i, a.m, c[0], c[1], c[2]);
-    int64_t b[3][2];
-    int k[3][2], n[3];
+  const uint32_t tot = uint32_t(a.m.n0 * a.m.n1 * a.m.n2);
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < tot; i += gridDim.x * NT) {
+    uint32_t c[3];
+    a.m.uf(i, c[0], c[1], c[2]);
+    uint32_t b0[3], b1[3];
+    int k0[3], k1[3];
+    bool two[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int64_t bb = c[d] / (H - 1);
+      const uint32_t bb = c[d] / (H - 1);
       const int kk = int(c[d] - bb * (H - 1));
-      if (bb == a.nb[d]) {            // the far end node
-        n[d] = 1;
-        b[d][0] = bb - 1;
-        k[d][0] = H - 1;
-      } else if (kk == 0 && bb > 0) { // a shared face: the block before, then this one
-        n[d] = 2;
-        b[d][0] = bb - 1;
-        k[d][0] = H - 1;
-        b[d][1] = bb;
-        k[d][1] = 0;
+      two[d] = kk == 0 && bb > 0 && bb < a.nb[d];   // a shared face: the block before, then this one
+      b1[d] = bb;
+      k1[d] = 0;
+      if (bb == a.nb[d] || two[d]) {                // (or the far end node)
+        b0[d] = bb - 1;
+        k0[d] = H - 1;
       } else {
-        n[d] = 1;
-        b[d][0] = bb;
-        k[d][0] = kk;
+        b0[d] = bb;
+        k0[d] = kk;
       }
     }
     double sum = 0.0;
-    for (int iz = 0; iz < n[0]; ++iz)
-      for (int iy = 0; iy < n[1]; ++iy)
-        for (int ix = 0; ix < n[2]; ++ix) {
-          const int64_t blk = (b[0][iz] * a.nb[1] + b[1][iy]) * a.nb[2] + b[2][ix];
-          sum += a.part[blk * (H * H * H) + (k[0][iz] * H + k[1][iy]) * H + k[2][ix]];
+#pragma unroll
+    for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+      for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+          if ((iz && !two[0]) || (iy && !two[1]) || (ix && !two[2])) continue;
+          const uint64_t blk = (uint64_t(iz ? b1[0] : b0[0]) * a.nb[1] + (iy ? b1[1] : b0[1])) * a.nb[2] +
+                               (ix ? b1[2] : b0[2]);
+          sum += a.part[blk * (H * H * H) + ((iz ? k1[0] : k0[0]) * H + (iy ? k1[1] : k0[1])) * H +
+                        (ix ? k1[2] : k0[2])];
         }
     a.out[i] = T(sum);
   }
@@ -592,10 +600,6 @@ static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const 
 // values are rounded once, to the plan's type, at the end): a level-wide
 // restriction followed by three solves would otherwise round more often
 // than the interleaved restriction + solve passes it replaces.
-__global__ __launch_bounds__(NT) void k_narrow(const double* src, float* dst, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) dst[i] = float(src[i]);
-}
-
 static void global_from_parts(bm_plan_s& p, int s, hipStream_t st) {
   const Level& L = p.lv[s - 1];
   const Level& B = p.lv[s - 2];
@@ -604,22 +608,19 @@ static void global_from_parts(bm_plan_s& p, int s, hipStream_t st) {
   if (size_t(tot) * sizeof(double) > p.ws.t_elems * p.esize) fail(BM_EINVAL, "plan workspace too small");
   double* t1 = static_cast<double*>(p.ws.t1);
   double* t2 = static_cast<double*>(p.ws.t2);
-  GatherArgs<double> a{static_cast<const double*>(p.ws.part), {B.nb[0], B.nb[1], B.nb[2]}, {m[0], m[1], m[2]}, t1};
+  GatherArgs<double> a{static_cast<const double*>(p.ws.part),
+                       {uint32_t(B.nb[0]), uint32_t(B.nb[1]), uint32_t(B.nb[2])}, {m[0], m[1], m[2]}, t1};
   if (p.cfg.block == 9)
     hipLaunchKernelGGL((k_gather_part<double, 3>), dim3(grid_for(tot)), dim3(NT), 0, st, a);
   else
     hipLaunchKernelGGL((k_gather_part<double, 5>), dim3(grid_for(tot)), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
-  // x: t1 -> t2, y: t2 -> t1, z: t1 -> the coarse grid (FP64) or t2 (FP32, narrowed after)
+  // x: t1 -> t2, y: t2 -> t1, z: t1 -> the coarse grid (narrowed to FP32 on the store for an FP32 plan)
   const bool f64 = p.cfg.dtype == BM_F64;
   launch_pass<double>(p, s, 2, dense_view(t1, m), nullptr, t2, nullptr, nullptr, nullptr, st, true);
   launch_pass<double>(p, s, 1, dense_view(t2, m), nullptr, t1, nullptr, nullptr, nullptr, st, true);
   launch_pass<double>(p, s, 0, dense_view(t1, m), nullptr, f64 ? p.ws.grid[s] : t2, nullptr, nullptr, nullptr, st,
-                      true);
-  if (!f64) {
-    hipLaunchKernelGGL(k_narrow, dim3(grid_for(tot)), dim3(NT), 0, st, t2, static_cast<float*>(p.ws.grid[s]), tot);
-    BM_HIP(hipGetLastError());
-  }
+                      true, f64 ? nullptr : static_cast<float*>(p.ws.grid[s]));
 }
 
 void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {

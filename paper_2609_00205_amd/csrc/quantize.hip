@@ -508,7 +508,11 @@ __global__ void k_batch_propagate(const PrepField* F, const int64_t* first, int 
 // coarsest values of a field with M == 0) straight from the taus: rounding
 // of tau * kappa is monotone, so the smallest Delta over a set of blocks is
 // the smallest tau times kappa, and its reciprocal is the largest 1/Delta.
-// Task = (block, class); class 13 (interior) also writes the block's own entry.
+// Task = (block, class), consecutive tasks write consecutive entries; class
+// 13 (interior) also writes the block's own entry.  Along an axis, class 0
+// (first face) takes the block and the one before, 1 the block alone, 2
+// (last face) the block and the one after.  32-bit index arithmetic (a
+// level has fewer than 2^32 / 27 blocks).
 __global__ void k_batch_tables(const PrepField* F, const int64_t* first, int nf, int64_t ntot, int s) {
   for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT) {
     const int f = field_of(first, nf, k);
@@ -517,22 +521,24 @@ __global__ void k_batch_tables(const PrepField* F, const int64_t* first, int nf,
     const QTab& T = s > 0 ? P.tab[li] : P.tab[kCoarseSlotHost];
     const double kap = s > 0 ? P.kap[li] : P.kapc;
     const double* tau = P.tau[li];
-    const int64_t i = k - first[f];
-    const int64_t blk = i / 27;
-    const int c = int(i - blk * 27);
+    const uint32_t i = uint32_t(k - first[f]);
+    const uint32_t blk = i / 27u;
+    const int c = int(i - blk * 27u);
     const int cls[3] = {c / 9, (c / 3) % 3, c % 3};
-    const int64_t* nb = P.nb[li];
-    const int64_t bx = blk % nb[2], t = blk / nb[2];
-    const int64_t b[3] = {t / nb[1], t % nb[1], bx};
-    int64_t lo[3], hi[3];
+    const uint32_t n0 = uint32_t(P.nb[li][0]), n1 = uint32_t(P.nb[li][1]), n2 = uint32_t(P.nb[li][2]);
+    const uint32_t t = blk / n2;
+    const uint32_t b[3] = {t / n1, t - (t / n1) * n1, blk - t * n2};
+    const uint32_t nb[3] = {n0, n1, n2};
+    uint32_t lo[3], hi[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       lo[d] = (cls[d] == 0 && b[d] > 0) ? b[d] - 1 : b[d];
       hi[d] = (cls[d] == 2 && b[d] + 1 < nb[d]) ? b[d] + 1 : b[d];
     }
     double m = INFINITY;
-    for (int64_t z = lo[0]; z <= hi[0]; ++z)
-      for (int64_t y = lo[1]; y <= hi[1]; ++y)
-        for (int64_t x = lo[2]; x <= hi[2]; ++x) m = fmin(m, tau[(z * nb[1] + y) * nb[2] + x]);
+    for (uint32_t z = lo[0]; z <= hi[0]; ++z)
+      for (uint32_t y = lo[1]; y <= hi[1]; ++y)
+        for (uint32_t x = lo[2]; x <= hi[2]; ++x) m = fmin(m, tau[(z * n1 + y) * n2 + x]);
     const double d = m * kap, iv = 1.0 / d;
     const_cast<double*>(T.cdel)[i] = d;
     const_cast<double*>(T.cinv)[i] = iv;
@@ -546,20 +552,31 @@ __global__ void k_batch_tables(const PrepField* F, const int64_t* first, int nf,
 // tau_global (minimum over the last block level, or the single map value
 // when there is none) and the scalar Deltas; one workgroup per field, which
 // also clears the field's overflow flag.
-__global__ __launch_bounds__(NT) void k_batch_scalar(const PrepField* F) {
-  __shared__ double red[NT];
+constexpr int kScalarNT = 1024;
+
+__global__ __launch_bounds__(kScalarNT) void k_batch_scalar(const PrepField* F) {
+  __shared__ double red[kScalarNT];
   const PrepField& P = F[blockIdx.x];
   double m = INFINITY;
   if (P.L > 0) {
     const int64_t* nb = P.nb[P.L - 1];
     const int64_t n = nb[0] * nb[1] * nb[2];
-    for (int64_t i = threadIdx.x; i < n; i += NT) m = fmin(m, P.tau[P.L - 1][i]);
+    const double* tau = P.tau[P.L - 1];
+    // eight independent loads in flight per lane
+    double mm[8] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
+    int64_t i = threadIdx.x;
+    for (; i + 7 * kScalarNT < n; i += 8 * kScalarNT)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mm[u] = fmin(mm[u], tau[i + u * kScalarNT]);
+    for (; i < n; i += kScalarNT) mm[0] = fmin(mm[0], tau[i]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmin(m, mm[u]);
   } else if (threadIdx.x == 0) {
     m = P.tau[0][0];
   }
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
+  for (int w = kScalarNT / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
@@ -610,7 +627,7 @@ void launch_prep_batch(const PrepStages& g, const PrepField* F, int nf, hipStrea
     if (g.tab_n[s] > 0)
       hipLaunchKernelGGL(k_batch_tables, dim3(grid_for(g.tab_n[s])), dim3(NT), 0, st, F, g.tab_first[s], nf,
                          g.tab_n[s], s);
-  hipLaunchKernelGGL(k_batch_scalar, dim3(unsigned(nf)), dim3(NT), 0, st, F);
+  hipLaunchKernelGGL(k_batch_scalar, dim3(unsigned(nf)), dim3(kScalarNT), 0, st, F);
   BM_HIP(hipGetLastError());
 }
 
