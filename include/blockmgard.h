@@ -69,8 +69,8 @@ typedef enum { BM_F32 = 0, BM_F64 = 1 } bm_dtype;
  *            (blocks of 2^k+1 nodes share one face with each neighbour);
  *            ignored when L == 0.  b = 33 runs each block level as two
  *            launches (three when recomposing) through a plan-owned scratch
- *            array, and is not taken by the transposes (bm_*_adjoint,
- *            bm_qoi_deltas) or by batches: those return BM_EUNSUPPORTED
+ *            array, its transposes likewise; batches do not take b = 33
+ *            (BM_EUNSUPPORTED)
  *   L, M     number of local (In-cache Block) and global levels (Sec. IV-B)
  *   pad_mode 0 = clamp (padded nodes copy the nearest node), 1 = zero fill
  *   eta      safety share of every tolerance kept back for working-precision

@@ -380,9 +380,334 @@ void launch_local_rec_T(const bm_plan_s& p, int s, const void* gin, const int64_
   }
 }
 
+// ------------------------------------------------------- 33^3 block levels
+// Transposes of the 33^3 block level, split like the forward kernels: a
+// block is cut along x into halves, here overlapping by two columns (x in
+// [0, 17] and [15, 32]) so that the transposed interpolation at the coarse
+// columns next to the cut (16 and 18) has both neighbours; the first half
+// stores x <= 16, the second x >= 17.  The transposed correction runs as an
+// x spread per block into a scratch array (the plan's line-pass buffer),
+// then the y and z spreads per half.  Halves of one colour class write
+// disjoint nodes, so the colour passes keep the summation order fixed.
+namespace w33 {
+constexpr int B = 33, MC = 17, MI = 15, HW = 18, NCOL = B * HW, NT = 640, T2B = MI * MI * B, ZB = MI * MI * MI;
+__device__ inline int x0(int h) { return h ? 15 : 0; }
+__device__ inline bool stores(int h, int x) { return h ? x >= 17 : x <= 16; }
+}  // namespace w33
+
+template <typename T>
+struct W33Args {
+  const T* gc;            // decompose: gradient of the coefficients (level view); recompose: output
+  int64_t cs[3];
+  const T* gcur;          // gradient of the coarse grid G^s (compact, dims cn); recompose: output
+  int64_t cn[3];
+  T* out;                 // decompose: gradient of G^{s-1} (dense, dims on)
+  int64_t on[3];
+  const T* gin;           // recompose: gradient of G^{s-1} (dense, dims in, zero at or beyond lim)
+  int64_t in[3], lim[3];
+  T* zs;                  // recompose: interior coarse gradients per block [ZB]
+  T* t2;                  // x-spread result per block [MI][MI][B]
+  int64_t nb[3];
+  ColorSet c;
+};
+
+// z part of P3^T at the even planes of a column of 33 values
+template <typename T>
+__device__ inline T restrict_z33(const T (&v)[w33::B], int j) {
+  using namespace w33;
+  T r = v[2 * j];
+  if (j > 0 && j < MC - 1)
+    r += T(0.5) * (v[2 * j - 1] + v[2 * j + 1]);
+  else if (j > 0)
+    r += T(0.5) * v[2 * j - 1];
+  else
+    r += T(0.5) * v[2 * j + 1];
+  return r;
+}
+
+// y and x parts of P3^T at coarse node (j, y, x) from R[MC][B][HW] of half h
+template <typename T>
+__device__ inline T gather33(const T* R, int j, int y, int xl, int x) {
+  using namespace w33;
+  const T* pl = R + j * B * HW;
+  auto at = [&](int yy, int dx) { return pl[yy * HW + xl + dx]; };
+  T acc = at(y, 0);
+  T side = T(0), corner = T(0);
+  if (y > 0) side += at(y - 1, 0);
+  if (y < B - 1) side += at(y + 1, 0);
+  if (x > 0) side += at(y, -1);
+  if (x < B - 1) side += at(y, 1);
+  if (y > 0 && x > 0) corner += at(y - 1, -1);
+  if (y > 0 && x < B - 1) corner += at(y - 1, 1);
+  if (y < B - 1 && x > 0) corner += at(y + 1, -1);
+  if (y < B - 1 && x < B - 1) corner += at(y + 1, 1);
+  return acc + T(0.5) * side + T(0.25) * corner;
+}
+
+// x spread of the transposed correction, one workgroup per block: Z[MI]^3
+// (from the coarse grid's interior nodes, or from zs) -> t2[MI][MI][B]
+template <typename T>
+__global__ __launch_bounds__(256) void k_w33_spread_x(W33Args<T> a, int from_zs) {
+  using namespace w33;
+  __shared__ T Z[ZB];
+  const int64_t blk = blockIdx.x;
+  const int64_t bx = blk % a.nb[2], t = blk / a.nb[2], by = t % a.nb[1], bz = t / a.nb[1];
+  const int64_t c0 = bz * (MC - 1), c1 = by * (MC - 1), c2 = bx * (MC - 1), cpl = a.cn[1] * a.cn[2];
+  for (int i = threadIdx.x; i < ZB; i += 256) {
+    const int J = i / (MI * MI), r = i - J * MI * MI, I = r / MI, K = r - I * MI;
+    Z[i] = from_zs ? a.zs[blk * ZB + i] : a.gcur[(c0 + J + 1) * cpl + (c1 + I + 1) * a.cn[2] + (c2 + K + 1)];
+  }
+  __syncthreads();
+  if (threadIdx.x < MI * MI) {
+    T l[MI], o[B];
+#pragma unroll
+    for (int K = 0; K < MI; ++K) l[K] = Z[threadIdx.x * MI + K];
+    solve_spread<T, B>(l, o);
+    T* dst = a.t2 + blk * T2B + threadIdx.x * B;
+#pragma unroll
+    for (int x = 0; x < B; ++x) dst[x] = o[x];
+  }
+}
+
+// y spread of one half's columns: t2 -> T1[MI][B][HW]
+template <typename T>
+__device__ inline void w33_spread_y(const W33Args<T>& a, int64_t blk, int h, T* T1) {
+  using namespace w33;
+  const int tid = threadIdx.x;
+  if (tid < MI * HW) {
+    const int J = tid / HW, c = tid - (tid / HW) * HW;
+    T l[MI], o[B];
+    const T* src = a.t2 + blk * T2B + J * MI * B + x0(h) + c;
+#pragma unroll
+    for (int I = 0; I < MI; ++I) l[I] = src[I * B];
+    solve_spread<T, B>(l, o);
+#pragma unroll
+    for (int y = 0; y < B; ++y) T1[(J * B + y) * HW + c] = o[y];
+  }
+}
+
+// Transpose of a decomposition level, per half: v = g + K^T cbar on the
+// fine nodes, then cbar - P3^T v on the coarse nodes, added into G^{s-1}.
+template <typename T>
+__global__ __launch_bounds__(w33::NT) void k_w33_dec_T(W33Args<T> a) {
+  using namespace w33;
+  __shared__ T lds[MC * B * HW];       // T1 [MI][B][HW], then R [MC][B][HW]
+  const int64_t g = blockIdx.x;
+  if (g >= 2 * a.c.nblocks) return;
+  const int h = int(g & 1);
+  int64_t bz, by, bx;
+  color_block(a.c, g >> 1, bz, by, bx);
+  const int64_t blk = (bz * a.nb[1] + by) * a.nb[2] + bx;
+  w33_spread_y(a, blk, h, lds);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const bool act = tid < NCOL;
+  const int y = act ? tid / HW : 0, xl = act ? tid - (tid / HW) * HW : 0, x = x0(h) + xl;
+  const bool ecol = ((y | x) & 1) == 0;
+  const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  T gv[B], v[B];
+  if (act) {
+    const bool own_yx = (y < B - 1 || by == a.nb[1] - 1) && (x < B - 1 || bx == a.nb[2] - 1);
+    const bool lastz = bz == a.nb[0] - 1;
+    const T* col = a.gc + gy * a.cs[1] + gx * a.cs[2];
+    const T* ccol = a.gcur + (gy >> 1) * a.cn[2] + (gx >> 1);
+    const int64_t cpl = a.cn[1] * a.cn[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z) {
+      T w = T(0);
+      if (own_yx && (z < B - 1 || lastz))
+        w = (ecol && !(z & 1)) ? ccol[((oz >> 1) + (z >> 1)) * cpl] : col[(oz + z) * a.cs[0]];
+      gv[z] = w;
+    }
+    T l[MI], t[B];
+#pragma unroll
+    for (int J = 0; J < MI; ++J) l[J] = lds[(J * B + y) * HW + xl];
+    solve_spread<T, B>(l, t);
+#pragma unroll
+    for (int z = 0; z < B; ++z) v[z] = (ecol && !(z & 1)) ? T(0) : gv[z] + t[z];
+  }
+  __syncthreads();                     // T1 is dead: R takes its place
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < MC; ++j) lds[(j * B + y) * HW + xl] = restrict_z33<T>(v, j);
+  }
+  __syncthreads();
+  if (act && stores(h, x)) {
+    if (ecol) {
+#pragma unroll
+      for (int j = 0; j < MC; ++j) v[2 * j] = gv[2 * j] - gather33<T>(lds, j, y, xl, x);
+    }
+    const bool fy = first_on_axis<B>(y, by, a.c.nb[1]), fx = first_on_axis<B>(x, bx, a.c.nb[2]);
+    T* dst = a.out + gy * a.on[2] + gx;
+    const int64_t pl = a.on[1] * a.on[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z) put(dst + (oz + z) * pl, v[z], fy && fx && first_on_axis<B>(z, bz, a.c.nb[0]));
+  }
+}
+
+// gradient of G^{s-1} on the nodes a block owns (zero elsewhere), one column
+template <typename T>
+__device__ inline void w33_owned_column(const W33Args<T>& a, int64_t bz, int64_t by, int64_t bx, int y, int x,
+                                        T (&gv)[w33::B]) {
+  using namespace w33;
+  const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  const bool own_yx = (y < B - 1 || by == a.nb[1] - 1) && (x < B - 1 || bx == a.nb[2] - 1) && gy < a.lim[1] &&
+                      gx < a.lim[2];
+  const bool lastz = bz == a.nb[0] - 1;
+  const T* col = a.gin + gy * a.in[2] + gx;
+  const int64_t pl = a.in[1] * a.in[2];
+#pragma unroll
+  for (int z = 0; z < B; ++z)
+    gv[z] = (own_yx && (z < B - 1 || lastz) && oz + z < a.lim[0]) ? col[(oz + z) * pl] : T(0);
+}
+
+// Transpose of a recomposition level, first part per half: r = P3^T g at
+// the coarse nodes, added into the coarse grid's gradient; the interior ones
+// also go to zs for the transposed correction.
+template <typename T>
+__global__ __launch_bounds__(w33::NT) void k_w33_rec_T_coarse(W33Args<T> a) {
+  using namespace w33;
+  __shared__ T R[MC * B * HW];
+  const int64_t g = blockIdx.x;
+  if (g >= 2 * a.c.nblocks) return;
+  const int h = int(g & 1);
+  int64_t bz, by, bx;
+  color_block(a.c, g >> 1, bz, by, bx);
+  const int64_t blk = (bz * a.nb[1] + by) * a.nb[2] + bx;
+  const int tid = threadIdx.x;
+  const bool act = tid < NCOL;
+  const int y = act ? tid / HW : 0, xl = act ? tid - (tid / HW) * HW : 0, x = x0(h) + xl;
+  const bool ecol = ((y | x) & 1) == 0;
+  if (act) {
+    T gv[B];
+    w33_owned_column(a, bz, by, bx, y, x, gv);
+#pragma unroll
+    for (int j = 0; j < MC; ++j) R[(j * B + y) * HW + xl] = restrict_z33<T>(gv, j);
+  }
+  __syncthreads();
+  if (act && ecol && stores(h, x)) {
+    const bool fy = first_on_axis<B>(y, by, a.c.nb[1]), fx = first_on_axis<B>(x, bx, a.c.nb[2]);
+    const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+    T* cdst = const_cast<T*>(a.gcur) + (gy >> 1) * a.cn[2] + (gx >> 1);
+    const int64_t cpl = a.cn[1] * a.cn[2];
+    const bool icol = y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      const T rc = gather33<T>(R, j, y, xl, x);
+      put(cdst + ((oz >> 1) + j) * cpl, rc, fy && fx && first_on_axis<B>(2 * j, bz, a.c.nb[0]));
+      if (icol && j >= 1 && j <= MC - 2) a.zs[blk * ZB + ((j - 1) * MI + ((y - 2) >> 1)) * MI + ((x - 2) >> 1)] = rc;
+    }
+  }
+}
+
+// Transpose of a recomposition level, last part per half: g - K^T r on the
+// fine nodes, added into the coefficients' gradient.
+template <typename T>
+__global__ __launch_bounds__(w33::NT) void k_w33_rec_T_fine(W33Args<T> a) {
+  using namespace w33;
+  __shared__ T T1[MI * B * HW];
+  const int64_t g = blockIdx.x;
+  if (g >= 2 * a.c.nblocks) return;
+  const int h = int(g & 1);
+  int64_t bz, by, bx;
+  color_block(a.c, g >> 1, bz, by, bx);
+  const int64_t blk = (bz * a.nb[1] + by) * a.nb[2] + bx;
+  w33_spread_y(a, blk, h, T1);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const bool act = tid < NCOL;
+  const int y = act ? tid / HW : 0, xl = act ? tid - (tid / HW) * HW : 0, x = x0(h) + xl;
+  if (!(act && stores(h, x))) return;
+  const bool ecol = ((y | x) & 1) == 0;
+  T gv[B], l[MI], t[B];
+  w33_owned_column(a, bz, by, bx, y, x, gv);
+#pragma unroll
+  for (int J = 0; J < MI; ++J) l[J] = T1[(J * B + y) * HW + xl];
+  solve_spread<T, B>(l, t);
+  const bool fy = first_on_axis<B>(y, by, a.c.nb[1]), fx = first_on_axis<B>(x, bx, a.c.nb[2]);
+  const int64_t oz = bz * (B - 1), gy = by * (B - 1) + y, gx = bx * (B - 1) + x;
+  T* dst = const_cast<T*>(a.gc) + gy * a.cs[1] + gx * a.cs[2];
+#pragma unroll
+  for (int z = 0; z < B; ++z) {
+    if (ecol && !(z & 1)) continue;    // coarse nodes: the coarse part above
+    put(dst + (oz + z) * a.cs[0], gv[z] - t[z], fy && fx && first_on_axis<B>(z, bz, a.c.nb[0]));
+  }
+}
+
+template <typename T>
+W33Args<T> w33_args(const bm_plan_s& p, int s) {
+  const Level& L = p.lv[s - 1];
+  W33Args<T> a{};
+  for (int k = 0; k < 3; ++k) {
+    a.cn[k] = L.m[k];
+    a.nb[k] = L.nb[k];
+  }
+  const int64_t nblocks = L.nb[0] * L.nb[1] * L.nb[2];
+  if (size_t(nblocks) * w33::T2B > p.ws.t_elems) fail(BM_EINVAL, "plan workspace too small for 33^3 blocks");
+  a.t2 = static_cast<T*>(p.ws.t1);
+  a.zs = static_cast<T*>(p.ws.t2);
+  return a;
+}
+
+template <typename T>
+void launch_w33_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  W33Args<T> a = w33_args<T>(p, s);
+  const View3 cv = level_view(p, s, const_cast<void*>(gcoeff));
+  a.gc = static_cast<const T*>(cv.ptr);
+  a.gcur = static_cast<const T*>(p.ws.grid[s]);
+  a.out = static_cast<T*>(out);
+  for (int k = 0; k < 3; ++k) {
+    a.cs[k] = cv.s[k];
+    a.on[k] = L.n[k];
+  }
+  const int64_t nblocks = L.nb[0] * L.nb[1] * L.nb[2];
+  hipLaunchKernelGGL(k_w33_spread_x<T>, dim3(unsigned(nblocks)), dim3(256), 0, st, a, 0);
+  BM_HIP(hipGetLastError());
+  for (int color = 0; color < 8; ++color) {
+    a.c = color_set(L, color, 1);
+    if (a.c.nblocks == 0) continue;
+    hipLaunchKernelGGL(k_w33_dec_T<T>, dim3(unsigned(2 * a.c.nblocks)), dim3(w33::NT), 0, st, a);
+    BM_HIP(hipGetLastError());
+  }
+}
+
+template <typename T>
+void launch_w33_rec_T(const bm_plan_s& p, int s, const void* gin, const int64_t in[3], const int64_t lim[3],
+                      void* gcoeff, hipStream_t st) {
+  const Level& L = p.lv[s - 1];
+  W33Args<T> a = w33_args<T>(p, s);
+  const View3 cv = level_view(p, s, gcoeff);
+  a.gc = static_cast<const T*>(cv.ptr);
+  a.gcur = static_cast<const T*>(p.ws.grid[s]);
+  a.gin = static_cast<const T*>(gin);
+  for (int k = 0; k < 3; ++k) {
+    a.cs[k] = cv.s[k];
+    a.in[k] = in[k];
+    a.lim[k] = lim[k];
+  }
+  const int64_t nblocks = L.nb[0] * L.nb[1] * L.nb[2];
+  for (int color = 0; color < 8; ++color) {
+    a.c = color_set(L, color, 1);
+    if (a.c.nblocks == 0) continue;
+    hipLaunchKernelGGL(k_w33_rec_T_coarse<T>, dim3(unsigned(2 * a.c.nblocks)), dim3(w33::NT), 0, st, a);
+    BM_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_w33_spread_x<T>, dim3(unsigned(nblocks)), dim3(256), 0, st, a, 1);
+  BM_HIP(hipGetLastError());
+  for (int color = 0; color < 8; ++color) {
+    a.c = color_set(L, color, 1);
+    if (a.c.nblocks == 0) continue;
+    hipLaunchKernelGGL(k_w33_rec_T_fine<T>, dim3(unsigned(2 * a.c.nblocks)), dim3(w33::NT), 0, st, a);
+    BM_HIP(hipGetLastError());
+  }
+}
+
 template <typename T>
 void local_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out, hipStream_t st) {
-  if (p.cfg.block == 9)
+  if (p.cfg.block == 33)
+    launch_w33_dec_T<T>(p, s, gcoeff, out, st);
+  else if (p.cfg.block == 9)
     launch_local_dec_T<T, 9>(p, s, gcoeff, out, st);
   else
     launch_local_dec_T<T, 17>(p, s, gcoeff, out, st);
@@ -391,7 +716,9 @@ void local_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out, hipSt
 template <typename T>
 void local_rec_T(const bm_plan_s& p, int s, const void* gin, const int64_t in[3], const int64_t lim[3], void* gcoeff,
                  hipStream_t st) {
-  if (p.cfg.block == 9)
+  if (p.cfg.block == 33)
+    launch_w33_rec_T<T>(p, s, gin, in, lim, gcoeff, st);
+  else if (p.cfg.block == 9)
     launch_local_rec_T<T, 9>(p, s, gin, in, lim, gcoeff, st);
   else
     launch_local_rec_T<T, 17>(p, s, gin, in, lim, gcoeff, st);
@@ -724,7 +1051,6 @@ void recompose_adjoint_t(bm_plan_s& p, const void* gx, void* gcoeff, hipStream_t
 }  // namespace
 
 void decompose_adjoint(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t st) {
-  if (p.L > 0 && p.cfg.block == 33) fail(BM_EUNSUPPORTED, "the transposes take b = 9 or 17");
   if (p.cfg.dtype == BM_F32)
     decompose_adjoint_t<float>(p, gcoeff, gx, st);
   else
@@ -732,7 +1058,6 @@ void decompose_adjoint(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t s
 }
 
 void recompose_adjoint(bm_plan_s& p, const void* gx, void* gcoeff, hipStream_t st) {
-  if (p.L > 0 && p.cfg.block == 33) fail(BM_EUNSUPPORTED, "the transposes take b = 9 or 17");
   if (p.cfg.dtype == BM_F32)
     recompose_adjoint_t<float>(p, gx, gcoeff, st);
   else

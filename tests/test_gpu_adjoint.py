@@ -31,6 +31,10 @@ CASES = [
     ((97, 65, 129), 17, 1, 2, torch.float32, "clamp"),    # 6 x 4 x 8 blocks
     ((40, 50, 61), 9, 2, 2, torch.float64, "clamp"),      # ragged everywhere
     ((17, 17, 17), 17, 1, 0, torch.float64, "clamp"),     # one block: no shared faces
+    ((65, 65, 65), 33, 1, 2, torch.float64, "clamp"),     # 33^3 blocks (split transposes)
+    ((70, 40, 100), 33, 1, 1, torch.float32, "zero"),     # 33^3 blocks, ragged: padded to 97 x 65 x 129
+    ((65, 65, 129), 33, 2, 1, torch.float64, "clamp"),    # two 33^3 block levels
+    ((33, 33, 33), 33, 1, 0, torch.float64, "clamp"),     # a single 33^3 block
 ]
 
 
@@ -101,7 +105,7 @@ def _dot_identity(p, shape, dt, seed, tol):
     assert abs(a - b_) <= tol * scale, (a, b_, scale)
 
 
-@pytest.mark.parametrize("case", CASES[:6], ids=_ids)
+@pytest.mark.parametrize("case", CASES[:6] + CASES[-4:-2], ids=_ids)
 def test_dot_product_identity(case):
     shape, b, L, M, dt, pad = case
     print("case", _ids(case), flush=True)

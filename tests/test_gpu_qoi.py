@@ -29,6 +29,7 @@ CASES = [
     ((33, 33, 33), 17, 1, 2, torch.float32, (8, 24), 1e-5),
     ((65, 33, 49), 9, 2, 1, torch.float64, (10, 30), 1e-6),
     ((40, 50, 61), 9, 1, 2, torch.float32, (12, 36), 1e-5),     # padded grid
+    ((65, 65, 65), 33, 1, 2, torch.float64, (16, 48), 1e-6),    # 33^3 blocks
 ]
 
 
