@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="roi512", choices=["roi512", "batch256", "qoi512", "turbo1024", "sweep512"],
+    ap.add_argument("--workload", default="roi512", choices=["roi512", "batch256", "qoi512", "turbo1024", "sweep512", "eq1"],
                     help="roi512: the 512^3 ROI field (default); batch256: 256 fields, batched vs per-field; "
                          "qoi512: adjoint-guided bounds for a mean over a 128^3 box vs a uniform bound; "
                          "turbo1024: FP64 1024x1024x512 turbulence + front, gradient ROI, autotuned (b, L, M)")
@@ -100,6 +100,9 @@ def main():
         return
     if args.workload == "sweep512":
         run_sweep(args)
+        return
+    if args.workload == "eq1":
+        run_eq1(args)
         return
 
     import numpy as np
@@ -602,6 +605,132 @@ def run_sweep(args):
         "config": {"workload": f"{n}^3 FP32 k^-3 Gaussian random field, two 64^3 ROI boxes at REL 1e-5, "
                                f"background REL 1e-2; b=17, L in 1..4, M in 0..3", "best": {"L": best["L"], "M": best["M"]}},
         "sweep": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_eq1(args):
+    """Eq. 1 (Sec. IV-B) re-fitted on this GPU.  A stage's time on N units is
+    t(N) = 1/Slope + N/TP_peak, i.e. throughput N / t(N) = N / (1/Slope +
+    N/TP_peak); a least-squares line of t against N gives Slope, TP_peak and
+    the knee N = TP_peak / Slope where half the peak is reached.  Stages: one
+    fused 17^3 block level (N = blocks), one fused global level (N = nodes of
+    its grid), the Huffman stage (N = codes, host-side wall time of the whole
+    encode).  The fitted stages then predict the fused decompose + quantize
+    time of (L, M) splits of the 512^3 workload, next to the measured time:
+    the prediction Algorithm 1 would select on."""
+    import numpy as np
+    import torch
+
+    from paper_2609_00205_amd import Plan, synth, api
+
+    torch.cuda.set_device(0)
+    reps = max(3, args.steps)
+
+    def timed_level(plan, x, bt, level):
+        codes = torch.empty(plan.coeff_shape, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            plan.decompose_quantize(x, bt, codes=codes, check=False)
+        torch.cuda.synchronize()
+        plan.timing(True)
+        for _ in range(reps):
+            plan.decompose_quantize(x, bt, codes=codes, check=False)
+        torch.cuda.synchronize()
+        t = plan.timing_get()
+        plan.timing(False)
+        return t["decompose"][level] / reps
+
+    def fit(Ns, ts):
+        b, a = np.polyfit(np.asarray(Ns, float), np.asarray(ts, float), 1)   # t = a + b N
+        return {"slope_per_ms": 1.0 / a if a > 0 else None, "tp_peak_per_ms": 1.0 / b,
+                "latency_ms": a, "knee_N": (1.0 / b) / (1.0 / a) if a > 0 else None,
+                "points": [{"N": int(n), "ms": round(float(t), 5)} for n, t in zip(Ns, ts)]}
+
+    local_N, local_t = [], []
+    for k in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32):
+        n = 16 * k + 1
+        x = torch.from_numpy(synth.gaussian_random_field((n, n, n), 3.0, seed=7)).cuda()
+        p = Plan((n, n, n), dtype=torch.float32, block=17, L=1, M=0)
+        bt = p.tolmap_from_boxes([], 1e-2 * float(x.abs().max()))
+        local_N.append(k ** 3)
+        local_t.append(timed_level(p, x, bt, 0))
+        print(f"[bench] block level, {k ** 3} blocks: {local_t[-1]:.4f} ms", file=sys.stderr, flush=True)
+        del p, x, bt
+    glob_N, glob_t = [], []
+    for j in range(4, 10):
+        n = (1 << j) + 1
+        x = torch.from_numpy(synth.gaussian_random_field((n, n, n), 3.0, seed=8)).cuda()
+        p = Plan((n, n, n), dtype=torch.float32, block=17, L=0, M=1)
+        bt = p.tolmap_from_boxes([], 1e-2 * float(x.abs().max()))
+        glob_N.append(n ** 3)
+        glob_t.append(timed_level(p, x, bt, 0))
+        print(f"[bench] global level, {n}^3 nodes: {glob_t[-1]:.4f} ms", file=sys.stderr, flush=True)
+        del p, x, bt
+    huf_N, huf_t = [], []
+    rng = np.random.default_rng(9)
+    for e in range(16, 28, 2):
+        nc = 1 << e
+        q = torch.from_numpy(np.rint(rng.laplace(0, 4.0, nc)).astype(np.int32)).cuda()
+        api.huffman_encode(q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.huffman_encode(q)
+        huf_N.append(nc)
+        huf_t.append((time.perf_counter() - t0) * 1e3 / reps)
+        print(f"[bench] Huffman, {nc} codes: {huf_t[-1]:.3f} ms", file=sys.stderr, flush=True)
+    fl, fg, fh = fit(local_N, local_t), fit(glob_N, glob_t), fit(huf_N, huf_t)
+
+    # predicted vs measured fused decompose + quantize of the 512^3 workload
+    n = args.n
+    x_np, boxes = synth.workload_roi(n, seed=2)
+    xd = torch.from_numpy(x_np).cuda()
+    scale = float(xd.abs().max())
+    abs_boxes = [bx + (1e-5 * scale,) for bx in boxes]
+    rows = []
+    for (L, M) in ((1, 0), (1, 1), (1, 2), (2, 0), (2, 2), (3, 0), (3, 2), (4, 0)):
+        p = Plan((n, n, n), dtype=torch.float32, block=17, L=L, M=M)
+        bt = p.tolmap_from_boxes(abs_boxes, 1e-2 * scale)
+        codes = torch.empty(p.coeff_shape, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            p.decompose_quantize(xd, bt, codes=codes, check=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            p.decompose_quantize(xd, bt, codes=codes, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        measured = e0.elapsed_time(e1) / reps
+        pred = 0.0
+        m = p.coeff_shape[0]
+        for s in range(1, L + M + 1):
+            if s <= L:
+                nb = ((m - 1) // 16) ** 3
+                pred += fl["latency_ms"] + nb / fl["tp_peak_per_ms"]
+            else:
+                pred += fg["latency_ms"] + m ** 3 / fg["tp_peak_per_ms"]
+            m = (m + 1) // 2
+        rows.append({"L": L, "M": M, "predicted_ms": round(pred, 4), "measured_ms": round(measured, 4)})
+        print(f"[bench] L={L} M={M}: predicted {pred:.4f} ms, measured {measured:.4f} ms", file=sys.stderr, flush=True)
+        del p, codes, bt
+    out = {
+        "metric": "Eq. 1 throughput model re-fitted on this GPU (Slope, TP_peak per stage)",
+        "value": round(fl["tp_peak_per_ms"], 3),
+        "unit": "17^3 blocks per ms (block level TP_peak)",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 2,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "k^-3 Gaussian random fields, cubes of 17..513 nodes per side, REL 1e-2; "
+                               "Laplace-distributed codes for the Huffman stage; 512^3 ROI workload for the (L, M) check"},
+        "block_level": fl, "global_level": fg, "huffman": fh,
+        "predicted_vs_measured": rows,
     }
     print(json.dumps(out), flush=True)
 

@@ -303,7 +303,7 @@ typedef struct {
 
 /* Chooses block size and level split for field x (device, logical dims and
  * dtype of *in) under a per-voxel absolute tolerance (device, logical dims,
- * FP64).  Candidates: pure global M = 1..6; b in {9, 17} with L = 1..4 and
+ * FP64).  Candidates: pure global M = 1..6; b in {9, 17, 33} with L = 1..4 and
  * M = 0..4; those the dims admit (a valid plan padding the volume by at most
  * 1/8).  Each is run: median time of `reps` fused decompose + quantize runs
  * and the exact Huffman-coded size.  The fastest candidate whose ratio is at
@@ -313,6 +313,18 @@ typedef struct {
  * candidate, slack outside [0, 1)). */
 bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_tol, double slack, int reps,
                       bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
+
+/* The same candidates and measurements, chosen by the rule of Algorithm 1
+ * (Sec. IV-B) under a time budget: of the candidates whose fused decompose +
+ * quantize time (median of reps) is at most budget_ms, the one with the
+ * most global levels M, then the fewest block levels L, then the best ratio
+ * (between block sizes).  The lossless stage is left out of the budget: its
+ * time depends on the number of codes, the same for every candidate.
+ * Errors: BM_ERANGE when no candidate fits (*out, the table and *ncands are
+ * still filled, *out with the fastest candidate), BM_EINVAL (budget not
+ * positive, no admissible candidate).  Synchronous. */
+bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* voxel_tol, double budget_ms, int reps,
+                             bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
 
 /* ---- diagnostics ---------------------------------------------------------- */
 

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libblockmga
 BM_F32, BM_F64 = 0, 1
 STATUS = {0: "BM_OK", -1: "BM_EINVAL", -2: "BM_ENOMEM", -3: "BM_EHIP", -4: "BM_ENONFINITE",
           -5: "BM_ECAPACITY", -6: "BM_ECORRUPT", -7: "BM_ERANGE", -8: "BM_EUNSUPPORTED"}
+BM_ERANGE = -7
 
 
 class BMConfig(C.Structure):
@@ -65,6 +66,8 @@ _SIGS = {
     "bm_dequantize_delta": [P, P, P, P, P],
     "bm_autotune": [C.POINTER(BMConfig), P, P, C.c_double, C.c_int, C.POINTER(BMConfig), C.POINTER(BMCandidate),
                     C.c_int, C.POINTER(C.c_int), P],
+    "bm_autotune_budget": [C.POINTER(BMConfig), P, P, C.c_double, C.c_int, C.POINTER(BMConfig),
+                           C.POINTER(BMCandidate), C.c_int, C.POINTER(C.c_int), P],
     "bm_batch_create": [C.c_int, C.POINTER(BMConfig), C.POINTER(P)],
     "bm_batch_destroy": [P],
     "bm_batch_plan": [P, C.c_int, C.POINTER(P)],

@@ -319,10 +319,15 @@ def parse_huffman(buf: bytes) -> dict:
 
 
 def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps: int = 3,
-             pad_mode: str = "clamp", eta: Optional[float] = None, stream=None):
+             pad_mode: str = "clamp", eta: Optional[float] = None, stream=None, budget_ms: Optional[float] = None):
     """Measured choice of (block, L, M) for field x under the per-voxel absolute
     tolerance voxel_tol (FP64, same shape).  Returns (choice, candidates):
-    choice = {"block", "L", "M"}; candidates = the measured table."""
+    choice = {"block", "L", "M"}; candidates = the measured table.
+
+    budget_ms: choose by the rule of Algorithm 1 instead (most global levels,
+    then fewest block levels, among the candidates whose fused decompose +
+    quantize time fits); choice["fits"] tells whether any did (if not, the
+    fastest candidate is returned)."""
     if x.dtype not in _DT:
         raise ValueError("x must be float32 or float64")
     _need(x, x.dtype, None, "x")
@@ -333,11 +338,22 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
     cap = 128
     table = (_lib.BMCandidate * cap)()
     n = C.c_int(0)
-    call("bm_autotune", C.byref(cfg), _ptr(x), _ptr(voxel_tol), float(slack), int(reps), C.byref(out), table, cap,
-         C.byref(n), _stream(stream))
+    fits = None
+    if budget_ms is None:
+        call("bm_autotune", C.byref(cfg), _ptr(x), _ptr(voxel_tol), float(slack), int(reps), C.byref(out), table,
+             cap, C.byref(n), _stream(stream))
+    else:
+        st = _lib.lib().bm_autotune_budget(C.byref(cfg), _ptr(x), _ptr(voxel_tol), float(budget_ms), int(reps),
+                                           C.byref(out), table, cap, C.byref(n), _stream(stream))
+        if st not in (0, _lib.BM_ERANGE):
+            _lib.check(st)
+        fits = st == 0
     cands = [{"block": table[i].block, "L": table[i].L, "M": table[i].M, "status": table[i].status,
               "ms": table[i].ms, "ratio": table[i].ratio} for i in range(min(n.value, cap))]
-    return {"block": out.block, "L": out.L, "M": out.M}, cands
+    choice = {"block": out.block, "L": out.L, "M": out.M}
+    if fits is not None:
+        choice["fits"] = fits
+    return choice, cands
 
 
 def max_block_levels(shape: Sequence[int], block: int) -> int:

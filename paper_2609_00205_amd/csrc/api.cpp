@@ -371,6 +371,22 @@ bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_to
   });
 }
 
+bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* voxel_tol, double budget_ms, int reps,
+                             bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t st) {
+  return guarded([&] {
+    need(in && x && voxel_tol && out, "null argument");
+    need(cap >= 0 && (cap == 0 || cands), "null candidate table");
+    need(budget_ms > 0.0, "budget must be positive");
+    bm_config o{};
+    bool fits = false;
+    const std::vector<bm_candidate> all = bm::autotune(*in, x, voxel_tol, 0.0, reps, o, st, budget_ms, &fits);
+    for (int i = 0; i < cap && i < int(all.size()); ++i) cands[i] = all[i];
+    if (ncands) *ncands = int(all.size());
+    *out = o;
+    if (!fits) bm::fail(BM_ERANGE, "no candidate fits the time budget; *out holds the fastest");
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");

@@ -6,10 +6,14 @@
 // every admissible candidate is run on the caller's field and tolerance:
 // the fused decompose + quantize is timed with HIP events (median over
 // repetitions) and the coded size is the exact Huffman stream size of its
-// codes.  The fastest candidate whose compression ratio is within a slack of
-// the best ratio wins.
+// codes.  Two rules pick from the measured table: the fastest candidate whose
+// compression ratio is within a slack of the best ratio, or the rule of
+// Algorithm 1 under a time budget: of the candidates that fit it, the most
+// global levels M, then the fewest block levels L (the paper's order), then
+// the best ratio.
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "internal.h"
@@ -77,8 +81,10 @@ void measure(const bm_config& cfg, const void* x, const double* voxel_tol, int r
 }  // namespace
 
 std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const double* voxel_tol, double slack, int reps,
-                                   bm_config& out, hipStream_t st) {
-  if (!(slack >= 0.0 && slack < 1.0)) fail(BM_EINVAL, "slack must lie in [0, 1)");
+                                   bm_config& out, hipStream_t st, double budget_ms, bool* fits) {
+  const bool budget = budget_ms > 0.0;
+  if (!budget && !(slack >= 0.0 && slack < 1.0)) fail(BM_EINVAL, "slack must lie in [0, 1)");
+  if (budget_ms < 0.0 || !std::isfinite(budget_ms)) fail(BM_EINVAL, "budget must be positive and finite");
   std::vector<bm_candidate> cands;
   int64_t nlog = 1;
   for (int a = 0; a < in.ndim; ++a) nlog *= in.dims[a];
@@ -109,11 +115,25 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
     for (int L = 1; L <= 4; ++L)
       for (int M = 0; M <= 4; ++M) consider(block, L, M);
   if (cands.empty()) fail(BM_EINVAL, "no admissible (block, L, M) for these dims");
-  double best = 0;
-  for (auto& k : cands) best = std::max(best, k.ratio);
   const bm_candidate* win = nullptr;
-  for (auto& k : cands)
-    if (k.ratio >= (1.0 - slack) * best && (!win || k.ms < win->ms)) win = &k;
+  if (budget) {
+    // Algorithm 1: argmax (M, -L) over the candidates within the budget;
+    // ties (block sizes) by the better ratio.  None fits: the fastest.
+    for (auto& k : cands) {
+      if (k.ms > budget_ms) continue;
+      if (!win || k.M > win->M || (k.M == win->M && (k.L < win->L || (k.L == win->L && k.ratio > win->ratio))))
+        win = &k;
+    }
+    if (fits) *fits = win != nullptr;
+    if (!win)
+      for (auto& k : cands)
+        if (!win || k.ms < win->ms) win = &k;
+  } else {
+    double best = 0;
+    for (auto& k : cands) best = std::max(best, k.ratio);
+    for (auto& k : cands)
+      if (k.ratio >= (1.0 - slack) * best && (!win || k.ms < win->ms)) win = &k;
+  }
   out = in;
   out.block = win->block == 0 ? in.block : win->block;
   out.L = win->L;

@@ -313,8 +313,10 @@ void batch_dequantize_recompose(bm_batch_s& b, const int32_t* const* codes, cons
 int batch_overflows(bm_batch_s& b, std::vector<int>& bad, hipStream_t st);
 
 // measured choice of (b, L, M); returns every measured candidate
+// (budget_ms > 0: Algorithm 1's rule under that budget; *fits tells whether
+// a candidate fit it, else the fastest is returned)
 std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const double* voxel_tol, double slack, int reps,
-                                   bm_config& out, hipStream_t st);
+                                   bm_config& out, hipStream_t st, double budget_ms = 0.0, bool* fits = nullptr);
 
 // huffman (host buffers)
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);

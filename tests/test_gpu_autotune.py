@@ -45,3 +45,38 @@ def test_autotune_rule_and_bounds(dt):
     xr = decompress(p.compress(xd, bt))
     err = (xr.double() - xd.double()).abs()
     assert bool((err <= vtd).all())
+
+
+def test_autotune_budget_rule():
+    # Algorithm 1 (Sec. IV-B) on the measured table: among the candidates whose
+    # fused decompose + quantize time fits the budget, the most global levels,
+    # then the fewest block levels (ties between block sizes: best ratio)
+    from oracle import selector
+    from paper_2609_00205_amd import autotune
+    shape = (65, 65, 33)
+    x = synth.turbulence_with_front(shape, seed=3)
+    sc = float(np.abs(x).max())
+    vt = np.full(shape, 1e-4 * sc)
+    xd = torch.from_numpy(x).cuda()
+    vtd = torch.from_numpy(vt).cuda()
+    _, cands = autotune(xd, vtd, reps=2)
+    budget = float(np.median([c["ms"] for c in cands]))
+    choice, cands = autotune(xd, vtd, reps=2, budget_ms=budget)
+    feasible = [c for c in cands if c["ms"] <= budget]
+    if not feasible:
+        assert choice["fits"] is False
+        return
+    assert choice["fits"] is True
+    win = max(feasible, key=lambda c: (c["M"], -c["L"], c["ratio"]))
+    assert (choice["L"], choice["M"]) == (win["L"], win["M"])
+    if win["L"] > 0:
+        assert choice["block"] == win["block"]
+    # the oracle's Algorithm 1 picks the same (L, M) from the same feasibility
+    times = {(c["L"], c["M"]): c["ms"] for c in feasible}
+    pick = selector.select(sorted(times), lambda L, M: times[(L, M)], budget)
+    assert pick == (choice["L"], choice["M"])
+    # a budget nothing meets: the fastest candidate, flagged as not fitting
+    choice2, cands2 = autotune(xd, vtd, reps=1, budget_ms=1e-6)
+    assert choice2["fits"] is False
+    fastest = min(cands2, key=lambda c: c["ms"])
+    assert (choice2["L"], choice2["M"]) == (fastest["L"], fastest["M"])
