@@ -243,13 +243,18 @@ bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int
 
 /* Decompose, quantize with block_tol (device map as above) and Huffman-code x
  * (device) into a self-describing host buffer: header (config, gains),
- * block tolerance map, Huffman stream, CRC32.  If the coded form is not
- * smaller than the raw data the raw bytes are stored instead (Sec. V-F).
- * Synchronous.  BM_ECAPACITY sets *out_bytes to the size needed. */
+ * block tolerance map, Huffman stream, CRC-32 (polynomial 0xEDB88320, as
+ * zlib) of the header with its CRC field zeroed followed by the payload.  If
+ * the coded form is not smaller than the raw data the raw bytes are stored
+ * instead (Sec. V-F).  Synchronous.  BM_ECAPACITY sets *out_bytes to the
+ * size needed (that call plans the stream's size but does not encode it). */
 bm_status bm_compress(bm_plan plan, const void* x, const double* block_tol, void* out,
                       size_t capacity, size_t* out_bytes, hipStream_t stream);
 
-/* Read the configuration stored in a compressed buffer (host, synchronous). */
+/* Read the configuration stored in a compressed buffer (host, synchronous).
+ * Checks the header (magic, version, payload size), not the CRC: a call that
+ * only sizes the destination does not pay for a pass over the payload;
+ * bm_decompress verifies the CRC.  Errors: BM_ECORRUPT. */
 bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg);
 
 /* Rebuild x (device, logical dims and dtype of the stored config) from a

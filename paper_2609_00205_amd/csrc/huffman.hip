@@ -363,6 +363,12 @@ size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st) {
 }
 
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st) {
+  const size_t bytes = huffman_size(codes, n, st);
+  out.resize(bytes);
+  return huffman_encode_to(codes, n, out.data(), bytes, st);
+}
+
+size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t capacity, hipStream_t st) {
   DevBuf<uint8_t> dlen(NSYM);
   DevBuf<uint32_t> dcw(NSYM);
   const StreamPlan sp = plan_stream(codes, n, st, dlen, dcw);
@@ -390,8 +396,8 @@ size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out
   const int64_t np = int64_t(psym.size());
   HuffHeader hh{kHuffMagic, 3, n, nch, nw, nout, np};
   const size_t bytes = sizeof(hh) + size_t(np) * 3 + (nch + 1) * 16 + size_t(nw) * 4 + size_t(nout) * 4;
-  out.resize(bytes);
-  uint8_t* o = out.data();
+  if (bytes > capacity) fail(BM_ECAPACITY, "Huffman stream larger than its buffer");
+  uint8_t* o = dst;
   std::memcpy(o, &hh, sizeof(hh));
   o += sizeof(hh);
   if (np) std::memcpy(o, psym.data(), size_t(np) * 2);

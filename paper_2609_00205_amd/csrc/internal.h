@@ -320,6 +320,9 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
 
 // huffman (host buffers)
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);
+// the same stream written to dst (host, at least capacity bytes: the size
+// huffman_size gives); returns its size
+size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t capacity, hipStream_t st);
 // exact size of the stream huffman_encode would write (synchronizes)
 size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);

@@ -189,6 +189,12 @@ def test_compress_decompress(shape, b, L, M):
     xd = torch.from_numpy(x).cuda()
     buf = p.compress(xd, bt)
     assert api.compressed_config(buf)["shape"] == shape
+    # the container's CRC is the standard CRC-32 of the header (CRC field
+    # zeroed, at byte 88 of the 96-byte header) followed by the payload
+    import struct
+    import zlib
+    stored = struct.unpack_from("<I", buf, 88)[0]
+    assert zlib.crc32(buf[:88] + bytes(4) + buf[92:]) == stored
     xr = api.decompress(buf).cpu().double().numpy()
     vt = roi.voxel_tolerance_from_boxes(shape, boxes, 1e-2 * scale)
     assert np.all(np.abs(xr - x.astype(np.float64)) <= vt)
