@@ -27,6 +27,16 @@ def _ptr(t: torch.Tensor) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _writable(buf: bytearray):
+    """A ctypes view of a bytearray the library writes into (no copy)."""
+    return (C.c_char * len(buf)).from_buffer(buf)
+
+
+def _take(buf: bytearray, n: int) -> bytes:
+    """The first n bytes of buf as bytes, copied once."""
+    return memoryview(buf)[:n].tobytes()
+
+
 def _need(t: torch.Tensor, dtype, shape, name):
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
@@ -256,10 +266,10 @@ class Plan:
         except _lib.BMError as e:
             if e.code != -5:
                 raise
-        buf = C.create_string_buffer(need.value)
+        buf = bytearray(need.value)
         got = C.c_size_t(0)
-        call("bm_compress", self._h, _ptr(x), _ptr(block_tol), buf, need.value, C.byref(got), st)
-        return buf.raw[: got.value]
+        call("bm_compress", self._h, _ptr(x), _ptr(block_tol), _writable(buf), need.value, C.byref(got), st)
+        return _take(buf, got.value)
 
 
 def compressed_config(buf: bytes) -> dict:
@@ -286,10 +296,10 @@ def huffman_encode(codes: torch.Tensor, stream=None) -> bytes:
     except _lib.BMError as e:
         if e.code != -5:
             raise
-    buf = C.create_string_buffer(need.value)
+    buf = bytearray(need.value)
     got = C.c_size_t(0)
-    call("bm_huffman_encode", _ptr(codes), codes.numel(), buf, need.value, C.byref(got), st)
-    return buf.raw[: got.value]
+    call("bm_huffman_encode", _ptr(codes), codes.numel(), _writable(buf), need.value, C.byref(got), st)
+    return _take(buf, got.value)
 
 
 def huffman_decode(buf: bytes, n: int, device=None, stream=None) -> torch.Tensor:
@@ -465,9 +475,10 @@ class Batch:
             _need(t, torch.float64, p.block_grid, "block_tol")
         cap = (C.c_size_t * nf)(*[64 + int(x.numel()) * x.element_size() * 2 + 8 * int(t.numel()) + (1 << 20)
                                   for x, t in zip(xs, block_tols)])
-        bufs = [C.create_string_buffer(int(c)) for c in cap]
-        outp = (C.c_void_p * nf)(*[C.cast(b, C.c_void_p).value for b in bufs])
+        bufs = [bytearray(int(c)) for c in cap]
+        views = [_writable(b) for b in bufs]
+        outp = (C.c_void_p * nf)(*[C.addressof(v) for v in views])
         got = (C.c_size_t * nf)()
         self._run(lambda st: call("bm_batch_compress", self._h, self._ptrs(xs), self._ptrs(block_tols), outp, cap,
                                   got, int(use_graph), st), use_graph, stream)
-        return [b.raw[: got[i]] for i, b in enumerate(bufs)]
+        return [_take(b, got[i]) for i, b in enumerate(bufs)]

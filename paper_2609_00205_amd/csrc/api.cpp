@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -80,6 +81,63 @@ uint32_t crc32(const uint8_t* p, size_t n, uint32_t crc = 0) {
   return ~crc;
 }
 
+// The CRC of a concatenation: crc(A B) = Z(crc(A)) ^ crc(B), where Z shifts
+// the CRC register over |B| zero bytes (the pre- and post-inversion cancel).
+// Z is a linear map over GF(2); its 32x32 matrix for 2^k zero bits comes
+// from squaring the one-bit matrix, and the bits of the byte count choose
+// which powers to apply (the combine step of zlib's crc32_combine).
+uint32_t gf2_apply(const uint32_t* mat, uint32_t v) {
+  uint32_t r = 0;
+  for (int i = 0; v; ++i, v >>= 1)
+    if (v & 1) r ^= mat[i];
+  return r;
+}
+
+void gf2_square(uint32_t* sq, const uint32_t* mat) {
+  for (int i = 0; i < 32; ++i) sq[i] = gf2_apply(mat, mat[i]);
+}
+
+uint32_t crc32_shift(uint32_t crc, uint64_t bytes) {
+  if (bytes == 0) return crc;
+  uint32_t a[32], b[32];
+  a[0] = 0xEDB88320u;                    // one zero bit
+  for (int i = 1; i < 32; ++i) a[i] = 1u << (i - 1);
+  gf2_square(b, a);                      // two
+  gf2_square(a, b);                      // four
+  for (;;) {
+    gf2_square(b, a);                    // 8, 32, 128, ... bits: one byte times 1, 4, 16, ...
+    if (bytes & 1) crc = gf2_apply(b, crc);
+    bytes >>= 1;
+    if (!bytes) break;
+    gf2_square(a, b);                    // 2, 8, 32, ... bytes
+    if (bytes & 1) crc = gf2_apply(a, crc);
+    bytes >>= 1;
+    if (!bytes) break;
+  }
+  return crc;
+}
+
+// crc32 of a large buffer on several host threads, continuing from crc
+uint32_t crc32_parallel(const uint8_t* p, size_t n, uint32_t crc) {
+  const size_t kMin = size_t(8) << 20;
+  unsigned nt = std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < kMin || nt < 2) return crc32(p, n, crc);
+  nt = unsigned(std::min<size_t>(nt, n / (kMin / 4)));
+  std::vector<uint32_t> part(nt);
+  std::vector<std::thread> th;
+  const size_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const size_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
+    th.emplace_back([&, t, lo, hi] { part[t] = crc32(p + lo, hi - lo); });
+  }
+  for (auto& t : th) t.join();
+  for (unsigned t = 0; t < nt; ++t) {
+    const size_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
+    crc = crc32_shift(crc, hi - lo) ^ part[t];
+  }
+  return crc;
+}
+
 // container header; payload follows (block tolerances + Huffman stream, or raw data)
 struct CHeader {
   uint32_t magic;       // "BMGD"
@@ -122,7 +180,7 @@ CHeader parse(const void* in, size_t in_bytes, bool check_crc = true) {
   CHeader z = h;
   z.crc = 0;
   uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&z), sizeof(z));
-  c = crc32(static_cast<const uint8_t*>(in) + sizeof(CHeader), size_t(h.payload), c);
+  c = crc32_parallel(static_cast<const uint8_t*>(in) + sizeof(CHeader), size_t(h.payload), c);
   if (c != h.crc) bm::fail(BM_ECORRUPT, "CRC mismatch");
   return h;
 }
@@ -187,7 +245,7 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
   }
   h.crc = 0;
   uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
-  c = crc32(o, size_t(h.payload), c);
+  c = crc32_parallel(o, size_t(h.payload), c);
   h.crc = c;
   std::memcpy(out, &h, sizeof(h));
   return true;
