@@ -16,6 +16,8 @@
 // lanes: both Thomas sweeps are first-order affine recurrences, evaluated
 // by a lane-local pass and a 64-lane scan of affine maps with wave shuffles.
 
+#include <type_traits>
+
 #include "internal.h"
 #include "line_solve.h"
 
@@ -112,20 +114,24 @@ __global__ __launch_bounds__(NT) void k_details(DetArgs<T> a) {
       return U(a.cm0 ? 2 * zz : zz, a.cm1 ? 2 * yy : yy, a.cm2 ? 2 * xx : xx);
     });
     const double inv = a.codes ? *a.qinv : 0.0;
+    // the cell's fine values are all fetched before the first store
+    T f[8];
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
+    for (int t = 1; t < 8; ++t) {
+      const int dz = t >> 2, dy = (t >> 1) & 1, dx = t & 1;
+      f[t] = (dz > k.oz || dy > k.oy || dx > k.ox) ? T(0) : U(z + dz, y + dy, x + dx);
+    }
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          if ((dz | dy | dx) == 0 || dz > k.oz || dy > k.oy || dx > k.ox) continue;
-          const T d = U(z + dz, y + dy, x + dx) - k.interp(dz, dy, dx);
-          const int64_t o = (z + dz) * a.cs[0] + (y + dy) * a.cs[1] + (x + dx) * a.cs[2];
-          if (a.codes)
-            a.codes[o] = quant_g(d, inv, a.flag);
-          else
-            a.coeff[o] = d;
-        }
+    for (int t = 1; t < 8; ++t) {
+      const int dz = t >> 2, dy = (t >> 1) & 1, dx = t & 1;
+      if (dz > k.oz || dy > k.oy || dx > k.ox) continue;
+      const T d = f[t] - k.interp(dz, dy, dx);
+      const int64_t o = (z + dz) * a.cs[0] + (y + dy) * a.cs[1] + (x + dx) * a.cs[2];
+      if (a.codes)
+        a.codes[o] = quant_g(d, inv, a.flag);
+      else
+        a.coeff[o] = d;
+    }
   }
 }
 
@@ -156,22 +162,32 @@ __global__ __launch_bounds__(NT) void k_interp_add(IntArgs<T> a) {
     load_corners(k, cz, cy, cx,
                  [&](int64_t zz, int64_t yy, int64_t xx) { return a.uc[(zz * a.m.n1 + yy) * a.m.n2 + xx]; });
     const double del = a.codes ? *a.qdel : 0.0;
+    // the cell's details are all fetched before the first store
+    T w[8];
+    int32_t qc[8];
+    auto co = [&](int t) {
+      return (z + (t >> 2)) * a.cs[0] + (y + ((t >> 1) & 1)) * a.cs[1] + (x + (t & 1)) * a.cs[2];
+    };
+    auto in = [&](int t) { return !((t >> 2) > k.oz || ((t >> 1) & 1) > k.oy || (t & 1) > k.ox); };
+    if (a.codes) {
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
+      for (int t = 1; t < 8; ++t) qc[t] = in(t) ? a.codes[co(t)] : 0;
+    } else {
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
+      for (int t = 1; t < 8; ++t) w[t] = in(t) ? a.coeff[co(t)] : T(0);
+    }
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          if (dz > k.oz || dy > k.oy || dx > k.ox) continue;
-          const int64_t o = ((z + dz) * a.n.n1 + (y + dy)) * a.n.n2 + (x + dx);
-          if ((dz | dy | dx) == 0) {
-            a.out[o] = k.c[0][0][0];
-            continue;
-          }
-          const int64_t co = (z + dz) * a.cs[0] + (y + dy) * a.cs[1] + (x + dx) * a.cs[2];
-          const T w = a.codes ? T(mul_rn(double(a.codes[co]), del)) : a.coeff[co];
-          a.out[o] = w + k.interp(dz, dy, dx);
-        }
+    for (int t = 0; t < 8; ++t) {
+      const int dz = t >> 2, dy = (t >> 1) & 1, dx = t & 1;
+      if (dz > k.oz || dy > k.oy || dx > k.ox) continue;
+      const int64_t o = ((z + dz) * a.n.n1 + (y + dy)) * a.n.n2 + (x + dx);
+      if (t == 0) {
+        a.out[o] = k.c[0][0][0];
+        continue;
+      }
+      const T wt = a.codes ? T(mul_rn(double(qc[t]), del)) : w[t];
+      a.out[o] = wt + k.interp(dz, dy, dx);
+    }
   }
 }
 
@@ -257,48 +273,114 @@ struct PassArgs {
   float* out_f32;        // optional: the result narrowed to FP32 here instead of out
 };
 
+constexpr int kU = 8;   // requests in flight per lane in the line passes
+
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   extern __shared__ unsigned char smem[];
-  T* tin = reinterpret_cast<T*>(smem);                 // [nl][W+1]
   const int WP = a.W + 1;
   const int nl = int(a.nl), m = int(a.m);
-  T* tout = tin + nl * WP;                             // [m][W+1]
-  T* piv = tout + m * WP;                              // [m] reciprocal pivots
+  T* piv = reinterpret_cast<T*>(smem);                 // [m] reciprocal pivots
+  T* tin = piv + m;                                    // [nl][W+1]
+  // the solution overwrites the first m rows of its own line: a line is
+  // solved by one wavefront, which reads all of its right-hand side first
+  T* tout = tin;                                       // [m][W+1]
   const int64_t L0 = int64_t(blockIdx.x) * a.W;
   const int wv = int(i64min(a.W, a.nlines - L0));   // valid lines in this tile
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t sA = a.is[a.axis], sQ = a.is[a.qa], sP = a.is[a.pa];
   const int cmA = a.cm[a.axis], cmQ = a.cm[a.qa], cmP = a.cm[a.pa];
-  // line w of the tile: (p, q) and whether its p and q are even where they coarsen
+  // line w of the tile: its coordinates (p, q) on the two other axes
   auto line = [&](int w, uint32_t& p, uint32_t& q) {
     const uint32_t l = uint32_t(L0 + w);
     p = a.fq.div(l);
     q = l - p * uint32_t(a.nq);
   };
-  auto load_line = [&](int w, int i0, int di) {
-    uint32_t p, q;
-    line(w, p, q);
-    const int64_t lb = int64_t(p) * sP + int64_t(q) * sQ;
-    // coarse-node test: every coarsening coordinate even
-    const bool pq_even = !(cmP && (p & 1)) && !(cmQ && (q & 1));
-    for (int i = i0; i < nl; i += di) {
-      const int64_t off = lb + i * sA;
-      T v = a.qin ? T(mul_rn(double(a.qin[off]), *a.qdel)) : a.in[off];
-      if (a.mask && pq_even && !(cmA && (i & 1))) v = T(0);
-      tin[i * WP + w] = v;
+  // Loads are issued kU at a time before any of them is written to LDS, so a
+  // lane keeps kU requests in flight instead of waiting on each element.
+  // (codes are dequantized after the batch has arrived)
+  const double qd = a.qin ? *a.qdel : 0.0;
+  auto value = [&](auto r) -> T {
+    if constexpr (std::is_same_v<decltype(r), int32_t>)
+      return T(mul_rn(double(r), qd));
+    else
+      return r;
+  };
+  // coarse-node test of line (p, q) at position i: every coarsening coordinate even
+  auto masked = [&](uint32_t p, uint32_t q, int i) {
+    return a.mask && !(cmP && (p & 1)) && !(cmQ && (q & 1)) && !(cmA && (i & 1));
+  };
+  auto load = [&](const auto* src) {
+    using R = std::remove_const_t<std::remove_pointer_t<decltype(src)>>;
+    if (a.axis == 2) {
+      // a wavefront per line (rows are contiguous): the wave's lines
+      // wave, wave + NW, ... in 64-wide slots, spl slots per line
+      constexpr int NW = NT / 64;
+      const int spl = (nl + 63) >> 6;
+      const int tot = wave < wv ? ((wv - wave + NW - 1) / NW) * spl : 0;
+      int lw = 0, sl = 0;
+      for (int g0 = 0; g0 < tot; g0 += kU) {
+        R v[kU];
+        int dst[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = sl * 64 + lane, w = wave + lw * NW;
+          dst[u] = -1;
+          if (g0 + u < tot && i < nl) {
+            uint32_t p, q;
+            line(w, p, q);
+            dst[u] = masked(p, q, i) ? -2 - (i * WP + w) : i * WP + w;
+            v[u] = src[int64_t(p) * sP + int64_t(q) * sQ + int64_t(i) * sA];
+          }
+          if (++sl == spl) {
+            sl = 0;
+            ++lw;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          if (dst[u] >= 0)
+            tin[dst[u]] = value(v[u]);
+          else if (dst[u] < -1)
+            tin[-2 - dst[u]] = T(0);
+        }
+      }
+    } else {
+      // the W lines of the tile side by side (W a power of two)
+      const int w = tid & (a.W - 1);
+      if (w >= wv) return;
+      uint32_t p, q;
+      line(w, p, q);
+      const R* lp = src + int64_t(p) * sP + int64_t(q) * sQ;
+      const int di = NT >> a.lw;
+      const int64_t step = int64_t(di) * sA;
+      for (int ib = tid >> a.lw; ib < nl; ib += kU * di) {
+        const R* bp = lp + int64_t(ib) * sA;
+        R v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (ib + u * di < nl) v[u] = bp[u * step];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = ib + u * di;
+          if (i < nl) tin[i * WP + w] = masked(p, q, i) ? T(0) : value(v[u]);
+        }
+      }
     }
   };
-  for (int J = tid; J < m; J += NT) piv[J] = T(a.inv[J]);
-  // load: a wavefront per line when lines are rows (x, contiguous); else the
-  // W lines of the tile side by side (W a power of two)
-  if (a.axis == 2) {
-    for (int w = wave; w < wv; w += NT / 64) load_line(w, lane, 64);
-  } else {
-    const int w = tid & (a.W - 1);
-    if (w < wv) load_line(w, tid >> a.lw, NT >> a.lw);
-  }
+  // the pivots (m <= 3 NT) are fetched with the first batch
+  static_assert(64 * kLineQ <= 3 * NT, "pivots: three per thread");
+  double pv[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pv[k] = tid + k * NT < m ? a.inv[tid + k * NT] : 0.0;
+  if (a.qin)
+    load(a.qin);
+  else
+    load(a.in);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (tid + k * NT < m) piv[tid + k * NT] = T(pv[k]);
   __syncthreads();
   // right-hand side 3 (P^T M u)_J: 5-point interior rows, 3-point end rows
   auto rhs = [&](int w, int J) {
@@ -320,25 +402,89 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   __syncthreads();
   const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
   const int64_t oA = os[a.axis], oQ = os[a.qa], oP = os[a.pa];
-  auto store_line = [&](int w, int J0, int dJ) {
-    uint32_t p, q;
-    line(w, p, q);
-    const int64_t ob = int64_t(p) * oP + int64_t(q) * oQ;
-    for (int J = J0; J < m; J += dJ) {
-      const int64_t o = ob + J * oA;
-      const T v = tout[J * WP + w];
-      if (a.out_f32)
-        a.out_f32[o] = float(v);
-      else
-        a.out[o] = a.base ? a.base[o] - v : v;
+  // stores kU at a time as well; one loop per kind of store (narrowed to
+  // FP32, subtracted from base values, plain), so each keeps its loads and
+  // stores in flight
+  auto store = [&](auto kind) {
+    constexpr int K = decltype(kind)::value;
+    auto put = [&](const int64_t (&o)[kU], const T (&v)[kU]) {
+      if constexpr (K == 0) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (o[u] >= 0) a.out_f32[o[u]] = float(v[u]);
+      } else if constexpr (K == 1) {
+        // (every lane loads, from element 0 where it has no value, so that
+        // all loads are issued before the first store)
+        T r[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) r[u] = a.base[o[u] >= 0 ? o[u] : 0];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) r[u] -= v[u];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (o[u] >= 0) a.out[o[u]] = r[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (o[u] >= 0) a.out[o[u]] = v[u];
+      }
+    };
+    if (a.axis == 2) {
+      constexpr int NW = NT / 64;
+      const int spl = (m + 63) >> 6;
+      const int tot = wave < wv ? ((wv - wave + NW - 1) / NW) * spl : 0;
+      int lw = 0, sl = 0;
+      for (int g0 = 0; g0 < tot; g0 += kU) {
+        T v[kU];
+        int64_t o[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int J = sl * 64 + lane, w = wave + lw * NW;
+          o[u] = -1;
+          v[u] = T(0);
+          if (g0 + u < tot && J < m) {
+            uint32_t p, q;
+            line(w, p, q);
+            o[u] = int64_t(p) * oP + int64_t(q) * oQ + int64_t(J) * oA;
+            v[u] = tout[J * WP + w];
+          }
+          if (++sl == spl) {
+            sl = 0;
+            ++lw;
+          }
+        }
+        put(o, v);
+      }
+    } else {
+      const int w = tid & (a.W - 1);
+      if (w >= wv) return;
+      uint32_t p, q;
+      line(w, p, q);
+      const int64_t ob = int64_t(p) * oP + int64_t(q) * oQ;
+      const int dJ = NT >> a.lw;
+      for (int Jb = tid >> a.lw; Jb < m; Jb += kU * dJ) {
+        T v[kU];
+        int64_t o[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int J = Jb + u * dJ;
+          o[u] = -1;
+          v[u] = T(0);
+          if (J < m) {
+            o[u] = ob + int64_t(J) * oA;
+            v[u] = tout[J * WP + w];
+          }
+        }
+        put(o, v);
+      }
     }
   };
-  if (a.axis == 2) {
-    for (int w = wave; w < wv; w += NT / 64) store_line(w, lane, 64);
-  } else {
-    const int w = tid & (a.W - 1);
-    if (w < wv) store_line(w, tid >> a.lw, NT >> a.lw);
-  }
+  if (a.out_f32)
+    store(std::integral_constant<int, 0>{});
+  else if (a.base)
+    store(std::integral_constant<int, 1>{});
+  else
+    store(std::integral_constant<int, 2>{});
 }
 
 template <typename T>
@@ -375,14 +521,17 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.qa = axis == 2 ? 1 : 2;
   a.nq = in.n[a.qa];
   const int64_t np = in.n[a.pa];
-  a.W = tile_width(a.nl + a.m + 1, sizeof(T), np, a.nq);
+  a.W = tile_width(a.nl + 1, sizeof(T), np, a.nq);
+  // rows (x lines) load a wavefront per line, so wider tiles do not coalesce
+  // better there; 16 lines keep more workgroups in flight (measured faster)
+  if (axis == 2 && a.W > 16) a.W = 16;
   a.lw = 0;
   while ((1 << a.lw) < a.W) ++a.lw;
   a.nlines = np * a.nq;
   if (a.nlines >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "too many lines");
   a.fq = FastDiv(uint32_t(a.nq));
   const int64_t tiles = (a.nlines + a.W - 1) / a.W;
-  const size_t shm = (size_t(a.nl + a.m) * (a.W + 1) + size_t(a.m)) * sizeof(T);
+  const size_t shm = (size_t(a.nl) * (a.W + 1) + size_t(a.m)) * sizeof(T);
   switch (row_q_for(a.m)) {
     case 3: hipLaunchKernelGGL((k_line_pass<T, 3>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case 5: hipLaunchKernelGGL((k_line_pass<T, 5>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
@@ -430,19 +579,21 @@ __global__ __launch_bounds__(NT) void k_gather_part(GatherArgs<T> a) {
         k0[d] = kk;
       }
     }
+    // all (up to 8) partials are fetched before the sum; an absent one adds
+    // +0, which leaves the sum unchanged (it starts at +0)
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int iz = t >> 2, iy = (t >> 1) & 1, ix = t & 1;
+      v[t] = 0.0;
+      if ((iz && !two[0]) || (iy && !two[1]) || (ix && !two[2])) continue;
+      const uint64_t blk = (uint64_t(iz ? b1[0] : b0[0]) * a.nb[1] + (iy ? b1[1] : b0[1])) * a.nb[2] +
+                           (ix ? b1[2] : b0[2]);
+      v[t] = a.part[blk * (H * H * H) + ((iz ? k1[0] : k0[0]) * H + (iy ? k1[1] : k0[1])) * H + (ix ? k1[2] : k0[2])];
+    }
     double sum = 0.0;
 #pragma unroll
-    for (int iz = 0; iz < 2; ++iz)
-#pragma unroll
-      for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-        for (int ix = 0; ix < 2; ++ix) {
-          if ((iz && !two[0]) || (iy && !two[1]) || (ix && !two[2])) continue;
-          const uint64_t blk = (uint64_t(iz ? b1[0] : b0[0]) * a.nb[1] + (iy ? b1[1] : b0[1])) * a.nb[2] +
-                               (ix ? b1[2] : b0[2]);
-          sum += a.part[blk * (H * H * H) + ((iz ? k1[0] : k0[0]) * H + (iy ? k1[1] : k0[1])) * H +
-                        (ix ? k1[2] : k0[2])];
-        }
+    for (int t = 0; t < 8; ++t) sum += v[t];
     a.out[i] = T(sum);
   }
 }
