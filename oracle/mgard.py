@@ -30,7 +30,13 @@ Readings where the paper is silent (each is listed in the design notes)
   restricted to interior coarse nodes ("face-fixed").  Face values are then
   functions of face data only, so both neighbours agree and every node of
   the grid stores exactly one coefficient.
-* Each local level re-tiles the current grid with b^3 blocks.
+* Each local level re-tiles the current grid with b^3 blocks.  A second,
+  "nested" schedule is kept as a defined variant (several block levels in
+  one on-chip block, Sec. IV-A): local level s uses blocks of
+  (b-1)/2^(s-1)+1 nodes, which tile the level-s grid over exactly the
+  regions of the level-1 blocks, so every block level of a region works on
+  that region's own coarse values.  Its results differ from re-tiling from
+  the second block level on.
 * Coefficient layout is "in place": one dense array of the padded grid,
   each node holding its own coefficient (detail of the level at which it
   leaves the grid, or the coarsest value).
@@ -318,16 +324,29 @@ def _global_chain_ok(n: int, M: int) -> bool:
     return True
 
 
-def padded_length(n: int, b: int, L: int, M: int) -> int:
+def level_block(b: int, s: int, nested: bool) -> int:
+    """Block size (nodes per side) of local level s: b when every level
+    re-tiles its grid, (b-1)/2^(s-1)+1 in the nested schedule."""
+    if not nested:
+        return b
+    w = (b - 1) >> (s - 1)
+    if w < 2 or w << (s - 1) != b - 1:
+        raise ValueError(f"nested schedule: level {s} of {b}-node blocks has no interior coarse row")
+    return w + 1
+
+
+def padded_length(n: int, b: int, L: int, M: int, nested: bool = False) -> int:
     """Smallest n' >= n on which the L block levels tile and the M global levels halve."""
     if n < 1:
         raise ValueError("empty axis")
-    q = (b - 1) * (1 << (L - 1)) if L > 0 else 1
+    if nested and L > 0:
+        level_block(b, L, True)   # validates the schedule
+    q = ((b - 1) if nested else (b - 1) * (1 << (L - 1))) if L > 0 else 1
     cand = max(n, (b if L > 0 else 1))
     while True:
         if (cand - 1) % q == 0:
             nl = (cand - 1) // (1 << L) + 1 if L > 0 else cand
-            if L == 0 or all(((cand - 1) >> (s - 1)) >= b - 1 for s in range(1, L + 1)):
+            if L == 0 or all(((cand - 1) >> (s - 1)) >= level_block(b, s, nested) - 1 for s in range(1, L + 1)):
                 if _global_chain_ok(nl, M):
                     return cand
         cand += 1
@@ -353,38 +372,43 @@ class Hierarchy:
     L: int
     M: int
     pos: List[List[np.ndarray]]          # pos[s][axis]: indices of grid G^s in the padded grid
+    nested: bool = False                 # nested block schedule (see level_block)
 
     @property
     def levels(self) -> int:
         return self.L + self.M
 
+    def block(self, s: int) -> int:
+        """Block size of local level s (1-based)."""
+        return level_block(self.b, s, self.nested)
 
-def hierarchy(shape: Sequence[int], b: int, L: int, M: int) -> Hierarchy:
+
+def hierarchy(shape: Sequence[int], b: int, L: int, M: int, nested: bool = False) -> Hierarchy:
     shape = tuple(int(n) for n in shape)
     if len(shape) != 3:
         raise ValueError("3D grids only")
     if L > 0 and (b < 3 or (b - 1) & (b - 2) != 0):
         raise ValueError("block size must be 2^k+1")
-    shape_p = tuple(padded_length(n, b, L, M) for n in shape)
+    shape_p = tuple(padded_length(n, b, L, M, nested) for n in shape)
     pos = [[np.arange(n) for n in shape_p]]
     for _ in range(L + M):
         prev = pos[-1]
         pos.append([p[coarse_indices(len(p))] for p in prev])
-    return Hierarchy(shape, shape_p, b, L, M, pos)
+    return Hierarchy(shape, shape_p, b, L, M, pos, nested)
 
 
-def decompose(x: np.ndarray, b: int, L: int, M: int, pad_mode: str = "clamp") -> np.ndarray:
+def decompose(x: np.ndarray, b: int, L: int, M: int, pad_mode: str = "clamp", nested: bool = False) -> np.ndarray:
     """Full hybrid decomposition: L block levels then M global levels (Sec. IV-B).
 
     Returns the in-place coefficient array on the padded grid.
     """
-    h = hierarchy(x.shape, b, L, M)
+    h = hierarchy(x.shape, b, L, M, nested)
     cur = pad(np.asarray(x, np.float64), h.shape_p, pad_mode)
     coeff = np.zeros(h.shape_p)
     for s in range(1, h.levels + 1):
         coords = [p.astype(np.float64) for p in h.pos[s - 1]]
         if s <= L:
-            out = local_decompose(cur, coords, b)
+            out = local_decompose(cur, coords, h.block(s))
         else:
             out = level_decompose(cur, coords, False)
         coeff[np.ix_(*h.pos[s - 1])] = out
@@ -392,9 +416,9 @@ def decompose(x: np.ndarray, b: int, L: int, M: int, pad_mode: str = "clamp") ->
     return coeff
 
 
-def recompose(coeff: np.ndarray, shape: Sequence[int], b: int, L: int, M: int) -> np.ndarray:
+def recompose(coeff: np.ndarray, shape: Sequence[int], b: int, L: int, M: int, nested: bool = False) -> np.ndarray:
     """Inverse of :func:`decompose`, cropped back to the logical ``shape``."""
-    h = hierarchy(shape, b, L, M)
+    h = hierarchy(shape, b, L, M, nested)
     if tuple(coeff.shape) != h.shape_p:
         raise ValueError("coefficient array has the wrong shape")
     cur = coeff[np.ix_(*h.pos[h.levels])].astype(np.float64)
@@ -403,7 +427,7 @@ def recompose(coeff: np.ndarray, shape: Sequence[int], b: int, L: int, M: int) -
         out = coeff[np.ix_(*h.pos[s - 1])].astype(np.float64)
         out[np.ix_(*(coarse_indices(len(p)) for p in h.pos[s - 1]))] = cur
         if s <= L:
-            cur = local_recompose(out, coords, b)
+            cur = local_recompose(out, coords, h.block(s))
         else:
             cur = level_recompose(out, coords, False)
     n = h.shape
@@ -501,13 +525,13 @@ def _local_T(g: np.ndarray, coords3, b: int, level_T) -> np.ndarray:
 
 
 def decompose_adjoint(gcoeff: np.ndarray, shape: Sequence[int], b: int, L: int, M: int,
-                      pad_mode: str = "clamp") -> np.ndarray:
+                      pad_mode: str = "clamp", nested: bool = False) -> np.ndarray:
     """D^T: gradient with respect to x of <decompose(x), gcoeff>.
 
     Levels run in reverse order; the transpose of clamp padding adds every
     padded node's gradient into the node it copied.
     """
-    h = hierarchy(shape, b, L, M)
+    h = hierarchy(shape, b, L, M, nested)
     gcoeff = np.asarray(gcoeff, np.float64)
     # gradient with respect to the coarsest grid
     gcur = gcoeff[np.ix_(*h.pos[h.levels])]
@@ -516,7 +540,7 @@ def decompose_adjoint(gcoeff: np.ndarray, shape: Sequence[int], b: int, L: int, 
         gout = gcoeff[np.ix_(*h.pos[s - 1])].copy()
         gout[np.ix_(*(coarse_indices(len(p)) for p in h.pos[s - 1]))] = gcur
         if s <= L:
-            gcur = _local_T(gout, coords, b, _level_decompose_T)
+            gcur = _local_T(gout, coords, h.block(s), _level_decompose_T)
         else:
             gcur = _level_decompose_T(gout, coords, False)
     # transpose of padding
@@ -529,9 +553,10 @@ def decompose_adjoint(gcoeff: np.ndarray, shape: Sequence[int], b: int, L: int, 
     return gx
 
 
-def recompose_adjoint(gx: np.ndarray, shape: Sequence[int], b: int, L: int, M: int) -> np.ndarray:
+def recompose_adjoint(gx: np.ndarray, shape: Sequence[int], b: int, L: int, M: int,
+                      nested: bool = False) -> np.ndarray:
     """R^T: gradient with respect to the coefficients of <recompose(c), gx>."""
-    h = hierarchy(shape, b, L, M)
+    h = hierarchy(shape, b, L, M, nested)
     gcur = np.zeros(h.shape_p)
     n = h.shape
     gcur[: n[0], : n[1], : n[2]] = gx
@@ -539,7 +564,7 @@ def recompose_adjoint(gx: np.ndarray, shape: Sequence[int], b: int, L: int, M: i
     for s in range(1, h.levels + 1):
         coords = [p.astype(np.float64) for p in h.pos[s - 1]]
         if s <= L:
-            gout = _local_T(gcur, coords, b, _level_recompose_T)
+            gout = _local_T(gcur, coords, h.block(s), _level_recompose_T)
         else:
             gout = _level_recompose_T(gcur, coords, False)
         gcoeff[np.ix_(*h.pos[s - 1])] = gout

@@ -69,14 +69,23 @@ def block_tolerance(voxel_tol: np.ndarray, shape_p: Sequence[int], b: int) -> np
     return out
 
 
-def propagate(tol: np.ndarray) -> np.ndarray:
+def propagate(tol: np.ndarray, nested: bool = False) -> np.ndarray:
     """Eq. 2: block (I,J,K) of the next level takes the min over the blocks of
     this level that share a node with it.
 
     A next-level block spans two current blocks per axis (2I, 2I+1); the
     blocks 2I-1 and 2I+2 touch it in one face of nodes and contribute too.
+    In the nested schedule the next-level block covers the same region as
+    block I of this level, so blocks I-1, I, I+1 per axis share its nodes.
     """
     nb = tol.shape
+    if nested:
+        out = np.empty(nb)
+        for I in range(nb[0]):
+            for J in range(nb[1]):
+                for K in range(nb[2]):
+                    out[I, J, K] = tol[max(0, I - 1): I + 2, max(0, J - 1): J + 2, max(0, K - 1): K + 2].min()
+        return out
     nn = [max(1, n // 2) for n in nb]
     out = np.empty(nn)
     for I in range(nn[0]):
@@ -89,11 +98,11 @@ def propagate(tol: np.ndarray) -> np.ndarray:
     return out
 
 
-def level_block_tolerances(tol1: np.ndarray, L: int) -> List[np.ndarray]:
+def level_block_tolerances(tol1: np.ndarray, L: int, nested: bool = False) -> List[np.ndarray]:
     """[tau^1, ..., tau^L]: level-1 map and its recursive propagation."""
     tols = [np.asarray(tol1, np.float64)]
     for _ in range(1, L):
-        tols.append(propagate(tols[-1]))
+        tols.append(propagate(tols[-1], nested))
     return tols
 
 
@@ -182,7 +191,7 @@ def level_gains(h: mgard.Hierarchy) -> List[float]:
     out = []
     for s in range(1, h.levels + 1):
         if s <= h.L:
-            c = [np.arange(h.b, dtype=float)] * 3
+            c = [np.arange(h.block(s), dtype=float)] * 3
             out.append(round_up4(amplification(c, True)))
         else:
             c = [np.arange(len(p), dtype=float) for p in h.pos[s - 1]]
@@ -232,7 +241,7 @@ def node_delta(h: mgard.Hierarchy, tol1, eta: float) -> np.ndarray:
     lev = mgard.node_level(h.shape_p, L, M)
     delta = np.zeros(h.shape_p)
     if L >= 1:
-        tols = level_block_tolerances(np.asarray(tol1, float), L)
+        tols = level_block_tolerances(np.asarray(tol1, float), L, h.nested)
         tau_global = float(tols[-1].min())
     else:
         tols = []
@@ -244,9 +253,9 @@ def node_delta(h: mgard.Hierarchy, tol1, eta: float) -> np.ndarray:
         if not mask.any():
             continue
         if s <= L:
-            tau = node_tolerance(tols[s - 1], [len(p) for p in h.pos[s - 1]], h.b)
+            tau = node_tolerance(tols[s - 1], [len(p) for p in h.pos[s - 1]], h.block(s))
         elif s == L + M + 1 and M == 0 and L >= 1:
-            tau = node_tolerance(tols[L - 1], [len(p) for p in h.pos[L - 1]], h.b)
+            tau = node_tolerance(tols[L - 1], [len(p) for p in h.pos[L - 1]], h.block(L))
             # coarsest nodes are the coarse nodes of the level-L grid
             tau = tau[np.ix_(*(mgard.coarse_indices(len(p)) for p in h.pos[L - 1]))]
         else:
