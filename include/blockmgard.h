@@ -74,7 +74,15 @@ typedef enum { BM_F32 = 0, BM_F64 = 1 } bm_dtype;
  *   L, M     number of local (In-cache Block) and global levels (Sec. IV-B)
  *   pad_mode 0 = clamp (padded nodes copy the nearest node), 1 = zero fill
  *   eta      safety share of every tolerance kept back for working-precision
- *            rounding, in [0, 0.5); the quantizer uses tau * (1 - eta). */
+ *            rounding, in [0, 0.5); the quantizer uses tau * (1 - eta).
+ *   nested   0: every block level re-tiles its grid with b-node blocks.
+ *            1: the nested schedule (several block levels inside one block
+ *            region, Sec. IV-A): block level s uses (b-1)/2^(s-1)+1-node
+ *            blocks, which cover exactly the level-1 block regions; each
+ *            level's block must have at least 9 nodes (b = 17: L <= 2;
+ *            b = 33: L <= 3), else BM_EINVAL.  Results differ from 0 from
+ *            the second block level on.  Batches do not take it
+ *            (BM_EUNSUPPORTED).  Zero-initialised configs get 0. */
 typedef struct {
   int ndim;
   int64_t dims[3];
@@ -84,6 +92,7 @@ typedef struct {
   int M;
   int pad_mode;
   double eta;
+  int nested;
 } bm_config;
 
 typedef struct bm_plan_s* bm_plan;

@@ -18,7 +18,7 @@ BM_ERANGE = -7
 
 class BMConfig(C.Structure):
     _fields_ = [("ndim", C.c_int), ("dims", C.c_int64 * 3), ("dtype", C.c_int), ("block", C.c_int),
-                ("L", C.c_int), ("M", C.c_int), ("pad_mode", C.c_int), ("eta", C.c_double)]
+                ("L", C.c_int), ("M", C.c_int), ("pad_mode", C.c_int), ("eta", C.c_double), ("nested", C.c_int)]
 
 
 class BMQStats(C.Structure):

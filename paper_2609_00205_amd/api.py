@@ -49,10 +49,14 @@ def _need(t: torch.Tensor, dtype, shape, name):
 
 
 class Plan:
-    """A decomposition plan: dims, dtype, block size b, L local + M global levels."""
+    """A decomposition plan: dims, dtype, block size b, L local + M global levels.
+
+    nested=True selects the nested block schedule: block level s uses
+    (b-1)/2^(s-1)+1-node blocks over the level-1 block regions (each at
+    least 9 nodes per side)."""
 
     def __init__(self, shape: Sequence[int], dtype=torch.float32, block: int = 17, L: int = 1, M: int = 2,
-                 pad_mode: str = "clamp", eta: Optional[float] = None, device=None):
+                 pad_mode: str = "clamp", eta: Optional[float] = None, device=None, nested: bool = False):
         shape = tuple(int(s) for s in shape)
         if len(shape) != 3:
             raise ValueError("3D shapes only")
@@ -61,7 +65,9 @@ class Plan:
         self.block, self.L, self.M = block, L, M
         self.eta = DEFAULT_ETA[dtype] if eta is None else float(eta)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        cfg = BMConfig(3, (C.c_int64 * 3)(*shape), _DT[dtype], block, L, M, 1 if pad_mode == "zero" else 0, self.eta)
+        cfg = BMConfig(3, (C.c_int64 * 3)(*shape), _DT[dtype], block, L, M, 1 if pad_mode == "zero" else 0, self.eta,
+                       int(bool(nested)))
+        self.nested = bool(nested)
         self._cfg = cfg
         h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -77,6 +83,7 @@ class Plan:
         self.shape = tuple(int(v) for v in cfg.dims)
         self.dtype = _TD[cfg.dtype]
         self.block, self.L, self.M = cfg.block, cfg.L, cfg.M
+        self.nested = bool(cfg.nested)
         self.eta = cfg.eta
         self.device = device
         self._cfg = cfg
@@ -276,7 +283,7 @@ def compressed_config(buf: bytes) -> dict:
     cfg = BMConfig()
     call("bm_compressed_config", buf, len(buf), C.byref(cfg))
     return {"shape": tuple(cfg.dims), "dtype": _TD[cfg.dtype], "block": cfg.block, "L": cfg.L, "M": cfg.M,
-            "pad_mode": cfg.pad_mode, "eta": cfg.eta}
+            "pad_mode": cfg.pad_mode, "eta": cfg.eta, "nested": bool(cfg.nested)}
 
 
 def decompress(buf: bytes, device=None, stream=None) -> torch.Tensor:

@@ -705,9 +705,9 @@ void launch_w33_rec_T(const bm_plan_s& p, int s, const void* gin, const int64_t 
 
 template <typename T>
 void local_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out, hipStream_t st) {
-  if (p.cfg.block == 33)
+  if (p.lv[s - 1].b == 33)
     launch_w33_dec_T<T>(p, s, gcoeff, out, st);
-  else if (p.cfg.block == 9)
+  else if (p.lv[s - 1].b == 9)
     launch_local_dec_T<T, 9>(p, s, gcoeff, out, st);
   else
     launch_local_dec_T<T, 17>(p, s, gcoeff, out, st);
@@ -716,9 +716,9 @@ void local_dec_T(const bm_plan_s& p, int s, const void* gcoeff, void* out, hipSt
 template <typename T>
 void local_rec_T(const bm_plan_s& p, int s, const void* gin, const int64_t in[3], const int64_t lim[3], void* gcoeff,
                  hipStream_t st) {
-  if (p.cfg.block == 33)
+  if (p.lv[s - 1].b == 33)
     launch_w33_rec_T<T>(p, s, gin, in, lim, gcoeff, st);
-  else if (p.cfg.block == 9)
+  else if (p.lv[s - 1].b == 9)
     launch_local_rec_T<T, 9>(p, s, gin, in, lim, gcoeff, st);
   else
     launch_local_rec_T<T, 17>(p, s, gin, in, lim, gcoeff, st);

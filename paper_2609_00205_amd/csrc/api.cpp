@@ -143,7 +143,7 @@ struct CHeader {
   uint32_t magic;       // "BMGD"
   uint32_t version;
   uint32_t flags;       // bit 0: raw copy
-  int32_t dtype, block, L, M, pad_mode, ndim, pad0;
+  int32_t dtype, block, L, M, pad_mode, ndim, nested;
   int64_t dims[3];
   double eta;
   int64_t ntol;         // block tolerance entries
@@ -165,6 +165,7 @@ bm_config header_config(const CHeader& h) {
   c.M = h.M;
   c.pad_mode = h.pad_mode;
   c.eta = h.eta;
+  c.nested = h.nested;
   return c;
 }
 
@@ -224,6 +225,7 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
   h.L = p.L;
   h.M = p.M;
   h.pad_mode = p.cfg.pad_mode;
+  h.nested = p.cfg.nested;
   h.ndim = 3;
   for (int a = 0; a < 3; ++a) h.dims[a] = p.dims[a];
   h.eta = p.cfg.eta;

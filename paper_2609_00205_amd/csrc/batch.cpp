@@ -207,6 +207,8 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
     for (int f = 0; f < nfields; ++f) {
       if (f > 0 && (cfgs[f].dtype != cfgs[0].dtype || cfgs[f].block != cfgs[0].block))
         fail(BM_EINVAL, "all fields of a batch share dtype and block size");
+      if (cfgs[f].nested)
+        fail(BM_EUNSUPPORTED, "batches take the plain block schedule (nested = 0)");
       if (cfgs[f].L > 0 && cfgs[f].block == 33)
         fail(BM_EUNSUPPORTED, "batched block levels take b = 9 or 17 (a 33^3 block needs several launches)");
       b->plans.push_back(bm_plan_build(&cfgs[f]));

@@ -761,7 +761,7 @@ static void global_from_parts(bm_plan_s& p, int s, hipStream_t st) {
   double* t2 = static_cast<double*>(p.ws.t2);
   GatherArgs<double> a{static_cast<const double*>(p.ws.part),
                        {uint32_t(B.nb[0]), uint32_t(B.nb[1]), uint32_t(B.nb[2])}, {m[0], m[1], m[2]}, t1};
-  if (p.cfg.block == 9)
+  if (B.b == 9)
     hipLaunchKernelGGL((k_gather_part<double, 3>), dim3(grid_for(tot)), dim3(NT), 0, st, a);
   else
     hipLaunchKernelGGL((k_gather_part<double, 5>), dim3(grid_for(tot)), dim3(NT), 0, st, a);

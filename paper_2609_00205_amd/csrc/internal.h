@@ -98,6 +98,7 @@ struct Level {
   int64_t n[3];        // dims of G^{s-1}
   int64_t m[3];        // dims of G^s
   int64_t nb[3];       // blocks per axis (local levels)
+  int b;               // nodes per block side (local levels)
   int64_t ps[3];       // spacing of G^{s-1} nodes in the padded grid, per axis
   bool coarsen[3];     // axis is halved at this level (false: length <= 2 stays)
   double gain;         // rounded-up L-inf gain of this level's details
@@ -159,7 +160,7 @@ struct bm_plan_s {
 
 namespace bm {
 
-int64_t padded_length(int64_t n, int b, int L, int M);
+int64_t padded_length(int64_t n, int b, int L, int M, bool nested = false);
 double level_gain_local(int b);
 double level_gain_global(const int64_t n[3]);
 void thomas_pivots_natural(int64_t m, std::vector<double>& inv);
@@ -238,6 +239,7 @@ struct PrepField {
   double* q;                  // scalar Delta, 1/Delta per level and for the coarsest values
   double kq[26];              // kappa per level and for the coarsest values
   int L, M, nlev;
+  int nested;                 // nested block schedule (propagation within the 3x3x3 block neighbourhood)
   int64_t* flag;              // overflow flag, cleared here
 };
 PrepField prep_field(bm_plan_s& p, const double* block_tol, const QPrep& q);

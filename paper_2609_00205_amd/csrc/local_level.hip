@@ -692,9 +692,9 @@ void dispatch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin,
 
 void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* coarse_out,
                      hipStream_t st) {
-  if (p.cfg.block == 33)
+  if (p.lv[s - 1].b == 33)
     wide_decompose(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
-  else if (p.cfg.block == 9)
+  else if (p.lv[s - 1].b == 9)
     dispatch_dec<9>(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
   else
     dispatch_dec<17>(p, s, src, first, coeff, coarse_out, nullptr, nullptr, st);
@@ -702,9 +702,9 @@ void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, vo
 
 void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* coarse_in, void* out, bool last,
                      hipStream_t st) {
-  if (p.cfg.block == 33)
+  if (p.lv[s - 1].b == 33)
     wide_recompose(p, s, coeff, const_cast<void*>(coarse_in), out, last, nullptr, nullptr, st);
-  else if (p.cfg.block == 9)
+  else if (p.lv[s - 1].b == 9)
     dispatch_rec<9>(p, s, coeff, coarse_in, out, last, nullptr, nullptr, st);
   else
     dispatch_rec<17>(p, s, coeff, coarse_in, out, last, nullptr, nullptr, st);
@@ -712,9 +712,9 @@ void local_recompose(const bm_plan_s& p, int s, const void* coeff, const void* c
 
 void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, int32_t* codes, void* coarse_out,
                        const QPrep& q, hipStream_t st) {
-  if (p.cfg.block == 33)
+  if (p.lv[s - 1].b == 33)
     wide_decompose(p, s, src, first, nullptr, coarse_out, codes, &q, st);
-  else if (p.cfg.block == 9)
+  else if (p.lv[s - 1].b == 9)
     dispatch_dec<9>(p, s, src, first, nullptr, coarse_out, codes, &q, st);
   else
     dispatch_dec<17>(p, s, src, first, nullptr, coarse_out, codes, &q, st);
@@ -722,16 +722,16 @@ void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, 
 
 void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const void* coarse_in, void* out, bool last,
                        const QPrep& q, hipStream_t st) {
-  if (p.cfg.block == 33)
+  if (p.lv[s - 1].b == 33)
     wide_recompose(p, s, nullptr, const_cast<void*>(coarse_in), out, last, codes, &q, st);
-  else if (p.cfg.block == 9)
+  else if (p.lv[s - 1].b == 9)
     dispatch_rec<9>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
   else
     dispatch_rec<17>(p, s, nullptr, coarse_in, out, last, codes, &q, st);
 }
 
 int64_t block_groups(const bm_plan_s& p, int s, bool dec) {
-  const int nbw = p.cfg.block <= 9 ? Geo<9>::NB
+  const int nbw = p.lv[s - 1].b <= 9 ? Geo<9>::NB
                                    : (p.esize == 4 ? (dec ? Geo<17, 4, true>::NB : Geo<17, 4, false>::NB) : Geo<17, 8>::NB);
   const int64_t* nb = p.lv[s - 1].nb;
   return (nb[0] * nb[1] * nb[2] + nbw - 1) / nbw;
@@ -745,11 +745,11 @@ size_t block_args_size(const bm_plan_s& p, bool dec) {
 void block_dec_args(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* cout, int32_t* codes,
                     const QPrep* q, void* out) {
   if (p.cfg.dtype == BM_F32) {
-    const auto a = p.cfg.block == 9 ? dec_args<float, 9>(p, s, src, first, coeff, cout, codes, q)
+    const auto a = p.lv[s - 1].b == 9 ? dec_args<float, 9>(p, s, src, first, coeff, cout, codes, q)
                                     : dec_args<float, 17>(p, s, src, first, coeff, cout, codes, q);
     std::memcpy(out, &a, sizeof(a));
   } else {
-    const auto a = p.cfg.block == 9 ? dec_args<double, 9>(p, s, src, first, coeff, cout, codes, q)
+    const auto a = p.lv[s - 1].b == 9 ? dec_args<double, 9>(p, s, src, first, coeff, cout, codes, q)
                                     : dec_args<double, 17>(p, s, src, first, coeff, cout, codes, q);
     std::memcpy(out, &a, sizeof(a));
   }
@@ -758,11 +758,11 @@ void block_dec_args(const bm_plan_s& p, int s, const View3& src, bool first, voi
 void block_rec_args(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* outp, bool last,
                     const int32_t* codes, const QPrep* q, void* out) {
   if (p.cfg.dtype == BM_F32) {
-    const auto a = p.cfg.block == 9 ? rec_args<float, 9>(p, s, coeff, cin, outp, last, codes, q)
+    const auto a = p.lv[s - 1].b == 9 ? rec_args<float, 9>(p, s, coeff, cin, outp, last, codes, q)
                                     : rec_args<float, 17>(p, s, coeff, cin, outp, last, codes, q);
     std::memcpy(out, &a, sizeof(a));
   } else {
-    const auto a = p.cfg.block == 9 ? rec_args<double, 9>(p, s, coeff, cin, outp, last, codes, q)
+    const auto a = p.lv[s - 1].b == 9 ? rec_args<double, 9>(p, s, coeff, cin, outp, last, codes, q)
                                     : rec_args<double, 17>(p, s, coeff, cin, outp, last, codes, q);
     std::memcpy(out, &a, sizeof(a));
   }

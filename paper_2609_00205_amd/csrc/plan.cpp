@@ -25,7 +25,9 @@ void check_hip(hipError_t e, const char* what) {
 // Smallest n' >= n on which L levels of b-node shared-face blocks tile
 // exactly ((n'-1) divisible by (b-1) 2^(L-1), at least b nodes at every
 // local level) and each of the M global levels halves an odd length (a
-// length <= 2 is left as it is).
+// length <= 2 is left as it is).  Nested schedule: level s has
+// (b-1)/2^(s-1)+1-node blocks over the level-1 block regions, so the
+// first level's tiling ((n'-1) divisible by b-1) is all that is needed.
 static bool global_chain_ok(int64_t n, int M) {
   for (int j = 0; j < M; ++j) {
     if (n <= 2) continue;
@@ -35,15 +37,15 @@ static bool global_chain_ok(int64_t n, int M) {
   return true;
 }
 
-int64_t padded_length(int64_t n, int b, int L, int M) {
+int64_t padded_length(int64_t n, int b, int L, int M, bool nested) {
   if (n < 1) fail(BM_EINVAL, "empty axis");
-  const int64_t q = L > 0 ? int64_t(b - 1) << (L - 1) : 1;
+  const int64_t q = L > 0 ? (nested ? int64_t(b - 1) : int64_t(b - 1) << (L - 1)) : 1;
   int64_t c = std::max<int64_t>(n, L > 0 ? b : 1);
   // first candidate of the form k*q + 1
   c = ((c - 1 + q - 1) / q) * q + 1;
   for (int iter = 0; iter < (1 << 22); ++iter, c += q) {
     bool ok = true;
-    for (int s = 1; s <= L && ok; ++s) ok = ((c - 1) >> (s - 1)) >= b - 1;
+    for (int s = 1; s <= L && ok; ++s) ok = ((c - 1) >> (s - 1)) >= (nested ? (b - 1) >> (s - 1) : b - 1);
     const int64_t nl = L > 0 ? ((c - 1) >> L) + 1 : c;
     if (ok && global_chain_ok(nl, M)) return c;
   }
@@ -269,6 +271,10 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
   if (c->L > 0 && c->block != 9 && c->block != 17 && c->block != 33) fail(BM_EINVAL, "block must be 9, 17 or 33");
   if (c->pad_mode != 0 && c->pad_mode != 1) fail(BM_EINVAL, "pad_mode must be 0 (clamp) or 1 (zero)");
   if (!(c->eta >= 0.0 && c->eta < 0.5)) fail(BM_EINVAL, "eta must lie in [0, 0.5)");
+  if (c->nested != 0 && c->nested != 1) fail(BM_EINVAL, "nested must be 0 or 1");
+  // nested schedule: every block level keeps at least 9 nodes per side
+  if (c->nested && c->L > 0 && ((c->block - 1) >> (c->L - 1)) < 8)
+    fail(BM_EINVAL, "nested schedule: block level L would have fewer than 9 nodes per side");
   // ndim < 3: dims[0..ndim-1] become the trailing axes
   int64_t d[3] = {1, 1, 1};
   for (int a = 0; a < c->ndim; ++a) d[3 - c->ndim + a] = c->dims[a];
@@ -286,7 +292,8 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
   p->nlev = c->L + c->M;
   const int b = c->L > 0 ? c->block : 0;
   try {
-    for (int a = 0; a < 3; ++a) p->pdims[a] = padded_length(d[a], b, c->L, c->M);
+    const bool nested = c->nested != 0;
+    for (int a = 0; a < 3; ++a) p->pdims[a] = padded_length(d[a], b, c->L, c->M, nested);
     int64_t n[3] = {p->pdims[0], p->pdims[1], p->pdims[2]};
     int64_t ps[3] = {1, 1, 1};
     for (int s = 1; s <= p->nlev; ++s) {
@@ -299,11 +306,14 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
         L.coarsen[a] = n[a] > 2;
         L.m[a] = n[a] > 2 ? (n[a] + 1) / 2 : n[a];
         any |= L.coarsen[a];
-        if (L.local) L.nb[a] = (n[a] - 1) / (b - 1);
+        if (L.local) {
+          L.b = nested ? ((b - 1) >> (s - 1)) + 1 : b;
+          L.nb[a] = (n[a] - 1) / (L.b - 1);
+        }
       }
       if (!any) fail(BM_EINVAL, "level " + std::to_string(s) + " has no axis left to coarsen; lower M");
       if (L.local) {
-        L.gain = level_gain_local(b);
+        L.gain = level_gain_local(L.b);
       } else {
         L.gain = level_gain_global(L.n);
         for (int a = 0; a < 3; ++a) {
@@ -322,10 +332,11 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
       }
     }
     for (int a = 0; a < 3; ++a) p->nb1[a] = c->L > 0 ? p->lv[0].nb[a] : 1;
-    p->fuse_next = c->L > 0 && c->M > 0 && b != 33;
+    const int bL = c->L > 0 ? p->lv[c->L - 1].b : 0;   // block size of the last block level
+    p->fuse_next = c->L > 0 && c->M > 0 && bL != 33;
     if (p->fuse_next) {
       // per-block partial load vectors of the first global level (FP64): H^3 per block, H = (b+3)/4
-      const int64_t h = (b + 3) / 4;
+      const int64_t h = (bL + 3) / 4;
       BM_HIP(hipMalloc(&p->ws.part, size_t(prod3(p->lv[c->L - 1].nb)) * h * h * h * sizeof(double)));
     }
     // workspace
@@ -336,7 +347,7 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     size_t t = 0;
     for (auto& L : p->lv) {
       if (L.local) {
-        if (b == 33) t = std::max(t, wide_scratch_elems(L.nb));   // y-pass result of the 33^3 blocks
+        if (L.b == 33) t = std::max(t, wide_scratch_elems(L.nb));   // y-pass result of the 33^3 blocks
         continue;
       }
       t = std::max<size_t>(t, size_t(L.n[0]) * L.n[1] * L.m[2]);

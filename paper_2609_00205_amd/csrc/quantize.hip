@@ -145,7 +145,8 @@ struct QArgs {
   Unflat32 uf;                // flat index -> (z, y, x) of the padded grid
   int L, M;
   int D[3];                   // levels each axis coarsens
-  int lw;                     // log2(b - 1)
+  int lw;                     // log2(b - 1), b of the first block level
+  int nested;                 // nested block schedule: every level's blocks span b - 1 padded cells
   // per-block Delta and 1/Delta: slot s-1 for the details of local level s;
   // slot kCoarseSlot for the coarsest values when M == 0 (level-L blocks)
   const double* bdelta[9];
@@ -175,10 +176,12 @@ constexpr int kCoarseSlot = 8;
 // Delta and 1/Delta of a node whose tolerance comes from the blocks of local
 // level s (grid coordinates q = g >> (s-1)), from table slot `slot`.  Block i
 // spans nodes [i w, (i+1) w]: a node on a shared face lies in two blocks per
-// axis.
+// axis.  In the nested schedule the blocks of every level span the same
+// padded-grid regions, so the padded coordinates g index them directly.
 __device__ inline void block_delta(const QArgs& a, int s, int slot, uint32_t g0, uint32_t g1, uint32_t g2,
                                    double& del, double& inv) {
-  const uint32_t q[3] = {g0 >> (s - 1), g1 >> (s - 1), g2 >> (s - 1)};
+  const int sh = a.nested ? 0 : s - 1;
+  const uint32_t q[3] = {g0 >> sh, g1 >> sh, g2 >> sh};
   const uint32_t wm = (1u << a.lw) - 1;
   uint32_t lo[3], hi[3];
 #pragma unroll
@@ -495,10 +498,14 @@ __global__ void k_batch_propagate(const PrepField* F, const int64_t* first, int 
     const int64_t* nb = P.nb[s - 1];
     const int64_t* nn = P.nb[s];
     const int64_t X = i % nn[2], t = i / nn[2], Y = t % nn[1], Z = t / nn[1];
+    // next-level block (Z, Y, X) spans blocks 2Z, 2Z+1 of this level and
+    // touches 2Z-1, 2Z+2; nested, it is block Z itself, touching Z-1, Z+1
+    const int64_t c0 = P.nested ? Z : 2 * Z, c1 = P.nested ? Y : 2 * Y, c2 = P.nested ? X : 2 * X;
+    const int64_t e = P.nested ? 1 : 2;
     double v = INFINITY;
-    for (int64_t z = i64max(0, 2 * Z - 1); z <= i64min(nb[0] - 1, 2 * Z + 2); ++z)
-      for (int64_t y = i64max(0, 2 * Y - 1); y <= i64min(nb[1] - 1, 2 * Y + 2); ++y)
-        for (int64_t x = i64max(0, 2 * X - 1); x <= i64min(nb[2] - 1, 2 * X + 2); ++x)
+    for (int64_t z = i64max(0, c0 - 1); z <= i64min(nb[0] - 1, c0 + e); ++z)
+      for (int64_t y = i64max(0, c1 - 1); y <= i64min(nb[1] - 1, c1 + e); ++y)
+        for (int64_t x = i64max(0, c2 - 1); x <= i64min(nb[2] - 1, c2 + e); ++x)
           v = fmin(v, P.tau[s - 1][(z * nb[1] + y) * nb[2] + x]);
     const_cast<double*>(P.tau[s])[i] = v;
   }
@@ -600,6 +607,7 @@ PrepField prep_field(bm_plan_s& p, const double* block_tol, const QPrep& q) {
   f.L = p.L;
   f.M = p.M;
   f.nlev = p.nlev;
+  f.nested = p.cfg.nested;
   if (p.nlev + 1 > 26) fail(BM_EUNSUPPORTED, "too many levels");
   for (int s = 1; s <= p.L; ++s) {
     f.tau[s - 1] = s == 1 ? block_tol : p.ws.tolbuf + p.ws.tol_off[s];
@@ -650,6 +658,7 @@ QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool tables
   a.lw = 0;
   if (p.L > 0)
     while ((1 << a.lw) < p.cfg.block - 1) ++a.lw;
+  a.nested = p.cfg.nested;
   a.counters = p.ws.counters;
   for (int k = 0; k < 9; ++k) {
     a.bdelta[k] = qp.lv[k].del;

@@ -50,7 +50,9 @@ def test_bad_config_rejected_before_touching_a_device(lib):
                 BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 7, 17, 1, 2, 0, 0.1),      # bad dtype
                 BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 12, 1, 2, 0, 0.1),      # block not 2^k+1
                 BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 0, 0, 0, 0.1),      # no levels
-                BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 1, 2, 0, 0.7)]:     # eta out of range
+                BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 1, 2, 0, 0.7),      # eta out of range
+                BMConfig(3, (C.c_int64 * 3)(40, 40, 40), 0, 17, 3, 1, 0, 0.1, 1),  # nested: level 3 of 5 nodes
+                BMConfig(3, (C.c_int64 * 3)(40, 40, 40), 0, 17, 1, 1, 0, 0.1, 2)]:  # nested must be 0 or 1
         assert lib.bm_plan_create(C.byref(cfg), C.byref(h)) == -1
         assert len(lib.bm_last_error()) > 0
     assert lib.bm_plan_create(None, C.byref(h)) == -1
