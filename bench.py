@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="roi512", choices=["roi512", "batch256", "qoi512", "turbo1024", "sweep512", "eq1"],
+    ap.add_argument("--workload", default="roi512", choices=["roi512", "batch256", "qoi512", "turbo1024", "sweep512", "eq1", "nested512"],
                     help="roi512: the 512^3 ROI field (default); batch256: 256 fields, batched vs per-field; "
                          "qoi512: adjoint-guided bounds for a mean over a 128^3 box vs a uniform bound; "
                          "turbo1024: FP64 1024x1024x512 turbulence + front, gradient ROI, autotuned (b, L, M)")
@@ -103,6 +103,9 @@ def main():
         return
     if args.workload == "eq1":
         run_eq1(args)
+        return
+    if args.workload == "nested512":
+        run_nested(args)
         return
 
     import numpy as np
@@ -605,6 +608,102 @@ def run_sweep(args):
         "config": {"workload": f"{n}^3 FP32 k^-3 Gaussian random field, two 64^3 ROI boxes at REL 1e-5, "
                                f"background REL 1e-2; b=17, L in 1..4, M in 0..3", "best": {"L": best["L"], "M": best["M"]}},
         "sweep": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_nested(args):
+    """The 512^3 FP32 ROI workload with two block levels, plain schedule
+    (each block level re-tiles its grid with 17-node blocks, one launch per
+    level) against the nested schedule (17- then 9-node blocks over the same
+    regions, both levels in one launch: the level-2 grid stays in LDS), at
+    the same bounds; b = 33 with three block levels (33 -> 17 -> 9, the last
+    two fused) as well.  Per configuration: fused decompose + quantize and
+    dequantize + recompose times, plain transform times, per-level times,
+    compression ratio and the bound check."""
+    import numpy as np
+    import torch
+
+    from paper_2609_00205_amd import Plan, synth
+
+    torch.cuda.set_device(0)
+    n = args.n
+    print(f"[bench] generating {n}^3 field", file=sys.stderr, flush=True)
+    x_np, boxes = synth.workload_roi(n, seed=2)
+    xd = torch.from_numpy(x_np).cuda()
+    scale = float(xd.abs().max())
+    abs_boxes = [bx + (1e-5 * scale,) for bx in boxes]
+    bg = 1e-2 * scale
+    in_bytes = n ** 3 * 4
+    K, W = args.steps, args.warmup
+    rows = []
+
+    def timed(fn):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ts = []
+        for _ in range(K):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(ts))
+
+    for (b, L, M) in [(17, 1, 2), (17, 2, 0), (17, 2, 1), (17, 2, 2), (33, 3, 1)]:
+        for nested in ([False] if L == 1 else [False, True]):
+            print(f"[bench] b={b} L={L} M={M} nested={nested}", file=sys.stderr, flush=True)
+            plan = Plan((n, n, n), dtype=torch.float32, block=b, L=L, M=M, nested=nested)
+            bt = plan.tolmap_from_boxes(abs_boxes, bg)
+            codes = torch.empty(plan.coeff_shape, dtype=torch.int32, device="cuda")
+            coeff = torch.empty(plan.coeff_shape, dtype=torch.float32, device="cuda")
+            xr = torch.empty_like(xd)
+            for _ in range(W):
+                plan.decompose_quantize(xd, bt, codes=codes, check=False)
+                plan.dequantize_recompose(codes, bt, out=xr)
+                plan.decompose(xd, out=coeff)
+                plan.recompose(coeff, out=xr)
+            torch.cuda.synchronize()
+            dq = timed(lambda: plan.decompose_quantize(xd, bt, codes=codes, check=False))
+            rq = timed(lambda: plan.dequantize_recompose(codes, bt, out=xr))
+            ok = bool(((xr - xd).abs() <= bg).all())
+            dt_ = timed(lambda: plan.decompose(xd, out=coeff))
+            rt_ = timed(lambda: plan.recompose(coeff, out=xr))
+            plan.timing(True)
+            plan.decompose(xd, out=coeff)
+            plan.recompose(coeff, out=xr)
+            torch.cuda.synchronize()
+            lv = plan.timing_get()
+            plan.timing(False)
+            buf = plan.compress(xd, bt)
+            rows.append({"block": b, "L": L, "M": M, "nested": nested,
+                         "ms_per_step": round(dq + rq, 4),
+                         "decompose_quantize_ms": round(dq, 4), "dequantize_recompose_ms": round(rq, 4),
+                         "decompose_ms": round(dt_, 4), "recompose_ms": round(rt_, 4),
+                         "decompose_GBps": round(in_bytes / (dt_ * 1e-3) / 1e9, 1),
+                         "recompose_GBps": round(in_bytes / (rt_ * 1e-3) / 1e9, 1),
+                         "decompose_levels_ms": [round(v, 4) for v in lv["decompose"]],
+                         "recompose_levels_ms": [round(v, 4) for v in lv["recompose"]],
+                         "compression_ratio": round(in_bytes / len(buf), 3), "background_bound_held": ok})
+            print(f"[bench] {rows[-1]}", file=sys.stderr, flush=True)
+            del plan, codes, coeff, xr, buf
+            torch.cuda.empty_cache()
+    ref = next(r for r in rows if r["block"] == 17 and r["L"] == 2 and r["M"] == 1 and r["nested"])
+    out = {
+        "metric": "decompose/recompose GB/s at 512^3 FP32, nested block levels in one launch vs one launch per level",
+        "value": round(2 * in_bytes / (ref["ms_per_step"] * 1e-3) / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ref["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 FP32 k^-3 Gaussian random field, two 64^3 ROI boxes at REL 1e-5, "
+                               f"background REL 1e-2; value: b=17, L=2 nested, M=1"},
+        "rows": rows,
     }
     print(json.dumps(out), flush=True)
 

@@ -781,6 +781,11 @@ void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
     TimedScope ts(p, 2 * (s - 1), st);
     if (L.local) {
       const View3 src = s == 1 ? xv : dense_view(p.ws.grid[s - 1], L.n);
+      if (nest_pair(p, s)) {
+        local_decompose_nest(p, s, src, s == 1, coeff, nullptr, nullptr, st);
+        ++s;   // block level s+1 ran in the same launch
+        continue;
+      }
       local_decompose(p, s, src, s == 1, coeff, p.ws.grid[s], st);
     } else {
       const void* u;
@@ -811,6 +816,13 @@ void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
     const Level& L = p.lv[s - 1];
     TimedScope ts(p, 2 * (s - 1) + 1, st);
     if (L.local) {
+      if (s > 1 && nest_pair(p, s - 1)) {
+        // block levels s and s-1 in one launch
+        void* out = s == 2 ? x : p.ws.grid[s - 2];
+        local_recompose_nest(p, s - 1, coeff, p.ws.grid[s], out, s == 2, nullptr, nullptr, st);
+        --s;
+        continue;
+      }
       void* out = s == 1 ? x : p.ws.grid[s - 1];
       local_recompose(p, s, coeff, p.ws.grid[s], out, s == 1, st);
     } else {
@@ -872,6 +884,11 @@ void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, in
     const Level& L = p.lv[s - 1];
     TimedScope ts(p, 2 * (s - 1), st);
     const View3 src = s == 1 ? xv : dense_view(p.ws.grid[s - 1], L.n);
+    if (nest_pair(p, s)) {
+      local_decompose_nest(p, s, src, s == 1, nullptr, codes, &q, st);
+      ++s;   // block level s+1 ran in the same launch
+      continue;
+    }
     local_decompose_q(p, s, src, s == 1, codes, p.ws.grid[s], q, st);
   }
   decompose_quantize_global(p, x, codes, q, st);
@@ -920,6 +937,13 @@ void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* bloc
   dequantize_recompose_global(p, codes, q, x, st);
   for (int s = p.L; s >= 1; --s) {
     TimedScope ts(p, 2 * (s - 1) + 1, st);
+    if (s > 1 && nest_pair(p, s - 1)) {
+      // block levels s and s-1 in one launch
+      void* out = s == 2 ? x : p.ws.grid[s - 2];
+      local_recompose_nest(p, s - 1, nullptr, p.ws.grid[s], out, s == 2, codes, &q, st);
+      --s;
+      continue;
+    }
     void* out = s == 1 ? x : p.ws.grid[s - 1];
     local_recompose_q(p, s, codes, p.ws.grid[s], out, s == 1, q, st);
   }

@@ -265,6 +265,15 @@ void local_decompose_q(const bm_plan_s& p, int s, const View3& src, bool first, 
                        const QPrep& q, hipStream_t st);
 void local_recompose_q(const bm_plan_s& p, int s, const int32_t* codes, const void* coarse_in, void* out, bool last,
                        const QPrep& q, hipStream_t st);
+// nested schedule: block levels s (17-node blocks) and s+1 (9-node blocks
+// over the same regions) in one launch.  Decomposition writes level s's and
+// s+1's coefficients (codes when q) and G^{s+1}; recomposition reads G^{s+1}
+// (cin) and writes level s's output.
+bool nest_pair(const bm_plan_s& p, int s);
+void local_decompose_nest(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, int32_t* codes,
+                          const QPrep* q, hipStream_t st);
+void local_recompose_nest(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
+                          const int32_t* codes, const QPrep* q, hipStream_t st);
 
 // many fields per launch (block levels): per-field kernel arguments are
 // built on the host (block_*_args writes block_args_size bytes), uploaded,

@@ -81,6 +81,9 @@ struct DecArgs {
   int fuse;
   const double* nqinv;
   double* part;           // per block: the next level's partial load vector [H][H][H] (FP64)
+  // nested schedule, next block level in the same launch: the block's coarse
+  // values stay in LDS (CC) for it, and nothing is written at them here
+  int nest;
 };
 
 template <typename T>
@@ -114,11 +117,25 @@ struct RecArgs {
 template <typename T>
 constexpr int kWavesPerEU = sizeof(T) == 4 ? 8 : 4;
 
-// One workgroup's block group g (NB blocks) of a decomposition level.
-template <typename T, int B, bool Q>
+// Nested schedule, two block levels in one launch: the finer level (blocks
+// of 2B-1 nodes) leaves each block's B^3 coarse values at the start of the
+// block's LDS region; the coarser level (B-node blocks over the same
+// regions) works in the same region after them, 16-byte aligned.
+template <typename T, int B>
+constexpr int nest_offset() {
+  return int(((size_t(B) * B * B * sizeof(T) + 15) / 16) * 16 / sizeof(T));
+}
+
+// One workgroup's block group g (NBG blocks) of a decomposition level.
+// SRC_LDS: the level's input is the coarse values a (2B-1)-node block level
+// left in LDS for this group (nested schedule), not the source grid.
+template <typename T, int B, bool Q, int NBG = Geo<B, sizeof(T)>::NB, bool SRC_LDS = false>
 __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B, sizeof(T)>;
-  constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
+  constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = NBG;
+  constexpr int PREG = SRC_LDS ? Geo<2 * B - 1>::DEC_LDS : G::DEC_LDS;   // LDS elements per block
+  constexpr int POFF = SRC_LDS ? nest_offset<T, B>() : 0;
+  static_assert(!SRC_LDS || POFF + G::DEC_LDS <= PREG, "nested level must fit in its parent's LDS region");
   const int tid = threadIdx.x;
   // lanes run along the rows of the group's x-neighbouring blocks (NB
   // columns x of row y side by side), so a wavefront reads and writes
@@ -128,7 +145,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   const int tb = row < B ? row * B + (rr - (rr / B) * B) : 0;   // column within the block
   const int64_t blk = g * NB + bl;
   const bool act = bl < NB && blk < a.nblocks;
-  T* UE = lds + (bl < NB ? bl : 0) * G::DEC_LDS;     // even-z planes [MC][B][B]
+  T* UE = lds + (bl < NB ? bl : 0) * PREG + POFF;   // even-z planes [MC][B][B]
   T* T1 = UE + MC * BB;                              // [MI][B][B]
   T* T2 = UE;                                        // [MI][MI][B], after UE is dead
   T* Z = T1;                                         // [MI][MI][MI], after T1 is dead
@@ -144,7 +161,13 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   double iv[3];
   if (Q && act) column_class<B>(a.tab.cinv, blk, y, x, iv);
   T v[B];
-  if (act) {
+  if (act && SRC_LDS) {
+    const T* cc = lds + bl * PREG;                   // [B][B][B] coarse values of the finer level
+#pragma unroll
+    for (int z = 0; z < B; ++z) v[z] = cc[(z * B + y) * B + x];
+#pragma unroll
+    for (int j = 0; j < MC; ++j) UE[j * BB + tb] = v[2 * j];
+  } else if (act) {
     if (!a.first || (oz + B <= a.sn[0] && gy < a.sn[1] && gx < a.sn[2])) {
       const T* col = a.src + oz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2];
 #pragma unroll
@@ -188,7 +211,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       // 0): a later level (or the coarsest copy) overwrites them.  The plane
       // z = B-1 belongs to the next block unless this is the last one.
       // (fused with the next level: the coarse nodes are written at the end)
-      const bool later = a.fuse && ecol;
+      const bool later = (a.fuse || a.nest) && ecol;
       if (!Q) {
         T* dst = a.coeff + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
 #pragma unroll
@@ -241,9 +264,11 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
 #pragma unroll
       for (int J = 0; J < MI; ++J) c[J + 1] += Z[(J * MI + I) * MI + K];
     }
-    if (a.fuse) {
+    if (a.fuse || a.nest) {
 #pragma unroll
       for (int j = 0; j < MC; ++j) CC[(j * MC + (y >> 1)) * MC + (x >> 1)] = c[j];
+    }
+    if (a.fuse) {
 #pragma unroll
       for (int k = 0; k < H; ++k)
         Z1[(k * MC + (y >> 1)) * MC + (x >> 1)] = restrict_half<double, MC>(k, [&](int t) { return double(c[t]); });
@@ -260,7 +285,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       for (int j = 0; j < MC - 1; ++j) dst[2 * j * a.cs0] = quant(c[j], ci[zcase<B>(2 * j)], false, bad);
       if (lastz) dst[(B - 1) * a.cs0] = quant(c[MC - 1], ci[2], false, bad);
       if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
-    } else if (!a.fuse) {
+    } else if (!a.fuse && !a.nest) {
       T* cdst = a.cout + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
       for (int j = 0; j < MC - 1; ++j) cdst[j * a.cpl] = c[j];
@@ -317,18 +342,26 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   }
 }
 
-// One workgroup's block group g of a recomposition level.
-template <typename T, int B, bool Q>
+// One workgroup's block group g (NBG blocks) of a recomposition level.
+// Nested schedule, two block levels in one launch: MODE 1 is the coarser
+// level (B-node blocks), which writes all B^3 values of each block to the
+// start of the block's LDS region of the finer (2B-1)-node level and works
+// after them; MODE 2 is that finer level, which reads its coarse values
+// there instead of from the coarse grid.
+template <typename T, int B, bool Q, int NBG = Geo<B, sizeof(T), false>::NB, int MODE = 0>
 __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B, sizeof(T), false>;
-  constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = G::NB;
+  constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = NBG;
+  constexpr int PREG = MODE == 1 ? Geo<2 * B - 1>::REC_LDS : G::REC_LDS;   // LDS elements per block
+  constexpr int POFF = MODE == 1 ? nest_offset<T, B>() : 0;
+  static_assert(MODE != 1 || POFF + G::REC_LDS <= PREG, "nested level must fit in its parent's LDS region");
   const int tid = threadIdx.x;
   const int row = tid / (NB * B), rr = tid - row * (NB * B);   // as in decompose_group
   const int bl = row < B ? rr / B : NB;
   const int tb = row < B ? row * B + (rr - (rr / B) * B) : 0;
   const int64_t blk = g * NB + bl;
   const bool act = bl < NB && blk < a.nblocks;
-  T* UC = lds + (bl < NB ? bl : 0) * G::REC_LDS;     // coarse values u_C [MC][MC][MC]
+  T* UC = lds + (bl < NB ? bl : 0) * PREG + POFF;   // coarse values u_C [MC][MC][MC]
   T* T1 = UC + MC * MC * MC;                         // [MI][B][B]
   T* T2 = T1 + MI * BB;                              // [MI][MI][B]
   T* Z = T1;                                         // [MI][MI][MI], after T1 is dead
@@ -398,6 +431,10 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
             ce[j] = w2 + in[j];
           }
         }
+      } else if (MODE == 2) {
+        // left here by the coarser level of the same launch
+#pragma unroll
+        for (int j = 0; j < MC; ++j) ce[j] = UC[(j * MC + (y >> 1)) * MC + (x >> 1)];
       } else {
         const T* ccol = a.cin + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
@@ -437,14 +474,21 @@ __device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
       const T* pl = UC + j * MC * MC;
       I2[j] = T(0.25) * ((pl[cy0 * MC + cx0] + pl[cy0 * MC + cx1]) + (pl[cy1 * MC + cx0] + pl[cy1 * MC + cx1]));
     }
+    auto val = [&](int z) {
+      return (z & 1) ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) + w[z] : (ecol ? I2[z >> 1] : I2[z >> 1] + w[z]);
+    };
+    if (MODE == 1) {
+      // every node of the block, faces included: the finer level's coarse values
+      T* dst = lds + bl * PREG;
+#pragma unroll
+      for (int z = 0; z < B; ++z) dst[(z * B + y) * B + x] = val(z);
+      return;
+    }
     const bool owny = (y < B - 1 || by == a.nb[1] - 1) && gy < a.on[1];
     const bool ownx = (x < B - 1 || bx == a.nb[2] - 1) && gx < a.on[2];
     const bool lastz = bz == a.nb[0] - 1;
     if (owny && ownx) {
       T* dst = a.out + oz * a.os[0] + gy * a.os[1] + gx * a.os[2];
-      auto val = [&](int z) {
-        return (z & 1) ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) + w[z] : (ecol ? I2[z >> 1] : I2[z >> 1] + w[z]);
-      };
       if (oz + B <= a.on[0]) {
 #pragma unroll
         for (int z = 0; z < B - 1; ++z) dst[z * a.os0] = val(z);
@@ -473,6 +517,34 @@ __global__ __launch_bounds__((Geo<B, sizeof(T), false>::NT)) void k_local_recomp
   const int64_t g = xcd_group(blockIdx.x, a.per);
   if (g >= a.nwg) return;
   recompose_group<T, B, Q>(a, g, lds);
+}
+
+// Nested schedule: block levels of 17- and 9-node blocks over the same
+// regions in one launch.  Decomposition: the 17-node level keeps each
+// block's 9^3 coarse values in LDS and the 9-node level decomposes them
+// there (the level-2 grid never goes through HBM).  Recomposition: the
+// 9-node level recomposes each block's 9^3 values into LDS, and the
+// 17-node level takes them as its coarse values.
+template <typename T, bool Q>
+__global__ __launch_bounds__((Geo<17, sizeof(T)>::NT)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T>))) void k_local_decompose_nest(DecArgs<T> a1, DecArgs<T> a2) {
+  constexpr int NB = Geo<17, sizeof(T)>::NB;
+  __shared__ __attribute__((aligned(16))) T lds[NB * Geo<17>::DEC_LDS];   // FP64 scratch inside
+  const int64_t g = xcd_group(blockIdx.x, a1.per);
+  if (g >= a1.nwg) return;
+  decompose_group<T, 17, Q>(a1, g, lds);
+  __syncthreads();
+  decompose_group<T, 9, Q, NB, true>(a2, g, lds);
+}
+
+template <typename T, bool Q>
+__global__ __launch_bounds__((Geo<17, sizeof(T), false>::NT)) void k_local_recompose_nest(RecArgs<T> a2, RecArgs<T> a1) {
+  constexpr int NB = Geo<17, sizeof(T), false>::NB;
+  __shared__ __attribute__((aligned(16))) T lds[NB * Geo<17>::REC_LDS];
+  const int64_t g = xcd_group(blockIdx.x, a1.per);
+  if (g >= a1.nwg) return;
+  recompose_group<T, 9, Q, NB, 1>(a2, g, lds);
+  __syncthreads();
+  recompose_group<T, 17, Q, NB, 2>(a1, g, lds);
 }
 
 // Many fields in one persistent launch: task k is block group k - first[f]
@@ -688,7 +760,59 @@ void dispatch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin,
     launch_rec<double, B>(p, s, coeff, cin, out, last, codes, q, st);
 }
 
+template <typename T>
+void launch_dec_nest(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, int32_t* codes,
+                     const QPrep* q, hipStream_t st) {
+  using G = Geo<17, sizeof(T)>;
+  DecArgs<T> a1 = dec_args<T, 17>(p, s, src, first, coeff, nullptr, codes, q);
+  a1.nest = 1;
+  const DecArgs<T> a2 = dec_args<T, 9>(p, s + 1, dense_view(p.ws.grid[s], p.lv[s].n), false, coeff,
+                                       p.ws.grid[s + 1], codes, q);
+  if (a1.fuse || a1.coarsest_here || a2.nblocks != a1.nblocks) fail(BM_EINVAL, "nested pair: inconsistent levels");
+  if (q)
+    hipLaunchKernelGGL((k_local_decompose_nest<T, true>), dim3(unsigned(8 * a1.per)), dim3(G::NT), 0, st, a1, a2);
+  else
+    hipLaunchKernelGGL((k_local_decompose_nest<T, false>), dim3(unsigned(8 * a1.per)), dim3(G::NT), 0, st, a1, a2);
+  BM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_rec_nest(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
+                     const int32_t* codes, const QPrep* q, hipStream_t st) {
+  using G = Geo<17, sizeof(T), false>;
+  const RecArgs<T> a1 = rec_args<T, 17>(p, s, coeff, nullptr, out, last, codes, q);
+  const RecArgs<T> a2 = rec_args<T, 9>(p, s + 1, coeff, cin, nullptr, false, codes, q);
+  if (a1.fuse || a1.coarsest_here || a2.nblocks != a1.nblocks) fail(BM_EINVAL, "nested pair: inconsistent levels");
+  if (q)
+    hipLaunchKernelGGL((k_local_recompose_nest<T, true>), dim3(unsigned(8 * a1.per)), dim3(G::NT), 0, st, a2, a1);
+  else
+    hipLaunchKernelGGL((k_local_recompose_nest<T, false>), dim3(unsigned(8 * a1.per)), dim3(G::NT), 0, st, a2, a1);
+  BM_HIP(hipGetLastError());
+}
+
 }  // namespace
+
+bool nest_pair(const bm_plan_s& p, int s) {
+  return p.cfg.nested && s >= 1 && s < p.L && p.lv[s - 1].b == 17 && p.lv[s].b == 9;
+}
+
+void local_decompose_nest(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, int32_t* codes,
+                          const QPrep* q, hipStream_t st) {
+  if (!nest_pair(p, s)) fail(BM_EINVAL, "block levels s, s+1 are not a nested 17/9 pair");
+  if (p.cfg.dtype == BM_F32)
+    launch_dec_nest<float>(p, s, src, first, coeff, codes, q, st);
+  else
+    launch_dec_nest<double>(p, s, src, first, coeff, codes, q, st);
+}
+
+void local_recompose_nest(const bm_plan_s& p, int s, const void* coeff, const void* cin, void* out, bool last,
+                          const int32_t* codes, const QPrep* q, hipStream_t st) {
+  if (!nest_pair(p, s)) fail(BM_EINVAL, "block levels s, s+1 are not a nested 17/9 pair");
+  if (p.cfg.dtype == BM_F32)
+    launch_rec_nest<float>(p, s, coeff, cin, out, last, codes, q, st);
+  else
+    launch_rec_nest<double>(p, s, coeff, cin, out, last, codes, q, st);
+}
 
 void local_decompose(const bm_plan_s& p, int s, const View3& src, bool first, void* coeff, void* coarse_out,
                      hipStream_t st) {
