@@ -13,7 +13,8 @@
 //
 // GPU work: an LDS-privatised histogram, one wavefront per chunk for the
 // bit counts and for the encode (LDS atomic ORs into the chunk's words),
-// one thread per chunk for decoding.  The codebook is built on the host.
+// one thread per chunk for decoding (tables and output staged in LDS).  The
+// codebook is built on the host.
 
 #include <algorithm>
 #include <cstring>
@@ -140,64 +141,95 @@ struct DecTables {
   const uint32_t* sorted;     // symbols in (length, symbol) order
 };
 
-// one thread per chunk
+// One thread per chunk, 64 chunks per workgroup.  The lookup tables live in
+// LDS; decoded symbols go to an LDS tile 64 at a time per lane, and the tile
+// is stored one lane's run at a time, so every store instruction writes 64
+// consecutive codes (a lane writing straight to its own chunk would put the
+// 64 lanes of a store 16 KiB apart).  A lane that meets a malformed stream
+// raises the flag and decodes nothing more (the caller then fails).
 __global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint64_t* woff, int64_t nch, int64_t n,
                                                DecTables t, const uint64_t* ooff, const int32_t* oval,
                                                int32_t* codes, int* err) {
-  const int64_t c = int64_t(blockIdx.x) * 64 + threadIdx.x;
-  if (c >= nch) return;
+  __shared__ uint32_t lut[1 << LUTB];
+  __shared__ uint32_t first[LMAX + 1], count[LMAX + 1], base[LMAX + 1];
+  __shared__ int32_t tile[64 * 65];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < (1 << LUTB); i += 64) lut[i] = t.lut[i];
+  if (lane <= LMAX) {
+    first[lane] = t.first[lane];
+    count[lane] = t.count[lane];
+    base[lane] = t.base[lane];
+  }
+  const int64_t c0 = int64_t(blockIdx.x) * 64;
+  const int64_t c = c0 + lane;
+  const bool valid = c < nch;
   const int64_t b0 = c * CHUNK;
-  const int cnt = int(b0 + CHUNK < n ? CHUNK : n - b0);
-  const uint64_t w0 = woff[c], w1 = woff[c + 1];
+  const int cnt = valid ? int(b0 + CHUNK < n ? CHUNK : n - b0) : 0;
+  const uint64_t w0 = valid ? woff[c] : 0, w1 = valid ? woff[c + 1] : 0;
   // this chunk's outliers, in the order of its escape symbols
-  uint64_t e = ooff[c];
-  const uint64_t e1 = ooff[c + 1];
+  uint64_t e = valid ? ooff[c] : 0;
+  const uint64_t e1 = valid ? ooff[c + 1] : 0;
   uint64_t buf = 0;
   int avail = 0;
   uint64_t wp = w0;
-  for (int k = 0; k < cnt; ++k) {
-    while (avail <= 32) {
-      const uint64_t wv = wp < w1 ? words[wp] : 0u;
-      ++wp;
-      buf |= wv << (32 - avail);
-      avail += 32;
-    }
-    uint32_t s, l;
-    const uint32_t lu = t.lut[buf >> (64 - LUTB)];
-    if ((lu >> 16) != 0) {
-      s = lu & 0xFFFFu;
-      l = lu >> 16;
-    } else {
-      l = 0;
-      s = 0;
-      for (uint32_t L = LUTB + 1; L <= LMAX; ++L) {
-        const uint32_t code = uint32_t(buf >> (64 - L));
-        if (t.count[L] && code - t.first[L] < t.count[L]) {
-          s = t.sorted[t.base[L] + code - t.first[L]];
-          l = L;
+  bool bad = false;
+  __syncthreads();
+  for (int k0 = 0; k0 < CHUNK; k0 += 64) {
+    for (int kk = 0; kk < 64; ++kk) {
+      const int k = k0 + kk;
+      if (bad || k >= cnt) break;
+      while (avail <= 32) {
+        const uint64_t wv = wp < w1 ? words[wp] : 0u;
+        ++wp;
+        buf |= wv << (32 - avail);
+        avail += 32;
+      }
+      uint32_t s, l;
+      const uint32_t lu = lut[buf >> (64 - LUTB)];
+      if ((lu >> 16) != 0) {
+        s = lu & 0xFFFFu;
+        l = lu >> 16;
+      } else {
+        l = 0;
+        s = 0;
+        for (uint32_t L = LUTB + 1; L <= LMAX; ++L) {
+          const uint32_t code = uint32_t(buf >> (64 - L));
+          if (count[L] && code - first[L] < count[L]) {
+            s = t.sorted[base[L] + code - first[L]];
+            l = L;
+            break;
+          }
+        }
+        if (l == 0) {
+          bad = true;
           break;
         }
       }
-      if (l == 0) {
-        atomicOr(err, 1);
-        return;
+      buf <<= l;
+      avail -= int(l);
+      int32_t q;
+      if (s == 0) {
+        if (e >= e1) {
+          bad = true;
+          break;
+        }
+        q = oval[e++];
+      } else {
+        q = int32_t(s) - R;
       }
+      tile[lane * 65 + kk] = q;
     }
-    buf <<= l;
-    avail -= int(l);
-    int32_t q;
-    if (s == 0) {
-      if (e >= e1) {
-        atomicOr(err, 1);
-        return;
-      }
-      q = oval[e++];
-    } else {
-      q = int32_t(s) - R;
+    __syncthreads();
+    // lane j's 64 codes, written by the whole wavefront
+    for (int j = 0; j < 64; ++j) {
+      const int64_t cj = c0 + j;
+      if (cj >= nch) break;
+      const int cntj = int(cj * CHUNK + CHUNK < n ? CHUNK : n - cj * CHUNK);
+      if (k0 + lane < cntj) codes[cj * CHUNK + k0 + lane] = tile[j * 65 + lane];
     }
-    codes[b0 + k] = q;
+    __syncthreads();
   }
-  if (e != e1) atomicOr(err, 1);
+  if (valid && (bad || e != e1)) atomicOr(err, 1);
 }
 
 // ------------------------------------------------------------------ host codebook
