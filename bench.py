@@ -86,8 +86,8 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the method shards fields across GPUs "
-                                   "without communication, see the design notes", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark measures one GPU; the method shards fields across GPUs "
+                                   "without communication, or one field by z-slabs of whole blocks", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "batch256":
         run_batch(args)

@@ -56,7 +56,7 @@ enum {
   BM_ECAPACITY = -5,     /* output buffer too small; *out_bytes holds the size needed */
   BM_ECORRUPT = -6,      /* compressed stream fails its magic, version, size or CRC check */
   BM_ERANGE = -7,        /* a quantization code does not fit in 32 bits */
-  BM_EUNSUPPORTED = -8   /* valid request outside what this build implements */
+  BM_EUNSUPPORTED = -8   /* valid request outside what this library implements */
 };
 
 typedef enum { BM_F32 = 0, BM_F64 = 1 } bm_dtype;

@@ -17,6 +17,6 @@ Modules
              Algorithm 1.
 
 Everything is written from the paper's text (sections II-B, IV-A..IV-D,
-V-A) and the readings listed in the design notes; every function cites the
-passage it follows.
+V-A) and the readings stated in each module's header where the paper is
+silent; every function cites the passage it follows.
 """

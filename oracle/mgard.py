@@ -19,8 +19,8 @@ Paper passages followed
 * Sec. IV-D: out-of-range reads of the block kernel are zero-filled (kept as
   the ``pad_mode="zero"`` option; clamp is the default reading).
 
-Readings where the paper is silent (each is listed in the design notes)
------------------------------------------------------------------------
+Readings where the paper is silent
+----------------------------------
 * Details use the tensor (multilinear) interpolant; the correction is the
   tensor L2 projection computed as restriction passes x, y, z followed by
   tridiagonal solves x, y, z.

@@ -14,8 +14,8 @@ Paper passages followed
 * Sec. IV-D: scalar or per-block reciprocal quantizer (multiply by 1/Delta).
 * Sec. V-A: the REL bound is tol * max|u|.
 
-Readings (listed in the design notes)
--------------------------------------
+Readings where the paper is silent
+----------------------------------
 * "Contributes" in Eq. 2 = shares at least one node (shared-face blocks).
 * A node's tolerance at a block level is the minimum over the blocks of that
   level that contain it.
