@@ -12,6 +12,8 @@ Modules
              hybrid hierarchy, padding, and the adjoint (transpose) maps.
 ``roi``      block tolerance maps, conservative propagation (Eq. 2), the
              per-level error budget and the reciprocal quantizer.
+``paper8``   the paper's own block form: disjoint 8^3 blocks whose 5^3
+             coarse outputs are re-assembled into the next level's blocks.
 ``huffman``  canonical Huffman code lengths, chunked MSB-first bitstream.
 ``selector`` the throughput model (Eq. 1) and the (L, M) selector of
              Algorithm 1.

@@ -1,0 +1,94 @@
+"""Pins of the oracle's paper-literal In-cache Block form (disjoint 8^3
+blocks, Sec. IV-A / IV-C) against what the paper prints and what the
+mathematics fixes: the working-set constants, hand-derived 8-node
+operators, the dense L2 projection of one block, the re-assembly of the
+5^3 outputs, multilinear exactness and reconstruction.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mgard, paper8
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_paper_working_set():
+    g = json.load(open(os.path.join(GOLD, "paper_constants.json")))
+    assert paper8.B == g["block_edge"]["value"]
+    assert paper8.MC == g["block_coarse_edge"]["value"] == len(paper8.COARSE)
+    assert paper8.working_set() == g["working_set_elements"]["value"]
+    assert paper8.MC ** 3 == g["coarse_writer_threads"]["value"]
+    assert paper8.B ** 3 - paper8.MC ** 3 == g["detail_threads"]["value"]
+
+
+def test_eight_node_operators_by_hand():
+    # linear elements on nodes 0..7, coarse nodes 0 2 4 6 7 (spacings 2 2 2 1)
+    ops = mgard.axis_ops(np.arange(8.0), False)
+    assert list(ops.cidx) == [0, 2, 4, 6, 7]
+    M = mgard.mass_matrix(np.arange(8.0))
+    R = ops.P.T @ M
+    want = np.zeros((5, 8))
+    want[0, :3] = [5 / 12, 1 / 2, 1 / 12]
+    want[1, :5] = [1 / 12, 1 / 2, 5 / 6, 1 / 2, 1 / 12]
+    want[2, 2:7] = [1 / 12, 1 / 2, 5 / 6, 1 / 2, 1 / 12]
+    want[3, 4:] = [1 / 12, 1 / 2, 3 / 4, 1 / 6]
+    want[4, 6:] = [1 / 6, 1 / 3]
+    assert np.allclose(R, want, atol=1e-15)
+    Mc = mgard.mass_matrix(np.array([0.0, 2, 4, 6, 7]))
+    assert np.allclose(np.diag(Mc), [2 / 3, 4 / 3, 4 / 3, 1, 1 / 3])
+    assert np.allclose(np.diag(Mc, 1), [1 / 3, 1 / 3, 1 / 3, 1 / 6])
+
+
+def _kron3(a):
+    return np.kron(np.kron(a[0], a[1]), a[2])
+
+
+def test_block_level_is_dense_l2_projection(rng):
+    u = rng.standard_normal((8, 8, 8))
+    coords = [np.arange(8.0)] * 3
+    out = mgard.level_decompose(u, coords, False)
+    ops = [mgard.axis_ops(c, False) for c in coords]
+    P3 = _kron3([o.P for o in ops])
+    M3 = _kron3([mgard.mass_matrix(c) for c in coords])
+    c_dense = np.linalg.solve(P3.T @ M3 @ P3, P3.T @ M3 @ u.ravel())
+    cid = np.ix_(*(o.cidx for o in ops))
+    assert np.allclose(out[cid].ravel(), c_dense, atol=1e-13)
+
+
+@pytest.mark.parametrize("shape,L,dims,last", [((512, 512, 512), 3, [(512,) * 3, (320,) * 3, (200,) * 3], (125,) * 3),
+                                               ((20, 30, 12), 2, [(24, 32, 16), (16, 24, 16)], (10, 15, 10))])
+def test_level_dims(shape, L, dims, last):
+    d, m = paper8.level_dims(shape, L)
+    assert d == dims and m == last
+
+
+def test_reassembly_places_block_outputs_side_by_side():
+    # a field constant on every block: no details, every coarse value is the
+    # block's constant, found at [5 b, 5 b + 5) of the next grid
+    nb = (2, 3, 2)
+    ids = np.arange(np.prod(nb), dtype=float).reshape(nb) + 1.0
+    x = np.kron(ids, np.ones((8, 8, 8)))
+    c = paper8.decompose(x, 1)
+    d, last = paper8.level_dims(x.shape, 1)
+    assert np.abs(c[: np.prod(d[0])]).max() < 1e-13
+    nxt = c[np.prod(d[0]):].reshape(last)
+    assert np.allclose(nxt, np.kron(ids, np.ones((5, 5, 5))), atol=1e-13)
+
+
+def test_multilinear_first_level_details_vanish():
+    z, y, x = np.meshgrid(*(np.arange(float(n)) for n in (16, 24, 16)), indexing="ij")
+    f = 0.5 + x - 2 * y + 0.25 * z + 0.1 * x * y - 0.05 * y * z + 0.003 * x * y * z
+    c = paper8.decompose(f, 2)
+    n1 = 16 * 24 * 16
+    assert np.abs(c[:n1]).max() < 1e-12 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("shape,L", [((16, 16, 16), 1), ((20, 30, 12), 2), ((33, 17, 40), 3)])
+def test_reconstruction(shape, L, rng):
+    x = rng.standard_normal(shape)
+    c = paper8.decompose(x, L)
+    assert c.size == paper8.coeff_size(shape, L)
+    assert np.abs(paper8.recompose(c, shape, L) - x).max() < 1e-12 * np.abs(x).max()
