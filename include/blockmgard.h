@@ -340,6 +340,28 @@ bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_to
 bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* voxel_tol, double budget_ms, int reps,
                              bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
 
+/* ---- the paper's own block form (Sec. IV-A, IV-C) ------------------------ */
+
+/* Disjoint 8^3 blocks, each decomposed as one MGARD level (Sec. II-B) with
+ * natural ends on its own 8 nodes per axis (coarse nodes 0 2 4 6 7); the
+ * 5^3 coarse outputs of a level's blocks, side by side in block order and
+ * zero-filled to a multiple of 8, form the next level's grid (Sec. IV-C's
+ * re-assembly); L block levels, no global levels.  The input (logical dims,
+ * C order, dtype) is read with zero fill up to a multiple of 8 (Sec. IV-D).
+ * Coefficients, one flat device array of dtype (bm_p8_coeff_size values):
+ * the level arrays s = 1..L (dims n_s, multiples of 8, C order: the details
+ * at the fine nodes, 0 at each block's 125 coarse nodes) one after the
+ * other, then the coarsest values (dims 5 n_L / 8).  The plan owns the
+ * assembled grids between levels: calls on one plan must not overlap.
+ * Stream-ordered and asynchronous.  Errors: BM_EINVAL (dims outside
+ * [1, 2^31], dtype, L outside [1, 8], null), BM_ENOMEM, BM_EHIP. */
+typedef struct bm_p8_s* bm_p8;
+bm_status bm_p8_create(const int64_t dims[3], int dtype, int L, bm_p8* out);
+bm_status bm_p8_destroy(bm_p8 plan);
+bm_status bm_p8_coeff_size(bm_p8 plan, int64_t* elems);
+bm_status bm_p8_decompose(bm_p8 plan, const void* x_dev, void* coeff_dev, hipStream_t stream);
+bm_status bm_p8_recompose(bm_p8 plan, const void* coeff_dev, void* x_dev, hipStream_t stream);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 
 /* Per-level timing.  bm_timing(plan, 1) resets the counters and makes every

@@ -75,6 +75,11 @@ _SIGS = {
     "bm_batch_dequantize_recompose": [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.c_int, P],
     "bm_batch_compress": [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(C.c_size_t),
                           C.POINTER(C.c_size_t), C.c_int, P],
+    "bm_p8_create": [C.POINTER(C.c_int64), C.c_int, C.c_int, C.POINTER(P)],
+    "bm_p8_destroy": [P],
+    "bm_p8_coeff_size": [P, C.POINTER(C.c_int64)],
+    "bm_p8_decompose": [P, P, P, P],
+    "bm_p8_recompose": [P, P, P, P],
     "bm_timing": [P, C.c_int],
     "bm_timing_get": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)],
 }

@@ -381,6 +381,48 @@ def max_block_levels(shape: Sequence[int], block: int) -> int:
     return L
 
 
+class Paper8Plan:
+    """The paper's own block form: disjoint 8^3 blocks, L block levels whose
+    5^3 coarse outputs are re-assembled into the next level's blocks.
+    Coefficients are one flat array (see ``bm_p8_create``)."""
+
+    def __init__(self, shape: Sequence[int], dtype=torch.float32, L: int = 1, device=None):
+        shape = tuple(int(s) for s in shape)
+        if len(shape) != 3:
+            raise ValueError("3D shapes only")
+        self.shape, self.dtype, self.L = shape, dtype, int(L)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            call("bm_p8_create", (C.c_int64 * 3)(*shape), _DT[dtype], self.L, C.byref(h))
+        self._h = h
+        n = C.c_int64(0)
+        call("bm_p8_coeff_size", h, C.byref(n))
+        self.coeff_size = int(n.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().bm_p8_destroy(h)
+            self._h = None
+
+    def decompose(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _need(x, self.dtype, self.shape, "x")
+        if out is None:
+            out = torch.empty(self.coeff_size, dtype=self.dtype, device=x.device)
+        _need(out, self.dtype, (self.coeff_size,), "out")
+        call("bm_p8_decompose", self._h, _ptr(x), _ptr(out), _stream(stream))
+        return out
+
+    def recompose(self, coeff: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _need(coeff, self.dtype, (self.coeff_size,), "coeff")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=coeff.device)
+        _need(out, self.dtype, self.shape, "out")
+        call("bm_p8_recompose", self._h, _ptr(coeff), _ptr(out), _stream(stream))
+        return out
+
+
 class Batch:
     """Many fields of one dtype and block size through the fused pipeline in
     few launches (one persistent launch per block level for all fields),

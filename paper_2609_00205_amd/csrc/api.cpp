@@ -467,6 +467,47 @@ bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* v
   });
 }
 
+bm_status bm_p8_create(const int64_t dims[3], int dtype, int L, bm_p8* out) {
+  return guarded([&] {
+    need(dims && out, "null argument");
+    *out = nullptr;
+    *out = bm::p8_create(dims, dtype, L);
+  });
+}
+
+bm_status bm_p8_destroy(bm_p8 p) {
+  return guarded([&] { bm::p8_free(p); });
+}
+
+bm_status bm_p8_coeff_size(bm_p8 p, int64_t* elems) {
+  return guarded([&] {
+    need(p && elems, "null argument");
+    *elems = bm::p8_coeff_size(*p);
+  });
+}
+
+static void p8_check_device(const bm_p8_s* p) {
+  int d = -1;
+  BM_HIP(hipGetDevice(&d));
+  if (d != bm::p8_device(*p)) bm::fail(BM_EINVAL, "the current device is not the plan's device");
+}
+
+bm_status bm_p8_decompose(bm_p8 p, const void* x, void* coeff, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && coeff, "null argument");
+    p8_check_device(p);
+    bm::p8_decompose(*p, x, coeff, st);
+  });
+}
+
+bm_status bm_p8_recompose(bm_p8 p, const void* coeff, void* x, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && coeff, "null argument");
+    p8_check_device(p);
+    bm::p8_recompose(*p, coeff, x, st);
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");

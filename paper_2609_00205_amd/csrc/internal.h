@@ -313,6 +313,14 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
 // batches of fields (one dtype and block size): build / free, the fused
 // pipeline both ways (graph: capture once per binding, then replay), and the
 // fields whose codes overflowed int32 (synchronizes)
+// the paper's own 8^3 block form (paper8.hip)
+bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L);
+void p8_free(bm_p8_s* p);
+int64_t p8_coeff_size(const bm_p8_s& p);
+void p8_decompose(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st);
+void p8_recompose(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st);
+int p8_device(const bm_p8_s& p);
+
 bm_batch_s* batch_build(int nfields, const bm_config* cfgs);
 void batch_free(bm_batch_s* b);
 int batch_size(const bm_batch_s& b);

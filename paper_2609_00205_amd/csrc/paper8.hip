@@ -1,0 +1,427 @@
+// The paper's own In-cache Block form (Sec. IV-A, IV-C): disjoint 8^3
+// blocks, each decomposed as one MGARD level (Sec. II-B) with natural ends
+// on its own 8 nodes per axis (coarse nodes 0 2 4 6 7, spacings 2 2 2 1);
+// the 5^3 coarse outputs of a level's blocks, side by side in block order,
+// form the next level's grid, zero-filled to a multiple of 8 (Sec. IV-D's
+// zero fill).
+//
+// Mapping to gfx950: a workgroup takes four x-neighbouring blocks, one lane
+// per z-column (256 lanes; a wavefront covers two rows of 32 consecutive
+// values, one 128 B line each).  The column stays in registers; the
+// interpolant reads the coarse-z planes of the block from LDS; the z pass
+// (restriction by P^T M and the 5x5 coarse mass-matrix solve) runs in
+// registers, the y and x passes on short LDS lines: the block's working
+// set is the paper's 8^3 + 5x8x8 + 5x5x8 + 5^3 values.  Every operator
+// entry is a compile-time constant.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <vector>
+
+#include "block.h"
+#include "internal.h"
+
+namespace bm {
+namespace p8 {
+
+constexpr int B = 8, MC = 5, NBX = 4, NT = 256;
+// coarse node j of an axis: 0 2 4 6 7
+__device__ inline int cz(int j) { return j < MC - 1 ? 2 * j : B - 1; }
+
+__device__ inline bool coarse(int i) { return (i & 1) == 0 || i == B - 1; }
+// neighbours that interpolate node i (equal for a coarse node)
+__device__ inline int lo_of(int i) { return coarse(i) ? i : i - 1; }
+__device__ inline int hi_of(int i) { return coarse(i) ? i : i + 1; }
+// slot of coarse node i in 0..4
+__device__ inline int slot(int i) { return i == B - 1 ? MC - 1 : i >> 1; }
+
+// Thomas elimination of the coarse mass matrix on nodes 0 2 4 6 7 (unit
+// fine spacing): diagonal {2/3, 4/3, 4/3, 1, 1/3}, off-diagonal {1/3, 1/3,
+// 1/3, 1/6}.  inv[k] = 1 / (pivot k), up[k] = off[k] / pivot k.
+struct McSolve {
+  double inv[MC], up[MC - 1], lo[MC - 1];
+  constexpr McSolve() : inv(), up(), lo() {
+    const double d[MC] = {2.0 / 3, 4.0 / 3, 4.0 / 3, 1.0, 1.0 / 3};
+    const double e[MC - 1] = {1.0 / 3, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+    double piv = d[0];
+    for (int k = 0; k < MC; ++k) {
+      if (k > 0) piv = d[k] - e[k - 1] * up[k - 1];
+      inv[k] = 1.0 / piv;
+      if (k < MC - 1) up[k] = e[k] / piv;
+      if (k > 0) lo[k - 1] = e[k - 1];
+    }
+  }
+};
+
+// z = Mc^{-1} P^T M w for a line of 8 values (natural end rows).
+template <typename T>
+__device__ inline void restrict_solve8(const T (&w)[B], T (&z)[MC]) {
+  constexpr McSolve S{};
+  const T a = T(1.0 / 12), h = T(0.5), c = T(5.0 / 6);
+  T r[MC];
+  r[0] = T(5.0 / 12) * w[0] + h * w[1] + a * w[2];
+  r[1] = a * (w[0] + w[4]) + h * (w[1] + w[3]) + c * w[2];
+  r[2] = a * (w[2] + w[6]) + h * (w[3] + w[5]) + c * w[4];
+  r[3] = a * w[4] + h * w[5] + T(0.75) * w[6] + T(1.0 / 6) * w[7];
+  r[4] = T(1.0 / 6) * w[6] + T(1.0 / 3) * w[7];
+  T y[MC];
+  y[0] = r[0] * T(S.inv[0]);
+#pragma unroll
+  for (int k = 1; k < MC; ++k) y[k] = (r[k] - T(S.lo[k - 1]) * y[k - 1]) * T(S.inv[k]);
+  z[MC - 1] = y[MC - 1];
+#pragma unroll
+  for (int k = MC - 2; k >= 0; --k) z[k] = y[k] - T(S.up[k]) * z[k + 1];
+}
+
+template <typename T>
+struct Args {
+  const T* src;        // level input (decompose) or coefficients (recompose)
+  int64_t sn[3];       // extent readable from src (zero fill beyond: decompose)
+  int64_t ss[3];       // strides of src
+  T* coeff;            // level array (decompose output), dims n
+  int64_t cs[3];
+  T* cdst;             // coarse values: next grid (decompose output) or its source (recompose)
+  int64_t ds[3];
+  T* out;              // recompose output grid
+  int64_t on[3], os[3];
+  int64_t nb[3], ngx;  // blocks per axis; workgroups along x (blocks of 4)
+  int64_t nwg, per;
+};
+
+// lane -> (block of the workgroup, y, x)
+__device__ inline void lane_map(int t, int& bl, int& y, int& x) {
+  y = t >> 5;
+  const int xx = t & 31;
+  bl = xx >> 3;
+  x = xx & 7;
+}
+
+__device__ inline void wg_blocks(const int64_t g, const int64_t nb[3], int64_t ngx, int64_t& bz, int64_t& by,
+                                 int64_t& bx0) {
+  const int64_t gx = g % ngx, t = g / ngx;
+  by = t % nb[1];
+  bz = t / nb[1];
+  bx0 = gx * NBX;
+}
+
+// LDS per block: UE[5][64] coarse-z planes, T1[5][64] z-pass result,
+// T2[5][5][8] y-pass result, Z[5][5][5] the correction at the coarse nodes
+constexpr int LDS_BLOCK = MC * 64 + MC * 64 + MC * MC * B + MC * MC * MC;
+
+template <typename T>
+__device__ inline void yx_passes(T* T1, T* T2, T* Z, int t) {
+  if (t < MC * B) {   // y pass: line (Jz, x) over y
+    const int J = t / B, x = t - (t / B) * B;
+    T w[B], z[MC];
+#pragma unroll
+    for (int y = 0; y < B; ++y) w[y] = T1[J * 64 + y * B + x];
+    restrict_solve8(w, z);
+#pragma unroll
+    for (int I = 0; I < MC; ++I) T2[(J * MC + I) * B + x] = z[I];
+  }
+  __syncthreads();
+  if (t < MC * MC) {  // x pass: line (Jz, Jy) over x
+    T w[B], z[MC];
+#pragma unroll
+    for (int x = 0; x < B; ++x) w[x] = T2[t * B + x];
+    restrict_solve8(w, z);
+#pragma unroll
+    for (int K = 0; K < MC; ++K) Z[t * MC + K] = z[K];
+  }
+  __syncthreads();
+}
+
+// interpolant of the block's coarse values along y, x at (y, x) for each
+// coarse z plane; then along z
+template <typename T>
+__device__ inline void interp_column(const T* UE, int y, int x, T (&I)[B]) {
+  const int ya = lo_of(y), yb = hi_of(y), xa = lo_of(x), xb = hi_of(x);
+  T I2[MC];
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    const T* p = UE + j * 64;
+    I2[j] = T(0.25) * ((p[ya * B + xa] + p[ya * B + xb]) + (p[yb * B + xa] + p[yb * B + xb]));
+  }
+#pragma unroll
+  for (int z = 0; z < B; ++z) I[z] = (z & 1) && z != B - 1 ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) : I2[slot(z)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_p8_decompose(Args<T> a) {
+  __shared__ T lds[NBX * LDS_BLOCK];
+  const int64_t g = xcd_group(blockIdx.x, a.per);
+  if (g >= a.nwg) return;
+  const int t = threadIdx.x;
+  int bl, y, x;
+  lane_map(t, bl, y, x);
+  int64_t bz, by, bx0;
+  wg_blocks(g, a.nb, a.ngx, bz, by, bx0);
+  const int64_t bx = bx0 + bl;
+  const bool act = bx < a.nb[2];
+  T* UE = lds + bl * LDS_BLOCK;
+  T* T1 = UE + MC * 64;
+  T* T2 = T1 + MC * 64;
+  T* Z = T2 + MC * MC * B;
+  const int64_t gz = bz * B, gy = by * B + y, gx = bx * B + x;
+  T v[B];
+  if (act) {
+    const bool yx_in = gy < a.sn[1] && gx < a.sn[2];
+    const T* col = a.src + gy * a.ss[1] + gx * a.ss[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z) v[z] = (yx_in && gz + z < a.sn[0]) ? col[(gz + z) * a.ss[0]] : T(0);
+#pragma unroll
+    for (int j = 0; j < MC; ++j) UE[j * 64 + y * B + x] = v[cz(j)];
+  }
+  __syncthreads();
+  const bool ccol = coarse(y) && coarse(x);
+  T w[B];
+  if (act) {
+    T I[B];
+    interp_column(UE, y, x, I);
+#pragma unroll
+    for (int z = 0; z < B; ++z) w[z] = (ccol && coarse(z)) ? T(0) : v[z] - I[z];
+    T* dst = a.coeff + gz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z) dst[z * a.cs[0]] = w[z];
+    T zc[MC];
+    restrict_solve8(w, zc);
+#pragma unroll
+    for (int J = 0; J < MC; ++J) T1[J * 64 + y * B + x] = zc[J];
+  }
+  __syncthreads();
+  yx_passes(T1, T2, Z, act ? y * B + x : NT);   // each block's 64 lanes run its passes
+  if (act && ccol) {
+    // coarse values u_C + z, to the next grid at 5 b + slot
+    const int sy = slot(y), sx = slot(x);
+    T* dst = a.cdst + (bz * MC) * a.ds[0] + (by * MC + sy) * a.ds[1] + (bx * MC + sx) * a.ds[2];
+#pragma unroll
+    for (int j = 0; j < MC; ++j) dst[j * a.ds[0]] = v[cz(j)] + Z[(j * MC + sy) * MC + sx];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_p8_recompose(Args<T> a) {
+  __shared__ T lds[NBX * LDS_BLOCK];
+  const int64_t g = xcd_group(blockIdx.x, a.per);
+  if (g >= a.nwg) return;
+  const int t = threadIdx.x;
+  int bl, y, x;
+  lane_map(t, bl, y, x);
+  int64_t bz, by, bx0;
+  wg_blocks(g, a.nb, a.ngx, bz, by, bx0);
+  const int64_t bx = bx0 + bl;
+  const bool act = bx < a.nb[2];
+  T* UE = lds + bl * LDS_BLOCK;
+  T* T1 = UE + MC * 64;
+  T* T2 = T1 + MC * 64;
+  T* Z = T2 + MC * MC * B;
+  const int64_t gz = bz * B, gy = by * B + y, gx = bx * B + x;
+  const bool ccol = coarse(y) && coarse(x);
+  const int sy = slot(y), sx = slot(x);
+  T w[B], c[MC];
+  if (act) {
+    const T* col = a.src + gz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2];
+#pragma unroll
+    for (int z = 0; z < B; ++z) w[z] = col[z * a.ss[0]];
+    if (ccol) {
+      const T* cs = a.cdst + (bz * MC) * a.ds[0] + (by * MC + sy) * a.ds[1] + (bx * MC + sx) * a.ds[2];
+#pragma unroll
+      for (int j = 0; j < MC; ++j) c[j] = cs[j * a.ds[0]];
+#pragma unroll
+      for (int z = 0; z < B; ++z)
+        if (coarse(z)) w[z] = T(0);
+    }
+    T zc[MC];
+    restrict_solve8(w, zc);
+#pragma unroll
+    for (int J = 0; J < MC; ++J) T1[J * 64 + y * B + x] = zc[J];
+  }
+  __syncthreads();
+  yx_passes(T1, T2, Z, act ? y * B + x : NT);
+  if (act && ccol) {
+    // u_C = c - z on this column's coarse nodes
+#pragma unroll
+    for (int j = 0; j < MC; ++j) UE[j * 64 + y * B + x] = c[j] - Z[(j * MC + sy) * MC + sx];
+  }
+  __syncthreads();
+  if (act) {
+    T I[B];
+    interp_column(UE, y, x, I);
+    if (gy < a.on[1] && gx < a.on[2]) {
+      T* dst = a.out + gz * a.os[0] + gy * a.os[1] + gx * a.os[2];
+#pragma unroll
+      for (int z = 0; z < B; ++z)
+        if (gz + z < a.on[0]) dst[z * a.os[0]] = I[z] + w[z];
+    }
+  }
+}
+
+}  // namespace p8
+}  // namespace bm
+
+// ------------------------------------------------------------------ host
+
+struct bm_p8_s {
+  int device = 0;
+  int dtype = BM_F32;
+  size_t esize = 4;
+  int L = 0;
+  int64_t dims[3] = {1, 1, 1};
+  std::vector<std::array<int64_t, 3>> n;   // level grid dims (multiples of 8)
+  int64_t last[3] = {0, 0, 0};             // coarsest dims
+  std::vector<int64_t> off;                // level array offsets in the coefficients (elements); off[L] = coarsest
+  std::vector<void*> grid;                 // grid[s] (s = 1..L-1): assembled coarse values, zero fill kept
+};
+
+namespace bm {
+
+namespace {
+
+inline int64_t up8(int64_t v) { return (v + 7) / 8 * 8; }
+
+template <typename T>
+p8::Args<T> p8_args(const bm_p8_s& p, int s) {
+  p8::Args<T> a{};
+  const auto& n = p.n[s];
+  for (int k = 0; k < 3; ++k) a.nb[k] = n[k] / 8;
+  a.ngx = (a.nb[2] + p8::NBX - 1) / p8::NBX;
+  a.nwg = a.nb[0] * a.nb[1] * a.ngx;
+  a.per = (a.nwg + 7) / 8;
+  a.cs[0] = n[1] * n[2];
+  a.cs[1] = n[2];
+  a.cs[2] = 1;
+  // the coarse values' array: the next level's grid, or the coarsest values
+  const int64_t d1 = s + 1 < p.L ? p.n[s + 1][1] : p.last[1];
+  const int64_t d2 = s + 1 < p.L ? p.n[s + 1][2] : p.last[2];
+  a.ds[0] = d1 * d2;
+  a.ds[1] = d2;
+  a.ds[2] = 1;
+  return a;
+}
+
+template <typename T>
+void p8_decompose_t(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st) {
+  T* c = static_cast<T*>(coeff);
+  for (int s = 0; s < p.L; ++s) {
+    p8::Args<T> a = p8_args<T>(p, s);
+    const auto& n = p.n[s];
+    if (s == 0) {
+      a.src = static_cast<const T*>(x);
+      for (int k = 0; k < 3; ++k) a.sn[k] = p.dims[k];
+      a.ss[0] = p.dims[1] * p.dims[2];
+      a.ss[1] = p.dims[2];
+      a.ss[2] = 1;
+    } else {
+      a.src = static_cast<const T*>(p.grid[s]);
+      for (int k = 0; k < 3; ++k) a.sn[k] = n[k];
+      a.ss[0] = n[1] * n[2];
+      a.ss[1] = n[2];
+      a.ss[2] = 1;
+    }
+    a.coeff = c + p.off[s];
+    a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : c + p.off[p.L];
+    hipLaunchKernelGGL(p8::k_p8_decompose<T>, dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
+    BM_HIP(hipGetLastError());
+  }
+}
+
+template <typename T>
+void p8_recompose_t(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st) {
+  const T* c = static_cast<const T*>(coeff);
+  for (int s = p.L - 1; s >= 0; --s) {
+    p8::Args<T> a = p8_args<T>(p, s);
+    const auto& n = p.n[s];
+    a.src = c + p.off[s];
+    for (int k = 0; k < 3; ++k) a.sn[k] = n[k];
+    a.ss[0] = n[1] * n[2];
+    a.ss[1] = n[2];
+    a.ss[2] = 1;
+    a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : const_cast<T*>(c) + p.off[p.L];
+    if (s == 0) {
+      a.out = static_cast<T*>(x);
+      for (int k = 0; k < 3; ++k) a.on[k] = p.dims[k];
+      a.os[0] = p.dims[1] * p.dims[2];
+      a.os[1] = p.dims[2];
+    } else {
+      // only the assembled values: the zero fill beyond them stays zero
+      a.out = static_cast<T*>(p.grid[s]);
+      for (int k = 0; k < 3; ++k) a.on[k] = 5 * (p.n[s - 1][k] / 8);
+      a.os[0] = n[1] * n[2];
+      a.os[1] = n[2];
+    }
+    a.os[2] = 1;
+    hipLaunchKernelGGL(p8::k_p8_recompose<T>, dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
+    BM_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace
+
+bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L) {
+  if (dtype != BM_F32 && dtype != BM_F64) fail(BM_EINVAL, "dtype must be BM_F32 or BM_F64");
+  if (L < 1 || L > 8) fail(BM_EINVAL, "L must lie in [1, 8]");
+  for (int k = 0; k < 3; ++k)
+    if (dims[k] < 1 || dims[k] > (int64_t(1) << 31)) fail(BM_EINVAL, "dims must lie in [1, 2^31]");
+  auto* p = new bm_p8_s();
+  try {
+    BM_HIP(hipGetDevice(&p->device));
+    p->dtype = dtype;
+    p->esize = dtype == BM_F32 ? 4 : 8;
+    p->L = L;
+    std::array<int64_t, 3> n{up8(dims[0]), up8(dims[1]), up8(dims[2])};
+    for (int k = 0; k < 3; ++k) p->dims[k] = dims[k];
+    int64_t o = 0;
+    for (int s = 0; s < L; ++s) {
+      p->n.push_back(n);
+      p->off.push_back(o);
+      o += n[0] * n[1] * n[2];
+      std::array<int64_t, 3> m{5 * (n[0] / 8), 5 * (n[1] / 8), 5 * (n[2] / 8)};
+      if (s + 1 < L) {
+        n = {up8(m[0]), up8(m[1]), up8(m[2])};
+      } else {
+        for (int k = 0; k < 3; ++k) p->last[k] = m[k];
+      }
+    }
+    p->off.push_back(o);
+    p->grid.assign(L, nullptr);
+    for (int s = 1; s < L; ++s) {
+      const size_t bytes = size_t(p->n[s][0] * p->n[s][1] * p->n[s][2]) * p->esize;
+      BM_HIP(hipMalloc(&p->grid[s], bytes));
+      BM_HIP(hipMemset(p->grid[s], 0, bytes));   // the zero fill beyond the assembled values
+    }
+  } catch (...) {
+    for (void* g : p->grid)
+      if (g) (void)hipFree(g);
+    delete p;
+    throw;
+  }
+  return p;
+}
+
+void p8_free(bm_p8_s* p) {
+  if (!p) return;
+  for (void* g : p->grid)
+    if (g) (void)hipFree(g);
+  delete p;
+}
+
+int64_t p8_coeff_size(const bm_p8_s& p) { return p.off[p.L] + p.last[0] * p.last[1] * p.last[2]; }
+
+int p8_device(const bm_p8_s& p) { return p.device; }
+
+void p8_decompose(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st) {
+  if (p.dtype == BM_F32)
+    p8_decompose_t<float>(p, x, coeff, st);
+  else
+    p8_decompose_t<double>(p, x, coeff, st);
+}
+
+void p8_recompose(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st) {
+  if (p.dtype == BM_F32)
+    p8_recompose_t<float>(p, coeff, x, st);
+  else
+    p8_recompose_t<double>(p, coeff, x, st);
+}
+
+}  // namespace bm

@@ -1,0 +1,90 @@
+"""The paper's own block form (disjoint 8^3 blocks, re-assembled 5^3
+outputs) on the GPU against the oracle's ``paper8`` mode, through the C ABI.
+
+Bar: coefficients within 1e-6 * max|x| (FP32) and 1e-13 (FP64) of the
+oracle; recomposition of the same coefficients within the same bound;
+round trips back to the input; the zero fill of the assembled grids kept
+across calls.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import paper8
+from paper_2609_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-6, torch.float64: 1e-13}
+
+CASES = [((16, 16, 16), 1, torch.float32),
+         ((16, 16, 16), 1, torch.float64),
+         ((20, 30, 12), 2, torch.float32),     # ragged: zero fill at every level
+         ((33, 17, 40), 3, torch.float64),
+         ((64, 64, 64), 2, torch.float32),
+         ((1, 40, 70), 2, torch.float32),      # a 2D field
+         ((72, 40, 100), 3, torch.float32)]
+
+
+def _ids(c):
+    return "x".join(map(str, c[0])) + f"-L{c[1]}-{str(c[2])[6:]}"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_00205_amd import _lib
+    _lib.lib()
+
+
+def _np(dt):
+    return np.float32 if dt == torch.float32 else np.float64
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_paper8_parity(case):
+    from paper_2609_00205_amd import Paper8Plan
+    shape, L, dt = case
+    print("case", _ids(case), flush=True)
+    p = Paper8Plan(shape, dtype=dt, L=L)
+    assert p.coeff_size == paper8.coeff_size(shape, L)
+    x = synth.gaussian_random_field(shape, 3.0, seed=41, dtype=np.float64).astype(_np(dt))
+    xd = torch.from_numpy(x).cuda()
+    c = p.decompose(xd).cpu().double().numpy()
+    ref = paper8.decompose(x.astype(np.float64), L)
+    err = np.abs(c - ref).max() / np.abs(x).max()
+    print("max rel coefficient error", err)
+    assert err <= TOL[dt]
+    rng = np.random.default_rng(3)
+    co = (ref + 0.01 * rng.standard_normal(ref.shape)).astype(_np(dt))
+    out = p.recompose(torch.from_numpy(co).cuda()).cpu().double().numpy()
+    rr = paper8.recompose(co.astype(np.float64), shape, L)
+    err = np.abs(out - rr).max() / np.abs(rr).max()
+    print("max rel recompose error", err)
+    assert err <= TOL[dt]
+    xr = p.recompose(p.decompose(xd)).cpu().double().numpy()
+    assert np.abs(xr - x).max() / np.abs(x).max() <= (2e-6 if dt == torch.float32 else 1e-13)
+
+
+def test_paper8_zero_fill_kept_across_calls():
+    # a recomposition must not leave values in the zero fill of the plan's
+    # assembled grids, or the next decomposition would read them
+    from paper_2609_00205_amd import Paper8Plan
+    shape = (20, 30, 12)
+    p = Paper8Plan(shape, dtype=torch.float64, L=3)
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=42, dtype=np.float64)).cuda()
+    c0 = p.decompose(x).clone()
+    noise = torch.randn(c0.shape, dtype=torch.float64, device="cuda")
+    p.recompose(c0 + noise)
+    c1 = p.decompose(x)
+    torch.cuda.synchronize()
+    assert torch.equal(c0, c1)
+
+
+def test_paper8_bad_arguments():
+    from paper_2609_00205_amd import Paper8Plan, _lib
+    with pytest.raises(_lib.BMError):
+        Paper8Plan((16, 16, 16), L=0)
+    p = Paper8Plan((16, 16, 16), L=1)
+    with pytest.raises(ValueError):
+        p.decompose(torch.zeros((16, 16, 15), device="cuda"))
