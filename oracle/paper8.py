@@ -30,6 +30,17 @@ Readings where the paper is silent
   nodes, 0 at the coarse nodes, whose values live in the next grid), one
   after the other in C order, then the coarsest array.
 * Only block levels (no global levels after them).
+* ROI bounds (Sec. IV-C): a level-1 block takes the smallest voxel
+  tolerance over its real nodes; Eq. 2 on the assembled grids (Fig. 6):
+  block I of level s+1 takes the smallest tau over the level-s blocks whose
+  5^3 outputs land in it.  Details of level s get half-width
+  tau (1-eta) w_s / A with A the rounded-up L-inf gain of the natural
+  8-node level and w_s the level's share, the coarsest values
+  tau (1-eta) w_c with tau of the block they came from; shares are
+  proportional to the number of detail / coarsest coefficients, floored at
+  1/(64 T), T = L+1, and renormalised (the rule of the shared-face form).
+  Coarsest errors reach the fine nodes through interpolation only (gain 1),
+  a level's detail errors with gain A, so every node keeps its bound.
 """
 from __future__ import annotations
 
@@ -37,7 +48,7 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-from . import mgard
+from . import mgard, roi
 
 B = 8
 MC = 5
@@ -126,3 +137,76 @@ def recompose(coeff: np.ndarray, shape: Sequence[int], L: int) -> np.ndarray:
 def working_set() -> int:
     """Elements of a block's working set: input, then the three shrinking passes."""
     return B ** 3 + MC * B * B + MC * MC * B + MC ** 3
+
+
+# --------------------------------------------------------------------------
+# ROI quantization of this form (Sec. IV-C, IV-D)
+# --------------------------------------------------------------------------
+
+
+def block_tolerance(voxel_tol: np.ndarray, L: int) -> np.ndarray:
+    """Level-1 block map: the smallest voxel tolerance over a block's real nodes."""
+    dims, _ = level_dims(voxel_tol.shape, L)
+    nb = [d // B for d in dims[0]]
+    out = np.empty(nb)
+    for i in range(nb[0]):
+        for j in range(nb[1]):
+            for k in range(nb[2]):
+                out[i, j, k] = voxel_tol[B * i: B * i + B, B * j: B * j + B, B * k: B * k + B].min()
+    return out
+
+
+def propagate(tau: np.ndarray, nb_next: Sequence[int]) -> np.ndarray:
+    """Eq. 2 on the assembled grid (Fig. 6): block I of the next level takes the
+    smallest tau over the blocks J whose outputs 5J..5J+4 meet 8I..8I+7."""
+    out = np.full(tuple(nb_next), np.inf)
+    for I in np.ndindex(*nb_next):
+        rng = []
+        for a in range(3):
+            lo, hi = B * I[a] // MC, (B * I[a] + B - 1) // MC
+            rng.append(range(lo, min(hi, tau.shape[a] - 1) + 1))
+        out[I] = tau[np.ix_(*rng)].min()
+    return out
+
+
+def level_tolerances(tau1: np.ndarray, shape: Sequence[int], L: int) -> List[np.ndarray]:
+    dims, _ = level_dims(shape, L)
+    taus = [np.asarray(tau1, np.float64)]
+    for s in range(1, L):
+        taus.append(propagate(taus[-1], [d // B for d in dims[s]]))
+    return taus
+
+
+def gain() -> float:
+    """Rounded-up L-inf gain of the details of one natural 8-node level."""
+    return roi.round_up4(roi.amplification([np.arange(float(B))] * 3, False))
+
+
+def weights(shape: Sequence[int], L: int) -> List[float]:
+    """Budget shares of the L levels' details and of the coarsest values."""
+    dims, last = level_dims(shape, L)
+    N = float(sum(np.prod(d) for d in dims) + np.prod(last))
+    counts = [float(np.prod(d)) * (B ** 3 - MC ** 3) / B ** 3 for d in dims] + [float(np.prod(last))]
+    w = [c / N for c in counts]
+    floor = 1.0 / (64.0 * float(L + 1))
+    w = [v if v > floor else floor for v in w]
+    total = 0.0
+    for v in w:
+        total += v
+    return [v / total for v in w]
+
+
+def node_delta(shape: Sequence[int], L: int, tau1: np.ndarray, eta: float) -> np.ndarray:
+    """Bin width Delta of every coefficient (flat layout of :func:`decompose`)."""
+    dims, last = level_dims(shape, L)
+    taus = level_tolerances(tau1, shape, L)
+    A = gain()
+    w = weights(shape, L)
+    parts = []
+    for s in range(L):
+        k = (2.0 * (1.0 - eta)) * w[s] / A
+        parts.append((np.kron(taus[s], np.ones((B, B, B))) * k).ravel())
+    kc = (2.0 * (1.0 - eta)) * w[L]
+    src = [np.arange(n) // MC for n in last]          # block of the last level each value came from
+    parts.append((taus[L - 1][np.ix_(*src)] * kc).ravel())
+    return np.concatenate(parts)

@@ -92,3 +92,60 @@ def test_reconstruction(shape, L, rng):
     c = paper8.decompose(x, L)
     assert c.size == paper8.coeff_size(shape, L)
     assert np.abs(paper8.recompose(c, shape, L) - x).max() < 1e-12 * np.abs(x).max()
+
+
+# --- ROI quantization of the 8^3 form -------------------------------------
+
+def test_propagation_by_assembled_positions(rng):
+    # Eq. 2 / Fig. 6 by brute force: every assembled position p came from
+    # block p // 5 of the finer level and lies in block p // 8 of the next
+    tau = rng.uniform(1e-4, 1e-2, (3, 4, 2))
+    m = [5 * n for n in tau.shape]
+    nn = [-(-v // 8) for v in m]
+    want = np.full(nn, np.inf)
+    for p in np.ndindex(*m):
+        I = tuple(v // 8 for v in p)
+        want[I] = min(want[I], tau[tuple(v // 5 for v in p)])
+    assert np.array_equal(paper8.propagate(tau, nn), want)
+
+
+def test_fig6_strictest_region_wins():
+    # three blocks in a row at tau0 > tau1 > tau2: the next-level block that
+    # takes outputs of the second and third gets tau2, the first one tau1
+    tau = np.array([1e-2, 1e-3, 1e-4]).reshape(1, 1, 3)
+    out = paper8.propagate(tau, (1, 1, 2))
+    assert out[0, 0, 0] == 1e-3 and out[0, 0, 1] == 1e-4
+
+
+def test_gain_is_the_dense_worst_case():
+    coords = [np.arange(8.0)] * 3
+    ops = [mgard.axis_ops(c, False) for c in coords]
+    P3 = _kron3([o.P for o in ops])
+    K3 = _kron3([o.K for o in ops])
+    E = np.eye(512) - P3 @ K3
+    coarse = np.zeros((8, 8, 8), bool)
+    coarse[np.ix_(*(o.cidx for o in ops))] = True
+    det = ~coarse.ravel()
+    A = np.abs(E[:, det]).sum(axis=1).max()
+    assert paper8.gain() >= A and paper8.gain() - A < 1e-4
+
+
+def test_shares_sum_to_one():
+    w = paper8.weights((100, 70, 33), 3)
+    assert abs(sum(w) - 1.0) < 1e-15 and min(w) > 0
+
+
+@pytest.mark.parametrize("shape,L,seed", [((16, 16, 16), 1, 0), ((20, 30, 12), 2, 1), ((33, 17, 40), 3, 2),
+                                          ((40, 40, 40), 2, 3)])
+def test_bound_holds(shape, L, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(shape)
+    vt = np.full(shape, 1e-2)
+    z0, y0, x0 = [int(rng.integers(0, max(1, s - 6))) for s in shape]
+    vt[z0:z0 + 6, y0:y0 + 6, x0:x0 + 6] = 1e-5
+    tau1 = paper8.block_tolerance(vt, L)
+    delta = paper8.node_delta(shape, L, tau1, 0.0)
+    c = paper8.decompose(x, L)
+    q = np.rint(c * (1.0 / delta))
+    xr = paper8.recompose(q * delta, shape, L)
+    assert np.all(np.abs(xr - x) <= vt)
