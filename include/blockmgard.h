@@ -362,6 +362,27 @@ bm_status bm_p8_coeff_size(bm_p8 plan, int64_t* elems);
 bm_status bm_p8_decompose(bm_p8 plan, const void* x_dev, void* coeff_dev, hipStream_t stream);
 bm_status bm_p8_recompose(bm_p8 plan, const void* coeff_dev, void* x_dev, hipStream_t stream);
 
+/* ROI bounds of this form (Sec. IV-C, Fig. 6).  Level-1 block map (blocks
+ * per axis = bm_p8_block_grid, C order, FP64, device): the smallest voxel
+ * tolerance over a block's real nodes (voxel_tol: logical dims, FP64,
+ * absolute L-inf bounds, device).  Eq. 2 on the assembled grids: block I
+ * of level s+1 takes the smallest tau of the level-s blocks whose 5^3
+ * outputs land in it.  A level's details get Delta = 2 tau (1-eta) w_s / A
+ * (A the rounded-up L-inf gain of the natural 8-node level, w_s the
+ * level's share, proportional to its count), the coarsest values
+ * 2 tau (1-eta) w_c with tau of the block they came from; codes
+ * q = rint(c * (1/Delta)) in FP64, int32, one per coefficient (the zero
+ * placeholders get 0).  bm_p8_quantize synchronizes the stream and returns
+ * BM_ERANGE if a code does not fit in 32 bits; the other calls are
+ * asynchronous.  eta in [0, 0.5) (else BM_EINVAL). */
+bm_status bm_p8_block_grid(bm_p8 plan, int64_t nb[3]);
+bm_status bm_p8_tolmap_from_voxels(bm_p8 plan, const double* voxel_tol_dev, double* block_tol_dev,
+                                   hipStream_t stream);
+bm_status bm_p8_quantize(bm_p8 plan, const void* coeff_dev, const double* block_tol_dev, double eta,
+                         int32_t* codes_dev, hipStream_t stream);
+bm_status bm_p8_dequantize(bm_p8 plan, const int32_t* codes_dev, const double* block_tol_dev, double eta,
+                           void* coeff_dev, hipStream_t stream);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 
 /* Per-level timing.  bm_timing(plan, 1) resets the counters and makes every

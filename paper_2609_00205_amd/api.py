@@ -399,6 +399,10 @@ class Paper8Plan:
         n = C.c_int64(0)
         call("bm_p8_coeff_size", h, C.byref(n))
         self.coeff_size = int(n.value)
+        nb = (C.c_int64 * 3)()
+        call("bm_p8_block_grid", h, nb)
+        self.block_grid = tuple(nb)
+        self.eta = DEFAULT_ETA[dtype]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -420,6 +424,27 @@ class Paper8Plan:
             out = torch.empty(self.shape, dtype=self.dtype, device=coeff.device)
         _need(out, self.dtype, self.shape, "out")
         call("bm_p8_recompose", self._h, _ptr(coeff), _ptr(out), _stream(stream))
+        return out
+
+    def tolmap_from_voxels(self, voxel_tol: torch.Tensor, stream=None) -> torch.Tensor:
+        """Level-1 block map from a per-voxel absolute bound (FP64, logical dims)."""
+        _need(voxel_tol, torch.float64, self.shape, "voxel_tol")
+        out = torch.empty(self.block_grid, dtype=torch.float64, device=voxel_tol.device)
+        call("bm_p8_tolmap_from_voxels", self._h, _ptr(voxel_tol), _ptr(out), _stream(stream))
+        return out
+
+    def quantize(self, coeff: torch.Tensor, block_tol: torch.Tensor, stream=None) -> torch.Tensor:
+        _need(coeff, self.dtype, (self.coeff_size,), "coeff")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        codes = torch.empty(self.coeff_size, dtype=torch.int32, device=coeff.device)
+        call("bm_p8_quantize", self._h, _ptr(coeff), _ptr(block_tol), self.eta, _ptr(codes), _stream(stream))
+        return codes
+
+    def dequantize(self, codes: torch.Tensor, block_tol: torch.Tensor, stream=None) -> torch.Tensor:
+        _need(codes, torch.int32, (self.coeff_size,), "codes")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        out = torch.empty(self.coeff_size, dtype=self.dtype, device=codes.device)
+        call("bm_p8_dequantize", self._h, _ptr(codes), _ptr(block_tol), self.eta, _ptr(out), _stream(stream))
         return out
 
 

@@ -508,6 +508,39 @@ bm_status bm_p8_recompose(bm_p8 p, const void* coeff, void* x, hipStream_t st) {
   });
 }
 
+bm_status bm_p8_block_grid(bm_p8 p, int64_t nb[3]) {
+  return guarded([&] {
+    need(p && nb, "null argument");
+    bm::p8_block_grid(*p, nb);
+  });
+}
+
+bm_status bm_p8_tolmap_from_voxels(bm_p8 p, const double* voxel_tol, double* block_tol, hipStream_t st) {
+  return guarded([&] {
+    need(p && voxel_tol && block_tol, "null argument");
+    p8_check_device(p);
+    bm::p8_tolmap_from_voxels(*p, voxel_tol, block_tol, st);
+  });
+}
+
+bm_status bm_p8_quantize(bm_p8 p, const void* coeff, const double* block_tol, double eta, int32_t* codes,
+                         hipStream_t st) {
+  return guarded([&] {
+    need(p && coeff && block_tol && codes, "null argument");
+    p8_check_device(p);
+    bm::p8_quantize(*p, coeff, block_tol, eta, codes, st);
+  });
+}
+
+bm_status bm_p8_dequantize(bm_p8 p, const int32_t* codes, const double* block_tol, double eta, void* coeff,
+                           hipStream_t st) {
+  return guarded([&] {
+    need(p && coeff && block_tol && codes, "null argument");
+    p8_check_device(p);
+    bm::p8_dequantize(*p, codes, block_tol, eta, coeff, st);
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");

@@ -320,6 +320,12 @@ int64_t p8_coeff_size(const bm_p8_s& p);
 void p8_decompose(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st);
 void p8_recompose(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st);
 int p8_device(const bm_p8_s& p);
+void p8_block_grid(const bm_p8_s& p, int64_t nb[3]);
+void p8_tolmap_from_voxels(const bm_p8_s& p, const double* vt, double* block_tol, hipStream_t st);
+void p8_quantize(const bm_p8_s& p, const void* coeff, const double* block_tol, double eta, int32_t* codes,
+                 hipStream_t st);
+void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* coeff,
+                   hipStream_t st);
 
 bm_batch_s* batch_build(int nfields, const bm_config* cfgs);
 void batch_free(bm_batch_s* b);

@@ -15,7 +15,9 @@
 // entry is a compile-time constant.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -257,6 +259,80 @@ __global__ __launch_bounds__(NT) void k_p8_recompose(Args<T> a) {
   }
 }
 
+// ---- ROI quantization of this form (Sec. IV-C, IV-D) ----
+
+// level-1 block map: the smallest voxel tolerance over a block's real nodes
+__global__ __launch_bounds__(256) void k_p8_block_tol(const double* vt, int64_t n0, int64_t n1, int64_t n2,
+                                                      int64_t nb0, int64_t nb1, int64_t nb2, double* out) {
+  const int64_t tot = nb0 * nb1 * nb2;
+  for (int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x; b < tot; b += int64_t(gridDim.x) * 256) {
+    const int64_t bx = b % nb2, t = b / nb2, by = t % nb1, bz = t / nb1;
+    double m = INFINITY;
+    for (int64_t z = bz * B; z < bz * B + B && z < n0; ++z)
+      for (int64_t y = by * B; y < by * B + B && y < n1; ++y)
+        for (int64_t x = bx * B; x < bx * B + B && x < n2; ++x) m = fmin(m, vt[(z * n1 + y) * n2 + x]);
+    out[b] = m;
+  }
+}
+
+// Eq. 2 on the assembled grid (Fig. 6): next-level block I takes the smallest
+// tau over the blocks J whose outputs 5J..5J+4 meet 8I..8I+7
+__global__ __launch_bounds__(256) void k_p8_propagate(const double* tau, int64_t s0, int64_t s1, int64_t s2,
+                                                      double* out, int64_t m0, int64_t m1, int64_t m2) {
+  const int64_t tot = m0 * m1 * m2;
+  for (int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x; b < tot; b += int64_t(gridDim.x) * 256) {
+    const int64_t I2 = b % m2, t = b / m2, I1 = t % m1, I0 = t / m1;
+    auto lo = [](int64_t I) { return B * I / MC; };
+    auto hi = [](int64_t I, int64_t n) { return i64min((B * I + B - 1) / MC, n - 1); };
+    double m = INFINITY;
+    for (int64_t z = lo(I0); z <= hi(I0, s0); ++z)
+      for (int64_t y = lo(I1); y <= hi(I1, s1); ++y)
+        for (int64_t x = lo(I2); x <= hi(I2, s2); ++x) m = fmin(m, tau[(z * s1 + y) * s2 + x]);
+    out[b] = m;
+  }
+}
+
+constexpr int kMaxL = 8;
+
+struct QArgs8 {
+  int L;
+  uint32_t off[kMaxL + 2];       // flat offset of level s (s = 0..L-1), coarsest at L, end at L+1
+  Unflat32 uf[kMaxL + 1];        // level grid (s < L) or coarsest dims (s = L)
+  uint32_t nb1[kMaxL], nb2[kMaxL];   // blocks along y, x of level s
+  const double* tau[kMaxL];      // block taus of level s
+  double k[kMaxL + 1];           // Delta per unit tau: level s, coarsest at L
+  int64_t* flag;                 // set when a code does not fit in int32
+};
+
+// Delta of flat coefficient i
+__device__ inline double delta_of(const QArgs8& a, uint32_t i) {
+  int s = 0;
+  while (s < a.L && i >= a.off[s + 1]) ++s;
+  uint32_t z, y, x;
+  a.uf[s](i - a.off[s], z, y, x);
+  if (s < a.L) return a.tau[s][(size_t(z >> 3) * a.nb1[s] + (y >> 3)) * a.nb2[s] + (x >> 3)] * a.k[s];
+  // a coarsest value: the tau of the last level's block it came from
+  const int l = a.L - 1;
+  return a.tau[l][(size_t(z / MC) * a.nb1[l] + y / MC) * a.nb2[l] + x / MC] * a.k[a.L];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_p8_quantize(const T* c, uint32_t n, QArgs8 a, int32_t* q) {
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const double inv = 1.0 / delta_of(a, i);
+    const double v = rint(mul_rn(double(c[i]), inv));
+    const bool ok = fabs(v) <= 2147483647.0;
+    if (!ok) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+    q[i] = ok ? int32_t(v) : 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_p8_dequantize(const int32_t* q, uint32_t n, QArgs8 a, T* c) {
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+    c[i] = T(mul_rn(double(q[i]), delta_of(a, i)));
+}
+
 }  // namespace p8
 }  // namespace bm
 
@@ -272,6 +348,8 @@ struct bm_p8_s {
   int64_t last[3] = {0, 0, 0};             // coarsest dims
   std::vector<int64_t> off;                // level array offsets in the coefficients (elements); off[L] = coarsest
   std::vector<void*> grid;                 // grid[s] (s = 1..L-1): assembled coarse values, zero fill kept
+  std::vector<double*> tau;                // tau[s] (s = 1..L-1): propagated block tolerances
+  int64_t* flag = nullptr;                 // quantizer overflow flag
 };
 
 namespace bm {
@@ -385,14 +463,20 @@ bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L) {
     }
     p->off.push_back(o);
     p->grid.assign(L, nullptr);
+    p->tau.assign(L, nullptr);
     for (int s = 1; s < L; ++s) {
       const size_t bytes = size_t(p->n[s][0] * p->n[s][1] * p->n[s][2]) * p->esize;
       BM_HIP(hipMalloc(&p->grid[s], bytes));
       BM_HIP(hipMemset(p->grid[s], 0, bytes));   // the zero fill beyond the assembled values
+      BM_HIP(hipMalloc(&p->tau[s], size_t(p->n[s][0] / 8) * (p->n[s][1] / 8) * (p->n[s][2] / 8) * sizeof(double)));
     }
+    BM_HIP(hipMalloc(&p->flag, sizeof(int64_t)));
   } catch (...) {
     for (void* g : p->grid)
       if (g) (void)hipFree(g);
+    for (double* t : p->tau)
+      if (t) (void)hipFree(t);
+    if (p->flag) (void)hipFree(p->flag);
     delete p;
     throw;
   }
@@ -403,7 +487,175 @@ void p8_free(bm_p8_s* p) {
   if (!p) return;
   for (void* g : p->grid)
     if (g) (void)hipFree(g);
+  for (double* t : p->tau)
+    if (t) (void)hipFree(t);
+  if (p->flag) (void)hipFree(p->flag);
   delete p;
+}
+
+void p8_block_grid(const bm_p8_s& p, int64_t nb[3]) {
+  for (int k = 0; k < 3; ++k) nb[k] = p.n[0][k] / 8;
+}
+
+void p8_tolmap_from_voxels(const bm_p8_s& p, const double* vt, double* block_tol, hipStream_t st) {
+  int64_t nb[3];
+  p8_block_grid(p, nb);
+  const int64_t tot = nb[0] * nb[1] * nb[2];
+  const unsigned g = unsigned(std::min<int64_t>(65536, (tot + 255) / 256));
+  hipLaunchKernelGGL(p8::k_p8_block_tol, dim3(g), dim3(256), 0, st, vt, p.dims[0], p.dims[1], p.dims[2], nb[0],
+                     nb[1], nb[2], block_tol);
+  BM_HIP(hipGetLastError());
+}
+
+// L-inf gain of the details of one natural 8-node level in its
+// reconstruction: max over nodes x of the sum over detail nodes y of
+// |delta_xy - prod_d a(x_d, y_d)|, a = P K on the 8-node axis (K = Mc^{-1}
+// P^T M with the coarse nodes 0 2 4 6 7), from the 1D row profiles (sum of
+// |a| over all and over coarse columns, diagonal, coarse flag); rounded up
+// to 4 decimals with a 1e-6 slack in units of the last decimal.
+static double p8_gain() {
+  constexpr int n = 8, m = 5;
+  const int cn[m] = {0, 2, 4, 6, 7};
+  double P[n][m] = {};
+  for (int j = 0; j < m; ++j) P[cn[j]][j] = 1.0;
+  for (int i : {1, 3, 5}) P[i][i / 2] = P[i][i / 2 + 1] = 0.5;
+  double M[n][n] = {};
+  for (int i = 0; i < n; ++i) {
+    M[i][i] = (i == 0 || i == n - 1) ? 1.0 / 3 : 2.0 / 3;
+    if (i + 1 < n) M[i][i + 1] = M[i + 1][i] = 1.0 / 6;
+  }
+  const double d[m] = {2.0 / 3, 4.0 / 3, 4.0 / 3, 1.0, 1.0 / 3};
+  const double e[m - 1] = {1.0 / 3, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+  double K[m][n];
+  for (int c = 0; c < n; ++c) {
+    double r[m];
+    for (int j = 0; j < m; ++j) {
+      r[j] = 0;
+      for (int i = 0; i < n; ++i) r[j] += P[i][j] * M[i][c];
+    }
+    // Thomas on Mc
+    double cp[m], dp[m];
+    cp[0] = e[0] / d[0];
+    dp[0] = r[0] / d[0];
+    for (int j = 1; j < m; ++j) {
+      const double den = d[j] - e[j - 1] * cp[j - 1];
+      cp[j] = j < m - 1 ? e[j] / den : 0.0;
+      dp[j] = (r[j] - e[j - 1] * dp[j - 1]) / den;
+    }
+    K[m - 1][c] = dp[m - 1];
+    for (int j = m - 2; j >= 0; --j) K[j][c] = dp[j] - cp[j] * K[j + 1][c];
+  }
+  double sall[n], sc[n], dg[n];
+  bool cf[n];
+  for (int i = 0; i < n; ++i) {
+    sall[i] = sc[i] = 0;
+    cf[i] = (i & 1) == 0 || i == n - 1;
+    for (int j = 0; j < n; ++j) {
+      double a = 0;
+      for (int k = 0; k < m; ++k) a += P[i][k] * K[k][j];
+      sall[i] += std::fabs(a);
+      if ((j & 1) == 0 || j == n - 1) sc[i] += std::fabs(a);
+      if (j == i) dg[i] = a;
+    }
+  }
+  double best = 0;
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        double v = sall[z] * sall[y] * sall[x] - sc[z] * sc[y] * sc[x];
+        if (!(cf[z] && cf[y] && cf[x])) v += std::fabs(1.0 - dg[z] * dg[y] * dg[x]) - std::fabs(dg[z] * dg[y] * dg[x]);
+        best = std::max(best, v);
+      }
+  return std::ceil(best * 10000.0 - 1e-6) / 10000.0;
+}
+
+// Budget shares of the levels' details and of the coarsest values:
+// proportional to their counts, floored at 1/(64 (L+1)), renormalised
+// (summed in order).
+static std::vector<double> p8_weights(const bm_p8_s& p) {
+  int64_t tot = 0;
+  for (int s = 0; s < p.L; ++s) tot += p.n[s][0] * p.n[s][1] * p.n[s][2];
+  const int64_t nlast = p.last[0] * p.last[1] * p.last[2];
+  tot += nlast;
+  const double N = double(tot);
+  std::vector<double> w;
+  for (int s = 0; s < p.L; ++s) w.push_back(double(p.n[s][0] * p.n[s][1] * p.n[s][2]) * (512 - 125) / 512 / N);
+  w.push_back(double(nlast) / N);
+  const double floor = 1.0 / (64.0 * double(p.L + 1));
+  double sum = 0.0;
+  for (double& v : w) {
+    v = v > floor ? v : floor;
+    sum += v;
+  }
+  for (double& v : w) v /= sum;
+  return w;
+}
+
+static p8::QArgs8 p8_qargs(const bm_p8_s& p, const double* block_tol, double eta, hipStream_t st) {
+  if (!(eta >= 0.0 && eta < 0.5)) fail(BM_EINVAL, "eta must lie in [0, 0.5)");
+  if (p8_coeff_size(p) >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "2^32 coefficients or more");
+  // propagated taus of levels 2..L
+  std::vector<const double*> tau(p.L);
+  tau[0] = block_tol;
+  for (int s = 1; s < p.L; ++s) {
+    const auto& a = p.n[s - 1];
+    const auto& b = p.n[s];
+    const int64_t tot = (b[0] / 8) * (b[1] / 8) * (b[2] / 8);
+    const unsigned g = unsigned(std::min<int64_t>(65536, (tot + 255) / 256));
+    hipLaunchKernelGGL(p8::k_p8_propagate, dim3(g), dim3(256), 0, st, tau[s - 1], a[0] / 8, a[1] / 8, a[2] / 8,
+                       p.tau[s], b[0] / 8, b[1] / 8, b[2] / 8);
+    BM_HIP(hipGetLastError());
+    tau[s] = p.tau[s];
+  }
+  const double A = p8_gain();
+  const std::vector<double> w = p8_weights(p);
+  p8::QArgs8 q{};
+  q.L = p.L;
+  for (int s = 0; s <= p.L; ++s) q.off[s] = uint32_t(p.off[s]);
+  q.off[p.L + 1] = uint32_t(p8_coeff_size(p));
+  for (int s = 0; s < p.L; ++s) {
+    q.uf[s] = Unflat32(p.n[s][1], p.n[s][2]);
+    q.nb1[s] = uint32_t(p.n[s][1] / 8);
+    q.nb2[s] = uint32_t(p.n[s][2] / 8);
+    q.tau[s] = tau[s];
+    q.k[s] = (2.0 * (1.0 - eta)) * w[s] / A;
+  }
+  q.uf[p.L] = Unflat32(p.last[1], p.last[2]);
+  q.k[p.L] = (2.0 * (1.0 - eta)) * w[p.L];
+  q.flag = p.flag;
+  return q;
+}
+
+void p8_quantize(const bm_p8_s& p, const void* coeff, const double* block_tol, double eta, int32_t* codes,
+                 hipStream_t st) {
+  const p8::QArgs8 q = p8_qargs(p, block_tol, eta, st);
+  BM_HIP(hipMemsetAsync(p.flag, 0, sizeof(int64_t), st));
+  const uint32_t n = uint32_t(p8_coeff_size(p));
+  const unsigned g = unsigned(std::min<int64_t>(65536, (int64_t(n) + 255) / 256));
+  if (p.dtype == BM_F32)
+    hipLaunchKernelGGL(p8::k_p8_quantize<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(coeff), n, q,
+                       codes);
+  else
+    hipLaunchKernelGGL(p8::k_p8_quantize<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(coeff), n,
+                       q, codes);
+  BM_HIP(hipGetLastError());
+  int64_t f = 0;
+  BM_HIP(hipMemcpyAsync(&f, p.flag, sizeof(f), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  if (f) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+}
+
+void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* coeff,
+                   hipStream_t st) {
+  const p8::QArgs8 q = p8_qargs(p, block_tol, eta, st);
+  const uint32_t n = uint32_t(p8_coeff_size(p));
+  const unsigned g = unsigned(std::min<int64_t>(65536, (int64_t(n) + 255) / 256));
+  if (p.dtype == BM_F32)
+    hipLaunchKernelGGL(p8::k_p8_dequantize<float>, dim3(g), dim3(256), 0, st, codes, n, q, static_cast<float*>(coeff));
+  else
+    hipLaunchKernelGGL(p8::k_p8_dequantize<double>, dim3(g), dim3(256), 0, st, codes, n, q,
+                       static_cast<double*>(coeff));
+  BM_HIP(hipGetLastError());
 }
 
 int64_t p8_coeff_size(const bm_p8_s& p) { return p.off[p.L] + p.last[0] * p.last[1] * p.last[2]; }

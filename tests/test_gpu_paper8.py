@@ -88,3 +88,39 @@ def test_paper8_bad_arguments():
     p = Paper8Plan((16, 16, 16), L=1)
     with pytest.raises(ValueError):
         p.decompose(torch.zeros((16, 16, 15), device="cuda"))
+
+
+def _vt(shape, seed):
+    rng = np.random.default_rng(seed)
+    vt = np.full(shape, 1e-2)
+    e = [max(1, s // 4) for s in shape]
+    o = [int(rng.integers(0, s - ee + 1)) for s, ee in zip(shape, e)]
+    vt[o[0]:o[0] + e[0], o[1]:o[1] + e[1], o[2]:o[2] + e[2]] = 1e-5
+    return vt
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_paper8_quantizer(case):
+    from paper_2609_00205_amd import Paper8Plan
+    shape, L, dt = case
+    print("case", _ids(case), flush=True)
+    p = Paper8Plan(shape, dtype=dt, L=L)
+    x = synth.gaussian_random_field(shape, 3.0, seed=43, dtype=np.float64)
+    vt = _vt(shape, 5) * np.abs(x).max()
+    bt = p.tolmap_from_voxels(torch.from_numpy(vt).cuda())
+    tau1 = paper8.block_tolerance(vt, L)
+    assert np.array_equal(bt.cpu().numpy(), tau1)
+    # codes bit-exact given the oracle's coefficients (both sides decide in FP64)
+    coeff = paper8.decompose(x, L).astype(_np(dt))
+    delta = paper8.node_delta(shape, L, tau1, p.eta)
+    ref = np.rint(coeff.astype(np.float64) * (1.0 / delta)).astype(np.int64)
+    got = p.quantize(torch.from_numpy(coeff).cuda(), bt).cpu().numpy()
+    assert np.array_equal(got, ref), int((got != ref).sum())
+    deq = p.dequantize(torch.from_numpy(got).cuda(), bt).cpu().double().numpy()
+    assert np.array_equal(deq, (ref * delta).astype(_np(dt)).astype(np.float64))
+    # end to end on the GPU: every voxel within its bound
+    xd = torch.from_numpy(x).to(dt).cuda()
+    xr = p.recompose(p.dequantize(p.quantize(p.decompose(xd), bt), bt)).cpu().double().numpy()
+    err = np.abs(xr - xd.cpu().double().numpy())
+    print("worst error / bound", float((err / vt).max()))
+    assert np.all(err <= vt)
