@@ -32,9 +32,22 @@ def _writable(buf: bytearray):
     return (C.c_char * len(buf)).from_buffer(buf)
 
 
-def _take(buf: bytearray, n: int) -> bytes:
-    """The first n bytes of buf as bytes, copied once."""
-    return memoryview(buf)[:n].tobytes()
+def _take(buf: bytearray, n: int) -> bytearray:
+    """buf cut to its first n bytes, in place (the size queries are exact, so
+    normally nothing is cut and nothing is copied)."""
+    if n < len(buf):
+        del buf[n:]
+    return buf
+
+
+def _readable(buf):
+    """A pointer argument for a bytes-like container (bytes, bytearray, memoryview)."""
+    if isinstance(buf, bytes):
+        return buf
+    mv = memoryview(buf)
+    if mv.readonly:
+        return bytes(mv)
+    return (C.c_char * mv.nbytes).from_buffer(mv)
 
 
 def _need(t: torch.Tensor, dtype, shape, name):
@@ -263,7 +276,7 @@ class Plan:
                           "quantize": calls[2 * nl], "dequantize": calls[2 * nl + 1]}}
 
     # -- end to end ----------------------------------------------------------
-    def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None) -> bytes:
+    def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None) -> bytearray:
         _need(x, self.dtype, self.shape, "x")
         _need(block_tol, torch.float64, self.block_grid, "block_tol")
         need = C.c_size_t(0)
@@ -275,26 +288,28 @@ class Plan:
                 raise
         buf = bytearray(need.value)
         got = C.c_size_t(0)
-        call("bm_compress", self._h, _ptr(x), _ptr(block_tol), _writable(buf), need.value, C.byref(got), st)
+        view = _writable(buf)
+        call("bm_compress", self._h, _ptr(x), _ptr(block_tol), view, need.value, C.byref(got), st)
+        del view
         return _take(buf, got.value)
 
 
-def compressed_config(buf: bytes) -> dict:
+def compressed_config(buf) -> dict:
     cfg = BMConfig()
-    call("bm_compressed_config", buf, len(buf), C.byref(cfg))
+    call("bm_compressed_config", _readable(buf), len(buf), C.byref(cfg))
     return {"shape": tuple(cfg.dims), "dtype": _TD[cfg.dtype], "block": cfg.block, "L": cfg.L, "M": cfg.M,
             "pad_mode": cfg.pad_mode, "eta": cfg.eta, "nested": bool(cfg.nested)}
 
 
-def decompress(buf: bytes, device=None, stream=None) -> torch.Tensor:
+def decompress(buf, device=None, stream=None) -> torch.Tensor:
     info = compressed_config(buf)
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = torch.empty(info["shape"], dtype=info["dtype"], device=dev)
-    call("bm_decompress", buf, len(buf), _ptr(out), _stream(stream))
+    call("bm_decompress", _readable(buf), len(buf), _ptr(out), _stream(stream))
     return out
 
 
-def huffman_encode(codes: torch.Tensor, stream=None) -> bytes:
+def huffman_encode(codes: torch.Tensor, stream=None) -> bytearray:
     _need(codes, torch.int32, None, "codes")
     need = C.c_size_t(0)
     st = _stream(stream)
@@ -305,14 +320,16 @@ def huffman_encode(codes: torch.Tensor, stream=None) -> bytes:
             raise
     buf = bytearray(need.value)
     got = C.c_size_t(0)
-    call("bm_huffman_encode", _ptr(codes), codes.numel(), _writable(buf), need.value, C.byref(got), st)
+    view = _writable(buf)
+    call("bm_huffman_encode", _ptr(codes), codes.numel(), view, need.value, C.byref(got), st)
+    del view
     return _take(buf, got.value)
 
 
-def huffman_decode(buf: bytes, n: int, device=None, stream=None) -> torch.Tensor:
+def huffman_decode(buf, n: int, device=None, stream=None) -> torch.Tensor:
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = torch.empty(n, dtype=torch.int32, device=dev)
-    call("bm_huffman_decode", buf, len(buf), _ptr(out), n, _stream(stream))
+    call("bm_huffman_decode", _readable(buf), len(buf), _ptr(out), n, _stream(stream))
     return out
 
 
@@ -555,4 +572,5 @@ class Batch:
         got = (C.c_size_t * nf)()
         self._run(lambda st: call("bm_batch_compress", self._h, self._ptrs(xs), self._ptrs(block_tols), outp, cap,
                                   got, int(use_graph), st), use_graph, stream)
+        del views   # (the buffers cannot be cut while they are exported)
         return [_take(b, got[i]) for i, b in enumerate(bufs)]
