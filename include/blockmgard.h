@@ -383,6 +383,18 @@ bm_status bm_p8_quantize(bm_p8 plan, const void* coeff_dev, const double* block_
 bm_status bm_p8_dequantize(bm_p8 plan, const int32_t* codes_dev, const double* block_tol_dev, double eta,
                            void* coeff_dev, hipStream_t stream);
 
+/* The fused pipeline of this form (Sec. IV-D): the block kernels write the
+ * codes of each level's details and, at the last level, of the coarsest
+ * values, straight from the block in registers; the recomposition
+ * dequantizes on load.  Equal, bit for bit, to bm_p8_quantize after
+ * bm_p8_decompose and to bm_p8_recompose after bm_p8_dequantize.
+ * bm_p8_decompose_quantize synchronizes (BM_ERANGE as bm_p8_quantize);
+ * bm_p8_dequantize_recompose is asynchronous. */
+bm_status bm_p8_decompose_quantize(bm_p8 plan, const void* x_dev, const double* block_tol_dev, double eta,
+                                   int32_t* codes_dev, hipStream_t stream);
+bm_status bm_p8_dequantize_recompose(bm_p8 plan, const int32_t* codes_dev, const double* block_tol_dev, double eta,
+                                     void* x_dev, hipStream_t stream);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 
 /* Per-level timing.  bm_timing(plan, 1) resets the counters and makes every

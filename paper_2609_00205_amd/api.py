@@ -464,6 +464,29 @@ class Paper8Plan:
         call("bm_p8_dequantize", self._h, _ptr(codes), _ptr(block_tol), self.eta, _ptr(out), _stream(stream))
         return out
 
+    def decompose_quantize(self, x: torch.Tensor, block_tol: torch.Tensor, codes: Optional[torch.Tensor] = None,
+                           stream=None) -> torch.Tensor:
+        """Fused: equal to quantize(decompose(x))."""
+        _need(x, self.dtype, self.shape, "x")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        if codes is None:
+            codes = torch.empty(self.coeff_size, dtype=torch.int32, device=x.device)
+        _need(codes, torch.int32, (self.coeff_size,), "codes")
+        call("bm_p8_decompose_quantize", self._h, _ptr(x), _ptr(block_tol), self.eta, _ptr(codes), _stream(stream))
+        return codes
+
+    def dequantize_recompose(self, codes: torch.Tensor, block_tol: torch.Tensor, out: Optional[torch.Tensor] = None,
+                             stream=None) -> torch.Tensor:
+        """Fused: equal to recompose(dequantize(codes))."""
+        _need(codes, torch.int32, (self.coeff_size,), "codes")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=codes.device)
+        _need(out, self.dtype, self.shape, "out")
+        call("bm_p8_dequantize_recompose", self._h, _ptr(codes), _ptr(block_tol), self.eta, _ptr(out),
+             _stream(stream))
+        return out
+
 
 class Batch:
     """Many fields of one dtype and block size through the fused pipeline in

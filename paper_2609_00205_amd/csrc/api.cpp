@@ -541,6 +541,24 @@ bm_status bm_p8_dequantize(bm_p8 p, const int32_t* codes, const double* block_to
   });
 }
 
+bm_status bm_p8_decompose_quantize(bm_p8 p, const void* x, const double* block_tol, double eta, int32_t* codes,
+                                   hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && codes, "null argument");
+    p8_check_device(p);
+    bm::p8_decompose_quantize(*p, x, block_tol, eta, codes, st);
+  });
+}
+
+bm_status bm_p8_dequantize_recompose(bm_p8 p, const int32_t* codes, const double* block_tol, double eta, void* x,
+                                     hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && codes, "null argument");
+    p8_check_device(p);
+    bm::p8_dequantize_recompose(*p, codes, block_tol, eta, x, st);
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");

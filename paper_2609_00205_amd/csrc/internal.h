@@ -326,6 +326,10 @@ void p8_quantize(const bm_p8_s& p, const void* coeff, const double* block_tol, d
                  hipStream_t st);
 void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* coeff,
                    hipStream_t st);
+void p8_decompose_quantize(const bm_p8_s& p, const void* x, const double* block_tol, double eta, int32_t* codes,
+                           hipStream_t st);
+void p8_dequantize_recompose(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* x,
+                             hipStream_t st);
 
 bm_batch_s* batch_build(int nfields, const bm_config* cfgs);
 void batch_free(bm_batch_s* b);

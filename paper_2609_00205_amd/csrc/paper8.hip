@@ -89,7 +89,23 @@ struct Args {
   int64_t on[3], os[3];
   int64_t nb[3], ngx;  // blocks per axis; workgroups along x (blocks of 4)
   int64_t nwg, per;
+  // fused quantization (Sec. IV-D): codes instead of coefficients
+  int32_t* q;          // level codes (same layout as coeff / src)
+  int32_t* qc;         // coarsest codes (last level), layout of cdst
+  const double* tau;   // this level's block taus
+  double k, kc;        // Delta per unit tau: details, coarsest values
+  int last;            // last level: the coarse values are the coarsest codes
+  int64_t* flag;       // set when a code does not fit in int32
 };
+
+// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag
+template <typename T>
+__device__ inline int32_t quant8(T c, double inv, bool& bad) {
+  const double v = rint(mul_rn(double(c), inv));
+  const bool ok = fabs(v) <= 2147483647.0;
+  bad |= !ok;
+  return ok ? int32_t(v) : 0;
+}
 
 // lane -> (block of the workgroup, y, x)
 __device__ inline void lane_map(int t, int& bl, int& y, int& x) {
@@ -149,7 +165,7 @@ __device__ inline void interp_column(const T* UE, int y, int x, T (&I)[B]) {
   for (int z = 0; z < B; ++z) I[z] = (z & 1) && z != B - 1 ? T(0.5) * (I2[z >> 1] + I2[(z >> 1) + 1]) : I2[slot(z)];
 }
 
-template <typename T>
+template <typename T, bool Q>
 __global__ __launch_bounds__(NT) void k_p8_decompose(Args<T> a) {
   __shared__ T lds[NBX * LDS_BLOCK];
   const int64_t g = xcd_group(blockIdx.x, a.per);
@@ -183,9 +199,18 @@ __global__ __launch_bounds__(NT) void k_p8_decompose(Args<T> a) {
     interp_column(UE, y, x, I);
 #pragma unroll
     for (int z = 0; z < B; ++z) w[z] = (ccol && coarse(z)) ? T(0) : v[z] - I[z];
-    T* dst = a.coeff + gz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
+    const int64_t o = gz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
+    if (Q) {
+      // the block's Delta of this level's details
+      const double inv = 1.0 / (a.tau[(bz * a.nb[1] + by) * a.nb[2] + bx] * a.k);
+      bool bad = false;
 #pragma unroll
-    for (int z = 0; z < B; ++z) dst[z * a.cs[0]] = w[z];
+      for (int z = 0; z < B; ++z) a.q[o + z * a.cs[0]] = quant8(w[z], inv, bad);
+      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+    } else {
+#pragma unroll
+      for (int z = 0; z < B; ++z) a.coeff[o + z * a.cs[0]] = w[z];
+    }
     T zc[MC];
     restrict_solve8(w, zc);
 #pragma unroll
@@ -196,13 +221,22 @@ __global__ __launch_bounds__(NT) void k_p8_decompose(Args<T> a) {
   if (act && ccol) {
     // coarse values u_C + z, to the next grid at 5 b + slot
     const int sy = slot(y), sx = slot(x);
-    T* dst = a.cdst + (bz * MC) * a.ds[0] + (by * MC + sy) * a.ds[1] + (bx * MC + sx) * a.ds[2];
+    const int64_t o = (bz * MC) * a.ds[0] + (by * MC + sy) * a.ds[1] + (bx * MC + sx) * a.ds[2];
+    if (Q && a.last) {
+      // the coarsest values: codes with the block's Delta
+      const double inv = 1.0 / (a.tau[(bz * a.nb[1] + by) * a.nb[2] + bx] * a.kc);
+      bool bad = false;
 #pragma unroll
-    for (int j = 0; j < MC; ++j) dst[j * a.ds[0]] = v[cz(j)] + Z[(j * MC + sy) * MC + sx];
+      for (int j = 0; j < MC; ++j) a.qc[o + j * a.ds[0]] = quant8(v[cz(j)] + Z[(j * MC + sy) * MC + sx], inv, bad);
+      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+    } else {
+#pragma unroll
+      for (int j = 0; j < MC; ++j) a.cdst[o + j * a.ds[0]] = v[cz(j)] + Z[(j * MC + sy) * MC + sx];
+    }
   }
 }
 
-template <typename T>
+template <typename T, bool Q>
 __global__ __launch_bounds__(NT) void k_p8_recompose(Args<T> a) {
   __shared__ T lds[NBX * LDS_BLOCK];
   const int64_t g = xcd_group(blockIdx.x, a.per);
@@ -223,13 +257,26 @@ __global__ __launch_bounds__(NT) void k_p8_recompose(Args<T> a) {
   const int sy = slot(y), sx = slot(x);
   T w[B], c[MC];
   if (act) {
-    const T* col = a.src + gz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2];
+    const int64_t o = gz * a.ss[0] + gy * a.ss[1] + gx * a.ss[2];
+    if (Q) {
+      // fused dequantization: c_hat = (T)(q * Delta)
+      const double del = a.tau[(bz * a.nb[1] + by) * a.nb[2] + bx] * a.k;
 #pragma unroll
-    for (int z = 0; z < B; ++z) w[z] = col[z * a.ss[0]];
+      for (int z = 0; z < B; ++z) w[z] = T(mul_rn(double(a.q[o + z * a.ss[0]]), del));
+    } else {
+#pragma unroll
+      for (int z = 0; z < B; ++z) w[z] = a.src[o + z * a.ss[0]];
+    }
     if (ccol) {
-      const T* cs = a.cdst + (bz * MC) * a.ds[0] + (by * MC + sy) * a.ds[1] + (bx * MC + sx) * a.ds[2];
+      const int64_t oc = (bz * MC) * a.ds[0] + (by * MC + sy) * a.ds[1] + (bx * MC + sx) * a.ds[2];
+      if (Q && a.last) {
+        const double del = a.tau[(bz * a.nb[1] + by) * a.nb[2] + bx] * a.kc;
 #pragma unroll
-      for (int j = 0; j < MC; ++j) c[j] = cs[j * a.ds[0]];
+        for (int j = 0; j < MC; ++j) c[j] = T(mul_rn(double(a.qc[oc + j * a.ds[0]]), del));
+      } else {
+#pragma unroll
+        for (int j = 0; j < MC; ++j) c[j] = a.cdst[oc + j * a.ds[0]];
+      }
 #pragma unroll
       for (int z = 0; z < B; ++z)
         if (coarse(z)) w[z] = T(0);
@@ -378,8 +425,15 @@ p8::Args<T> p8_args(const bm_p8_s& p, int s) {
   return a;
 }
 
-template <typename T>
-void p8_decompose_t(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st) {
+// quantization context of a fused call: the levels' taus and Delta factors
+struct P8Quant {
+  const double* tau[p8::kMaxL];
+  double k[p8::kMaxL + 1];
+};
+
+template <typename T, bool Q>
+void p8_decompose_t(const bm_p8_s& p, const void* x, void* coeff, int32_t* codes, const P8Quant* qz,
+                    hipStream_t st) {
   T* c = static_cast<T*>(coeff);
   for (int s = 0; s < p.L; ++s) {
     p8::Args<T> a = p8_args<T>(p, s);
@@ -397,25 +451,47 @@ void p8_decompose_t(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st
       a.ss[1] = n[2];
       a.ss[2] = 1;
     }
-    a.coeff = c + p.off[s];
-    a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : c + p.off[p.L];
-    hipLaunchKernelGGL(p8::k_p8_decompose<T>, dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
+    if (Q) {
+      a.q = codes + p.off[s];
+      a.qc = codes + p.off[p.L];
+      a.tau = qz->tau[s];
+      a.k = qz->k[s];
+      a.kc = qz->k[p.L];
+      a.last = s == p.L - 1;
+      a.flag = p.flag;
+      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : nullptr;
+    } else {
+      a.coeff = c + p.off[s];
+      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : c + p.off[p.L];
+    }
+    hipLaunchKernelGGL((p8::k_p8_decompose<T, Q>), dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
     BM_HIP(hipGetLastError());
   }
 }
 
-template <typename T>
-void p8_recompose_t(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st) {
+template <typename T, bool Q>
+void p8_recompose_t(const bm_p8_s& p, const void* coeff, void* x, const int32_t* codes, const P8Quant* qz,
+                    hipStream_t st) {
   const T* c = static_cast<const T*>(coeff);
   for (int s = p.L - 1; s >= 0; --s) {
     p8::Args<T> a = p8_args<T>(p, s);
     const auto& n = p.n[s];
-    a.src = c + p.off[s];
     for (int k = 0; k < 3; ++k) a.sn[k] = n[k];
     a.ss[0] = n[1] * n[2];
     a.ss[1] = n[2];
     a.ss[2] = 1;
-    a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : const_cast<T*>(c) + p.off[p.L];
+    if (Q) {
+      a.q = const_cast<int32_t*>(codes) + p.off[s];
+      a.qc = const_cast<int32_t*>(codes) + p.off[p.L];
+      a.tau = qz->tau[s];
+      a.k = qz->k[s];
+      a.kc = qz->k[p.L];
+      a.last = s == p.L - 1;
+      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : nullptr;
+    } else {
+      a.src = c + p.off[s];
+      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : const_cast<T*>(c) + p.off[p.L];
+    }
     if (s == 0) {
       a.out = static_cast<T*>(x);
       for (int k = 0; k < 3; ++k) a.on[k] = p.dims[k];
@@ -429,7 +505,7 @@ void p8_recompose_t(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st
       a.os[1] = n[2];
     }
     a.os[2] = 1;
-    hipLaunchKernelGGL(p8::k_p8_recompose<T>, dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
+    hipLaunchKernelGGL((p8::k_p8_recompose<T, Q>), dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
     BM_HIP(hipGetLastError());
   }
 }
@@ -664,16 +740,51 @@ int p8_device(const bm_p8_s& p) { return p.device; }
 
 void p8_decompose(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st) {
   if (p.dtype == BM_F32)
-    p8_decompose_t<float>(p, x, coeff, st);
+    p8_decompose_t<float, false>(p, x, coeff, nullptr, nullptr, st);
   else
-    p8_decompose_t<double>(p, x, coeff, st);
+    p8_decompose_t<double, false>(p, x, coeff, nullptr, nullptr, st);
 }
 
 void p8_recompose(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st) {
   if (p.dtype == BM_F32)
-    p8_recompose_t<float>(p, coeff, x, st);
+    p8_recompose_t<float, false>(p, coeff, x, nullptr, nullptr, st);
   else
-    p8_recompose_t<double>(p, coeff, x, st);
+    p8_recompose_t<double, false>(p, coeff, x, nullptr, nullptr, st);
+}
+
+// Fused pipeline of this form (the paper's Sec. IV-D): the block kernel
+// writes the codes of each level's details (and, at the last level, of the
+// coarsest values); the recomposition dequantizes on load.  Codes and
+// values equal bm_p8_quantize after bm_p8_decompose, and bm_p8_recompose
+// after bm_p8_dequantize, bit for bit.
+static P8Quant p8_quant(const p8::QArgs8& q) {
+  P8Quant z{};
+  for (int s = 0; s < q.L; ++s) z.tau[s] = q.tau[s];
+  for (int s = 0; s <= q.L; ++s) z.k[s] = q.k[s];
+  return z;
+}
+
+void p8_decompose_quantize(const bm_p8_s& p, const void* x, const double* block_tol, double eta, int32_t* codes,
+                           hipStream_t st) {
+  const P8Quant z = p8_quant(p8_qargs(p, block_tol, eta, st));
+  BM_HIP(hipMemsetAsync(p.flag, 0, sizeof(int64_t), st));
+  if (p.dtype == BM_F32)
+    p8_decompose_t<float, true>(p, x, nullptr, codes, &z, st);
+  else
+    p8_decompose_t<double, true>(p, x, nullptr, codes, &z, st);
+  int64_t f = 0;
+  BM_HIP(hipMemcpyAsync(&f, p.flag, sizeof(f), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  if (f) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+}
+
+void p8_dequantize_recompose(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* x,
+                             hipStream_t st) {
+  const P8Quant z = p8_quant(p8_qargs(p, block_tol, eta, st));
+  if (p.dtype == BM_F32)
+    p8_recompose_t<float, true>(p, nullptr, x, codes, &z, st);
+  else
+    p8_recompose_t<double, true>(p, nullptr, x, codes, &z, st);
 }
 
 }  // namespace bm

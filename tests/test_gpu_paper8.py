@@ -124,3 +124,23 @@ def test_paper8_quantizer(case):
     err = np.abs(xr - xd.cpu().double().numpy())
     print("worst error / bound", float((err / vt).max()))
     assert np.all(err <= vt)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_paper8_fused_equals_unfused(case):
+    from paper_2609_00205_amd import Paper8Plan
+    shape, L, dt = case
+    print("case", _ids(case), flush=True)
+    p = Paper8Plan(shape, dtype=dt, L=L)
+    x = synth.gaussian_random_field(shape, 3.0, seed=44, dtype=np.float64)
+    vt = _vt(shape, 6) * np.abs(x).max()
+    bt = p.tolmap_from_voxels(torch.from_numpy(vt).cuda())
+    xd = torch.from_numpy(x).to(dt).cuda()
+    qu = p.quantize(p.decompose(xd), bt)
+    qf = p.decompose_quantize(xd, bt)
+    assert torch.equal(qu, qf), int((qu != qf).sum())
+    xu = p.recompose(p.dequantize(qu, bt))
+    xf = p.dequantize_recompose(qf, bt)
+    assert torch.equal(xu, xf)
+    err = np.abs(xf.cpu().double().numpy() - xd.cpu().double().numpy())
+    assert np.all(err <= vt)
