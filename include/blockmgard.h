@@ -395,6 +395,15 @@ bm_status bm_p8_decompose_quantize(bm_p8 plan, const void* x_dev, const double* 
 bm_status bm_p8_dequantize_recompose(bm_p8 plan, const int32_t* codes_dev, const double* block_tol_dev, double eta,
                                      void* x_dev, hipStream_t stream);
 
+/* Container of this form (host buffer, the layout of bm_compress): the
+ * header with flags bit 1 set (block = 8, M = 0, pad_mode = 1), the level-1
+ * block map, then the Huffman stream of the fused codes; raw data when a
+ * code does not fit in 32 bits or coding does not pay.  Capacity and size
+ * query as bm_compress; bm_decompress and bm_compressed_config read it.
+ * Synchronous. */
+bm_status bm_p8_compress(bm_p8 plan, const void* x_dev, const double* block_tol_dev, double eta, void* out_host,
+                         size_t out_capacity, size_t* out_bytes, hipStream_t stream);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 
 /* Per-level timing.  bm_timing(plan, 1) resets the counters and makes every

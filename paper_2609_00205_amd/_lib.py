@@ -86,6 +86,7 @@ _SIGS = {
     "bm_p8_dequantize": [P, P, P, C.c_double, P, P],
     "bm_p8_decompose_quantize": [P, P, P, C.c_double, P, P],
     "bm_p8_dequantize_recompose": [P, P, P, C.c_double, P, P],
+    "bm_p8_compress": [P, P, P, C.c_double, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_timing": [P, C.c_int],
     "bm_timing_get": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)],
 }

@@ -487,6 +487,24 @@ class Paper8Plan:
              _stream(stream))
         return out
 
+    def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None) -> bytearray:
+        """Container (header, block map, Huffman stream); ``decompress`` reads it."""
+        _need(x, self.dtype, self.shape, "x")
+        _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        need = C.c_size_t(0)
+        st = _stream(stream)
+        try:
+            call("bm_p8_compress", self._h, _ptr(x), _ptr(block_tol), self.eta, None, 0, C.byref(need), st)
+        except _lib.BMError as e:
+            if e.code != -5:
+                raise
+        buf = bytearray(need.value)
+        got = C.c_size_t(0)
+        view = _writable(buf)
+        call("bm_p8_compress", self._h, _ptr(x), _ptr(block_tol), self.eta, view, need.value, C.byref(got), st)
+        del view
+        return _take(buf, got.value)
+
 
 class Batch:
     """Many fields of one dtype and block size through the fused pipeline in

@@ -253,6 +253,61 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
   return true;
 }
 
+// Container of the paper's 8^3 form: the same header with flags bit 1 set
+// (block = 8, M = 0, zero fill), the level-1 block map, then the Huffman
+// stream of the codes (flat layout of bm_p8_decompose), or the raw data.
+constexpr uint32_t kFlagP8 = 2u;
+
+bool write_container_p8(bm_p8_s& p, const void* x, const double* block_tol, double eta, bool too_fine, void* out,
+                        size_t capacity, size_t* needed, hipStream_t st) {
+  int64_t dims[3], nb[3];
+  int dtype = 0, L = 0;
+  size_t esize = 0;
+  p8_info(p, dims, &dtype, &L, &esize);
+  p8_block_grid(p, nb);
+  const int64_t ntol = nb[0] * nb[1] * nb[2];
+  const int64_t nlog = dims[0] * dims[1] * dims[2];
+  std::vector<double> tol(ntol);
+  BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
+  const int32_t* codes = p8_codes(p);
+  const int64_t ncodes = p8_coeff_size(p);
+  const size_t sb = too_fine ? 0 : huffman_size(codes, ncodes, st);
+  BM_HIP(hipStreamSynchronize(st));
+  CHeader h{};
+  h.magic = kMagic;
+  h.version = 1;
+  h.dtype = dtype;
+  h.block = 8;
+  h.L = L;
+  h.M = 0;
+  h.pad_mode = 1;
+  h.ndim = 3;
+  for (int a = 0; a < 3; ++a) h.dims[a] = dims[a];
+  h.eta = eta;
+  h.ntol = ntol;
+  const size_t coded = size_t(ntol) * 8 + sb;
+  const size_t raw = size_t(nlog) * esize;
+  h.flags = kFlagP8 | ((too_fine || coded >= raw) ? 1u : 0u);
+  h.payload = (h.flags & 1u) ? raw : coded;
+  const size_t total = sizeof(CHeader) + size_t(h.payload);
+  *needed = total;
+  if (!out || capacity < total) return false;
+  uint8_t* o = static_cast<uint8_t*>(out) + sizeof(CHeader);
+  if (h.flags & 1u) {
+    BM_HIP(hipMemcpyAsync(o, x, raw, hipMemcpyDeviceToHost, st));
+    BM_HIP(hipStreamSynchronize(st));
+  } else {
+    std::memcpy(o, tol.data(), size_t(ntol) * 8);
+    huffman_encode_to(codes, ncodes, o + size_t(ntol) * 8, sb, st);
+  }
+  h.crc = 0;
+  uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
+  c = crc32_parallel(o, size_t(h.payload), c);
+  h.crc = c;
+  std::memcpy(out, &h, sizeof(h));
+  return true;
+}
+
 }  // namespace bm
 
 extern "C" {
@@ -559,6 +614,23 @@ bm_status bm_p8_dequantize_recompose(bm_p8 p, const int32_t* codes, const double
   });
 }
 
+bm_status bm_p8_compress(bm_p8 p, const void* x, const double* block_tol, double eta, void* out, size_t capacity,
+                         size_t* out_bytes, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && out_bytes, "null argument");
+    p8_check_device(p);
+    bool too_fine = false;   // codes beyond 32 bits: store the raw data
+    try {
+      bm::p8_decompose_quantize(*p, x, block_tol, eta, bm::p8_codes(*p), st);
+    } catch (const bm::Error& e) {
+      if (e.code != BM_ERANGE) throw;
+      too_fine = true;
+    }
+    if (!bm::write_container_p8(*p, x, block_tol, eta, too_fine, out, capacity, out_bytes, st))
+      bm::fail(BM_ECAPACITY, "output buffer too small");
+  });
+}
+
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out) {
   return guarded([&] {
     need(cfgs && out && nfields > 0, "null argument or empty batch");
@@ -642,6 +714,39 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
   return guarded([&] {
     need(x != nullptr, "null output");
     const CHeader h = parse(in, in_bytes);
+    if (h.flags & bm::kFlagP8) {
+      bm_p8_s* q = bm::p8_create(h.dims, h.dtype, h.L);
+      struct Guard8 {
+        bm_p8_s* q;
+        double* d = nullptr;
+        ~Guard8() {
+          if (d) (void)hipFree(d);
+          bm::p8_free(q);
+        }
+      } g8{q};
+      const uint8_t* pl = static_cast<const uint8_t*>(in) + sizeof(CHeader);
+      int64_t dims[3], nb[3];
+      int dtype = 0, L = 0;
+      size_t esize = 0;
+      bm::p8_info(*q, dims, &dtype, &L, &esize);
+      if (h.flags & 1u) {
+        if (h.payload != uint64_t(dims[0] * dims[1] * dims[2]) * esize)
+          bm::fail(BM_ECORRUPT, "raw payload size mismatch");
+        BM_HIP(hipMemcpyAsync(x, pl, size_t(h.payload), hipMemcpyHostToDevice, st));
+        BM_HIP(hipStreamSynchronize(st));
+        return;
+      }
+      bm::p8_block_grid(*q, nb);
+      const int64_t ntol = nb[0] * nb[1] * nb[2];
+      if (h.ntol != ntol || h.payload < uint64_t(ntol) * 8) bm::fail(BM_ECORRUPT, "tolerance map size mismatch");
+      BM_HIP(hipMalloc(&g8.d, size_t(ntol) * sizeof(double)));
+      BM_HIP(hipMemcpyAsync(g8.d, pl, size_t(ntol) * 8, hipMemcpyHostToDevice, st));
+      int32_t* codes = bm::p8_codes(*q);
+      bm::huffman_decode(pl + ntol * 8, size_t(h.payload) - size_t(ntol) * 8, codes, bm::p8_coeff_size(*q), st);
+      bm::p8_dequantize_recompose(*q, codes, g8.d, h.eta, x, st);
+      BM_HIP(hipStreamSynchronize(st));
+      return;
+    }
     const bm_config c = header_config(h);
     bm_plan_s* p = bm_plan_build(&c);
     struct Guard {

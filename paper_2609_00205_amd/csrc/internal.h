@@ -328,6 +328,8 @@ void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_t
                    hipStream_t st);
 void p8_decompose_quantize(const bm_p8_s& p, const void* x, const double* block_tol, double eta, int32_t* codes,
                            hipStream_t st);
+int32_t* p8_codes(bm_p8_s& p);
+void p8_info(const bm_p8_s& p, int64_t dims[3], int* dtype, int* L, size_t* esize);
 void p8_dequantize_recompose(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* x,
                              hipStream_t st);
 

@@ -397,6 +397,7 @@ struct bm_p8_s {
   std::vector<void*> grid;                 // grid[s] (s = 1..L-1): assembled coarse values, zero fill kept
   std::vector<double*> tau;                // tau[s] (s = 1..L-1): propagated block tolerances
   int64_t* flag = nullptr;                 // quantizer overflow flag
+  int32_t* codes = nullptr;                // codes of the compress path (allocated on first use)
 };
 
 namespace bm {
@@ -566,7 +567,20 @@ void p8_free(bm_p8_s* p) {
   for (double* t : p->tau)
     if (t) (void)hipFree(t);
   if (p->flag) (void)hipFree(p->flag);
+  if (p->codes) (void)hipFree(p->codes);
   delete p;
+}
+
+int32_t* p8_codes(bm_p8_s& p) {
+  if (!p.codes) BM_HIP(hipMalloc(&p.codes, size_t(p8_coeff_size(p)) * sizeof(int32_t)));
+  return p.codes;
+}
+
+void p8_info(const bm_p8_s& p, int64_t dims[3], int* dtype, int* L, size_t* esize) {
+  for (int k = 0; k < 3; ++k) dims[k] = p.dims[k];
+  *dtype = p.dtype;
+  *L = p.L;
+  *esize = p.esize;
 }
 
 void p8_block_grid(const bm_p8_s& p, int64_t nb[3]) {

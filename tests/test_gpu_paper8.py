@@ -144,3 +144,25 @@ def test_paper8_fused_equals_unfused(case):
     assert torch.equal(xu, xf)
     err = np.abs(xf.cpu().double().numpy() - xd.cpu().double().numpy())
     assert np.all(err <= vt)
+
+
+def test_paper8_container_round_trip():
+    import struct
+    import zlib
+    from paper_2609_00205_amd import Paper8Plan, api
+    shape, L = (72, 40, 100), 3
+    p = Paper8Plan(shape, dtype=torch.float32, L=L)
+    x = synth.gaussian_random_field(shape, 3.0, seed=45, dtype=np.float32)
+    vt = _vt(shape, 7) * float(np.abs(x).max())
+    bt = p.tolmap_from_voxels(torch.from_numpy(vt).cuda())
+    xd = torch.from_numpy(x).cuda()
+    buf = p.compress(xd, bt)
+    info = api.compressed_config(buf)
+    assert info["block"] == 8 and info["L"] == L and info["shape"] == shape
+    stored = struct.unpack_from("<I", buf, 88)[0]
+    assert zlib.crc32(bytes(buf[:88]) + bytes(4) + bytes(buf[92:])) == stored
+    xr = api.decompress(buf)
+    # the container's reconstruction is the fused pipeline's
+    assert torch.equal(xr, p.dequantize_recompose(p.decompose_quantize(xd, bt), bt))
+    assert np.all(np.abs(xr.cpu().double().numpy() - x.astype(np.float64)) <= vt)
+    assert len(buf) < x.nbytes / 2
