@@ -485,7 +485,7 @@ def run_turbo(args):
     choice, cands = autotune(xd, vt, slack=0.05, reps=3)
     t_tune = time.perf_counter() - t0
     plan = Plan(shape, dtype=torch.float64, block=choice["block"] if choice["L"] else 17, L=choice["L"],
-                M=choice["M"])
+                M=choice["M"], nested=choice["nested"])
     bt = plan.tolmap_from_voxels(vt)
     strict = float((bt <= 1e-6 * sc * (1 + 1e-12)).double().mean())
     codes = torch.empty(plan.coeff_shape, dtype=torch.int32, device="cuda")

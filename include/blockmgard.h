@@ -313,13 +313,14 @@ typedef struct {
   int status;             /* BM_OK, or BM_ERANGE: codes overflow, stored raw */
   double ms;              /* fused decompose + quantize, median of the repetitions */
   double ratio;           /* raw bytes / container bytes at the given tolerances */
+  int nested;             /* 1: the nested block schedule (bm_config.nested) */
 } bm_candidate;
 
 /* Chooses block size and level split for field x (device, logical dims and
  * dtype of *in) under a per-voxel absolute tolerance (device, logical dims,
  * FP64).  Candidates: pure global M = 1..6; b in {9, 17, 33} with L = 1..4 and
- * M = 0..4; those the dims admit (a valid plan padding the volume by at most
- * 1/8).  Each is run: median time of `reps` fused decompose + quantize runs
+ * M = 0..4, in the plain schedule and, for L >= 2, in the nested one; those
+ * the dims admit (a valid plan padding the volume by at most 1/8).  Each is run: median time of `reps` fused decompose + quantize runs
  * and the exact Huffman-coded size.  The fastest candidate whose ratio is at
  * least (1 - slack) times the best ratio wins; *out is *in with block, L, M
  * set.  cands (optional, room for cap entries) receives the measured table

@@ -356,7 +356,7 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
              pad_mode: str = "clamp", eta: Optional[float] = None, stream=None, budget_ms: Optional[float] = None):
     """Measured choice of (block, L, M) for field x under the per-voxel absolute
     tolerance voxel_tol (FP64, same shape).  Returns (choice, candidates):
-    choice = {"block", "L", "M"}; candidates = the measured table.
+    choice = {"block", "L", "M", "nested"}; candidates = the measured table.
 
     budget_ms: choose by the rule of Algorithm 1 instead (most global levels,
     then fewest block levels, among the candidates whose fused decompose +
@@ -383,8 +383,9 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
             _lib.check(st)
         fits = st == 0
     cands = [{"block": table[i].block, "L": table[i].L, "M": table[i].M, "status": table[i].status,
-              "ms": table[i].ms, "ratio": table[i].ratio} for i in range(min(n.value, cap))]
-    choice = {"block": out.block, "L": out.L, "M": out.M}
+              "ms": table[i].ms, "ratio": table[i].ratio, "nested": bool(table[i].nested)}
+             for i in range(min(n.value, cap))]
+    choice = {"block": out.block, "L": out.L, "M": out.M, "nested": bool(out.nested)}
     if fits is not None:
         choice["fits"] = fits
     return choice, cands

@@ -88,11 +88,12 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
   std::vector<bm_candidate> cands;
   int64_t nlog = 1;
   for (int a = 0; a < in.ndim; ++a) nlog *= in.dims[a];
-  auto consider = [&](int block, int L, int M) {
+  auto consider = [&](int block, int L, int M, int nested) {
     bm_config c = in;
     c.block = block;
     c.L = L;
     c.M = M;
+    c.nested = nested;
     // admissible: the plan exists and pads the volume by at most 1/8
     bm_plan_s* probe = nullptr;
     try {
@@ -107,13 +108,17 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
     k.block = block;
     k.L = L;
     k.M = M;
+    k.nested = nested;
     measure(c, x, voxel_tol, reps, k, st);
     cands.push_back(k);
   };
-  for (int M = 1; M <= 6; ++M) consider(0, 0, M);
+  for (int M = 1; M <= 6; ++M) consider(0, 0, M, 0);
   for (int block : {9, 17, 33})
     for (int L = 1; L <= 4; ++L)
-      for (int M = 0; M <= 4; ++M) consider(block, L, M);
+      for (int M = 0; M <= 4; ++M) {
+        consider(block, L, M, 0);
+        if (L >= 2) consider(block, L, M, 1);   // (a plan the schedule does not admit is skipped)
+      }
   if (cands.empty()) fail(BM_EINVAL, "no admissible (block, L, M) for these dims");
   const bm_candidate* win = nullptr;
   if (budget) {
@@ -138,6 +143,7 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
   out.block = win->block == 0 ? in.block : win->block;
   out.L = win->L;
   out.M = win->M;
+  out.nested = win->nested;
   return cands;
 }
 

@@ -37,10 +37,12 @@ def test_autotune_rule_and_bounds(dt):
     best = max(c["ratio"] for c in cands)
     elig = [c for c in cands if c["ratio"] >= 0.95 * best]
     win = min(elig, key=lambda c: c["ms"])
-    assert (choice["L"], choice["M"]) == (win["L"], win["M"])
+    assert (choice["L"], choice["M"], choice["nested"]) == (win["L"], win["M"], win["nested"])
     if win["L"] > 0:
         assert choice["block"] == win["block"]
-    p = Plan(shape, dtype=dt, block=choice["block"] if choice["L"] else 17, L=choice["L"], M=choice["M"])
+    assert any(c["nested"] for c in cands)                      # the nested schedule is searched too
+    p = Plan(shape, dtype=dt, block=choice["block"] if choice["L"] else 17, L=choice["L"], M=choice["M"],
+             nested=choice["nested"])
     bt = p.tolmap_from_voxels(vtd)
     xr = decompress(p.compress(xd, bt))
     err = (xr.double() - xd.double()).abs()
