@@ -520,39 +520,51 @@ __global__ void k_batch_propagate(const PrepField* F, const int64_t* first, int 
 // (first face) takes the block and the one before, 1 the block alone, 2
 // (last face) the block and the one after.  32-bit index arithmetic (a
 // level has fewer than 2^32 / 27 blocks).
+// one task of k_batch_tables: task i of field P
+__device__ inline void table_task(const PrepField& P, int s, uint32_t i) {
+  const int li = s > 0 ? s - 1 : P.L - 1;
+  const QTab& T = s > 0 ? P.tab[li] : P.tab[kCoarseSlotHost];
+  const double kap = s > 0 ? P.kap[li] : P.kapc;
+  const double* tau = P.tau[li];
+  const uint32_t blk = i / 27u;
+  const int c = int(i - blk * 27u);
+  const int cls[3] = {c / 9, (c / 3) % 3, c % 3};
+  const uint32_t n0 = uint32_t(P.nb[li][0]), n1 = uint32_t(P.nb[li][1]), n2 = uint32_t(P.nb[li][2]);
+  const uint32_t t = blk / n2;
+  const uint32_t b[3] = {t / n1, t - (t / n1) * n1, blk - t * n2};
+  const uint32_t nb[3] = {n0, n1, n2};
+  uint32_t lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (cls[d] == 0 && b[d] > 0) ? b[d] - 1 : b[d];
+    hi[d] = (cls[d] == 2 && b[d] + 1 < nb[d]) ? b[d] + 1 : b[d];
+  }
+  // each axis spans at most two blocks: the eight corners of the box
+  // (repeated where lo == hi) are loaded together, then reduced
+  double tv[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    tv[j] = tau[(((j & 4) ? hi[0] : lo[0]) * n1 + ((j & 2) ? hi[1] : lo[1])) * n2 + ((j & 1) ? hi[2] : lo[2])];
+  const double m = fmin(fmin(fmin(tv[0], tv[1]), fmin(tv[2], tv[3])), fmin(fmin(tv[4], tv[5]), fmin(tv[6], tv[7])));
+  const double d = m * kap, iv = 1.0 / d;
+  const_cast<double*>(T.cdel)[i] = d;
+  const_cast<double*>(T.cinv)[i] = iv;
+  if (c == 13) {
+    const_cast<double*>(T.del)[blk] = d;
+    const_cast<double*>(T.inv)[blk] = iv;
+  }
+}
+
 __global__ void k_batch_tables(const PrepField* F, const int64_t* first, int nf, int64_t ntot, int s) {
+  if (nf == 1) {
+    // one field: its record is the same for every lane (scalar loads)
+    for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT)
+      table_task(F[0], s, uint32_t(k - first[0]));
+    return;
+  }
   for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT) {
     const int f = field_of(first, nf, k);
-    const PrepField& P = F[f];
-    const int li = s > 0 ? s - 1 : P.L - 1;
-    const QTab& T = s > 0 ? P.tab[li] : P.tab[kCoarseSlotHost];
-    const double kap = s > 0 ? P.kap[li] : P.kapc;
-    const double* tau = P.tau[li];
-    const uint32_t i = uint32_t(k - first[f]);
-    const uint32_t blk = i / 27u;
-    const int c = int(i - blk * 27u);
-    const int cls[3] = {c / 9, (c / 3) % 3, c % 3};
-    const uint32_t n0 = uint32_t(P.nb[li][0]), n1 = uint32_t(P.nb[li][1]), n2 = uint32_t(P.nb[li][2]);
-    const uint32_t t = blk / n2;
-    const uint32_t b[3] = {t / n1, t - (t / n1) * n1, blk - t * n2};
-    const uint32_t nb[3] = {n0, n1, n2};
-    uint32_t lo[3], hi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = (cls[d] == 0 && b[d] > 0) ? b[d] - 1 : b[d];
-      hi[d] = (cls[d] == 2 && b[d] + 1 < nb[d]) ? b[d] + 1 : b[d];
-    }
-    double m = INFINITY;
-    for (uint32_t z = lo[0]; z <= hi[0]; ++z)
-      for (uint32_t y = lo[1]; y <= hi[1]; ++y)
-        for (uint32_t x = lo[2]; x <= hi[2]; ++x) m = fmin(m, tau[(z * n1 + y) * n2 + x]);
-    const double d = m * kap, iv = 1.0 / d;
-    const_cast<double*>(T.cdel)[i] = d;
-    const_cast<double*>(T.cinv)[i] = iv;
-    if (c == 13) {
-      const_cast<double*>(T.del)[blk] = d;
-      const_cast<double*>(T.inv)[blk] = iv;
-    }
+    table_task(F[f], s, uint32_t(k - first[f]));
   }
 }
 
