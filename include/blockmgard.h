@@ -110,7 +110,8 @@ typedef struct {
  * gains and device workspace.  The padded length of every axis is the
  * smallest n' >= n on which the L block levels tile exactly and each of the
  * M global levels halves an odd length (lengths <= 2 are left alone).
- * Errors: BM_EINVAL (bad shape/b/L/M/eta, null), BM_ENOMEM, BM_EHIP. */
+ * Errors: BM_EINVAL (bad shape/b/L/M/eta, a padded grid of more than 2^40
+ * nodes, null), BM_ENOMEM, BM_EHIP. */
 bm_status bm_plan_create(const bm_config* cfg, bm_plan* out);
 
 /* Free a plan and its workspace.  NULL is accepted. */
@@ -355,7 +356,8 @@ bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* v
  * other, then the coarsest values (dims 5 n_L / 8).  The plan owns the
  * assembled grids between levels: calls on one plan must not overlap.
  * Stream-ordered and asynchronous.  Errors: BM_EINVAL (dims outside
- * [1, 2^31], dtype, L outside [1, 8], null), BM_ENOMEM, BM_EHIP. */
+ * [1, 2^31] or a level-1 grid of more than 2^40 nodes, dtype, L outside
+ * [1, 8], null), BM_ENOMEM, BM_EHIP. */
 typedef struct bm_p8_s* bm_p8;
 bm_status bm_p8_create(const int64_t dims[3], int dtype, int L, bm_p8* out);
 bm_status bm_p8_destroy(bm_p8 plan);

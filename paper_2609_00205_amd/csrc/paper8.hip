@@ -518,6 +518,8 @@ bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L) {
   if (L < 1 || L > 8) fail(BM_EINVAL, "L must lie in [1, 8]");
   for (int k = 0; k < 3; ++k)
     if (dims[k] < 1 || dims[k] > (int64_t(1) << 31)) fail(BM_EINVAL, "dims must lie in [1, 2^31]");
+  if (up8(dims[1]) * up8(dims[2]) > (int64_t(1) << 40) / up8(dims[0]))
+    fail(BM_EINVAL, "grid of more than 2^40 nodes");
   auto* p = new bm_p8_s();
   try {
     BM_HIP(hipGetDevice(&p->device));

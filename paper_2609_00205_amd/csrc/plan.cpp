@@ -280,6 +280,13 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
   for (int a = 0; a < c->ndim; ++a) d[3 - c->ndim + a] = c->dims[a];
   for (int a = 0; a < 3; ++a)
     if (d[a] < 1 || d[a] > (int64_t(1) << 31)) fail(BM_EINVAL, "dims must lie in [1, 2^31]");
+  {
+    // element counts stay far from int64 overflow (each padded length is at
+    // most about 2^31, so the product of two fits)
+    int64_t pd[3];
+    for (int a = 0; a < 3; ++a) pd[a] = padded_length(d[a], c->L > 0 ? c->block : 0, c->L, c->M, c->nested != 0);
+    if (pd[1] * pd[2] > (int64_t(1) << 40) / pd[0]) fail(BM_EINVAL, "padded grid of more than 2^40 nodes");
+  }
   int dev = 0;
   BM_HIP(hipGetDevice(&dev));
   auto p = new bm_plan_s();

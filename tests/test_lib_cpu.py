@@ -52,10 +52,20 @@ def test_bad_config_rejected_before_touching_a_device(lib):
                 BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 0, 0, 0, 0.1),      # no levels
                 BMConfig(3, (C.c_int64 * 3)(9, 9, 9), 0, 17, 1, 2, 0, 0.7),      # eta out of range
                 BMConfig(3, (C.c_int64 * 3)(40, 40, 40), 0, 17, 3, 1, 0, 0.1, 1),  # nested: level 3 of 5 nodes
-                BMConfig(3, (C.c_int64 * 3)(40, 40, 40), 0, 17, 1, 1, 0, 0.1, 2)]:  # nested must be 0 or 1
+                BMConfig(3, (C.c_int64 * 3)(40, 40, 40), 0, 17, 1, 1, 0, 0.1, 2),   # nested must be 0 or 1
+                BMConfig(3, (C.c_int64 * 3)(1 << 31, 1 << 31, 1 << 31), 0, 17, 1, 2, 0, 0.1),   # > 2^40 nodes
+                BMConfig(3, (C.c_int64 * 3)(1 << 14, 1 << 14, 1 << 13), 0, 17, 1, 2, 0, 0.1)]:  # 2^41 nodes
         assert lib.bm_plan_create(C.byref(cfg), C.byref(h)) == -1
         assert len(lib.bm_last_error()) > 0
     assert lib.bm_plan_create(None, C.byref(h)) == -1
+
+
+def test_bad_paper8_config_rejected_before_touching_a_device(lib):
+    h = C.c_void_p()
+    for dims, dt, L in [((0, 8, 8), 0, 1), ((8, 8, 8), 3, 1), ((8, 8, 8), 0, 0), ((8, 8, 8), 0, 9),
+                        ((1 << 31, 1 << 31, 1 << 31), 0, 1), ((1 << 14, 1 << 14, 1 << 13), 0, 1)]:
+        assert lib.bm_p8_create((C.c_int64 * 3)(*dims), dt, L, C.byref(h)) == -1, dims
+        assert len(lib.bm_last_error()) > 0
 
 
 def test_corrupt_container_rejected(lib):
