@@ -140,8 +140,14 @@ def test_tau_global_is_min_of_last_local_level():
     d = roi.node_delta(h, tol, 0.0)
     lev = mgard.node_level(h.shape_p, 2, 1)
     A3 = roi.level_gains(h)[2]
-    w3 = (9 ** 3 - 5 ** 3) / 33 ** 3          # level-3 coefficients of the 33^3 grid
-    assert np.allclose(d[lev == 3], 1e-6 * 2 * w3 / A3)
+    # level-3 share: its count over the 33^3 grid, renormalised after the
+    # coarsest share 5^3 / 33^3 is raised to the floor 1/(64 T), T = 4
+    floor = 1.0 / 256.0
+    raw = [(33 ** 3 - 17 ** 3) / 33 ** 3, (17 ** 3 - 9 ** 3) / 33 ** 3, (9 ** 3 - 5 ** 3) / 33 ** 3, floor]
+    w3 = raw[2] / sum(raw)
+    got = d[lev == 3]
+    assert got.size == 9 ** 3 - 5 ** 3
+    np.testing.assert_allclose(got, 1e-6 * 2 * w3 / A3, rtol=1e-13, atol=0)
 
 
 def test_budget_shares_tighten_as_levels_coarsen():
