@@ -111,11 +111,16 @@ typedef struct {
  * smallest n' >= n on which the L block levels tile exactly and each of the
  * M global levels halves an odd length (lengths <= 2 are left alone).
  * Errors: BM_EINVAL (bad shape/b/L/M/eta, a padded grid of more than 2^40
- * nodes, null), BM_ENOMEM, BM_EHIP. */
+ * nodes, null), BM_EUNSUPPORTED (a global level would run line solves on an
+ * axis of more than 1151 nodes, i.e. more than 576 coarse nodes per line:
+ * add a block level), BM_ENOMEM, BM_EHIP. */
 bm_status bm_plan_create(const bm_config* cfg, bm_plan* out);
 
 /* Free a plan and its workspace.  NULL is accepted. */
 bm_status bm_plan_destroy(bm_plan plan);
+
+/* The configuration the plan was built from (a batch field's L resolved). */
+bm_status bm_plan_config(bm_plan plan, bm_config* cfg);
 
 /* Padded dims n' (the coefficient array's dims). */
 bm_status bm_coeff_shape(bm_plan plan, int64_t padded_dims[3]);
@@ -133,7 +138,9 @@ bm_status bm_level_gains(bm_plan plan, double* gains);
 /* coeff = D(x).  x: device, logical dims, dtype of the plan.  coeff: device,
  * padded dims, same dtype; every node holds its own coefficient ("in
  * place"): the detail of the level at which the node leaves the grid, or
- * the coarsest value.  Asynchronous on stream. */
+ * the coarsest value.  Asynchronous on stream; the data are not checked (a
+ * NaN or Inf in x gives non-finite coefficients, which the quantizing calls
+ * report as BM_ENONFINITE). */
 bm_status bm_decompose(bm_plan plan, const void* x, void* coeff, hipStream_t stream);
 
 /* x = R(coeff) = D^{-1}(coeff), cropped to the logical dims.  Asynchronous. */
@@ -175,15 +182,21 @@ bm_status bm_tolmap_from_voxels(bm_plan plan, const double* voxel_tol, double* b
 
 /* ---- quantization (Sec. IV-C, IV-D) ------------------------------------- */
 
-/* codes = rint(c * (1/Delta)) per node, Delta = tau * 2 (1 - eta) / (T A_s)
- * for a detail of level s and tau * 2 (1 - eta) / T for a coarsest value,
- * T = L + M + 1.  tau is the node's propagated block tolerance at local
- * levels (min over the level's blocks that contain it, with block maps
- * propagated by Eq. 2) and tau_global = min over the last local level at
- * global levels.  coeff: device, padded dims; block_tol: device double map
- * from the calls above; codes: device int32, padded dims.  If stats is
- * non-NULL the call synchronizes the stream and fills it; a code beyond
- * int32 range then returns BM_ERANGE. */
+/* codes = rint(c * (1/Delta)) per node (FP64), with Delta = 2 tau (1 - eta) w_s / A_s
+ * for a detail of level s and 2 tau (1 - eta) w_c for a coarsest value
+ * (Sec. II-B level-dependent budget, Sec. IV-C).  A_s = bm_level_gains.
+ * Shares: w_s = (details of level s) / (padded node count) for a block level;
+ * the M global levels split (their details) / (node count) equally; w_c =
+ * (coarsest values) / (node count); every share below 1/(64 T), T = L + M + 1,
+ * is raised to it and the shares are then divided by their sum.  tau is the
+ * node's propagated block tolerance at block levels (min over the level's
+ * blocks that contain it, block maps propagated by Eq. 2), tau_global = min
+ * over the last block level at global levels (and for the coarsest values
+ * when M > 0; with M = 0 they keep their node's tau).  coeff: device, padded
+ * dims; block_tol: device double map from the calls above; codes: device
+ * int32, padded dims.  If stats is non-NULL the call synchronizes the stream
+ * and fills it; then a NaN or infinite coefficient returns BM_ENONFINITE and
+ * a code beyond int32 range BM_ERANGE. */
 bm_status bm_quantize_roi(bm_plan plan, const void* coeff, const double* block_tol, int32_t* codes,
                           bm_qstats* stats, hipStream_t stream);
 
@@ -216,8 +229,10 @@ bm_status bm_dequantize_delta(bm_plan plan, const int32_t* codes, const double* 
  * block levels write codes straight from on-chip memory; global-level
  * details are quantized as they are produced.  codes (device int32, padded
  * dims) equal bm_decompose followed by bm_quantize_roi with the same map.
- * If stats is non-NULL the call synchronizes and returns BM_ERANGE for a
- * code beyond int32 (n_outliers and max_abs_code are then -1: not counted). */
+ * If stats is non-NULL the call synchronizes and returns BM_ENONFINITE when
+ * x holds a NaN or Inf (it reaches the coefficient of its own node), else
+ * BM_ERANGE for a code beyond int32 (n_outliers and max_abs_code are -1:
+ * not counted).  Without stats nothing is checked. */
 bm_status bm_decompose_quantize(bm_plan plan, const void* x, const double* block_tol, int32_t* codes,
                                 bm_qstats* stats, hipStream_t stream);
 
@@ -257,7 +272,8 @@ bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int
  * zlib) of the header with its CRC field zeroed followed by the payload.  If
  * the coded form is not smaller than the raw data the raw bytes are stored
  * instead (Sec. V-F).  Synchronous.  BM_ECAPACITY sets *out_bytes to the
- * size needed (that call plans the stream's size but does not encode it). */
+ * size needed (that call plans the stream's size but does not encode it).
+ * BM_ENONFINITE: NaN or Inf in x or in block_tol (nothing is written). */
 bm_status bm_compress(bm_plan plan, const void* x, const double* block_tol, void* out,
                       size_t capacity, size_t* out_bytes, hipStream_t stream);
 
@@ -268,7 +284,9 @@ bm_status bm_compress(bm_plan plan, const void* x, const double* block_tol, void
 bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg);
 
 /* Rebuild x (device, logical dims and dtype of the stored config) from a
- * buffer written by bm_compress.  Synchronous.  Errors: BM_ECORRUPT. */
+ * buffer written by bm_compress.  Synchronous.  Errors: BM_ECORRUPT (bad
+ * magic, version, size or CRC, or a stored block tolerance that is not
+ * positive and finite). */
 bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t stream);
 
 /* ---- many fields (the paper's batched multi-field workloads, Sec. V) ------- */
@@ -283,7 +301,9 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
  * (bm_batch_plan borrows it: coefficient shapes, tolerance maps); a batch is
  * used from one stream at a time.  Errors: BM_EINVAL (mixed dtype or block
  * size, null pointers), BM_EUNSUPPORTED (b = 33 with block levels),
- * BM_ENOMEM. */
+ * BM_ENOMEM.  A field config with L = -1 takes the most block levels its
+ * logical dims tile without padding (at least 1; b = 9 or 17 only);
+ * bm_plan_config of the field's bm_batch_plan returns the resolved config. */
 typedef struct bm_batch_s* bm_batch;
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out);
 bm_status bm_batch_destroy(bm_batch batch);
@@ -292,7 +312,8 @@ bm_status bm_batch_plan(bm_batch batch, int field, bm_plan* out);
 /* codes[f] = the fused decompose + ROI quantize of x[f] with block_tol[f]
  * (arrays of nfields device pointers; layouts as bm_decompose_quantize).
  * Asynchronous, unless n_overflow is non-null: then the call waits and
- * stores the number of fields whose codes did not fit in 32 bits. */
+ * stores the number of fields whose codes did not fit in 32 bits, or
+ * returns BM_ENONFINITE if a field's data hold a NaN or Inf. */
 bm_status bm_batch_decompose_quantize(bm_batch batch, const void* const* x, const double* const* block_tol,
                                       int32_t* const* codes, int use_graph, int* n_overflow, hipStream_t stream);
 

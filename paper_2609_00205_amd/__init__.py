@@ -5,7 +5,7 @@ behind the C ABI in ``include/blockmgard.h``); this package only marshals
 arguments.  Importing it does not load the library; the first call does,
 and raises if the library has not been built.
 """
-__all__ = ["Plan", "Paper8Plan", "Batch", "autotune", "max_block_levels", "decompress", "compressed_config", "huffman_encode",
+__all__ = ["Plan", "Paper8Plan", "Batch", "autotune", "decompress", "compressed_config", "huffman_encode",
            "huffman_decode", "DecomposeFn", "RecomposeFn"]
 
 

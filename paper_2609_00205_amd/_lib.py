@@ -44,6 +44,7 @@ _SIGS = {
     "bm_plan_create": [C.POINTER(BMConfig), C.POINTER(P)],
     "bm_plan_destroy": [P],
     "bm_coeff_shape": [P, C.POINTER(C.c_int64)],
+    "bm_plan_config": [P, C.POINTER(BMConfig)],
     "bm_block_grid": [P, C.POINTER(C.c_int64)],
     "bm_level_gains": [P, C.POINTER(C.c_double)],
     "bm_decompose": [P, P, P, P],

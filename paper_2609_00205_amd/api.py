@@ -391,14 +391,6 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
     return choice, cands
 
 
-def max_block_levels(shape: Sequence[int], block: int) -> int:
-    """The most block levels a shape tiles without padding (at least 1)."""
-    L = 1
-    while all(((n - 1) >> L) >= block - 1 and (n - 1) % ((block - 1) << L) == 0 for n in shape):
-        L += 1
-    return L
-
-
 class Paper8Plan:
     """The paper's own block form: disjoint 8^3 blocks, L block levels whose
     5^3 coarse outputs are re-assembled into the next level's blocks.
@@ -513,15 +505,14 @@ class Batch:
     optionally captured once in a HIP graph and replayed.
 
     L: per-field block levels (default: the most each shape tiles without
-    padding); M: global levels (int or per field).
+    padding, chosen by the library); M: global levels (int or per field).
     """
 
     def __init__(self, shapes: Sequence[Sequence[int]], dtype=torch.float32, block: int = 17, L=None, M=0,
                  pad_mode: str = "clamp", eta: Optional[float] = None, device=None):
         shapes = [tuple(int(v) for v in sh) for sh in shapes]
         nf = len(shapes)
-        Ls = [max_block_levels(sh, block) for sh in shapes] if L is None else (
-            [int(L)] * nf if isinstance(L, int) else [int(v) for v in L])
+        Ls = [-1] * nf if L is None else ([int(L)] * nf if isinstance(L, int) else [int(v) for v in L])
         Ms = [int(M)] * nf if isinstance(M, int) else [int(v) for v in M]
         self.dtype = dtype
         self.eta = DEFAULT_ETA[dtype] if eta is None else float(eta)
@@ -539,7 +530,9 @@ class Batch:
         for i in range(nf):
             ph = C.c_void_p()
             call("bm_batch_plan", h, i, C.byref(ph))
-            self.plans.append(Plan._borrow(ph, cfgs[i], self.device))
+            resolved = BMConfig()
+            call("bm_plan_config", ph, C.byref(resolved))
+            self.plans.append(Plan._borrow(ph, resolved, self.device))
         self._graph_stream = None
 
     def __len__(self):
@@ -572,10 +565,17 @@ class Batch:
         cur.wait_stream(side)
         return r
 
+    def _same_len(self, **lists):
+        # the library reads one pointer per field from every array
+        for name, v in lists.items():
+            if v is not None and len(v) != len(self.plans):
+                raise ValueError(f"{name}: {len(v)} entries for a batch of {len(self.plans)} fields")
+
     def decompose_quantize(self, xs, block_tols, codes=None, use_graph: bool = False, check: bool = False,
                            stream=None):
         """codes[f] = fused decompose + ROI quantize of xs[f]; with check, the
         number of fields whose codes overflowed int32 is returned as well."""
+        self._same_len(xs=xs, block_tols=block_tols, codes=codes)
         for p, x, t in zip(self.plans, xs, block_tols):
             _need(x, p.dtype, p.shape, "x")
             _need(t, torch.float64, p.block_grid, "block_tol")
@@ -590,6 +590,7 @@ class Batch:
         return (codes, nbad.value) if check else codes
 
     def dequantize_recompose(self, codes, block_tols, outs=None, use_graph: bool = False, stream=None):
+        self._same_len(codes=codes, block_tols=block_tols, outs=outs)
         for p, c, t in zip(self.plans, codes, block_tols):
             _need(c, torch.int32, p.coeff_shape, "codes")
             _need(t, torch.float64, p.block_grid, "block_tol")
@@ -603,6 +604,7 @@ class Batch:
 
     def compress(self, xs, block_tols, use_graph: bool = False, stream=None) -> list:
         nf = len(self.plans)
+        self._same_len(xs=xs, block_tols=block_tols)
         for p, x, t in zip(self.plans, xs, block_tols):
             _need(x, p.dtype, p.shape, "x")
             _need(t, torch.float64, p.block_grid, "block_tol")

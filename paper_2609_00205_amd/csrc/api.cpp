@@ -169,6 +169,17 @@ bm_config header_config(const CHeader& h) {
   return c;
 }
 
+// The stored block tolerance map must hold positive, finite tolerances (a
+// container whose CRC matches can still carry a bad map if it was written
+// by other code): BM_ECORRUPT otherwise.
+void check_stored_tol(const uint8_t* pl, int64_t ntol) {
+  for (int64_t i = 0; i < ntol; ++i) {
+    double t;
+    std::memcpy(&t, pl + 8 * i, 8);
+    if (!(t > 0) || !std::isfinite(t)) bm::fail(BM_ECORRUPT, "stored block tolerance not positive and finite");
+  }
+}
+
 // header checks; the CRC over header and payload only when check_crc
 CHeader parse(const void* in, size_t in_bytes, bool check_crc = true) {
   if (!in || in_bytes < sizeof(CHeader)) bm::fail(BM_ECORRUPT, "buffer shorter than the container header");
@@ -321,6 +332,13 @@ bm_status bm_plan_create(const bm_config* cfg, bm_plan* out) {
 
 bm_status bm_plan_destroy(bm_plan plan) {
   return guarded([&] { bm_plan_free(plan); });
+}
+
+bm_status bm_plan_config(bm_plan p, bm_config* cfg) {
+  return guarded([&] {
+    need(p && cfg, "null argument");
+    *cfg = p->cfg;
+  });
 }
 
 bm_status bm_coeff_shape(bm_plan p, int64_t padded_dims[3]) {
@@ -714,6 +732,11 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
   return guarded([&] {
     need(x != nullptr, "null output");
     const CHeader h = parse(in, in_bytes);
+    if (!(h.flags & 1u)) {
+      // the stored map is checked before any plan or device buffer is made
+      if (h.ntol < 1 || uint64_t(h.ntol) > h.payload / 8) bm::fail(BM_ECORRUPT, "tolerance map size mismatch");
+      check_stored_tol(static_cast<const uint8_t*>(in) + sizeof(CHeader), h.ntol);
+    }
     if (h.flags & bm::kFlagP8) {
       bm_p8_s* q = bm::p8_create(h.dims, h.dtype, h.L);
       struct Guard8 {

@@ -209,9 +209,25 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
         fail(BM_EINVAL, "all fields of a batch share dtype and block size");
       if (cfgs[f].nested)
         fail(BM_EUNSUPPORTED, "batches take the plain block schedule (nested = 0)");
-      if (cfgs[f].L > 0 && cfgs[f].block == 33)
+      bm_config c = cfgs[f];
+      if (c.L == -1) {
+        // the most block levels the logical dims tile without padding (at least 1)
+        if (c.block != 9 && c.block != 17) fail(BM_EINVAL, "L = -1 needs block 9 or 17");
+        int64_t d[3] = {1, 1, 1};
+        if (c.ndim < 1 || c.ndim > 3) fail(BM_EINVAL, "ndim must be 1, 2 or 3");
+        for (int a = 0; a < c.ndim; ++a) d[3 - c.ndim + a] = c.dims[a];
+        const int64_t q = c.block - 1;
+        c.L = 1;
+        auto tiles = [&](int L) {
+          for (int a = 0; a < 3; ++a)
+            if (((d[a] - 1) >> L) < q || (d[a] - 1) % (q << L) != 0) return false;
+          return true;
+        };
+        while (c.L < 24 && tiles(c.L)) ++c.L;
+      }
+      if (c.L > 0 && c.block == 33)
         fail(BM_EUNSUPPORTED, "batched block levels take b = 9 or 17 (a 33^3 block needs several launches)");
-      b->plans.push_back(bm_plan_build(&cfgs[f]));
+      b->plans.push_back(bm_plan_build(&c));
       b->Lmax = std::max(b->Lmax, b->plans.back()->L);
     }
     b->block = cfgs[0].block;
@@ -258,6 +274,8 @@ int batch_overflows(bm_batch_s& b, std::vector<int>& bad, hipStream_t st) {
   BM_HIP(hipStreamSynchronize(st));
   bad.assign(nf, 0);
   int n = 0;
+  for (int f = 0; f < nf; ++f)
+    if (flags[f] & kFlagNonFinite) fail(BM_ENONFINITE, "field " + std::to_string(f) + ": NaN or Inf in the data");
   for (int f = 0; f < nf; ++f)
     if (flags[f]) {
       bad[f] = 1;

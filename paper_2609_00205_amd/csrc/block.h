@@ -136,13 +136,15 @@ __device__ inline void column_class(const double* tab, int64_t blk, int y, int x
 template <int B>
 __device__ inline int zcase(int z) { return z == 0 ? 0 : (z == B - 1 ? 2 : 1); }
 
-// q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag.
-// skip: a placeholder (zero) is written instead and nothing is checked.
+// q = rint(c * (1/Delta)) in FP64.  A code outside int32 sets bit kFlagRange
+// of bad, a coefficient that is NaN or infinite (non-finite data) sets
+// kFlagNonFinite; either way 0 is written.  skip: a placeholder (zero) is
+// written instead and nothing is checked.
 template <typename T>
-__device__ inline int32_t quant(T c, double inv, bool skip, bool& bad) {
+__device__ inline int32_t quant(T c, double inv, bool skip, unsigned& bad) {
   const double v = rint(mul_rn(double(c), inv));
   const bool ok = fabs(v) <= 2147483647.0;
-  bad |= !ok && !skip;
+  if (!ok && !skip) bad |= code_flag(double(c));
   return (ok && !skip) ? int32_t(v) : 0;
 }
 

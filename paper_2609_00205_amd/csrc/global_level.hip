@@ -65,7 +65,7 @@ template <typename T>
 __device__ inline int32_t quant_g(T c, double inv, int64_t* flag) {
   const double v = rint(mul_rn(double(c), inv));
   if (!(fabs(v) <= 2147483647.0)) {
-    atomicOr(reinterpret_cast<unsigned long long*>(flag), 1ull);
+    atomicOr(reinterpret_cast<unsigned long long*>(flag), (unsigned long long)code_flag(double(c)));
     return 0;
   }
   return int32_t(v);
@@ -899,7 +899,7 @@ void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, in
     stats->n_codes = p.pdims[0] * p.pdims[1] * p.pdims[2];
     stats->n_outliers = -1;
     stats->max_abs_code = -1;
-    if (f) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+    check_code_flag(f, "tolerance too small for the data");
   }
 }
 

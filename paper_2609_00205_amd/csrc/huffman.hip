@@ -3,7 +3,9 @@
 // codebook, encoding; Sec. IV-B).
 //
 // Symbols: q + 2^15 for |q| < 2^15, else the escape symbol 0 with the
-// (raster index, q) pair kept as an outlier.  Code lengths come from
+// value q kept as an outlier, in raster order: an outlier's position is
+// that of its escape symbol, and per-chunk outlier offsets locate the
+// outliers of each chunk (stream version 3).  Code lengths come from
 // Huffman's algorithm merging the two smallest (weight, smallest symbol in
 // the subtree) keys, so the tree is unique; lengths above 32 are cut to 32
 // and the longest codes below 32 are lengthened (largest symbol first) until

@@ -74,6 +74,14 @@ __device__ inline T cell_mean(int dz, int dy, int dx, F rd) {
   return s * T(0.125);
 }
 
+// Bits of a quantizer's error flag: a code beyond int32 (tolerance too small
+// for the data), and a NaN or infinite coefficient (non-finite data: a NaN or
+// Inf input reaches the coefficient of its own node at some level).
+constexpr unsigned kFlagRange = 1u, kFlagNonFinite = 2u;
+__device__ inline unsigned code_flag(double c) { return isfinite(c) ? kFlagRange : kFlagNonFinite; }
+// Host side: BM_ENONFINITE or BM_ERANGE for a non-zero flag word.
+void check_code_flag(int64_t f, const char* what);
+
 __host__ __device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
 __host__ __device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
 

@@ -223,7 +223,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
         }
       } else {
         int32_t* dst = a.codes + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
-        bool bad = false;
+        unsigned bad = 0;
 #pragma unroll
         for (int z = 1; z < B - 1; z += 2) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], false, bad);
         if (!later) {   // even planes in one branch
@@ -231,7 +231,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
           for (int z = 0; z < B - 1; z += 2) dst[z * a.cs0] = quant(v[z], iv[zcase<B>(z)], ecol, bad);
           if (lastz) dst[(B - 1) * a.cs0] = quant(v[B - 1], iv[2], ecol, bad);
         }
-        if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+        if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
       }
     }
     // correction, z pass: w is zero on the coarse nodes
@@ -280,11 +280,11 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       double ci[3];
       column_class<B>(a.ctab.cinv, blk, y, x, ci);
       int32_t* dst = a.codes + oz * a.cs[0] + gy * a.cs[1] + gx * a.cs[2];
-      bool bad = false;
+      unsigned bad = 0;
 #pragma unroll
       for (int j = 0; j < MC - 1; ++j) dst[2 * j * a.cs0] = quant(c[j], ci[zcase<B>(2 * j)], false, bad);
       if (lastz) dst[(B - 1) * a.cs0] = quant(c[MC - 1], ci[2], false, bad);
-      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
     } else if (!a.fuse && !a.nest) {
       T* cdst = a.cout + (oz >> 1) * int64_t(a.cpl) + (gy >> 1) * a.cn[2] + (gx >> 1);
 #pragma unroll
@@ -303,7 +303,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
       const double inv = Q ? *a.nqinv : 0.0;
       T in[MC];
       column_interp<T, MC>(p, q, [&](int J, int P, int K) { return CC[((2 * J) * MC + 2 * P) * MC + 2 * K]; }, in);
-      bool bad = false;
+      unsigned bad = 0;
 #pragma unroll
       for (int j = 0; j < MC; ++j) {
         if (j == MC - 1 && !lastz) continue;
@@ -315,7 +315,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
         else
           a.coeff[o] = d;
       }
-      if (Q && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+      if (Q && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
     }
     // The next level's load vector 3 P^T M (per axis) at its coarse nodes in
     // this block, from the block's own coarse values only: rows on the block

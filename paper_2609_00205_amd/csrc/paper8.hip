@@ -100,10 +100,10 @@ struct Args {
 
 // q = rint(c * (1/Delta)) in FP64; a code outside int32 raises the flag
 template <typename T>
-__device__ inline int32_t quant8(T c, double inv, bool& bad) {
+__device__ inline int32_t quant8(T c, double inv, unsigned& bad) {
   const double v = rint(mul_rn(double(c), inv));
   const bool ok = fabs(v) <= 2147483647.0;
-  bad |= !ok;
+  if (!ok) bad |= code_flag(double(c));
   return ok ? int32_t(v) : 0;
 }
 
@@ -203,10 +203,10 @@ __global__ __launch_bounds__(NT) void k_p8_decompose(Args<T> a) {
     if (Q) {
       // the block's Delta of this level's details
       const double inv = 1.0 / (a.tau[(bz * a.nb[1] + by) * a.nb[2] + bx] * a.k);
-      bool bad = false;
+      unsigned bad = 0;
 #pragma unroll
       for (int z = 0; z < B; ++z) a.q[o + z * a.cs[0]] = quant8(w[z], inv, bad);
-      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
     } else {
 #pragma unroll
       for (int z = 0; z < B; ++z) a.coeff[o + z * a.cs[0]] = w[z];
@@ -225,10 +225,10 @@ __global__ __launch_bounds__(NT) void k_p8_decompose(Args<T> a) {
     if (Q && a.last) {
       // the coarsest values: codes with the block's Delta
       const double inv = 1.0 / (a.tau[(bz * a.nb[1] + by) * a.nb[2] + bx] * a.kc);
-      bool bad = false;
+      unsigned bad = 0;
 #pragma unroll
       for (int j = 0; j < MC; ++j) a.qc[o + j * a.ds[0]] = quant8(v[cz(j)] + Z[(j * MC + sy) * MC + sx], inv, bad);
-      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+      if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
     } else {
 #pragma unroll
       for (int j = 0; j < MC; ++j) a.cdst[o + j * a.ds[0]] = v[cz(j)] + Z[(j * MC + sy) * MC + sx];
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_p8_quantize(const T* c, uint32_t n, QAr
     const double inv = 1.0 / delta_of(a, i);
     const double v = rint(mul_rn(double(c[i]), inv));
     const bool ok = fabs(v) <= 2147483647.0;
-    if (!ok) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+    if (!ok) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)code_flag(double(c[i])));
     q[i] = ok ? int32_t(v) : 0;
   }
 }
@@ -734,7 +734,7 @@ void p8_quantize(const bm_p8_s& p, const void* coeff, const double* block_tol, d
   int64_t f = 0;
   BM_HIP(hipMemcpyAsync(&f, p.flag, sizeof(f), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
-  if (f) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+  check_code_flag(f, "tolerance too small for the data");
 }
 
 void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* coeff,
@@ -791,7 +791,7 @@ void p8_decompose_quantize(const bm_p8_s& p, const void* x, const double* block_
   int64_t f = 0;
   BM_HIP(hipMemcpyAsync(&f, p.flag, sizeof(f), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
-  if (f) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+  check_code_flag(f, "tolerance too small for the data");
 }
 
 void p8_dequantize_recompose(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* x,

@@ -12,6 +12,7 @@
 #include <tuple>
 
 #include "internal.h"
+#include "line_solve.h"
 
 namespace bm {
 
@@ -19,6 +20,11 @@ namespace bm {
 
 void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(BM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void check_code_flag(int64_t f, const char* what) {
+  if (f & kFlagNonFinite) fail(BM_ENONFINITE, "NaN or Inf in the data (a coefficient is not finite)");
+  if (f) fail(BM_ERANGE, std::string("a quantization code does not fit in 32 bits (") + what + ")");
 }
 
 // ------------------------------------------------------------------ padding
@@ -286,6 +292,20 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     int64_t pd[3];
     for (int a = 0; a < 3; ++a) pd[a] = padded_length(d[a], c->L > 0 ? c->block : 0, c->L, c->M, c->nested != 0);
     if (pd[1] * pd[2] > (int64_t(1) << 40) / pd[0]) fail(BM_EINVAL, "padded grid of more than 2^40 nodes");
+    // the line solves of a global level take at most 64 kLineQ coarse nodes
+    // per line, i.e. axes of at most 2 (64 kLineQ) - 1 = 1151 nodes
+    for (int a = 0; a < 3; ++a) {
+      int64_t n = pd[a];
+      for (int s = 1; s <= c->L + c->M; ++s) {
+        if (n <= 2) break;
+        const int64_t m = (n + 1) / 2;
+        if (s > c->L && m > 64 * kLineQ)
+          fail(BM_EUNSUPPORTED, "global level " + std::to_string(s) + " has an axis of " + std::to_string(n) +
+                                    " nodes; global levels take axes of at most " +
+                                    std::to_string(2 * 64 * kLineQ - 1) + " nodes (add a block level)");
+        n = m;
+      }
+    }
   }
   int dev = 0;
   BM_HIP(hipGetDevice(&dev));

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_quantize(QArgs a, const T* c, int32_t* c
       const double v = rint(mul_rn(cv[k], inv[k]));
       int32_t qv;
       if (!(fabs(v) <= 2147483647.0)) {
-        bad = 1;
+        bad |= int64_t(code_flag(double(cv[k])));
         qv = 0;
       } else {
         qv = int32_t(v);
@@ -740,7 +740,7 @@ void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t*
     stats->n_codes = tot;
     stats->n_outliers = h[0];
     stats->max_abs_code = h[1];
-    if (h[2]) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (tolerance too small for the data)");
+    check_code_flag(h[2], "tolerance too small for the data");
   }
 }
 
@@ -808,7 +808,7 @@ void quantize_delta(bm_plan_s& p, const void* coeff, const double* delta, int32_
     stats->n_codes = int64_t(a.tot);
     stats->n_outliers = h[0];
     stats->max_abs_code = h[1];
-    if (h[2]) fail(BM_ERANGE, "a quantization code does not fit in 32 bits (Delta too small for the data)");
+    check_code_flag(h[2], "Delta too small for the data");
   }
 }
 

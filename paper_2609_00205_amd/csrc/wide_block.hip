@@ -159,11 +159,11 @@ __global__ __launch_bounds__(NT1) void k_wide_columns(WideArgs<T> a) {
           if (lastz) dst[(B - 1) * a.cs[0]] = v[B - 1];
         } else {
           int32_t* dst = a.codes + off;
-          bool bad = false;
+          unsigned bad = 0;
 #pragma unroll
           for (int z = 0; z < B - 1; ++z) dst[z * a.cs[0]] = quant(v[z], iv[zcase<B>(z)], ecol && !(z & 1), bad);
           if (lastz) dst[(B - 1) * a.cs[0]] = quant(v[B - 1], iv[2], ecol, bad);
-          if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+          if (bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
         }
         if (ecol) {
           // u_C into the compact coarse grid; the coarse kernel adds z
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(NT2) void k_wide_coarse(WideArgs<T> a) {
   }
   // codes of the coarsest values: every coarse node the block owns
   const int64_t oz = bz * (B - 1), oy = by * (B - 1), ox = bx * (B - 1);
-  bool bad = false;
+  unsigned bad = 0;
   for (int i = tid; i < MC * MC * MC; i += NT2) {
     const int j = i / (MC * MC), r = i - j * MC * MC, k1 = r / MC, k2 = r - k1 * MC;
     const bool owned = (j < MC - 1 || bz == a.nb[0] - 1) && (k1 < MC - 1 || by == a.nb[1] - 1) &&
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(NT2) void k_wide_coarse(WideArgs<T> a) {
       *c = cv - z;
     }
   }
-  if (DEC && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), 1ull);
+  if (DEC && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
 }
 
 // Interpolation kernel of the recomposition: one workgroup per block half.

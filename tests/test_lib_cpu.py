@@ -79,3 +79,63 @@ def test_null_plan_calls(lib):
     assert lib.bm_decompose(None, None, None, None) == -1
     assert lib.bm_quantize_roi(None, None, None, None, None, None) == -1
     assert lib.bm_plan_destroy(None) == 0
+
+
+def test_long_global_axis_rejected_at_plan_creation(lib):
+    # global-level line solves take at most 576 coarse nodes per line (axes of at most 1151 nodes)
+    from paper_2609_00205_amd._lib import BMConfig
+    h = C.c_void_p()
+    for dims, b, L, M in [((3, 3, 1153), 17, 0, 1),       # first global level on 1153 nodes
+                          ((1153, 5, 5), 17, 0, 2),
+                          ((17, 17, 2305), 17, 1, 1)]:    # a block level leaves 1153 nodes
+        cfg = BMConfig(3, (C.c_int64 * 3)(*dims), 0, b, L, M, 0, 0.1)
+        assert lib.bm_plan_create(C.byref(cfg), C.byref(h)) == -8, dims
+        assert b"1151" in lib.bm_last_error()
+
+
+def _container(tol, flags=0, dims=(9, 9, 9), block=9, L=1, M=1, extra=b"\0" * 64):
+    # the container layout of bm_compress: header (CRC over the header with
+    # its CRC field zeroed, then the payload), the block map, the stream
+    import struct
+    import zlib
+    payload = struct.pack(f"<{len(tol)}d", *tol) + extra
+
+    def hdr(crc):
+        return struct.pack("<III7i3qdqQII", 0x44474D42, 1, flags, 0, block, L, M, 0, 3, 0, *dims, 0.1,
+                           len(tol), len(payload), crc, 0)
+    crc = zlib.crc32(payload, zlib.crc32(hdr(0)))
+    return hdr(crc) + payload
+
+
+@pytest.mark.parametrize("bad", [0.0, -1e-3, float("inf"), float("nan")])
+def test_decompress_rejects_a_bad_stored_tolerance(lib, bad):
+    buf = _container([1e-3, bad])
+    out = C.c_void_p(1)       # never written: the map is checked before anything else
+    assert lib.bm_decompress(buf, len(buf), out, None) == -6
+    assert b"tolerance" in lib.bm_last_error()
+
+
+def test_decompress_rejects_a_map_larger_than_the_payload(lib):
+    buf = _container([1e-3] * 4, extra=b"")
+    import struct
+    b = bytearray(buf)
+    struct.pack_into("<q", b, 72, 5)            # ntol beyond the payload (CRC recomputed below)
+    import zlib
+    struct.pack_into("<I", b, 88, 0)
+    crc = zlib.crc32(bytes(b[96:]), zlib.crc32(bytes(b[:96])))
+    struct.pack_into("<I", b, 88, crc)
+    assert lib.bm_decompress(bytes(b), len(b), C.c_void_p(1), None) == -6
+
+
+def test_batch_checks_list_lengths():
+    # the library reads one pointer per field from each array: the binding
+    # refuses lists of another length before building any pointer array
+    from paper_2609_00205_amd.api import Batch
+    b = Batch.__new__(Batch)
+    b.plans = [object(), object()]
+    with pytest.raises(ValueError):
+        b.decompose_quantize([1], [1, 2])
+    with pytest.raises(ValueError):
+        b.dequantize_recompose([1, 2], [1, 2], outs=[1])
+    with pytest.raises(ValueError):
+        b.compress([1, 2, 3], [1, 2])
