@@ -206,15 +206,20 @@ bm_status bm_dequantize(bm_plan plan, const int32_t* codes, const double* block_
 
 /* Per-coefficient bin widths for a linear quantity of interest Q(x) = <g, x>
  * (the adjoint-guided bounds): s = R^T g gives each coefficient's
- * sensitivity; the N coefficients with s_i != 0 get equal shares,
- * Delta_i = 2 (1 - eta) tol_q / (N |s_i|), so the dequantization errors move Q
- * by at most (1 - eta) tol_q; every Delta_i is also capped by the node's L-inf
- * Delta from block_tol (so that map's bounds still hold).  g: device, logical
- * dims, dtype of the plan; delta: device, padded dims, FP64 (written);
- * *n_sensitive = N if non-NULL.  Synchronous (N is needed on the host).
+ * sensitivity, so quantization moves Q by at most sum |s_i| Delta_i / 2.
+ * Every Delta_i is capped by the node's L-inf width cap_i from block_tol (so
+ * that map's bounds still hold); below the caps every coefficient takes the
+ * same share: |s_i| Delta_i / 2 = min(|s_i| cap_i / 2, lambda), lambda the
+ * largest level with sum_i min(|s_i| cap_i / 2, lambda) <= (1 - eta) tol_q
+ * (found to the last bit by a bracketing search; no such limit when the caps
+ * already fit, and then Delta = cap).  These widths maximise the sum of
+ * log Delta_i (the bits saved) under both bounds.  g: device, logical dims,
+ * dtype of the plan; delta: device, padded dims, FP64 (written);
+ * *n_set (if non-NULL) = the number of coefficients whose width the
+ * quantity sets (Delta_i < cap_i).  Synchronous (a few host round trips).
  * Errors: BM_ENONFINITE (tol_q not positive and finite). */
 bm_status bm_qoi_deltas(bm_plan plan, const void* g, double tol_q, const double* block_tol, double* delta,
-                        int64_t* n_sensitive, hipStream_t stream);
+                        int64_t* n_set, hipStream_t stream);
 
 /* Quantization with an explicit per-node Delta (device, padded dims, FP64):
  * q = rint(c * (1 / Delta_i)) in FP64; stats as bm_quantize_roi. */

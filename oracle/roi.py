@@ -287,3 +287,53 @@ def dequantize(codes: np.ndarray, delta: np.ndarray) -> np.ndarray:
 def rel_to_abs(rel: float, x: np.ndarray) -> float:
     """Sec. V-A: the REL bound is tol * max|u|."""
     return float(rel) * float(np.max(np.abs(x)))
+
+
+# --------------------------------------------------------------------------
+# Adjoint-guided bounds for a linear quantity of interest (an addition to the
+# method: per-coefficient bin widths from the transpose of recomposition)
+# --------------------------------------------------------------------------
+
+
+def qoi_delta(h: mgard.Hierarchy, tol1, g: np.ndarray, tol_q: float, eta: float) -> Tuple[np.ndarray, int]:
+    """Bin widths that keep Q(x) = <g, x> within tol_q after quantization.
+
+    The coefficients' sensitivities are s = R^T g (the recomposition's
+    transpose), so quantization moves Q by at most sum |s_i| Delta_i / 2.
+    Every Delta_i is capped by the node's L-infinity width from the tolerance
+    map (``node_delta``), so the map's bounds still hold.  Reading (the
+    widths that maximise the sum of log Delta_i, i.e. the code length saved,
+    under the two constraints): each coefficient's share |s_i| Delta_i / 2 is
+    the same level lambda, except where the cap is smaller:
+
+        |s_i| Delta_i / 2 = min(a_i, lambda),   a_i = |s_i| cap_i / 2,
+
+    with lambda the root of sum_i min(a_i, lambda) = (1 - eta) tol_q (no root:
+    sum a_i <= (1 - eta) tol_q and every coefficient keeps its cap).  The
+    root is found plainly: a sorted ascending, the first k with
+    prefix_k + a_k (N - k) >= target gives lambda = (target - prefix_k) / (N - k).
+    Returns (Delta, number of coefficients whose width the quantity sets,
+    i.e. a_i > lambda).
+    """
+    s = mgard.recompose_adjoint(np.asarray(g, np.float64), h.shape, h.b, h.L, h.M, h.nested)
+    cap = node_delta(h, tol1, eta)
+    a = np.abs(s) * cap / 2.0
+    target = (1.0 - eta) * float(tol_q)
+    lam = qoi_level(a.ravel(), target)
+    if lam is None:
+        return cap, 0
+    set_by_q = a > lam
+    delta = cap.copy()
+    delta[set_by_q] = 2.0 * lam / np.abs(s[set_by_q])
+    return delta, int(set_by_q.sum())
+
+
+def qoi_level(a: np.ndarray, target: float):
+    """lambda with sum_i min(a_i, lambda) = target, or None if sum a_i <= target."""
+    if float(np.sum(a)) <= target:
+        return None
+    srt = np.sort(np.asarray(a, np.float64))
+    n = srt.size
+    prefix = np.concatenate([[0.0], np.cumsum(srt)[:-1]])     # sum of the k smallest
+    k = int(np.argmax(prefix + srt * (n - np.arange(n)) >= target))
+    return (target - prefix[k]) / (n - k)

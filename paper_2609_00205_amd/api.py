@@ -199,7 +199,8 @@ class Plan:
     # -- adjoint-guided bounds for a linear quantity of interest ---------------
     def qoi_deltas(self, g: torch.Tensor, tol_q: float, block_tol: torch.Tensor, stream=None):
         """Per-node Delta keeping <g, x> within tol_q (capped by the block map's
-        L-inf Delta); returns (delta, number of sensitive coefficients)."""
+        L-inf Delta); returns (delta, number of coefficients whose width the
+        quantity sets, i.e. below the cap)."""
         _need(g, self.dtype, self.shape, "g")
         _need(block_tol, torch.float64, self.block_grid, "block_tol")
         delta = torch.empty(self.coeff_shape, dtype=torch.float64, device=g.device)

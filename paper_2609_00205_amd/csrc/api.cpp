@@ -485,12 +485,12 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
 }
 
 bm_status bm_qoi_deltas(bm_plan p, const void* g, double tol_q, const double* block_tol, double* delta,
-                        int64_t* n_sensitive, hipStream_t st) {
+                        int64_t* n_set, hipStream_t st) {
   return guarded([&] {
     need(p && g && block_tol && delta, "null argument");
     check_device(p);
     const int64_t n = bm::qoi_deltas(*p, g, tol_q, block_tol, delta, st);
-    if (n_sensitive) *n_sensitive = n;
+    if (n_set) *n_set = n;
   });
 }
 

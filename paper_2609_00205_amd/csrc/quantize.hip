@@ -363,37 +363,118 @@ int64_t prod3(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 
 }  // namespace
 
-// Build every per-level quantizer table on the device from the level-1 map.
-// number of nonzero entries (one atomic add per workgroup)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_count_nonzero(const T* v, int64_t n, unsigned long long* out) {
-  __shared__ unsigned long long red[NT];
-  unsigned long long c = 0;
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) c += v[i] != T(0);
-  red[threadIdx.x] = c;
+// Adjoint-guided widths for a linear quantity of interest Q = <g, x>: with
+// s = R^T g, quantization moves Q by at most sum |s_i| Delta_i / 2.  Each
+// coefficient's share |s_i| Delta_i / 2 is one level lambda, except where the
+// node's L-inf width cap_i is smaller: share = min(a_i, lambda) with
+// a_i = |s_i| cap_i / 2, and lambda the root of sum_i min(a_i, lambda) =
+// (1 - eta) tol_q.  Sums are reduced per workgroup in a fixed order, then by
+// one workgroup (deterministic).
+constexpr int kQoiK = 15;           // candidate levels per pass
+constexpr int kQoiGroups = 1024;    // workgroups of a pass (partials: kQoiK per group)
+
+struct Cand {
+  double v[kQoiK];
+};
+
+__device__ inline double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0]) atomicAdd(out, red[0]);
+  const double r = red[0];
+  __syncthreads();
+  return r;
 }
 
-// Per-node Delta keeping a linear quantity of interest within its tolerance:
-// with s the sensitivities of the quantity to the coefficients, the share of
-// coefficient i is e_i = tol / (N |s_i|) (N nonzero s_i), so the errors
-// |s_i| Delta_i / 2 add up to at most tol (1 - eta); the node's L-inf Delta
-// from the tolerance map caps it.  kq = 2 (1 - eta) tol / N.
+__device__ inline double block_max(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// a_i = |s_i| cap_i / 2 into share[i]; partials[2 g] = sum, [2 g + 1] = max
 template <typename T>
-__global__ __launch_bounds__(NT) void k_qoi_delta(QArgs a, const T* s, double kq, double* delta) {
+__global__ __launch_bounds__(NT) void k_qoi_shares(QArgs a, const T* s, double* share, double* partials) {
+  __shared__ double red[NT];
+  double sum = 0.0, mx = 0.0;
   for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
     uint32_t z, y, x;
     a.uf(i, z, y, x);
     double del, inv;
     node_delta(a, z, y, x, del, inv);
-    const double sv = fabs(double(s[i]));
-    delta[i] = sv > 0.0 ? fmin(del, kq / sv) : del;
+    const double v = fabs(double(s[i])) * del * 0.5;
+    share[i] = v;
+    sum += v;
+    mx = fmax(mx, v);
   }
+  sum = block_sum(sum, red);
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sum;
+    partials[2 * blockIdx.x + 1] = mx;
+  }
+}
+
+// f(c_j) = sum_i min(a_i, c_j) for the kQoiK candidates: partials[g kQoiK + j]
+__global__ __launch_bounds__(NT) void k_qoi_eval(const double* share, uint32_t n, Cand c, double* partials) {
+  __shared__ double red[NT];
+  double acc[kQoiK];
+#pragma unroll
+  for (int j = 0; j < kQoiK; ++j) acc[j] = 0.0;
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    const double v = share[i];
+#pragma unroll
+    for (int j = 0; j < kQoiK; ++j) acc[j] += fmin(v, c.v[j]);
+  }
+  for (int j = 0; j < kQoiK; ++j) {
+    const double r = block_sum(acc[j], red);
+    if (threadIdx.x == 0) partials[blockIdx.x * kQoiK + j] = r;
+  }
+}
+
+// out[j] = sum (or max, for odd j when max_odd) over ng groups of partials[g k + j]
+__global__ __launch_bounds__(NT) void k_qoi_fold(const double* partials, int ng, int k, int max_odd, double* out) {
+  __shared__ double red[NT];
+  for (int j = 0; j < k; ++j) {
+    const bool mx = max_odd && (j & 1);
+    double v = 0.0;
+    for (int g = threadIdx.x; g < ng; g += NT) v = mx ? fmax(v, partials[g * k + j]) : v + partials[g * k + j];
+    v = mx ? block_max(v, red) : block_sum(v, red);
+    if (threadIdx.x == 0) out[j] = v;
+  }
+}
+
+// Delta_i = 2 lambda / |s_i| where a_i > lambda (the quantity sets the
+// width), else the node's L-inf width; counts the former
+template <typename T>
+__global__ __launch_bounds__(NT) void k_qoi_final(QArgs a, const T* s, double lambda, double* delta,
+                                                  unsigned long long* count) {
+  __shared__ double red[NT];
+  double c = 0.0;
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < a.tot; i += gridDim.x * NT) {
+    const double ai = delta[i];
+    uint32_t z, y, x;
+    a.uf(i, z, y, x);
+    double del, inv;
+    node_delta(a, z, y, x, del, inv);
+    if (ai > lambda) {
+      delta[i] = 2.0 * lambda / fabs(double(s[i]));
+      c += 1.0;
+    } else {
+      delta[i] = del;
+    }
+  }
+  c = block_sum(c, red);
+  if (threadIdx.x == 0 && c > 0.0) atomicAdd(count, (unsigned long long)c);
 }
 
 QPrep qprep_layout(bm_plan_s& p, const double* block_tol) {
@@ -764,28 +845,79 @@ int64_t qoi_deltas(bm_plan_s& p, const void* g, double tol_q, const double* bloc
   if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, npad * p.esize));
   // sensitivities s = R^T g of the quantity to the coefficients
   recompose_adjoint(p, g, p.ws.coeff, st);
+  QArgs a = prepare(p, block_tol, st);
+  const bool f32 = p.cfg.dtype == BM_F32;
+  // partial sums live in the plan's statistics scratch (3 x 8192 slots after
+  // the 16 counters): up to kQoiGroups x kQoiK partials, then 16 folded values
+  double* part = reinterpret_cast<double*>(p.ws.counters + 16);
+  double* fold = part + kQoiGroups * kQoiK;
+  static_assert(kQoiGroups * kQoiK + 16 <= 3 * 8192, "QoI partials exceed the statistics scratch");
+  const unsigned gs = std::min<unsigned>(grid_for(int64_t(a.tot)), unsigned(kQoiGroups));
+  // a_i = |s_i| cap_i / 2 (held in delta until the last pass), their sum and max
+  if (f32)
+    hipLaunchKernelGGL(k_qoi_shares<float>, dim3(gs), dim3(NT), 0, st, a, static_cast<const float*>(p.ws.coeff),
+                       delta, part);
+  else
+    hipLaunchKernelGGL(k_qoi_shares<double>, dim3(gs), dim3(NT), 0, st, a, static_cast<const double*>(p.ws.coeff),
+                       delta, part);
+  hipLaunchKernelGGL(k_qoi_fold, dim3(1), dim3(NT), 0, st, part, int(gs), 2, 1, fold);
+  BM_HIP(hipGetLastError());
+  double sm[2];
+  BM_HIP(hipMemcpyAsync(sm, fold, sizeof(sm), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  const double target = (1.0 - p.cfg.eta) * tol_q;
+  double lambda = INFINITY;   // every cap fits: no width is set by the quantity
+  if (sm[0] > target) {
+    // f(lambda) = sum min(a_i, lambda) rises from f(lo) <= tot lo = target to
+    // f(max a) = sum a > target; kQoiK candidates per pass narrow [lo, hi]
+    // (geometric steps while hi > 2 lo, then even steps) until no double lies
+    // between; lambda = lo keeps f(lambda) <= target, so the quantity's bound holds
+    double lo = target / double(a.tot), hi = sm[1];
+    for (int pass = 0; pass < 80 && hi > lo; ++pass) {
+      Cand c;
+      for (int j = 0; j < kQoiK; ++j) {
+        const double t = double(j + 1) / double(kQoiK + 1);
+        c.v[j] = hi > 2.0 * lo ? lo * std::pow(hi / lo, t) : lo + (hi - lo) * t;
+      }
+      hipLaunchKernelGGL(k_qoi_eval, dim3(unsigned(kQoiGroups)), dim3(NT), 0, st, static_cast<const double*>(delta),
+                         a.tot, c, part);
+      hipLaunchKernelGGL(k_qoi_fold, dim3(1), dim3(NT), 0, st, part, kQoiGroups, kQoiK, 0, fold);
+      BM_HIP(hipGetLastError());
+      double f[kQoiK];
+      BM_HIP(hipMemcpyAsync(f, fold, sizeof(f), hipMemcpyDeviceToHost, st));
+      BM_HIP(hipStreamSynchronize(st));
+      double nlo = lo, nhi = hi;
+      for (int j = 0; j < kQoiK; ++j) {
+        if (!(c.v[j] > lo && c.v[j] < hi)) continue;
+        if (f[j] <= target)
+          nlo = std::max(nlo, c.v[j]);
+        else
+          nhi = std::min(nhi, c.v[j]);
+      }
+      if (nlo == lo && nhi == hi) break;   // no candidate strictly inside: converged
+      if (nlo >= nhi) {                    // sums not monotone at rounding level
+        lo = nlo;
+        break;
+      }
+      lo = nlo;
+      hi = nhi;
+    }
+    lambda = lo;
+  }
   auto* cnt = reinterpret_cast<unsigned long long*>(p.ws.counters + 3);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, cnt);
-  if (p.cfg.dtype == BM_F32)
-    hipLaunchKernelGGL(k_count_nonzero<float>, dim3(grid_for(int64_t(npad))), dim3(NT), 0, st,
-                       static_cast<const float*>(p.ws.coeff), int64_t(npad), cnt);
-  else
-    hipLaunchKernelGGL(k_count_nonzero<double>, dim3(grid_for(int64_t(npad))), dim3(NT), 0, st,
-                       static_cast<const double*>(p.ws.coeff), int64_t(npad), cnt);
-  unsigned long long nnz = 0;
-  BM_HIP(hipMemcpyAsync(&nnz, cnt, sizeof(nnz), hipMemcpyDeviceToHost, st));
-  QArgs a = prepare(p, block_tol, st);
-  BM_HIP(hipStreamSynchronize(st));
-  const double kq = nnz ? (2.0 * (1.0 - p.cfg.eta)) * tol_q / double(nnz) : 0.0;
   const unsigned gq = grid_for(int64_t(a.tot));
-  if (p.cfg.dtype == BM_F32)
-    hipLaunchKernelGGL(k_qoi_delta<float>, dim3(gq), dim3(NT), 0, st, a, static_cast<const float*>(p.ws.coeff), kq,
-                       delta);
+  if (f32)
+    hipLaunchKernelGGL(k_qoi_final<float>, dim3(gq), dim3(NT), 0, st, a, static_cast<const float*>(p.ws.coeff),
+                       lambda, delta, cnt);
   else
-    hipLaunchKernelGGL(k_qoi_delta<double>, dim3(gq), dim3(NT), 0, st, a, static_cast<const double*>(p.ws.coeff),
-                       kq, delta);
+    hipLaunchKernelGGL(k_qoi_final<double>, dim3(gq), dim3(NT), 0, st, a, static_cast<const double*>(p.ws.coeff),
+                       lambda, delta, cnt);
   BM_HIP(hipGetLastError());
-  return int64_t(nnz);
+  unsigned long long nset = 0;
+  BM_HIP(hipMemcpyAsync(&nset, cnt, sizeof(nset), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  return int64_t(nset);
 }
 
 void quantize_delta(bm_plan_s& p, const void* coeff, const double* delta, int32_t* codes, bm_qstats* stats,

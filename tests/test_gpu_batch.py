@@ -1,6 +1,6 @@
 """Batched many-field pipeline (one persistent launch per block level,
-optionally captured in a HIP graph) against the single-field path, through
-the C ABI.
+optionally captured in a HIP graph) against the single-field path and
+against the oracle, through the C ABI.
 
 Bar: codes and reconstructions bit-identical to each field's own
 bm_decompose_quantize / bm_dequantize_recompose (which the quantizer tests
@@ -103,3 +103,58 @@ def test_batch_overflow_count():
     tols = [p.tolmap_from_boxes([], 1e-6) for p in batch.plans]
     _, nbad = batch.decompose_quantize(xs, tols, check=True)
     assert nbad == 1
+
+
+ORACLE_CASES = [
+    ([(33, 17, 65), (65, 33, 33), (17, 33, 17)], torch.float32, 17, None, 0),
+    ([(33, 65, 33), (17, 17, 33)], torch.float64, 17, None, 0),
+    ([(33, 33, 65), (65, 17, 33)], torch.float32, 9, None, 0),
+    ([(33, 33, 33), (65, 33, 33)], torch.float64, 9, 1, 2),          # global levels per field
+]
+
+
+@pytest.mark.parametrize("case", ORACLE_CASES, ids=_id)
+def test_batch_matches_oracle(case):
+    """Batched codes and reconstructions against the oracle directly.  The
+    GPU's coefficients (not an output of the batch) lie within the
+    coefficient tolerance e = 1e-6 / 1e-13 of max|x| of the oracle's, so a
+    code may differ from the oracle's quantization of its own coefficient by
+    at most e / Delta + 1, and where e / Delta < 1/2 only where a bin edge
+    lies within e of the oracle's coefficient (count printed);
+    reconstructions equal the oracle's recomposition of the dequantized batch
+    codes; every voxel within its bound."""
+    from oracle import mgard, roi
+    from paper_2609_00205_amd import Batch
+    shapes, dt, b, L, M = case
+    print("case", _id(case), flush=True)
+    batch = Batch(shapes, dtype=dt, block=b, L=L, M=M)
+    xs = _fields(shapes, dt, 700)
+    tols = _tols(batch, xs)
+    codes = batch.decompose_quantize(xs, tols, use_graph=True)
+    outs = batch.dequantize_recompose(codes, tols, use_graph=True)
+    torch.cuda.synchronize()
+    ctol = 1e-6 if dt == torch.float32 else 1e-13
+    for p, x, t, c, o in zip(batch.plans, xs, tols, codes, outs):
+        xn = x.cpu().double().numpy()
+        h = mgard.hierarchy(p.shape, b, p.L, p.M)
+        co = mgard.decompose(xn, b, p.L, p.M)
+        tol1 = t.cpu().numpy() if p.L > 0 else float(t.cpu().numpy().ravel()[0])
+        delta = roi.node_delta(h, tol1, p.eta)
+        ref = roi.quantize(co, delta)
+        got = c.cpu().numpy().astype(np.int64)
+        flips = got != ref
+        r = co * (1.0 / delta)
+        edge = np.abs(r - np.floor(r) - 0.5) * delta
+        scale = float(np.abs(xn).max())
+        print(f"field {p.shape} L={p.L}: codes across a bin edge {int(flips.sum())} of {got.size}")
+        reach = ctol * scale / delta
+        assert np.all(np.abs(got - ref) <= reach + 1)
+        near = flips & (reach < 0.5)
+        assert np.all(edge[near] <= ctol * scale)
+        xr_ref = mgard.recompose(roi.dequantize(got, delta), p.shape, b, p.L, p.M)
+        on = o.cpu().double().numpy()
+        assert float(np.abs(on - xr_ref).max()) <= ctol * max(scale, float(np.abs(xr_ref).max()))
+        n = p.shape
+        box = (n[0] // 4, n[1] // 4, n[2] // 4, n[0] // 2 + 1, n[1] // 2 + 1, n[2] // 2 + 1, 1e-5 * scale)
+        vt = roi.voxel_tolerance_from_boxes(n, [box], 1e-3 * scale)
+        assert np.all(np.abs(on - xn) <= vt)

@@ -1,12 +1,11 @@
 """Full-size parity: 512^3 FP32, b = 17, L = 1, M = 2, the configuration the
 benchmark times.
 
-The oracle cannot run the whole field quickly, so it checks sampled outputs
-it can compute one by one: level-1 coefficients of sampled blocks (each
-block is decomposed on its own), and level-2 details at sampled nodes (they
-need only the level-1 coarse values of the blocks around the node).  The
-rest is checked by properties that hold at any size: the round trip and
-every ROI bound.
+The oracle decomposes and recomposes the whole field (about half a minute
+each on the host): every coefficient and every reconstructed value is
+compared.  Sampled checks it computes one block at a time (level-1 blocks,
+level-2 details at sampled nodes) localise a mismatch; the round trip and
+every ROI bound hold on the whole field.
 """
 import numpy as np
 import pytest
@@ -110,3 +109,33 @@ def test_roundtrip_and_roi_bounds(setup):
     h = mgard.hierarchy((N, N, N), B, L, M)
     ref = roi.block_tolerance(roi.voxel_tolerance_from_boxes((N, N, N), abs_boxes, 1e-2 * scale), h.shape_p, B)
     assert np.array_equal(bt.cpu().numpy(), ref)
+
+
+def test_whole_field_decompose_matches_oracle(setup):
+    """Every coefficient of the 513^3 array (level-1 details, the first global
+    level's solve-only passes on 257-node lines, the second global level,
+    the coarsest values) against the oracle's decomposition of the whole
+    field."""
+    x, boxes, p, xd, c = setup
+    print("oracle decomposition of the whole field", flush=True)
+    ref = mgard.decompose(x.astype(np.float64), B, L, M)
+    got = c.cpu().double().numpy()
+    scale = float(np.abs(x).max())
+    lev = mgard.node_level(ref.shape, L, M)
+    for s in range(1, L + M + 2):
+        e = float(np.abs(got[lev == s] - ref[lev == s]).max()) / scale
+        print(f"level {s}: max coefficient error / max|x| = {e:.2e}", flush=True)
+    err = float(np.abs(got - ref).max()) / scale
+    assert err <= 1e-6
+
+
+def test_whole_field_recompose_matches_oracle(setup):
+    """Recomposition of the GPU's own coefficient array, whole field, against
+    the oracle's recomposition of the same coefficients."""
+    x, boxes, p, xd, c = setup
+    y = p.recompose(c).cpu().double().numpy()
+    print("oracle recomposition of the whole field", flush=True)
+    ref = mgard.recompose(c.cpu().double().numpy(), (N, N, N), B, L, M)
+    err = float(np.abs(y - ref).max()) / float(np.abs(ref).max())
+    print(f"max recompose error / max|ref| = {err:.2e}")
+    assert err <= 1e-6

@@ -1,12 +1,13 @@
 """Adjoint-guided bounds for a linear quantity of interest (per-coefficient
 bin widths from the sensitivities R^T g), through the C ABI.
 
-Checks: the quantity moves by at most tol_q after decompose -> quantize with
-the per-node Delta -> dequantize -> recompose; the L-inf background bound
-still holds everywhere; every Delta is capped by the ROI quantizer's own
-Delta; sum |s_i| Delta_i / 2 <= (1 - eta) tol_q over the sensitive
-coefficients; quantization with a per-node Delta equals the ROI quantizer
-when the Delta array holds the ROI quantizer's own values.
+Checks: the widths equal the oracle's rule element by element (FP64); the
+quantity moves by at most tol_q after decompose -> quantize with the
+per-node Delta -> dequantize -> recompose; the L-inf background bound still
+holds everywhere; every Delta is capped by the ROI quantizer's own Delta;
+sum |s_i| Delta_i / 2 reaches (1 - eta) tol_q when the quantity binds;
+quantization with a per-node Delta equals the ROI quantizer when the Delta
+array holds the ROI quantizer's own values.
 """
 import numpy as np
 import pytest
@@ -49,8 +50,8 @@ def test_qoi_bound(case):
     g[lo:hi, lo:hi, lo:hi] = 1.0 / (hi - lo) ** 3
     tol_q, bg = rel_q * sc, 1e-3 * sc
     bt = p.tolmap_from_boxes([], bg)
-    delta, nsens = p.qoi_deltas(g, tol_q, bt)
-    assert 0 < nsens <= int(np.prod(p.coeff_shape))
+    delta, nset = p.qoi_deltas(g, tol_q, bt)
+    assert 0 < nset <= int(np.prod(p.coeff_shape))
     c = p.decompose(x)
     q, st = p.quantize_delta(c, delta)
     xr = p.recompose(p.dequantize_delta(q, delta))
@@ -64,9 +65,11 @@ def test_qoi_bound(case):
     ones = p.dequantize(torch.ones_like(codes_roi), bt).double()      # the ROI quantizer's own Delta (as dtype)
     d = delta
     assert bool((d.to(ones.dtype) <= ones * (1 + 1e-6)).all())
-    nz = s != 0
-    assert int(nz.sum()) == nsens
-    assert float((s[nz].abs() * d[nz]).sum() / 2) <= (1 - p.eta) * tol_q * (1 + 1e-9)
+    assert int((d.to(ones.dtype) < ones * (1 - 1e-6)).sum()) <= nset
+    # the quantity binds: its budget is used up to rounding (FP32 sensitivities: to their precision)
+    used = float((s.abs() * d).sum() / 2)
+    assert used <= (1 - p.eta) * tol_q * (1 + 1e-9)
+    assert used >= (1 - p.eta) * tol_q * (1 - (1e-9 if dt == torch.float64 else 1e-4))
 
 
 def test_delta_quantizer_matches_roi_quantizer():
@@ -87,3 +90,36 @@ def test_delta_quantizer_matches_roi_quantizer():
         r = (c.double() / delta)[diff]
         assert float((r - r.floor() - 0.5).abs().max()) < 1e-9
     assert torch.equal(p.dequantize_delta(ref, delta), p.dequantize(ref, bt))
+
+
+ORACLE_CASES = [((33, 33, 33), 17, 1, 2, (8, 24)), ((65, 33, 49), 9, 2, 1, (10, 30)),
+                ((40, 50, 61), 9, 1, 2, (12, 36)), ((65, 65, 65), 33, 1, 2, (16, 48)),
+                ((33, 17, 65), 17, 0, 3, (4, 12))]
+
+
+@pytest.mark.parametrize("case", ORACLE_CASES, ids=lambda c: "x".join(map(str, c[0])) + f"-b{c[1]}-L{c[2]}M{c[3]}")
+def test_qoi_deltas_match_oracle(case):
+    """bm_qoi_deltas equals the oracle's rule (sensitivities from the oracle's
+    R^T g; every share |s_i| Delta_i / 2 at one level lambda below the map's
+    cap, lambda spending (1 - eta) tol_q), FP64, element by element; the
+    number of widths the quantity sets agrees up to shares within rounding
+    of lambda."""
+    from oracle import mgard, roi
+    from paper_2609_00205_amd import Plan
+    shape, b, L, M, (lo, hi) = case
+    print("case", case, flush=True)
+    p = Plan(shape, dtype=torch.float64, block=b, L=L, M=M)
+    g = np.zeros(shape)
+    g[lo:hi, lo:hi, lo:hi] = 1.0 / (hi - lo) ** 3
+    boxes = [(2, 2, 2, 9, 9, 9, 1e-5)]
+    bt = p.tolmap_from_boxes(boxes, 1e-3)
+    tol_q = 1e-6
+    delta, nset = p.qoi_deltas(torch.from_numpy(g).cuda(), tol_q, bt)
+    h = mgard.hierarchy(shape, b, L, M)
+    vt = roi.voxel_tolerance_from_boxes(shape, boxes, 1e-3)
+    tol1 = roi.block_tolerance(vt, h.shape_p, b) if L > 0 else vt.min()
+    ref, n = roi.qoi_delta(h, tol1, g, tol_q, p.eta)
+    print("widths set by the quantity: GPU", nset, "oracle", n)
+    assert n > 0 and abs(nset - n) <= max(2, n // 100000)
+    got = delta.cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=0)

@@ -225,3 +225,34 @@ def test_raw_fallback_for_incompressible_data(tol):
     assert len(buf) > x.nbytes
     xr = api.decompress(buf).cpu().numpy()
     assert np.array_equal(xr, x)
+
+
+NONFINITE_CASES = [((33, 33, 33), 17, 1, 2), ((20, 30, 12), 9, 1, 1), ((65, 65, 65), 17, 0, 6),
+                   ((70, 40, 100), 33, 1, 1), ((33, 33, 17), 9, 2, 0)]
+
+
+@pytest.mark.parametrize("shape,b,L,M", NONFINITE_CASES)
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")], ids=["nan", "inf", "-inf"])
+@pytest.mark.parametrize("where", ["interior", "corner", "last"])
+def test_nonfinite_data_reported(shape, b, L, M, bad, where):
+    """A NaN or Inf in the data reaches the coefficient of its own node; the
+    quantizing calls that check (fused with stats, quantize with stats,
+    compress) return BM_ENONFINITE, and compress writes nothing."""
+    from paper_2609_00205_amd import _lib
+    p = _plan(shape, b, L, M)
+    x = synth.gaussian_random_field(shape, 3.0, seed=25, dtype=np.float32)
+    pos = {"interior": tuple(s // 2 + 1 for s in shape), "corner": (0, 0, 0),
+           "last": tuple(s - 1 for s in shape)}[where]
+    x[pos] = bad
+    xd = torch.from_numpy(x).cuda()
+    bt = p.tolmap_from_boxes([], 1e-2)
+    for call in (lambda: p.decompose_quantize(xd, bt), lambda: p.quantize(p.decompose(xd), bt),
+                 lambda: p.compress(xd, bt)):
+        with pytest.raises(_lib.BMError) as e:
+            call()
+        assert e.value.code == -4, e.value
+    # the range error stays distinct: finite data, codes beyond int32
+    x[pos] = 1.0
+    with pytest.raises(_lib.BMError) as e:
+        p.decompose_quantize(torch.from_numpy(x * 1e6).cuda(), p.tolmap_from_boxes([], 1e-9))
+    assert e.value.code == -7

@@ -173,3 +173,60 @@ def test_quantizer_round_half_even_and_reciprocal():
     delta = np.full(6, 0.5)
     c = np.array([0.25, 0.75, -0.25, 1.0, 0.1, -1.3])
     assert list(roi.quantize(c, delta)) == [0, 2, 0, 2, 0, -3]
+
+
+def test_qoi_level_hand_examples():
+    # sum_i min(a_i, lambda) = target, worked by hand
+    assert roi.qoi_level(np.array([1.0, 2.0, 3.0]), 4.5) == pytest.approx(1.75, abs=1e-15)   # 1 + 1.75 + 1.75
+    assert roi.qoi_level(np.array([3.0, 1.0, 2.0]), 3.0) == pytest.approx(1.0, abs=1e-15)    # 1 + 1 + 1
+    assert roi.qoi_level(np.array([0.0, 0.0, 5.0]), 2.0) == pytest.approx(2.0, abs=1e-15)    # zeros take nothing
+    assert roi.qoi_level(np.array([1.0, 2.0]), 3.0) is None                                  # the caps fit
+
+
+@pytest.mark.parametrize("shape,b,L,M,box", [((9, 9, 9), 9, 1, 1, (2, 6)), ((9, 5, 13), 9, 1, 1, (1, 4)),
+                                             ((5, 9, 17), 9, 0, 3, (1, 4))])
+@pytest.mark.parametrize("bg", [1e-2, 1e-7])
+def test_qoi_delta_keeps_the_quantity(shape, b, L, M, box, bg):
+    # Q(x) = mean over a sub-box.  Sensitivities by brute force (Q of the
+    # recomposition of every unit coefficient) agree with R^T g; the worst
+    # case of the quantization errors (every coefficient off by Delta/2 with
+    # the sign of its sensitivity) moves Q by exactly tol_q when the
+    # quantity binds (bg 1e-2) and by less when every cap fits (bg 1e-7);
+    # no width exceeds the map's; widths set by the quantity all carry the
+    # same share |s_i| Delta_i / 2; quantizing a random field keeps Q within
+    # tol_q and every node within the map's bound.
+    rng = np.random.default_rng(3)
+    h = mgard.hierarchy(shape, b, L, M)
+    lo, hi = box
+    g = np.zeros(shape)
+    g[lo:hi, lo:hi, lo:hi] = 1.0 / (hi - lo) ** 3
+    tol1 = np.full([(n - 1) // (b - 1) for n in h.shape_p], bg) if L > 0 else bg
+    tol_q = 1e-6
+    delta, nset = roi.qoi_delta(h, tol1, g, tol_q, 0.0)
+    npad = int(np.prod(h.shape_p))
+    s = np.empty(npad)
+    for i in range(npad):
+        e = np.zeros(npad)
+        e[i] = 1.0
+        s[i] = float((g * mgard.recompose(e.reshape(h.shape_p), shape, b, L, M)).sum())
+    s = s.reshape(h.shape_p)
+    st = mgard.recompose_adjoint(g, shape, b, L, M)
+    assert np.abs(s - st).max() <= 1e-14 * np.abs(s).max()
+    base = roi.node_delta(h, tol1, 0.0)
+    assert np.all(delta <= base)
+    worst = float((np.abs(s) * delta / 2).sum())
+    if bg == 1e-2:
+        assert nset > 0
+        assert worst == pytest.approx(tol_q, rel=1e-9)
+        share = np.abs(s) * delta / 2
+        setq = delta < base
+        assert int(setq.sum()) == nset
+        assert np.allclose(share[setq], share[setq].max(), rtol=1e-12, atol=0)
+        assert np.all(share[~setq] <= share[setq].max() * (1 + 1e-12))
+    else:
+        assert nset == 0 and np.array_equal(delta, base) and worst <= tol_q
+    x = rng.standard_normal(shape)
+    c = mgard.decompose(x, b, L, M)
+    xr = mgard.recompose(roi.dequantize(roi.quantize(c, delta), delta), shape, b, L, M)
+    assert abs(float((g * (xr - x)).sum())) <= tol_q
+    assert float(np.abs(xr - x).max()) <= bg
