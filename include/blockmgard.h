@@ -264,6 +264,20 @@ bm_status bm_dequantize_recompose(bm_plan plan, const int32_t* codes, const doub
 bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity,
                             size_t* out_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): bm_huffman_encode
+ * with the stream written to device memory.  out (device, capacity bytes)
+ * receives exactly the bytes bm_huffman_encode writes; codes: device int32,
+ * 0 <= n <= 2^28 (else BM_EINVAL).  Nothing is allocated, on the device or the
+ * host: the work arrays (histogram, code table, per-chunk bit and escape
+ * counts and offsets: 2.3 MiB) live in a fixed device array of the library,
+ * one copy per GPU held until the process ends, and in static host arrays.
+ * Calls are serialised on the host; calls that overlap in time on one GPU
+ * (from other processes or streams) race on that GPU's copy.  Synchronous.
+ * BM_ECAPACITY sets *out_bytes to the size needed and writes nothing. */
+bm_status bm_huffman_encode_device(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
+                                   hipStream_t stream);
+
 /* Inverse of bm_huffman_encode into codes (device, n entries).  Synchronous.
  * Errors: BM_ECORRUPT for a malformed stream, BM_EINVAL if n mismatches. */
 bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int64_t n,

@@ -57,6 +57,7 @@ _SIGS = {
     "bm_dequantize": [P, P, P, P, P],
     "bm_huffman_encode": [P, C.c_int64, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_huffman_decode": [P, C.c_size_t, P, C.c_int64, P],
+    "bm_huffman_encode_device": [P, C.c_int64, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_compress": [P, P, P, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_compressed_config": [P, C.c_size_t, C.POINTER(BMConfig)],
     "bm_decompress": [P, C.c_size_t, P, P],

@@ -327,6 +327,24 @@ def huffman_encode(codes: torch.Tensor, stream=None) -> bytearray:
     return _take(buf, got.value)
 
 
+def huffman_encode_device(codes: torch.Tensor, out: torch.Tensor, stream=None) -> int:
+    """bm_huffman_encode into a device byte tensor (the entry point that
+    allocates nothing); returns the stream size.  When out is too small the
+    BMError (BM_ECAPACITY) carries the size needed in ``.needed``."""
+    if codes.dtype != torch.int32 or not codes.is_cuda or not codes.is_contiguous():
+        raise ValueError("codes: contiguous int32 device tensor")
+    if out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out: contiguous uint8 device tensor")
+    got = C.c_size_t(0)
+    st = _lib.lib().bm_huffman_encode_device(_ptr(codes), int(codes.numel()), _ptr(out), int(out.numel()),
+                                             C.byref(got), _stream(stream))
+    if st != 0:
+        err = _lib.BMError(st, _lib.lib().bm_last_error().decode())
+        err.needed = int(got.value)
+        raise err
+    return int(got.value)
+
+
 def huffman_decode(buf, n: int, device=None, stream=None) -> torch.Tensor:
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = torch.empty(n, dtype=torch.int32, device=dev)

@@ -457,6 +457,14 @@ bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t c
   });
 }
 
+bm_status bm_huffman_encode_device(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
+                                   hipStream_t st) {
+  return guarded([&] {
+    need(out_bytes != nullptr, "null out_bytes");
+    bm::huffman_encode_noalloc(codes, n, out, capacity, out_bytes, st);
+  });
+}
+
 bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st) {
   return guarded([&] {
     need(codes || n == 0, "null codes");

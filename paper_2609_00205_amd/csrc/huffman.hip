@@ -20,7 +20,8 @@
 
 #include <algorithm>
 #include <cstring>
-#include <queue>
+#include <memory>
+#include <mutex>
 
 #include "internal.h"
 
@@ -93,10 +94,26 @@ __device__ inline uint32_t wave_excl_scan(uint32_t v, int lane) {
   return s - v;
 }
 
+// a 32-bit little-endian store; BYTES: four byte stores (a destination that
+// is not 4-byte aligned)
+template <bool BYTES>
+__device__ inline void store32(void* base, uint64_t i, uint32_t v) {
+  if (BYTES) {
+    uint8_t* p = static_cast<uint8_t*>(base) + 4 * i;
+    p[0] = uint8_t(v);
+    p[1] = uint8_t(v >> 8);
+    p[2] = uint8_t(v >> 16);
+    p[3] = uint8_t(v >> 24);
+  } else {
+    static_cast<uint32_t*>(base)[i] = v;
+  }
+}
+
 // one wavefront per chunk; lane l codes symbols [64 l, 64 l + 64) of the chunk
+template <bool BYTES = false>
 __global__ __launch_bounds__(64) void k_encode(const int32_t* codes, int64_t n, const uint8_t* len,
                                                const uint32_t* cw, const uint64_t* woff, const uint64_t* ooff,
-                                               uint32_t* words, int32_t* oval) {
+                                               void* words, void* oval) {
   __shared__ uint32_t sym[64 * 65];
   __shared__ uint32_t out[CHUNK];
   const int lane = threadIdx.x;
@@ -129,10 +146,10 @@ __global__ __launch_bounds__(64) void k_encode(const int32_t* codes, int64_t n, 
       atomicOr(&out[w + 1], v << (64 - o - l));
     }
     p += l;
-    if (s == 0) oval[e++] = codes[b0 + lane * 64 + k];
+    if (s == 0) store32<BYTES>(oval, e++, uint32_t(codes[b0 + lane * 64 + k]));
   }
   __syncthreads();
-  for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = out[i];
+  for (uint64_t i = lane; i < nw; i += 64) store32<BYTES>(words, w0 + i, out[i]);
 }
 
 struct DecTables {
@@ -235,78 +252,135 @@ __global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint
 }
 
 // ------------------------------------------------------------------ host codebook
+// The codebook is built in fixed arrays (no allocation), so the same code
+// serves the entry point that may not allocate.
 
-void code_lengths(const std::vector<uint64_t>& hist, std::vector<uint8_t>& len) {
-  len.assign(NSYM, 0);
-  std::vector<int> present;
+// Work arrays of the code-length construction: a binary min-heap of live
+// nodes keyed by (weight, smallest symbol in the subtree), parents and depths
+// of the merge tree.  The key is unique among live nodes (the smallest symbol
+// of a subtree belongs to it alone), so any correct heap pops in one order.
+struct LenWork {
+  uint64_t hw[NSYM];
+  int32_t hmin[NSYM], hid[NSYM];
+  int32_t parent[2 * NSYM], depth[2 * NSYM], L[NSYM], present[NSYM];
+};
+
+inline bool heap_less(const LenWork& w, int a, int b) {
+  return w.hw[a] != w.hw[b] ? w.hw[a] < w.hw[b] : w.hmin[a] < w.hmin[b];
+}
+
+inline void heap_swap(LenWork& w, int a, int b) {
+  std::swap(w.hw[a], w.hw[b]);
+  std::swap(w.hmin[a], w.hmin[b]);
+  std::swap(w.hid[a], w.hid[b]);
+}
+
+inline void heap_up(LenWork& w, int i) {
+  while (i > 0) {
+    const int p = (i - 1) / 2;
+    if (!heap_less(w, i, p)) break;
+    heap_swap(w, i, p);
+    i = p;
+  }
+}
+
+inline void heap_down(LenWork& w, int n, int i) {
+  for (;;) {
+    const int l = 2 * i + 1, r = l + 1;
+    int m = i;
+    if (l < n && heap_less(w, l, m)) m = l;
+    if (r < n && heap_less(w, r, m)) m = r;
+    if (m == i) break;
+    heap_swap(w, i, m);
+    i = m;
+  }
+}
+
+// Huffman code lengths of the symbols with hist[s] > 0 (len[s] = 0 for the
+// others): merge the two smallest (weight, smallest symbol) keys until one
+// tree remains; lengths above 32 are cut to 32 and the longest codes below
+// 32 are lengthened (largest symbol first) until Kraft's sum is <= 1.
+void code_lengths(const uint64_t* hist, uint8_t* len, LenWork& w) {
+  std::memset(len, 0, NSYM);
+  int np = 0;
   for (int s = 0; s < NSYM; ++s)
-    if (hist[s]) present.push_back(s);
-  if (present.empty()) return;
-  if (present.size() == 1) {
-    len[present[0]] = 1;
+    if (hist[s]) w.present[np++] = s;
+  if (np == 0) return;
+  if (np == 1) {
+    len[w.present[0]] = 1;
     return;
   }
-  struct Node {
-    uint64_t w;
-    int minsym;
-    int id;
-  };
-  auto gt = [](const Node& a, const Node& b) { return a.w != b.w ? a.w > b.w : a.minsym > b.minsym; };
-  std::priority_queue<Node, std::vector<Node>, decltype(gt)> heap(gt);
-  std::vector<int> parent(2 * NSYM, -1);
-  for (int s : present) heap.push({hist[s], s, s});
+  int hn = 0;
+  for (int k = 0; k < np; ++k) {
+    const int s = w.present[k];
+    w.hw[hn] = hist[s];
+    w.hmin[hn] = s;
+    w.hid[hn] = s;
+    heap_up(w, hn++);
+  }
   int next = NSYM;
-  while (heap.size() > 1) {
-    const Node a = heap.top();
-    heap.pop();
-    const Node b = heap.top();
-    heap.pop();
-    parent[a.id] = next;
-    parent[b.id] = next;
-    heap.push({a.w + b.w, std::min(a.minsym, b.minsym), next});
+  while (hn > 1) {
+    const uint64_t aw = w.hw[0];
+    const int am = w.hmin[0], aid = w.hid[0];
+    heap_swap(w, 0, --hn);
+    heap_down(w, hn, 0);
+    const uint64_t bw = w.hw[0];
+    const int bm = w.hmin[0], bid = w.hid[0];
+    heap_swap(w, 0, --hn);
+    heap_down(w, hn, 0);
+    w.parent[aid] = next;
+    w.parent[bid] = next;
+    w.hw[hn] = aw + bw;
+    w.hmin[hn] = std::min(am, bm);
+    w.hid[hn] = next;
+    heap_up(w, hn++);
     ++next;
   }
-  std::vector<int> depth(next, -1);
-  depth[next - 1] = 0;
-  for (int v = next - 2; v >= NSYM; --v) depth[v] = depth[parent[v]] + 1;  // parents are created after children
-  std::vector<int> L(NSYM, 0);
+  w.depth[next - 1] = 0;
+  for (int v = next - 2; v >= NSYM; --v) w.depth[v] = w.depth[w.parent[v]] + 1;  // parents come after children
   int maxl = 0;
-  for (int s : present) {
-    L[s] = depth[parent[s]] + 1;
-    maxl = std::max(maxl, L[s]);
+  for (int k = 0; k < np; ++k) {
+    const int s = w.present[k];
+    w.L[s] = w.depth[w.parent[s]] + 1;
+    maxl = std::max(maxl, w.L[s]);
   }
   if (maxl > LMAX) {
-    // cap, then lengthen the longest codes below the cap until Kraft holds
     uint64_t kraft = 0;
-    for (int s : present) {
-      if (L[s] > LMAX) L[s] = LMAX;
-      kraft += uint64_t(1) << (LMAX - L[s]);
+    for (int k = 0; k < np; ++k) {
+      const int s = w.present[k];
+      if (w.L[s] > LMAX) w.L[s] = LMAX;
+      kraft += uint64_t(1) << (LMAX - w.L[s]);
     }
     while (kraft > (uint64_t(1) << LMAX)) {
       int best = -1;
-      for (int s : present)
-        if (L[s] < LMAX && (best < 0 || L[s] > L[best] || (L[s] == L[best] && s > best))) best = s;
-      kraft -= uint64_t(1) << (LMAX - L[best] - 1);
-      L[best] += 1;
+      for (int k = 0; k < np; ++k) {
+        const int s = w.present[k];
+        if (w.L[s] < LMAX && (best < 0 || w.L[s] > w.L[best] || (w.L[s] == w.L[best] && s > best))) best = s;
+      }
+      kraft -= uint64_t(1) << (LMAX - w.L[best] - 1);
+      w.L[best] += 1;
     }
   }
-  for (int s : present) len[s] = uint8_t(L[s]);
+  for (int k = 0; k < np; ++k) len[w.present[k]] = uint8_t(w.L[w.present[k]]);
 }
 
-void canonical(const std::vector<uint8_t>& len, std::vector<uint32_t>& code, std::vector<uint32_t>& sorted) {
-  code.assign(NSYM, 0);
-  sorted.clear();
+// Canonical codes in (length, symbol) order; sorted receives the coded
+// symbols in that order, *nsorted their count.
+void canonical(const uint8_t* len, uint32_t* code, uint32_t* sorted, int* nsorted) {
+  std::memset(code, 0, NSYM * sizeof(uint32_t));
+  int n = 0;
   for (int l = 1; l <= LMAX; ++l)
     for (int s = 0; s < NSYM; ++s)
-      if (len[s] == l) sorted.push_back(uint32_t(s));
+      if (len[s] == l) sorted[n++] = uint32_t(s);
   uint64_t c = 0;
   int prev = 0;
-  for (size_t i = 0; i < sorted.size(); ++i) {
+  for (int i = 0; i < n; ++i) {
     const int l = len[sorted[i]];
     if (i) c = (c + 1) << (l - prev);
     code[sorted[i]] = uint32_t(c);
     prev = l;
   }
+  *nsorted = n;
 }
 
 // stream header; the code-length table lists present symbols only:
@@ -359,8 +433,16 @@ StreamPlan plan_stream(const int32_t* codes, int64_t n, hipStream_t st, DevBuf<u
   std::vector<uint64_t> h(NSYM);
   BM_HIP(hipMemcpyAsync(h.data(), hist.p, NSYM * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
-  code_lengths(h, sp.len);
-  canonical(sp.len, sp.cw, sp.sorted);
+  {
+    auto work = std::make_unique<LenWork>();
+    sp.len.assign(NSYM, 0);
+    code_lengths(h.data(), sp.len.data(), *work);
+  }
+  sp.cw.assign(NSYM, 0);
+  sp.sorted.assign(NSYM, 0);
+  int ns = 0;
+  canonical(sp.len.data(), sp.cw.data(), sp.sorted.data(), &ns);
+  sp.sorted.resize(ns);
   BM_HIP(hipMemcpyAsync(dlen.p, sp.len.data(), NSYM, hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dcw.p, sp.cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   DevBuf<uint32_t> bits(size_t(std::max<int64_t>(nch, 1))), esc(size_t(std::max<int64_t>(nch, 1)));
@@ -417,8 +499,8 @@ size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t c
   BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   if (nch)
-    hipLaunchKernelGGL(k_encode, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p, dooff.p,
-                       dwords.p, doval.p);
+    hipLaunchKernelGGL(k_encode<false>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p,
+                       dooff.p, static_cast<void*>(dwords.p), static_cast<void*>(doval.p));
   BM_HIP(hipGetLastError());
   std::vector<uint16_t> psym;
   std::vector<uint8_t> plen;
@@ -490,8 +572,10 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
     if (len[s]) kraft += uint64_t(1) << (LMAX - len[s]);
   }
   if (kraft > (uint64_t(1) << LMAX)) fail(BM_ECORRUPT, "code lengths violate Kraft's inequality");
-  std::vector<uint32_t> cw, sorted;
-  canonical(len, cw, sorted);
+  std::vector<uint32_t> cw(NSYM), sorted(NSYM);
+  int ns = 0;
+  canonical(len.data(), cw.data(), sorted.data(), &ns);
+  sorted.resize(ns);
   std::vector<uint32_t> first(LMAX + 1, 0), count(LMAX + 1, 0), base(LMAX + 1, 0), lut(1u << LUTB, 0);
   for (size_t i = 0; i < sorted.size(); ++i) {
     const int l = len[sorted[i]];
@@ -532,6 +616,138 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   BM_HIP(hipMemcpyAsync(&herr, derr.p, sizeof(int), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
   if (herr) fail(BM_ECORRUPT, "Huffman stream does not decode");
+}
+
+// ------------------------------------------------------------------ no allocation
+// Huffman encoding into a device buffer with every work array fixed in size:
+// device scratch in one file-scope array (per GPU, held until the process
+// ends), host work arrays static.  Calls share both, so they are serialised
+// by a mutex on the host; calls on one GPU must not overlap in time (they
+// share that GPU's scratch).
+
+namespace {
+
+constexpr int64_t kNoAllocMaxCh = kNoAllocMaxCodes / CHUNK;
+constexpr size_t kScrHist = 0;                                         // uint64 [NSYM]
+constexpr size_t kScrLen = kScrHist + size_t(NSYM) * 8;                // uint8  [NSYM]
+constexpr size_t kScrCw = kScrLen + size_t(NSYM);                      // uint32 [NSYM]
+constexpr size_t kScrBits = kScrCw + size_t(NSYM) * 4;                 // uint32 [chunks]
+constexpr size_t kScrEsc = kScrBits + size_t(kNoAllocMaxCh) * 4;       // uint32 [chunks]
+constexpr size_t kScrWoff = kScrEsc + size_t(kNoAllocMaxCh) * 4;       // uint64 [chunks + 1]
+constexpr size_t kScrOoff = kScrWoff + size_t(kNoAllocMaxCh + 1) * 8;  // uint64 [chunks + 1]
+constexpr size_t kScratchBytes = kScrOoff + size_t(kNoAllocMaxCh + 1) * 8;
+static_assert(kScrCw % 4 == 0 && kScrWoff % 8 == 0 && kScrOoff % 8 == 0, "scratch alignment");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct NoAllocHost {
+  uint64_t hist[NSYM];
+  uint8_t len[NSYM];
+  uint32_t cw[NSYM], sorted[NSYM];
+  uint16_t psym[NSYM];
+  uint8_t plen[NSYM];
+  uint32_t bits[kNoAllocMaxCh], esc[kNoAllocMaxCh];
+  uint64_t woff[kNoAllocMaxCh + 1], ooff[kNoAllocMaxCh + 1];
+  LenWork work;
+};
+NoAllocHost g_na;
+std::mutex g_na_mu;
+constexpr int kMaxDevices = 64;
+unsigned char* g_scratch[kMaxDevices] = {};   // each GPU's copy of `scratch` (device address)
+
+unsigned char* scratch_ptr() {
+  int dev = 0;
+  BM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(BM_EUNSUPPORTED, "device index beyond 63");
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    BM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  return g_scratch[dev];
+}
+
+}  // namespace
+
+size_t huffman_encode_noalloc(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
+                              hipStream_t st) {
+  if (n < 0 || n > kNoAllocMaxCodes) fail(BM_EINVAL, "n outside [0, 2^28] for the entry point that does not allocate");
+  if (n > 0 && !codes) fail(BM_EINVAL, "null codes");
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  NoAllocHost& H = g_na;
+  unsigned char* scr = scratch_ptr();
+  auto* hist = reinterpret_cast<unsigned long long*>(scr + kScrHist);
+  auto* dlen = scr + kScrLen;
+  auto* dcw = reinterpret_cast<uint32_t*>(scr + kScrCw);
+  auto* bits = reinterpret_cast<uint32_t*>(scr + kScrBits);
+  auto* esc = reinterpret_cast<uint32_t*>(scr + kScrEsc);
+  auto* dwoff = reinterpret_cast<uint64_t*>(scr + kScrWoff);
+  auto* dooff = reinterpret_cast<uint64_t*>(scr + kScrOoff);
+  const int64_t nch = (n + CHUNK - 1) / CHUNK;
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, hist, int64_t(NSYM));
+  if (n) {
+    const int64_t g = std::min<int64_t>(2048, (n + 255) / 256);
+    hipLaunchKernelGGL(k_hist, dim3(unsigned(g)), dim3(256), 0, st, codes, n, hist);
+  }
+  BM_HIP(hipGetLastError());
+  BM_HIP(hipMemcpyAsync(H.hist, hist, sizeof(H.hist), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  code_lengths(H.hist, H.len, H.work);
+  int ns = 0;
+  canonical(H.len, H.cw, H.sorted, &ns);
+  BM_HIP(hipMemcpyAsync(dlen, H.len, sizeof(H.len), hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dcw, H.cw, sizeof(H.cw), hipMemcpyHostToDevice, st));
+  if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen, bits, esc);
+  BM_HIP(hipGetLastError());
+  if (nch) {
+    BM_HIP(hipMemcpyAsync(H.bits, bits, size_t(nch) * 4, hipMemcpyDeviceToHost, st));
+    BM_HIP(hipMemcpyAsync(H.esc, esc, size_t(nch) * 4, hipMemcpyDeviceToHost, st));
+  }
+  BM_HIP(hipStreamSynchronize(st));
+  H.woff[0] = 0;
+  H.ooff[0] = 0;
+  for (int64_t c = 0; c < nch; ++c) {
+    H.woff[c + 1] = H.woff[c] + (uint64_t(H.bits[c]) + 31) / 32;
+    H.ooff[c + 1] = H.ooff[c] + H.esc[c];
+  }
+  int64_t np = 0;
+  for (int s = 0; s < NSYM; ++s)
+    if (H.len[s]) {
+      H.psym[np] = uint16_t(s);
+      H.plen[np] = H.len[s];
+      ++np;
+    }
+  const int64_t nw = int64_t(H.woff[nch]), nout = int64_t(H.ooff[nch]);
+  HuffHeader hh{kHuffMagic, 3, n, nch, nw, nout, np};
+  const size_t off_tab = sizeof(hh), off_off = off_tab + size_t(np) * 3;
+  const size_t off_words = off_off + size_t(nch + 1) * 16, off_out = off_words + size_t(nw) * 4;
+  const size_t bytes = off_out + size_t(nout) * 4;
+  *out_bytes = bytes;
+  if (!out || capacity < bytes) fail(BM_ECAPACITY, "output buffer too small");
+  uint8_t* o = static_cast<uint8_t*>(out);
+  BM_HIP(hipMemcpyAsync(o, &hh, sizeof(hh), hipMemcpyHostToDevice, st));
+  if (np) {
+    BM_HIP(hipMemcpyAsync(o + off_tab, H.psym, size_t(np) * 2, hipMemcpyHostToDevice, st));
+    BM_HIP(hipMemcpyAsync(o + off_tab + size_t(np) * 2, H.plen, size_t(np), hipMemcpyHostToDevice, st));
+  }
+  BM_HIP(hipMemcpyAsync(o + off_off, H.woff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(o + off_off + size_t(nch + 1) * 8, H.ooff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dwoff, H.woff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dooff, H.ooff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
+  if (nch) {
+    void* wd = o + off_words;
+    void* od = o + off_out;
+    const bool aligned = (reinterpret_cast<uintptr_t>(wd) & 3) == 0;   // off_out - off_words is a multiple of 4
+    if (aligned)
+      hipLaunchKernelGGL(k_encode<false>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen, dcw, dwoff, dooff,
+                         wd, od);
+    else
+      hipLaunchKernelGGL(k_encode<true>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen, dcw, dwoff, dooff,
+                         wd, od);
+  }
+  BM_HIP(hipGetLastError());
+  BM_HIP(hipStreamSynchronize(st));
+  return bytes;
 }
 
 }  // namespace bm

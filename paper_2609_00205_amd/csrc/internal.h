@@ -365,6 +365,11 @@ size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t c
 // exact size of the stream huffman_encode would write (synchronizes)
 size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);
+// the encoder that allocates nothing: stream written to device memory, work
+// arrays of fixed size (at most kNoAllocMaxCodes codes)
+constexpr int64_t kNoAllocMaxCodes = int64_t(1) << 28;
+size_t huffman_encode_noalloc(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
+                              hipStream_t st);
 
 // RAII event pair around the work of one timing slot (no-op unless timing is on)
 struct TimedScope {
