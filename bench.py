@@ -975,86 +975,37 @@ def run_paper8(args):
 
 
 def run_eq1(args):
-    """Eq. 1 (Sec. IV-B) re-fitted on this GPU.  A stage's time on N units is
-    t(N) = 1/Slope + N/TP_peak, i.e. throughput N / t(N) = N / (1/Slope +
-    N/TP_peak); a least-squares line of t against N gives Slope, TP_peak and
-    the knee N = TP_peak / Slope where half the peak is reached.  Stages: one
-    fused 17^3 block level (N = blocks), one fused global level (N = nodes of
-    its grid), the Huffman stage (N = codes, host-side wall time of the whole
-    encode).  The fitted stages then predict the fused decompose + quantize
-    time of (L, M) splits of the 512^3 workload, next to the measured time:
-    the prediction Algorithm 1 would select on."""
+    """Eq. 1 and Algorithm 1 (Sec. IV-B) on this GPU.  The library fits its
+    stage models on the device (bm_model_calibrate: block levels by Eq. 1,
+    global levels and Huffman stages by lines, quantization by
+    max(slope N, T_lat)); then every admissible (L, M) of the 512^3 workload
+    is predicted (bm_model_predict) and measured (fused decompose + quantize,
+    HIP events; the lossless stage by host wall time of the Huffman coder),
+    and Algorithm 1 picks (L, M) from the predictions alone under a range of
+    time budgets (bm_select_levels)."""
     import numpy as np
     import torch
 
-    from paper_2609_00205_amd import Plan, synth, api
+    from paper_2609_00205_amd import Plan, api, synth
 
     torch.cuda.set_device(0)
     reps = max(3, args.steps)
-
-    def timed_level(plan, x, bt, level):
-        codes = torch.empty(plan.coeff_shape, dtype=torch.int32, device="cuda")
-        for _ in range(2):
-            plan.decompose_quantize(x, bt, codes=codes, check=False)
-        torch.cuda.synchronize()
-        plan.timing(True)
-        for _ in range(reps):
-            plan.decompose_quantize(x, bt, codes=codes, check=False)
-        torch.cuda.synchronize()
-        t = plan.timing_get()
-        plan.timing(False)
-        return t["decompose"][level] / reps
-
-    def fit(Ns, ts):
-        b, a = np.polyfit(np.asarray(Ns, float), np.asarray(ts, float), 1)   # t = a + b N
-        return {"slope_per_ms": 1.0 / a if a > 0 else None, "tp_peak_per_ms": 1.0 / b,
-                "latency_ms": a, "knee_N": (1.0 / b) / (1.0 / a) if a > 0 else None,
-                "points": [{"N": int(n), "ms": round(float(t), 5)} for n, t in zip(Ns, ts)]}
-
-    local_N, local_t = [], []
-    for k in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32):
-        n = 16 * k + 1
-        x = torch.from_numpy(synth.gaussian_random_field((n, n, n), 3.0, seed=7)).cuda()
-        p = Plan((n, n, n), dtype=torch.float32, block=17, L=1, M=0)
-        bt = p.tolmap_from_boxes([], 1e-2 * float(x.abs().max()))
-        local_N.append(k ** 3)
-        local_t.append(timed_level(p, x, bt, 0))
-        print(f"[bench] block level, {k ** 3} blocks: {local_t[-1]:.4f} ms", file=sys.stderr, flush=True)
-        del p, x, bt
-    glob_N, glob_t = [], []
-    for j in range(4, 10):
-        n = (1 << j) + 1
-        x = torch.from_numpy(synth.gaussian_random_field((n, n, n), 3.0, seed=8)).cuda()
-        p = Plan((n, n, n), dtype=torch.float32, block=17, L=0, M=1)
-        bt = p.tolmap_from_boxes([], 1e-2 * float(x.abs().max()))
-        glob_N.append(n ** 3)
-        glob_t.append(timed_level(p, x, bt, 0))
-        print(f"[bench] global level, {n}^3 nodes: {glob_t[-1]:.4f} ms", file=sys.stderr, flush=True)
-        del p, x, bt
-    huf_N, huf_t = [], []
-    rng = np.random.default_rng(9)
-    for e in range(16, 28, 2):
-        nc = 1 << e
-        q = torch.from_numpy(np.rint(rng.laplace(0, 4.0, nc)).astype(np.int32)).cuda()
-        api.huffman_encode(q)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            api.huffman_encode(q)
-        huf_N.append(nc)
-        huf_t.append((time.perf_counter() - t0) * 1e3 / reps)
-        print(f"[bench] Huffman, {nc} codes: {huf_t[-1]:.3f} ms", file=sys.stderr, flush=True)
-    fl, fg, fh = fit(local_N, local_t), fit(glob_N, glob_t), fit(huf_N, huf_t)
-
-    # predicted vs measured fused decompose + quantize of the 512^3 workload
+    print("[bench] calibrating the stage models", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    model = api.model_calibrate(torch.float32, 17)
+    cal_s = time.perf_counter() - t0
     n = args.n
+    shape = (n, n, n)
     x_np, boxes = synth.workload_roi(n, seed=2)
     xd = torch.from_numpy(x_np).cuda()
     scale = float(xd.abs().max())
     abs_boxes = [bx + (1e-5 * scale,) for bx in boxes]
+    _, cands = api.select_levels(shape, 1e9, model)
     rows = []
-    for (L, M) in ((1, 0), (1, 1), (1, 2), (2, 0), (2, 2), (3, 0), (3, 2), (4, 0)):
-        p = Plan((n, n, n), dtype=torch.float32, block=17, L=L, M=M)
+    worst = 0.0
+    for c in cands:
+        L, M = c["L"], c["M"]
+        p = Plan(shape, dtype=torch.float32, block=17, L=L, M=M)
         bt = p.tolmap_from_boxes(abs_boxes, 1e-2 * scale)
         codes = torch.empty(p.coeff_shape, dtype=torch.int32, device="cuda")
         for _ in range(2):
@@ -1067,35 +1018,47 @@ def run_eq1(args):
         e1.record()
         torch.cuda.synchronize()
         measured = e0.elapsed_time(e1) / reps
-        pred = 0.0
-        m = p.coeff_shape[0]
-        for s in range(1, L + M + 1):
-            if s <= L:
-                nb = ((m - 1) // 16) ** 3
-                pred += fl["latency_ms"] + nb / fl["tp_peak_per_ms"]
-            else:
-                pred += fg["latency_ms"] + m ** 3 / fg["tp_peak_per_ms"]
-            m = (m + 1) // 2
-        rows.append({"L": L, "M": M, "predicted_ms": round(pred, 4), "measured_ms": round(measured, 4)})
-        print(f"[bench] L={L} M={M}: predicted {pred:.4f} ms, measured {measured:.4f} ms", file=sys.stderr, flush=True)
+        api.huffman_encode(codes)
+        t1 = time.perf_counter()
+        api.huffman_encode(codes)
+        lossless = (time.perf_counter() - t1) * 1e3
+        pred = api.model_predict(model, shape, L, M)
+        pdq = pred["decompose"] + pred["quantize"]
+        err = abs(pdq - measured) / measured
+        worst = max(worst, err)
+        rows.append({"L": L, "M": M, "predicted_decompose_quantize_ms": round(pdq, 4),
+                     "measured_decompose_quantize_ms": round(measured, 4), "error": round(err, 3),
+                     "predicted_lossless_ms": round(pred["lossless"], 3), "measured_lossless_ms": round(lossless, 3),
+                     "predicted_total_ms": round(pred["total"], 3)})
+        print(f"[bench] L={L} M={M}: predicted {pdq:.4f} ms, measured {measured:.4f} ms; lossless predicted "
+              f"{pred['lossless']:.2f} ms, measured {lossless:.2f} ms", file=sys.stderr, flush=True)
         del p, codes, bt
+    totals = sorted(r["predicted_total_ms"] for r in rows)
+    budgets = [round(totals[0] * 0.9, 3)] + [round(t * 1.001, 3) for t in totals[::max(1, len(totals) // 6)]]
+    choices = []
+    for b in budgets:
+        ch, _ = api.select_levels(shape, b, model)
+        choices.append({"budget_ms": b, "L": ch["L"], "M": ch["M"], "fits": ch["fits"]})
     out = {
-        "metric": "Eq. 1 throughput model re-fitted on this GPU (Slope, TP_peak per stage)",
-        "value": round(fl["tp_peak_per_ms"], 3),
-        "unit": "17^3 blocks per ms (block level TP_peak)",
+        "metric": "Algorithm 1 on the fitted time model: worst error of predicted decompose + quantize time",
+        "value": round(worst, 4),
+        "unit": "relative error (max over admissible (L, M) at 512^3)",
         "n_gpus": 1,
         "steps": reps,
         "warmup": 2,
         "ms_per_step": None,
-        "higher_is_better": True,
+        "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "k^-3 Gaussian random fields, cubes of 17..513 nodes per side, REL 1e-2; "
-                               "Laplace-distributed codes for the Huffman stage; 512^3 ROI workload for the (L, M) check"},
-        "block_level": fl, "global_level": fg, "huffman": fh,
+        "config": {"workload": "model fits on synthetic cubes (1..32 blocks of 17^3, global grids 17^3..513^3, "
+                               "2^16..2^26 codes); predictions checked on the 512^3 FP32 ROI workload"},
+        "calibration_s": round(cal_s, 2),
+        "model": {k: (v if not isinstance(v, torch.dtype) else str(v)) for k, v in model.items()},
+        "knee_blocks": model["blk_tp"] * model["blk_lat_ms"],
         "predicted_vs_measured": rows,
+        "algorithm1_choices": choices,
     }
     print(json.dumps(out), flush=True)
 

@@ -374,13 +374,63 @@ bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_to
  * (Sec. IV-B) under a time budget: of the candidates whose fused decompose +
  * quantize time (median of reps) is at most budget_ms, the one with the
  * most global levels M, then the fewest block levels L, then the best ratio
- * (between block sizes).  The lossless stage is left out of the budget: its
- * time depends on the number of codes, the same for every candidate.
+ * (between block sizes).  budget_ms bounds the measured transform and
+ * quantization only; the lossless stage is not timed per candidate (its cost
+ * varies with the padded node count and the code histogram).
+ * bm_select_levels applies the same rule to predicted times of all three
+ * stages.
  * Errors: BM_ERANGE when no candidate fits (*out, the table and *ncands are
  * still filled, *out with the fastest candidate), BM_EINVAL (budget not
  * positive, no admissible candidate).  Synchronous. */
 bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* voxel_tol, double budget_ms, int reps,
                              bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
+
+/* ---- choice of (L, M) from a time model (Sec. IV-B, Eq. 1, Algorithm 1) -- */
+
+/* Fitted stage times of the pipeline for one dtype and block size (ms, N as
+ * noted).  Eq. 1: a block level of N blocks takes 1/Slope + N/TP_peak, i.e.
+ * blk_lat_ms + N / blk_tp (blk_tp = TP_peak in blocks per ms, Slope =
+ * 1/blk_lat_ms); the last block level before a global level (it forms that
+ * level's details and partial load vectors) has its own fit (fblk_*).  A
+ * global level of N nodes takes glob_a_ms + glob_b_ms N; the first global
+ * level after a block level, which only gathers and solves, fglob_*.
+ * Quantization: max(q_slope_ms N, q_lat_ms), N = padded nodes.  Lossless:
+ * stage k of the Huffman coder (0 histogram, 1 code table, 2 chunk sizes and
+ * encode, 3 copy-out and CRC) takes huf_a_ms[k] + huf_b_ms[k] N for N codes. */
+typedef struct {
+  int dtype, block;
+  double blk_lat_ms, blk_tp;
+  double fblk_lat_ms, fblk_tp;
+  double fglob_a_ms, fglob_b_ms;
+  double glob_a_ms, glob_b_ms;
+  double q_slope_ms, q_lat_ms;
+  double huf_a_ms[4], huf_b_ms[4];
+} bm_model;
+
+/* Fits every stage of *out on this device (the device current at the call):
+ * each stage runs on synthetic inputs of growing size (cubes of 1 to 32
+ * blocks per side, global grids 17^3 to 513^3, 2^16 to 2^26 codes), timed by
+ * HIP events and host clocks, and a least-squares line is taken through the
+ * (N, time) points.  Synchronous; takes a few seconds and about 2 GB of
+ * device memory.  Errors: BM_EINVAL (dtype, block not 9/17/33). */
+bm_status bm_model_calibrate(int dtype, int block, bm_model* out, hipStream_t stream);
+
+/* Predicted times of cfg under the model (its dtype and block replace
+ * cfg's): ms[0] decomposition (sum over the levels), ms[1] quantization,
+ * ms[2] lossless stage, ms[3] their sum.  Host only. */
+bm_status bm_model_predict(const bm_model* model, const bm_config* cfg, double ms[4]);
+
+/* Algorithm 1 (Sec. IV-B) on the model's predictions alone: among the (L, M)
+ * with L in 0..4, M in 0..6 that the dims admit (a valid plan padding the
+ * volume by at most 1/8), those whose predicted total time is at most
+ * budget_ms; of them the one with the most global levels M, then the fewest
+ * block levels L.  *out = *in with block, L, M set (nested = 0); cands
+ * (optional, cap entries) receives every candidate with its predicted time in
+ * ms (ratio 0, not measured).  Host only.  BM_ERANGE when none fits (*out
+ * then holds the fastest predicted candidate); BM_EINVAL (budget not positive
+ * and finite, no admissible candidate). */
+bm_status bm_select_levels(const bm_config* in, const bm_model* model, double budget_ms, bm_config* out,
+                           bm_candidate* cands, int cap, int* ncands);
 
 /* ---- the paper's own block form (Sec. IV-A, IV-C) ------------------------ */
 

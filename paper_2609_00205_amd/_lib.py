@@ -30,6 +30,14 @@ class BMCandidate(C.Structure):
                 ("ratio", C.c_double), ("nested", C.c_int)]
 
 
+class BMModel(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("block", C.c_int), ("blk_lat_ms", C.c_double), ("blk_tp", C.c_double),
+                ("fblk_lat_ms", C.c_double), ("fblk_tp", C.c_double), ("fglob_a_ms", C.c_double),
+                ("fglob_b_ms", C.c_double), ("glob_a_ms", C.c_double), ("glob_b_ms", C.c_double),
+                ("q_slope_ms", C.c_double), ("q_lat_ms", C.c_double), ("huf_a_ms", C.c_double * 4),
+                ("huf_b_ms", C.c_double * 4)]
+
+
 class BMError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -44,6 +52,10 @@ _SIGS = {
     "bm_plan_create": [C.POINTER(BMConfig), C.POINTER(P)],
     "bm_plan_destroy": [P],
     "bm_coeff_shape": [P, C.POINTER(C.c_int64)],
+    "bm_model_calibrate": [C.c_int, C.c_int, C.POINTER(BMModel), P],
+    "bm_model_predict": [C.POINTER(BMModel), C.POINTER(BMConfig), C.POINTER(C.c_double)],
+    "bm_select_levels": [C.POINTER(BMConfig), C.POINTER(BMModel), C.c_double, C.POINTER(BMConfig),
+                         C.POINTER(BMCandidate), C.c_int, C.POINTER(C.c_int)],
     "bm_plan_config": [P, C.POINTER(BMConfig)],
     "bm_block_grid": [P, C.POINTER(C.c_int64)],
     "bm_level_gains": [P, C.POINTER(C.c_double)],

@@ -410,6 +410,64 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
     return choice, cands
 
 
+_MODEL_KEYS = ["blk_lat_ms", "blk_tp", "fblk_lat_ms", "fblk_tp", "fglob_a_ms", "fglob_b_ms", "glob_a_ms",
+               "glob_b_ms", "q_slope_ms", "q_lat_ms"]
+
+
+def _model_struct(model: dict) -> "_lib.BMModel":
+    m = _lib.BMModel()
+    m.dtype = _DT[model["dtype"]] if not isinstance(model["dtype"], int) else model["dtype"]
+    m.block = int(model["block"])
+    for k in _MODEL_KEYS:
+        setattr(m, k, float(model[k]))
+    for k in range(4):
+        m.huf_a_ms[k] = float(model["huf_a_ms"][k])
+        m.huf_b_ms[k] = float(model["huf_b_ms"][k])
+    return m
+
+
+def model_calibrate(dtype=torch.float32, block: int = 17, stream=None) -> dict:
+    """Stage fits of the time model on the current device (bm_model_calibrate)."""
+    m = _lib.BMModel()
+    call("bm_model_calibrate", _DT[dtype], int(block), C.byref(m), _stream(stream))
+    out = {"dtype": dtype, "block": m.block}
+    for k in _MODEL_KEYS:
+        out[k] = float(getattr(m, k))
+    out["huf_a_ms"] = [float(m.huf_a_ms[k]) for k in range(4)]
+    out["huf_b_ms"] = [float(m.huf_b_ms[k]) for k in range(4)]
+    return out
+
+
+def _cfg(shape, dtype, block, L=1, M=0):
+    return BMConfig(3, (C.c_int64 * 3)(*[int(v) for v in shape]), _DT[dtype], int(block), int(L), int(M), 0,
+                    DEFAULT_ETA[dtype])
+
+
+def model_predict(model: dict, shape, L: int, M: int) -> dict:
+    """Predicted stage times (ms) of (model's block, L, M) on shape (bm_model_predict)."""
+    ms = (C.c_double * 4)()
+    cfg = _cfg(shape, model["dtype"], model["block"], L, M)
+    call("bm_model_predict", C.byref(_model_struct(model)), C.byref(cfg), ms)
+    return {"decompose": ms[0], "quantize": ms[1], "lossless": ms[2], "total": ms[3]}
+
+
+def select_levels(shape, budget_ms: float, model: dict):
+    """Algorithm 1 on the model's predictions (bm_select_levels): returns
+    ({"block", "L", "M", "fits"}, [{"block", "L", "M", "ms"}...])."""
+    cfg = _cfg(shape, model["dtype"], model["block"])
+    out = BMConfig()
+    cap = 64
+    table = (_lib.BMCandidate * cap)()
+    n = C.c_int(0)
+    st = _lib.lib().bm_select_levels(C.byref(cfg), C.byref(_model_struct(model)), float(budget_ms), C.byref(out),
+                                     table, cap, C.byref(n))
+    if st not in (0, _lib.BM_ERANGE):
+        _lib.check(st)
+    cands = [{"block": table[i].block, "L": table[i].L, "M": table[i].M, "ms": table[i].ms}
+             for i in range(min(n.value, cap))]
+    return {"block": out.block, "L": out.L, "M": out.M, "fits": st == 0}, cands
+
+
 class Paper8Plan:
     """The paper's own block form: disjoint 8^3 blocks, L block levels whose
     5^3 coarse outputs are re-assembled into the next level's blocks.

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libblockmgard.so")
 
-SOURCES = ["plan.cpp", "api.cpp", "local_level.hip", "global_level.hip", "quantize.hip", "huffman.hip", "adjoint.hip", "wide_block.hip", "batch.cpp", "autotune.cpp", "paper8.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "local_level.hip", "global_level.hip", "quantize.hip", "huffman.hip", "adjoint.hip", "wide_block.hip", "batch.cpp", "autotune.cpp", "paper8.hip", "model.hip"]
 
 # Packed FP32 instructions are kept off (-packed-fp32-ops); gfx950 only.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -809,7 +809,9 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
   });
 }
 
-static void drain_timing(bm_plan_s& p) {
+extern "C++" {
+namespace bm {
+void drain_timing(bm_plan_s& p) {
   for (auto& e : p.timing.pending) {
     float ms = 0.f;
     if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess &&
@@ -821,6 +823,43 @@ static void drain_timing(bm_plan_s& p) {
     (void)hipEventDestroy(e.b);
   }
   p.timing.pending.clear();
+}
+uint32_t container_crc(const uint8_t* p, size_t n) { return crc32_parallel(p, n, 0); }
+}  // namespace bm
+}  // extern "C++"
+using bm::drain_timing;
+
+bm_status bm_model_calibrate(int dtype, int block, bm_model* out, hipStream_t st) {
+  return guarded([&] {
+    need(out != nullptr, "null model");
+    bm_model m{};
+    bm::model_calibrate(dtype, block, m, st);
+    *out = m;
+  });
+}
+
+bm_status bm_model_predict(const bm_model* model, const bm_config* cfg, double ms[4]) {
+  return guarded([&] {
+    need(model && cfg && ms, "null argument");
+    double t[4];
+    bm::model_predict(*model, *cfg, t);
+    for (int k = 0; k < 4; ++k) ms[k] = t[k];
+  });
+}
+
+bm_status bm_select_levels(const bm_config* in, const bm_model* model, double budget_ms, bm_config* out,
+                           bm_candidate* cands, int cap, int* ncands) {
+  return guarded([&] {
+    need(in && model && out, "null argument");
+    std::vector<bm_candidate> c;
+    bm_config o{};
+    const bool fits = bm::select_levels(*in, *model, budget_ms, o, c);
+    *out = o;
+    if (ncands) *ncands = int(c.size());
+    if (cands)
+      for (int k = 0; k < cap && k < int(c.size()); ++k) cands[k] = c[k];
+    if (!fits) bm::fail(BM_ERANGE, "no (L, M) fits the time budget; *out holds the fastest predicted");
+  });
 }
 
 bm_status bm_timing(bm_plan p, int enable) {

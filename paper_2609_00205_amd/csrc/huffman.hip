@@ -19,6 +19,7 @@
 // codebook is built on the host.
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -616,6 +617,86 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   BM_HIP(hipMemcpyAsync(&herr, derr.p, sizeof(int), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
   if (herr) fail(BM_ECORRUPT, "Huffman stream does not decode");
+}
+
+// ------------------------------------------------------------------ stage times
+// The encoder's stages timed one by one (the lossless part of the time model
+// of Algorithm 1): histogram, code table, chunk sizes + encode, copy-out + CRC.
+void huffman_stage_times(const int32_t* codes, int64_t n, hipStream_t st, double ms[4]) {
+  using clk = std::chrono::steady_clock;
+  auto since = [](clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); };
+  hipEvent_t e0, e1;
+  BM_HIP(hipEventCreate(&e0));
+  BM_HIP(hipEventCreate(&e1));
+  auto elapsed = [&]() {
+    BM_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    BM_HIP(hipEventElapsedTime(&t, e0, e1));
+    return double(t);
+  };
+  const int64_t nch = (n + CHUNK - 1) / CHUNK;
+  DevBuf<unsigned long long> hist(NSYM);
+  DevBuf<uint8_t> dlen(NSYM);
+  DevBuf<uint32_t> dcw(NSYM);
+  DevBuf<uint32_t> bits(size_t(std::max<int64_t>(nch, 1))), esc(size_t(std::max<int64_t>(nch, 1)));
+  // (0) histogram
+  BM_HIP(hipEventRecord(e0, st));
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, hist.p, int64_t(NSYM));
+  if (n) hipLaunchKernelGGL(k_hist, dim3(unsigned(std::min<int64_t>(2048, (n + 255) / 256))), dim3(256), 0, st, codes, n,
+                            hist.p);
+  BM_HIP(hipEventRecord(e1, st));
+  ms[0] = elapsed();
+  // (1) code table on the host
+  auto t1 = clk::now();
+  std::vector<uint64_t> h(NSYM);
+  BM_HIP(hipMemcpyAsync(h.data(), hist.p, NSYM * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  auto work = std::make_unique<LenWork>();
+  std::vector<uint8_t> len(NSYM);
+  std::vector<uint32_t> cw(NSYM), sorted(NSYM);
+  int ns = 0;
+  code_lengths(h.data(), len.data(), *work);
+  canonical(len.data(), cw.data(), sorted.data(), &ns);
+  ms[1] = since(t1);
+  // (2) chunk sizes, offsets on the host, encode
+  auto t2 = clk::now();
+  BM_HIP(hipMemcpyAsync(dlen.p, len.data(), NSYM, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dcw.p, cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, bits.p, esc.p);
+  std::vector<uint32_t> hb(nch), he(nch);
+  if (nch) {
+    BM_HIP(hipMemcpyAsync(hb.data(), bits.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    BM_HIP(hipMemcpyAsync(he.data(), esc.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  }
+  BM_HIP(hipStreamSynchronize(st));
+  std::vector<uint64_t> woff(nch + 1, 0), ooff(nch + 1, 0);
+  for (int64_t c = 0; c < nch; ++c) {
+    woff[c + 1] = woff[c] + (uint64_t(hb[c]) + 31) / 32;
+    ooff[c + 1] = ooff[c] + he[c];
+  }
+  const int64_t nw = int64_t(woff[nch]), nout = int64_t(ooff[nch]);
+  DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
+  DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
+  DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
+  BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  if (nch)
+    hipLaunchKernelGGL(k_encode<false>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p,
+                       dooff.p, static_cast<void*>(dwords.p), static_cast<void*>(doval.p));
+  BM_HIP(hipGetLastError());
+  BM_HIP(hipStreamSynchronize(st));
+  ms[2] = since(t2);
+  // (3) the stream to the host and its CRC
+  auto t3 = clk::now();
+  std::vector<uint8_t> out(size_t(nw) * 4 + size_t(nout) * 4 + 16);
+  if (nw) BM_HIP(hipMemcpyAsync(out.data(), dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, st));
+  if (nout) BM_HIP(hipMemcpyAsync(out.data() + size_t(nw) * 4, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, st));
+  BM_HIP(hipStreamSynchronize(st));
+  volatile uint32_t crc = container_crc(out.data(), out.size());
+  (void)crc;
+  ms[3] = since(t3);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 // ------------------------------------------------------------------ no allocation

@@ -365,6 +365,19 @@ size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t c
 // exact size of the stream huffman_encode would write (synchronizes)
 size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);
+// Stage times of the Huffman encoder for n codes (ms): histogram (device),
+// code table (host), chunk sizes and encode (device, with the host's offsets),
+// copy of the stream to the host and its CRC-32.
+void huffman_stage_times(const int32_t* codes, int64_t n, hipStream_t st, double ms[4]);
+// time model of the pipeline and Algorithm 1 (model.hip)
+void model_calibrate(int dtype, int b, bm_model& m, hipStream_t st);
+void model_predict(const bm_model& m, const bm_config& cfg, double out[4]);
+bool select_levels(const bm_config& in, const bm_model& m, double budget_ms, bm_config& out,
+                   std::vector<bm_candidate>& cands);
+// waits for a plan's recorded timing events and adds them to its totals
+void drain_timing(bm_plan_s& p);
+// CRC-32 of the container (zlib's polynomial), on host threads
+uint32_t container_crc(const uint8_t* p, size_t n);
 // the encoder that allocates nothing: stream written to device memory, work
 // arrays of fixed size (at most kNoAllocMaxCodes codes)
 constexpr int64_t kNoAllocMaxCodes = int64_t(1) << 28;
