@@ -279,9 +279,41 @@ bm_status bm_huffman_encode_device(const int32_t* codes, int64_t n, void* out, s
                                    hipStream_t stream);
 
 /* Inverse of bm_huffman_encode into codes (device, n entries).  Synchronous.
- * Errors: BM_ECORRUPT for a malformed stream, BM_EINVAL if n mismatches. */
+ * Each chunk is decoded by one wavefront whose lanes split its bits.
+ * Errors: BM_ECORRUPT for a malformed stream (a chunk that does not decode
+ * to exactly its 4096 symbols within its own words, or to its outlier
+ * count), BM_EINVAL if n mismatches. */
 bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int64_t n,
                             hipStream_t stream);
+
+/* The code lengths of the lossless stage's canonical Huffman code for a
+ * symbol histogram, on the host (no GPU; the step the encoder runs between
+ * its histogram and its chunk sizes, Sec. IV-B).  hist: 65536 counts
+ * (symbol q + 32768 for |q| < 32768, symbol 0 the escape), len: 65536 code
+ * lengths out (0 for absent symbols).  Huffman's algorithm merging the two
+ * smallest (weight, smallest symbol in the subtree) keys; lengths above 32
+ * cut to 32, then the longest codes below 32 lengthened (largest symbol
+ * first) until Kraft's sum is <= 1.  Errors: BM_EINVAL for a null pointer. */
+bm_status bm_huffman_code_lengths(const uint64_t* hist, uint8_t* len);
+
+/* Stage times (ms) of the calling thread's last Huffman encode (by
+ * bm_huffman_encode, bm_compress or bm_batch_compress) and last decode (by
+ * bm_huffman_decode or bm_decompress), the lossless stages of Sec. IV-B.
+ * Device stages are timed with events on the call's stream, host stages with
+ * a steady clock.  Encode: enc_hist (histogram, device), enc_table (code
+ * lengths and canonical codes, host), enc_sizes (per-chunk bit and escape
+ * counts on the device, offsets on the host), enc_encode (device),
+ * enc_copy (the stream's words and outliers to the host), enc_crc (the
+ * container's CRC-32 on host threads; 0 outside bm_compress).  Decode:
+ * dec_parse (header checks and decode tables, host), dec_upload (tables,
+ * offsets, words and outliers to the device), dec_decode (device).  enc_n
+ * and dec_n: symbols of those calls (0: none yet).  Never fails. */
+typedef struct {
+  double enc_hist_ms, enc_table_ms, enc_sizes_ms, enc_encode_ms, enc_copy_ms, enc_crc_ms;
+  double dec_parse_ms, dec_upload_ms, dec_decode_ms;
+  int64_t enc_n, dec_n;
+} bm_lossless_times;
+bm_status bm_lossless_last_times(bm_lossless_times* out);
 
 /* ---- end to end (Sec. IV, V-F) -------------------------------------------- */
 
@@ -290,8 +322,10 @@ bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int
  * block tolerance map, Huffman stream, CRC-32 (polynomial 0xEDB88320, as
  * zlib) of the header with its CRC field zeroed followed by the payload.  If
  * the coded form is not smaller than the raw data the raw bytes are stored
- * instead (Sec. V-F).  Synchronous.  BM_ECAPACITY sets *out_bytes to the
- * size needed (that call plans the stream's size but does not encode it).
+ * instead (Sec. V-F).  Synchronous.  The stream is planned once (histogram,
+ * code table, chunk sizes) and encoded straight into out.  BM_ECAPACITY sets
+ * *out_bytes to the size needed (that call plans the stream but does not
+ * encode it).
  * BM_ENONFINITE: NaN or Inf in x or in block_tol (nothing is written). */
 bm_status bm_compress(bm_plan plan, const void* x, const double* block_tol, void* out,
                       size_t capacity, size_t* out_bytes, hipStream_t stream);

@@ -6,7 +6,7 @@ arguments.  Importing it does not load the library; the first call does,
 and raises if the library has not been built.
 """
 __all__ = ["Plan", "Paper8Plan", "Batch", "autotune", "decompress", "compressed_config", "huffman_encode",
-           "huffman_decode", "huffman_encode_device", "model_calibrate", "model_predict",
+           "huffman_decode", "huffman_encode_device", "lossless_times", "huffman_code_lengths", "model_calibrate", "model_predict",
            "select_levels", "DecomposeFn", "RecomposeFn"]
 
 

@@ -38,6 +38,12 @@ class BMModel(C.Structure):
                 ("huf_b_ms", C.c_double * 4)]
 
 
+class BMLosslessTimes(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("enc_hist_ms", "enc_table_ms", "enc_sizes_ms", "enc_encode_ms",
+                                          "enc_copy_ms", "enc_crc_ms", "dec_parse_ms", "dec_upload_ms",
+                                          "dec_decode_ms")] + [("enc_n", C.c_int64), ("dec_n", C.c_int64)]
+
+
 class BMError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -69,6 +75,8 @@ _SIGS = {
     "bm_dequantize": [P, P, P, P, P],
     "bm_huffman_encode": [P, C.c_int64, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_huffman_decode": [P, C.c_size_t, P, C.c_int64, P],
+    "bm_lossless_last_times": [C.POINTER(BMLosslessTimes)],
+    "bm_huffman_code_lengths": [P, P],
     "bm_huffman_encode_device": [P, C.c_int64, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_compress": [P, P, P, P, C.c_size_t, C.POINTER(C.c_size_t), P],
     "bm_compressed_config": [P, C.c_size_t, C.POINTER(BMConfig)],

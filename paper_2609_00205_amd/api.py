@@ -352,6 +352,27 @@ def huffman_decode(buf, n: int, device=None, stream=None) -> torch.Tensor:
     return out
 
 
+def huffman_code_lengths(hist):
+    """Code lengths (uint8 [65536]) of the lossless stage for a histogram of
+    65536 symbol counts (bm_huffman_code_lengths; host only)."""
+    import numpy as np
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    if h.shape != (65536,):
+        raise ValueError("hist: 65536 counts")
+    out = np.zeros(65536, np.uint8)
+    call("bm_huffman_code_lengths", h.ctypes.data, out.ctypes.data)
+    return out
+
+
+def lossless_times() -> dict:
+    """Stage times (ms) of this thread's last Huffman encode and decode
+    (bm_lossless_last_times): enc_hist, enc_table, enc_sizes, enc_encode,
+    enc_copy, enc_crc, dec_parse, dec_upload, dec_decode, plus enc_n, dec_n."""
+    t = _lib.BMLosslessTimes()
+    call("bm_lossless_last_times", C.byref(t))
+    return {f: getattr(t, f) for f, _ in t._fields_}
+
+
 def parse_huffman(buf: bytes) -> dict:
     """Split a bm_huffman_encode stream into its arrays (layout in blockmgard.h)."""
     import numpy as np

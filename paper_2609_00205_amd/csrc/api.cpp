@@ -3,6 +3,7 @@
 // transform -> quantize -> lossless; raw copy of incompressible data,
 // Sec. V-F).
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -226,7 +227,9 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
   // the stream's size first (histogram and code plan only); the encode runs
   // only when the container is written, straight into the caller's buffer
   const int32_t* codes = static_cast<const int32_t*>(p.ws.codes);
-  const size_t sb = too_fine ? 0 : huffman_size(codes, npad, st);
+  std::unique_ptr<HuffmanEncoder> enc;
+  if (!too_fine) enc = std::make_unique<HuffmanEncoder>(codes, npad, st);
+  const size_t sb = enc ? enc->bytes() : 0;
   BM_HIP(hipStreamSynchronize(st));
   CHeader h{};
   h.magic = kMagic;
@@ -254,12 +257,14 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
     BM_HIP(hipStreamSynchronize(st));
   } else {
     std::memcpy(o, tol.data(), size_t(ntol) * 8);
-    huffman_encode_to(codes, npad, o + size_t(ntol) * 8, sb, st);
+    enc->write(o + size_t(ntol) * 8, sb);
   }
   h.crc = 0;
+  const auto t0 = std::chrono::steady_clock::now();
   uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
   c = crc32_parallel(o, size_t(h.payload), c);
   h.crc = c;
+  if (enc) set_lossless_crc_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   std::memcpy(out, &h, sizeof(h));
   return true;
 }
@@ -282,7 +287,9 @@ bool write_container_p8(bm_p8_s& p, const void* x, const double* block_tol, doub
   BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
   const int32_t* codes = p8_codes(p);
   const int64_t ncodes = p8_coeff_size(p);
-  const size_t sb = too_fine ? 0 : huffman_size(codes, ncodes, st);
+  std::unique_ptr<HuffmanEncoder> enc;
+  if (!too_fine) enc = std::make_unique<HuffmanEncoder>(codes, ncodes, st);
+  const size_t sb = enc ? enc->bytes() : 0;
   BM_HIP(hipStreamSynchronize(st));
   CHeader h{};
   h.magic = kMagic;
@@ -309,12 +316,14 @@ bool write_container_p8(bm_p8_s& p, const void* x, const double* block_tol, doub
     BM_HIP(hipStreamSynchronize(st));
   } else {
     std::memcpy(o, tol.data(), size_t(ntol) * 8);
-    huffman_encode_to(codes, ncodes, o + size_t(ntol) * 8, sb, st);
+    enc->write(o + size_t(ntol) * 8, sb);
   }
   h.crc = 0;
+  const auto t0 = std::chrono::steady_clock::now();
   uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
   c = crc32_parallel(o, size_t(h.payload), c);
   h.crc = c;
+  if (enc) set_lossless_crc_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   std::memcpy(out, &h, sizeof(h));
   return true;
 }
@@ -450,10 +459,11 @@ bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t c
   return guarded([&] {
     need(out_bytes != nullptr, "null out_bytes");
     need(codes || n == 0, "null codes");
-    const size_t bytes = bm::huffman_size(codes, n, st);
+    bm::HuffmanEncoder enc(codes, n, st);
+    const size_t bytes = enc.bytes();
     *out_bytes = bytes;
     if (!out || capacity < bytes) bm::fail(BM_ECAPACITY, "output buffer too small");
-    bm::huffman_encode_to(codes, n, static_cast<uint8_t*>(out), bytes, st);
+    enc.write(static_cast<uint8_t*>(out), bytes);
   });
 }
 
@@ -469,6 +479,20 @@ bm_status bm_huffman_decode(const void* in, size_t in_bytes, int32_t* codes, int
   return guarded([&] {
     need(codes || n == 0, "null codes");
     bm::huffman_decode(static_cast<const uint8_t*>(in), in_bytes, codes, n, st);
+  });
+}
+
+bm_status bm_huffman_code_lengths(const uint64_t* hist, uint8_t* len) {
+  return guarded([&] {
+    need(hist && len, "null argument");
+    bm::huffman_code_lengths(hist, len);
+  });
+}
+
+bm_status bm_lossless_last_times(bm_lossless_times* out) {
+  return guarded([&] {
+    need(out != nullptr, "null argument");
+    *out = bm::lossless_times();
   });
 }
 

@@ -13,10 +13,21 @@
 // The stream is cut into chunks of 4096 symbols, each packed MSB-first into
 // 32-bit words and starting on a word boundary.
 //
-// GPU work: an LDS-privatised histogram, one wavefront per chunk for the
-// bit counts and for the encode (LDS atomic ORs into the chunk's words),
-// one thread per chunk for decoding (tables and output staged in LDS).  The
-// codebook is built on the host.
+// GPU work: an LDS-privatised histogram; bit counts and encode with a
+// workgroup of 256 threads per chunk (16 consecutive symbols per thread,
+// their bit offsets from a workgroup scan, LDS atomic ORs into the chunk's
+// words); decode with four wavefronts per chunk.  Decoding a chunk is split
+// over its 256 lanes by bit position: lane l owns the codewords that start in
+// the l-th 1/256 of the chunk's bits.  Where that first codeword starts is
+// only known once lane l - 1 has decoded, so every lane first decodes its part
+// from a guessed start (the part's first bit) and hands its end position to
+// the next lane; the hand-over is repeated, re-decoding only the lanes whose
+// start changed, until no start changes, which is the exact decomposition
+// (the fixed point of "start of lane l + 1 = end of lane l from the start of
+// lane l", reached in at most 256 rounds).  Huffman codes resynchronise within
+// a few codewords from a wrong start, so a few rounds are the rule
+// (self-synchronising parallel decoding, as in Weissenberger and Schmidt,
+// ICPP 2018).  The codebook is built on the host.
 
 #include <algorithm>
 #include <chrono>
@@ -33,8 +44,17 @@ constexpr int R = 1 << 15;
 constexpr int NSYM = 2 * R;
 constexpr int CHUNK = 4096;
 constexpr int LMAX = 32;
-constexpr int HW = 4096;           // LDS histogram window: symbols [R - HW, R + HW)
-constexpr int LUTB = 10;           // decode lookup bits
+constexpr int HW = 4096;             // LDS histogram window: symbols [R - HW, R + HW)
+constexpr int DLB = 11;              // decode lookup bits
+constexpr int ET = 256;              // threads per chunk in the bit count and the encode
+constexpr int EPT = CHUNK / ET;      // consecutive symbols per thread there
+constexpr uint32_t kNoPos = 0xFFFFFFFFu;   // decode position after an invalid code
+constexpr size_t kLdsCap = 64 * 1024;      // LDS bytes a decode workgroup may take
+
+using clk = std::chrono::steady_clock;
+inline double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
 
 __device__ inline uint32_t sym_of(int32_t q) { return (q > -R && q < R) ? uint32_t(q + R) : 0u; }
 
@@ -64,35 +84,73 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) p[i] = 0;
 }
 
-// one wavefront per chunk: bit count and escape count
-__global__ __launch_bounds__(64) void k_chunk_bits(const int32_t* codes, int64_t n, const uint8_t* len,
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+__device__ inline uint32_t wave_excl_scan(uint32_t v, int lane) { return wave_incl_scan(v, lane) - v; }
+
+// The EPT consecutive codes [i0, i0 + EPT) of a chunk of cnt codes at p
+// (0 past cnt); VEC: 16-byte loads (p is 16-byte aligned).
+template <bool VEC>
+__device__ inline void load_run(const int32_t* p, int i0, int cnt, int32_t (&q)[EPT]) {
+  if (VEC && i0 + EPT <= cnt) {
+    const int4* v = reinterpret_cast<const int4*>(p + i0);
+#pragma unroll
+    for (int k = 0; k < EPT / 4; ++k) {
+      const int4 w = v[k];
+      q[4 * k] = w.x;
+      q[4 * k + 1] = w.y;
+      q[4 * k + 2] = w.z;
+      q[4 * k + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) q[k] = i0 + k < cnt ? p[i0 + k] : 0;
+  }
+}
+
+// bits and escapes of each chunk (a workgroup per chunk)
+template <bool VEC>
+__global__ __launch_bounds__(ET) void k_chunk_bits(const int32_t* codes, int64_t n, const uint8_t* len,
                                                    uint32_t* bits, uint32_t* esc) {
-  const int64_t c = blockIdx.x;
-  const int64_t b0 = c * CHUNK;
-  const int64_t b1 = b0 + CHUNK < n ? b0 + CHUNK : n;
+  __shared__ uint32_t part[2][ET / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t c = blockIdx.x, b0 = c * CHUNK;
+  const int cnt = int(b0 + CHUNK < n ? CHUNK : n - b0);
+  int32_t q[EPT];
+  load_run<VEC>(codes + b0, EPT * t, cnt, q);
   uint32_t nb = 0, ne = 0;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += 64) {
-    const uint32_t s = sym_of(codes[i]);
-    nb += len[s];
-    ne += s == 0;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    if (EPT * t + k < cnt) {
+      const uint32_t s = sym_of(q[k]);
+      nb += len[s];
+      ne += s == 0;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     nb += __shfl_down(nb, off, 64);
     ne += __shfl_down(ne, off, 64);
   }
-  if (threadIdx.x == 0) {
-    bits[c] = nb;
-    esc[c] = ne;
+  if (lane == 0) {
+    part[0][wave] = nb;
+    part[1][wave] = ne;
   }
-}
-
-__device__ inline uint32_t wave_excl_scan(uint32_t v, int lane) {
-  uint32_t s = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t t = __shfl_up(s, off, 64);
-    if (lane >= off) s += t;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t sb = 0, se = 0;
+    for (int w = 0; w < ET / 64; ++w) {
+      sb += part[0][w];
+      se += part[1][w];
+    }
+    bits[c] = sb;
+    esc[c] = se;
   }
-  return s - v;
 }
 
 // a 32-bit little-endian store; BYTES: four byte stores (a destination that
@@ -110,231 +168,385 @@ __device__ inline void store32(void* base, uint64_t i, uint32_t v) {
   }
 }
 
-// one wavefront per chunk; lane l codes symbols [64 l, 64 l + 64) of the chunk
-template <bool BYTES = false>
-__global__ __launch_bounds__(64) void k_encode(const int32_t* codes, int64_t n, const uint8_t* len,
+// A workgroup per chunk; thread t codes symbols [16 t, 16 t + 16) of the
+// chunk at the bit offset a workgroup scan of the code lengths gives, OR-ing
+// each code into the chunk's words in LDS (dynamic size: the longest chunk's
+// words).  Code lengths and codes are looked up for all 16 symbols before any
+// is placed, so the table reads overlap.
+template <bool BYTES, bool VEC>
+__global__ __launch_bounds__(ET) void k_encode(const int32_t* codes, int64_t n, const uint8_t* len,
                                                const uint32_t* cw, const uint64_t* woff, const uint64_t* ooff,
                                                void* words, void* oval) {
-  __shared__ uint32_t sym[64 * 65];
-  __shared__ uint32_t out[CHUNK];
-  const int lane = threadIdx.x;
-  const int64_t c = blockIdx.x;
-  const int64_t b0 = c * CHUNK;
+  extern __shared__ uint32_t out[];
+  __shared__ uint32_t part[2][ET / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t c = blockIdx.x, b0 = c * CHUNK;
   const int cnt = int(b0 + CHUNK < n ? CHUNK : n - b0);
-  const uint64_t w0 = woff[c], nw = woff[c + 1] - w0;
-  for (int i = lane; i < CHUNK; i += 64) sym[(i >> 6) * 65 + (i & 63)] = i < cnt ? sym_of(codes[b0 + i]) : 0xFFFFFFFFu;
-  for (uint64_t i = lane; i < nw; i += 64) out[i] = 0;
-  __syncthreads();
+  const uint64_t w0 = woff[c];
+  const uint32_t nw = uint32_t(woff[c + 1] - w0);
+  for (uint32_t i = t; i < nw; i += ET) out[i] = 0;
+  int32_t q[EPT];
+  load_run<VEC>(codes + b0, EPT * t, cnt, q);
+  uint32_t l[EPT], v[EPT];
   uint32_t nb = 0, ne = 0;
-  for (int k = 0; k < 64; ++k) {
-    const uint32_t s = sym[lane * 65 + k];
-    if (s != 0xFFFFFFFFu) {
-      nb += len[s];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    l[k] = 0;
+    v[k] = 0;
+    if (EPT * t + k < cnt) {
+      const uint32_t s = sym_of(q[k]);
+      l[k] = len[s];
+      v[k] = cw[s];
       ne += s == 0;
     }
+    nb += l[k];
   }
-  uint32_t p = wave_excl_scan(nb, lane);
-  uint64_t e = ooff[c] + wave_excl_scan(ne, lane);
-  for (int k = 0; k < 64; ++k) {
-    const uint32_t s = sym[lane * 65 + k];
-    if (s == 0xFFFFFFFFu) break;
-    const uint32_t l = len[s], v = cw[s];
-    const uint32_t w = p >> 5, o = p & 31;
-    if (o + l <= 32) {
-      atomicOr(&out[w], v << (32 - o - l));
-    } else {
-      atomicOr(&out[w], v >> (o + l - 32));
-      atomicOr(&out[w + 1], v << (64 - o - l));
-    }
-    p += l;
-    if (s == 0) store32<BYTES>(oval, e++, uint32_t(codes[b0 + lane * 64 + k]));
+  const uint32_t ib = wave_incl_scan(nb, lane), ie = wave_incl_scan(ne, lane);
+  if (lane == 63) {
+    part[0][wave] = ib;
+    part[1][wave] = ie;
   }
   __syncthreads();
-  for (uint64_t i = lane; i < nw; i += 64) store32<BYTES>(words, w0 + i, out[i]);
+  uint32_t p = ib - nb, pe = ie - ne;
+  for (int w = 0; w < wave; ++w) {
+    p += part[0][w];
+    pe += part[1][w];
+  }
+  uint64_t e = ooff[c] + pe;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    if (l[k] == 0) break;   // past the chunk's end (a coded symbol has a length >= 1)
+    const uint32_t w = p >> 5, o = p & 31;
+    if (o + l[k] <= 32) {
+      atomicOr(&out[w], v[k] << (32 - o - l[k]));
+    } else {
+      atomicOr(&out[w], v[k] >> (o + l[k] - 32));
+      atomicOr(&out[w + 1], v[k] << (64 - o - l[k]));
+    }
+    p += l[k];
+    if (q[k] <= -R || q[k] >= R) store32<BYTES>(oval, e++, uint32_t(q[k]));
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < nw; i += ET) store32<BYTES>(words, w0 + i, out[i]);
 }
 
+// ------------------------------------------------------------------ decode
+// Tables (built on the host from the code lengths):
+// * lut[2^DLB], indexed by the next DLB bits: for a code of l <= DLB bits,
+//   its symbol | l << 16; for a prefix whose codes all
+//   have one length l > DLB and fill it, kOne | the index of its first code
+//   | l << 16 (the code's index is that plus the l - DLB bits after the
+//   prefix); for any other prefix of longer codes, kLong | Lmin << 16 |
+//   Lmax << 24, the shortest and longest code lengths with that prefix; 0 for
+//   a prefix of no code;
+// * lastc[L]: the largest 32-bit left-justified code value of length <= L
+//   (codes are canonical, so a code of length L is the 32-bit window w with
+//   lastc[L - 1] < w <= lastc[L]);
+// * offs[L]: index in canonical order of a code of length L minus its value;
+// * sorted16: the coded symbols in canonical order (device memory).
+constexpr uint32_t kLong = 0x80000000u;
+constexpr uint32_t kOne = 0x40000000u;
+constexpr int kDecHdrWords = (1 << DLB) + 2 * (LMAX + 1);
+
 struct DecTables {
-  const uint32_t* lut;        // [1 << LUTB]: symbol | length << 16 (length 0: longer code)
-  const uint32_t* first;      // [LMAX + 1] first canonical code of each length
-  const uint32_t* count;      // [LMAX + 1]
-  const uint32_t* base;       // [LMAX + 1] index of the first symbol of each length in `sorted`
-  const uint32_t* sorted;     // symbols in (length, symbol) order
+  const uint32_t* hdr;        // [kDecHdrWords]: lut, lastc, offs
+  const uint16_t* sorted16;   // coded symbols in (length, symbol) order
+  uint32_t nsorted;           // their count (>= 1)
+  uint32_t escidx;            // index of the escape symbol in canonical order (nsorted: none)
 };
 
-// One thread per chunk, 64 chunks per workgroup.  The lookup tables live in
-// LDS; decoded symbols go to an LDS tile 64 at a time per lane, and the tile
-// is stored one lane's run at a time, so every store instruction writes 64
-// consecutive codes (a lane writing straight to its own chunk would put the
-// 64 lanes of a store 16 KiB apart).  A lane that meets a malformed stream
-// raises the flag and decodes nothing more (the caller then fails).
-__global__ __launch_bounds__(64) void k_decode(const uint32_t* words, const uint64_t* woff, int64_t nch, int64_t n,
-                                               DecTables t, const uint64_t* ooff, const int32_t* oval,
-                                               int32_t* codes, int* err) {
-  __shared__ uint32_t lut[1 << LUTB];
-  __shared__ uint32_t first[LMAX + 1], count[LMAX + 1], base[LMAX + 1];
-  __shared__ int32_t tile[64 * 65];
-  const int lane = threadIdx.x;
-  for (int i = lane; i < (1 << LUTB); i += 64) lut[i] = t.lut[i];
-  if (lane <= LMAX) {
-    first[lane] = t.first[lane];
-    count[lane] = t.count[lane];
-    base[lane] = t.base[lane];
+struct DecLds {
+  const uint32_t* lut;
+  const uint32_t* lastc;
+  const uint32_t* offs;
+};
+
+// Decodes the codewords of a chunk that start at x and after, while they
+// start before hi.  wl: the chunk's words in LDS followed by two zero words.
+// Returns the position of the first codeword at or past hi (x itself when
+// x >= hi), or kNoPos at an invalid code; ns counts the codewords decoded.
+// With EMIT, emit(k, v, lng, e) receives for the k-th code its symbol (lng
+// false: a code of at most DLB bits) or its index in canonical order (lng
+// true) and the position where it ends.  Each step reads the two words under
+// the position (one LDS instruction) and shifts them, so a step is a dozen
+// vector instructions; an invalid code ends the loop through its condition
+// (pos = kNoPos), so the loop has a single exit and the common path no branch
+// but the rare long-code one.
+template <bool EMIT, typename Emit>
+__device__ inline uint32_t decode_run(const uint32_t* wl, const DecLds& d, uint32_t x, uint32_t hi, uint32_t& ns,
+                                      Emit emit) {
+  ns = 0;
+  uint32_t pos = x;
+  while (pos < hi) {
+    const uint32_t i = pos >> 5;   // i + 1 <= nw while pos < hi <= 32 nw
+    const uint64_t win = (uint64_t(wl[i]) << 32) | wl[i + 1];
+    const uint32_t top = uint32_t((win << (pos & 31)) >> 32);
+    const uint32_t lu = d.lut[top >> (32 - DLB)];
+    uint32_t l = (lu >> 16) & 63u, v = lu & 0xFFFFu;
+    if (lu & kLong) {   // a prefix of codes of several lengths, or one they do not fill (rare)
+      const uint32_t lmax = (lu >> 24) & 63u;
+      uint32_t lc = d.lastc[l];
+      while (top > lc && l < lmax) lc = d.lastc[++l];
+      if (EMIT) v = d.offs[l] + (top >> (32 - l));
+      if (top > lc) l = 0;
+    } else if (EMIT && (lu & kOne)) {
+      v += (top << DLB) >> (32 - l + DLB);
+    }
+    const bool valid = l != 0;
+    if (EMIT && valid) emit(ns, v, l > DLB, pos + l);
+    ns += valid;
+    pos = valid ? pos + l : kNoPos;
   }
-  const int64_t c0 = int64_t(blockIdx.x) * 64;
-  const int64_t c = c0 + lane;
-  const bool valid = c < nch;
-  const int64_t b0 = c * CHUNK;
-  const int cnt = valid ? int(b0 + CHUNK < n ? CHUNK : n - b0) : 0;
-  const uint64_t w0 = valid ? woff[c] : 0, w1 = valid ? woff[c + 1] : 0;
-  // this chunk's outliers, in the order of its escape symbols
-  uint64_t e = valid ? ooff[c] : 0;
-  const uint64_t e1 = valid ? ooff[c + 1] : 0;
-  uint64_t buf = 0;
-  int avail = 0;
-  uint64_t wp = w0;
-  bool bad = false;
+  return pos;
+}
+
+// Decode: CPW chunks per workgroup, WPC wavefronts (NL = 64 WPC lanes) per
+// chunk; chunk lane L owns the codewords that start in the L-th 1/NL of the
+// chunk's bits.  LDS: the tables (shared), then per chunk its words
+// (wcap + 2), a bit mask of the tile's long codes, a tile of its 4096 symbols
+// (uint16; for a code longer than DLB bits its index in canonical order) and
+// a small control block.  Rounds of the start hand-over end with workgroup
+// barriers (lane 63 of a wavefront hands its end to lane 0 of the next
+// through LDS).  The tile is turned into codes by the chunk's wavefronts, a
+// segment of 4096 / WPC positions each, 256 at a time: the long codes'
+// symbols gathered from sorted16 (only the lanes that hold one load), then
+// stored 64 consecutive codes per instruction; an escape's position in the
+// chunk goes to rel (in outlier order) and k_outliers puts the outlier values
+// in place afterwards, so no lane waits for a load from the outlier array.
+// A chunk whose symbols do not decode from its own words (an invalid code,
+// too few codewords, a codeword that runs past the chunk's last word) or
+// whose escapes do not match its outlier count raises the flag (the caller
+// then fails); bits after the chunk's last symbol are not read as symbols.
+constexpr int kCtl = 20;   // control words per chunk: hand-over [4], first bad lane [4], wave totals [8], escapes [4]
+
+template <int WPC, int CPW>
+__global__ __launch_bounds__(64 * WPC * CPW) void k_decode(const uint32_t* words, const uint64_t* woff, int64_t nch,
+                                                           int64_t n, DecTables t, const uint64_t* ooff,
+                                                           uint16_t* rel, int32_t* codes, int* err, int wcap) {
+  static_assert(WPC == 1 || WPC == 2 || WPC == 4, "1, 2 or 4 wavefronts per chunk");
+  constexpr int NL = 64 * WPC, SEG = CHUNK / WPC;
+  extern __shared__ uint32_t smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int slot = wave / WPC, wic = wave % WPC, L = wic * 64 + lane;
+  const int per = wcap + 2 + CHUNK / 32 + CHUNK / 2 + kCtl;
+  uint32_t* flag = smem + kDecHdrWords;                     // [2] workgroup: a start changed in the round
+  uint32_t* wl = smem + kDecHdrWords + 2 + slot * per;      // chunk words, two zero words
+  uint32_t* lmask = wl + wcap + 2;
+  uint16_t* tile = reinterpret_cast<uint16_t*>(lmask + CHUNK / 32);
+  uint32_t* ctl = lmask + CHUNK / 32 + CHUNK / 2;
+  uint32_t* xch = ctl;        // [WPC] end of each wavefront's lane 63
+  uint32_t* fbad = ctl + 4;   // [WPC] first lane of each wavefront that met an invalid code (64: none)
+  uint32_t* wtot = ctl + 8;   // [WPC] codewords of each wavefront; [WPC] of lanes up to the first bad one
+  uint32_t* esc = ctl + 16;   // [WPC] escapes in each tile segment
+  for (int i = tid; i < kDecHdrWords; i += 64 * WPC * CPW) smem[i] = t.hdr[i];
+  if (tid < 2) flag[tid] = 0;
+  const int64_t c = int64_t(blockIdx.x) * CPW + slot;
+  const bool valid = c < nch;   // uniform over the chunk's wavefronts
+  uint64_t w0 = 0;
+  uint32_t nw = 0;
+  if (valid) {
+    w0 = woff[c];
+    nw = uint32_t(woff[c + 1] - w0);   // <= wcap (checked on the host)
+  }
+  for (uint32_t i = L; i < nw + 2; i += NL) wl[i] = i < nw ? words[w0 + i] : 0u;
+  for (int i = L; i < CHUNK / 32; i += NL) lmask[i] = 0;
+  if (L < kCtl) ctl[L] = 0;
   __syncthreads();
-  for (int k0 = 0; k0 < CHUNK; k0 += 64) {
-    for (int kk = 0; kk < 64; ++kk) {
-      const int k = k0 + kk;
-      if (bad || k >= cnt) break;
-      while (avail <= 32) {
-        const uint64_t wv = wp < w1 ? words[wp] : 0u;
-        ++wp;
-        buf |= wv << (32 - avail);
-        avail += 32;
-      }
-      uint32_t s, l;
-      const uint32_t lu = lut[buf >> (64 - LUTB)];
-      if ((lu >> 16) != 0) {
-        s = lu & 0xFFFFu;
-        l = lu >> 16;
-      } else {
-        l = 0;
-        s = 0;
-        for (uint32_t L = LUTB + 1; L <= LMAX; ++L) {
-          const uint32_t code = uint32_t(buf >> (64 - L));
-          if (count[L] && code - first[L] < count[L]) {
-            s = t.sorted[base[L] + code - first[L]];
-            l = L;
-            break;
-          }
-        }
-        if (l == 0) {
-          bad = true;
-          break;
-        }
-      }
-      buf <<= l;
-      avail -= int(l);
-      int32_t q;
-      if (s == 0) {
-        if (e >= e1) {
-          bad = true;
-          break;
-        }
-        q = oval[e++];
-      } else {
-        q = int32_t(s) - R;
-      }
-      tile[lane * 65 + kk] = q;
-    }
+  const DecLds d{smem, smem + (1 << DLB), smem + (1 << DLB) + (LMAX + 1)};
+  const int64_t b0 = c * CHUNK;
+  const uint32_t cnt = valid ? uint32_t(b0 + CHUNK < n ? CHUNK : n - b0) : 0u;
+  const uint32_t NB = nw * 32, S = max((NB + NL - 1) / NL, 32u);
+  const uint32_t lo = min(uint32_t(L) * S, NB), hi = min(lo + S, NB);
+  auto none = [](uint32_t, uint32_t, bool, uint32_t) {};
+  // The lanes' start positions: guessed, then handed over until they hold.
+  // A lane whose predecessor met an invalid code keeps its own start (a
+  // wrong start of the predecessor is the likely cause); lanes up to the
+  // first one that ends in an invalid code hold exact starts at the fixed
+  // point, and only their symbols are used.
+  // Later rounds decode only the lanes whose start changed.
+  uint32_t x = lo, ns = 0, end = 0;
+  bool ok = false, dirty = true;
+  for (int round = 0; round <= NL; ++round) {
+    if (dirty) end = decode_run<false>(wl, d, x, hi, ns, none);
+    if (lane == 63) xch[wic] = end;
     __syncthreads();
-    // lane j's 64 codes, written by the whole wavefront
-    for (int j = 0; j < 64; ++j) {
-      const int64_t cj = c0 + j;
-      if (cj >= nch) break;
-      const int cntj = int(cj * CHUNK + CHUNK < n ? CHUNK : n - cj * CHUNK);
-      if (k0 + lane < cntj) codes[cj * CHUNK + k0 + lane] = tile[j * 65 + lane];
-    }
+    uint32_t xn = __shfl_up(end, 1, 64);
+    if (lane == 0) xn = wic ? xch[wic - 1] : 0u;
+    if (xn == kNoPos) xn = x;
+    dirty = xn != x;
+    if (__any(dirty) && lane == 0) atomicOr(&flag[round & 1], 1u);
     __syncthreads();
+    const bool again = flag[round & 1] != 0;
+    if (tid == 0) flag[(round + 1) & 1] = 0;
+    x = xn;
+    if (!again) {
+      ok = true;
+      break;
+    }
   }
-  if (valid && (bad || e != e1)) atomicOr(err, 1);
+  // lanes past the chunk's first one that ends in an invalid code are not used
+  const uint64_t badm = __ballot(end == kNoPos);
+  const uint32_t fb = badm ? uint32_t(__ffsll((unsigned long long)badm) - 1) : 64u;
+  const uint32_t incl = wave_incl_scan(ns, lane);
+  if (lane == 63) {
+    fbad[wic] = fb;
+    wtot[wic] = incl;
+  }
+  if (fb < 64 && uint32_t(lane) == fb) wtot[4 + wic] = incl;
+  __syncthreads();
+  uint32_t before = 0, total = 0, lastw = WPC;
+  for (int w = 0; w < WPC; ++w) {
+    if (lastw == WPC && fbad[w] < 64) lastw = uint32_t(w);
+    if (w < wic) before += wtot[w];
+  }
+  for (int w = 0; w < WPC; ++w) {
+    if (uint32_t(w) < lastw) total += wtot[w];
+    if (uint32_t(w) == lastw) total += wtot[4 + w];
+  }
+  const bool used = uint32_t(wic) < lastw || (uint32_t(wic) == lastw && uint32_t(lane) <= fbad[wic]);
+  const uint32_t start = before + incl - ns;
+  const bool good = valid && ok && total >= cnt;   // uniform over the chunk
+  if (valid && !good && L == 0) atomicOr(err, 1);
+  bool over = false;   // a codeword of the chunk's symbols runs past its words
+  uint32_t ne[WPC] = {};
+  if (good && used)
+    decode_run<true>(wl, d, x, hi, ns, [&](uint32_t k, uint32_t v, bool lng, uint32_t e) {
+      const uint32_t i = start + k;
+      if (i < cnt) {
+        tile[i] = uint16_t(v);
+        if (lng) atomicOr(&lmask[i >> 5], 1u << (i & 31));
+        over |= e > NB;
+        if (lng ? v == t.escidx : v == 0) {
+#pragma unroll
+          for (int w = 0; w < WPC; ++w) ne[w] += i / SEG == uint32_t(w);
+        }
+      }
+    });
+#pragma unroll
+  for (int w = 0; w < WPC; ++w)
+    if (ne[w]) atomicAdd(&esc[w], ne[w]);
+  if (__any(over) && lane == 0) atomicOr(err, 1);
+  __syncthreads();
+  if (!good) return;   // no barrier follows
+  uint64_t run = ooff[c];
+  for (int w = 0; w < wic; ++w) run += esc[w];
+  const uint64_t e1 = ooff[c + 1];
+  const uint32_t s0 = uint32_t(wic) * SEG, s1 = min(s0 + SEG, cnt);
+  for (uint32_t k0 = s0; k0 < s1; k0 += 256) {
+    uint32_t s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t i = k0 + 64 * j + lane;
+      s[j] = 1u;
+      if (i < s1) {
+        s[j] = tile[i];
+        if ((lmask[i >> 5] >> (i & 31)) & 1u) s[j] = t.sorted16[min(s[j], t.nsorted - 1)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t i = k0 + 64 * j + lane;
+      const uint64_t m = __ballot(s[j] == 0);
+      if (s[j] == 0) {
+        const uint64_t ei = run + __popcll(m & ((uint64_t(1) << lane) - 1));
+        if (ei < e1) rel[ei] = uint16_t(i);
+      }
+      if (i < s1) codes[b0 + i] = int32_t(s[j]) - R;
+      run += __popcll(m);
+    }
+  }
+  // the segment's escapes as counted in the write pass, and all of them the chunk's count
+  uint64_t upto = ooff[c];
+  for (int w = 0; w <= wic; ++w) upto += esc[w];
+  if (lane == 0 && (run != upto || (wic == WPC - 1 && upto != e1))) atomicOr(err, 1);
+}
+
+// The outlier values of each chunk to their positions (a workgroup per
+// chunk).  Positions are bounded by the chunk's length: a chunk that failed
+// to decode may have left its entries of rel unset (the call then fails).
+__global__ __launch_bounds__(256) void k_outliers(const uint64_t* ooff, const uint16_t* rel, const int32_t* oval,
+                                                  int32_t* codes, int64_t n) {
+  const int64_t c = blockIdx.x, b0 = c * CHUNK;
+  const uint32_t cnt = uint32_t(b0 + CHUNK < n ? CHUNK : n - b0);
+  const uint64_t e0 = ooff[c], e1 = ooff[c + 1];
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const uint32_t r = rel[e];
+    if (r < cnt) codes[b0 + r] = oval[e];
+  }
 }
 
 // ------------------------------------------------------------------ host codebook
 // The codebook is built in fixed arrays (no allocation), so the same code
 // serves the entry point that may not allocate.
 
-// Work arrays of the code-length construction: a binary min-heap of live
-// nodes keyed by (weight, smallest symbol in the subtree), parents and depths
-// of the merge tree.  The key is unique among live nodes (the smallest symbol
-// of a subtree belongs to it alone), so any correct heap pops in one order.
+// Work arrays of the code-length construction: the leaves sorted by key
+// (weight, symbol), the merged nodes in the order they are made, parents and
+// depths of the merge tree.
+struct HNode {
+  uint64_t w;     // weight
+  uint32_t m;     // smallest symbol in the subtree
+  uint32_t id;    // node: a symbol, or NSYM + merge number
+};
 struct LenWork {
-  uint64_t hw[NSYM];
-  int32_t hmin[NSYM], hid[NSYM];
+  HNode leaf[NSYM], tmp[NSYM], node[NSYM];
+  uint32_t digit[2048];
   int32_t parent[2 * NSYM], depth[2 * NSYM], L[NSYM], present[NSYM];
 };
 
-inline bool heap_less(const LenWork& w, int a, int b) {
-  return w.hw[a] != w.hw[b] ? w.hw[a] < w.hw[b] : w.hmin[a] < w.hmin[b];
-}
-
-inline void heap_swap(LenWork& w, int a, int b) {
-  std::swap(w.hw[a], w.hw[b]);
-  std::swap(w.hmin[a], w.hmin[b]);
-  std::swap(w.hid[a], w.hid[b]);
-}
-
-inline void heap_up(LenWork& w, int i) {
-  while (i > 0) {
-    const int p = (i - 1) / 2;
-    if (!heap_less(w, i, p)) break;
-    heap_swap(w, i, p);
-    i = p;
-  }
-}
-
-inline void heap_down(LenWork& w, int n, int i) {
-  for (;;) {
-    const int l = 2 * i + 1, r = l + 1;
-    int m = i;
-    if (l < n && heap_less(w, l, m)) m = l;
-    if (r < n && heap_less(w, r, m)) m = r;
-    if (m == i) break;
-    heap_swap(w, i, m);
-    i = m;
-  }
-}
+inline bool key_less(const HNode& a, const HNode& b) { return a.w != b.w ? a.w < b.w : a.m < b.m; }
 
 // Huffman code lengths of the symbols with hist[s] > 0 (len[s] = 0 for the
-// others): merge the two smallest (weight, smallest symbol) keys until one
-// tree remains; lengths above 32 are cut to 32 and the longest codes below
-// 32 are lengthened (largest symbol first) until Kraft's sum is <= 1.
+// others): merge the two smallest (weight, smallest symbol in the subtree)
+// keys until one tree remains; lengths above 32 are cut to 32 and the
+// longest codes below 32 are lengthened (largest symbol first) until Kraft's
+// sum is <= 1.  The keys are unique, so the tree is.  Two sorted queues give
+// the smallest keys in O(n): the leaves sorted by key (a stable radix sort by
+// weight of the symbols in ascending order), and the merged nodes in the
+// order they are made, which is key order too: merges take keys in
+// increasing order, so merged weights do not decrease, and two merged nodes
+// of one weight 2w both come from pairs of weight-w nodes taken in
+// increasing symbol order, so their smallest symbols increase.
 void code_lengths(const uint64_t* hist, uint8_t* len, LenWork& w) {
   std::memset(len, 0, NSYM);
   int np = 0;
+  uint64_t wmax = 0;
   for (int s = 0; s < NSYM; ++s)
-    if (hist[s]) w.present[np++] = s;
+    if (hist[s]) {
+      w.present[np++] = s;
+      wmax = std::max(wmax, hist[s]);
+    }
   if (np == 0) return;
   if (np == 1) {
     len[w.present[0]] = 1;
     return;
   }
-  int hn = 0;
-  for (int k = 0; k < np; ++k) {
-    const int s = w.present[k];
-    w.hw[hn] = hist[s];
-    w.hmin[hn] = s;
-    w.hid[hn] = s;
-    heap_up(w, hn++);
+  HNode* A = w.leaf;
+  HNode* T = w.tmp;
+  for (int k = 0; k < np; ++k) A[k] = HNode{hist[w.present[k]], uint32_t(w.present[k]), uint32_t(w.present[k])};
+  for (int sh = 0; sh < 64 && (wmax >> sh) != 0; sh += 11) {   // stable LSD passes of 11 bits
+    std::memset(w.digit, 0, sizeof(w.digit));
+    for (int k = 0; k < np; ++k) ++w.digit[(A[k].w >> sh) & 2047u];
+    uint32_t sum = 0;
+    for (int d = 0; d < 2048; ++d) {
+      const uint32_t c = w.digit[d];
+      w.digit[d] = sum;
+      sum += c;
+    }
+    for (int k = 0; k < np; ++k) T[w.digit[(A[k].w >> sh) & 2047u]++] = A[k];
+    std::swap(A, T);
   }
+  HNode* B = w.node;
+  int ai = 0, bi = 0, bn = 0;
+  auto pop = [&]() -> HNode {
+    if (ai < np && (bi >= bn || key_less(A[ai], B[bi]))) return A[ai++];
+    return B[bi++];
+  };
   int next = NSYM;
-  while (hn > 1) {
-    const uint64_t aw = w.hw[0];
-    const int am = w.hmin[0], aid = w.hid[0];
-    heap_swap(w, 0, --hn);
-    heap_down(w, hn, 0);
-    const uint64_t bw = w.hw[0];
-    const int bm = w.hmin[0], bid = w.hid[0];
-    heap_swap(w, 0, --hn);
-    heap_down(w, hn, 0);
-    w.parent[aid] = next;
-    w.parent[bid] = next;
-    w.hw[hn] = aw + bw;
-    w.hmin[hn] = std::min(am, bm);
-    w.hid[hn] = next;
-    heap_up(w, hn++);
+  for (int k = 0; k < np - 1; ++k) {
+    const HNode a = pop(), b = pop();
+    w.parent[a.id] = next;
+    w.parent[b.id] = next;
+    B[bn++] = HNode{a.w + b.w, std::min(a.m, b.m), uint32_t(next)};
     ++next;
   }
   w.depth[next - 1] = 0;
@@ -366,13 +578,16 @@ void code_lengths(const uint64_t* hist, uint8_t* len, LenWork& w) {
 }
 
 // Canonical codes in (length, symbol) order; sorted receives the coded
-// symbols in that order, *nsorted their count.
+// symbols in that order (a counting sort by length), *nsorted their count.
 void canonical(const uint8_t* len, uint32_t* code, uint32_t* sorted, int* nsorted) {
   std::memset(code, 0, NSYM * sizeof(uint32_t));
-  int n = 0;
-  for (int l = 1; l <= LMAX; ++l)
-    for (int s = 0; s < NSYM; ++s)
-      if (len[s] == l) sorted[n++] = uint32_t(s);
+  uint32_t at[LMAX + 2] = {};
+  for (int s = 0; s < NSYM; ++s)
+    if (len[s]) ++at[len[s] + 1];
+  for (int l = 1; l <= LMAX; ++l) at[l + 1] += at[l];
+  const int n = int(at[LMAX + 1]);
+  for (int s = 0; s < NSYM; ++s)
+    if (len[s]) sorted[at[len[s]]++] = uint32_t(s);
   uint64_t c = 0;
   int prev = 0;
   for (int i = 0; i < n; ++i) {
@@ -405,134 +620,223 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
 };
 
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    BM_HIP(hipEventCreate(&a));
+    BM_HIP(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  double ms() const {
+    BM_HIP(hipEventSynchronize(b));
+    float t = 0.f;
+    BM_HIP(hipEventElapsedTime(&t, a, b));
+    return double(t);
+  }
+};
+
+thread_local bm_lossless_times g_times{};
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+void launch_chunk_bits(const int32_t* codes, int64_t n, int64_t nch, const uint8_t* len, uint32_t* bits,
+                       uint32_t* esc, hipStream_t st) {
+  if (!nch) return;
+  if (aligned16(codes))
+    hipLaunchKernelGGL(k_chunk_bits<true>, dim3(unsigned(nch)), dim3(ET), 0, st, codes, n, len, bits, esc);
+  else
+    hipLaunchKernelGGL(k_chunk_bits<false>, dim3(unsigned(nch)), dim3(ET), 0, st, codes, n, len, bits, esc);
+  BM_HIP(hipGetLastError());
+}
+
+void launch_encode(const int32_t* codes, int64_t n, int64_t nch, const uint8_t* len, const uint32_t* cw,
+                   const uint64_t* woff, const uint64_t* ooff, uint64_t wmax, void* words, void* oval,
+                   hipStream_t st) {
+  if (!nch) return;
+  const size_t shm = size_t(wmax) * 4;
+  const bool bytes = (reinterpret_cast<uintptr_t>(words) & 3) != 0;   // oval - words is a multiple of 4
+  const bool vec = aligned16(codes);
+  const dim3 g{unsigned(nch)}, b{unsigned(ET)};
+  if (bytes && vec)
+    hipLaunchKernelGGL((k_encode<true, true>), g, b, shm, st, codes, n, len, cw, woff, ooff, words, oval);
+  else if (bytes)
+    hipLaunchKernelGGL((k_encode<true, false>), g, b, shm, st, codes, n, len, cw, woff, ooff, words, oval);
+  else if (vec)
+    hipLaunchKernelGGL((k_encode<false, true>), g, b, shm, st, codes, n, len, cw, woff, ooff, words, oval);
+  else
+    hipLaunchKernelGGL((k_encode<false, false>), g, b, shm, st, codes, n, len, cw, woff, ooff, words, oval);
+  BM_HIP(hipGetLastError());
+}
+
+constexpr int kDecWpc = 4;   // wavefronts per chunk in the decode
+constexpr int kDecCpw = 2;   // chunks per decode workgroup
+
+template <int WPC, int CPW>
+void launch_decode(const uint32_t* words, const uint64_t* woff, int64_t nch, int64_t n, const DecTables& t,
+                   const uint64_t* ooff, uint16_t* rel, int32_t* codes, int* err, int wcap, hipStream_t st) {
+  // LDS: tables, two flags, then per chunk its words (+2), long-code mask, tile and control block
+  const size_t per = size_t(wcap) + 2 + CHUNK / 32 + CHUNK / 2 + kCtl;
+  const size_t bytes = (size_t(kDecHdrWords) + 2 + CPW * per) * 4;
+  if (bytes > kLdsCap) fail(BM_EUNSUPPORTED, "decode workgroup does not fit in LDS");
+  hipLaunchKernelGGL((k_decode<WPC, CPW>), dim3(unsigned((nch + CPW - 1) / CPW)), dim3(64 * WPC * CPW), bytes, st,
+                     words, woff, nch, n, t, ooff, rel, codes, err, wcap);
+}
+
 }  // namespace
 
-namespace {
-
-// Code table and stream layout of a code array: histogram (device), code
-// lengths and canonical codes (host), per-chunk bit and escape counts
-// (device), word and outlier offsets (host).
-struct StreamPlan {
+// ------------------------------------------------------------------ encoder
+// One plan per code array: histogram (device), code lengths and canonical
+// codes (host), per-chunk bit and escape counts (device), word and outlier
+// offsets (host).  write() encodes with that plan.
+struct HuffmanEncoder::Impl {
+  const int32_t* codes;
+  int64_t n, nch;
+  hipStream_t st;
   std::vector<uint8_t> len;
   std::vector<uint32_t> cw, sorted;
   std::vector<uint64_t> woff, ooff;
-  int64_t nch = 0;
+  std::vector<uint16_t> psym;
+  std::vector<uint8_t> plen;
+  uint64_t wmax = 0;
+  size_t bytes = 0;
+  DevBuf<uint8_t> dlen{NSYM};
+  DevBuf<uint32_t> dcw{NSYM};
+  Impl(const int32_t* c, int64_t n_, hipStream_t s) : codes(c), n(n_), nch((n_ + CHUNK - 1) / CHUNK), st(s) {}
 };
 
-StreamPlan plan_stream(const int32_t* codes, int64_t n, hipStream_t st, DevBuf<uint8_t>& dlen, DevBuf<uint32_t>& dcw) {
+HuffmanEncoder::HuffmanEncoder(const int32_t* codes, int64_t n, hipStream_t st) {
   if (n < 0 || (n > 0 && !codes)) fail(BM_EINVAL, "bad code array");
-  StreamPlan sp;
-  const int64_t nch = (n + CHUNK - 1) / CHUNK;
-  sp.nch = nch;
+  d_ = std::make_unique<Impl>(codes, n, st);
+  Impl& I = *d_;
+  bm_lossless_times& T = g_times;
+  T.enc_n = n;
+  T.enc_hist_ms = T.enc_table_ms = T.enc_sizes_ms = T.enc_encode_ms = T.enc_copy_ms = T.enc_crc_ms = 0.0;
+  const int64_t nch = I.nch;
   DevBuf<unsigned long long> hist(NSYM);
+  EventPair eh, eb;
+  BM_HIP(hipEventRecord(eh.a, st));
   hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, hist.p, int64_t(NSYM));
   if (n) {
     const int64_t g = std::min<int64_t>(2048, (n + 255) / 256);
     hipLaunchKernelGGL(k_hist, dim3(unsigned(g)), dim3(256), 0, st, codes, n, hist.p);
   }
   BM_HIP(hipGetLastError());
+  BM_HIP(hipEventRecord(eh.b, st));
   std::vector<uint64_t> h(NSYM);
   BM_HIP(hipMemcpyAsync(h.data(), hist.p, NSYM * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
+  T.enc_hist_ms = eh.ms();
+  const auto t1 = clk::now();
   {
     auto work = std::make_unique<LenWork>();
-    sp.len.assign(NSYM, 0);
-    code_lengths(h.data(), sp.len.data(), *work);
+    I.len.assign(NSYM, 0);
+    code_lengths(h.data(), I.len.data(), *work);
   }
-  sp.cw.assign(NSYM, 0);
-  sp.sorted.assign(NSYM, 0);
+  I.cw.assign(NSYM, 0);
+  I.sorted.assign(NSYM, 0);
   int ns = 0;
-  canonical(sp.len.data(), sp.cw.data(), sp.sorted.data(), &ns);
-  sp.sorted.resize(ns);
-  BM_HIP(hipMemcpyAsync(dlen.p, sp.len.data(), NSYM, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dcw.p, sp.cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  canonical(I.len.data(), I.cw.data(), I.sorted.data(), &ns);
+  I.sorted.resize(ns);
+  for (int s = 0; s < NSYM; ++s)
+    if (I.len[s]) {
+      I.psym.push_back(uint16_t(s));
+      I.plen.push_back(I.len[s]);
+    }
+  T.enc_table_ms = ms_since(t1);
+  const auto t2 = clk::now();
+  BM_HIP(hipMemcpyAsync(I.dlen.p, I.len.data(), NSYM, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(I.dcw.p, I.cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   DevBuf<uint32_t> bits(size_t(std::max<int64_t>(nch, 1))), esc(size_t(std::max<int64_t>(nch, 1)));
-  if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, bits.p, esc.p);
-  BM_HIP(hipGetLastError());
+  BM_HIP(hipEventRecord(eb.a, st));
+  launch_chunk_bits(codes, n, nch, I.dlen.p, bits.p, esc.p, st);
+  BM_HIP(hipEventRecord(eb.b, st));
   std::vector<uint32_t> hb(nch), he(nch);
   if (nch) {
     BM_HIP(hipMemcpyAsync(hb.data(), bits.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     BM_HIP(hipMemcpyAsync(he.data(), esc.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   }
   BM_HIP(hipStreamSynchronize(st));
-  sp.woff.assign(nch + 1, 0);
-  sp.ooff.assign(nch + 1, 0);
+  I.woff.assign(nch + 1, 0);
+  I.ooff.assign(nch + 1, 0);
   for (int64_t c = 0; c < nch; ++c) {
-    sp.woff[c + 1] = sp.woff[c] + (uint64_t(hb[c]) + 31) / 32;
-    sp.ooff[c + 1] = sp.ooff[c] + he[c];
+    const uint64_t w = (uint64_t(hb[c]) + 31) / 32;
+    I.wmax = std::max(I.wmax, w);
+    I.woff[c + 1] = I.woff[c] + w;
+    I.ooff[c + 1] = I.ooff[c] + he[c];
   }
-  return sp;
+  T.enc_sizes_ms = ms_since(t2);
+  I.bytes = sizeof(HuffHeader) + I.psym.size() * 3 + size_t(nch + 1) * 16 + size_t(I.woff[nch]) * 4 +
+            size_t(I.ooff[nch]) * 4;
 }
 
-size_t stream_bytes(const StreamPlan& sp) {
-  int64_t np = 0;
-  for (int s = 0; s < NSYM; ++s) np += sp.len[s] != 0;
-  return sizeof(HuffHeader) + size_t(np) * 3 + size_t(sp.nch + 1) * 16 + size_t(sp.woff[sp.nch]) * 4 +
-         size_t(sp.ooff[sp.nch]) * 4;
-}
+HuffmanEncoder::~HuffmanEncoder() = default;
 
-}  // namespace
+size_t HuffmanEncoder::bytes() const { return d_->bytes; }
 
-size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st) {
-  DevBuf<uint8_t> dlen(NSYM);
-  DevBuf<uint32_t> dcw(NSYM);
-  return stream_bytes(plan_stream(codes, n, st, dlen, dcw));
-}
-
-size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st) {
-  const size_t bytes = huffman_size(codes, n, st);
-  out.resize(bytes);
-  return huffman_encode_to(codes, n, out.data(), bytes, st);
-}
-
-size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t capacity, hipStream_t st) {
-  DevBuf<uint8_t> dlen(NSYM);
-  DevBuf<uint32_t> dcw(NSYM);
-  const StreamPlan sp = plan_stream(codes, n, st, dlen, dcw);
-  const int64_t nch = sp.nch;
-  const std::vector<uint8_t>& len = sp.len;
-  const std::vector<uint64_t>& woff = sp.woff;
-  const std::vector<uint64_t>& ooff = sp.ooff;
-  const int64_t nw = int64_t(woff[nch]), nout = int64_t(ooff[nch]);
+void HuffmanEncoder::write(uint8_t* dst, size_t capacity) {
+  Impl& I = *d_;
+  bm_lossless_times& T = g_times;
+  if (I.bytes > capacity) fail(BM_ECAPACITY, "Huffman stream larger than its buffer");
+  const int64_t nch = I.nch, nw = int64_t(I.woff[nch]), nout = int64_t(I.ooff[nch]);
+  const int64_t np = int64_t(I.psym.size());
   DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
   DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
   DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
-  BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  if (nch)
-    hipLaunchKernelGGL(k_encode<false>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p,
-                       dooff.p, static_cast<void*>(dwords.p), static_cast<void*>(doval.p));
-  BM_HIP(hipGetLastError());
-  std::vector<uint16_t> psym;
-  std::vector<uint8_t> plen;
-  for (int s = 0; s < NSYM; ++s)
-    if (len[s]) {
-      psym.push_back(uint16_t(s));
-      plen.push_back(len[s]);
-    }
-  const int64_t np = int64_t(psym.size());
-  HuffHeader hh{kHuffMagic, 3, n, nch, nw, nout, np};
-  const size_t bytes = sizeof(hh) + size_t(np) * 3 + (nch + 1) * 16 + size_t(nw) * 4 + size_t(nout) * 4;
-  if (bytes > capacity) fail(BM_ECAPACITY, "Huffman stream larger than its buffer");
+  BM_HIP(hipMemcpyAsync(dwoff.p, I.woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, I.st));
+  BM_HIP(hipMemcpyAsync(dooff.p, I.ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, I.st));
+  EventPair ee, ec;
+  BM_HIP(hipEventRecord(ee.a, I.st));
+  launch_encode(I.codes, I.n, nch, I.dlen.p, I.dcw.p, dwoff.p, dooff.p, I.wmax, dwords.p, doval.p, I.st);
+  BM_HIP(hipEventRecord(ee.b, I.st));
+  HuffHeader hh{kHuffMagic, 3, I.n, nch, nw, nout, np};
   uint8_t* o = dst;
   std::memcpy(o, &hh, sizeof(hh));
   o += sizeof(hh);
-  if (np) std::memcpy(o, psym.data(), size_t(np) * 2);
+  if (np) std::memcpy(o, I.psym.data(), size_t(np) * 2);
   o += size_t(np) * 2;
-  if (np) std::memcpy(o, plen.data(), size_t(np));
+  if (np) std::memcpy(o, I.plen.data(), size_t(np));
   o += size_t(np);
-  std::memcpy(o, woff.data(), (nch + 1) * 8);
+  std::memcpy(o, I.woff.data(), (nch + 1) * 8);
   o += (nch + 1) * 8;
-  std::memcpy(o, ooff.data(), (nch + 1) * 8);
+  std::memcpy(o, I.ooff.data(), (nch + 1) * 8);
   o += (nch + 1) * 8;
-  if (nw) BM_HIP(hipMemcpyAsync(o, dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, st));
+  BM_HIP(hipEventRecord(ec.a, I.st));
+  if (nw) BM_HIP(hipMemcpyAsync(o, dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, I.st));
   o += size_t(nw) * 4;
-  if (nout) BM_HIP(hipMemcpyAsync(o, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, st));
-  BM_HIP(hipStreamSynchronize(st));
-  return bytes;
+  if (nout) BM_HIP(hipMemcpyAsync(o, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, I.st));
+  BM_HIP(hipEventRecord(ec.b, I.st));
+  BM_HIP(hipStreamSynchronize(I.st));
+  T.enc_encode_ms = ee.ms();
+  T.enc_copy_ms = ec.ms();
 }
 
+size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st) { return HuffmanEncoder(codes, n, st).bytes(); }
+
+size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st) {
+  HuffmanEncoder e(codes, n, st);
+  out.resize(e.bytes());
+  e.write(out.data(), out.size());
+  return out.size();
+}
+
+void set_lossless_crc_ms(double ms) { g_times.enc_crc_ms = ms; }
+
+void huffman_code_lengths(const uint64_t* hist, uint8_t* len) {
+  auto work = std::make_unique<LenWork>();
+  code_lengths(hist, len, *work);
+}
+
+bm_lossless_times lossless_times() { return g_times; }
+
+// ------------------------------------------------------------------ decode (host)
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st) {
+  bm_lossless_times& T = g_times;
+  T.dec_n = n;
+  T.dec_parse_ms = T.dec_upload_ms = T.dec_decode_ms = 0.0;
+  const auto t0 = clk::now();
   if (!in || in_bytes < sizeof(HuffHeader)) fail(BM_ECORRUPT, "Huffman stream too short");
   HuffHeader hh;
   std::memcpy(&hh, in, sizeof(hh));
@@ -563,10 +867,15 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   std::memcpy(ooff.data(), p, (nch + 1) * 8);
   p += (nch + 1) * 8;
   if (woff[0] != 0 || ooff[0] != 0 || ooff[nch] != uint64_t(nout)) fail(BM_ECORRUPT, "bad chunk offsets");
-  for (int64_t c = 0; c < nch; ++c)
-    if (woff[c + 1] < woff[c] || woff[c + 1] > uint64_t(nw) || ooff[c + 1] < ooff[c] ||
-        ooff[c + 1] - ooff[c] > uint64_t(CHUNK))
+  uint64_t wcap = 0;
+  for (int64_t c = 0; c < nch; ++c) {
+    const uint64_t cnt = uint64_t(std::min<int64_t>(CHUNK, n - c * CHUNK));
+    // a chunk of cnt symbols has at most 32 cnt bits
+    if (woff[c + 1] < woff[c] || woff[c + 1] > uint64_t(nw) || woff[c + 1] - woff[c] > cnt ||
+        ooff[c + 1] < ooff[c] || ooff[c + 1] - ooff[c] > cnt)
       fail(BM_ECORRUPT, "bad chunk offsets");
+    wcap = std::max(wcap, woff[c + 1] - woff[c]);
+  }
   uint64_t kraft = 0;
   for (int s = 0; s < NSYM; ++s) {
     if (len[s] > LMAX) fail(BM_ECORRUPT, "code length above 32");
@@ -577,30 +886,60 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   int ns = 0;
   canonical(len.data(), cw.data(), sorted.data(), &ns);
   sorted.resize(ns);
-  std::vector<uint32_t> first(LMAX + 1, 0), count(LMAX + 1, 0), base(LMAX + 1, 0), lut(1u << LUTB, 0);
-  for (size_t i = 0; i < sorted.size(); ++i) {
-    const int l = len[sorted[i]];
-    if (count[l] == 0) {
-      first[l] = cw[sorted[i]];
-      base[l] = uint32_t(i);
+  // decode tables (layout at k_decode)
+  std::vector<uint32_t> hdr(kDecHdrWords, 0);
+  std::vector<uint16_t> sorted16(std::max<size_t>(sorted.size(), 1));
+  {
+    uint32_t* lut = hdr.data();
+    uint32_t* lastc = lut + (1 << DLB);
+    uint32_t* offs = lastc + (LMAX + 1);
+    uint32_t first[LMAX + 1] = {}, count[LMAX + 1] = {}, base[LMAX + 1] = {};
+    for (size_t i = 0; i < sorted.size(); ++i) {
+      const uint32_t s = sorted[i], l = len[s];
+      sorted16[i] = uint16_t(s);
+      if (count[l] == 0) {
+        first[l] = cw[s];
+        base[l] = uint32_t(i);
+      }
+      ++count[l];
+      if (l <= DLB) {
+        const uint32_t lo = cw[s] << (DLB - l), span = 1u << (DLB - l);
+        for (uint32_t k = 0; k < span; ++k) lut[lo + k] = s | (l << 16);
+      } else {
+        uint32_t& e = lut[cw[s] >> (l - DLB)];
+        e = e ? ((e & ~(63u << 24)) | (l << 24)) : (kLong | (l << 16) | (l << 24) | uint32_t(i));
+      }
     }
-    ++count[l];
-    if (l <= LUTB) {
-      const uint32_t lo = cw[sorted[i]] << (LUTB - l), span = 1u << (LUTB - l);
-      for (uint32_t k = 0; k < span; ++k) lut[lo + k] = sorted[i] | (uint32_t(l) << 16);
+    // prefixes of one code length whose codes fill them: length and first index in the entry
+    for (uint32_t pf = 0; pf < (1u << DLB); ++pf) {
+      const uint32_t e = lut[pf];
+      if (!(e & kLong)) continue;
+      const uint32_t lmin = (e >> 16) & 63u, lmax = (e >> 24) & 63u, i0 = e & 0xFFFFu;
+      if (lmin != lmax || i0 + (1u << (lmin - DLB)) > uint32_t(sorted.size())) continue;
+      const uint32_t s0 = sorted[i0], sl = sorted[i0 + (1u << (lmin - DLB)) - 1];
+      // the prefix's first code starts it; the 2^(l - DLB)-th code of length l from there ends it
+      if (len[sl] == lmin && (cw[s0] >> (lmin - DLB)) == pf && (cw[sl] >> (lmin - DLB)) == pf)
+        lut[pf] = kOne | i0 | (lmin << 16);
+    }
+    uint64_t end = 0;   // left-justified end of the codes of length <= L
+    for (int l = 1; l <= LMAX; ++l) {
+      if (count[l]) end = (uint64_t(first[l]) + count[l]) << (LMAX - l);
+      lastc[l] = end ? uint32_t(end - 1) : 0u;
+      offs[l] = base[l] - first[l];
     }
   }
-  DevBuf<uint32_t> dlut(lut.size()), dfirst(LMAX + 1), dcount(LMAX + 1), dbase(LMAX + 1),
-      dsorted(std::max<size_t>(sorted.size(), 1));
+  T.dec_parse_ms = ms_since(t0);
+  DevBuf<uint32_t> dhdr(hdr.size());
+  DevBuf<uint16_t> dsorted(sorted16.size());
   DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
   DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
   DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
+  DevBuf<uint16_t> drel(size_t(std::max<int64_t>(nout, 1)));
   DevBuf<int> derr(1);
-  BM_HIP(hipMemcpyAsync(dlut.p, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dfirst.p, first.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dcount.p, count.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dbase.p, base.data(), (LMAX + 1) * 4, hipMemcpyHostToDevice, st));
-  if (!sorted.empty()) BM_HIP(hipMemcpyAsync(dsorted.p, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice, st));
+  EventPair eu, ed;
+  BM_HIP(hipEventRecord(eu.a, st));
+  BM_HIP(hipMemcpyAsync(dhdr.p, hdr.data(), hdr.size() * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(dsorted.p, sorted16.data(), sorted16.size() * 2, hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
   if (nw) BM_HIP(hipMemcpyAsync(dwords.p, p, size_t(nw) * 4, hipMemcpyHostToDevice, st));
@@ -608,14 +947,25 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   if (nout) BM_HIP(hipMemcpyAsync(doval.p, p, size_t(nout) * 4, hipMemcpyHostToDevice, st));
   const int zero = 0;
   BM_HIP(hipMemcpyAsync(derr.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
-  DecTables t{dlut.p, dfirst.p, dcount.p, dbase.p, dsorted.p};
-  if (nch)
-    hipLaunchKernelGGL(k_decode, dim3(unsigned((nch + 63) / 64)), dim3(64), 0, st, dwords.p, dwoff.p, nch, n, t,
-                       dooff.p, doval.p, codes, derr.p);
-  BM_HIP(hipGetLastError());
+  BM_HIP(hipEventRecord(eu.b, st));
+  uint32_t escidx = uint32_t(sorted16.size());
+  for (size_t i = 0; i < sorted.size(); ++i)
+    if (sorted[i] == 0) escidx = uint32_t(i);
+  const DecTables t{dhdr.p, dsorted.p, uint32_t(sorted16.size()), escidx};
+  BM_HIP(hipEventRecord(ed.a, st));
+  if (nch) {
+    launch_decode<kDecWpc, kDecCpw>(dwords.p, dwoff.p, nch, n, t, dooff.p, drel.p, codes, derr.p, int(wcap), st);
+    BM_HIP(hipGetLastError());
+    if (nout)
+      hipLaunchKernelGGL(k_outliers, dim3(unsigned(nch)), dim3(256), 0, st, dooff.p, drel.p, doval.p, codes, n);
+    BM_HIP(hipGetLastError());
+  }
+  BM_HIP(hipEventRecord(ed.b, st));
   int herr = 0;
   BM_HIP(hipMemcpyAsync(&herr, derr.p, sizeof(int), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
+  T.dec_upload_ms = eu.ms();
+  T.dec_decode_ms = ed.ms();
   if (herr) fail(BM_ECORRUPT, "Huffman stream does not decode");
 }
 
@@ -623,80 +973,18 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
 // The encoder's stages timed one by one (the lossless part of the time model
 // of Algorithm 1): histogram, code table, chunk sizes + encode, copy-out + CRC.
 void huffman_stage_times(const int32_t* codes, int64_t n, hipStream_t st, double ms[4]) {
-  using clk = std::chrono::steady_clock;
-  auto since = [](clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); };
-  hipEvent_t e0, e1;
-  BM_HIP(hipEventCreate(&e0));
-  BM_HIP(hipEventCreate(&e1));
-  auto elapsed = [&]() {
-    BM_HIP(hipEventSynchronize(e1));
-    float t = 0.f;
-    BM_HIP(hipEventElapsedTime(&t, e0, e1));
-    return double(t);
-  };
-  const int64_t nch = (n + CHUNK - 1) / CHUNK;
-  DevBuf<unsigned long long> hist(NSYM);
-  DevBuf<uint8_t> dlen(NSYM);
-  DevBuf<uint32_t> dcw(NSYM);
-  DevBuf<uint32_t> bits(size_t(std::max<int64_t>(nch, 1))), esc(size_t(std::max<int64_t>(nch, 1)));
-  // (0) histogram
-  BM_HIP(hipEventRecord(e0, st));
-  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, hist.p, int64_t(NSYM));
-  if (n) hipLaunchKernelGGL(k_hist, dim3(unsigned(std::min<int64_t>(2048, (n + 255) / 256))), dim3(256), 0, st, codes, n,
-                            hist.p);
-  BM_HIP(hipEventRecord(e1, st));
-  ms[0] = elapsed();
-  // (1) code table on the host
-  auto t1 = clk::now();
-  std::vector<uint64_t> h(NSYM);
-  BM_HIP(hipMemcpyAsync(h.data(), hist.p, NSYM * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  BM_HIP(hipStreamSynchronize(st));
-  auto work = std::make_unique<LenWork>();
-  std::vector<uint8_t> len(NSYM);
-  std::vector<uint32_t> cw(NSYM), sorted(NSYM);
-  int ns = 0;
-  code_lengths(h.data(), len.data(), *work);
-  canonical(len.data(), cw.data(), sorted.data(), &ns);
-  ms[1] = since(t1);
-  // (2) chunk sizes, offsets on the host, encode
-  auto t2 = clk::now();
-  BM_HIP(hipMemcpyAsync(dlen.p, len.data(), NSYM, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dcw.p, cw.data(), NSYM * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-  if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, bits.p, esc.p);
-  std::vector<uint32_t> hb(nch), he(nch);
-  if (nch) {
-    BM_HIP(hipMemcpyAsync(hb.data(), bits.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    BM_HIP(hipMemcpyAsync(he.data(), esc.p, nch * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  }
-  BM_HIP(hipStreamSynchronize(st));
-  std::vector<uint64_t> woff(nch + 1, 0), ooff(nch + 1, 0);
-  for (int64_t c = 0; c < nch; ++c) {
-    woff[c + 1] = woff[c] + (uint64_t(hb[c]) + 31) / 32;
-    ooff[c + 1] = ooff[c] + he[c];
-  }
-  const int64_t nw = int64_t(woff[nch]), nout = int64_t(ooff[nch]);
-  DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
-  DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
-  DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
-  BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  if (nch)
-    hipLaunchKernelGGL(k_encode<false>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen.p, dcw.p, dwoff.p,
-                       dooff.p, static_cast<void*>(dwords.p), static_cast<void*>(doval.p));
-  BM_HIP(hipGetLastError());
-  BM_HIP(hipStreamSynchronize(st));
-  ms[2] = since(t2);
-  // (3) the stream to the host and its CRC
-  auto t3 = clk::now();
-  std::vector<uint8_t> out(size_t(nw) * 4 + size_t(nout) * 4 + 16);
-  if (nw) BM_HIP(hipMemcpyAsync(out.data(), dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, st));
-  if (nout) BM_HIP(hipMemcpyAsync(out.data() + size_t(nw) * 4, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, st));
-  BM_HIP(hipStreamSynchronize(st));
+  HuffmanEncoder e(codes, n, st);
+  std::vector<uint8_t> out(e.bytes());
+  e.write(out.data(), out.size());
+  const auto t0 = clk::now();
   volatile uint32_t crc = container_crc(out.data(), out.size());
   (void)crc;
-  ms[3] = since(t3);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  const double crc_ms = ms_since(t0);
+  const bm_lossless_times& T = g_times;
+  ms[0] = T.enc_hist_ms;
+  ms[1] = T.enc_table_ms;
+  ms[2] = T.enc_sizes_ms + T.enc_encode_ms;
+  ms[3] = T.enc_copy_ms + crc_ms;
 }
 
 // ------------------------------------------------------------------ no allocation
@@ -778,8 +1066,7 @@ size_t huffman_encode_noalloc(const int32_t* codes, int64_t n, void* out, size_t
   canonical(H.len, H.cw, H.sorted, &ns);
   BM_HIP(hipMemcpyAsync(dlen, H.len, sizeof(H.len), hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dcw, H.cw, sizeof(H.cw), hipMemcpyHostToDevice, st));
-  if (nch) hipLaunchKernelGGL(k_chunk_bits, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen, bits, esc);
-  BM_HIP(hipGetLastError());
+  launch_chunk_bits(codes, n, nch, dlen, bits, esc, st);
   if (nch) {
     BM_HIP(hipMemcpyAsync(H.bits, bits, size_t(nch) * 4, hipMemcpyDeviceToHost, st));
     BM_HIP(hipMemcpyAsync(H.esc, esc, size_t(nch) * 4, hipMemcpyDeviceToHost, st));
@@ -787,8 +1074,11 @@ size_t huffman_encode_noalloc(const int32_t* codes, int64_t n, void* out, size_t
   BM_HIP(hipStreamSynchronize(st));
   H.woff[0] = 0;
   H.ooff[0] = 0;
+  uint64_t wmax = 0;
   for (int64_t c = 0; c < nch; ++c) {
-    H.woff[c + 1] = H.woff[c] + (uint64_t(H.bits[c]) + 31) / 32;
+    const uint64_t w = (uint64_t(H.bits[c]) + 31) / 32;
+    wmax = std::max(wmax, w);
+    H.woff[c + 1] = H.woff[c] + w;
     H.ooff[c + 1] = H.ooff[c] + H.esc[c];
   }
   int64_t np = 0;
@@ -815,18 +1105,7 @@ size_t huffman_encode_noalloc(const int32_t* codes, int64_t n, void* out, size_t
   BM_HIP(hipMemcpyAsync(o + off_off + size_t(nch + 1) * 8, H.ooff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dwoff, H.woff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
   BM_HIP(hipMemcpyAsync(dooff, H.ooff, size_t(nch + 1) * 8, hipMemcpyHostToDevice, st));
-  if (nch) {
-    void* wd = o + off_words;
-    void* od = o + off_out;
-    const bool aligned = (reinterpret_cast<uintptr_t>(wd) & 3) == 0;   // off_out - off_words is a multiple of 4
-    if (aligned)
-      hipLaunchKernelGGL(k_encode<false>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen, dcw, dwoff, dooff,
-                         wd, od);
-    else
-      hipLaunchKernelGGL(k_encode<true>, dim3(unsigned(nch)), dim3(64), 0, st, codes, n, dlen, dcw, dwoff, dooff,
-                         wd, od);
-  }
-  BM_HIP(hipGetLastError());
+  launch_encode(codes, n, nch, dlen, dcw, dwoff, dooff, wmax, o + off_words, o + off_out, st);
   BM_HIP(hipStreamSynchronize(st));
   return bytes;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -357,14 +358,31 @@ int batch_overflows(bm_batch_s& b, std::vector<int>& bad, hipStream_t st);
 std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const double* voxel_tol, double slack, int reps,
                                    bm_config& out, hipStream_t st, double budget_ms = 0.0, bool* fits = nullptr);
 
-// huffman (host buffers)
+// huffman (host buffers).  An encoder plans its stream once on creation
+// (histogram and chunk sizes on the device, code table on the host;
+// synchronizes): bytes() is the exact stream size, write() encodes into a
+// host buffer of at least that size.  Stage times of the calling thread's
+// last encode and decode are kept for lossless_times().
+class HuffmanEncoder {
+ public:
+  HuffmanEncoder(const int32_t* codes, int64_t n, hipStream_t st);
+  ~HuffmanEncoder();
+  HuffmanEncoder(const HuffmanEncoder&) = delete;
+  HuffmanEncoder& operator=(const HuffmanEncoder&) = delete;
+  size_t bytes() const;
+  void write(uint8_t* dst, size_t capacity);
+
+ private:
+  struct Impl;
+  std::unique_ptr<Impl> d_;
+};
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);
-// the same stream written to dst (host, at least capacity bytes: the size
-// huffman_size gives); returns its size
-size_t huffman_encode_to(const int32_t* codes, int64_t n, uint8_t* dst, size_t capacity, hipStream_t st);
-// exact size of the stream huffman_encode would write (synchronizes)
+// exact size of the stream an encoder of these codes writes (synchronizes)
 size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);
+bm_lossless_times lossless_times();
+void huffman_code_lengths(const uint64_t* hist, uint8_t* len);
+void set_lossless_crc_ms(double ms);
 // Stage times of the Huffman encoder for n codes (ms): histogram (device),
 // code table (host), chunk sizes and encode (device, with the host's offsets),
 // copy of the stream to the host and its CRC-32.

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -139,3 +140,40 @@ def test_batch_checks_list_lengths():
         b.dequantize_recompose([1, 2], [1, 2], outs=[1])
     with pytest.raises(ValueError):
         b.compress([1, 2, 3], [1, 2])
+
+
+def _hist_cases():
+    rng = np.random.default_rng(9)
+    out = []
+    for kind in ("ties", "pow2", "wide", "equal", "laplace", "two", "one"):
+        h = np.zeros(65536, np.uint64)
+        np_ = {"two": 2, "one": 1}.get(kind, 3000 if kind != "laplace" else 65536)
+        sym = np.sort(rng.choice(65536, np_, replace=False))
+        if kind == "ties":
+            h[sym] = rng.integers(1, 4, np_)
+        elif kind == "pow2":
+            h[sym] = np.uint64(1) << rng.integers(0, 40, np_).astype(np.uint64)
+        elif kind == "wide":
+            h[sym] = rng.integers(1, 10 ** 6, np_)
+        elif kind == "equal":
+            h[sym] = 7
+        elif kind == "laplace":
+            h[:] = (1 + 4e6 * np.exp(-np.abs(np.arange(65536) - 32768) / 300.0)).astype(np.uint64)
+        else:
+            h[sym] = rng.integers(1, 100, np_)
+        out.append((kind, h))
+    return out
+
+
+@pytest.mark.parametrize("kind,hist", _hist_cases(), ids=[k for k, _ in _hist_cases()])
+def test_code_lengths_match_oracle(lib, kind, hist):
+    """The encoder's host codebook step (bm_huffman_code_lengths: two sorted
+    queues) equals the oracle's heap-based Huffman construction, ties, the
+    32-bit length cap and a dense 65536-symbol table included."""
+    from oracle import huffman as ohf
+    from paper_2609_00205_amd import api
+    got = api.huffman_code_lengths(hist)
+    ref = ohf.code_lengths(hist.astype(np.int64))
+    assert np.array_equal(got.astype(np.int64), ref)
+    if kind == "pow2":
+        assert int(ref.max()) == 32      # the cap is reached
