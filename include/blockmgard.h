@@ -264,6 +264,20 @@ bm_status bm_dequantize_recompose(bm_plan plan, const int32_t* codes, const doub
 bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity,
                             size_t* out_bytes, hipStream_t stream);
 
+/* bm_huffman_encode in two calls, so a caller that sizes its buffer from the
+ * first does not plan the stream twice: bm_huffman_plan runs the histogram,
+ * code table and chunk sizes of codes (device, n entries; synchronous) and
+ * returns a handle and the stream's exact size; bm_huffman_write encodes into
+ * out (host, capacity bytes; synchronous) the bytes bm_huffman_encode
+ * writes, and may be called again.  codes must stay allocated and unchanged
+ * until the last write.  bm_huffman_destroy frees the handle (NULL is
+ * accepted).  Errors: BM_EINVAL (bad n or pointer), BM_ECAPACITY (out too
+ * small; *out_bytes holds the size). */
+typedef struct bm_huffman_s* bm_huffman;
+bm_status bm_huffman_plan(const int32_t* codes, int64_t n, bm_huffman* out, size_t* out_bytes, hipStream_t stream);
+bm_status bm_huffman_write(bm_huffman h, void* out, size_t capacity, size_t* out_bytes);
+bm_status bm_huffman_destroy(bm_huffman h);
+
 /* For callers that cannot allocate memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation): bm_huffman_encode
  * with the stream written to device memory.  out (device, capacity bytes)
@@ -329,6 +343,20 @@ bm_status bm_lossless_last_times(bm_lossless_times* out);
  * BM_ENONFINITE: NaN or Inf in x or in block_tol (nothing is written). */
 bm_status bm_compress(bm_plan plan, const void* x, const double* block_tol, void* out,
                       size_t capacity, size_t* out_bytes, hipStream_t stream);
+
+/* bm_compress in two calls, so a caller that sizes its buffer from the
+ * result does not decompose, quantize and plan twice.  bm_compress_plan does
+ * all but the writing (decompose, quantize, histogram, code table, chunk
+ * sizes; synchronous), keeps the pending container in the plan and sets
+ * *out_bytes to its exact size; bm_compress_write writes it to out (host,
+ * capacity bytes; synchronous) and drops it.  x and block_tol must not change
+ * in between (the raw copy reads x when written).  Another bm_compress or
+ * bm_compress_plan on the plan drops a pending container; bm_compress_write
+ * without one: BM_EINVAL; a buffer too small: BM_ECAPACITY, the container
+ * stays pending.  Errors of the plan step as bm_compress. */
+bm_status bm_compress_plan(bm_plan plan, const void* x, const double* block_tol, size_t* out_bytes,
+                           hipStream_t stream);
+bm_status bm_compress_write(bm_plan plan, void* out, size_t capacity, size_t* out_bytes);
 
 /* Read the configuration stored in a compressed buffer (host, synchronous).
  * Checks the header (magic, version, payload size), not the CRC: a call that

@@ -280,17 +280,13 @@ class Plan:
     def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None) -> bytearray:
         _need(x, self.dtype, self.shape, "x")
         _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        # planned once (bm_compress_plan), written into a buffer of its exact size
         need = C.c_size_t(0)
-        st = _stream(stream)
-        try:
-            call("bm_compress", self._h, _ptr(x), _ptr(block_tol), None, 0, C.byref(need), st)
-        except _lib.BMError as e:
-            if e.code != -5:
-                raise
+        call("bm_compress_plan", self._h, _ptr(x), _ptr(block_tol), C.byref(need), _stream(stream))
         buf = bytearray(need.value)
         got = C.c_size_t(0)
         view = _writable(buf)
-        call("bm_compress", self._h, _ptr(x), _ptr(block_tol), view, need.value, C.byref(got), st)
+        call("bm_compress_write", self._h, view, need.value, C.byref(got))
         del view
         return _take(buf, got.value)
 
@@ -311,19 +307,20 @@ def decompress(buf, device=None, stream=None) -> torch.Tensor:
 
 
 def huffman_encode(codes: torch.Tensor, stream=None) -> bytearray:
+    """The Huffman stream of int32 device codes (bm_huffman_plan, then
+    bm_huffman_write into a buffer of the stream's exact size)."""
     _need(codes, torch.int32, None, "codes")
     need = C.c_size_t(0)
-    st = _stream(stream)
+    h = C.c_void_p()
+    call("bm_huffman_plan", _ptr(codes), codes.numel(), C.byref(h), C.byref(need), _stream(stream))
     try:
-        call("bm_huffman_encode", _ptr(codes), codes.numel(), None, 0, C.byref(need), st)
-    except _lib.BMError as e:
-        if e.code != -5:
-            raise
-    buf = bytearray(need.value)
-    got = C.c_size_t(0)
-    view = _writable(buf)
-    call("bm_huffman_encode", _ptr(codes), codes.numel(), view, need.value, C.byref(got), st)
-    del view
+        buf = bytearray(need.value)
+        got = C.c_size_t(0)
+        view = _writable(buf)
+        call("bm_huffman_write", h, view, need.value, C.byref(got))
+        del view
+    finally:
+        _lib.lib().bm_huffman_destroy(h)
     return _take(buf, got.value)
 
 

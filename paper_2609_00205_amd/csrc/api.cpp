@@ -217,19 +217,30 @@ void check_block_tol(bm_plan_s& p, const double* block_tol, hipStream_t st) {
     if (!(t > 0) || !std::isfinite(t)) fail(BM_ENONFINITE, "block tolerances must be positive and finite");
 }
 
-bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine, void* out,
-                     size_t capacity, size_t* needed, hipStream_t st) {
+struct PendingContainer {
+  std::vector<uint8_t> head;   // the header, CRC not set
+  std::vector<double> tol;     // block tolerance map
+  std::unique_ptr<HuffmanEncoder> enc;
+  const void* x = nullptr;     // source of the raw copy (device)
+  size_t total = 0;
+  hipStream_t st = nullptr;
+};
+
+size_t pending_bytes(const PendingContainer& c) { return c.total; }
+
+std::shared_ptr<PendingContainer> plan_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine,
+                                                 hipStream_t st) {
   const int64_t npad = p.pdims[0] * p.pdims[1] * p.pdims[2];
   const int64_t nlog = p.dims[0] * p.dims[1] * p.dims[2];
   const int64_t ntol = p.nb1[0] * p.nb1[1] * p.nb1[2];
-  std::vector<double> tol(ntol);
-  BM_HIP(hipMemcpyAsync(tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
-  // the stream's size first (histogram and code plan only); the encode runs
-  // only when the container is written, straight into the caller's buffer
+  auto c = std::make_shared<PendingContainer>();
+  c->tol.resize(ntol);
+  BM_HIP(hipMemcpyAsync(c->tol.data(), block_tol, ntol * sizeof(double), hipMemcpyDeviceToHost, st));
+  // the stream is planned once (histogram, code table, chunk sizes); it is
+  // encoded when the container is written, straight into the caller's buffer
   const int32_t* codes = static_cast<const int32_t*>(p.ws.codes);
-  std::unique_ptr<HuffmanEncoder> enc;
-  if (!too_fine) enc = std::make_unique<HuffmanEncoder>(codes, npad, st);
-  const size_t sb = enc ? enc->bytes() : 0;
+  if (!too_fine) c->enc = std::make_unique<HuffmanEncoder>(codes, npad, st);
+  const size_t sb = c->enc ? c->enc->bytes() : 0;
   BM_HIP(hipStreamSynchronize(st));
   CHeader h{};
   h.magic = kMagic;
@@ -248,24 +259,42 @@ bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool 
   const size_t raw = size_t(nlog) * p.esize;
   h.flags = (too_fine || coded >= raw) ? 1u : 0u;
   h.payload = h.flags ? raw : coded;
-  const size_t total = sizeof(CHeader) + size_t(h.payload);
-  *needed = total;
-  if (!out || capacity < total) return false;
+  if (h.flags) c->enc.reset();
+  c->head.assign(reinterpret_cast<const uint8_t*>(&h), reinterpret_cast<const uint8_t*>(&h) + sizeof(h));
+  c->x = x;
+  c->total = sizeof(CHeader) + size_t(h.payload);
+  c->st = st;
+  return c;
+}
+
+void write_pending(PendingContainer& c, void* out) {
+  CHeader h;
+  std::memcpy(&h, c.head.data(), sizeof(h));
+  const size_t ntol = size_t(h.ntol);
   uint8_t* o = static_cast<uint8_t*>(out) + sizeof(CHeader);
-  if (h.flags) {
-    BM_HIP(hipMemcpyAsync(o, x, raw, hipMemcpyDeviceToHost, st));
-    BM_HIP(hipStreamSynchronize(st));
+  if (h.flags & 1u) {
+    BM_HIP(hipMemcpyAsync(o, c.x, size_t(h.payload), hipMemcpyDeviceToHost, c.st));
+    BM_HIP(hipStreamSynchronize(c.st));
   } else {
-    std::memcpy(o, tol.data(), size_t(ntol) * 8);
-    enc->write(o + size_t(ntol) * 8, sb);
+    std::memcpy(o, c.tol.data(), ntol * 8);
+    c.enc->write(o + ntol * 8, size_t(h.payload) - ntol * 8);
   }
   h.crc = 0;
   const auto t0 = std::chrono::steady_clock::now();
-  uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
-  c = crc32_parallel(o, size_t(h.payload), c);
-  h.crc = c;
-  if (enc) set_lossless_crc_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+  uint32_t crc = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
+  crc = crc32_parallel(o, size_t(h.payload), crc);
+  h.crc = crc;
+  if (!(h.flags & 1u))
+    set_lossless_crc_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   std::memcpy(out, &h, sizeof(h));
+}
+
+bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine, void* out,
+                     size_t capacity, size_t* needed, hipStream_t st) {
+  std::shared_ptr<PendingContainer> c = plan_container(p, x, block_tol, too_fine, st);
+  *needed = c->total;
+  if (!out || capacity < c->total) return false;
+  write_pending(*c, out);
   return true;
 }
 
@@ -467,6 +496,41 @@ bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t c
   });
 }
 
+struct bm_huffman_s {
+  std::unique_ptr<bm::HuffmanEncoder> enc;
+  int device = 0;
+};
+
+bm_status bm_huffman_plan(const int32_t* codes, int64_t n, bm_huffman* out, size_t* out_bytes, hipStream_t st) {
+  return guarded([&] {
+    need(out && out_bytes, "null argument");
+    need(codes || n == 0, "null codes");
+    *out = nullptr;
+    auto h = std::make_unique<bm_huffman_s>();
+    BM_HIP(hipGetDevice(&h->device));
+    h->enc = std::make_unique<bm::HuffmanEncoder>(codes, n, st);
+    *out_bytes = h->enc->bytes();
+    *out = h.release();
+  });
+}
+
+bm_status bm_huffman_write(bm_huffman h, void* out, size_t capacity, size_t* out_bytes) {
+  return guarded([&] {
+    need(h && out_bytes, "null argument");
+    const size_t bytes = h->enc->bytes();
+    *out_bytes = bytes;
+    if (!out || capacity < bytes) bm::fail(BM_ECAPACITY, "output buffer too small");
+    int dev = 0;
+    BM_HIP(hipGetDevice(&dev));
+    if (dev != h->device) bm::fail(BM_EINVAL, "handle planned on another device");
+    h->enc->write(static_cast<uint8_t*>(out), bytes);
+  });
+}
+
+bm_status bm_huffman_destroy(bm_huffman h) {
+  return guarded([&] { delete h; });
+}
+
 bm_status bm_huffman_encode_device(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
                                    hipStream_t st) {
   return guarded([&] {
@@ -501,6 +565,7 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
   return guarded([&] {
     need(p && x && block_tol && out_bytes, "null argument");
     check_device(p);
+    p->pending.reset();
     bm::ensure_pipeline_buffers(*p);
     bool too_fine = false;   // codes beyond 32 bits: store the raw data
     bm::check_block_tol(*p, block_tol, st);
@@ -513,6 +578,39 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
     }
     if (!bm::write_container(*p, x, block_tol, too_fine, out, capacity, out_bytes, st))
       bm::fail(BM_ECAPACITY, "output buffer too small");
+  });
+}
+
+bm_status bm_compress_plan(bm_plan p, const void* x, const double* block_tol, size_t* out_bytes, hipStream_t st) {
+  return guarded([&] {
+    need(p && x && block_tol && out_bytes, "null argument");
+    check_device(p);
+    p->pending.reset();
+    bm::ensure_pipeline_buffers(*p);
+    bool too_fine = false;   // codes beyond 32 bits: store the raw data
+    bm::check_block_tol(*p, block_tol, st);
+    try {
+      bm_qstats qs;
+      bm::decompose_quantize(*p, x, block_tol, static_cast<int32_t*>(p->ws.codes), &qs, st);
+    } catch (const bm::Error& e) {
+      if (e.code != BM_ERANGE) throw;
+      too_fine = true;
+    }
+    p->pending = bm::plan_container(*p, x, block_tol, too_fine, st);
+    *out_bytes = bm::pending_bytes(*p->pending);
+  });
+}
+
+bm_status bm_compress_write(bm_plan p, void* out, size_t capacity, size_t* out_bytes) {
+  return guarded([&] {
+    need(p && out_bytes, "null argument");
+    if (!p->pending) bm::fail(BM_EINVAL, "no compress planned on this plan (bm_compress_plan)");
+    const size_t total = bm::pending_bytes(*p->pending);
+    *out_bytes = total;
+    if (!out || capacity < total) bm::fail(BM_ECAPACITY, "output buffer too small");
+    check_device(p);
+    std::shared_ptr<bm::PendingContainer> c = std::move(p->pending);
+    bm::write_pending(*c, out);
   });
 }
 

@@ -148,6 +148,9 @@ struct Timing {
   std::vector<double> ms;
   std::vector<int64_t> calls;
 };
+// a compress call planned but not written (bm_compress_plan)
+struct PendingContainer;
+
 }  // namespace bm
 
 struct bm_plan_s {
@@ -165,6 +168,7 @@ struct bm_plan_s {
   // (decomposition) and its interpolation (recomposition): a global cell of
   // that level never crosses a block face (b = 9, 17 with M >= 1)
   bool fuse_next = false;
+  std::shared_ptr<bm::PendingContainer> pending;   // dropped by every compress call on the plan
 };
 
 namespace bm {
@@ -318,6 +322,11 @@ void ensure_pipeline_buffers(bm_plan_s& p);
 void check_block_tol(bm_plan_s& p, const double* block_tol, hipStream_t st);
 bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine, void* out, size_t capacity,
                      size_t* needed, hipStream_t st);
+// the same in two steps: plan (sizes, Huffman plan; synchronizes), then write
+std::shared_ptr<PendingContainer> plan_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine,
+                                                 hipStream_t st);
+size_t pending_bytes(const PendingContainer& c);
+void write_pending(PendingContainer& c, void* out);
 
 // batches of fields (one dtype and block size): build / free, the fused
 // pipeline both ways (graph: capture once per binding, then replay), and the

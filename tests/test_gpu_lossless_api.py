@@ -1,0 +1,112 @@
+"""The two-step forms of the lossless stage and its stage times, through the
+C ABI: bm_compress_plan + bm_compress_write write the bytes bm_compress
+writes (the pending container's rules: a short buffer keeps it pending, a
+second plan replaces it, a write without one fails); bm_huffman_plan +
+bm_huffman_write write the bytes bm_huffman_encode writes, also twice from
+one handle; bm_lossless_last_times reports every stage of the last encode
+and decode of the calling thread.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_00205_amd import _lib
+    _lib.lib()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _one_shot(lib, p, x, bt):
+    need = C.c_size_t(0)
+    st = lib.bm_compress(p._h, _ptr(x), _ptr(bt), None, 0, C.byref(need), None)
+    assert st == -5
+    buf = (C.c_char * need.value)()
+    got = C.c_size_t(0)
+    assert lib.bm_compress(p._h, _ptr(x), _ptr(bt), buf, need.value, C.byref(got), None) == 0
+    return bytes(buf[:got.value])
+
+
+@pytest.mark.parametrize("shape,b,L,M", [((33, 33, 33), 17, 1, 2), ((40, 50, 61), 9, 1, 2), ((65, 65, 65), 33, 1, 0)])
+def test_compress_plan_write_equals_compress(shape, b, L, M):
+    from paper_2609_00205_amd import Plan, _lib, api
+    lib = _lib.lib()
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=41, dtype=np.float32)).cuda()
+    sc = float(x.abs().max())
+    p = Plan(shape, dtype=torch.float32, block=b, L=L, M=M)
+    bt = p.tolmap_from_boxes([(2, 2, 2, 12, 12, 12, 1e-5 * sc)], 1e-2 * sc)
+    ref = _one_shot(lib, p, x, bt)
+    # write without a pending container
+    got = C.c_size_t(0)
+    assert lib.bm_compress_write(p._h, None, 0, C.byref(got)) == -1
+    need = C.c_size_t(0)
+    assert lib.bm_compress_plan(p._h, _ptr(x), _ptr(bt), C.byref(need), None) == 0
+    assert need.value == len(ref)
+    small = (C.c_char * (need.value - 1))()
+    assert lib.bm_compress_write(p._h, small, need.value - 1, C.byref(got)) == -5 and got.value == need.value
+    buf = (C.c_char * need.value)()
+    assert lib.bm_compress_write(p._h, buf, need.value, C.byref(got)) == 0   # still pending after the short buffer
+    assert bytes(buf[:got.value]) == ref
+    assert lib.bm_compress_write(p._h, buf, need.value, C.byref(got)) == -1  # written: no longer pending
+    # a second plan replaces the first; the Python binding uses the two steps
+    x2 = x * 0.5
+    assert lib.bm_compress_plan(p._h, _ptr(x), _ptr(bt), C.byref(need), None) == 0
+    assert bytes(p.compress(x2, bt)) == _one_shot(lib, p, x2, bt)
+    assert lib.bm_compress_write(p._h, buf, need.value, C.byref(got)) == -1
+    xr = api.decompress(ref)
+    assert float((xr - x).abs().max()) <= 1e-2 * sc
+
+
+@pytest.mark.parametrize("n", [1, 5000, 3 * 4096])
+def test_huffman_plan_write_equals_encode(n):
+    from paper_2609_00205_amd import _lib
+    lib = _lib.lib()
+    rng = np.random.default_rng(n)
+    q = torch.from_numpy(np.rint(rng.laplace(0, 9.0, n)).astype(np.int32)).cuda()
+    need = C.c_size_t(0)
+    assert lib.bm_huffman_encode(_ptr(q), n, None, 0, C.byref(need), None) == -5
+    ref = (C.c_char * need.value)()
+    got = C.c_size_t(0)
+    assert lib.bm_huffman_encode(_ptr(q), n, ref, need.value, C.byref(got), None) == 0
+    h = C.c_void_p()
+    size = C.c_size_t(0)
+    assert lib.bm_huffman_plan(_ptr(q), n, C.byref(h), C.byref(size), None) == 0
+    assert size.value == need.value
+    try:
+        assert lib.bm_huffman_write(h, None, 0, C.byref(got)) == -5 and got.value == size.value
+        for _ in range(2):
+            buf = (C.c_char * size.value)()
+            assert lib.bm_huffman_write(h, buf, size.value, C.byref(got)) == 0
+            assert bytes(buf) == bytes(ref)
+    finally:
+        assert lib.bm_huffman_destroy(h) == 0
+    assert lib.bm_huffman_destroy(None) == 0
+
+
+def test_stage_times_reported():
+    from paper_2609_00205_amd import Plan, api
+    shape = (65, 65, 65)
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=43, dtype=np.float32)).cuda()
+    p = Plan(shape, dtype=torch.float32, block=17, L=1, M=2)
+    bt = p.tolmap_from_boxes([], 1e-3 * float(x.abs().max()))
+    buf = p.compress(x, bt)
+    t = api.lossless_times()
+    assert t["enc_n"] == int(np.prod(p.coeff_shape))
+    for k in ("enc_hist_ms", "enc_table_ms", "enc_sizes_ms", "enc_encode_ms", "enc_copy_ms", "enc_crc_ms"):
+        assert t[k] > 0, k
+    api.decompress(buf)
+    t = api.lossless_times()
+    assert t["dec_n"] == int(np.prod(p.coeff_shape))
+    for k in ("dec_parse_ms", "dec_upload_ms", "dec_decode_ms"):
+        assert t[k] > 0, k
