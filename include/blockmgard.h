@@ -246,6 +246,19 @@ bm_status bm_decompose_quantize(bm_plan plan, const void* x, const double* block
 bm_status bm_dequantize_recompose(bm_plan plan, const int32_t* codes, const double* block_tol, void* x,
                                   hipStream_t stream);
 
+/* Keep the quantizer tables of one block tolerance map in the plan (Sec.
+ * IV-C: Eq. 2 propagation of the map to every block level, the per-block
+ * Delta classes of every level and tau_global).  Every quantizing call
+ * (bm_quantize_roi, bm_dequantize, bm_decompose_quantize,
+ * bm_dequantize_recompose, bm_compress) builds these tables from its map
+ * first, a few launches (about 20 us at 512^3); after this call, calls
+ * given the same block_tol pointer use the kept tables instead.  The map's
+ * contents must not change while it is kept (call again after changing
+ * them), and later calls on another stream must be ordered after this one.
+ * A call with another map builds its own tables over the kept ones and
+ * drops them; block_tol = NULL drops them.  Stream-ordered. */
+bm_status bm_quant_prepare(bm_plan plan, const double* block_tol, hipStream_t stream);
+
 /* ---- lossless stage (Sec. IV-B lossless stages) ----------------------- */
 
 /* Canonical Huffman coding of n int32 codes (device) in raster order.

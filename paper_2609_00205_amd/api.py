@@ -245,6 +245,14 @@ class Plan:
              C.byref(st) if check else None, _stream(stream))
         return codes
 
+    def quant_prepare(self, block_tol: Optional[torch.Tensor], stream=None) -> None:
+        """Keep the quantizer tables of block_tol in the plan (bm_quant_prepare):
+        later quantizing calls given this same tensor skip building them.  Its
+        contents must not change meanwhile; None drops the kept tables."""
+        if block_tol is not None:
+            _need(block_tol, torch.float64, self.block_grid, "block_tol")
+        call("bm_quant_prepare", self._h, _ptr(block_tol) if block_tol is not None else None, _stream(stream))
+
     def dequantize_recompose(self, codes: torch.Tensor, block_tol: torch.Tensor, out: Optional[torch.Tensor] = None,
                              stream=None) -> torch.Tensor:
         """Fused dequantize + recompose: equals recompose(dequantize(codes))."""

@@ -483,6 +483,14 @@ bm_status bm_dequantize_recompose(bm_plan p, const int32_t* codes, const double*
   });
 }
 
+bm_status bm_quant_prepare(bm_plan p, const double* block_tol, hipStream_t st) {
+  return guarded([&] {
+    need(p != nullptr, "null plan");
+    if (block_tol) check_device(p);
+    bm::quant_keep(*p, block_tol, st);
+  });
+}
+
 bm_status bm_huffman_encode(const int32_t* codes, int64_t n, void* out, size_t capacity, size_t* out_bytes,
                             hipStream_t st) {
   return guarded([&] {

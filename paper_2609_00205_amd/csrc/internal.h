@@ -132,6 +132,7 @@ struct Workspace {
   void* prep_dev = nullptr;      // quantizer preparation of this plan: field record + task prefixes (device)
   void* part = nullptr;          // double: per-block partial load vectors of the first global level (fused)
   std::vector<uint8_t> prep_key; // field record last uploaded
+  const double* kept_tol = nullptr;  // map whose tables are kept (bm_quant_prepare); null: none
 };
 
 }  // namespace bm
@@ -238,8 +239,11 @@ struct QPrep {
 constexpr int kCoarseSlotHost = 8;
 // where a plan's quantizer tables live (host arithmetic, no launches)
 QPrep qprep_layout(bm_plan_s& p, const double* block_tol);
-// builds the tables on the device (stream-ordered) and returns their layout
+// builds the tables on the device (stream-ordered) and returns their layout;
+// with the kept map (quant_keep) only the overflow flag is cleared
 QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st);
+// builds the tables of block_tol and keeps them (null: drops the kept ones)
+void quant_keep(bm_plan_s& p, const double* block_tol, hipStream_t st);
 
 // The same preparation for many fields at once: one field's inputs...
 struct PrepField {

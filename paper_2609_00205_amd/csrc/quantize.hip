@@ -515,8 +515,20 @@ QPrep qprep_layout(bm_plan_s& p, const double* block_tol) {
 // launch per propagation step, one per table level, one for tau_global and
 // the scalar Deltas (which also clears the overflow flag).  The field record
 // is uploaded only when it changes (a new tolerance map pointer).
+namespace {
+__global__ void k_clear_flag(int64_t* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+}  // namespace
+
 QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   const QPrep a = qprep_layout(p, block_tol);
+  if (block_tol && block_tol == p.ws.kept_tol) {   // the kept tables are this map's
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, a.flag);
+    BM_HIP(hipGetLastError());
+    return a;
+  }
+  p.ws.kept_tol = nullptr;   // the tables built here replace the kept ones
   const PrepField f = prep_field(p, block_tol, a);
   constexpr size_t kFirst = 2048;                   // offset of the task prefix arrays
   static_assert(sizeof(PrepField) <= kFirst, "field record too large");
@@ -552,6 +564,13 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
   }
   launch_prep_batch(g, static_cast<const PrepField*>(p.ws.prep_dev), 1, st);
   return a;
+}
+
+void quant_keep(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+  p.ws.kept_tol = nullptr;
+  if (!block_tol) return;
+  quant_prepare(p, block_tol, st);
+  p.ws.kept_tol = block_tol;
 }
 
 // ---- many fields per launch -------------------------------------------------
