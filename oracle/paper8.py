@@ -210,3 +210,101 @@ def node_delta(shape: Sequence[int], L: int, tau1: np.ndarray, eta: float) -> np
     src = [np.arange(n) // MC for n in last]          # block of the last level each value came from
     parts.append((taus[L - 1][np.ix_(*src)] * kc).ravel())
     return np.concatenate(parts)
+
+
+# --------------------------------------------------------------------------
+# The paper's hybrid with this block form (Sec. IV-B, IV-C; Sec. V-D's
+# default L = 1, M = 2): L block levels, then M global levels on the
+# assembled coarsest grid
+# --------------------------------------------------------------------------
+#
+# Readings: the coarsest values of the block levels (dims 5 nb_L per axis,
+# side by side in block order) are the grid the global levels work on, with
+# the node index as coordinate (the block levels' own coordinates are block
+# local); each global level is one MGARD level with natural ends on the whole
+# grid (Sec. II-B), whose axes are extended by clamp to the smallest length
+# on which the M levels halve an odd length (the padding rule of the shared-
+# face form).  Coefficients: the block levels' arrays, then the global
+# levels' in-place array of that extended grid.  Quantization: shares over
+# the L block levels, the M global levels (their details split equally) and
+# the coarsest values, proportional to counts, floored at 1/(64 T) with
+# T = L+M+1 and renormalised; block-level details keep their blocks' taus,
+# every global coefficient takes tau_global = the smallest last-level block
+# tau (Sec. IV-C), global details with the natural level's gain.  Errors of
+# the assembled grid reach the fine nodes through the block levels'
+# interpolation only (gain 1), so every node keeps its bound.
+
+
+def global_hierarchy(shape: Sequence[int], L: int, M: int) -> mgard.Hierarchy:
+    """The M global levels on the assembled coarsest grid of L block levels."""
+    _, last = level_dims(shape, L)
+    return mgard.hierarchy(last, 0, 0, M)
+
+
+def hybrid_coeff_size(shape: Sequence[int], L: int, M: int) -> int:
+    dims, _ = level_dims(shape, L)
+    return int(sum(np.prod(d) for d in dims) + np.prod(global_hierarchy(shape, L, M).shape_p))
+
+
+def decompose_hybrid(x: np.ndarray, L: int, M: int) -> np.ndarray:
+    """Block levels, then global levels on their coarsest values (flat, FP64)."""
+    if M == 0:
+        return decompose(x, L)
+    dims, last = level_dims(np.shape(x), L)
+    c = decompose(x, L)
+    off = int(sum(np.prod(d) for d in dims))
+    g = mgard.decompose(c[off:].reshape(last), 0, 0, M)
+    return np.concatenate([c[:off], g.ravel()])
+
+
+def recompose_hybrid(coeff: np.ndarray, shape: Sequence[int], L: int, M: int) -> np.ndarray:
+    """Inverse of :func:`decompose_hybrid`, cropped to ``shape``."""
+    if M == 0:
+        return recompose(coeff, shape, L)
+    dims, last = level_dims(shape, L)
+    h = global_hierarchy(shape, L, M)
+    coeff = np.asarray(coeff, np.float64)
+    if coeff.size != hybrid_coeff_size(shape, L, M):
+        raise ValueError("coefficient array has the wrong size")
+    off = int(sum(np.prod(d) for d in dims))
+    g = mgard.recompose(coeff[off:].reshape(h.shape_p), last, 0, 0, M)
+    return recompose(np.concatenate([coeff[:off], g.ravel()]), shape, L)
+
+
+def hybrid_weights(shape: Sequence[int], L: int, M: int) -> List[float]:
+    """Shares of the L block levels, the M global levels and the coarsest values."""
+    if M == 0:
+        return weights(shape, L)
+    dims, _ = level_dims(shape, L)
+    h = global_hierarchy(shape, L, M)
+    sizes = [float(np.prod([len(p) for p in pos])) for pos in h.pos]
+    N = float(sum(np.prod(d) for d in dims)) + sizes[0]
+    w = [float(np.prod(d)) * (B ** 3 - MC ** 3) / B ** 3 / N for d in dims]
+    w += [((sizes[0] - sizes[M]) / N) / float(M)] * M
+    w.append(sizes[M] / N)
+    floor = 1.0 / (64.0 * float(L + M + 1))
+    w = [v if v > floor else floor for v in w]
+    total = 0.0
+    for v in w:
+        total += v
+    return [v / total for v in w]
+
+
+def hybrid_node_delta(shape: Sequence[int], L: int, M: int, tau1: np.ndarray, eta: float) -> np.ndarray:
+    """Bin width Delta of every coefficient (flat layout of :func:`decompose_hybrid`)."""
+    if M == 0:
+        return node_delta(shape, L, tau1, eta)
+    dims, _ = level_dims(shape, L)
+    taus = level_tolerances(tau1, shape, L)
+    A = gain()
+    w = hybrid_weights(shape, L, M)
+    parts = []
+    for s in range(L):
+        parts.append((np.kron(taus[s], np.ones((B, B, B))) * roi.kappa(w[s], A, eta)).ravel())
+    tg = float(taus[L - 1].min())
+    h = global_hierarchy(shape, L, M)
+    gains = roi.level_gains(h)
+    lev = mgard.node_level(h.shape_p, 0, M)
+    k = [roi.kappa(w[L + s], gains[s], eta) for s in range(M)] + [(2.0 * (1.0 - eta)) * w[L + M]]
+    parts.append((tg * np.asarray(k)[lev - 1]).ravel())
+    return np.concatenate(parts)

@@ -149,3 +149,78 @@ def test_bound_holds(shape, L, seed):
     q = np.rint(c * (1.0 / delta))
     xr = paper8.recompose(q * delta, shape, L)
     assert np.all(np.abs(xr - x) <= vt)
+
+
+# ---- the hybrid: block levels, then global levels on the assembled grid ----
+
+HYBRID = [((20, 30, 17), 1, 1), ((20, 30, 17), 1, 2), ((40, 24, 33), 2, 1), ((16, 16, 16), 1, 2)]
+
+
+@pytest.mark.parametrize("shape,L,M", HYBRID)
+def test_hybrid_reconstruction(shape, L, M, rng):
+    x = rng.standard_normal(shape)
+    c = paper8.decompose_hybrid(x, L, M)
+    assert c.size == paper8.hybrid_coeff_size(shape, L, M)
+    assert np.abs(paper8.recompose_hybrid(c, shape, L, M) - x).max() < 1e-12
+
+
+def test_hybrid_without_global_levels_is_the_block_form(rng):
+    x = rng.standard_normal((20, 30, 17))
+    assert np.array_equal(paper8.decompose_hybrid(x, 2, 0), paper8.decompose(x, 2))
+    assert paper8.hybrid_weights((20, 30, 17), 2, 0) == paper8.weights((20, 30, 17), 2)
+
+
+@pytest.mark.parametrize("shape,L,M", [((16, 24, 40), 1, 1), ((24, 16, 32), 1, 2), ((64, 64, 64), 2, 1)])
+def test_hybrid_constant_field(shape, L, M):
+    """A constant field on grids the blocks tile without zero fill at every
+    level: every detail (block and global) is zero; the global levels'
+    coarsest values are the constant and nothing else is non-zero in the
+    global array but them (one per node of the coarsest grid)."""
+    x = np.full(shape, 3.25)
+    c = paper8.decompose_hybrid(x, L, M)
+    dims, last = paper8.level_dims(shape, L)
+    off = int(sum(np.prod(d) for d in dims))
+    assert np.abs(c[:off]).max() < 1e-12
+    tail = c[off:]
+    n = list(paper8.global_hierarchy(shape, L, M).shape_p)
+    for _ in range(M):
+        n = [(v + 1) // 2 if v > 2 else v for v in n]
+    nz = np.abs(tail) > 1e-12
+    assert int(nz.sum()) == int(np.prod(n))
+    assert np.abs(tail[nz] - 3.25).max() < 1e-12
+
+
+def test_hybrid_shares_by_hand():
+    """512^3, L = 1, M = 2 (the paper's default split): block details
+    64^3 blocks x 387 nodes, the assembled 320^3 grid extended to 321^3,
+    global details 321^3 - 81^3 split over two levels, coarsest 81^3, whose
+    share 81^3 / N = 0.0032 is raised to the floor 1 / (64 * 4)."""
+    w = paper8.hybrid_weights((512, 512, 512), 1, 2)
+    N = 512.0 ** 3 + 321.0 ** 3
+    ref = [64.0 ** 3 * 387 / N, (321.0 ** 3 - 81.0 ** 3) / N / 2, (321.0 ** 3 - 81.0 ** 3) / N / 2, 1.0 / 256]
+    assert 81.0 ** 3 / N < 1.0 / 256 < min(ref[:3])
+    ref = [v / sum(ref) for v in ref]
+    assert np.allclose(w, ref, rtol=1e-14, atol=0)
+    assert paper8.global_hierarchy((512, 512, 512), 1, 2).shape_p == (321, 321, 321)
+
+
+@pytest.mark.parametrize("shape,L,M,seed", [((16, 16, 16), 1, 1, 0), ((20, 30, 17), 1, 2, 1), ((40, 24, 33), 2, 1, 2),
+                                            ((33, 40, 40), 1, 2, 3)])
+def test_hybrid_bound_holds(shape, L, M, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(shape)
+    vt = np.full(shape, 1e-2)
+    z0, y0, x0 = [int(rng.integers(0, max(1, s - 6))) for s in shape]
+    vt[z0:z0 + 6, y0:y0 + 6, x0:x0 + 6] = 1e-5
+    tau1 = paper8.block_tolerance(vt, L)
+    delta = paper8.hybrid_node_delta(shape, L, M, tau1, 0.0)
+    c = paper8.decompose_hybrid(x, L, M)
+    q = np.rint(c * (1.0 / delta))
+    xr = paper8.recompose_hybrid(q * delta, shape, L, M)
+    assert np.all(np.abs(xr - x) <= vt)
+    # global coefficients all take tau_global, the strictest block's tau
+    dims, _ = paper8.level_dims(shape, L)
+    off = int(sum(np.prod(d) for d in dims))
+    taus = paper8.level_tolerances(tau1, shape, L)
+    assert taus[-1].min() == pytest.approx(1e-5)
+    assert np.all(delta[off:] <= 2 * 1e-5)
