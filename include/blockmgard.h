@@ -525,6 +525,22 @@ bm_status bm_select_levels(const bm_config* in, const bm_model* model, double bu
  * [1, 8], null), BM_ENOMEM, BM_EHIP. */
 typedef struct bm_p8_s* bm_p8;
 bm_status bm_p8_create(const int64_t dims[3], int dtype, int L, bm_p8* out);
+
+/* The paper's hybrid with this block form (Sec. IV-B, IV-C; the L = 1,
+ * M = 2 default of Sec. V-D): the L block levels, then M global levels
+ * (Sec. II-B, natural ends, node index as coordinate) on their assembled
+ * coarsest values (dims 5 n_L / 8), extended by clamp per axis to the
+ * smallest length on which the M levels halve an odd length.  Coefficients:
+ * the level arrays as above, then the global levels' in-place array of that
+ * extended grid (bm_p8_coeff_size counts it).  Quantization: the shares of
+ * the L block levels, the M global levels (their details split equally) and
+ * the coarsest values, proportional to counts, floored at 1/(64 (L+M+1));
+ * block details as above, every global coefficient at tau_global (the
+ * smallest last-level block tau, Sec. IV-C) with the natural level's gain.
+ * Every other bm_p8_* call takes such a plan; M = 0 is bm_p8_create.
+ * Errors as bm_p8_create; M outside [0, 16], or a global axis the line
+ * solver does not take: BM_EINVAL / BM_EUNSUPPORTED. */
+bm_status bm_p8_create_hybrid(const int64_t dims[3], int dtype, int L, int M, bm_p8* out);
 bm_status bm_p8_destroy(bm_p8 plan);
 bm_status bm_p8_coeff_size(bm_p8 plan, int64_t* elems);
 bm_status bm_p8_decompose(bm_p8 plan, const void* x_dev, void* coeff_dev, hipStream_t stream);
@@ -564,7 +580,8 @@ bm_status bm_p8_dequantize_recompose(bm_p8 plan, const int32_t* codes_dev, const
                                      void* x_dev, hipStream_t stream);
 
 /* Container of this form (host buffer, the layout of bm_compress): the
- * header with flags bit 1 set (block = 8, M = 0, pad_mode = 1), the level-1
+ * header with flags bit 1 set (block = 8, M = the plan's global levels,
+ * pad_mode = 1), the level-1
  * block map, then the Huffman stream of the fused codes; raw data when a
  * code does not fit in 32 bits or coding does not pay.  Capacity and size
  * query as bm_compress; bm_decompress and bm_compressed_config read it.

@@ -77,6 +77,7 @@ _SIGS = {
     "bm_huffman_decode": [P, C.c_size_t, P, C.c_int64, P],
     "bm_lossless_last_times": [C.POINTER(BMLosslessTimes)],
     "bm_quant_prepare": [P, P, P],
+    "bm_p8_create_hybrid": [C.POINTER(C.c_int64), C.c_int, C.c_int, C.c_int, C.POINTER(P)],
     "bm_huffman_plan": [P, C.c_int64, C.POINTER(P), C.POINTER(C.c_size_t), P],
     "bm_huffman_write": [P, P, C.c_size_t, C.POINTER(C.c_size_t)],
     "bm_huffman_destroy": [P],

@@ -496,18 +496,20 @@ def select_levels(shape, budget_ms: float, model: dict):
 
 class Paper8Plan:
     """The paper's own block form: disjoint 8^3 blocks, L block levels whose
-    5^3 coarse outputs are re-assembled into the next level's blocks.
-    Coefficients are one flat array (see ``bm_p8_create``)."""
+    5^3 coarse outputs are re-assembled into the next level's blocks, then M
+    global levels on the assembled coarsest grid (the paper's hybrid; M = 0:
+    block levels only).  Coefficients are one flat array (see
+    ``bm_p8_create`` and ``bm_p8_create_hybrid``)."""
 
-    def __init__(self, shape: Sequence[int], dtype=torch.float32, L: int = 1, device=None):
+    def __init__(self, shape: Sequence[int], dtype=torch.float32, L: int = 1, M: int = 0, device=None):
         shape = tuple(int(s) for s in shape)
         if len(shape) != 3:
             raise ValueError("3D shapes only")
-        self.shape, self.dtype, self.L = shape, dtype, int(L)
+        self.shape, self.dtype, self.L, self.M = shape, dtype, int(L), int(M)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            call("bm_p8_create", (C.c_int64 * 3)(*shape), _DT[dtype], self.L, C.byref(h))
+            call("bm_p8_create_hybrid", (C.c_int64 * 3)(*shape), _DT[dtype], self.L, self.M, C.byref(h))
         self._h = h
         n = C.c_int64(0)
         call("bm_p8_coeff_size", h, C.byref(n))

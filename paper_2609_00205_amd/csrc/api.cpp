@@ -326,7 +326,7 @@ bool write_container_p8(bm_p8_s& p, const void* x, const double* block_tol, doub
   h.dtype = dtype;
   h.block = 8;
   h.L = L;
-  h.M = 0;
+  h.M = p8_global_levels(p);
   h.pad_mode = 1;
   h.ndim = 3;
   for (int a = 0; a < 3; ++a) h.dims[a] = dims[a];
@@ -686,6 +686,14 @@ bm_status bm_p8_create(const int64_t dims[3], int dtype, int L, bm_p8* out) {
   });
 }
 
+bm_status bm_p8_create_hybrid(const int64_t dims[3], int dtype, int L, int M, bm_p8* out) {
+  return guarded([&] {
+    need(dims && out, "null argument");
+    *out = nullptr;
+    *out = bm::p8_create(dims, dtype, L, M);
+  });
+}
+
 bm_status bm_p8_destroy(bm_p8 p) {
   return guarded([&] { bm::p8_free(p); });
 }
@@ -876,7 +884,7 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
       check_stored_tol(static_cast<const uint8_t*>(in) + sizeof(CHeader), h.ntol);
     }
     if (h.flags & bm::kFlagP8) {
-      bm_p8_s* q = bm::p8_create(h.dims, h.dtype, h.L);
+      bm_p8_s* q = bm::p8_create(h.dims, h.dtype, h.L, h.M);
       struct Guard8 {
         bm_p8_s* q;
         double* d = nullptr;

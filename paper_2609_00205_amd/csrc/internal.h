@@ -170,6 +170,10 @@ struct bm_plan_s {
   // that level never crosses a block face (b = 9, 17 with M >= 1)
   bool fuse_next = false;
   std::shared_ptr<bm::PendingContainer> pending;   // dropped by every compress call on the plan
+  // budget shares (levels 1..L+M, coarsest) set by an owner that spreads one
+  // budget over more levels than the plan's (the 8^3 form's hybrid); empty:
+  // the plan's own rule
+  std::vector<double> w_override;
 };
 
 namespace bm {
@@ -336,7 +340,9 @@ void write_pending(PendingContainer& c, void* out);
 // pipeline both ways (graph: capture once per binding, then replay), and the
 // fields whose codes overflowed int32 (synchronizes)
 // the paper's own 8^3 block form (paper8.hip)
-bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L);
+// M > 0: the paper's hybrid, M global levels on the assembled coarsest grid
+bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L, int M = 0);
+int p8_global_levels(const bm_p8_s& p);
 void p8_free(bm_p8_s* p);
 int64_t p8_coeff_size(const bm_p8_s& p);
 void p8_decompose(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st);

@@ -374,6 +374,20 @@ __global__ __launch_bounds__(256) void k_p8_quantize(const T* c, uint32_t n, QAr
   }
 }
 
+// the smallest of n taus (one workgroup): tau_global of the hybrid
+__global__ __launch_bounds__(256) void k_p8_min(const double* t, int64_t n, double* out) {
+  __shared__ double m[256];
+  double v = INFINITY;
+  for (int64_t i = threadIdx.x; i < n; i += 256) v = fmin(v, t[i]);
+  m[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) m[threadIdx.x] = fmin(m[threadIdx.x], m[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = m[0];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_p8_dequantize(const int32_t* q, uint32_t n, QArgs8 a, T* c) {
   for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
@@ -398,7 +412,15 @@ struct bm_p8_s {
   std::vector<double*> tau;                // tau[s] (s = 1..L-1): propagated block tolerances
   int64_t* flag = nullptr;                 // quantizer overflow flag
   int32_t* codes = nullptr;                // codes of the compress path (allocated on first use)
+  // the hybrid (M > 0): global levels on the assembled coarsest grid
+  int M = 0;
+  bm_plan_s* glob = nullptr;               // global-only plan over the coarsest grid (dims last)
+  void* gin = nullptr;                     // the coarsest grid between the block and global levels
+  double* tg = nullptr;                    // tau_global: the smallest last-level block tau (one value)
 };
+
+bm_plan_s* bm_plan_build(const bm_config* c);
+void bm_plan_free(bm_plan_s* p);
 
 namespace bm {
 
@@ -463,7 +485,11 @@ void p8_decompose_t(const bm_p8_s& p, const void* x, void* coeff, int32_t* codes
       a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : nullptr;
     } else {
       a.coeff = c + p.off[s];
-      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : c + p.off[p.L];
+      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : (p.M ? static_cast<T*>(p.gin) : c + p.off[p.L]);
+    }
+    if (Q && p.M && s == p.L - 1) {   // hybrid: the coarsest values go to the global levels
+      a.last = 0;
+      a.cdst = static_cast<T*>(p.gin);
     }
     hipLaunchKernelGGL((p8::k_p8_decompose<T, Q>), dim3(unsigned(8 * a.per)), dim3(p8::NT), 0, st, a);
     BM_HIP(hipGetLastError());
@@ -491,7 +517,12 @@ void p8_recompose_t(const bm_p8_s& p, const void* coeff, void* x, const int32_t*
       a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : nullptr;
     } else {
       a.src = c + p.off[s];
-      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1]) : const_cast<T*>(c) + p.off[p.L];
+      a.cdst = s + 1 < p.L ? static_cast<T*>(p.grid[s + 1])
+                           : (p.M ? static_cast<T*>(p.gin) : const_cast<T*>(c) + p.off[p.L]);
+    }
+    if (Q && p.M && s == p.L - 1) {   // hybrid: the coarsest values come from the global levels
+      a.last = 0;
+      a.cdst = static_cast<T*>(p.gin);
     }
     if (s == 0) {
       a.out = static_cast<T*>(x);
@@ -513,9 +544,10 @@ void p8_recompose_t(const bm_p8_s& p, const void* coeff, void* x, const int32_t*
 
 }  // namespace
 
-bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L) {
+bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L, int M) {
   if (dtype != BM_F32 && dtype != BM_F64) fail(BM_EINVAL, "dtype must be BM_F32 or BM_F64");
   if (L < 1 || L > 8) fail(BM_EINVAL, "L must lie in [1, 8]");
+  if (M < 0 || M > 16) fail(BM_EINVAL, "M must lie in [0, 16]");
   for (int k = 0; k < 3; ++k)
     if (dims[k] < 1 || dims[k] > (int64_t(1) << 31)) fail(BM_EINVAL, "dims must lie in [1, 2^31]");
   if (up8(dims[1]) * up8(dims[2]) > (int64_t(1) << 40) / up8(dims[0]))
@@ -550,17 +582,39 @@ bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L) {
       BM_HIP(hipMalloc(&p->tau[s], size_t(p->n[s][0] / 8) * (p->n[s][1] / 8) * (p->n[s][2] / 8) * sizeof(double)));
     }
     BM_HIP(hipMalloc(&p->flag, sizeof(int64_t)));
+    if (M > 0) {
+      // the global levels: a plan of their own over the coarsest grid (clamp
+      // extension to the lengths they halve, natural ends)
+      bm_config c{};
+      c.ndim = 3;
+      for (int k = 0; k < 3; ++k) c.dims[k] = p->last[k];
+      c.dtype = dtype;
+      c.block = 0;
+      c.L = 0;
+      c.M = M;
+      c.pad_mode = 0;
+      c.eta = 0.0;
+      c.nested = 0;
+      p->glob = bm_plan_build(&c);
+      p->M = M;
+      BM_HIP(hipMalloc(&p->gin, size_t(p->last[0] * p->last[1] * p->last[2]) * p->esize));
+      BM_HIP(hipMalloc(&p->tg, sizeof(double)));
+    }
   } catch (...) {
     for (void* g : p->grid)
       if (g) (void)hipFree(g);
     for (double* t : p->tau)
       if (t) (void)hipFree(t);
     if (p->flag) (void)hipFree(p->flag);
+    if (p->glob) bm_plan_free(p->glob);
+    if (p->gin) (void)hipFree(p->gin);
     delete p;
     throw;
   }
   return p;
 }
+
+int p8_global_levels(const bm_p8_s& p) { return p.M; }
 
 void p8_free(bm_p8_s* p) {
   if (!p) return;
@@ -570,6 +624,9 @@ void p8_free(bm_p8_s* p) {
     if (t) (void)hipFree(t);
   if (p->flag) (void)hipFree(p->flag);
   if (p->codes) (void)hipFree(p->codes);
+  if (p->glob) bm_plan_free(p->glob);
+  if (p->gin) (void)hipFree(p->gin);
+  if (p->tg) (void)hipFree(p->tg);
   delete p;
 }
 
@@ -664,16 +721,30 @@ static double p8_gain() {
 // Budget shares of the levels' details and of the coarsest values:
 // proportional to their counts, floored at 1/(64 (L+1)), renormalised
 // (summed in order).
+// The hybrid: L block levels, then the M global levels (their details split
+// equally) and the coarsest values of the global plan, floored at
+// 1/(64 (L+M+1)).
 static std::vector<double> p8_weights(const bm_p8_s& p) {
   int64_t tot = 0;
   for (int s = 0; s < p.L; ++s) tot += p.n[s][0] * p.n[s][1] * p.n[s][2];
   const int64_t nlast = p.last[0] * p.last[1] * p.last[2];
-  tot += nlast;
-  const double N = double(tot);
   std::vector<double> w;
-  for (int s = 0; s < p.L; ++s) w.push_back(double(p.n[s][0] * p.n[s][1] * p.n[s][2]) * (512 - 125) / 512 / N);
-  w.push_back(double(nlast) / N);
-  const double floor = 1.0 / (64.0 * double(p.L + 1));
+  if (p.M == 0) {
+    tot += nlast;
+    const double N = double(tot);
+    for (int s = 0; s < p.L; ++s) w.push_back(double(p.n[s][0] * p.n[s][1] * p.n[s][2]) * (512 - 125) / 512 / N);
+    w.push_back(double(nlast) / N);
+  } else {
+    const bm_plan_s& g = *p.glob;
+    const int64_t gsize = g.pdims[0] * g.pdims[1] * g.pdims[2];
+    const Level& lc = g.lv[g.nlev - 1];
+    const int64_t ncoarse = lc.m[0] * lc.m[1] * lc.m[2];
+    const double N = double(tot + gsize);
+    for (int s = 0; s < p.L; ++s) w.push_back(double(p.n[s][0] * p.n[s][1] * p.n[s][2]) * (512 - 125) / 512 / N);
+    for (int s = 0; s < p.M; ++s) w.push_back((double(gsize - ncoarse) / N) / double(p.M));
+    w.push_back(double(ncoarse) / N);
+  }
+  const double floor = 1.0 / (64.0 * double(p.L + p.M + 1));
   double sum = 0.0;
   for (double& v : w) {
     v = v > floor ? v : floor;
@@ -715,14 +786,27 @@ static p8::QArgs8 p8_qargs(const bm_p8_s& p, const double* block_tol, double eta
   q.uf[p.L] = Unflat32(p.last[1], p.last[2]);
   q.k[p.L] = (2.0 * (1.0 - eta)) * w[p.L];
   q.flag = p.flag;
+  if (p.M) {
+    // the global levels quantize at tau_global (the smallest last-level
+    // block tau, Sec. IV-C) with this budget's shares of them
+    const auto& nl = p.n[p.L - 1];
+    hipLaunchKernelGGL(p8::k_p8_min, dim3(1), dim3(256), 0, st, tau[p.L - 1], (nl[0] / 8) * (nl[1] / 8) * (nl[2] / 8),
+                       p.tg);
+    BM_HIP(hipGetLastError());
+    p.glob->cfg.eta = eta;
+    p.glob->w_override.assign(w.begin() + p.L, w.end());
+  }
   return q;
 }
+
+// coefficient offset (bytes) of the global levels' array of the hybrid
+static size_t p8_goff(const bm_p8_s& p) { return size_t(p.off[p.L]) * p.esize; }
 
 void p8_quantize(const bm_p8_s& p, const void* coeff, const double* block_tol, double eta, int32_t* codes,
                  hipStream_t st) {
   const p8::QArgs8 q = p8_qargs(p, block_tol, eta, st);
   BM_HIP(hipMemsetAsync(p.flag, 0, sizeof(int64_t), st));
-  const uint32_t n = uint32_t(p8_coeff_size(p));
+  const uint32_t n = uint32_t(p.M ? p.off[p.L] : p8_coeff_size(p));
   const unsigned g = unsigned(std::min<int64_t>(65536, (int64_t(n) + 255) / 256));
   if (p.dtype == BM_F32)
     hipLaunchKernelGGL(p8::k_p8_quantize<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(coeff), n, q,
@@ -735,12 +819,16 @@ void p8_quantize(const bm_p8_s& p, const void* coeff, const double* block_tol, d
   BM_HIP(hipMemcpyAsync(&f, p.flag, sizeof(f), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
   check_code_flag(f, "tolerance too small for the data");
+  if (p.M) {
+    bm_qstats qs;
+    quantize(*p.glob, static_cast<const uint8_t*>(coeff) + p8_goff(p), p.tg, codes + p.off[p.L], &qs, st);
+  }
 }
 
 void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* coeff,
                    hipStream_t st) {
   const p8::QArgs8 q = p8_qargs(p, block_tol, eta, st);
-  const uint32_t n = uint32_t(p8_coeff_size(p));
+  const uint32_t n = uint32_t(p.M ? p.off[p.L] : p8_coeff_size(p));
   const unsigned g = unsigned(std::min<int64_t>(65536, (int64_t(n) + 255) / 256));
   if (p.dtype == BM_F32)
     hipLaunchKernelGGL(p8::k_p8_dequantize<float>, dim3(g), dim3(256), 0, st, codes, n, q, static_cast<float*>(coeff));
@@ -748,9 +836,13 @@ void p8_dequantize(const bm_p8_s& p, const int32_t* codes, const double* block_t
     hipLaunchKernelGGL(p8::k_p8_dequantize<double>, dim3(g), dim3(256), 0, st, codes, n, q,
                        static_cast<double*>(coeff));
   BM_HIP(hipGetLastError());
+  if (p.M) dequantize(*p.glob, codes + p.off[p.L], p.tg, static_cast<uint8_t*>(coeff) + p8_goff(p), st);
 }
 
-int64_t p8_coeff_size(const bm_p8_s& p) { return p.off[p.L] + p.last[0] * p.last[1] * p.last[2]; }
+int64_t p8_coeff_size(const bm_p8_s& p) {
+  if (p.M) return p.off[p.L] + p.glob->pdims[0] * p.glob->pdims[1] * p.glob->pdims[2];
+  return p.off[p.L] + p.last[0] * p.last[1] * p.last[2];
+}
 
 int p8_device(const bm_p8_s& p) { return p.device; }
 
@@ -759,9 +851,11 @@ void p8_decompose(const bm_p8_s& p, const void* x, void* coeff, hipStream_t st) 
     p8_decompose_t<float, false>(p, x, coeff, nullptr, nullptr, st);
   else
     p8_decompose_t<double, false>(p, x, coeff, nullptr, nullptr, st);
+  if (p.M) decompose(*p.glob, p.gin, static_cast<uint8_t*>(coeff) + p8_goff(p), st);
 }
 
 void p8_recompose(const bm_p8_s& p, const void* coeff, void* x, hipStream_t st) {
+  if (p.M) recompose(*p.glob, static_cast<const uint8_t*>(coeff) + p8_goff(p), p.gin, st);
   if (p.dtype == BM_F32)
     p8_recompose_t<float, false>(p, coeff, x, nullptr, nullptr, st);
   else
@@ -792,11 +886,16 @@ void p8_decompose_quantize(const bm_p8_s& p, const void* x, const double* block_
   BM_HIP(hipMemcpyAsync(&f, p.flag, sizeof(f), hipMemcpyDeviceToHost, st));
   BM_HIP(hipStreamSynchronize(st));
   check_code_flag(f, "tolerance too small for the data");
+  if (p.M) {
+    bm_qstats qs;
+    decompose_quantize(*p.glob, p.gin, p.tg, codes + p.off[p.L], &qs, st);
+  }
 }
 
 void p8_dequantize_recompose(const bm_p8_s& p, const int32_t* codes, const double* block_tol, double eta, void* x,
                              hipStream_t st) {
   const P8Quant z = p8_quant(p8_qargs(p, block_tol, eta, st));
+  if (p.M) dequantize_recompose(*p.glob, codes + p.off[p.L], p.tg, p.gin, st);
   if (p.dtype == BM_F32)
     p8_recompose_t<float, true>(p, nullptr, x, codes, &z, st);
   else

@@ -210,6 +210,7 @@ void thomas_pivots_natural(int64_t m, std::vector<double>& inv) {
 // that minimises the total code length).  Sec. IV-C: the M global levels
 // share their part equally.  The shares sum to 1.
 std::vector<double> level_weights(const bm_plan_s& p) {
+  if (p.w_override.size() == size_t(p.nlev + 1)) return p.w_override;
   auto prod = [](const int64_t* n) { return n[0] * n[1] * n[2]; };
   const double N = double(prod(p.pdims));
   std::vector<double> w(p.nlev + 1, 0.0);
