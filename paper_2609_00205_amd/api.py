@@ -522,7 +522,10 @@ class Paper8Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.lib().bm_p8_destroy(h)
+            try:
+                _lib.lib().bm_p8_destroy(h)
+            except Exception:   # interpreter shutdown: the library may be gone already
+                pass
             self._h = None
 
     def decompose(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

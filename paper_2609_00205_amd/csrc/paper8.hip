@@ -374,18 +374,36 @@ __global__ __launch_bounds__(256) void k_p8_quantize(const T* c, uint32_t n, QAr
   }
 }
 
-// the smallest of n taus (one workgroup): tau_global of the hybrid
+// The smallest of n taus: tau_global of the hybrid, written to out[0].  The
+// workgroups meet in one 64-bit integer atomicMin on out[1], which holds the
+// running minimum as an order-preserving key of the double's bits (a sign
+// flip of the magnitude bits of negatives makes signed-integer order equal
+// double order); k_p8_min_init sets it to the key of +inf and k_p8_min_done
+// turns it back into a double.  NaN taus are ignored, as fmin ignores them.
+__device__ inline long long min_key(double v) {
+  const long long b = __double_as_longlong(v);
+  return b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFll;
+}
+
+__global__ void k_p8_min_init(double* out) {
+  if (threadIdx.x == 0) reinterpret_cast<long long*>(out)[1] = min_key(INFINITY);
+}
+
 __global__ __launch_bounds__(256) void k_p8_min(const double* t, int64_t n, double* out) {
   __shared__ double m[256];
   double v = INFINITY;
-  for (int64_t i = threadIdx.x; i < n; i += 256) v = fmin(v, t[i]);
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) v = fmin(v, t[i]);
   m[threadIdx.x] = v;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (int(threadIdx.x) < o) m[threadIdx.x] = fmin(m[threadIdx.x], m[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = m[0];
+  if (threadIdx.x == 0) atomicMin(reinterpret_cast<long long*>(out) + 1, min_key(m[0]));
+}
+
+__global__ void k_p8_min_done(double* out) {
+  if (threadIdx.x == 0) out[0] = __longlong_as_double(min_key(__longlong_as_double(reinterpret_cast<long long*>(out)[1])));
 }
 
 template <typename T>
@@ -416,7 +434,7 @@ struct bm_p8_s {
   int M = 0;
   bm_plan_s* glob = nullptr;               // global-only plan over the coarsest grid (dims last)
   void* gin = nullptr;                     // the coarsest grid between the block and global levels
-  double* tg = nullptr;                    // tau_global: the smallest last-level block tau (one value)
+  double* tg = nullptr;                    // tau_global (the smallest last-level block tau), then its reduction key
 };
 
 bm_plan_s* bm_plan_build(const bm_config* c);
@@ -598,7 +616,7 @@ bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L, int M) {
       p->glob = bm_plan_build(&c);
       p->M = M;
       BM_HIP(hipMalloc(&p->gin, size_t(p->last[0] * p->last[1] * p->last[2]) * p->esize));
-      BM_HIP(hipMalloc(&p->tg, sizeof(double)));
+      BM_HIP(hipMalloc(&p->tg, 2 * sizeof(double)));
     }
   } catch (...) {
     for (void* g : p->grid)
@@ -790,8 +808,11 @@ static p8::QArgs8 p8_qargs(const bm_p8_s& p, const double* block_tol, double eta
     // the global levels quantize at tau_global (the smallest last-level
     // block tau, Sec. IV-C) with this budget's shares of them
     const auto& nl = p.n[p.L - 1];
-    hipLaunchKernelGGL(p8::k_p8_min, dim3(1), dim3(256), 0, st, tau[p.L - 1], (nl[0] / 8) * (nl[1] / 8) * (nl[2] / 8),
-                       p.tg);
+    const int64_t nbl = (nl[0] / 8) * (nl[1] / 8) * (nl[2] / 8);
+    hipLaunchKernelGGL(p8::k_p8_min_init, dim3(1), dim3(64), 0, st, p.tg);
+    hipLaunchKernelGGL(p8::k_p8_min, dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(1024, (nbl + 255) / 256)))),
+                       dim3(256), 0, st, tau[p.L - 1], nbl, p.tg);
+    hipLaunchKernelGGL(p8::k_p8_min_done, dim3(1), dim3(64), 0, st, p.tg);
     BM_HIP(hipGetLastError());
     p.glob->cfg.eta = eta;
     p.glob->w_override.assign(w.begin() + p.L, w.end());
