@@ -430,6 +430,9 @@ typedef struct {
   double ms;              /* fused decompose + quantize, median of the repetitions */
   double ratio;           /* raw bytes / container bytes at the given tolerances */
   int nested;             /* 1: the nested block schedule (bm_config.nested) */
+  double lossless_ms;     /* Huffman encode of its codes into host memory (histogram, code
+                             table, chunk sizes, encode, copy out), host wall time; 0 when
+                             the codes overflow */
 } bm_candidate;
 
 /* Chooses block size and level split for field x (device, logical dims and
@@ -446,17 +449,15 @@ bm_status bm_autotune(const bm_config* in, const void* x, const double* voxel_to
                       bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
 
 /* The same candidates and measurements, chosen by the rule of Algorithm 1
- * (Sec. IV-B) under a time budget: of the candidates whose fused decompose +
- * quantize time (median of reps) is at most budget_ms, the one with the
- * most global levels M, then the fewest block levels L, then the best ratio
- * (between block sizes).  budget_ms bounds the measured transform and
- * quantization only; the lossless stage is not timed per candidate (its cost
- * varies with the padded node count and the code histogram).
- * bm_select_levels applies the same rule to predicted times of all three
+ * (Sec. IV-B) under a time budget: of the candidates whose pipeline time
+ * ms + lossless_ms (fused decompose + quantize, then the Huffman encode of
+ * their codes) is at most budget_ms, the one with the most global levels M,
+ * then the fewest block levels L, then the best ratio (between block sizes).
+ * bm_select_levels applies the same rule to predicted times of the same
  * stages.
  * Errors: BM_ERANGE when no candidate fits (*out, the table and *ncands are
- * still filled, *out with the fastest candidate), BM_EINVAL (budget not
- * positive, no admissible candidate).  Synchronous. */
+ * still filled, *out with the candidate of the shortest pipeline time),
+ * BM_EINVAL (budget not positive, no admissible candidate).  Synchronous. */
 bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* voxel_tol, double budget_ms, int reps,
                              bm_config* out, bm_candidate* cands, int cap, int* ncands, hipStream_t stream);
 

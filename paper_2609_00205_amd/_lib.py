@@ -27,7 +27,7 @@ class BMQStats(C.Structure):
 
 class BMCandidate(C.Structure):
     _fields_ = [("block", C.c_int), ("L", C.c_int), ("M", C.c_int), ("status", C.c_int), ("ms", C.c_double),
-                ("ratio", C.c_double), ("nested", C.c_int)]
+                ("ratio", C.c_double), ("nested", C.c_int), ("lossless_ms", C.c_double)]
 
 
 class BMModel(C.Structure):

@@ -404,9 +404,10 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
     choice = {"block", "L", "M", "nested"}; candidates = the measured table.
 
     budget_ms: choose by the rule of Algorithm 1 instead (most global levels,
-    then fewest block levels, among the candidates whose fused decompose +
-    quantize time fits); choice["fits"] tells whether any did (if not, the
-    fastest candidate is returned)."""
+    then fewest block levels, among the candidates whose pipeline time, fused
+    decompose + quantize ("ms") plus the Huffman encode of their codes
+    ("lossless_ms"), fits); choice["fits"] tells whether any did (if not, the
+    candidate of the shortest pipeline time is returned)."""
     if x.dtype not in _DT:
         raise ValueError("x must be float32 or float64")
     _need(x, x.dtype, None, "x")
@@ -428,7 +429,8 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
             _lib.check(st)
         fits = st == 0
     cands = [{"block": table[i].block, "L": table[i].L, "M": table[i].M, "status": table[i].status,
-              "ms": table[i].ms, "ratio": table[i].ratio, "nested": bool(table[i].nested)}
+              "ms": table[i].ms, "ratio": table[i].ratio, "nested": bool(table[i].nested),
+              "lossless_ms": table[i].lossless_ms}
              for i in range(min(n.value, cap))]
     choice = {"block": out.block, "L": out.L, "M": out.M, "nested": bool(out.nested)}
     if fits is not None:

@@ -51,8 +51,9 @@ def test_autotune_rule_and_bounds(dt):
 
 def test_autotune_budget_rule():
     # Algorithm 1 (Sec. IV-B) on the measured table: among the candidates whose
-    # fused decompose + quantize time fits the budget, the most global levels,
-    # then the fewest block levels (ties between block sizes: best ratio)
+    # pipeline time (fused decompose + quantize, then the Huffman encode)
+    # fits the budget, the most global levels, then the fewest block levels
+    # (ties between block sizes: best ratio)
     from oracle import selector
     from paper_2609_00205_amd import autotune
     shape = (65, 65, 33)
@@ -62,9 +63,10 @@ def test_autotune_budget_rule():
     xd = torch.from_numpy(x).cuda()
     vtd = torch.from_numpy(vt).cuda()
     _, cands = autotune(xd, vtd, reps=2)
-    budget = float(np.median([c["ms"] for c in cands]))
+    assert all(c["lossless_ms"] > 0 for c in cands if c["status"] == 0)
+    budget = float(np.median([c["ms"] + c["lossless_ms"] for c in cands]))
     choice, cands = autotune(xd, vtd, reps=2, budget_ms=budget)
-    feasible = [c for c in cands if c["ms"] <= budget]
+    feasible = [c for c in cands if c["ms"] + c["lossless_ms"] <= budget]
     if not feasible:
         assert choice["fits"] is False
         return
@@ -74,11 +76,11 @@ def test_autotune_budget_rule():
     if win["L"] > 0:
         assert choice["block"] == win["block"]
     # the oracle's Algorithm 1 picks the same (L, M) from the same feasibility
-    times = {(c["L"], c["M"]): c["ms"] for c in feasible}
+    times = {(c["L"], c["M"]): c["ms"] + c["lossless_ms"] for c in feasible}
     pick = selector.select(sorted(times), lambda L, M: times[(L, M)], budget)
     assert pick == (choice["L"], choice["M"])
     # a budget nothing meets: the fastest candidate, flagged as not fitting
     choice2, cands2 = autotune(xd, vtd, reps=1, budget_ms=1e-6)
     assert choice2["fits"] is False
-    fastest = min(cands2, key=lambda c: c["ms"])
+    fastest = min(cands2, key=lambda c: c["ms"] + c["lossless_ms"])
     assert (choice2["L"], choice2["M"]) == (fastest["L"], fastest["M"])
