@@ -240,6 +240,46 @@ __global__ __launch_bounds__(NT) void k_pad(PadArgs<T> a) {
   }
 }
 
+// The extension of a padded grid whose logical region already sits at its
+// place in it (the padded strides): nodes past the logical extent take the
+// value of the nearest logical node, or zero.  The extension is walked as
+// three slabs (z past the end; then y past the end; then x past the end), so
+// only nodes outside the logical region are written and only nodes inside
+// it are read.
+template <typename T>
+struct PadExtArgs {
+  T* g;
+  int64_t sn[3], dn[3];   // logical and padded dims
+  Idx3 ez, ey, ex;        // the three slabs
+  int zero;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pad_extend(PadExtArgs<T> a) {
+  const int64_t nz = a.ez.n0 * a.ez.n1 * a.ez.n2, ny = a.ey.n0 * a.ey.n1 * a.ey.n2;
+  const int64_t tot = nz + ny + a.ex.n0 * a.ex.n1 * a.ex.n2;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < tot; i += int64_t(gridDim.x) * NT) {
+    int64_t z, y, x;
+    if (i < nz) {
+      unflat(i, a.ez, z, y, x);
+      z += a.sn[0];
+    } else if (i < nz + ny) {
+      unflat(i - nz, a.ey, z, y, x);
+      y += a.sn[1];
+    } else {
+      unflat(i - nz - ny, a.ex, z, y, x);
+      x += a.sn[2];
+    }
+    T v = T(0);
+    if (!a.zero) {
+      const int64_t cz = z < a.sn[0] ? z : a.sn[0] - 1, cy = y < a.sn[1] ? y : a.sn[1] - 1;
+      const int64_t cx = x < a.sn[2] ? x : a.sn[2] - 1;
+      v = a.g[(cz * a.dn[1] + cy) * a.dn[2] + cx];
+    }
+    a.g[(z * a.dn[1] + y) * a.dn[2] + x] = v;
+  }
+}
+
 inline unsigned grid_for(int64_t tot) {
   int64_t g = (tot + NT - 1) / NT;
   if (g > 65536) g = 65536;
@@ -706,6 +746,37 @@ void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t 
   BM_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_pad_extend(const bm_plan_s& p, void* g, bool zero, hipStream_t st) {
+  const int64_t* d = p.dims;
+  const int64_t* n = p.pdims;
+  // an axis that is not extended leaves its slab empty (no divisor of 0 on the host)
+  auto slab = [](int64_t a, int64_t b, int64_t c) { return a > 0 && b > 0 && c > 0 ? Idx3(a, b, c) : Idx3(0, 1, 1); };
+  PadExtArgs<T> a{static_cast<T*>(g), {d[0], d[1], d[2]}, {n[0], n[1], n[2]}, slab(n[0] - d[0], n[1], n[2]),
+                  slab(d[0], n[1] - d[1], n[2]), slab(d[0], d[1], n[2] - d[2]), zero ? 1 : 0};
+  const int64_t tot = n[0] * n[1] * n[2] - d[0] * d[1] * d[2];
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_pad_extend<T>, dim3(grid_for(tot)), dim3(NT), 0, st, a);
+  BM_HIP(hipGetLastError());
+}
+
+// The level-1 grid of a plan without block levels: the input padded into
+// the plan's grid, or, when the input is that grid already (its logical
+// region at the padded strides, as a caller inside the library leaves it),
+// only its extension filled in place.
+static void level1_input(const bm_plan_s& p, const void* x, hipStream_t st) {
+  const bool zero = p.cfg.pad_mode == 1;
+  if (x != p.ws.grid[0]) {
+    pad_input(p, x, p.ws.grid[0], zero, st);
+  } else if (p.cfg.dtype == BM_F32) {
+    launch_pad_extend<float>(p, p.ws.grid[0], zero, st);
+  } else {
+    launch_pad_extend<double>(p, p.ws.grid[0], zero, st);
+  }
+}
+
+void* level1_grid(const bm_plan_s& p) { return p.cfg.L == 0 ? p.ws.grid[0] : nullptr; }
+
 void pad_input(const bm_plan_s& p, const void* x, void* dst, bool zero, hipStream_t st) {
   const int64_t tot = p.pdims[0] * p.pdims[1] * p.pdims[2];
   if (p.cfg.dtype == BM_F32) {
@@ -790,7 +861,7 @@ void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st) {
     } else {
       const void* u;
       if (s == 1) {
-        pad_input(p, x, p.ws.grid[0], p.cfg.pad_mode == 1, st);
+        level1_input(p, x, st);
         u = p.ws.grid[0];
       } else {
         u = p.ws.grid[s - 1];
@@ -832,7 +903,7 @@ void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
       if (p.fuse_next && s == p.L + 1) continue;
       void* out = p.ws.grid[s - 1];
       global_interp_add(p, s, coeff, p.ws.grid[s], out, st);
-      if (s == 1) {
+      if (s == 1 && x != out) {   // (a caller that passed the plan's grid reads it in place)
         View3 src = dense_view(out, p.pdims);
         src.n[0] = p.dims[0];
         src.n[1] = p.dims[1];
@@ -853,7 +924,7 @@ void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, cons
     TimedScope ts(p, 2 * (s - 1), st);
     const void* u;
     if (s == 1) {
-      pad_input(p, x, p.ws.grid[0], p.cfg.pad_mode == 1, st);
+      level1_input(p, x, st);
       u = p.ws.grid[0];
     } else {
       u = p.ws.grid[s - 1];
@@ -920,7 +991,7 @@ void dequantize_recompose_global(bm_plan_s& p, const int32_t* codes, const QPrep
       launch_interp<float>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
     else
       launch_interp<double>(p, s, nullptr, codes, qdel, p.ws.grid[s], out, st);
-    if (s == 1) {
+    if (s == 1 && x != out) {   // (a caller that passed the plan's grid reads it in place)
       View3 src = dense_view(out, p.pdims);
       src.n[0] = p.dims[0];
       src.n[1] = p.dims[1];

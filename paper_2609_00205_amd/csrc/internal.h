@@ -212,6 +212,12 @@ void line_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64
 void strided_copy(size_t esize, const View3& src, const View3& dst, hipStream_t st);
 // logical input -> padded grid (clamp, or zero fill when zero is set)
 void pad_input(const bm_plan_s& p, const void* x, void* dst, bool zero, hipStream_t st);
+// The level-1 grid of a plan without block levels (padded dims, C order), or
+// null.  Passed as the input of decompose / decompose_quantize, its logical
+// region is taken in place (only the extension is filled); passed as the
+// output of recompose / dequantize_recompose, the result is left there at the
+// padded strides (no cropping copy).
+void* level1_grid(const bm_plan_s& p);
 
 // decompose / recompose drivers
 void decompose(bm_plan_s& p, const void* x, void* coeff, hipStream_t st);

@@ -433,7 +433,8 @@ struct bm_p8_s {
   // the hybrid (M > 0): global levels on the assembled coarsest grid
   int M = 0;
   bm_plan_s* glob = nullptr;               // global-only plan over the coarsest grid (dims last)
-  void* gin = nullptr;                     // the coarsest grid between the block and global levels
+  void* gin = nullptr;                     // the coarsest grid between the block and global levels (the
+                                           // global plan's padded level-1 grid, owned by that plan)
   double* tg = nullptr;                    // tau_global (the smallest last-level block tau), then its reduction key
 };
 
@@ -457,9 +458,16 @@ p8::Args<T> p8_args(const bm_p8_s& p, int s) {
   a.cs[0] = n[1] * n[2];
   a.cs[1] = n[2];
   a.cs[2] = 1;
-  // the coarse values' array: the next level's grid, or the coarsest values
-  const int64_t d1 = s + 1 < p.L ? p.n[s + 1][1] : p.last[1];
-  const int64_t d2 = s + 1 < p.L ? p.n[s + 1][2] : p.last[2];
+  // the coarse values' array: the next level's grid, the global levels'
+  // padded level-1 grid (the hybrid), or the coarsest values
+  int64_t d1 = p.last[1], d2 = p.last[2];
+  if (s + 1 < p.L) {
+    d1 = p.n[s + 1][1];
+    d2 = p.n[s + 1][2];
+  } else if (p.M) {
+    d1 = p.glob->pdims[1];
+    d2 = p.glob->pdims[2];
+  }
   a.ds[0] = d1 * d2;
   a.ds[1] = d2;
   a.ds[2] = 1;
@@ -615,7 +623,9 @@ bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L, int M) {
       c.nested = 0;
       p->glob = bm_plan_build(&c);
       p->M = M;
-      BM_HIP(hipMalloc(&p->gin, size_t(p->last[0] * p->last[1] * p->last[2]) * p->esize));
+      // the last block level writes its assembled values straight into the
+      // global plan's padded level-1 grid, and reads them back from there
+      p->gin = level1_grid(*p->glob);
       BM_HIP(hipMalloc(&p->tg, 2 * sizeof(double)));
     }
   } catch (...) {
@@ -625,7 +635,6 @@ bm_p8_s* p8_create(const int64_t dims[3], int dtype, int L, int M) {
       if (t) (void)hipFree(t);
     if (p->flag) (void)hipFree(p->flag);
     if (p->glob) bm_plan_free(p->glob);
-    if (p->gin) (void)hipFree(p->gin);
     delete p;
     throw;
   }
@@ -643,7 +652,6 @@ void p8_free(bm_p8_s* p) {
   if (p->flag) (void)hipFree(p->flag);
   if (p->codes) (void)hipFree(p->codes);
   if (p->glob) bm_plan_free(p->glob);
-  if (p->gin) (void)hipFree(p->gin);
   if (p->tg) (void)hipFree(p->tg);
   delete p;
 }
