@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libblockmga
 BM_F32, BM_F64 = 0, 1
 STATUS = {0: "BM_OK", -1: "BM_EINVAL", -2: "BM_ENOMEM", -3: "BM_EHIP", -4: "BM_ENONFINITE",
           -5: "BM_ECAPACITY", -6: "BM_ECORRUPT", -7: "BM_ERANGE", -8: "BM_EUNSUPPORTED"}
+BM_ECAPACITY = -5
 BM_ERANGE = -7
 
 

@@ -40,11 +40,26 @@ def _take(buf: bytearray, n: int) -> bytearray:
     return buf
 
 
+def _host_view(buf) -> memoryview:
+    """A byte memoryview of a host buffer: any bytes-like object, or a
+    contiguous uint8 CPU tensor (pinned ones included), without a copy."""
+    if isinstance(buf, torch.Tensor):
+        if buf.is_cuda or buf.dtype != torch.uint8 or not buf.is_contiguous() or buf.dim() != 1:
+            raise ValueError("a tensor buffer must be a contiguous 1-D uint8 host tensor")
+        buf = buf.numpy()
+    return memoryview(buf).cast("B")
+
+
+def _nbytes(buf) -> int:
+    return len(buf) if isinstance(buf, bytes) else _host_view(buf).nbytes
+
+
 def _readable(buf):
-    """A pointer argument for a bytes-like container (bytes, bytearray, memoryview)."""
+    """A pointer argument for a bytes-like container (bytes, bytearray,
+    memoryview, a uint8 host tensor)."""
     if isinstance(buf, bytes):
         return buf
-    mv = memoryview(buf)
+    mv = _host_view(buf)
     if mv.readonly:
         return bytes(mv)
     return (C.c_char * mv.nbytes).from_buffer(mv)
@@ -285,12 +300,33 @@ class Plan:
                           "quantize": calls[2 * nl], "dequantize": calls[2 * nl + 1]}}
 
     # -- end to end ----------------------------------------------------------
-    def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None) -> bytearray:
+    def compress(self, x: torch.Tensor, block_tol: torch.Tensor, stream=None, out=None):
+        """The container of x under block_tol (bm_compress_plan, then
+        bm_compress_write).  Returns a new bytearray of its exact size; or,
+        given ``out`` (a writable host buffer: bytearray, numpy array,
+        memoryview, or a contiguous 1-D uint8 CPU tensor, e.g. pinned and
+        reused, which takes the stream's copy at full PCIe rate), writes into
+        it and returns a memoryview of the bytes written.  An ``out`` too
+        small raises BMError (BM_ECAPACITY) with the size needed in
+        ``.needed`` (the plan stays pending, nothing is written)."""
         _need(x, self.dtype, self.shape, "x")
         _need(block_tol, torch.float64, self.block_grid, "block_tol")
         # planned once (bm_compress_plan), written into a buffer of its exact size
         need = C.c_size_t(0)
         call("bm_compress_plan", self._h, _ptr(x), _ptr(block_tol), C.byref(need), _stream(stream))
+        if out is not None:
+            mv = _host_view(out)
+            if mv.readonly:
+                raise ValueError("out must be writable")
+            if mv.nbytes < need.value:
+                err = _lib.BMError(_lib.BM_ECAPACITY, f"out holds {mv.nbytes} bytes, the container needs {need.value}")
+                err.needed = int(need.value)
+                raise err
+            got = C.c_size_t(0)
+            view = (C.c_char * mv.nbytes).from_buffer(mv)
+            call("bm_compress_write", self._h, view, mv.nbytes, C.byref(got))
+            del view
+            return mv[:got.value]
         buf = bytearray(need.value)
         got = C.c_size_t(0)
         view = _writable(buf)
@@ -301,7 +337,7 @@ class Plan:
 
 def compressed_config(buf) -> dict:
     cfg = BMConfig()
-    call("bm_compressed_config", _readable(buf), len(buf), C.byref(cfg))
+    call("bm_compressed_config", _readable(buf), _nbytes(buf), C.byref(cfg))
     return {"shape": tuple(cfg.dims), "dtype": _TD[cfg.dtype], "block": cfg.block, "L": cfg.L, "M": cfg.M,
             "pad_mode": cfg.pad_mode, "eta": cfg.eta, "nested": bool(cfg.nested)}
 
@@ -310,7 +346,7 @@ def decompress(buf, device=None, stream=None) -> torch.Tensor:
     info = compressed_config(buf)
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = torch.empty(info["shape"], dtype=info["dtype"], device=dev)
-    call("bm_decompress", _readable(buf), len(buf), _ptr(out), _stream(stream))
+    call("bm_decompress", _readable(buf), _nbytes(buf), _ptr(out), _stream(stream))
     return out
 
 
@@ -353,7 +389,7 @@ def huffman_encode_device(codes: torch.Tensor, out: torch.Tensor, stream=None) -
 def huffman_decode(buf, n: int, device=None, stream=None) -> torch.Tensor:
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = torch.empty(n, dtype=torch.int32, device=dev)
-    call("bm_huffman_decode", _readable(buf), len(buf), _ptr(out), n, _stream(stream))
+    call("bm_huffman_decode", _readable(buf), _nbytes(buf), _ptr(out), n, _stream(stream))
     return out
 
 

@@ -110,3 +110,35 @@ def test_stage_times_reported():
     assert t["dec_n"] == int(np.prod(p.coeff_shape))
     for k in ("dec_parse_ms", "dec_upload_ms", "dec_decode_ms"):
         assert t[k] > 0, k
+
+
+def test_compress_into_caller_buffers():
+    # Plan.compress(out=...): the bytes of the allocating form, written into a
+    # pinned uint8 tensor (then a bytearray, a numpy array); a short buffer
+    # raises BM_ECAPACITY with the size needed and writes nothing;
+    # decompress reads the returned view and the pinned tensor alike
+    import numpy as np
+    from paper_2609_00205_amd import Plan, _lib, api
+    shape = (40, 50, 61)
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=44, dtype=np.float32)).cuda()
+    sc = float(x.abs().max())
+    p = Plan(shape, dtype=torch.float32, block=9, L=1, M=2)
+    bt = p.tolmap_from_boxes([(2, 2, 2, 12, 12, 12, 1e-5 * sc)], 1e-2 * sc)
+    ref = bytes(p.compress(x, bt))
+    pin = torch.full((len(ref) + 64,), 0xAB, dtype=torch.uint8).pin_memory()
+    mv = p.compress(x, bt, out=pin)
+    assert mv.nbytes == len(ref) and bytes(mv) == ref
+    assert bytes(pin[len(ref):].numpy()) == b"\xab" * 64          # nothing past the container
+    short = bytearray(len(ref) - 1)
+    with pytest.raises(_lib.BMError) as e:
+        p.compress(x, bt, out=short)
+    assert e.value.code == -5 and e.value.needed == len(ref) and short == bytearray(len(ref) - 1)
+    arr = np.zeros(len(ref), np.uint8)
+    assert bytes(p.compress(x, bt, out=arr)) == ref
+    ba = bytearray(len(ref) + 5)
+    assert bytes(p.compress(x, bt, out=ba)) == ref
+    x_ref = api.decompress(ref)
+    assert torch.equal(api.decompress(mv), x_ref)
+    assert torch.equal(api.decompress(pin[:len(ref)]), x_ref)
+    with pytest.raises(ValueError):
+        p.compress(x, bt, out=bytes(len(ref)))                       # read-only

@@ -177,3 +177,24 @@ def test_code_lengths_match_oracle(lib, kind, hist):
     assert np.array_equal(got.astype(np.int64), ref)
     if kind == "pow2":
         assert int(ref.max()) == 32      # the cap is reached
+
+
+def test_host_buffers_of_every_kind_read_alike(lib):
+    # the binding reads a container from bytes, bytearray, a numpy array, a
+    # 1-D uint8 host tensor or a memoryview cut from a larger buffer, without
+    # a copy where the buffer is writable, and counts bytes, not items
+    import numpy as np
+    import torch
+
+    from paper_2609_00205_amd import api
+    buf = _container([1e-3, 2e-3])
+    big = bytearray(buf) + b"\xff" * 100
+    kinds = [buf, bytearray(buf), np.frombuffer(bytearray(buf), np.uint8), torch.tensor(list(buf), dtype=torch.uint8),
+             memoryview(big)[:len(buf)]]
+    for k in kinds:
+        assert api._nbytes(k) == len(buf)
+        info = api.compressed_config(k)
+        assert info["shape"] == (9, 9, 9) and info["block"] == 9 and info["L"] == 1 and info["M"] == 1
+    assert api._nbytes(np.zeros(4, np.float64)) == 32
+    with pytest.raises(ValueError):
+        api._host_view(torch.zeros(4, dtype=torch.int32))
