@@ -125,6 +125,19 @@ bm_status bm_plan_config(bm_plan plan, bm_config* cfg);
 /* Padded dims n' (the coefficient array's dims). */
 bm_status bm_coeff_shape(bm_plan plan, int64_t padded_dims[3]);
 
+/* Device memory the plan holds now, in bytes: the workspace built with it
+ * (the compact grids of every level after the first, the global levels'
+ * pass temporaries, the first global level's partial load vectors, the
+ * tolerance maps and quantizer tables, the Thomas pivots) plus buffers that
+ * calls add on first use and keep until bm_plan_destroy: the padded code
+ * array of bm_compress / bm_compress_plan / bm_decompress and the batch
+ * (padded nodes x 4), the padded coefficient array of bm_qoi_deltas and the
+ * adjoint's padded gradient (padded nodes x sizeof dtype each), and the
+ * quantizer's task table.  The plan
+ * owns all of it; a caller cannot supply its own.  Host memory (pinned
+ * staging of the box list) is not counted.  Errors: BM_EINVAL (null). */
+bm_status bm_workspace_size(bm_plan plan, size_t* bytes);
+
 /* Number of level-1 blocks per axis ({1,1,1} when L == 0): the shape of the
  * block tolerance map taken by the quantizer. */
 bm_status bm_block_grid(bm_plan plan, int64_t nblocks[3]);

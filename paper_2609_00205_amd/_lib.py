@@ -59,6 +59,7 @@ _SIGS = {
     "bm_plan_create": [C.POINTER(BMConfig), C.POINTER(P)],
     "bm_plan_destroy": [P],
     "bm_coeff_shape": [P, C.POINTER(C.c_int64)],
+    "bm_workspace_size": [P, C.POINTER(C.c_size_t)],
     "bm_model_calibrate": [C.c_int, C.c_int, C.POINTER(BMModel), P],
     "bm_model_predict": [C.POINTER(BMModel), C.POINTER(BMConfig), C.POINTER(C.c_double)],
     "bm_select_levels": [C.POINTER(BMConfig), C.POINTER(BMModel), C.c_double, C.POINTER(BMConfig),

@@ -132,6 +132,13 @@ class Plan:
         call("bm_level_gains", h, g)
         self.gains = list(g)
 
+    @property
+    def workspace_bytes(self) -> int:
+        """Device memory the plan holds now (bm_workspace_size)."""
+        n = C.c_size_t(0)
+        call("bm_workspace_size", self._h, C.byref(n))
+        return int(n.value)
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and getattr(self, "_owned", False):

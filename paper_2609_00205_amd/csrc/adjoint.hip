@@ -1001,7 +1001,7 @@ void decompose_adjoint_t(bm_plan_s& p, const void* gcoeff, void* gx, hipStream_t
     if (p.L == 0) {
       top = p.ws.grid[0];
     } else {
-      if (!p.ws.gpad) BM_HIP(hipMalloc(&p.ws.gpad, size_t(p.pdims[0] * p.pdims[1] * p.pdims[2]) * p.esize));
+      if (!p.ws.gpad) plan_alloc(p, &p.ws.gpad, size_t(p.pdims[0] * p.pdims[1] * p.pdims[2]) * p.esize);
       top = p.ws.gpad;
     }
   }

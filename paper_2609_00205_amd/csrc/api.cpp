@@ -202,10 +202,11 @@ CHeader parse(const void* in, size_t in_bytes, bool check_crc = true) {
 
 namespace bm {
 
-void ensure_pipeline_buffers(bm_plan_s& p) {
+// the codes of the padded grid, written by compress and read by decompress
+// (the fused paths need no coefficient array)
+void ensure_code_buffer(bm_plan_s& p) {
   const size_t n = size_t(p.pdims[0]) * p.pdims[1] * p.pdims[2];
-  if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, n * p.esize));
-  if (!p.ws.codes) BM_HIP(hipMalloc(&p.ws.codes, n * sizeof(int32_t)));
+  if (!p.ws.codes) plan_alloc(p, &p.ws.codes, n * sizeof(int32_t));
 }
 
 void check_block_tol(bm_plan_s& p, const double* block_tol, hipStream_t st) {
@@ -383,6 +384,13 @@ bm_status bm_coeff_shape(bm_plan p, int64_t padded_dims[3]) {
   return guarded([&] {
     need(p && padded_dims, "null argument");
     for (int a = 0; a < 3; ++a) padded_dims[a] = p->pdims[a];
+  });
+}
+
+bm_status bm_workspace_size(bm_plan p, size_t* bytes) {
+  return guarded([&] {
+    need(p && bytes, "null argument");
+    *bytes = p->dev_bytes;
   });
 }
 
@@ -574,7 +582,7 @@ bm_status bm_compress(bm_plan p, const void* x, const double* block_tol, void* o
     need(p && x && block_tol && out_bytes, "null argument");
     check_device(p);
     p->pending.reset();
-    bm::ensure_pipeline_buffers(*p);
+    bm::ensure_code_buffer(*p);
     bool too_fine = false;   // codes beyond 32 bits: store the raw data
     bm::check_block_tol(*p, block_tol, st);
     try {
@@ -594,7 +602,7 @@ bm_status bm_compress_plan(bm_plan p, const void* x, const double* block_tol, si
     need(p && x && block_tol && out_bytes, "null argument");
     check_device(p);
     p->pending.reset();
-    bm::ensure_pipeline_buffers(*p);
+    bm::ensure_code_buffer(*p);
     bool too_fine = false;   // codes beyond 32 bits: store the raw data
     bm::check_block_tol(*p, block_tol, st);
     try {
@@ -853,7 +861,7 @@ bm_status bm_batch_compress(bm_batch b, const void* const* x, const double* cons
       bm_plan_s& p = *bm::batch_plan(*b, f);
       check_device(&p);
       bm::check_block_tol(p, block_tol[f], st);
-      bm::ensure_pipeline_buffers(p);
+      bm::ensure_code_buffer(p);
       codes[f] = static_cast<int32_t*>(p.ws.codes);
     }
     bm::batch_decompose_quantize(*b, x, block_tol, codes.data(), use_graph != 0, st);
@@ -936,7 +944,7 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
     }
     const int64_t ntol = p->nb1[0] * p->nb1[1] * p->nb1[2];
     if (h.ntol != ntol || h.payload < uint64_t(ntol) * 8) bm::fail(BM_ECORRUPT, "tolerance map size mismatch");
-    bm::ensure_pipeline_buffers(*p);
+    bm::ensure_code_buffer(*p);
     BM_HIP(hipMalloc(&g.d, size_t(ntol) * sizeof(double)));
     BM_HIP(hipMemcpyAsync(g.d, pl, size_t(ntol) * 8, hipMemcpyHostToDevice, st));
     const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];

@@ -48,7 +48,7 @@ void measure(const bm_config& cfg, const void* x, const double* voxel_tol, int r
   const int64_t nlog = p.dims[0] * p.dims[1] * p.dims[2];
   const int64_t ntol = p.nb1[0] * p.nb1[1] * p.nb1[2];
   BM_HIP(hipMalloc(&g.tol, size_t(ntol) * sizeof(double)));
-  BM_HIP(hipMalloc(&p.ws.codes, size_t(npad) * sizeof(int32_t)));
+  plan_alloc(p, &p.ws.codes, size_t(npad) * sizeof(int32_t));
   int32_t* codes = static_cast<int32_t*>(p.ws.codes);
   tolmap_from_voxels(p, voxel_tol, g.tol, st);
   bm_qstats qs;

@@ -121,7 +121,7 @@ struct Workspace {
   void* t2 = nullptr;
   size_t t_elems = 0;
   void* codes = nullptr;         // int32, padded grid (compress path)
-  void* coeff = nullptr;         // dtype, padded grid (compress path)
+  void* coeff = nullptr;         // dtype, padded grid (bm_qoi_deltas: the adjoint of the quantity)
   double* tolbuf = nullptr;      // propagated block tolerances, all local levels
   double* qparam = nullptr;      // per-level quantizer parameters (device)
   std::vector<int64_t> tol_off;  // offset of level-s block map in tolbuf
@@ -174,9 +174,17 @@ struct bm_plan_s {
   // budget over more levels than the plan's (the 8^3 form's hybrid); empty:
   // the plan's own rule
   std::vector<double> w_override;
+  size_t dev_bytes = 0;          // device memory the plan holds (bm_workspace_size)
 };
 
 namespace bm {
+
+// Device memory owned by a plan, counted for bm_workspace_size.
+template <typename P>
+void plan_alloc(bm_plan_s& p, P** ptr, size_t bytes) {
+  BM_HIP(hipMalloc(reinterpret_cast<void**>(ptr), bytes));
+  p.dev_bytes += bytes;
+}
 
 int64_t padded_length(int64_t n, int b, int L, int M, bool nested = false);
 double level_gain_local(int b);
@@ -332,7 +340,7 @@ void dequantize_delta(bm_plan_s& p, const int32_t* codes, const double* delta, v
 // compress path: lazily allocated code / coefficient buffers of a plan, the
 // tolerance-map check, and the container writer (false: capacity too small,
 // *needed holds the size)
-void ensure_pipeline_buffers(bm_plan_s& p);
+void ensure_code_buffer(bm_plan_s& p);
 void check_block_tol(bm_plan_s& p, const double* block_tol, hipStream_t st);
 bool write_container(bm_plan_s& p, const void* x, const double* block_tol, bool too_fine, void* out, size_t capacity,
                      size_t* needed, hipStream_t st);

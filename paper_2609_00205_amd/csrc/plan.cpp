@@ -349,7 +349,7 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
           if (!L.coarsen[a]) continue;
           std::vector<double> inv;
           thomas_pivots_natural(L.m[a], inv);
-          BM_HIP(hipMalloc(&L.d_inv[a], inv.size() * sizeof(double)));
+          plan_alloc(*p, &L.d_inv[a], inv.size() * sizeof(double));
           BM_HIP(hipMemcpy(L.d_inv[a], inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
         }
       }
@@ -365,13 +365,13 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     if (p->fuse_next) {
       // per-block partial load vectors of the first global level (FP64): H^3 per block, H = (b+3)/4
       const int64_t h = (bL + 3) / 4;
-      BM_HIP(hipMalloc(&p->ws.part, size_t(prod3(p->lv[c->L - 1].nb)) * h * h * h * sizeof(double)));
+      plan_alloc(*p, &p->ws.part, size_t(prod3(p->lv[c->L - 1].nb)) * h * h * h * sizeof(double));
     }
     // workspace
     p->ws.grid.assign(p->nlev + 1, nullptr);
-    if (c->L == 0) BM_HIP(hipMalloc(&p->ws.grid[0], size_t(prod3(p->pdims)) * p->esize));
+    if (c->L == 0) plan_alloc(*p, &p->ws.grid[0], size_t(prod3(p->pdims)) * p->esize);
     for (int s = 1; s <= p->nlev; ++s)
-      BM_HIP(hipMalloc(&p->ws.grid[s], size_t(prod3(p->lv[s - 1].m)) * p->esize));
+      plan_alloc(*p, &p->ws.grid[s], size_t(prod3(p->lv[s - 1].m)) * p->esize);
     size_t t = 0;
     for (auto& L : p->lv) {
       if (L.local) {
@@ -383,8 +383,8 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     }
     p->ws.t_elems = t;
     if (t) {
-      BM_HIP(hipMalloc(&p->ws.t1, t * p->esize));
-      BM_HIP(hipMalloc(&p->ws.t2, t * p->esize));
+      plan_alloc(*p, &p->ws.t1, t * p->esize);
+      plan_alloc(*p, &p->ws.t2, t * p->esize);
     }
     int64_t tot = 0;
     p->ws.tol_off.assign(p->nlev + 2, 0);
@@ -396,12 +396,12 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     const int64_t nlastb = c->L > 0 ? prod3(p->lv[c->L - 1].nb) : 0;
     // propagated taus, Delta, 1/Delta per block; tau_global; coarsest-value
     // Delta and 1/Delta; then the 27-class Delta and 1/Delta tables
-    BM_HIP(hipMalloc(&p->ws.tolbuf, size_t(3 * tot + 8 + 2 * nlastb + 8 + 54 * (tot + nlastb)) * sizeof(double)));
-    BM_HIP(hipMalloc(&p->ws.boxbuf, size_t(kMaxBoxes) * 7 * sizeof(double)));
+    plan_alloc(*p, &p->ws.tolbuf, size_t(3 * tot + 8 + 2 * nlastb + 8 + 54 * (tot + nlastb)) * sizeof(double));
+    plan_alloc(*p, &p->ws.boxbuf, size_t(kMaxBoxes) * 7 * sizeof(double));
     BM_HIP(hipHostMalloc(&p->ws.boxhost, size_t(kMaxBoxes) * 7 * sizeof(double), hipHostMallocDefault));
-    BM_HIP(hipMalloc(&p->ws.qparam, size_t(4 * (p->nlev + 2)) * sizeof(double)));
+    plan_alloc(*p, &p->ws.qparam, size_t(4 * (p->nlev + 2)) * sizeof(double));
     // 16 counters, then per-workgroup partial statistics of the quantizer (3 x 8192)
-    BM_HIP(hipMalloc(&p->ws.counters, (16 + 3 * 8192) * sizeof(int64_t)));
+    plan_alloc(*p, &p->ws.counters, (16 + 3 * 8192) * sizeof(int64_t));
   } catch (...) {
     // release what was allocated, then rethrow
     for (auto& L : p->lv)

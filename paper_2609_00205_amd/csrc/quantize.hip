@@ -544,7 +544,7 @@ QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
       first[18 + 2 * s] = 0;
       first[18 + 2 * s + 1] = cnt_tab[s];
     }
-    BM_HIP(hipMalloc(&p.ws.prep_dev, kFirst + first.size() * sizeof(int64_t)));
+    plan_alloc(p, &p.ws.prep_dev, kFirst + first.size() * sizeof(int64_t));
     BM_HIP(hipMemcpy(static_cast<uint8_t*>(p.ws.prep_dev) + kFirst, first.data(), first.size() * sizeof(int64_t),
                      hipMemcpyHostToDevice));
   }
@@ -861,7 +861,7 @@ int64_t qoi_deltas(bm_plan_s& p, const void* g, double tol_q, const double* bloc
                    hipStream_t st) {
   if (!(tol_q > 0) || !std::isfinite(tol_q)) fail(BM_ENONFINITE, "tol_q must be positive and finite");
   const size_t npad = size_t(prod3(p.pdims));
-  if (!p.ws.coeff) BM_HIP(hipMalloc(&p.ws.coeff, npad * p.esize));
+  if (!p.ws.coeff) plan_alloc(p, &p.ws.coeff, npad * p.esize);
   // sensitivities s = R^T g of the quantity to the coefficients
   recompose_adjoint(p, g, p.ws.coeff, st);
   QArgs a = prepare(p, block_tol, st);

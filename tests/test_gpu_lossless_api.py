@@ -142,3 +142,27 @@ def test_compress_into_caller_buffers():
     assert torch.equal(api.decompress(pin[:len(ref)]), x_ref)
     with pytest.raises(ValueError):
         p.compress(x, bt, out=bytes(len(ref)))                       # read-only
+
+
+def test_workspace_size_counts_what_the_plan_holds():
+    # bm_workspace_size: the workspace built with the plan, then the padded
+    # code array that the first compress adds (and keeps; the fused path
+    # needs no coefficient array)
+    import numpy as np
+    from paper_2609_00205_amd import Plan
+    shape = (65, 65, 65)
+    p = Plan(shape, dtype=torch.float32, block=17, L=1, M=2)
+    n = int(np.prod(p.coeff_shape))
+    w0 = p.workspace_bytes
+    grids = sum(int(np.prod(((np.array(p.coeff_shape) - 1) >> s) + 1)) for s in (1, 2, 3)) * 4
+    assert w0 >= grids                     # the compact grids of levels 2.., at least
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=45, dtype=np.float32)).cuda()
+    bt = p.tolmap_from_boxes([], 1e-3 * float(x.abs().max()))
+    p.decompose_quantize(x, bt)            # adds the quantizer's task table (2048 + 36 x 8 bytes)
+    assert p.workspace_bytes == w0 + 2048 + 36 * 8
+    w0 = p.workspace_bytes
+    p.compress(x, bt)
+    w1 = p.workspace_bytes
+    assert w1 - w0 == n * 4                # the code array of the padded grid
+    p.compress(x, bt)
+    assert p.workspace_bytes == w1         # kept, not allocated again
