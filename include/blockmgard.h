@@ -81,8 +81,9 @@ typedef enum { BM_F32 = 0, BM_F64 = 1 } bm_dtype;
  *            blocks, which cover exactly the level-1 block regions; each
  *            level's block must have at least 9 nodes (b = 17: L <= 2;
  *            b = 33: L <= 3), else BM_EINVAL.  Results differ from 0 from
- *            the second block level on.  Batches do not take it
- *            (BM_EUNSUPPORTED).  Zero-initialised configs get 0. */
+ *            the second block level on.  Batches take it with b = 17
+ *            (every field of a batch on one schedule).  Zero-initialised
+ *            configs get 0. */
 typedef struct {
   int ndim;
   int64_t dims[3];
@@ -406,10 +407,14 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
  * HIP graph (per set of bound pointers) and replayed; use_graph needs a
  * stream other than the null stream.  The batch owns one plan per field
  * (bm_batch_plan borrows it: coefficient shapes, tolerance maps); a batch is
- * used from one stream at a time.  Errors: BM_EINVAL (mixed dtype or block
- * size, null pointers), BM_EUNSUPPORTED (b = 33 with block levels),
- * BM_ENOMEM.  A field config with L = -1 takes the most block levels its
- * logical dims tile without padding (at least 1; b = 9 or 17 only);
+ * used from one stream at a time.  With the nested schedule (b = 17, every
+ * field) a field's 17- and 9-node levels run as one pair: one persistent
+ * launch covers the pairs of all such fields, beside the plain launch of
+ * the fields with one block level.  Errors: BM_EINVAL (mixed dtype, block
+ * size or schedule, null pointers), BM_EUNSUPPORTED (b = 33 with block
+ * levels, the nested schedule with b != 17), BM_ENOMEM.  A field config with
+ * L = -1 takes the most block levels its logical dims tile without padding
+ * (at least 1; b = 9 or 17 only; nested: 2 when they tile, else 1);
  * bm_plan_config of the field's bm_batch_plan returns the resolved config. */
 typedef struct bm_batch_s* bm_batch;
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out);

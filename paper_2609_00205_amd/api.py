@@ -658,11 +658,13 @@ class Batch:
     optionally captured once in a HIP graph and replayed.
 
     L: per-field block levels (default: the most each shape tiles without
-    padding, chosen by the library); M: global levels (int or per field).
+    padding, chosen by the library); M: global levels (int or per field);
+    nested: the nested block schedule for every field (b = 17: a field's
+    17- and 9-node levels run as one pair in one persistent launch).
     """
 
     def __init__(self, shapes: Sequence[Sequence[int]], dtype=torch.float32, block: int = 17, L=None, M=0,
-                 pad_mode: str = "clamp", eta: Optional[float] = None, device=None):
+                 pad_mode: str = "clamp", eta: Optional[float] = None, device=None, nested: bool = False):
         shapes = [tuple(int(v) for v in sh) for sh in shapes]
         nf = len(shapes)
         Ls = [-1] * nf if L is None else ([int(L)] * nf if isinstance(L, int) else [int(v) for v in L])
@@ -673,7 +675,7 @@ class Batch:
         cfgs = (BMConfig * nf)()
         for i, sh in enumerate(shapes):
             cfgs[i] = BMConfig(3, (C.c_int64 * 3)(*sh), _DT[dtype], block, Ls[i], Ms[i],
-                               1 if pad_mode == "zero" else 0, self.eta)
+                               1 if pad_mode == "zero" else 0, self.eta, 1 if nested else 0)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             call("bm_batch_create", nf, cfgs, C.byref(h))

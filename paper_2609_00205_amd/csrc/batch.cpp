@@ -35,6 +35,13 @@ struct Bound {
   const int64_t* first[kMaxLev] = {};
   int nf[kMaxLev] = {};
   int64_t ntasks[kMaxLev] = {};
+  int blk[kMaxLev] = {};           // block size of the level's launch
+  // nested schedule: the fields whose levels 1 and 2 run as one pair
+  const void* nargs1 = nullptr;
+  const void* nargs2 = nullptr;
+  const int64_t* nfirst = nullptr;
+  int nnf = 0;
+  int64_t nntasks = 0;
   void* arena = nullptr;
   size_t arena_bytes = 0;
   hipGraphExec_t graph = nullptr;
@@ -63,7 +70,7 @@ struct Image {
 
 struct bm_batch_s {
   std::vector<bm_plan_s*> plans;
-  int block = 0, dtype = 0, Lmax = 0, device = 0;
+  int block = 0, dtype = 0, Lmax = 0, device = 0, nested = 0;
   bm::Bound dq, rq;
 };
 
@@ -113,13 +120,19 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
     off_tab[s] = im.put(ft.data(), ft.size() * sizeof(int64_t));
   }
   // block levels: arguments of the fields that have level s, in field order
+  // (a field whose levels 1 and 2 form a nested pair is in neither list: it
+  // takes the pair launch below)
   size_t off_args[kMaxLev] = {}, off_first[kMaxLev] = {};
   for (int s = 1; s <= b.Lmax; ++s) {
     std::vector<uint8_t> args;
     std::vector<int64_t> first(1, 0);
+    B.blk[s] = 0;
     for (int f = 0; f < nf; ++f) {
       bm_plan_s& p = *b.plans[f];
       if (p.L < s) continue;
+      if (s <= 2 && nest_pair(p, 1)) continue;
+      if (!B.blk[s]) B.blk[s] = p.lv[s - 1].b;
+      if (p.lv[s - 1].b != B.blk[s]) fail(BM_EUNSUPPORTED, "fields of one batched level use one block size");
       const size_t sz = block_args_size(p, dec);
       args.resize(args.size() + sz);
       uint8_t* dst = args.data() + args.size() - sz;
@@ -137,6 +150,28 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
     off_args[s] = im.put(args.data(), args.size());
     off_first[s] = im.put(first.data(), first.size() * sizeof(int64_t));
   }
+  // nested pairs: level 1's and level 2's arguments side by side
+  size_t off_n1 = 0, off_n2 = 0, off_nfirst = 0;
+  {
+    std::vector<uint8_t> a1, a2;
+    std::vector<int64_t> first(1, 0);
+    for (int f = 0; f < nf; ++f) {
+      bm_plan_s& p = *b.plans[f];
+      if (!nest_pair(p, 1)) continue;
+      const size_t sz = block_args_size(p, dec);
+      a1.resize(a1.size() + sz);
+      a2.resize(a2.size() + sz);
+      const View3 src = dense_view(const_cast<void*>(x[f]), p.dims);
+      block_nest_args(p, dec, src, const_cast<void*>(x[f]), codes[f], &B.q[f], a1.data() + a1.size() - sz,
+                      a2.data() + a2.size() - sz);
+      first.push_back(first.back() + block_groups(p, 1, dec));
+    }
+    B.nnf = int(first.size()) - 1;
+    B.nntasks = first.back();
+    off_n1 = im.put(a1.data(), a1.size());
+    off_n2 = im.put(a2.data(), a2.size());
+    off_nfirst = im.put(first.data(), first.size() * sizeof(int64_t));
+  }
   B.arena_bytes = im.bytes.size();
   BM_HIP(hipMalloc(&B.arena, B.arena_bytes));
   BM_HIP(hipMemcpyAsync(B.arena, im.bytes.data(), B.arena_bytes, hipMemcpyHostToDevice, st));
@@ -151,6 +186,9 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
     B.args[s] = at(off_args[s]);
     B.first[s] = static_cast<const int64_t*>(at(off_first[s]));
   }
+  B.nargs1 = at(off_n1);
+  B.nargs2 = at(off_n2);
+  B.nfirst = static_cast<const int64_t*>(at(off_nfirst));
   B.x.assign(x, x + nf);
   B.tol.assign(tol, tol + nf);
   B.codes.assign(codes, codes + nf);
@@ -160,16 +198,22 @@ void enqueue(bm_batch_s& b, Bound& B, bool dec, hipStream_t st) {
   const int nf = int(b.plans.size());
   launch_prep_batch(B.stages, B.fields, nf, st);
   if (dec) {
-    for (int s = 1; s <= b.Lmax; ++s)
-      launch_block_batch(b.block, b.dtype, true, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+    for (int s = 1; s <= b.Lmax; ++s) {
+      if (s == 1) launch_block_batch_nest(b.dtype, true, B.nargs1, B.nargs2, B.nfirst, B.nnf, B.nntasks, st);
+      if (B.ntasks[s] > 0)
+        launch_block_batch(B.blk[s], b.dtype, true, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+    }
     for (int f = 0; f < nf; ++f)
       decompose_quantize_global(*b.plans[f], B.x[f], static_cast<int32_t*>(const_cast<void*>(B.codes[f])), B.q[f], st);
   } else {
     for (int f = 0; f < nf; ++f)
       dequantize_recompose_global(*b.plans[f], static_cast<const int32_t*>(B.codes[f]), B.q[f],
                                   const_cast<void*>(B.x[f]), st);
-    for (int s = b.Lmax; s >= 1; --s)
-      launch_block_batch(b.block, b.dtype, false, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+    for (int s = b.Lmax; s >= 1; --s) {
+      if (B.ntasks[s] > 0)
+        launch_block_batch(B.blk[s], b.dtype, false, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+      if (s == 1) launch_block_batch_nest(b.dtype, false, B.nargs1, B.nargs2, B.nfirst, B.nnf, B.nntasks, st);
+    }
   }
 }
 
@@ -207,10 +251,20 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
     for (int f = 0; f < nfields; ++f) {
       if (f > 0 && (cfgs[f].dtype != cfgs[0].dtype || cfgs[f].block != cfgs[0].block))
         fail(BM_EINVAL, "all fields of a batch share dtype and block size");
-      if (cfgs[f].nested)
-        fail(BM_EUNSUPPORTED, "batches take the plain block schedule (nested = 0)");
+      if (f > 0 && cfgs[f].nested != cfgs[0].nested) fail(BM_EINVAL, "all fields of a batch share the block schedule");
       bm_config c = cfgs[f];
-      if (c.L == -1) {
+      if (c.nested && c.block != 17)
+        fail(BM_EUNSUPPORTED, "batched nested schedule: b = 17 (17- then 9-node blocks)");
+      if (c.L == -1 && c.nested) {
+        // nested: level 2 tiles wherever level 1 does (9-node blocks inside the
+        // 17-node regions); both levels when the dims tile without padding
+        int64_t d[3] = {1, 1, 1};
+        if (c.ndim < 1 || c.ndim > 3) fail(BM_EINVAL, "ndim must be 1, 2 or 3");
+        for (int a = 0; a < c.ndim; ++a) d[3 - c.ndim + a] = c.dims[a];
+        bool tiles = true;
+        for (int a = 0; a < 3; ++a) tiles = tiles && d[a] >= 17 && (d[a] - 1) % 16 == 0;
+        c.L = tiles ? 2 : 1;
+      } else if (c.L == -1) {
         // the most block levels the logical dims tile without padding (at least 1)
         if (c.block != 9 && c.block != 17) fail(BM_EINVAL, "L = -1 needs block 9 or 17");
         int64_t d[3] = {1, 1, 1};
@@ -232,6 +286,7 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
     }
     b->block = cfgs[0].block;
     b->dtype = cfgs[0].dtype;
+    b->nested = cfgs[0].nested;
     if (b->Lmax >= kMaxLev) fail(BM_EUNSUPPORTED, "too many block levels");
   } catch (...) {
     for (auto* p : b->plans) bm_plan_free(p);

@@ -321,6 +321,13 @@ void block_rec_args(const bm_plan_s& p, int s, const void* coeff, const void* ci
                     const int32_t* codes, const QPrep* q, void* out);
 void launch_block_batch(int block, int dtype, bool dec, bool quant, const void* args, const int64_t* first, int nf,
                         int64_t ntasks, hipStream_t st);
+// the nested pair (levels 1 and 2) of many fields per launch: level 1's and
+// level 2's arguments of each field (block_args_size bytes each; x is the
+// recomposition's output), block_groups(p_f, 1) groups per field
+void block_nest_args(const bm_plan_s& p, bool dec, const View3& src, void* x, int32_t* codes, const QPrep* q,
+                     void* out1, void* out2);
+void launch_block_batch_nest(int dtype, bool dec, const void* a1, const void* a2, const int64_t* first, int nf,
+                             int64_t ntasks, hipStream_t st);
 
 // quantization
 void tolmap_from_boxes(bm_plan_s& p, const double* boxes, int nbox, double background, double* block_tol,

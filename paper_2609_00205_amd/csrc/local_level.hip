@@ -130,7 +130,7 @@ constexpr int nest_offset() {
 // SRC_LDS: the level's input is the coarse values a (2B-1)-node block level
 // left in LDS for this group (nested schedule), not the source grid.
 template <typename T, int B, bool Q, int NBG = Geo<B, sizeof(T)>::NB, bool SRC_LDS = false>
-__device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
+__device__ __attribute__((always_inline)) inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B, sizeof(T)>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = NBG;
   constexpr int PREG = SRC_LDS ? Geo<2 * B - 1>::DEC_LDS : G::DEC_LDS;   // LDS elements per block
@@ -349,7 +349,7 @@ __device__ inline void decompose_group(const DecArgs<T>& a, int64_t g, T* lds) {
 // after them; MODE 2 is that finer level, which reads its coarse values
 // there instead of from the coarse grid.
 template <typename T, int B, bool Q, int NBG = Geo<B, sizeof(T), false>::NB, int MODE = 0>
-__device__ inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
+__device__ __attribute__((always_inline)) inline void recompose_group(const RecArgs<T>& a, int64_t g, T* lds) {
   using G = Geo<B, sizeof(T), false>;
   constexpr int BB = G::BB, MC = G::MC, MI = G::MI, NB = NBG;
   constexpr int PREG = MODE == 1 ? Geo<2 * B - 1>::REC_LDS : G::REC_LDS;   // LDS elements per block
@@ -588,6 +588,43 @@ __global__ __launch_bounds__((Geo<B, sizeof(T), false>::NT)) void k_batch_recomp
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
     recompose_group<T, B, Q>(fa[f], k - first[f], lds);
+    __syncthreads();
+  }
+}
+
+// The nested schedule of every field in one persistent launch: task k is
+// block group k - first[f] of field f at its 17-node level (arguments f1[f]),
+// then the same group of its 9-node level (f2[f]) on the coarse values the
+// first left in LDS, as k_local_decompose_nest / k_local_recompose_nest do
+// for one field.
+template <typename T, bool Q>
+__global__ __launch_bounds__((Geo<17, sizeof(T)>::NT)) void k_batch_decompose_nest(
+    const DecArgs<T>* __restrict__ f1, const DecArgs<T>* __restrict__ f2, const int64_t* __restrict__ first, int nf,
+    int64_t ntasks) {
+  constexpr int NB = Geo<17, sizeof(T)>::NB;
+  __shared__ __attribute__((aligned(16))) T lds[NB * Geo<17>::DEC_LDS];   // FP64 scratch inside
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
+    const int64_t g = k - first[f];
+    decompose_group<T, 17, Q>(f1[f], g, lds);
+    __syncthreads();
+    decompose_group<T, 9, Q, NB, true>(f2[f], g, lds);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool Q>
+__global__ __launch_bounds__((Geo<17, sizeof(T), false>::NT)) void k_batch_recompose_nest(
+    const RecArgs<T>* __restrict__ f1, const RecArgs<T>* __restrict__ f2, const int64_t* __restrict__ first, int nf,
+    int64_t ntasks) {
+  constexpr int NB = Geo<17, sizeof(T), false>::NB;
+  __shared__ T lds[NB * Geo<17>::REC_LDS];
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
+    const int64_t g = k - first[f];
+    recompose_group<T, 9, Q, NB, 1>(f2[f], g, lds);
+    __syncthreads();
+    recompose_group<T, 17, Q, NB, 2>(f1[f], g, lds);
     __syncthreads();
   }
 }
@@ -910,6 +947,74 @@ void launch_block_batch(int block, int dtype, bool dec, bool quant, const void* 
     else
       launch_batch<double, 17>(dec, quant, args, first, nf, ntasks, st);
   }
+}
+
+namespace {
+
+template <typename T>
+void nest_dec_pair(const bm_plan_s& p, const View3& src, int32_t* codes, const QPrep* q, void* out1, void* out2) {
+  DecArgs<T> a1 = dec_args<T, 17>(p, 1, src, true, nullptr, nullptr, codes, q);
+  a1.nest = 1;
+  const DecArgs<T> a2 = dec_args<T, 9>(p, 2, dense_view(p.ws.grid[1], p.lv[1].n), false, nullptr, p.ws.grid[2], codes, q);
+  if (a1.fuse || a1.coarsest_here || a2.nblocks != a1.nblocks) fail(BM_EINVAL, "nested pair: inconsistent levels");
+  std::memcpy(out1, &a1, sizeof(a1));
+  std::memcpy(out2, &a2, sizeof(a2));
+}
+
+template <typename T>
+void nest_rec_pair(const bm_plan_s& p, void* x, const int32_t* codes, const QPrep* q, void* out1, void* out2) {
+  const RecArgs<T> a1 = rec_args<T, 17>(p, 1, nullptr, nullptr, x, true, codes, q);
+  const RecArgs<T> a2 = rec_args<T, 9>(p, 2, nullptr, p.ws.grid[2], nullptr, false, codes, q);
+  if (a1.fuse || a1.coarsest_here || a2.nblocks != a1.nblocks) fail(BM_EINVAL, "nested pair: inconsistent levels");
+  std::memcpy(out1, &a1, sizeof(a1));
+  std::memcpy(out2, &a2, sizeof(a2));
+}
+
+template <typename T>
+void launch_batch_nest(bool dec, const void* a1, const void* a2, const int64_t* first, int nf, int64_t ntasks,
+                       hipStream_t st) {
+  if (ntasks <= 0) return;
+  if (dec) {
+    auto k = k_batch_decompose_nest<T, true>;
+    const int nt = Geo<17, sizeof(T)>::NT;
+    hipLaunchKernelGGL(k, dim3(resident_grid(k, nt, ntasks)), dim3(nt), 0, st, static_cast<const DecArgs<T>*>(a1),
+                       static_cast<const DecArgs<T>*>(a2), first, nf, ntasks);
+  } else {
+    auto k = k_batch_recompose_nest<T, true>;
+    const int nt = Geo<17, sizeof(T), false>::NT;
+    hipLaunchKernelGGL(k, dim3(resident_grid(k, nt, ntasks)), dim3(nt), 0, st, static_cast<const RecArgs<T>*>(a1),
+                       static_cast<const RecArgs<T>*>(a2), first, nf, ntasks);
+  }
+  BM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// Arguments of a field's nested pair (17-node level 1, 9-node level 2) for
+// the batched nest launch: out1 gets level 1's, out2 level 2's (each
+// block_args_size bytes).
+void block_nest_args(const bm_plan_s& p, bool dec, const View3& src, void* x, int32_t* codes, const QPrep* q,
+                     void* out1, void* out2) {
+  if (!nest_pair(p, 1)) fail(BM_EINVAL, "block levels 1, 2 are not a nested 17/9 pair");
+  if (dec) {
+    if (p.cfg.dtype == BM_F32)
+      nest_dec_pair<float>(p, src, codes, q, out1, out2);
+    else
+      nest_dec_pair<double>(p, src, codes, q, out1, out2);
+  } else {
+    if (p.cfg.dtype == BM_F32)
+      nest_rec_pair<float>(p, x, codes, q, out1, out2);
+    else
+      nest_rec_pair<double>(p, x, codes, q, out1, out2);
+  }
+}
+
+void launch_block_batch_nest(int dtype, bool dec, const void* a1, const void* a2, const int64_t* first, int nf,
+                             int64_t ntasks, hipStream_t st) {
+  if (dtype == BM_F32)
+    launch_batch_nest<float>(dec, a1, a2, first, nf, ntasks, st);
+  else
+    launch_batch_nest<double>(dec, a1, a2, first, nf, ntasks, st);
 }
 
 }  // namespace bm

@@ -48,20 +48,28 @@ CASES = [
     ([(17, 33, 17), (33, 33, 65), (65, 65, 65)], torch.float32, 9, None, 0),
     ([(33, 33, 33), (65, 33, 33), (33, 65, 17)], torch.float32, 17, 1, 2),        # global levels per field
     ([(40, 20, 33), (25, 30, 17)], torch.float32, 9, 1, 1),                       # padded fields
+    # nested schedule: a field's 17- and 9-node levels as one pair per launch
+    ([(33, 17, 65), (17, 17, 17), (65, 65, 33), (33, 33, 33)], torch.float32, 17, None, 0, True),
+    ([(33, 17, 65), (65, 33, 33)], torch.float64, 17, None, 0, True),
+    ([(33, 33, 33), (40, 20, 33), (65, 33, 17)], torch.float32, 17, [2, 1, 2], 0, True),   # pairs beside a plain level
+    ([(33, 33, 33), (65, 33, 33)], torch.float32, 17, 2, 1, True),                # pairs, then a global level
 ]
 
 
 def _id(c):
-    return f"{len(c[0])}f-{str(c[1])[6:]}-b{c[2]}-L{c[3]}-M{c[4]}"
+    return f"{len(c[0])}f-{str(c[1])[6:]}-b{c[2]}-L{c[3]}-M{c[4]}" + ("-nested" if len(c) > 5 and c[5] else "")
 
 
 @pytest.mark.parametrize("case", CASES, ids=_id)
 @pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
 def test_batch_equals_single(case, use_graph):
     from paper_2609_00205_amd import Batch
-    shapes, dt, b, L, M = case
+    shapes, dt, b, L, M = case[:5]
+    nested = len(case) > 5 and case[5]
     print("case", _id(case), "graph" if use_graph else "eager", flush=True)
-    batch = Batch(shapes, dtype=dt, block=b, L=L, M=M)
+    batch = Batch(shapes, dtype=dt, block=b, L=L, M=M, nested=nested)
+    if nested:
+        assert all(p.nested for p in batch.plans)
     xs = _fields(shapes, dt, 100)
     tols = _tols(batch, xs)
     codes = [torch.empty(p.coeff_shape, dtype=torch.int32, device="cuda") for p in batch.plans]
@@ -110,6 +118,8 @@ ORACLE_CASES = [
     ([(33, 65, 33), (17, 17, 33)], torch.float64, 17, None, 0),
     ([(33, 33, 65), (65, 17, 33)], torch.float32, 9, None, 0),
     ([(33, 33, 33), (65, 33, 33)], torch.float64, 9, 1, 2),          # global levels per field
+    ([(33, 17, 65), (65, 33, 33), (17, 33, 17)], torch.float32, 17, None, 0, True),   # nested pairs
+    ([(33, 33, 33), (65, 33, 17)], torch.float64, 17, 2, 1, True),
 ]
 
 
@@ -125,9 +135,10 @@ def test_batch_matches_oracle(case):
     codes; every voxel within its bound."""
     from oracle import mgard, roi
     from paper_2609_00205_amd import Batch
-    shapes, dt, b, L, M = case
+    shapes, dt, b, L, M = case[:5]
+    nested = len(case) > 5 and case[5]
     print("case", _id(case), flush=True)
-    batch = Batch(shapes, dtype=dt, block=b, L=L, M=M)
+    batch = Batch(shapes, dtype=dt, block=b, L=L, M=M, nested=nested)
     xs = _fields(shapes, dt, 700)
     tols = _tols(batch, xs)
     codes = batch.decompose_quantize(xs, tols, use_graph=True)
@@ -136,8 +147,8 @@ def test_batch_matches_oracle(case):
     ctol = 1e-6 if dt == torch.float32 else 1e-13
     for p, x, t, c, o in zip(batch.plans, xs, tols, codes, outs):
         xn = x.cpu().double().numpy()
-        h = mgard.hierarchy(p.shape, b, p.L, p.M)
-        co = mgard.decompose(xn, b, p.L, p.M)
+        h = mgard.hierarchy(p.shape, b, p.L, p.M, nested)
+        co = mgard.decompose(xn, b, p.L, p.M, nested=nested)
         tol1 = t.cpu().numpy() if p.L > 0 else float(t.cpu().numpy().ravel()[0])
         delta = roi.node_delta(h, tol1, p.eta)
         ref = roi.quantize(co, delta)
@@ -151,7 +162,7 @@ def test_batch_matches_oracle(case):
         assert np.all(np.abs(got - ref) <= reach + 1)
         near = flips & (reach < 0.5)
         assert np.all(edge[near] <= ctol * scale)
-        xr_ref = mgard.recompose(roi.dequantize(got, delta), p.shape, b, p.L, p.M)
+        xr_ref = mgard.recompose(roi.dequantize(got, delta), p.shape, b, p.L, p.M, nested)
         on = o.cpu().double().numpy()
         assert float(np.abs(on - xr_ref).max()) <= ctol * max(scale, float(np.abs(xr_ref).max()))
         n = p.shape

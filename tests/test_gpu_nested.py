@@ -153,10 +153,24 @@ def test_nested_container_round_trip():
     assert np.all(np.abs(xr - x.astype(np.float64)) <= vt)
 
 
-def test_batches_take_the_plain_schedule():
+def test_batch_schedule_rules():
+    # batches take the nested schedule with b = 17 (its pairs run in one
+    # persistent launch); every field shares the schedule; b = 9 nested is refused
     from paper_2609_00205_amd import _lib
     from paper_2609_00205_amd._lib import BMConfig
     import ctypes as C
-    cfg = (BMConfig * 1)(BMConfig(3, (C.c_int64 * 3)(33, 33, 33), 0, 17, 2, 1, 0, 0.1, 1))
+    lib = _lib.lib()
     h = C.c_void_p()
-    assert _lib.lib().bm_batch_create(1, cfg, C.byref(h)) == -8
+    ok = (BMConfig * 2)(BMConfig(3, (C.c_int64 * 3)(33, 33, 33), 0, 17, 2, 1, 0, 0.1, 1),
+                        BMConfig(3, (C.c_int64 * 3)(65, 33, 17), 0, 17, -1, 0, 0, 0.1, 1))
+    assert lib.bm_batch_create(2, ok, C.byref(h)) == 0
+    p = C.c_void_p()
+    cfg = BMConfig()
+    assert lib.bm_batch_plan(h, 1, C.byref(p)) == 0 and lib.bm_plan_config(p, C.byref(cfg)) == 0
+    assert cfg.nested == 1 and cfg.L == 2                      # L = -1: both levels of the pair
+    assert lib.bm_batch_destroy(h) == 0
+    mixed = (BMConfig * 2)(BMConfig(3, (C.c_int64 * 3)(33, 33, 33), 0, 17, 2, 0, 0, 0.1, 1),
+                           BMConfig(3, (C.c_int64 * 3)(33, 33, 33), 0, 17, 2, 0, 0, 0.1, 0))
+    assert lib.bm_batch_create(2, mixed, C.byref(h)) == -1
+    b9 = (BMConfig * 1)(BMConfig(3, (C.c_int64 * 3)(33, 33, 33), 0, 9, 1, 0, 0, 0.1, 1))
+    assert lib.bm_batch_create(1, b9, C.byref(h)) == -8
