@@ -846,6 +846,7 @@ void launch_pass_T(const bm_plan_s& p, int s, int axis, const View3& in, const V
     case 3: hipLaunchKernelGGL((k_line_pass_T<T, 3>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case 5: hipLaunchKernelGGL((k_line_pass_T<T, 5>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case 9: hipLaunchKernelGGL((k_line_pass_T<T, 9>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case 11: hipLaunchKernelGGL((k_line_pass_T<T, 11>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case kRowQ: hipLaunchKernelGGL((k_line_pass_T<T, kRowQ>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     default: hipLaunchKernelGGL((k_line_pass_T<T, 0>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
   }

@@ -576,6 +576,7 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
     case 3: hipLaunchKernelGGL((k_line_pass<T, 3>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case 5: hipLaunchKernelGGL((k_line_pass<T, 5>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case 9: hipLaunchKernelGGL((k_line_pass<T, 9>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
+    case 11: hipLaunchKernelGGL((k_line_pass<T, 11>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     case kRowQ: hipLaunchKernelGGL((k_line_pass<T, kRowQ>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
     default: hipLaunchKernelGGL((k_line_pass<T, 0>), dim3(unsigned(tiles)), dim3(NT), shm, st, a); break;
   }

@@ -2,14 +2,15 @@
 the C ABI: decompose, recompose and both transposes.
 
 The line solver takes a register layout per line length m (coarse nodes per
-line): 16-lane groups with 3, 5, 9 or 17 unknowns per lane for m <= 48, 80,
-144 or 272, and a whole wavefront for m <= 576.  Short grids reach only the
+line): 16-lane groups with 3, 5, 9, 11 or 17 unknowns per lane for m <= 48,
+80, 144, 176 or 272, and a whole wavefront for m <= 576.  Short grids reach only the
 first two; these cases put the long lines of the full-size workloads on
 small grids that the oracle finishes at once:
 
 * L = 0, M = 1 on (3, 3, n), (3, n, 3), (n, 3, 3): one global level whose
-  lines along the long axis have m = (n + 1) / 2 = 129, 257, 513 coarse nodes
-  (the restriction + solve passes);
+  lines along the long axis have m = (n + 1) / 2 = 129, 161, 257, 513 coarse
+  nodes (the restriction + solve passes; 161 is the global axis of the 8^3
+  form's hybrid at 512^3);
 * b = 17, L = 1, M = 1 on (17, 17, n) and its permutations: the first
   global level fused into the block level, whose solve-only passes run on
   the 9 x 9 x (n + 1) / 2 block-coarse grid, lines of (n + 1) / 2 nodes;
@@ -33,12 +34,13 @@ TOL_T = {torch.float32: 2e-6, torch.float64: 1e-12}
 
 def _variant(m):
     # the solver's register layout for lines of m coarse nodes (named in the test id)
-    return "Q3" if m <= 48 else "Q5" if m <= 80 else "Q9" if m <= 144 else "Q17" if m <= 272 else "Qwave"
+    return ("Q3" if m <= 48 else "Q5" if m <= 80 else "Q9" if m <= 144 else "Q11" if m <= 176 else "Q17" if m <= 272
+            else "Qwave")
 
 
 def _cases():
     out = []
-    for n in (257, 513, 1025):
+    for n in (257, 321, 513, 1025):
         m = (n + 1) // 2
         for ax in range(3):
             shape = [3, 3, 3]
