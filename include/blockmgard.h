@@ -410,11 +410,13 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
  * used from one stream at a time.  With the nested schedule (b = 17, every
  * field) a field's 17- and 9-node levels run as one pair: one persistent
  * launch covers the pairs of all such fields, beside the plain launch of
- * the fields with one block level.  Errors: BM_EINVAL (mixed dtype, block
- * size or schedule, null pointers), BM_EUNSUPPORTED (b = 33 with block
- * levels, the nested schedule with b != 17), BM_ENOMEM.  A field config with
- * L = -1 takes the most block levels its logical dims tile without padding
- * (at least 1; b = 9 or 17 only; nested: 2 when they tile, else 1);
+ * the fields with one block level.  A 33-node level runs its column,
+ * coarse (and, recomposing, interpolation) steps as one persistent launch
+ * each over the block halves or blocks of every field.  Errors: BM_EINVAL
+ * (mixed dtype, block size or schedule, null pointers), BM_EUNSUPPORTED (the
+ * nested schedule with b != 17), BM_ENOMEM.  A field config with L = -1
+ * takes the most block levels its logical dims tile without padding (at
+ * least 1; nested: 2 when they tile, else 1);
  * bm_plan_config of the field's bm_batch_plan returns the resolved config. */
 typedef struct bm_batch_s* bm_batch;
 bm_status bm_batch_create(int nfields, const bm_config* cfgs, bm_batch* out);

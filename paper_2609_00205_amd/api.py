@@ -654,8 +654,9 @@ class Paper8Plan:
 
 class Batch:
     """Many fields of one dtype and block size through the fused pipeline in
-    few launches (one persistent launch per block level for all fields),
-    optionally captured once in a HIP graph and replayed.
+    few launches (one persistent launch per block level for all fields; for
+    33-node blocks one per step of the split block), optionally captured once
+    in a HIP graph and replayed.
 
     L: per-field block levels (default: the most each shape tiles without
     padding, chosen by the library); M: global levels (int or per field);

@@ -3,8 +3,10 @@
 // The fused pipeline of every field (decompose + ROI quantize, or dequantize
 // + recompose) is issued as: one launch per stage of the quantizer-table
 // preparation for all fields, one persistent launch per block level
-// covering the blocks of every field that has that level, and the (small)
-// global levels of each field.  The whole sequence can be captured once in
+// covering the blocks of every field that has that level (a 33-node level:
+// one per step of the split block, over halves or blocks; the nested
+// schedule: one for the 17/9 pairs), and the (small) global levels of each
+// field.  The whole sequence can be captured once in
 // a HIP graph and replayed while the bound buffers stay the same.
 //
 // Per-field kernel arguments and task lists are built on the host and
@@ -36,6 +38,9 @@ struct Bound {
   int nf[kMaxLev] = {};
   int64_t ntasks[kMaxLev] = {};
   int blk[kMaxLev] = {};           // block size of the level's launch
+  // 33-node levels: tasks are block halves (first[]) and blocks (firstb[])
+  const int64_t* firstb[kMaxLev] = {};
+  int64_t nblk[kMaxLev] = {};
   // nested schedule: the fields whose levels 1 and 2 run as one pair
   const void* nargs1 = nullptr;
   const void* nargs2 = nullptr;
@@ -122,10 +127,10 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
   // block levels: arguments of the fields that have level s, in field order
   // (a field whose levels 1 and 2 form a nested pair is in neither list: it
   // takes the pair launch below)
-  size_t off_args[kMaxLev] = {}, off_first[kMaxLev] = {};
+  size_t off_args[kMaxLev] = {}, off_first[kMaxLev] = {}, off_firstb[kMaxLev] = {};
   for (int s = 1; s <= b.Lmax; ++s) {
     std::vector<uint8_t> args;
-    std::vector<int64_t> first(1, 0);
+    std::vector<int64_t> first(1, 0), firstb(1, 0);
     B.blk[s] = 0;
     for (int f = 0; f < nf; ++f) {
       bm_plan_s& p = *b.plans[f];
@@ -133,6 +138,21 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
       if (s <= 2 && nest_pair(p, 1)) continue;
       if (!B.blk[s]) B.blk[s] = p.lv[s - 1].b;
       if (p.lv[s - 1].b != B.blk[s]) fail(BM_EUNSUPPORTED, "fields of one batched level use one block size");
+      if (B.blk[s] == 33) {
+        // a 33-node level: column and coarse steps (and interpolation) over halves and blocks
+        const size_t sz = wide_args_size(p);
+        args.resize(args.size() + sz);
+        uint8_t* dst = args.data() + args.size() - sz;
+        const View3 src =
+            dec ? (s == 1 ? dense_view(const_cast<void*>(x[f]), p.dims) : dense_view(p.ws.grid[s - 1], p.lv[s - 1].n))
+                : View3{};
+        void* out = s == 1 ? const_cast<void*>(x[f]) : p.ws.grid[s - 1];
+        wide_batch_args(p, s, dec, src, s == 1, out, codes[f], &B.q[f], dst);
+        const int64_t nb = p.lv[s - 1].nb[0] * p.lv[s - 1].nb[1] * p.lv[s - 1].nb[2];
+        first.push_back(first.back() + 2 * nb);
+        firstb.push_back(firstb.back() + nb);
+        continue;
+      }
       const size_t sz = block_args_size(p, dec);
       args.resize(args.size() + sz);
       uint8_t* dst = args.data() + args.size() - sz;
@@ -147,8 +167,10 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
     }
     B.nf[s] = int(first.size()) - 1;
     B.ntasks[s] = first.back();
+    B.nblk[s] = firstb.back();
     off_args[s] = im.put(args.data(), args.size());
     off_first[s] = im.put(first.data(), first.size() * sizeof(int64_t));
+    off_firstb[s] = im.put(firstb.data(), firstb.size() * sizeof(int64_t));
   }
   // nested pairs: level 1's and level 2's arguments side by side
   size_t off_n1 = 0, off_n2 = 0, off_nfirst = 0;
@@ -185,6 +207,7 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
   for (int s = 1; s <= b.Lmax; ++s) {
     B.args[s] = at(off_args[s]);
     B.first[s] = static_cast<const int64_t*>(at(off_first[s]));
+    B.firstb[s] = static_cast<const int64_t*>(at(off_firstb[s]));
   }
   B.nargs1 = at(off_n1);
   B.nargs2 = at(off_n2);
@@ -194,14 +217,21 @@ void bind(bm_batch_s& b, Bound& B, bool dec, const void* const* x, const double*
   B.codes.assign(codes, codes + nf);
 }
 
+void level_launch(const bm_batch_s& b, const Bound& B, int s, bool dec, hipStream_t st) {
+  if (B.ntasks[s] <= 0) return;
+  if (B.blk[s] == 33)
+    launch_wide_batch(b.dtype, dec, B.args[s], B.first[s], B.firstb[s], B.nf[s], B.ntasks[s], B.nblk[s], st);
+  else
+    launch_block_batch(B.blk[s], b.dtype, dec, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+}
+
 void enqueue(bm_batch_s& b, Bound& B, bool dec, hipStream_t st) {
   const int nf = int(b.plans.size());
   launch_prep_batch(B.stages, B.fields, nf, st);
   if (dec) {
     for (int s = 1; s <= b.Lmax; ++s) {
       if (s == 1) launch_block_batch_nest(b.dtype, true, B.nargs1, B.nargs2, B.nfirst, B.nnf, B.nntasks, st);
-      if (B.ntasks[s] > 0)
-        launch_block_batch(B.blk[s], b.dtype, true, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+      level_launch(b, B, s, true, st);
     }
     for (int f = 0; f < nf; ++f)
       decompose_quantize_global(*b.plans[f], B.x[f], static_cast<int32_t*>(const_cast<void*>(B.codes[f])), B.q[f], st);
@@ -210,8 +240,7 @@ void enqueue(bm_batch_s& b, Bound& B, bool dec, hipStream_t st) {
       dequantize_recompose_global(*b.plans[f], static_cast<const int32_t*>(B.codes[f]), B.q[f],
                                   const_cast<void*>(B.x[f]), st);
     for (int s = b.Lmax; s >= 1; --s) {
-      if (B.ntasks[s] > 0)
-        launch_block_batch(B.blk[s], b.dtype, false, true, B.args[s], B.first[s], B.nf[s], B.ntasks[s], st);
+      level_launch(b, B, s, false, st);
       if (s == 1) launch_block_batch_nest(b.dtype, false, B.nargs1, B.nargs2, B.nfirst, B.nnf, B.nntasks, st);
     }
   }
@@ -266,7 +295,7 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
         c.L = tiles ? 2 : 1;
       } else if (c.L == -1) {
         // the most block levels the logical dims tile without padding (at least 1)
-        if (c.block != 9 && c.block != 17) fail(BM_EINVAL, "L = -1 needs block 9 or 17");
+        if (c.block != 9 && c.block != 17 && c.block != 33) fail(BM_EINVAL, "L = -1 needs block 9, 17 or 33");
         int64_t d[3] = {1, 1, 1};
         if (c.ndim < 1 || c.ndim > 3) fail(BM_EINVAL, "ndim must be 1, 2 or 3");
         for (int a = 0; a < c.ndim; ++a) d[3 - c.ndim + a] = c.dims[a];
@@ -279,8 +308,6 @@ bm_batch_s* batch_build(int nfields, const bm_config* cfgs) {
         };
         while (c.L < 24 && tiles(c.L)) ++c.L;
       }
-      if (c.L > 0 && c.block == 33)
-        fail(BM_EUNSUPPORTED, "batched block levels take b = 9 or 17 (a 33^3 block needs several launches)");
       b->plans.push_back(bm_plan_build(&c));
       b->Lmax = std::max(b->Lmax, b->plans.back()->L);
     }

@@ -328,6 +328,16 @@ void block_nest_args(const bm_plan_s& p, bool dec, const View3& src, void* x, in
                      void* out1, void* out2);
 void launch_block_batch_nest(int dtype, bool dec, const void* a1, const void* a2, const int64_t* first, int nf,
                              int64_t ntasks, hipStream_t st);
+// 33-node block levels of many fields: each field's arguments
+// (wide_args_size bytes; src / first as for the decomposition, out / first =
+// the caller's output for the recomposition), then the column, coarse (and,
+// recomposing, interpolation) steps as persistent launches over all fields'
+// block halves (first_half: 2 x blocks per field) and blocks (first_block)
+size_t wide_args_size(const bm_plan_s& p);
+void wide_batch_args(const bm_plan_s& p, int s, bool dec, const View3& src, bool first, void* out, int32_t* codes,
+                     const QPrep* q, void* dst);
+void launch_wide_batch(int dtype, bool dec, const void* args, const int64_t* first_half, const int64_t* first_block,
+                       int nf, int64_t nhalf, int64_t nblock, hipStream_t st);
 
 // quantization
 void tolmap_from_boxes(bm_plan_s& p, const double* boxes, int nbox, double background, double* block_tol,

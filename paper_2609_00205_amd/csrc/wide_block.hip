@@ -20,6 +20,9 @@
 // node (the y-pass result) through HBM twice more, and the recomposition
 // reads its coefficients twice.
 
+#include <algorithm>
+#include <cstring>
+
 #include "block.h"
 #include "internal.h"
 
@@ -82,13 +85,11 @@ __device__ inline void load_coeff_column(const WideArgs<T>& a, uint32_t blk, int
   }
 }
 
-// Column kernel: one workgroup per block half g (block g/2, half g%2).
+// Column step: block half g (block g/2, half g%2) with NT1 lanes; lds holds
+// MI * B * HW values (decomposition: the half's coarse nodes UC[MC][MC][HC],
+// then T1[MI][B][HW]).
 template <typename T, bool DEC, bool Q>
-__global__ __launch_bounds__(NT1) void k_wide_columns(WideArgs<T> a) {
-  // decomposition: the half's coarse nodes UC[MC][MC][HC]; then T1[MI][B][HW]
-  __shared__ T lds[MI * B * HW];
-  const int64_t g = xcd_group(blockIdx.x, a.per1);
-  if (g >= 2 * int64_t(a.nblocks)) return;
+__device__ __attribute__((always_inline)) inline void wide_columns(const WideArgs<T>& a, int64_t g, T* lds) {
   const uint32_t blk = uint32_t(g >> 1);
   const int h = int(g & 1);
   const int tid = threadIdx.x;
@@ -211,14 +212,20 @@ __global__ __launch_bounds__(NT1) void k_wide_columns(WideArgs<T> a) {
   }
 }
 
-// Coarse kernel: one workgroup per block.  x pass, then the interior coarse
-// nodes (and, at the last level of a quantized hierarchy, the codes of all of
-// the block's coarse nodes).
 template <typename T, bool DEC, bool Q>
-__global__ __launch_bounds__(NT2) void k_wide_coarse(WideArgs<T> a) {
-  __shared__ T S[T2B];   // T2[MI][MI][B]; the x pass leaves Z[J][I][K] in the first MI of each row
-  const int64_t g = xcd_group(blockIdx.x, a.per2);
-  if (g >= int64_t(a.nblocks)) return;
+__global__ __launch_bounds__(NT1) void k_wide_columns(WideArgs<T> a) {
+  __shared__ T lds[MI * B * HW];
+  const int64_t g = xcd_group(blockIdx.x, a.per1);
+  if (g >= 2 * int64_t(a.nblocks)) return;
+  wide_columns<T, DEC, Q>(a, g, lds);
+}
+
+// Coarse step: block g with NT2 lanes.  x pass, then the interior coarse
+// nodes (and, at the last level of a quantized hierarchy, the codes of all of
+// the block's coarse nodes).  S holds T2B values: T2[MI][MI][B]; the x pass
+// leaves Z[J][I][K] in the first MI of each row.
+template <typename T, bool DEC, bool Q>
+__device__ __attribute__((always_inline)) inline void wide_coarse(const WideArgs<T>& a, int64_t g, T* S) {
   const uint32_t blk = uint32_t(g);
   const int tid = threadIdx.x;
   const T* src = a.t2 + int64_t(blk) * T2B;
@@ -269,12 +276,19 @@ __global__ __launch_bounds__(NT2) void k_wide_coarse(WideArgs<T> a) {
   if (DEC && bad) atomicOr(reinterpret_cast<unsigned long long*>(a.flag), (unsigned long long)bad);
 }
 
-// Interpolation kernel of the recomposition: one workgroup per block half.
+template <typename T, bool DEC, bool Q>
+__global__ __launch_bounds__(NT2) void k_wide_coarse(WideArgs<T> a) {
+  __shared__ T S[T2B];
+  const int64_t g = xcd_group(blockIdx.x, a.per2);
+  if (g >= int64_t(a.nblocks)) return;
+  wide_coarse<T, DEC, Q>(a, g, S);
+}
+
+// Interpolation step of the recomposition: block half g with NT1 lanes; UC
+// holds the half's coarse values [MC][MC][HC].  Lanes leave early only after
+// the step's one barrier.
 template <typename T, bool Q>
-__global__ __launch_bounds__(NT1) void k_wide_interp(WideArgs<T> a) {
-  __shared__ T UC[MC * MC * HC];
-  const int64_t g = xcd_group(blockIdx.x, a.per1);
-  if (g >= 2 * int64_t(a.nblocks)) return;
+__device__ __attribute__((always_inline)) inline void wide_interp(const WideArgs<T>& a, int64_t g, T* UC) {
   const uint32_t blk = uint32_t(g >> 1);
   const int h = int(g & 1);
   const int tid = threadIdx.x;
@@ -322,6 +336,73 @@ __global__ __launch_bounds__(NT1) void k_wide_interp(WideArgs<T> a) {
     }
     if ((z < B - 1 || lastz) && oz + z < a.on[0]) dst[z * a.os[0]] = u;
   }
+}
+
+template <typename T, bool Q>
+__global__ __launch_bounds__(NT1) void k_wide_interp(WideArgs<T> a) {
+  __shared__ T UC[MC * MC * HC];
+  const int64_t g = xcd_group(blockIdx.x, a.per1);
+  if (g >= 2 * int64_t(a.nblocks)) return;
+  wide_interp<T, Q>(a, g, UC);
+}
+
+// Many fields in one persistent launch per step: task k is half (columns,
+// interp) or block (coarse) k - first[f] of field f; the field index is
+// uniform over the workgroup and its record is read with scalar loads.
+__device__ inline int wide_field_of(const int64_t* first, int nf, int64_t k) {
+  int lo = 0, hi = nf;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, bool DEC, bool Q>
+__global__ __launch_bounds__(NT1) void k_batch_wide_columns(const WideArgs<T>* __restrict__ fa,
+                                                            const int64_t* __restrict__ first, int nf,
+                                                            int64_t ntasks) {
+  __shared__ T lds[MI * B * HW];
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = __builtin_amdgcn_readfirstlane(wide_field_of(first, nf, k));
+    wide_columns<T, DEC, Q>(fa[f], k - first[f], lds);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool DEC, bool Q>
+__global__ __launch_bounds__(NT2) void k_batch_wide_coarse(const WideArgs<T>* __restrict__ fa,
+                                                           const int64_t* __restrict__ first, int nf, int64_t ntasks) {
+  __shared__ T S[T2B];
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = __builtin_amdgcn_readfirstlane(wide_field_of(first, nf, k));
+    wide_coarse<T, DEC, Q>(fa[f], k - first[f], S);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool Q>
+__global__ __launch_bounds__(NT1) void k_batch_wide_interp(const WideArgs<T>* __restrict__ fa,
+                                                           const int64_t* __restrict__ first, int nf, int64_t ntasks) {
+  __shared__ T UC[MC * MC * HC];
+  for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
+    const int f = __builtin_amdgcn_readfirstlane(wide_field_of(first, nf, k));
+    wide_interp<T, Q>(fa[f], k - first[f], UC);
+    __syncthreads();
+  }
+}
+
+template <typename K>
+unsigned wide_resident_grid(K kernel, int nt, int64_t ntasks) {
+  int dev = 0, per_cu = 0, cus = 0;
+  BM_HIP(hipGetDevice(&dev));
+  BM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0));
+  BM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t g = std::max<int64_t>(1, int64_t(per_cu) * cus);
+  return unsigned(std::min<int64_t>(g, ntasks));
 }
 
 template <typename T>
@@ -400,7 +481,72 @@ void launch_wide_rec(const bm_plan_s& p, int s, const void* coeff, void* cin, vo
   BM_HIP(hipGetLastError());
 }
 
+template <typename T>
+void wide_batch_args_t(const bm_plan_s& p, int s, bool dec, const View3& src, bool first, void* out, int32_t* codes,
+                       const QPrep* q, void* dst) {
+  WideArgs<T> a = wide_args<T>(p, s, nullptr, codes, p.ws.grid[s], q);
+  if (dec) {
+    a.src = static_cast<const T*>(src.ptr);
+    for (int k = 0; k < 3; ++k) {
+      a.sn[k] = src.n[k];
+      a.ss[k] = src.s[k];
+    }
+    a.first = first;
+    a.zero_pad = p.cfg.pad_mode == 1;
+  } else {
+    a.out = static_cast<T*>(out);
+    const int64_t* on = first ? p.dims : p.lv[s - 1].n;
+    for (int k = 0; k < 3; ++k) a.on[k] = on[k];
+    a.os[0] = on[1] * on[2];
+    a.os[1] = on[2];
+    a.os[2] = 1;
+  }
+  std::memcpy(dst, &a, sizeof(a));
+}
+
+template <typename T>
+void launch_wide_batch_t(bool dec, const void* args, const int64_t* first_half, const int64_t* first_block, int nf,
+                         int64_t nhalf, int64_t nblock, hipStream_t st) {
+  if (nblock <= 0) return;
+  const auto* fa = static_cast<const WideArgs<T>*>(args);
+  if (dec) {
+    auto kc = k_batch_wide_columns<T, true, true>;
+    auto ko = k_batch_wide_coarse<T, true, true>;
+    hipLaunchKernelGGL(kc, dim3(wide_resident_grid(kc, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
+    hipLaunchKernelGGL(ko, dim3(wide_resident_grid(ko, NT2, nblock)), dim3(NT2), 0, st, fa, first_block, nf, nblock);
+  } else {
+    auto kc = k_batch_wide_columns<T, false, true>;
+    auto ko = k_batch_wide_coarse<T, false, true>;
+    auto ki = k_batch_wide_interp<T, true>;
+    hipLaunchKernelGGL(kc, dim3(wide_resident_grid(kc, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
+    hipLaunchKernelGGL(ko, dim3(wide_resident_grid(ko, NT2, nblock)), dim3(NT2), 0, st, fa, first_block, nf, nblock);
+    hipLaunchKernelGGL(ki, dim3(wide_resident_grid(ki, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
+  }
+  BM_HIP(hipGetLastError());
+}
+
 }  // namespace
+
+size_t wide_args_size(const bm_plan_s& p) {
+  return p.cfg.dtype == BM_F32 ? sizeof(WideArgs<float>) : sizeof(WideArgs<double>);
+}
+
+void wide_batch_args(const bm_plan_s& p, int s, bool dec, const View3& src, bool first, void* out, int32_t* codes,
+                     const QPrep* q, void* dst) {
+  if (p.lv[s - 1].b != B) fail(BM_EINVAL, "not a 33-node block level");
+  if (p.cfg.dtype == BM_F32)
+    wide_batch_args_t<float>(p, s, dec, src, first, out, codes, q, dst);
+  else
+    wide_batch_args_t<double>(p, s, dec, src, first, out, codes, q, dst);
+}
+
+void launch_wide_batch(int dtype, bool dec, const void* args, const int64_t* first_half, const int64_t* first_block,
+                       int nf, int64_t nhalf, int64_t nblock, hipStream_t st) {
+  if (dtype == BM_F32)
+    launch_wide_batch_t<float>(dec, args, first_half, first_block, nf, nhalf, nblock, st);
+  else
+    launch_wide_batch_t<double>(dec, args, first_half, first_block, nf, nhalf, nblock, st);
+}
 
 size_t wide_scratch_elems(const int64_t nb[3]) { return size_t(nb[0] * nb[1] * nb[2]) * T2B; }
 

@@ -53,6 +53,10 @@ CASES = [
     ([(33, 17, 65), (65, 33, 33)], torch.float64, 17, None, 0, True),
     ([(33, 33, 33), (40, 20, 33), (65, 33, 17)], torch.float32, 17, [2, 1, 2], 0, True),   # pairs beside a plain level
     ([(33, 33, 33), (65, 33, 33)], torch.float32, 17, 2, 1, True),                # pairs, then a global level
+    # 33-node blocks: column, coarse (and interpolation) steps over all fields
+    ([(33, 65, 33), (65, 65, 33), (33, 33, 33)], torch.float32, 33, None, 0),
+    ([(65, 33, 33), (33, 33, 65)], torch.float64, 33, 1, 0),
+    ([(33, 33, 65), (65, 33, 33), (40, 30, 50)], torch.float32, 33, 1, 1),       # padded, global level
 ]
 
 
@@ -120,6 +124,7 @@ ORACLE_CASES = [
     ([(33, 33, 33), (65, 33, 33)], torch.float64, 9, 1, 2),          # global levels per field
     ([(33, 17, 65), (65, 33, 33), (17, 33, 17)], torch.float32, 17, None, 0, True),   # nested pairs
     ([(33, 33, 33), (65, 33, 17)], torch.float64, 17, 2, 1, True),
+    ([(33, 65, 33), (65, 33, 33)], torch.float32, 33, None, 0),      # 33-node blocks
 ]
 
 
