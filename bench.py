@@ -177,7 +177,6 @@ def main():
         transform()
     torch.cuda.synchronize()
     print(f"[bench] timing {K} steps", file=sys.stderr, flush=True)
-    plan.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -186,7 +185,18 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / K
+    # per-level phases (and the block kernel's launch time for the roofline)
+    # from the same K steps run again with the library's per-level events on:
+    # the events are diagnostics and stay out of the timed steps above
+    plan.timing(True)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    for _ in range(K):
+        step()
+    e3.record()
+    torch.cuda.synchronize()
     t = plan.timing_get()
+    ms_step_events = e2.elapsed_time(e3) / K
     # the plain transform (no quantization), timed the same way
     plan.timing(True)
     for _ in range(K):
@@ -357,6 +367,7 @@ def main():
                            "flushed_p10": pct(per_fl, 10), "flushed_median": pct(per_fl, 50),
                            "flushed_p90": pct(per_fl, 90)},
         "level1_decompose_GBps": round(in_bytes / (local_ms * 1e-3) / 1e9, 2),
+        "ms_per_step_with_level_events": round(ms_step_events, 4),
         "phases_ms": {"decompose_quantize": round(dec_ms, 4), "dequantize_recompose": round(rec_ms, 4),
                       "decompose_levels": [round(v / K, 4) for v in t["decompose"]],
                       "recompose_levels": [round(v / K, 4) for v in t["recompose"]],
@@ -408,7 +419,6 @@ def run_c1(args):
     for _ in range(args.warmup):
         step()
     K = args.steps
-    plan.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -417,6 +427,11 @@ def run_c1(args):
     e1.record()
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / K
+    # per-level phases from the same steps run again with the level events on
+    plan.timing(True)
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
     t = plan.timing_get()
     plan.timing(False)
     t0 = time.perf_counter()
