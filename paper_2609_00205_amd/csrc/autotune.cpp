@@ -37,10 +37,30 @@ struct PlanGuard {
   }
 };
 
+// pinned host memory for the candidates' Huffman streams, kept across the
+// candidates of one autotune call (grown when a stream needs more)
+struct PinnedStream {
+  uint8_t* p = nullptr;
+  size_t cap = 0;
+  uint8_t* get(size_t n) {
+    if (n > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      BM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), n, hipHostMallocDefault));
+      cap = n;
+    }
+    return p;
+  }
+  ~PinnedStream() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 // one candidate: time (ms) and ratio; status BM_OK, or BM_ERANGE when codes
 // overflow (the container would store the raw data: ratio 1)
 void measure(const bm_config& cfg, const void* x, const double* voxel_tol, int reps, bm_candidate& c,
-             hipStream_t st) {
+             PinnedStream& pin, hipStream_t st) {
   PlanGuard g;
   g.p = bm_plan_build(&cfg);
   bm_plan_s& p = *g.p;
@@ -80,12 +100,15 @@ void measure(const bm_config& cfg, const void* x, const double* voxel_tol, int r
   double coded = raw;
   c.lossless_ms = 0.0;
   if (c.status == BM_OK) {
-    // one encode into host memory gives the coded size and the lossless
-    // stage's time (its work buffers are allocated per encode, as in compress)
-    std::vector<uint8_t> stream;
+    // one encode into pinned host memory gives the coded size and the
+    // lossless stage's time (histogram, code table, chunk sizes, encode, copy
+    // out; its work buffers are allocated per encode, as in compress)
     const auto t0 = std::chrono::steady_clock::now();
-    coded = double(huffman_encode(codes, npad, stream, st)) + 8.0 * double(ntol) + 128.0;
+    HuffmanEncoder enc(codes, npad, st);
+    const size_t bytes = enc.bytes();
+    enc.write(pin.get(bytes), bytes);
     c.lossless_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    coded = double(bytes) + 8.0 * double(ntol) + 128.0;
   }
   c.ratio = raw / std::min(coded, raw);
 }
@@ -98,6 +121,7 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
   if (!budget && !(slack >= 0.0 && slack < 1.0)) fail(BM_EINVAL, "slack must lie in [0, 1)");
   if (budget_ms < 0.0 || !std::isfinite(budget_ms)) fail(BM_EINVAL, "budget must be positive and finite");
   std::vector<bm_candidate> cands;
+  PinnedStream pin;
   int64_t nlog = 1;
   for (int a = 0; a < in.ndim; ++a) nlog *= in.dims[a];
   auto consider = [&](int block, int L, int M, int nested) {
@@ -121,7 +145,7 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
     k.L = L;
     k.M = M;
     k.nested = nested;
-    measure(c, x, voxel_tol, reps, k, st);
+    measure(c, x, voxel_tol, reps, k, pin, st);
     cands.push_back(k);
   };
   for (int M = 1; M <= 6; ++M) consider(0, 0, M, 0);
