@@ -80,6 +80,20 @@ __device__ inline T cell_mean(int dz, int dy, int dx, F rd) {
 // Inf input reaches the coefficient of its own node at some level).
 constexpr unsigned kFlagRange = 1u, kFlagNonFinite = 2u;
 __device__ inline unsigned code_flag(double c) { return isfinite(c) ? kFlagRange : kFlagNonFinite; }
+
+// Persistent launches over many fields: task k belongs to field f with
+// first[f] <= k < first[f+1] (first[] ascending, first[nf] = total).
+__device__ inline int task_field(const int64_t* first, int nf, int64_t k) {
+  int lo = 0, hi = nf;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
 // Host side: BM_ENONFINITE or BM_ERANGE for a non-zero flag word.
 void check_code_flag(int64_t f, const char* what);
 
@@ -184,6 +198,18 @@ template <typename P>
 void plan_alloc(bm_plan_s& p, P** ptr, size_t bytes) {
   BM_HIP(hipMalloc(reinterpret_cast<void**>(ptr), bytes));
   p.dev_bytes += bytes;
+}
+
+// Workgroups of a persistent launch over ntasks tasks: as many as stay
+// resident on the device (at least 1, at most ntasks).
+template <typename K>
+unsigned resident_grid(K kernel, int nt, int64_t ntasks) {
+  int dev = 0, per_cu = 0, cus = 0;
+  BM_HIP(hipGetDevice(&dev));
+  BM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0));
+  BM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t g = per_cu * int64_t(cus) > 1 ? per_cu * int64_t(cus) : 1;
+  return unsigned(g < ntasks ? g : ntasks);
 }
 
 int64_t padded_length(int64_t n, int b, int L, int M, bool nested = false);

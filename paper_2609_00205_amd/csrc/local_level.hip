@@ -550,19 +550,8 @@ __global__ __launch_bounds__((Geo<17, sizeof(T), false>::NT)) void k_local_recom
 }
 
 // Many fields in one persistent launch: task k is block group k - first[f]
-// of field f (first[] ascending, first[nf] = total); workgroups stride over
-// the tasks.
-__device__ inline int field_of(const int64_t* first, int nf, int64_t k) {
-  int lo = 0, hi = nf;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= k)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
+// of field f (first[] ascending, first[nf] = total, task_field); workgroups
+// stride over the tasks.
 
 // (no wave target here: the per-field arguments come from memory and the
 // extra registers are cheaper than spills.  The field index is the same for
@@ -576,7 +565,7 @@ __global__ __launch_bounds__((Geo<B, sizeof(T)>::NT)) void k_batch_decompose(
     const DecArgs<T>* __restrict__ fa, const int64_t* __restrict__ first, int nf, int64_t ntasks) {
   __shared__ __attribute__((aligned(16))) T lds[Geo<B, sizeof(T)>::NB * Geo<B>::DEC_LDS];   // FP64 scratch inside
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     decompose_group<T, B, Q>(fa[f], k - first[f], lds);
     __syncthreads();
   }
@@ -588,7 +577,7 @@ __global__ __launch_bounds__((Geo<B, sizeof(T), false>::NT)) void k_batch_recomp
                                                                               int64_t ntasks) {
   __shared__ T lds[Geo<B, sizeof(T), false>::NB * Geo<B>::REC_LDS];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     recompose_group<T, B, Q>(fa[f], k - first[f], lds);
     __syncthreads();
   }
@@ -606,7 +595,7 @@ __global__ __launch_bounds__((Geo<17, sizeof(T)>::NT)) void k_batch_decompose_ne
   constexpr int NB = Geo<17, sizeof(T)>::NB;
   __shared__ __attribute__((aligned(16))) T lds[NB * Geo<17>::DEC_LDS];   // FP64 scratch inside
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     const int64_t g = k - first[f];
     decompose_group<T, 17, Q>(f1[f], g, lds);
     __syncthreads();
@@ -622,7 +611,7 @@ __global__ __launch_bounds__((Geo<17, sizeof(T), false>::NT)) void k_batch_recom
   constexpr int NB = Geo<17, sizeof(T), false>::NB;
   __shared__ T lds[NB * Geo<17>::REC_LDS];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     const int64_t g = k - first[f];
     recompose_group<T, 9, Q, NB, 1>(f2[f], g, lds);
     __syncthreads();
@@ -747,16 +736,6 @@ void launch_rec(const bm_plan_s& p, int s, const void* coeff, const void* cin, v
   BM_HIP(hipGetLastError());
 }
 
-// workgroups of a persistent batched launch: as many as stay resident
-template <typename K>
-unsigned resident_grid(K kernel, int nt, int64_t ntasks) {
-  int dev = 0, per_cu = 0, cus = 0;
-  BM_HIP(hipGetDevice(&dev));
-  BM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0));
-  BM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t g = std::max<int64_t>(1, int64_t(per_cu) * cus);
-  return unsigned(std::min<int64_t>(g, ntasks));
-}
 
 template <typename T, int B>
 void launch_batch(bool dec, bool quant, const void* args, const int64_t* first, int nf, int64_t ntasks,

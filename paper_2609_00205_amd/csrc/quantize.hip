@@ -577,22 +577,10 @@ void quant_keep(bm_plan_s& p, const double* block_tol, hipStream_t st) {
 
 namespace {
 
-__device__ inline int field_of(const int64_t* first, int nf, int64_t k) {
-  int lo = 0, hi = nf;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= k)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // Eq. 2 from level s to level s+1 (s 1-based) for every field that has it
 __global__ void k_batch_propagate(const PrepField* F, const int64_t* first, int nf, int64_t ntot, int s) {
   for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT) {
-    const int f = field_of(first, nf, k);
+    const int f = task_field(first, nf, k);
     const PrepField& P = F[f];
     const int64_t i = k - first[f];
     const int64_t* nb = P.nb[s - 1];
@@ -663,7 +651,7 @@ __global__ void k_batch_tables(const PrepField* F, const int64_t* first, int nf,
     return;
   }
   for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < ntot; k += int64_t(gridDim.x) * NT) {
-    const int f = field_of(first, nf, k);
+    const int f = task_field(first, nf, k);
     table_task(F[f], s, uint32_t(k - first[f]));
   }
 }

@@ -349,17 +349,6 @@ __global__ __launch_bounds__(NT1) void k_wide_interp(WideArgs<T> a) {
 // Many fields in one persistent launch per step: task k is half (columns,
 // interp) or block (coarse) k - first[f] of field f; the field index is
 // uniform over the workgroup and its record is read with scalar loads.
-__device__ inline int wide_field_of(const int64_t* first, int nf, int64_t k) {
-  int lo = 0, hi = nf;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= k)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 template <typename T, bool DEC, bool Q>
 __global__ __launch_bounds__(NT1) void k_batch_wide_columns(const WideArgs<T>* __restrict__ fa,
@@ -367,7 +356,7 @@ __global__ __launch_bounds__(NT1) void k_batch_wide_columns(const WideArgs<T>* _
                                                             int64_t ntasks) {
   __shared__ T lds[MI * B * HW];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(wide_field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     wide_columns<T, DEC, Q>(fa[f], k - first[f], lds);
     __syncthreads();
   }
@@ -378,7 +367,7 @@ __global__ __launch_bounds__(NT2) void k_batch_wide_coarse(const WideArgs<T>* __
                                                            const int64_t* __restrict__ first, int nf, int64_t ntasks) {
   __shared__ T S[T2B];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(wide_field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     wide_coarse<T, DEC, Q>(fa[f], k - first[f], S);
     __syncthreads();
   }
@@ -389,21 +378,12 @@ __global__ __launch_bounds__(NT1) void k_batch_wide_interp(const WideArgs<T>* __
                                                            const int64_t* __restrict__ first, int nf, int64_t ntasks) {
   __shared__ T UC[MC * MC * HC];
   for (int64_t k = blockIdx.x; k < ntasks; k += gridDim.x) {
-    const int f = __builtin_amdgcn_readfirstlane(wide_field_of(first, nf, k));
+    const int f = __builtin_amdgcn_readfirstlane(task_field(first, nf, k));
     wide_interp<T, Q>(fa[f], k - first[f], UC);
     __syncthreads();
   }
 }
 
-template <typename K>
-unsigned wide_resident_grid(K kernel, int nt, int64_t ntasks) {
-  int dev = 0, per_cu = 0, cus = 0;
-  BM_HIP(hipGetDevice(&dev));
-  BM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0));
-  BM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t g = std::max<int64_t>(1, int64_t(per_cu) * cus);
-  return unsigned(std::min<int64_t>(g, ntasks));
-}
 
 template <typename T>
 WideArgs<T> wide_args(const bm_plan_s& p, int s, void* coeff, int32_t* codes, void* cgrid, const QPrep* q) {
@@ -512,15 +492,15 @@ void launch_wide_batch_t(bool dec, const void* args, const int64_t* first_half, 
   if (dec) {
     auto kc = k_batch_wide_columns<T, true, true>;
     auto ko = k_batch_wide_coarse<T, true, true>;
-    hipLaunchKernelGGL(kc, dim3(wide_resident_grid(kc, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
-    hipLaunchKernelGGL(ko, dim3(wide_resident_grid(ko, NT2, nblock)), dim3(NT2), 0, st, fa, first_block, nf, nblock);
+    hipLaunchKernelGGL(kc, dim3(resident_grid(kc, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
+    hipLaunchKernelGGL(ko, dim3(resident_grid(ko, NT2, nblock)), dim3(NT2), 0, st, fa, first_block, nf, nblock);
   } else {
     auto kc = k_batch_wide_columns<T, false, true>;
     auto ko = k_batch_wide_coarse<T, false, true>;
     auto ki = k_batch_wide_interp<T, true>;
-    hipLaunchKernelGGL(kc, dim3(wide_resident_grid(kc, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
-    hipLaunchKernelGGL(ko, dim3(wide_resident_grid(ko, NT2, nblock)), dim3(NT2), 0, st, fa, first_block, nf, nblock);
-    hipLaunchKernelGGL(ki, dim3(wide_resident_grid(ki, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
+    hipLaunchKernelGGL(kc, dim3(resident_grid(kc, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
+    hipLaunchKernelGGL(ko, dim3(resident_grid(ko, NT2, nblock)), dim3(NT2), 0, st, fa, first_block, nf, nblock);
+    hipLaunchKernelGGL(ki, dim3(resident_grid(ki, NT1, nhalf)), dim3(NT1), 0, st, fa, first_half, nf, nhalf);
   }
   BM_HIP(hipGetLastError());
 }
