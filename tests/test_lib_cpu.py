@@ -80,6 +80,10 @@ def test_null_plan_calls(lib):
     assert lib.bm_decompose(None, None, None, None) == -1
     assert lib.bm_quantize_roi(None, None, None, None, None, None) == -1
     assert lib.bm_plan_destroy(None) == 0
+    n = C.c_size_t(7)
+    assert lib.bm_workspace_size(None, C.byref(n)) == -1 and n.value == 7
+    assert lib.bm_compress_write(None, None, 0, C.byref(n)) == -1
+    assert lib.bm_huffman_write(None, None, 0, C.byref(n)) == -1
 
 
 def test_long_global_axis_rejected_at_plan_creation(lib):
