@@ -24,9 +24,13 @@
  *   - Device pointers are HIP device memory owned by the caller; host
  *     pointers are ordinary host memory owned by the caller.  The library
  *     never frees caller memory.
- *   - A plan owns its constant tables and device workspace.  It is
- *     immutable after creation; calls on one plan must not overlap in time
- *     on different streams (they share the workspace).
+ *   - A plan owns its constant tables and device workspace, and keeps
+ *     state between calls: buffers that first calls allocate
+ *     (bm_workspace_size), a kept map's quantizer tables
+ *     (bm_quant_prepare), a planned container (bm_compress_plan).  Calls on
+ *     one plan must not overlap in time, from one thread on several streams
+ *     or from several threads (they share the workspace); different plans
+ *     are independent.
  *   - Calls are stream-ordered and asynchronous unless documented as
  *     synchronous.  Passing stream 0 uses the null stream.
  *   - Every call returns a bm_status.  No C++ exception crosses the ABI.
