@@ -442,6 +442,12 @@ __device__ __attribute__((always_inline)) inline void recompose_group(const RecA
 #pragma unroll
         for (int j = 0; j < MC; ++j) ce[j] = ccol[j * a.cpl];
       }
+      // c waits in UC through the correction passes (which do not touch UC)
+      // instead of in registers; a nested finer level finds it there already
+      if (MODE != 2) {
+#pragma unroll
+        for (int j = 0; j < MC; ++j) UC[(j * MC + (y >> 1)) * MC + (x >> 1)] = ce[j];
+      }
 #pragma unroll
       for (int j = 0; j < MC; ++j) w[2 * j] = T(0);
     }
@@ -455,15 +461,14 @@ __device__ __attribute__((always_inline)) inline void recompose_group(const RecA
   __syncthreads();
   if (act) pass_x<T, B>(T2, Z, tb);
   __syncthreads();
-  if (act && ecol) {
-    // u_C = c - z on this column's coarse nodes
-    const bool icol = y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3;
+  if (act && ecol && y >= 2 && y <= B - 3 && x >= 2 && x <= B - 3) {
+    // u_C = c - z on this column's interior coarse nodes (z = 0 on the block
+    // surface, where u_C = c already)
     const int I = (y - 2) >> 1, K = (x - 2) >> 1;
 #pragma unroll
-    for (int j = 0; j < MC; ++j) {
-      T u = ce[j];
-      if (icol && j >= 1 && j <= MC - 2) u -= Z[((j - 1) * MI + I) * MI + K];
-      UC[(j * MC + (y >> 1)) * MC + (x >> 1)] = u;
+    for (int j = 1; j <= MC - 2; ++j) {
+      T& u = UC[(j * MC + (y >> 1)) * MC + (x >> 1)];
+      u = u - Z[((j - 1) * MI + I) * MI + K];
     }
   }
   __syncthreads();
