@@ -1115,7 +1115,8 @@ def run_eq1(args):
     global levels and Huffman stages by lines, quantization by
     max(slope N, T_lat)); then every admissible (L, M) of the 512^3 workload
     is predicted (bm_model_predict) and measured (fused decompose + quantize,
-    HIP events; the lossless stage by host wall time of the Huffman coder),
+    HIP events; the lossless stage by the coder's own stage timers in a
+    compress, the four stages the model fits),
     and Algorithm 1 picks (L, M) from the predictions alone under a range of
     time budgets (bm_select_levels)."""
     import numpy as np
@@ -1153,10 +1154,19 @@ def run_eq1(args):
         e1.record()
         torch.cuda.synchronize()
         measured = e0.elapsed_time(e1) / reps
-        api.huffman_encode(codes)
-        t1 = time.perf_counter()
-        api.huffman_encode(codes)
-        lossless = (time.perf_counter() - t1) * 1e3
+        # the lossless stage as the model splits it: histogram, code table,
+        # chunk sizes + encode, copy-out + CRC, from the library's own stage
+        # timers during a container compress (warm-up first)
+        p.compress(xd, bt)
+        nbytes = len(p.compress(xd, bt))
+        lt = api.lossless_times()
+        stages = {"hist": lt["enc_hist_ms"], "table": lt["enc_table_ms"],
+                  "sizes_encode": lt["enc_sizes_ms"] + lt["enc_encode_ms"],
+                  "copy_crc": lt["enc_copy_ms"] + lt["enc_crc_ms"]}
+        lossless = sum(stages.values())
+        ncodes = int(np.prod(p.coeff_shape))
+        pstages = {k: model["huf_a_ms"][i] + model["huf_b_ms"][i] * ncodes
+                   for i, k in enumerate(("hist", "table", "sizes_encode", "copy_crc"))}
         pred = api.model_predict(model, shape, L, M)
         pdq = pred["decompose"] + pred["quantize"]
         err = abs(pdq - measured) / measured
@@ -1164,6 +1174,8 @@ def run_eq1(args):
         rows.append({"L": L, "M": M, "predicted_decompose_quantize_ms": round(pdq, 4),
                      "measured_decompose_quantize_ms": round(measured, 4), "error": round(err, 3),
                      "predicted_lossless_ms": round(pred["lossless"], 3), "measured_lossless_ms": round(lossless, 3),
+                     "lossless_stages_ms": {k: [round(pstages[k], 3), round(stages[k], 3)] for k in stages},
+                     "stream_bits_per_code": round(8.0 * nbytes / ncodes, 2),
                      "predicted_total_ms": round(pred["total"], 3)})
         print(f"[bench] L={L} M={M}: predicted {pdq:.4f} ms, measured {measured:.4f} ms; lossless predicted "
               f"{pred['lossless']:.2f} ms, measured {lossless:.2f} ms", file=sys.stderr, flush=True)
