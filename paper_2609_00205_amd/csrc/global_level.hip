@@ -17,6 +17,7 @@
 // by a lane-local pass and a 64-lane scan of affine maps with wave shuffles.
 
 #include <type_traits>
+#include <utility>
 
 #include "internal.h"
 #include "line_solve.h"
@@ -583,6 +584,177 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   BM_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------- plane pass
+
+// K along x, then along y, for every z-plane of a level grid in one launch.
+// A workgroup stages its plane in LDS (dequantized, coarse nodes zeroed on
+// request), restricts and solves its rows along x into a second LDS plane
+// (in place when the lines hold the restriction already), then restricts
+// and solves that plane's columns along y in place, and stores the m1 x m2
+// result.  The arithmetic is the line passes' own (same restriction rows,
+// same 16-lane solves), so the result equals theirs bit for bit; the plane
+// pass only saves the launch and the round trip of the x pass's result.
+// It is used where both planes fit a workgroup's LDS and both axes take the
+// same row layout Q.
+constexpr int kPlaneNT = 1024;
+constexpr int kPlaneLds = 152 * 1024;
+
+template <typename T>
+struct PlaneArgs {
+  const T* in;
+  const int32_t* qin;    // optional: codes (same strides), times *qdel
+  const double* qdel;
+  int64_t is[3];         // input strides
+  int n1, n2;            // plane dims (y, x)
+  int m1, m2;            // result dims
+  FastDiv fn2;           // plane index -> (y, x)
+  int mask;              // zero the level's coarse nodes on load
+  int cm[3];             // coarsening flags
+  int solve_only;        // lines already hold 3 P^T M u: solve only (n = m)
+  int sr, sp;            // LDS row strides of the staged plane and of the x result
+  const double* inv_x;   // reciprocal pivots along x (m2) and y (m1)
+  const double* inv_y;
+  T* out;                // dense [planes][m1][m2]
+};
+
+// 3 (P^T M v)_J of a line of nl values read by v(i): interior rows
+// {1/12, 1/2, 5/6, 1/2, 1/12}, the natural end rows {5/12, 1/2, 1/12}
+template <typename T, typename V>
+__device__ inline T restrict_row(int J, int nl, int m, V v) {
+  const int c = 2 * J;
+  T r;
+  if (J == 0)
+    r = T(5.0 / 12.0) * v(0) + T(0.5) * v(1) + T(1.0 / 12.0) * v(2);
+  else if (J == m - 1)
+    r = T(1.0 / 12.0) * v(nl - 3) + T(0.5) * v(nl - 2) + T(5.0 / 12.0) * v(nl - 1);
+  else
+    r = T(1.0 / 12.0) * (v(c - 2) + v(c + 2)) + T(0.5) * (v(c - 1) + v(c + 1)) + T(5.0 / 6.0) * v(c);
+  return T(3) * r;
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(kPlaneNT) void k_plane_pass(PlaneArgs<T> a) {
+  __shared__ __align__(16) unsigned char smem[kPlaneLds];
+  const int n1 = a.n1, n2 = a.n2, m1 = a.m1, m2 = a.m2, sr = a.sr, sp = a.sp;
+  T* px = reinterpret_cast<T*>(smem);                 // [m2] pivots along x
+  T* py = px + m2;                                    // [m1] pivots along y
+  T* R = py + m1;                                     // [n1][sr] the staged plane
+  T* P = a.solve_only ? R : R + int64_t(n1) * sr;     // [n1][sp] its rows solved along x
+  const int tid = threadIdx.x;
+  const int64_t zb = int64_t(blockIdx.x) * a.is[0];
+  const bool zc = !(a.cm[0] && (blockIdx.x & 1));     // even z along a coarsening z axis
+  const double qd = a.qin ? *a.qdel : 0.0;
+  auto stage = [&](const auto* src) {
+    using Rt = std::remove_const_t<std::remove_pointer_t<decltype(src)>>;
+    const int tot = n1 * n2;
+    for (int i0 = tid; i0 < tot; i0 += kU * kPlaneNT) {
+      Rt v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kPlaneNT;
+        if (i < tot) {
+          const int y = int(a.fn2.div(uint32_t(i))), x = i - y * n2;
+          v[u] = src[zb + int64_t(y) * a.is[1] + int64_t(x) * a.is[2]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kPlaneNT;
+        if (i < tot) {
+          const int y = int(a.fn2.div(uint32_t(i))), x = i - y * n2;
+          const bool coarse = a.mask && zc && !(a.cm[1] && (y & 1)) && !(a.cm[2] && (x & 1));
+          T w;
+          if constexpr (std::is_same_v<Rt, int32_t>)
+            w = T(mul_rn(double(v[u]), qd));
+          else
+            w = v[u];
+          R[y * sr + x] = coarse ? T(0) : w;
+        }
+      }
+    }
+  };
+  for (int k = tid; k < m2; k += kPlaneNT) px[k] = T(a.inv_x[k]);
+  for (int k = tid; k < m1; k += kPlaneNT) py[k] = T(a.inv_y[k]);
+  if (a.qin)
+    stage(a.qin);
+  else
+    stage(a.in);
+  __syncthreads();
+  // rows along x: R -> P (in place when solving only)
+  solve_lines<T, kPlaneNT, Q>(
+      m2, px, n1, tid,
+      [&](int w, int J) {
+        const T* row = R + w * sr;
+        if (a.solve_only) return row[J];
+        return restrict_row<T>(J, n2, m2, [&](int i) { return row[i]; });
+      },
+      [&](int w, int J, T v) { P[w * sp + J] = v; });
+  __syncthreads();
+  // columns along y, in place in P (a column is read whole before it is written)
+  solve_lines<T, kPlaneNT, Q>(
+      m1, py, m2, tid,
+      [&](int w, int J) {
+        const T* col = P + w;
+        if (a.solve_only) return col[J * sp];
+        return restrict_row<T>(J, n1, m1, [&](int i) { return col[i * sp]; });
+      },
+      [&](int w, int J, T v) { P[J * sp + w] = v; });
+  __syncthreads();
+  T* dst = a.out + int64_t(blockIdx.x) * m1 * m2;
+  for (int i = tid; i < m1 * m2; i += kPlaneNT) {
+    const int J1 = i / m2, J2 = i - J1 * m2;
+    dst[i] = P[J1 * sp + J2];
+  }
+}
+
+// K_y K_x of every z-plane of `in` into the dense array out (dims n0, m1,
+// m2) with one plane pass; false (nothing launched) where the planes do not
+// fit a workgroup's LDS or the two axes take different row layouts.
+template <typename T>
+bool launch_plane(const bm_plan_s& p, int s, const View3& in, bool mask, void* out, const int32_t* qin,
+                  const double* qdel, hipStream_t st, bool solve_only = false) {
+  const Level& L = p.lv[s - 1];
+  if (!L.coarsen[1] || !L.coarsen[2]) return false;
+  const int64_t n1 = in.n[1], n2 = in.n[2], m1 = L.m[1], m2 = L.m[2];
+  if (solve_only ? (n1 != m1 || n2 != m2) : (m1 != (n1 + 1) / 2 || m2 != (n2 + 1) / 2 || n1 < 3 || n2 < 3))
+    return false;
+  const int q = row_q_for(m2);
+  if (q != row_q_for(m1) || (q != 3 && q != 5 && q != 9 && q != 11)) return false;
+  const int64_t sr = n2 | 1, sp = solve_only ? sr : (m2 | 1);
+  const int64_t elems = m1 + m2 + n1 * sr + (solve_only ? 0 : n1 * sp);
+  if (elems * int64_t(sizeof(T)) > kPlaneLds) return false;
+  if (in.n[0] >= (int64_t(1) << 31)) return false;
+  PlaneArgs<T> a{};
+  a.in = static_cast<const T*>(in.ptr);
+  a.qin = qin;
+  a.qdel = qdel;
+  for (int k = 0; k < 3; ++k) {
+    a.is[k] = in.s[k];
+    a.cm[k] = L.coarsen[k] ? 1 : 0;
+  }
+  a.n1 = int(n1);
+  a.n2 = int(n2);
+  a.m1 = int(m1);
+  a.m2 = int(m2);
+  a.fn2 = FastDiv(uint32_t(n2));
+  a.mask = mask ? 1 : 0;
+  a.solve_only = solve_only ? 1 : 0;
+  a.sr = int(sr);
+  a.sp = int(sp);
+  a.inv_x = L.d_inv[2];
+  a.inv_y = L.d_inv[1];
+  a.out = static_cast<T*>(out);
+  const dim3 g{unsigned(in.n[0])}, b{unsigned(kPlaneNT)};
+  switch (q) {
+    case 3: hipLaunchKernelGGL((k_plane_pass<T, 3>), g, b, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_plane_pass<T, 5>), g, b, 0, st, a); break;
+    case 9: hipLaunchKernelGGL((k_plane_pass<T, 9>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_plane_pass<T, 11>), g, b, 0, st, a); break;
+  }
+  BM_HIP(hipGetLastError());
+  return true;
+}
+
 // The first global level's load vector when the last block level is fused
 // with it: every block left partial sums, over its own coarse nodes, at the
 // H^3 coarse nodes of the next level inside it; node c along an axis lies in
@@ -794,11 +966,23 @@ void pad_input(const bm_plan_s& p, const void* x, void* dst, bool zero, hipStrea
 
 // ------------------------------------------------------------- drivers
 
+static bool plane_pass(const bm_plan_s& p, int s, const View3& in, bool mask, void* out, const int32_t* qin,
+                       const double* qdel, hipStream_t st) {
+  if (p.cfg.dtype == BM_F32) return launch_plane<float>(p, s, in, mask, out, qin, qdel, st);
+  return launch_plane<double>(p, s, in, mask, out, qin, qdel, st);
+}
+
 // coarse = K_z K_y K_x (in), applied as line passes over the axes that
 // coarsen; intermediate results go through the plan's temporaries.
 static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const void* base, hipStream_t st,
                      const int32_t* qin = nullptr, const double* qdel = nullptr) {
   const Level& L = p.lv[s - 1];
+  // x and y in one plane pass where the planes fit, then z
+  if (L.coarsen[0] && plane_pass(p, s, in, mask, p.ws.t1, qin, qdel, st)) {
+    const int64_t on[3] = {in.n[0], L.m[1], L.m[2]};
+    line_pass_q(p, s, 0, dense_view(p.ws.t1, on), nullptr, out, base, nullptr, qdel, st);
+    return;
+  }
   int axes[3], na = 0;
   for (int a : {2, 1, 0})
     if (L.coarsen[a]) axes[na++] = a;
@@ -838,11 +1022,15 @@ static void global_from_parts(bm_plan_s& p, int s, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_gather_part<double, 5>), dim3(grid_for(tot)), dim3(NT), 0, st, a);
   BM_HIP(hipGetLastError());
-  // x: t1 -> t2, y: t2 -> t1, z: t1 -> the coarse grid (narrowed to FP32 on the store for an FP32 plan)
+  // x and y: t1 -> t2 (one plane pass where the planes fit), z: t2 -> the
+  // coarse grid (narrowed to FP32 on the store for an FP32 plan)
   const bool f64 = p.cfg.dtype == BM_F64;
-  launch_pass<double>(p, s, 2, dense_view(t1, m), nullptr, t2, nullptr, nullptr, nullptr, st, true);
-  launch_pass<double>(p, s, 1, dense_view(t2, m), nullptr, t1, nullptr, nullptr, nullptr, st, true);
-  launch_pass<double>(p, s, 0, dense_view(t1, m), nullptr, f64 ? p.ws.grid[s] : t2, nullptr, nullptr, nullptr, st,
+  if (!launch_plane<double>(p, s, dense_view(t1, m), false, t2, nullptr, nullptr, st, true)) {
+    launch_pass<double>(p, s, 2, dense_view(t1, m), nullptr, t2, nullptr, nullptr, nullptr, st, true);
+    launch_pass<double>(p, s, 1, dense_view(t2, m), nullptr, t1, nullptr, nullptr, nullptr, st, true);
+    std::swap(t1, t2);
+  }
+  launch_pass<double>(p, s, 0, dense_view(t2, m), nullptr, f64 ? p.ws.grid[s] : t1, nullptr, nullptr, nullptr, st,
                       true, f64 ? nullptr : static_cast<float*>(p.ws.grid[s]));
 }
 
