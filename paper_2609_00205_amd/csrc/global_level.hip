@@ -312,6 +312,23 @@ struct PassArgs {
   int pa, qa;            // the two other axes (q fastest)
   int solve_only;        // lines of m values that already hold 3 P^T M u: solve only
   float* out_f32;        // optional: the result narrowed to FP32 here instead of out
+  // the coarsest values of the hierarchy in the code array (last pass of the
+  // last level only): the result quantized into cout instead of out, or the
+  // base values dequantized from cbase instead of read from base
+  int32_t* cout;
+  const int32_t* cbase;
+  int64_t cst[3];        // strides of those codes per axis
+  const double* cq;      // 1/Delta for cout, Delta for cbase (device scalar)
+  int64_t* flag;         // set when a code does not fit in int32
+};
+
+// The coarsest values' codes for the last line pass of the hierarchy.
+struct CoarseIO {
+  int32_t* cout = nullptr;
+  const int32_t* cbase = nullptr;
+  int64_t s[3] = {0, 0, 0};
+  const double* q = nullptr;
+  int64_t* flag = nullptr;
 };
 
 constexpr int kU = 8;   // requests in flight per lane in the line passes
@@ -443,12 +460,14 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
   __syncthreads();
   const int64_t os[3] = {a.on[1] * a.on[2], a.on[2], 1};
   const int64_t oA = os[a.axis], oQ = os[a.qa], oP = os[a.pa];
+  const int64_t cA = a.cst[a.axis], cQ = a.cst[a.qa], cP = a.cst[a.pa];
   // stores kU at a time as well; one loop per kind of store (narrowed to
-  // FP32, subtracted from base values, plain), so each keeps its loads and
-  // stores in flight
+  // FP32, subtracted from base values, plain, quantized into the coarsest
+  // codes, subtracted from the dequantized coarsest codes), so each keeps
+  // its loads and stores in flight
   auto store = [&](auto kind) {
     constexpr int K = decltype(kind)::value;
-    auto put = [&](const int64_t (&o)[kU], const T (&v)[kU]) {
+    auto put = [&](const int64_t (&o)[kU], const int64_t (&oc)[kU], const T (&v)[kU]) {
       if constexpr (K == 0) {
 #pragma unroll
         for (int u = 0; u < kU; ++u)
@@ -464,6 +483,19 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
 #pragma unroll
         for (int u = 0; u < kU; ++u)
           if (o[u] >= 0) a.out[o[u]] = r[u];
+      } else if constexpr (K == 4) {
+        const double inv = *a.cq;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (o[u] >= 0) a.cout[oc[u]] = quant_g(v[u], inv, a.flag);
+      } else if constexpr (K == 5) {
+        const double del = *a.cq;
+        int32_t c[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) c[u] = a.cbase[o[u] >= 0 ? oc[u] : 0];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (o[u] >= 0) a.out[o[u]] = T(mul_rn(double(c[u]), del)) - v[u];
       } else {
 #pragma unroll
         for (int u = 0; u < kU; ++u)
@@ -477,16 +509,18 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
       int lw = 0, sl = 0;
       for (int g0 = 0; g0 < tot; g0 += kU) {
         T v[kU];
-        int64_t o[kU];
+        int64_t o[kU], oc[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int J = sl * 64 + lane, w = wave + lw * NW;
           o[u] = -1;
+          oc[u] = 0;
           v[u] = T(0);
           if (g0 + u < tot && J < m) {
             uint32_t p, q;
             line(w, p, q);
             o[u] = int64_t(p) * oP + int64_t(q) * oQ + int64_t(J) * oA;
+            if constexpr (K >= 4) oc[u] = int64_t(p) * cP + int64_t(q) * cQ + int64_t(J) * cA;
             v[u] = tout[J * WP + w];
           }
           if (++sl == spl) {
@@ -494,7 +528,7 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
             ++lw;
           }
         }
-        put(o, v);
+        put(o, oc, v);
       }
     } else {
       const int w = tid & (a.W - 1);
@@ -502,25 +536,32 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
       uint32_t p, q;
       line(w, p, q);
       const int64_t ob = int64_t(p) * oP + int64_t(q) * oQ;
+      const int64_t cb = int64_t(p) * cP + int64_t(q) * cQ;
       const int dJ = NT >> a.lw;
       for (int Jb = tid >> a.lw; Jb < m; Jb += kU * dJ) {
         T v[kU];
-        int64_t o[kU];
+        int64_t o[kU], oc[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int J = Jb + u * dJ;
           o[u] = -1;
+          oc[u] = 0;
           v[u] = T(0);
           if (J < m) {
             o[u] = ob + int64_t(J) * oA;
+            if constexpr (K >= 4) oc[u] = cb + int64_t(J) * cA;
             v[u] = tout[J * WP + w];
           }
         }
-        put(o, v);
+        put(o, oc, v);
       }
     }
   };
-  if (a.out_f32)
+  if (a.cout)
+    store(std::integral_constant<int, 4>{});
+  else if (a.cbase)
+    store(std::integral_constant<int, 5>{});
+  else if (a.out_f32)
     store(std::integral_constant<int, 0>{});
   else if (a.base)
     store(std::integral_constant<int, 1>{});
@@ -531,7 +572,7 @@ __global__ __launch_bounds__(NT) void k_line_pass(PassArgs<T> a) {
 template <typename T>
 void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
                  const void* base, const int32_t* qin, const double* qdel, hipStream_t st, bool solve_only = false,
-                 float* out_f32 = nullptr) {
+                 float* out_f32 = nullptr, const CoarseIO* cio = nullptr) {
   const Level& L = p.lv[s - 1];
   PassArgs<T> a{};
   a.in = static_cast<const T*>(in.ptr);
@@ -550,6 +591,14 @@ void launch_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int
   a.on[axis] = a.m;
   a.solve_only = solve_only ? 1 : 0;
   a.out_f32 = out_f32;
+  if (cio) {
+    if (out_f32 || base) fail(BM_EINVAL, "line pass: coarsest codes with another output kind");
+    a.cout = cio->cout;
+    a.cbase = cio->cbase;
+    for (int k = 0; k < 3; ++k) a.cst[k] = cio->s[k];
+    a.cq = cio->q;
+    a.flag = cio->flag;
+  }
   if (solve_only) {
     if (a.nl != a.m || a.m < 2 || a.m > 64 * kLineQ) fail(BM_EUNSUPPORTED, "line length not supported");
   } else if (a.nl < 3 || a.m != (a.nl + 1) / 2 || a.m > 64 * kLineQ) {
@@ -881,11 +930,12 @@ void line_pass(const bm_plan_s& p, int s, int axis, const View3& in, const int64
 namespace {
 
 void line_pass_q(const bm_plan_s& p, int s, int axis, const View3& in, const int64_t cmask[3], void* out,
-                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st) {
+                 const void* base, const int32_t* qin, const double* qdel, hipStream_t st,
+                 const CoarseIO* cio = nullptr) {
   if (p.cfg.dtype == BM_F32)
-    launch_pass<float>(p, s, axis, in, cmask, out, base, qin, qdel, st);
+    launch_pass<float>(p, s, axis, in, cmask, out, base, qin, qdel, st, false, nullptr, cio);
   else
-    launch_pass<double>(p, s, axis, in, cmask, out, base, qin, qdel, st);
+    launch_pass<double>(p, s, axis, in, cmask, out, base, qin, qdel, st, false, nullptr, cio);
 }
 
 void qcopy(const bm_plan_s& p, const View3& src, const int32_t* csrc, const View3& dst, int32_t* cdst,
@@ -975,12 +1025,12 @@ static bool plane_pass(const bm_plan_s& p, int s, const View3& in, bool mask, vo
 // coarse = K_z K_y K_x (in), applied as line passes over the axes that
 // coarsen; intermediate results go through the plan's temporaries.
 static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const void* base, hipStream_t st,
-                     const int32_t* qin = nullptr, const double* qdel = nullptr) {
+                     const int32_t* qin = nullptr, const double* qdel = nullptr, const CoarseIO* cio = nullptr) {
   const Level& L = p.lv[s - 1];
   // x and y in one plane pass where the planes fit, then z
   if (L.coarsen[0] && plane_pass(p, s, in, mask, p.ws.t1, qin, qdel, st)) {
     const int64_t on[3] = {in.n[0], L.m[1], L.m[2]};
-    line_pass_q(p, s, 0, dense_view(p.ws.t1, on), nullptr, out, base, nullptr, qdel, st);
+    line_pass_q(p, s, 0, dense_view(p.ws.t1, on), nullptr, out, base, nullptr, qdel, st, cio);
     return;
   }
   int axes[3], na = 0;
@@ -994,7 +1044,7 @@ static void apply_K3(bm_plan_s& p, int s, View3 in, bool mask, void* out, const 
     const bool last = k == na - 1;
     void* dst = last ? out : tmp[k & 1];
     line_pass_q(p, s, ax, cur, (k == 0 && mask) ? cm : nullptr, dst, last ? base : nullptr, k == 0 ? qin : nullptr,
-                qdel, st);
+                qdel, st, last ? cio : nullptr);
     int64_t on[3] = {cur.n[0], cur.n[1], cur.n[2]};
     on[ax] = L.m[ax];
     cur = dense_view(dst, on);
@@ -1108,6 +1158,7 @@ void recompose(bm_plan_s& p, const void* coeff, void* x, hipStream_t st) {
 // detail stencil produces them, and the coarsest values last.  The codes are
 // identical to bm_decompose followed by bm_quantize_roi.
 void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, const QPrep& q, hipStream_t st) {
+  bool coarsest_done = false;
   for (int s = p.L + 1; s <= p.nlev; ++s) {
     const Level& L = p.lv[s - 1];
     TimedScope ts(p, 2 * (s - 1), st);
@@ -1127,9 +1178,20 @@ void decompose_quantize_global(bm_plan_s& p, const void* x, int32_t* codes, cons
       launch_details<float>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
     else
       launch_details<double>(p, s, u, nullptr, codes, q.q + 2 * (s - 1) + 1, q.flag, st);
-    apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st);
+    // the last level's last pass quantizes the coarsest values into the codes
+    CoarseIO cio;
+    if (s == p.nlev) {
+      const View3 cv = coarsest_view(p, codes);
+      cio.cout = codes;
+      for (int k = 0; k < 3; ++k) cio.s[k] = cv.s[k];
+      cio.q = q.q + 2 * p.nlev + 1;
+      cio.flag = q.flag;
+      coarsest_done = true;
+    }
+    apply_K3(p, s, dense_view(const_cast<void*>(u), L.n), false, p.ws.grid[s], nullptr, st, nullptr, nullptr,
+             s == p.nlev ? &cio : nullptr);
   }
-  if (p.M > 0 || p.L == 0) {
+  if ((p.M > 0 || p.L == 0) && !coarsest_done) {
     const Level& last = p.lv[p.nlev - 1];
     const View3 cv = coarsest_view(p, codes);
     qcopy(p, dense_view(p.ws.grid[p.nlev], last.m), nullptr, cv, codes, q.q + 2 * p.nlev + 1, q.flag, st);
@@ -1164,16 +1226,23 @@ void decompose_quantize(bm_plan_s& p, const void* x, const double* block_tol, in
 }
 
 void dequantize_recompose_global(bm_plan_s& p, const int32_t* codes, const QPrep& q, void* x, hipStream_t st) {
-  if (p.M > 0 || p.L == 0) {
-    const Level& last = p.lv[p.nlev - 1];
-    const View3 cv = coarsest_view(p, const_cast<int32_t*>(codes));
-    qcopy(p, cv, codes, dense_view(p.ws.grid[p.nlev], last.m), nullptr, q.q + 2 * p.nlev, nullptr, st);
-  }
+  // (the coarsest values, a global level's, are dequantized by the last pass
+  // of that level, where they are the base of u_C = c - K3 w)
   for (int s = p.nlev; s > p.L; --s) {
     const Level& L = p.lv[s - 1];
     TimedScope ts(p, 2 * (s - 1) + 1, st);
     const double* qdel = q.q + 2 * (s - 1);
-    apply_K3(p, s, level_view(p, s, const_cast<int32_t*>(codes)), true, p.ws.grid[s], p.ws.grid[s], st, codes, qdel);
+    const View3 lvw = level_view(p, s, const_cast<int32_t*>(codes));
+    if (s == p.nlev) {
+      CoarseIO cio;
+      const View3 cv = coarsest_view(p, const_cast<int32_t*>(codes));
+      cio.cbase = codes;
+      for (int k = 0; k < 3; ++k) cio.s[k] = cv.s[k];
+      cio.q = q.q + 2 * p.nlev;
+      apply_K3(p, s, lvw, true, p.ws.grid[s], nullptr, st, codes, qdel, &cio);
+    } else {
+      apply_K3(p, s, lvw, true, p.ws.grid[s], p.ws.grid[s], st, codes, qdel);
+    }
     if (p.fuse_next && s == p.L + 1) continue;   // the last block level interpolates
     void* out = p.ws.grid[s - 1];
     if (p.cfg.dtype == BM_F32)
@@ -1193,7 +1262,7 @@ void dequantize_recompose_global(bm_plan_s& p, const int32_t* codes, const QPrep
 // Inverse of decompose_quantize: dequantize on load, then recompose.  Equal
 // to bm_dequantize followed by bm_recompose.
 void dequantize_recompose(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* x, hipStream_t st) {
-  const QPrep q = quant_prepare(p, block_tol, st);
+  const QPrep q = quant_prepare(p, block_tol, st, false);
   dequantize_recompose_global(p, codes, q, x, st);
   for (int s = p.L; s >= 1; --s) {
     TimedScope ts(p, 2 * (s - 1) + 1, st);

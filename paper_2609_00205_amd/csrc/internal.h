@@ -284,8 +284,9 @@ constexpr int kCoarseSlotHost = 8;
 // where a plan's quantizer tables live (host arithmetic, no launches)
 QPrep qprep_layout(bm_plan_s& p, const double* block_tol);
 // builds the tables on the device (stream-ordered) and returns their layout;
-// with the kept map (quant_keep) only the overflow flag is cleared
-QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st);
+// with the kept map (quant_keep) only the overflow flag is cleared, and not
+// even that for the dequantizing callers (clear_flag false: they set no flag)
+QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool clear_flag = true);
 // builds the tables of block_tol and keeps them (null: drops the kept ones)
 void quant_keep(bm_plan_s& p, const double* block_tol, hipStream_t st);
 

@@ -521,11 +521,13 @@ __global__ void k_clear_flag(int64_t* flag) {
 }
 }  // namespace
 
-QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st) {
+QPrep quant_prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool clear_flag) {
   const QPrep a = qprep_layout(p, block_tol);
   if (block_tol && block_tol == p.ws.kept_tol) {   // the kept tables are this map's
-    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, a.flag);
-    BM_HIP(hipGetLastError());
+    if (clear_flag) {
+      hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, a.flag);
+      BM_HIP(hipGetLastError());
+    }
     return a;
   }
   p.ws.kept_tol = nullptr;   // the tables built here replace the kept ones
@@ -741,8 +743,8 @@ void launch_prep_batch(const PrepStages& g, const PrepField* F, int nf, hipStrea
 
 namespace {
 
-QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool tables = true) {
-  const QPrep qp = tables ? quant_prepare(p, block_tol, st) : qprep_layout(p, block_tol);
+QArgs prepare(bm_plan_s& p, const double* block_tol, hipStream_t st, bool tables = true, bool clear_flag = true) {
+  const QPrep qp = tables ? quant_prepare(p, block_tol, st, clear_flag) : qprep_layout(p, block_tol);
   QArgs a{};
   const int64_t npad = prod3(p.pdims);
   if (npad >= (int64_t(1) << 32)) fail(BM_EUNSUPPORTED, "quantizer: padded grid of 2^32 nodes or more");
@@ -834,7 +836,7 @@ void quantize(bm_plan_s& p, const void* coeff, const double* block_tol, int32_t*
 
 void dequantize(bm_plan_s& p, const int32_t* codes, const double* block_tol, void* coeff, hipStream_t st) {
   TimedScope ts(p, 2 * p.nlev + 1, st);
-  QArgs a = prepare(p, block_tol, st);
+  QArgs a = prepare(p, block_tol, st, true, false);
   const int64_t tot = prod3(p.pdims);
   (void)tot;
   const unsigned g = qgroups(a.tot);
