@@ -38,6 +38,10 @@
  *     caller-visible output except an out_bytes size has been written.
  *   - The plan's device is the device current at bm_plan_create; calls
  *     must be made with that device current.
+ *   - Environment: BM_PLANE_PASS=0 at bm_plan_create gives the plan one
+ *     launch per axis in every global level instead of the plane pass that
+ *     runs x and y together (a diagnostic switch: the results are the same
+ *     bit for bit, only slower).
  */
 #ifndef BLOCKMGARD_H
 #define BLOCKMGARD_H

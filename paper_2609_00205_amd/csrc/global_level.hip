@@ -763,7 +763,7 @@ template <typename T>
 bool launch_plane(const bm_plan_s& p, int s, const View3& in, bool mask, void* out, const int32_t* qin,
                   const double* qdel, hipStream_t st, bool solve_only = false) {
   const Level& L = p.lv[s - 1];
-  if (!L.coarsen[1] || !L.coarsen[2]) return false;
+  if (!p.plane_pass || !L.coarsen[1] || !L.coarsen[2]) return false;
   const int64_t n1 = in.n[1], n2 = in.n[2], m1 = L.m[1], m2 = L.m[2];
   if (solve_only ? (n1 != m1 || n2 != m2) : (m1 != (n1 + 1) / 2 || m2 != (n2 + 1) / 2 || n1 < 3 || n2 < 3))
     return false;

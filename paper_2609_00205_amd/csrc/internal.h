@@ -183,6 +183,9 @@ struct bm_plan_s {
   // (decomposition) and its interpolation (recomposition): a global cell of
   // that level never crosses a block face (b = 9, 17 with M >= 1)
   bool fuse_next = false;
+  // global levels may run K along x and y as one plane pass (cleared by
+  // BM_PLANE_PASS=0 at plan creation: line passes only, same results)
+  bool plane_pass = true;
   std::shared_ptr<bm::PendingContainer> pending;   // dropped by every compress call on the plan
   // budget shares (levels 1..L+M, coarsest) set by an owner that spreads one
   // budget over more levels than the plan's (the 8^3 form's hybrid); empty:

@@ -5,6 +5,7 @@
 // down to the coarsest representation.  Sec. IV-B: the hybrid hierarchy runs
 // L In-cache Block levels, then M global levels on the block-coarse grid.
 
+#include <cstdlib>
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -362,6 +363,10 @@ bm_plan_s* bm_plan_build(const bm_config* c) {
     for (int a = 0; a < 3; ++a) p->nb1[a] = c->L > 0 ? p->lv[0].nb[a] : 1;
     const int bL = c->L > 0 ? p->lv[c->L - 1].b : 0;   // block size of the last block level
     p->fuse_next = c->L > 0 && c->M > 0 && bL != 33;
+    {
+      const char* e = std::getenv("BM_PLANE_PASS");
+      p->plane_pass = !(e && e[0] == '0' && e[1] == '\0');
+    }
     if (p->fuse_next) {
       // per-block partial load vectors of the first global level (FP64): H^3 per block, H = (b+3)/4
       const int64_t h = (bL + 3) / 4;
