@@ -283,7 +283,12 @@ void write_pending(PendingContainer& c, void* out) {
   h.crc = 0;
   const auto t0 = std::chrono::steady_clock::now();
   uint32_t crc = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
-  crc = crc32_parallel(o, size_t(h.payload), crc);
+  if (h.flags & 1u) {
+    crc = crc32_parallel(o, size_t(h.payload), crc);
+  } else {
+    crc = crc32(o, ntol * 8, crc);
+    crc = stream_crc(*c.enc, o + ntol * 8, size_t(h.payload) - ntol * 8, crc);
+  }
   h.crc = crc;
   if (!(h.flags & 1u))
     set_lossless_crc_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
@@ -351,7 +356,12 @@ bool write_container_p8(bm_p8_s& p, const void* x, const double* block_tol, doub
   h.crc = 0;
   const auto t0 = std::chrono::steady_clock::now();
   uint32_t c = crc32(reinterpret_cast<const uint8_t*>(&h), sizeof(h));
-  c = crc32_parallel(o, size_t(h.payload), c);
+  if (h.flags & 1u) {
+    c = crc32_parallel(o, size_t(h.payload), c);
+  } else {
+    c = crc32(o, size_t(ntol) * 8, c);
+    c = stream_crc(*enc, o + size_t(ntol) * 8, sb, c);
+  }
   h.crc = c;
   if (enc) set_lossless_crc_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   std::memcpy(out, &h, sizeof(h));
@@ -971,6 +981,37 @@ void drain_timing(bm_plan_s& p) {
   p.timing.pending.clear();
 }
 uint32_t container_crc(const uint8_t* p, size_t n) { return crc32_parallel(p, n, 0); }
+
+void crc32_shift_matrix(uint64_t bytes, uint32_t out[32]) {
+  for (int i = 0; i < 32; ++i) out[i] = crc32_shift(1u << i, bytes);
+}
+
+uint32_t stream_crc(const HuffmanEncoder& e, const uint8_t* stream, size_t n, uint32_t crc) {
+  // the shift over one block as four byte tables: Z(v) = T0[v & 255] ^ T1[..] ^ T2[..] ^ T3[v >> 24]
+  static const std::vector<uint32_t> zt = [] {
+    uint32_t m[32];
+    crc32_shift_matrix(HuffmanEncoder::kCrcBlock, m);
+    std::vector<uint32_t> t(4 * 256);
+    for (int k = 0; k < 4; ++k)
+      for (uint32_t b = 0; b < 256; ++b) t[k * 256 + b] = gf2_apply(m, b << (8 * k));
+    return t;
+  }();
+  size_t at = 0;
+  for (const HuffmanEncoder::DeviceSpan& d : e.device_spans()) {
+    const size_t done = d.block_crc.size() * HuffmanEncoder::kCrcBlock;
+    if (d.offset < at || d.offset + d.bytes > n || done > d.bytes)
+      fail(BM_EINVAL, "stream CRC: the encoder's layout does not match the stream");
+    crc = crc32_parallel(stream + at, d.offset - at, crc);    // host bytes before the span
+    // the span: the device's block CRCs in order, then its last partial block
+    uint32_t w = 0;
+    for (uint32_t b : d.block_crc)
+      w = (zt[w & 255u] ^ zt[256 + ((w >> 8) & 255u)] ^ zt[512 + ((w >> 16) & 255u)] ^ zt[768 + (w >> 24)]) ^ b;
+    w = crc32_parallel(stream + d.offset + done, d.bytes - done, w);
+    crc = crc32_shift(crc, d.bytes) ^ w;
+    at = d.offset + d.bytes;
+  }
+  return crc32_parallel(stream + at, n - at, crc);
+}
 }  // namespace bm
 }  // extern "C++"
 using bm::drain_timing;

@@ -685,6 +685,67 @@ void launch_decode(const uint32_t* words, const uint64_t* woff, int64_t nch, int
                      words, woff, nch, n, t, ooff, rel, codes, err, wcap);
 }
 
+// CRC-32 (the reflected polynomial 0xEDB88320 with pre- and post-inversion,
+// as zlib) of every 16 KiB block of the code words: each lane takes 64
+// consecutive bytes with a four-table byte-slicing update, then the
+// workgroup folds its 256 lane CRCs in order by a tree whose level k moves
+// the left CRC over the right part's 64 * 2^k bytes (crc(A B) = Z(crc(A)) ^
+// crc(B), Z linear over GF(2): its 32 columns come with the launch).
+struct CrcTree {
+  uint32_t m[8][32];
+};
+
+__device__ inline uint32_t gf2_mul(const uint32_t (&m)[32], uint32_t v) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    if ((v >> i) & 1u) r ^= m[i];
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_crc_blocks(const uint4* words, CrcTree t, uint32_t* out) {
+  static_assert(HuffmanEncoder::kCrcBlock == 256 * 64, "one 64-byte run per lane");
+  __shared__ uint32_t tab[4][256];
+  __shared__ uint32_t s[256];
+  const int tid = threadIdx.x;
+  const uint4* q = words + (size_t(blockIdx.x) * 256 + tid) * 4;
+  uint4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = q[k];
+  uint32_t c = uint32_t(tid);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+  tab[0][tid] = c;
+  __syncthreads();
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    c = (c >> 8) ^ tab[0][c & 0xFFu];
+    tab[k][tid] = c;
+  }
+  __syncthreads();
+  uint32_t crc = 0xFFFFFFFFu;
+  auto step = [&](uint32_t w) {
+    crc ^= w;
+    crc = tab[3][crc & 0xFFu] ^ tab[2][(crc >> 8) & 0xFFu] ^ tab[1][(crc >> 16) & 0xFFu] ^ tab[0][crc >> 24];
+  };
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    step(v[k].x);
+    step(v[k].y);
+    step(v[k].z);
+    step(v[k].w);
+  }
+  s[tid] = ~crc;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int w = 1 << k;
+    if ((tid & (2 * w - 1)) == 0) s[tid] = gf2_mul(t.m[k], s[tid]) ^ s[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) out[blockIdx.x] = s[0];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ encoder
@@ -702,6 +763,7 @@ struct HuffmanEncoder::Impl {
   std::vector<uint8_t> plen;
   uint64_t wmax = 0;
   size_t bytes = 0;
+  HuffmanEncoder::DeviceSpan span[2];      // the last write's words and outlier values
   DevBuf<uint8_t> dlen{NSYM};
   DevBuf<uint32_t> dcw{NSYM};
   Impl(const int32_t* c, int64_t n_, hipStream_t s) : codes(c), n(n_), nch((n_ + CHUNK - 1) / CHUNK), st(s) {}
@@ -775,6 +837,19 @@ HuffmanEncoder::HuffmanEncoder(const int32_t* codes, int64_t n, hipStream_t st) 
 HuffmanEncoder::~HuffmanEncoder() = default;
 
 size_t HuffmanEncoder::bytes() const { return d_->bytes; }
+const HuffmanEncoder::DeviceSpan (&HuffmanEncoder::device_spans() const)[2] { return d_->span; }
+
+namespace {
+// the columns of the tree's shifts over 64, 128, ..., 8192 zero bytes
+const CrcTree& crc_tree() {
+  static const CrcTree t = [] {
+    CrcTree r{};
+    for (int k = 0; k < 8; ++k) crc32_shift_matrix(uint64_t(64) << k, r.m[k]);
+    return r;
+  }();
+  return t;
+}
+}  // namespace
 
 void HuffmanEncoder::write(uint8_t* dst, size_t capacity) {
   Impl& I = *d_;
@@ -790,6 +865,22 @@ void HuffmanEncoder::write(uint8_t* dst, size_t capacity) {
   EventPair ee, ec;
   BM_HIP(hipEventRecord(ee.a, I.st));
   launch_encode(I.codes, I.n, nch, I.dlen.p, I.dcw.p, dwoff.p, dooff.p, I.wmax, dwords.p, doval.p, I.st);
+  // the CRC-32 of every whole 16 KiB block of the words and of the outlier
+  // values, while they are on the device
+  const void* dsrc[2] = {dwords.p, doval.p};
+  const size_t dbytes[2] = {size_t(nw) * 4, size_t(nout) * 4};
+  size_t nblk[2];
+  for (int k = 0; k < 2; ++k) nblk[k] = dbytes[k] / kCrcBlock;
+  DevBuf<uint32_t> dcrc(std::max<size_t>(nblk[0] + nblk[1], 1));
+  for (int k = 0; k < 2; ++k) {
+    I.span[k].bytes = dbytes[k];
+    I.span[k].block_crc.assign(nblk[k], 0u);
+    if (!nblk[k]) continue;
+    if (nblk[k] >= (size_t(1) << 31)) fail(BM_EUNSUPPORTED, "Huffman stream too large");
+    hipLaunchKernelGGL(k_crc_blocks, dim3(unsigned(nblk[k])), dim3(256), 0, I.st, static_cast<const uint4*>(dsrc[k]),
+                       crc_tree(), dcrc.p + (k ? nblk[0] : 0));
+    BM_HIP(hipGetLastError());
+  }
   BM_HIP(hipEventRecord(ee.b, I.st));
   HuffHeader hh{kHuffMagic, 3, I.n, nch, nw, nout, np};
   uint8_t* o = dst;
@@ -804,8 +895,14 @@ void HuffmanEncoder::write(uint8_t* dst, size_t capacity) {
   std::memcpy(o, I.ooff.data(), (nch + 1) * 8);
   o += (nch + 1) * 8;
   BM_HIP(hipEventRecord(ec.a, I.st));
+  I.span[0].offset = size_t(o - dst);
   if (nw) BM_HIP(hipMemcpyAsync(o, dwords.p, size_t(nw) * 4, hipMemcpyDeviceToHost, I.st));
+  for (int k = 0; k < 2; ++k)
+    if (nblk[k])
+      BM_HIP(hipMemcpyAsync(I.span[k].block_crc.data(), dcrc.p + (k ? nblk[0] : 0), nblk[k] * 4, hipMemcpyDeviceToHost,
+                            I.st));
   o += size_t(nw) * 4;
+  I.span[1].offset = size_t(o - dst);
   if (nout) BM_HIP(hipMemcpyAsync(o, doval.p, size_t(nout) * 4, hipMemcpyDeviceToHost, I.st));
   BM_HIP(hipEventRecord(ec.b, I.st));
   BM_HIP(hipStreamSynchronize(I.st));
@@ -977,7 +1074,7 @@ void huffman_stage_times(const int32_t* codes, int64_t n, hipStream_t st, double
   std::vector<uint8_t> out(e.bytes());
   e.write(out.data(), out.size());
   const auto t0 = clk::now();
-  volatile uint32_t crc = container_crc(out.data(), out.size());
+  volatile uint32_t crc = stream_crc(e, out.data(), out.size(), 0);
   (void)crc;
   const double crc_ms = ms_since(t0);
   const bm_lossless_times& T = g_times;

@@ -451,11 +451,26 @@ class HuffmanEncoder {
   HuffmanEncoder& operator=(const HuffmanEncoder&) = delete;
   size_t bytes() const;
   void write(uint8_t* dst, size_t capacity);
+  // after write: the stream's parts that came from the device (the code
+  // words, the outlier values), where they lie in it, and the CRC-32 of each
+  // whole kCrcBlock of them, formed on the device before they were copied
+  struct DeviceSpan {
+    size_t offset = 0, bytes = 0;
+    std::vector<uint32_t> block_crc;
+  };
+  const DeviceSpan (&device_spans() const)[2];
+  static constexpr size_t kCrcBlock = 16384;
 
  private:
   struct Impl;
   std::unique_ptr<Impl> d_;
 };
+// The 32 columns of the GF(2) map that moves a CRC-32 register over `bytes`
+// zero bytes (crc(A B) = shift(crc(A), |B|) ^ crc(B)).
+void crc32_shift_matrix(uint64_t bytes, uint32_t out[32]);
+// CRC-32 of a stream an encoder wrote (after its write), continuing from
+// crc: the device's block CRCs of its code words, the rest on the host.
+uint32_t stream_crc(const HuffmanEncoder& e, const uint8_t* stream, size_t n, uint32_t crc);
 size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out, hipStream_t st);
 // exact size of the stream an encoder of these codes writes (synchronizes)
 size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);

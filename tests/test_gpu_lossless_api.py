@@ -166,3 +166,25 @@ def test_workspace_size_counts_what_the_plan_holds():
     assert w1 - w0 == n * 4                # the code array of the padded grid
     p.compress(x, bt)
     assert p.workspace_bytes == w1         # kept, not allocated again
+
+
+@pytest.mark.parametrize("shape,b,L,M", [((33, 33, 33), 17, 1, 2), ((129, 129, 129), 17, 1, 2),
+                                         ((257, 257, 257), 9, 1, 1)])
+def test_container_crc_is_zlib_crc32(shape, b, L, M):
+    # the container's CRC combines CRCs of the code words' 16 KiB blocks
+    # formed on the device with the host's CRCs of the rest: it must still be
+    # the standard CRC-32 of header (CRC field zeroed) and payload, for
+    # streams below one block, of a few blocks and of hundreds plus a tail
+    import struct
+    import zlib
+    from paper_2609_00205_amd import Plan, api
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=46, dtype=np.float32)).cuda()
+    sc = float(x.abs().max())
+    p = Plan(shape, dtype=torch.float32, block=b, L=L, M=M)
+    bt = p.tolmap_from_boxes([(1, 1, 1, 9, 9, 9, 1e-5 * sc)], 1e-3 * sc)
+    buf = bytes(p.compress(x, bt))
+    stored = struct.unpack_from("<I", buf, 88)[0]
+    assert zlib.crc32(buf[:88] + bytes(4) + buf[92:]) == stored
+    t = api.lossless_times()
+    print("stream bytes", len(buf), "crc ms", t["enc_crc_ms"], flush=True)
+    assert float((api.decompress(buf) - x).abs().max()) <= 1e-3 * sc
