@@ -895,11 +895,24 @@ bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg) 
 bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st) {
   return guarded([&] {
     need(x != nullptr, "null output");
-    const CHeader h = parse(in, in_bytes);
-    if (!(h.flags & 1u)) {
+    const CHeader h = parse(in, in_bytes, false);
+    const uint8_t* pl0 = static_cast<const uint8_t*>(in) + sizeof(CHeader);
+    CHeader z = h;
+    z.crc = 0;
+    const uint32_t hcrc = crc32(reinterpret_cast<const uint8_t*>(&z), sizeof(z));
+    // the CRC over header and payload is checked before any plan is made: on
+    // the host for a raw copy; for a coded payload with the stream's code
+    // words and outlier values CRC'd on the device once they are uploaded
+    std::unique_ptr<bm::HuffmanDecoder> dec;
+    if (h.flags & 1u) {
+      if (crc32_parallel(pl0, size_t(h.payload), hcrc) != h.crc) bm::fail(BM_ECORRUPT, "CRC mismatch");
+    } else {
       // the stored map is checked before any plan or device buffer is made
       if (h.ntol < 1 || uint64_t(h.ntol) > h.payload / 8) bm::fail(BM_ECORRUPT, "tolerance map size mismatch");
-      check_stored_tol(static_cast<const uint8_t*>(in) + sizeof(CHeader), h.ntol);
+      check_stored_tol(pl0, h.ntol);
+      const size_t tb = size_t(h.ntol) * 8;
+      dec = std::make_unique<bm::HuffmanDecoder>(pl0 + tb, size_t(h.payload) - tb, st);
+      if (dec->crc(crc32(pl0, tb, hcrc)) != h.crc) bm::fail(BM_ECORRUPT, "CRC mismatch");
     }
     if (h.flags & bm::kFlagP8) {
       bm_p8_s* q = bm::p8_create(h.dims, h.dtype, h.L, h.M);
@@ -929,7 +942,7 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
       BM_HIP(hipMalloc(&g8.d, size_t(ntol) * sizeof(double)));
       BM_HIP(hipMemcpyAsync(g8.d, pl, size_t(ntol) * 8, hipMemcpyHostToDevice, st));
       int32_t* codes = bm::p8_codes(*q);
-      bm::huffman_decode(pl + ntol * 8, size_t(h.payload) - size_t(ntol) * 8, codes, bm::p8_coeff_size(*q), st);
+      dec->decode(codes, bm::p8_coeff_size(*q));
       bm::p8_dequantize_recompose(*q, codes, g8.d, h.eta, x, st);
       BM_HIP(hipStreamSynchronize(st));
       return;
@@ -958,8 +971,7 @@ bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t st
     BM_HIP(hipMalloc(&g.d, size_t(ntol) * sizeof(double)));
     BM_HIP(hipMemcpyAsync(g.d, pl, size_t(ntol) * 8, hipMemcpyHostToDevice, st));
     const int64_t npad = p->pdims[0] * p->pdims[1] * p->pdims[2];
-    bm::huffman_decode(pl + ntol * 8, size_t(h.payload) - size_t(ntol) * 8, static_cast<int32_t*>(p->ws.codes),
-                       npad, st);
+    dec->decode(static_cast<int32_t*>(p->ws.codes), npad);
     bm::dequantize_recompose(*p, static_cast<const int32_t*>(p->ws.codes), g.d, x, st);
     BM_HIP(hipStreamSynchronize(st));
   });
@@ -986,31 +998,36 @@ void crc32_shift_matrix(uint64_t bytes, uint32_t out[32]) {
   for (int i = 0; i < 32; ++i) out[i] = crc32_shift(1u << i, bytes);
 }
 
-uint32_t stream_crc(const HuffmanEncoder& e, const uint8_t* stream, size_t n, uint32_t crc) {
+uint32_t crc_with_spans(const uint8_t* buf, size_t n, uint32_t crc, const CrcSpan* spans, int nspans) {
   // the shift over one block as four byte tables: Z(v) = T0[v & 255] ^ T1[..] ^ T2[..] ^ T3[v >> 24]
   static const std::vector<uint32_t> zt = [] {
     uint32_t m[32];
-    crc32_shift_matrix(HuffmanEncoder::kCrcBlock, m);
+    crc32_shift_matrix(kCrcBlock, m);
     std::vector<uint32_t> t(4 * 256);
     for (int k = 0; k < 4; ++k)
       for (uint32_t b = 0; b < 256; ++b) t[k * 256 + b] = gf2_apply(m, b << (8 * k));
     return t;
   }();
   size_t at = 0;
-  for (const HuffmanEncoder::DeviceSpan& d : e.device_spans()) {
-    const size_t done = d.block_crc.size() * HuffmanEncoder::kCrcBlock;
+  for (int i = 0; i < nspans; ++i) {
+    const CrcSpan& d = spans[i];
+    const size_t done = d.block_crc.size() * kCrcBlock;
     if (d.offset < at || d.offset + d.bytes > n || done > d.bytes)
-      fail(BM_EINVAL, "stream CRC: the encoder's layout does not match the stream");
-    crc = crc32_parallel(stream + at, d.offset - at, crc);    // host bytes before the span
+      fail(BM_EINVAL, "stream CRC: the device parts do not match the stream");
+    crc = crc32_parallel(buf + at, d.offset - at, crc);    // host bytes before the span
     // the span: the device's block CRCs in order, then its last partial block
     uint32_t w = 0;
     for (uint32_t b : d.block_crc)
       w = (zt[w & 255u] ^ zt[256 + ((w >> 8) & 255u)] ^ zt[512 + ((w >> 16) & 255u)] ^ zt[768 + (w >> 24)]) ^ b;
-    w = crc32_parallel(stream + d.offset + done, d.bytes - done, w);
+    w = crc32_parallel(buf + d.offset + done, d.bytes - done, w);
     crc = crc32_shift(crc, d.bytes) ^ w;
     at = d.offset + d.bytes;
   }
-  return crc32_parallel(stream + at, n - at, crc);
+  return crc32_parallel(buf + at, n - at, crc);
+}
+
+uint32_t stream_crc(const HuffmanEncoder& e, const uint8_t* stream, size_t n, uint32_t crc) {
+  return crc_with_spans(stream, n, crc, e.device_spans(), 2);
 }
 }  // namespace bm
 }  // extern "C++"

@@ -704,7 +704,7 @@ __device__ inline uint32_t gf2_mul(const uint32_t (&m)[32], uint32_t v) {
 }
 
 __global__ __launch_bounds__(256) void k_crc_blocks(const uint4* words, CrcTree t, uint32_t* out) {
-  static_assert(HuffmanEncoder::kCrcBlock == 256 * 64, "one 64-byte run per lane");
+  static_assert(kCrcBlock == 256 * 64, "one 64-byte run per lane");
   __shared__ uint32_t tab[4][256];
   __shared__ uint32_t s[256];
   const int tid = threadIdx.x;
@@ -763,7 +763,7 @@ struct HuffmanEncoder::Impl {
   std::vector<uint8_t> plen;
   uint64_t wmax = 0;
   size_t bytes = 0;
-  HuffmanEncoder::DeviceSpan span[2];      // the last write's words and outlier values
+  CrcSpan span[2];      // the last write's words and outlier values
   DevBuf<uint8_t> dlen{NSYM};
   DevBuf<uint32_t> dcw{NSYM};
   Impl(const int32_t* c, int64_t n_, hipStream_t s) : codes(c), n(n_), nch((n_ + CHUNK - 1) / CHUNK), st(s) {}
@@ -837,7 +837,7 @@ HuffmanEncoder::HuffmanEncoder(const int32_t* codes, int64_t n, hipStream_t st) 
 HuffmanEncoder::~HuffmanEncoder() = default;
 
 size_t HuffmanEncoder::bytes() const { return d_->bytes; }
-const HuffmanEncoder::DeviceSpan (&HuffmanEncoder::device_spans() const)[2] { return d_->span; }
+const CrcSpan (&HuffmanEncoder::device_spans() const)[2] { return d_->span; }
 
 namespace {
 // the columns of the tree's shifts over 64, 128, ..., 8192 zero bytes
@@ -929,17 +929,40 @@ void huffman_code_lengths(const uint64_t* hist, uint8_t* len) {
 bm_lossless_times lossless_times() { return g_times; }
 
 // ------------------------------------------------------------------ decode (host)
-void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st) {
+struct HuffmanDecoder::Impl {
+  hipStream_t st;
+  const uint8_t* in;
+  size_t in_bytes;
+  int64_t n = 0, nch = 0, nw = 0, nout = 0;
+  uint64_t wcap = 0;
+  CrcSpan span[2];
+  std::vector<uint32_t> hdr;
+  std::vector<uint16_t> sorted16;
+  std::vector<uint64_t> woff, ooff;
+  uint32_t escidx = 0;
+  std::unique_ptr<DevBuf<uint32_t>> dhdr, dwords;
+  std::unique_ptr<DevBuf<uint16_t>> dsorted, drel;
+  std::unique_ptr<DevBuf<uint64_t>> dwoff, dooff;
+  std::unique_ptr<DevBuf<int32_t>> doval;
+  std::unique_ptr<DevBuf<int>> derr;
+  EventPair eu;
+  Impl(const uint8_t* i, size_t ib, hipStream_t s) : st(s), in(i), in_bytes(ib) {}
+};
+
+HuffmanDecoder::~HuffmanDecoder() = default;
+
+HuffmanDecoder::HuffmanDecoder(const uint8_t* in, size_t in_bytes, hipStream_t st) {
+  d_ = std::make_unique<Impl>(in, in_bytes, st);
+  Impl& I = *d_;
   bm_lossless_times& T = g_times;
-  T.dec_n = n;
   T.dec_parse_ms = T.dec_upload_ms = T.dec_decode_ms = 0.0;
   const auto t0 = clk::now();
   if (!in || in_bytes < sizeof(HuffHeader)) fail(BM_ECORRUPT, "Huffman stream too short");
   HuffHeader hh;
   std::memcpy(&hh, in, sizeof(hh));
   if (hh.magic != kHuffMagic || hh.version != 3) fail(BM_ECORRUPT, "bad Huffman stream header");
-  if (hh.n != n) fail(BM_EINVAL, "symbol count does not match the destination");
-  if (hh.nchunks != (n + CHUNK - 1) / CHUNK || hh.nwords < 0 || hh.noutliers < 0 || hh.noutliers > n ||
+  const int64_t n = hh.n;
+  if (n < 0 || hh.nchunks != (n + CHUNK - 1) / CHUNK || hh.nwords < 0 || hh.noutliers < 0 || hh.noutliers > n ||
       hh.npresent < 0 || hh.npresent > NSYM || hh.nwords > (int64_t(1) << 40))
     fail(BM_ECORRUPT, "inconsistent Huffman stream header");
   const int64_t nch = hh.nchunks, nw = hh.nwords, nout = hh.noutliers, np = hh.npresent;
@@ -957,10 +980,12 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
     }
   }
   p += size_t(np) * 3;
-  std::vector<uint64_t> woff(nch + 1);
+  std::vector<uint64_t>& woff = I.woff;
+  woff.resize(nch + 1);
   std::memcpy(woff.data(), p, (nch + 1) * 8);
   p += (nch + 1) * 8;
-  std::vector<uint64_t> ooff(nch + 1);
+  std::vector<uint64_t>& ooff = I.ooff;
+  ooff.resize(nch + 1);
   std::memcpy(ooff.data(), p, (nch + 1) * 8);
   p += (nch + 1) * 8;
   if (woff[0] != 0 || ooff[0] != 0 || ooff[nch] != uint64_t(nout)) fail(BM_ECORRUPT, "bad chunk offsets");
@@ -984,8 +1009,10 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
   canonical(len.data(), cw.data(), sorted.data(), &ns);
   sorted.resize(ns);
   // decode tables (layout at k_decode)
-  std::vector<uint32_t> hdr(kDecHdrWords, 0);
-  std::vector<uint16_t> sorted16(std::max<size_t>(sorted.size(), 1));
+  std::vector<uint32_t>& hdr = I.hdr;
+  hdr.assign(kDecHdrWords, 0);
+  std::vector<uint16_t>& sorted16 = I.sorted16;
+  sorted16.assign(std::max<size_t>(sorted.size(), 1), 0);
   {
     uint32_t* lut = hdr.data();
     uint32_t* lastc = lut + (1 << DLB);
@@ -1026,44 +1053,95 @@ void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t 
     }
   }
   T.dec_parse_ms = ms_since(t0);
-  DevBuf<uint32_t> dhdr(hdr.size());
-  DevBuf<uint16_t> dsorted(sorted16.size());
-  DevBuf<uint64_t> dwoff(nch + 1), dooff(nch + 1);
-  DevBuf<uint32_t> dwords(size_t(std::max<int64_t>(nw, 1)));
-  DevBuf<int32_t> doval(size_t(std::max<int64_t>(nout, 1)));
-  DevBuf<uint16_t> drel(size_t(std::max<int64_t>(nout, 1)));
-  DevBuf<int> derr(1);
-  EventPair eu, ed;
-  BM_HIP(hipEventRecord(eu.a, st));
-  BM_HIP(hipMemcpyAsync(dhdr.p, hdr.data(), hdr.size() * 4, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dsorted.p, sorted16.data(), sorted16.size() * 2, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
-  BM_HIP(hipMemcpyAsync(dooff.p, ooff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
-  if (nw) BM_HIP(hipMemcpyAsync(dwords.p, p, size_t(nw) * 4, hipMemcpyHostToDevice, st));
+  I.n = n;
+  I.nch = nch;
+  I.nw = nw;
+  I.nout = nout;
+  I.wcap = wcap;
+  I.dhdr = std::make_unique<DevBuf<uint32_t>>(hdr.size());
+  I.dsorted = std::make_unique<DevBuf<uint16_t>>(sorted16.size());
+  I.dwoff = std::make_unique<DevBuf<uint64_t>>(nch + 1);
+  I.dooff = std::make_unique<DevBuf<uint64_t>>(nch + 1);
+  I.dwords = std::make_unique<DevBuf<uint32_t>>(size_t(std::max<int64_t>(nw, 1)));
+  I.doval = std::make_unique<DevBuf<int32_t>>(size_t(std::max<int64_t>(nout, 1)));
+  I.drel = std::make_unique<DevBuf<uint16_t>>(size_t(std::max<int64_t>(nout, 1)));
+  I.derr = std::make_unique<DevBuf<int>>(1);
+  BM_HIP(hipEventRecord(I.eu.a, st));
+  BM_HIP(hipMemcpyAsync(I.dhdr->p, hdr.data(), hdr.size() * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(I.dsorted->p, sorted16.data(), sorted16.size() * 2, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(I.dwoff->p, woff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
+  BM_HIP(hipMemcpyAsync(I.dooff->p, ooff.data(), (nch + 1) * 8, hipMemcpyHostToDevice, st));
+  I.span[0].offset = size_t(p - in);
+  I.span[0].bytes = size_t(nw) * 4;
+  if (nw) BM_HIP(hipMemcpyAsync(I.dwords->p, p, size_t(nw) * 4, hipMemcpyHostToDevice, st));
   p += size_t(nw) * 4;
-  if (nout) BM_HIP(hipMemcpyAsync(doval.p, p, size_t(nout) * 4, hipMemcpyHostToDevice, st));
-  const int zero = 0;
-  BM_HIP(hipMemcpyAsync(derr.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
-  BM_HIP(hipEventRecord(eu.b, st));
-  uint32_t escidx = uint32_t(sorted16.size());
+  I.span[1].offset = size_t(p - in);
+  I.span[1].bytes = size_t(nout) * 4;
+  if (nout) BM_HIP(hipMemcpyAsync(I.doval->p, p, size_t(nout) * 4, hipMemcpyHostToDevice, st));
+  BM_HIP(hipEventRecord(I.eu.b, st));
+  I.escidx = uint32_t(sorted16.size());
   for (size_t i = 0; i < sorted.size(); ++i)
-    if (sorted[i] == 0) escidx = uint32_t(i);
-  const DecTables t{dhdr.p, dsorted.p, uint32_t(sorted16.size()), escidx};
-  BM_HIP(hipEventRecord(ed.a, st));
-  if (nch) {
-    launch_decode<kDecWpc, kDecCpw>(dwords.p, dwoff.p, nch, n, t, dooff.p, drel.p, codes, derr.p, int(wcap), st);
+    if (sorted[i] == 0) I.escidx = uint32_t(i);
+  I.sorted16.resize(sorted16.size());
+}
+
+uint32_t HuffmanDecoder::crc(uint32_t crc) {
+  Impl& I = *d_;
+  const void* src[2] = {I.dwords->p, I.doval->p};
+  size_t nblk[2];
+  for (int k = 0; k < 2; ++k) nblk[k] = I.span[k].bytes / kCrcBlock;
+  DevBuf<uint32_t> dcrc(std::max<size_t>(nblk[0] + nblk[1], 1));
+  for (int k = 0; k < 2; ++k) {
+    I.span[k].block_crc.assign(nblk[k], 0u);
+    if (!nblk[k]) continue;
+    if (nblk[k] >= (size_t(1) << 31)) fail(BM_EUNSUPPORTED, "Huffman stream too large");
+    hipLaunchKernelGGL(k_crc_blocks, dim3(unsigned(nblk[k])), dim3(256), 0, I.st, static_cast<const uint4*>(src[k]),
+                       crc_tree(), dcrc.p + (k ? nblk[0] : 0));
     BM_HIP(hipGetLastError());
-    if (nout)
-      hipLaunchKernelGGL(k_outliers, dim3(unsigned(nch)), dim3(256), 0, st, dooff.p, drel.p, doval.p, codes, n);
+    BM_HIP(hipMemcpyAsync(I.span[k].block_crc.data(), dcrc.p + (k ? nblk[0] : 0), nblk[k] * 4,
+                          hipMemcpyDeviceToHost, I.st));
+  }
+  BM_HIP(hipStreamSynchronize(I.st));
+  return crc_with_spans(I.in, I.in_bytes, crc, I.span, 2);
+}
+
+void HuffmanDecoder::decode(int32_t* codes, int64_t n) {
+  Impl& I = *d_;
+  bm_lossless_times& T = g_times;
+  if (I.n != n) fail(BM_EINVAL, "symbol count does not match the destination");
+  T.dec_n = n;
+  const int64_t nch = I.nch;
+  const DecTables t{I.dhdr->p, I.dsorted->p, uint32_t(I.sorted16.size()), I.escidx};
+  const int zero = 0;
+  BM_HIP(hipMemcpyAsync(I.derr->p, &zero, sizeof(int), hipMemcpyHostToDevice, I.st));
+  EventPair ed;
+  BM_HIP(hipEventRecord(ed.a, I.st));
+  if (nch) {
+    launch_decode<kDecWpc, kDecCpw>(I.dwords->p, I.dwoff->p, nch, n, t, I.dooff->p, I.drel->p, codes, I.derr->p,
+                                    int(I.wcap), I.st);
+    BM_HIP(hipGetLastError());
+    if (I.nout)
+      hipLaunchKernelGGL(k_outliers, dim3(unsigned(nch)), dim3(256), 0, I.st, I.dooff->p, I.drel->p, I.doval->p, codes,
+                         n);
     BM_HIP(hipGetLastError());
   }
-  BM_HIP(hipEventRecord(ed.b, st));
+  BM_HIP(hipEventRecord(ed.b, I.st));
   int herr = 0;
-  BM_HIP(hipMemcpyAsync(&herr, derr.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  BM_HIP(hipStreamSynchronize(st));
-  T.dec_upload_ms = eu.ms();
+  BM_HIP(hipMemcpyAsync(&herr, I.derr->p, sizeof(int), hipMemcpyDeviceToHost, I.st));
+  BM_HIP(hipStreamSynchronize(I.st));
+  T.dec_upload_ms = I.eu.ms();
   T.dec_decode_ms = ed.ms();
   if (herr) fail(BM_ECORRUPT, "Huffman stream does not decode");
+}
+
+void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st) {
+  if (!in || in_bytes < sizeof(HuffHeader)) fail(BM_ECORRUPT, "Huffman stream too short");
+  HuffHeader hh;
+  std::memcpy(&hh, in, sizeof(hh));
+  if (hh.magic == kHuffMagic && hh.version == 3 && hh.n != n)
+    fail(BM_EINVAL, "symbol count does not match the destination");
+  HuffmanDecoder d(in, in_bytes, st);
+  d.decode(codes, n);
 }
 
 // ------------------------------------------------------------------ stage times

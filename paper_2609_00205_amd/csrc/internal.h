@@ -443,6 +443,17 @@ std::vector<bm_candidate> autotune(const bm_config& in, const void* x, const dou
 // synchronizes): bytes() is the exact stream size, write() encodes into a
 // host buffer of at least that size.  Stage times of the calling thread's
 // last encode and decode are kept for lossless_times().
+// A part of a byte stream that is also on the device, with the CRC-32 of
+// each of its whole kCrcBlock-byte blocks formed there.
+struct CrcSpan {
+  size_t offset = 0, bytes = 0;
+  std::vector<uint32_t> block_crc;
+};
+constexpr size_t kCrcBlock = 16384;
+// CRC-32 (zlib's) of buf[0, n), continuing from crc: the spans' block CRCs
+// folded on the host, every other byte read there.
+uint32_t crc_with_spans(const uint8_t* buf, size_t n, uint32_t crc, const CrcSpan* spans, int nspans);
+
 class HuffmanEncoder {
  public:
   HuffmanEncoder(const int32_t* codes, int64_t n, hipStream_t st);
@@ -454,12 +465,7 @@ class HuffmanEncoder {
   // after write: the stream's parts that came from the device (the code
   // words, the outlier values), where they lie in it, and the CRC-32 of each
   // whole kCrcBlock of them, formed on the device before they were copied
-  struct DeviceSpan {
-    size_t offset = 0, bytes = 0;
-    std::vector<uint32_t> block_crc;
-  };
-  const DeviceSpan (&device_spans() const)[2];
-  static constexpr size_t kCrcBlock = 16384;
+  const CrcSpan (&device_spans() const)[2];
 
  private:
   struct Impl;
@@ -475,6 +481,24 @@ size_t huffman_encode(const int32_t* codes, int64_t n, std::vector<uint8_t>& out
 // exact size of the stream an encoder of these codes writes (synchronizes)
 size_t huffman_size(const int32_t* codes, int64_t n, hipStream_t st);
 void huffman_decode(const uint8_t* in, size_t in_bytes, int32_t* codes, int64_t n, hipStream_t st);
+// The same in steps: the constructor checks the stream, builds the decode
+// tables and uploads the stream (stream-ordered); crc() gives the CRC-32 of
+// the stream's bytes continuing from crc, the code words and outlier values
+// CRC'd on the device (synchronizes); decode() writes the n codes
+// (synchronizes; BM_ECORRUPT if the stream does not decode).
+class HuffmanDecoder {
+ public:
+  HuffmanDecoder(const uint8_t* in, size_t in_bytes, hipStream_t st);
+  ~HuffmanDecoder();
+  HuffmanDecoder(const HuffmanDecoder&) = delete;
+  HuffmanDecoder& operator=(const HuffmanDecoder&) = delete;
+  uint32_t crc(uint32_t crc);
+  void decode(int32_t* codes, int64_t n);
+
+ private:
+  struct Impl;
+  std::unique_ptr<Impl> d_;
+};
 bm_lossless_times lossless_times();
 void huffman_code_lengths(const uint64_t* hist, uint8_t* len);
 void set_lossless_crc_ms(double ms);

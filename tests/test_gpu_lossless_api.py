@@ -188,3 +188,24 @@ def test_container_crc_is_zlib_crc32(shape, b, L, M):
     t = api.lossless_times()
     print("stream bytes", len(buf), "crc ms", t["enc_crc_ms"], flush=True)
     assert float((api.decompress(buf) - x).abs().max()) <= 1e-3 * sc
+
+
+def test_decompress_detects_a_flipped_byte_in_the_stream():
+    # the container's CRC is checked, partly on the device, before anything
+    # is decoded: one flipped bit in the code words, in the outlier values
+    # region's neighbourhood, or in the tolerance map gives BM_ECORRUPT
+    from paper_2609_00205_amd import Plan, _lib, api
+    shape = (129, 129, 129)
+    x = torch.from_numpy(synth.gaussian_random_field(shape, 3.0, seed=47, dtype=np.float32)).cuda()
+    sc = float(x.abs().max())
+    p = Plan(shape, dtype=torch.float32, block=17, L=1, M=2)
+    bt = p.tolmap_from_boxes([(1, 1, 1, 30, 30, 30, 1e-6 * sc)], 1e-3 * sc)
+    buf = bytes(p.compress(x, bt))
+    xr = api.decompress(buf)
+    for at in (96 + 8, len(buf) // 2, len(buf) - 5):     # the map, the middle of the words, the last bytes
+        bad = bytearray(buf)
+        bad[at] ^= 0x10
+        with pytest.raises(_lib.BMError) as e:
+            api.decompress(bytes(bad))
+        assert e.value.code == -6, at
+    assert torch.equal(api.decompress(buf), xr)
