@@ -351,9 +351,11 @@ bm_status bm_huffman_code_lengths(const uint64_t* hist, uint8_t* len);
  * Device stages are timed with events on the call's stream, host stages with
  * a steady clock.  Encode: enc_hist (histogram, device), enc_table (code
  * lengths and canonical codes, host), enc_sizes (per-chunk bit and escape
- * counts on the device, offsets on the host), enc_encode (device),
+ * counts on the device, offsets on the host), enc_encode (device; with
+ * the CRC-32 of each 16 KiB block of the words and outlier values),
  * enc_copy (the stream's words and outliers to the host), enc_crc (the
- * container's CRC-32 on host threads; 0 outside bm_compress).  Decode:
+ * container's CRC-32 from those block CRCs and the host's bytes; 0 outside
+ * bm_compress).  Decode:
  * dec_parse (header checks and decode tables, host), dec_upload (tables,
  * offsets, words and outliers to the device), dec_decode (device).  enc_n
  * and dec_n: symbols of those calls (0: none yet).  Never fails. */
@@ -400,9 +402,11 @@ bm_status bm_compress_write(bm_plan plan, void* out, size_t capacity, size_t* ou
 bm_status bm_compressed_config(const void* in, size_t in_bytes, bm_config* cfg);
 
 /* Rebuild x (device, logical dims and dtype of the stored config) from a
- * buffer written by bm_compress.  Synchronous.  Errors: BM_ECORRUPT (bad
- * magic, version, size or CRC, or a stored block tolerance that is not
- * positive and finite). */
+ * buffer written by bm_compress.  Synchronous.  The CRC is checked before
+ * anything is decoded (the stream's words and outlier values in 16 KiB
+ * blocks on the device, once uploaded).  Errors: BM_ECORRUPT (bad magic,
+ * version, size or CRC, or a stored block tolerance that is not positive
+ * and finite). */
 bm_status bm_decompress(const void* in, size_t in_bytes, void* x, hipStream_t stream);
 
 /* ---- many fields (the paper's batched multi-field workloads, Sec. V) ------- */
