@@ -502,9 +502,12 @@ bm_status bm_autotune_budget(const bm_config* in, const void* x, const double* v
  * level's details and partial load vectors) has its own fit (fblk_*).  A
  * global level of N nodes takes glob_a_ms + glob_b_ms N; the first global
  * level after a block level, which only gathers and solves, fglob_*.
- * Quantization: max(q_slope_ms N, q_lat_ms), N = padded nodes.  Lossless:
- * stage k of the Huffman coder (0 histogram, 1 code table, 2 chunk sizes and
- * encode, 3 copy-out and CRC) takes huf_a_ms[k] + huf_b_ms[k] N for N codes. */
+ * Quantization, fitted apart for the local and the global quantizer as
+ * Sec. IV-B does: max(q_slope_ms N_s, q_lat_ms) for each block level s (its
+ * per-block tables; N_s its grid's nodes), max(gq_slope_ms N, gq_lat_ms)
+ * for an all-global hierarchy (N its padded nodes).  Lossless: stage k of the Huffman coder (0
+ * histogram, 1 code table, 2 chunk sizes and encode, 3 copy-out and CRC)
+ * takes huf_a_ms[k] + huf_b_ms[k] N for N codes. */
 typedef struct {
   int dtype, block;
   double blk_lat_ms, blk_tp;
@@ -513,6 +516,7 @@ typedef struct {
   double glob_a_ms, glob_b_ms;
   double q_slope_ms, q_lat_ms;
   double huf_a_ms[4], huf_b_ms[4];
+  double gq_slope_ms, gq_lat_ms;
 } bm_model;
 
 /* Fits every stage of *out on this device (the device current at the call):

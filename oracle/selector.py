@@ -36,21 +36,25 @@ def predict(shape, b: int, L: int, M: int, model: dict) -> Tuple[float, float, f
     """Predicted decomposition, quantization and lossless times (ms) of the
     hybrid hierarchy (b, L, M) on a grid of ``shape`` under a stage model
     (Sec. IV-B: PredictDecompTime from Eq. 1 for block levels and a line in
-    the node count for global levels, PredictQuantTime = max(slope N, T_lat),
-    PredictLosslessTime = one line per Huffman stage).
+    the node count for global levels, PredictQuantTime = max(slope N, T_lat)
+    fitted apart for local and global quantization, PredictLosslessTime = one
+    line per Huffman stage).
 
     ``model`` keys: blk_lat_ms, blk_tp (Eq. 1 with Slope = 1/blk_lat_ms and
     TP_peak = blk_tp blocks per ms); fblk_lat_ms, fblk_tp for the last block
     level when a global level follows it; glob_a_ms, glob_b_ms and fglob_a_ms,
     fglob_b_ms (the first global level after a block level) per node;
-    q_slope_ms, q_lat_ms; huf_a_ms[4], huf_b_ms[4] per code.  Block size 33
-    takes the plain fits throughout.
+    q_slope_ms, q_lat_ms (the local quantizer, one term per block level on
+    that level's grid) and gq_slope_ms, gq_lat_ms (the global one, for an
+    all-global hierarchy);
+    huf_a_ms[4], huf_b_ms[4] per code.  Block size 33 takes the plain fits
+    throughout.
     """
     from . import mgard
     n = [mgard.padded_length(int(d), b, L, M) for d in shape]
     nodes = float(n[0]) * float(n[1]) * float(n[2])
     fused = L > 0 and M > 0 and b != 33
-    td = 0.0
+    td = tq = 0.0
     for s in range(1, L + M + 1):
         if s <= L:
             blocks = 1.0
@@ -61,6 +65,8 @@ def predict(shape, b: int, L: int, M: int, model: dict) -> Tuple[float, float, f
             else:
                 lat, tp = model["blk_lat_ms"], model["blk_tp"]
             td += blocks / throughput(blocks, 1.0 / lat, tp)          # = 1/Slope + N / TP_peak
+            # local quantization, one term per block level (its tables)
+            tq += quant_time(float(n[0]) * float(n[1]) * float(n[2]), model["q_slope_ms"], model["q_lat_ms"])
         else:
             g = float(n[0]) * float(n[1]) * float(n[2])
             if fused and s == L + 1:
@@ -68,6 +74,7 @@ def predict(shape, b: int, L: int, M: int, model: dict) -> Tuple[float, float, f
             else:
                 td += model["glob_a_ms"] + model["glob_b_ms"] * g
         n = [(v + 1) // 2 if v > 2 else v for v in n]
-    tq = quant_time(nodes, model["q_slope_ms"], model["q_lat_ms"])
+    if L == 0:
+        tq = quant_time(nodes, model["gq_slope_ms"], model["gq_lat_ms"])
     tl = sum(a + bb * nodes for a, bb in zip(model["huf_a_ms"], model["huf_b_ms"]))
     return td, tq, tl, td + tq + tl

@@ -36,7 +36,7 @@ class BMModel(C.Structure):
                 ("fblk_lat_ms", C.c_double), ("fblk_tp", C.c_double), ("fglob_a_ms", C.c_double),
                 ("fglob_b_ms", C.c_double), ("glob_a_ms", C.c_double), ("glob_b_ms", C.c_double),
                 ("q_slope_ms", C.c_double), ("q_lat_ms", C.c_double), ("huf_a_ms", C.c_double * 4),
-                ("huf_b_ms", C.c_double * 4)]
+                ("huf_b_ms", C.c_double * 4), ("gq_slope_ms", C.c_double), ("gq_lat_ms", C.c_double)]
 
 
 class BMLosslessTimes(C.Structure):

@@ -482,7 +482,7 @@ def autotune(x: torch.Tensor, voxel_tol: torch.Tensor, slack: float = 0.05, reps
 
 
 _MODEL_KEYS = ["blk_lat_ms", "blk_tp", "fblk_lat_ms", "fblk_tp", "fglob_a_ms", "fglob_b_ms", "glob_a_ms",
-               "glob_b_ms", "q_slope_ms", "q_lat_ms"]
+               "glob_b_ms", "q_slope_ms", "q_lat_ms", "gq_slope_ms", "gq_lat_ms"]
 
 
 def _model_struct(model: dict) -> "_lib.BMModel":

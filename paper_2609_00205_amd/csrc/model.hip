@@ -167,7 +167,7 @@ void model_calibrate(int dtype, int b, bm_model& m, hipStream_t st) {
   // block levels: cubes of k blocks per side, (L, M) = (1, 0) (plain) and (1, 1)
   // (fused block level + fused global level); the quantizer preparation is the
   // call time outside the level events
-  std::vector<double> nb, tp, tf, nf, tg2, nq, tq;
+  std::vector<double> nb, tp, tf, nf, tg2, nq, tq, ngq, tgq;
   for (int k : {1, 2, 4, 8, 16, 32}) {
     const int64_t n = w * k + 1;
     if (n > 1025 || (b == 33 && k > 16)) continue;
@@ -205,8 +205,8 @@ void model_calibrate(int dtype, int b, bm_model& m, hipStream_t st) {
     const Run r = time_plan(dtype, b, 0, 1, n, reps, st);
     ng.push_back(double(n) * n * n);
     tgl.push_back(r.level_ms[0]);
-    nq.push_back(double(r.nodes));
-    tq.push_back(std::max(0.0, r.call_ms - r.level_ms[0]));
+    ngq.push_back(double(r.nodes));
+    tgq.push_back(std::max(0.0, r.call_ms - r.level_ms[0]));
   }
   const Line lg = fit_line(ng, tgl);
   m.glob_a_ms = lg.a;
@@ -215,19 +215,22 @@ void model_calibrate(int dtype, int b, bm_model& m, hipStream_t st) {
     m.fglob_a_ms = m.glob_a_ms;
     m.fglob_b_ms = m.glob_b_ms;
   }
-  // quantization: max(slope N, T_lat); T_lat the smallest inputs' mean, slope
-  // from the largest
-  {
-    std::vector<size_t> idx(nq.size());
+  // quantization: max(slope N, T_lat), fitted apart for the local quantizer
+  // (block plans: per-block tables) and the global one (all-global plans);
+  // T_lat the smallest inputs' mean, slope from the largest
+  auto quant_fit = [](const std::vector<double>& N, const std::vector<double>& t, double& slope, double& lat) {
+    std::vector<size_t> idx(N.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return nq[x] < nq[y]; });
-    double lat = 0;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return N[x] < N[y]; });
+    double s = 0;
     const size_t k0 = std::min<size_t>(3, idx.size());
-    for (size_t i = 0; i < k0; ++i) lat += tq[idx[i]];
-    m.q_lat_ms = lat / double(k0);
-    const size_t il = idx.back();
-    m.q_slope_ms = nq[il] > 0 ? tq[il] / nq[il] : 0.0;
-  }
+    for (size_t i = 0; i < k0; ++i) s += t[idx[i]];
+    lat = k0 ? s / double(k0) : 0.0;
+    const size_t il = idx.empty() ? 0 : idx.back();
+    slope = (!idx.empty() && N[il] > 0) ? t[il] / N[il] : 0.0;
+  };
+  quant_fit(nq, tq, m.q_slope_ms, m.q_lat_ms);
+  quant_fit(ngq, tgq, m.gq_slope_ms, m.gq_lat_ms);
   // lossless: one line per Huffman stage, on code arrays of 2^16 .. 2^26
   int32_t* q = nullptr;
   const int64_t qmax = int64_t(1) << 26;
@@ -271,7 +274,7 @@ void model_predict(const bm_model& m, const bm_config& cfg, double out[4]) {
   for (int a = 0; a < 3; ++a) n[a] = padded_length(d[a], c.L > 0 ? c.block : 0, c.L, c.M, c.nested != 0);
   const double nodes = double(n[0]) * double(n[1]) * double(n[2]);
   const bool fused = c.L > 0 && c.M > 0 && c.block != 33;
-  double td = 0;
+  double td = 0, tq = 0;
   for (int s = 1; s <= c.L + c.M; ++s) {
     if (s <= c.L) {
       double blocks = 1;
@@ -279,6 +282,8 @@ void model_predict(const bm_model& m, const bm_config& cfg, double out[4]) {
       const bool fb = fused && s == c.L;
       const double lat = fb ? m.fblk_lat_ms : m.blk_lat_ms, tp = fb ? m.fblk_tp : m.blk_tp;
       td += lat + (tp > 0 ? blocks / tp : 0.0);
+      // the local quantizer builds its tables per block level
+      tq += std::max(m.q_slope_ms * double(n[0]) * double(n[1]) * double(n[2]), m.q_lat_ms);
     } else {
       const double g = double(n[0]) * double(n[1]) * double(n[2]);
       const bool fg = fused && s == c.L + 1;
@@ -287,7 +292,8 @@ void model_predict(const bm_model& m, const bm_config& cfg, double out[4]) {
     for (int a = 0; a < 3; ++a)
       if (n[a] > 2) n[a] = (n[a] + 1) / 2;
   }
-  const double tq = std::max(m.q_slope_ms * nodes, m.q_lat_ms);
+  // an all-global hierarchy: the global quantizer alone
+  if (c.L == 0) tq = std::max(m.gq_slope_ms * nodes, m.gq_lat_ms);
   double tl = 0;
   for (int k = 0; k < 4; ++k) tl += m.huf_a_ms[k] + m.huf_b_ms[k] * nodes;
   out[0] = td;

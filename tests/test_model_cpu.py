@@ -12,16 +12,16 @@ from oracle import selector
 MODELS = [
     {"dtype": torch.float32, "block": 17, "blk_lat_ms": 0.007, "blk_tp": 1.0e5, "fblk_lat_ms": 0.009,
      "fblk_tp": 0.9e5, "fglob_a_ms": 0.03, "fglob_b_ms": 2.0e-9, "glob_a_ms": 0.012, "glob_b_ms": 1.2e-8,
-     "q_slope_ms": 1.0e-10, "q_lat_ms": 0.02, "huf_a_ms": [0.05, 0.4, 0.1, 0.05],
-     "huf_b_ms": [2e-9, 0.0, 3e-8, 5e-8]},
+     "q_slope_ms": 1.0e-10, "q_lat_ms": 0.02, "gq_slope_ms": 2.0e-11, "gq_lat_ms": 0.011,
+     "huf_a_ms": [0.05, 0.4, 0.1, 0.05], "huf_b_ms": [2e-9, 0.0, 3e-8, 5e-8]},
     {"dtype": torch.float64, "block": 9, "blk_lat_ms": 0.004, "blk_tp": 4.0e5, "fblk_lat_ms": 0.005,
      "fblk_tp": 3.5e5, "fglob_a_ms": 0.02, "fglob_b_ms": 4.0e-9, "glob_a_ms": 0.01, "glob_b_ms": 2.5e-8,
-     "q_slope_ms": 3.0e-10, "q_lat_ms": 0.015, "huf_a_ms": [0.04, 0.3, 0.08, 0.03],
-     "huf_b_ms": [1e-9, 1e-10, 2e-8, 4e-8]},
+     "q_slope_ms": 3.0e-10, "q_lat_ms": 0.015, "gq_slope_ms": 5.0e-10, "gq_lat_ms": 0.008,
+     "huf_a_ms": [0.04, 0.3, 0.08, 0.03], "huf_b_ms": [1e-9, 1e-10, 2e-8, 4e-8]},
     {"dtype": torch.float32, "block": 33, "blk_lat_ms": 0.02, "blk_tp": 2.0e4, "fblk_lat_ms": 0.02,
      "fblk_tp": 2.0e4, "fglob_a_ms": 0.012, "fglob_b_ms": 1.2e-8, "glob_a_ms": 0.012, "glob_b_ms": 1.2e-8,
-     "q_slope_ms": 1.0e-10, "q_lat_ms": 0.02, "huf_a_ms": [0.05, 0.4, 0.1, 0.05],
-     "huf_b_ms": [2e-9, 0.0, 3e-8, 5e-8]},
+     "q_slope_ms": 1.0e-10, "q_lat_ms": 0.02, "gq_slope_ms": 2.0e-11, "gq_lat_ms": 0.011,
+     "huf_a_ms": [0.05, 0.4, 0.1, 0.05], "huf_b_ms": [2e-9, 0.0, 3e-8, 5e-8]},
 ]
 SHAPES = [(513, 513, 513), (512, 512, 512), (100, 500, 500), (257, 129, 65), (65, 65, 65)]
 

@@ -29,7 +29,7 @@ def test_predict_by_hand():
     # 513^3, b = 17: level 1 has 32^3 blocks, level 2 (global) a 257^3 grid, level 3 a 129^3 grid
     m = {"blk_lat_ms": 0.01, "blk_tp": 1e5, "fblk_lat_ms": 0.02, "fblk_tp": 5e4, "fglob_a_ms": 0.03,
          "fglob_b_ms": 1e-9, "glob_a_ms": 0.04, "glob_b_ms": 2e-9, "q_slope_ms": 1e-10, "q_lat_ms": 0.5,
-         "huf_a_ms": [1.0, 2.0, 3.0, 4.0], "huf_b_ms": [1e-9, 0.0, 2e-9, 3e-9]}
+         "gq_slope_ms": 3e-9, "gq_lat_ms": 0.25, "huf_a_ms": [1.0, 2.0, 3.0, 4.0], "huf_b_ms": [1e-9, 0.0, 2e-9, 3e-9]}
     nodes = 513.0 ** 3
     # pure block level: Eq. 1 time N / TP(N) = 1/Slope + N/TP_peak
     td, tq, tl, tot = selector.predict((513, 513, 513), 17, 1, 0, m)
@@ -38,6 +38,13 @@ def test_predict_by_hand():
     assert tl == pytest.approx(10.0 + 6e-9 * nodes, rel=1e-12)
     assert tot == pytest.approx(td + tq + tl, rel=1e-12)
     # L = 1, M = 2: the fused block level, the fused first global level, a plain global level
-    td, _, _, _ = selector.predict((513, 513, 513), 17, 1, 2, m)
+    td, tq, _, _ = selector.predict((513, 513, 513), 17, 1, 2, m)
     assert td == pytest.approx((0.02 + 32 ** 3 / 5e4) + (0.03 + 1e-9 * 257.0 ** 3) + (0.04 + 2e-9 * 129.0 ** 3),
                                rel=1e-12)
+    assert tq == pytest.approx(max(1e-10 * nodes, 0.5), rel=1e-12)       # one block level: the local quantizer
+    # two block levels (513^3 then 257^3 grids): one local term each
+    _, tq, _, _ = selector.predict((513, 513, 513), 17, 2, 1, {**m, "q_lat_ms": 0.001})
+    assert tq == pytest.approx(1e-10 * nodes + 1e-10 * 257.0 ** 3, rel=1e-12)
+    # all global (L = 0, M = 1): the global quantizer's own fit, 3e-9 N above its floor
+    _, tq, _, _ = selector.predict((513, 513, 513), 17, 0, 1, m)
+    assert tq == pytest.approx(3e-9 * nodes, rel=1e-12)
