@@ -1082,7 +1082,6 @@ HuffmanDecoder::HuffmanDecoder(const uint8_t* in, size_t in_bytes, hipStream_t s
   I.escidx = uint32_t(sorted16.size());
   for (size_t i = 0; i < sorted.size(); ++i)
     if (sorted[i] == 0) I.escidx = uint32_t(i);
-  I.sorted16.resize(sorted16.size());
 }
 
 uint32_t HuffmanDecoder::crc(uint32_t crc) {
